@@ -1,0 +1,326 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows.  None of them compares the oracle
+with itself: the expected values are printed numbers of the paper, closed
+forms, exact special cases (Poiseuille / Couette flow between half-way
+bounce-back walls, the 1-D equilibrium profile, the Langmuir isotherm, the
+circular cap), conservation identities, or symmetries.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_26332_amd import inputs
+
+
+def sim(cfg):
+    return oracle.OracleSim(cfg)
+
+
+# --------------------------------------------------------------- constants
+def test_printed_solid_tensions_sec44():
+    """Sec. 4.4: sigma_sg0 - sigma_sl0 = sigma cos(theta0), sum 16 sigma/15 give
+    the printed 0.00709135 and 0.00432198 for sigma = 0.0107, theta0 = 75 deg."""
+    cfg = inputs.sessile_drop(nx=8, ny=8, R=2, theta0_deg=75.0, psi_b=0.01, sigma_gl0=0.0107)
+    d = sim(cfg).derived()
+    assert d["sigma_sg0"] == pytest.approx(0.00709135, abs=5e-9)
+    assert d["sigma_sl0"] == pytest.approx(0.00432198, abs=5e-9)
+
+
+def test_printed_langmuir_constant_sec44():
+    """Sec. 4.4 prints psi_c = 0.017 for Ex = 1, Pi = 0.18407 (Pi relation of Sec. 4)."""
+    cfg = inputs.stationary_drop(nx=8, ny=8, R=2, Ex=1.0, Pi=0.18407)
+    d = sim(cfg).derived()
+    assert d["psi_c"] == pytest.approx(0.017, rel=2e-4)
+
+
+def test_manufactured_parameters_sec41():
+    """Sec. 4.1 prints beta = 0.03, kappa = 9.375e-6, k_BT = 0.162, W = 0.24; the
+    lattice-unit configuration must reproduce them (kappa scales with 1/dx^2),
+    and eps = sqrt(2 kappa / beta) (Sec. 2.2) with sigma = (4 sqrt2/3) sqrt(kappa beta)."""
+    for n in (32, 64):
+        cfg = inputs.manufactured(n)
+        d = sim(cfg).derived()
+        dx = 1.0 / n
+        assert d["beta"] == pytest.approx(0.03, rel=1e-14)
+        assert d["kappa"] * dx * dx == pytest.approx(9.375e-6, rel=1e-14)
+        assert d["kBT"] == 0.162 and d["W"] == 0.24
+        assert math.sqrt(2 * d["kappa"] / d["beta"]) == pytest.approx(cfg["eps"], rel=1e-14)
+        assert cfg["sigma_gl0"] == pytest.approx(4 * math.sqrt(2) / 3 * math.sqrt(d["kappa"] * d["beta"]), rel=1e-14)
+
+
+def test_ex_pi_definitions_sec4():
+    """Sec. 4: Ex = 4 beta / W and Pi = k_BT / (4 beta); Ex = 0.5, Pi = 1.35 with
+    beta = 0.03 give the W = 0.24 and k_BT = 0.162 printed in Sec. 4.1."""
+    cfg = inputs.stationary_drop(nx=8, ny=8, R=2, sigma_gl0=0.04, eps=1.0)  # beta = 3 sigma/(4 eps) = 0.03
+    d = sim(cfg).derived()
+    assert d["beta"] == pytest.approx(0.03, rel=1e-14)
+    assert d["W"] == pytest.approx(0.24, rel=1e-14)
+    assert d["kBT"] == pytest.approx(0.162, rel=1e-14)
+
+
+# ------------------------------------------------- exact flows (flow lattice)
+def _single_phase(ny, **kw):
+    # all liquid: a "bubble" of negative radius makes phi = +phi_b everywhere
+    return inputs._base(nx=4, ny=ny, bc_bottom=inputs.NOSLIP, bc_top=inputs.NOSLIP, psi_b=0.0,
+                        init_kind=inputs.INIT_BUBBLE, R0=-1000.0, x0=0.0, y0=0.0, **kw)
+
+
+def test_poiseuille_exact_with_magic_rate():
+    """Body-force channel flow between half-way bounce-back walls at y = -1/2 and
+    ny - 1/2: u = g (y+1/2)(ny-1/2-y) / (2 nu).  Exact for the MRT step when the
+    even/odd rates satisfy (1/s2 - 1/2)(1/s3 - 1/2) = 3/16 (textbook result)."""
+    ny, g, nu = 12, 1e-6, 0.1
+    s3 = 1.0 / (0.5 + 0.1875 / 0.3)
+    s = sim(_single_phase(ny, gx=g, s_f=[1.0, 1.0, 0.0, s3, 1.0]))
+    s.step(30000)
+    ux = s.fields(["ux"])["ux"][:, 0]
+    y = np.arange(ny)
+    exact = g / (2 * nu) * (y + 0.5) * (ny - 0.5 - y)
+    # residual O(u^2) from the quadratic equilibrium terms; with s3 = 1 it is ~8e-4
+    assert np.abs(ux - exact).max() / exact.max() < 1e-7
+
+
+def test_couette_moving_wall():
+    """Top wall moving at u_w, bottom at rest: linear profile u_w (y+1/2)/ny."""
+    ny, uw = 12, 1e-4
+    s = sim(_single_phase(ny, u_wall_top=uw))
+    s.step(20000)
+    ux = s.fields(["ux"])["ux"][:, 0]
+    assert np.abs(ux - uw * (np.arange(ny) + 0.5) / ny).max() / uw < 1e-6
+
+
+def test_freeslip_half_channel():
+    """Free-slip top (specular reflection) over a no-slip bottom: half of a
+    Poiseuille profile, u = (g/nu) (Y ny - Y^2/2) with Y = y + 1/2."""
+    ny, g, nu = 12, 1e-6, 0.1
+    s3 = 1.0 / (0.5 + 0.1875 / 0.3)
+    cfg = _single_phase(ny, gx=g, s_f=[1.0, 1.0, 0.0, s3, 1.0])
+    cfg["bc_top"] = inputs.FREESLIP
+    s = sim(cfg)
+    s.step(60000)
+    ux = s.fields(["ux"])["ux"][:, 0]
+    Y = np.arange(ny) + 0.5
+    exact = g / nu * (Y * ny - Y * Y / 2)
+    assert np.abs(ux - exact).max() / exact.max() < 1e-5
+
+
+# ------------------------------------------------------------ equilibria
+def _slab(psi_b, steps, nx=128, eps=4.0):
+    s = sim(inputs.flat_slab(nx=nx, ny=4, width=nx / 2, psi_b=psi_b, eps=eps))
+    s.step(steps)
+    return s
+
+
+def _interface_x(phi_row):
+    # right-hand interface of the slab centred at nx/2: phi goes + to -
+    x = np.arange(phi_row.size)
+    i = np.where((phi_row[:-1] > 0) & (phi_row[1:] <= 0))[0][0]
+    return x[i] + phi_row[i] / (phi_row[i] - phi_row[i + 1])
+
+
+def test_flat_interface_tanh_profile_sec22():
+    """Clean flat interface: the continuous equilibrium is tanh(2 x / eps)
+    (Sec. 2.2).  The discrete steady profile differs by O((dx/eps)^2): about
+    1e-2 at eps = 4 and four times less at eps = 8."""
+    errs = []
+    for eps, nx, steps in ((4.0, 128, 6000), (8.0, 256, 16000)):
+        s = _slab(0.0, steps, nx=nx, eps=eps)
+        phi = s.fields(["phi"])["phi"][0]
+        x0 = _interface_x(phi)
+        x = np.arange(phi.size)
+        near = np.abs(x - x0) < 3 * eps
+        errs.append(np.abs(phi[near] - np.tanh(-2 * (x[near] - x0) / eps)).max())
+    assert errs[0] < 2e-2
+    assert 0.2 < errs[1] / errs[0] < 0.32
+
+
+def _isotherm_error(s):
+    f = s.fields(["phi", "psi"])
+    phi, psi = f["phi"][0], f["psi"][0]
+    d = s.derived()
+    beta, W, kBT = d["beta"], d["W"], d["kBT"]
+    psi_far = psi[0]                 # gas far field
+    phib_far = phi[phi.size // 2]    # liquid bulk at the slab centre
+    b2 = phib_far ** 2
+    R = (b2 - phi ** 2) * (beta * (2 - b2 - phi ** 2) + W / 2)
+    iso = psi_far / (psi_far + (1 - psi_far) * np.exp(-R / kBT))
+    return np.abs(psi - iso).max() / psi.max(), phi, psi, d
+
+
+def test_bulk_phase_value_and_langmuir_isotherm_sec22():
+    """With bulk surfactant and lambda_s = 0, at steady state (Sec. 2.2):
+    phi reaches phi_b with phi_b^2 = 1 - W psi/(4 beta (1 - psi)) in both bulks, and
+    psi follows psi_b / (psi_b + (1 - psi_b) exp(-R/kBT)) pointwise with
+    R = (phi_b^2 - phi^2)(beta (2 - phi_b^2 - phi^2) + W/2).  Without the auxiliary
+    diffusion M0 the isotherm is met to round-off; with M0 = M_phi kappa (added in
+    the LB equation, removed in R_psi) the streamed source leaves an
+    O(M0 dx^4 grad^4 psi) residue, under 1% here."""
+    s = _slab(0.01, 20000)
+    err, phi, psi, d = _isotherm_error(s)
+    beta, W = d["beta"], d["W"]
+    for k in (phi.size // 2, 0):
+        ps = psi[k]
+        assert abs(phi[k]) == pytest.approx(math.sqrt(1 - W * ps / (4 * beta * (1 - ps))), rel=1e-6)
+    assert err < 1e-2
+    assert psi.max() > 2 * psi[0]   # surfactant enriched at the interface
+    s0 = sim(inputs.flat_slab(nx=128, ny=4, width=64, psi_b=0.01, M0=0.0))
+    s0.step(20000)
+    assert _isotherm_error(s0)[0] < 1e-7
+
+
+# ----------------------------------------------------------- conservation
+def test_surfactant_mass_and_identities_sec41():
+    """Linear constraint for psi: sum R_psi = 0 every step and total surfactant
+    mass conserved to round-off (Sec. 4.1 reports < 1.9e-14); the weighted
+    multiplier satisfies the orthogonality sum h'(mu - lambda h') = 0 (Sec. 2.4)."""
+    s = sim(inputs.stationary_drop())
+    m0 = s.invariants()["mass_psi"]
+    worst_R, worst_o = 0.0, 0.0
+    for _ in range(10):
+        s.step(100)
+        inv = s.invariants()
+        worst_R = max(worst_R, abs(inv["sum_R_psi"]))
+        worst_o = max(worst_o, abs(inv["orthogonality"]))
+    assert abs(inv["mass_psi"] - m0) / m0 < 1e-13
+    # round-off of N = 4096 terms of size up to M_psi max|mu_psi| ~ 3e-3
+    assert worst_R < 1e-12
+    assert worst_o < 1e-13
+
+
+def test_linear_constraint_conserves_sum_phi():
+    """With h = phi the multiplier conserves sum phi exactly (Sec. 2.1)."""
+    s = sim(inputs.stationary_drop(constraint_phi=inputs.LINEAR))
+    a = s.invariants()["sum_phi"]
+    s.step(1000)
+    b = s.invariants()["sum_phi"]
+    assert abs(b - a) / abs(a) < 1e-13
+
+
+def test_nonlinear_constraint_preserves_area_better_sec41():
+    """Sec. 4.1/4.3: the weighted nonlinear constraint removes the curvature-induced
+    bulk shift, so the zero-level-set area of a drop drifts far less than with the
+    linear constraint (the paper reports about one order of magnitude)."""
+    drift = {}
+    for con in (inputs.NONLINEAR, inputs.LINEAR):
+        s = sim(inputs.stationary_drop(psi_b=0.0, constraint_phi=con))
+        a0 = s.invariants()["area_phi_pos"]
+        s.step(6000)
+        drift[con] = abs(s.invariants()["area_phi_pos"] - a0) / a0
+    assert drift[inputs.LINEAR] > 5 * drift[inputs.NONLINEAR]
+
+
+def test_linear_model_bulk_shift_direction_sec43():
+    """Linear constraint: the bulk values shift by about eps/(12R) (eq. ca1) in the
+    direction that shrinks the drop; the nonlinear model keeps the shift small."""
+    shifts = {}
+    for con in (inputs.NONLINEAR, inputs.LINEAR):
+        s = sim(inputs.stationary_drop(psi_b=0.0, constraint_phi=con))
+        s.step(8000)
+        phi = s.fields(["phi"])["phi"]
+        shifts[con] = 0.5 * (phi[32, 32] + phi[0, 0])
+    theory = 4.0 / (12 * 16.0)
+    assert shifts[inputs.LINEAR] > 0.3 * theory
+    assert abs(shifts[inputs.NONLINEAR]) < 0.2 * shifts[inputs.LINEAR]
+
+
+# -------------------------------------------------------------- Laplace law
+def test_laplace_multiplier_sec23():
+    """Matched asymptotics (Appendix A): lambda_0 = -gamma phi_b c0 K with
+    gamma = 3 sigma/4, c0 = 4/3, K = -1/R, i.e. lambda_phi -> sigma / R for a clean
+    drop; with the potential-form force the pressure jump approaches it too, and
+    surfactant lowers the effective tension."""
+    s = sim(inputs.stationary_drop(psi_b=0.0))
+    s.step(6000)
+    inv = s.invariants()
+    p = s.fields(["p"])["p"]
+    sR = 0.01 / 16.0
+    assert inv["lambda_phi"] == pytest.approx(sR, rel=0.03)
+    assert (p[32, 32] - p[0, 0]) == pytest.approx(sR, rel=0.12)
+    s2 = sim(inputs.stationary_drop(psi_b=0.01))
+    s2.step(6000)
+    assert s2.invariants()["lambda_phi"] < inv["lambda_phi"]
+
+
+# ---------------------------------------------------------------- symmetry
+def test_mirror_symmetry_of_centred_drop():
+    """A drop centred in a periodic box keeps its mirror and diagonal symmetries."""
+    s = sim(inputs.stationary_drop())
+    s.step(300)
+    f = s.fields(["phi", "psi", "ux"])
+    phi = f["phi"]
+    mirror = np.roll(phi[:, ::-1], 1, axis=1)  # x -> 64 - x
+    assert np.abs(phi - mirror).max() < 1e-13
+    assert np.abs(phi - phi.T).max() < 1e-13
+    assert np.abs(f["ux"] + np.roll(f["ux"][:, ::-1], 1, axis=1)).max() < 1e-16
+
+
+# -------------------------------------------------------- manufactured case
+def test_manufactured_second_order_sec41():
+    """Sec. 4.1, Table 1: second-order convergence under diffusive scaling for
+    the phi and psi lattices (order between 1.9 and 2.1 from 16^2 to 64^2), and
+    the linear-constraint sums of phi and psi conserved to round-off."""
+    errs = []
+    for n in (16, 32, 64):
+        cfg = inputs.manufactured(n)
+        s = sim(cfg)
+        steps = int(round(5.0 / (1.0 / n) ** 2 * 0.15))
+        i0 = s.invariants()
+        s.step(steps)
+        i1 = s.invariants()
+        errs.append(s.mms_errors())
+        assert abs(i1["mass_psi"] - i0["mass_psi"]) / i0["mass_psi"] < 1e-13
+        assert abs(i1["sum_phi"] - i0["sum_phi"]) < 1e-12
+    for k in range(2):
+        for comp in range(2):
+            order = math.log(errs[k][comp] / errs[k + 1][comp]) / math.log(2)
+            assert 1.9 < order < 2.1, (errs, k, comp, order)
+
+
+# ------------------------------------------------------------- diagnostics
+def test_two_triangle_area_exact_and_circle():
+    """Two-triangle reconstruction of {phi > 0} (Sec. 4.1): exact for a linear
+    field (a flat front, periodic in x, with and without the half-cell wall strip)
+    and second-order accurate for a disc of radius R (area pi R^2)."""
+    nx, ny = 16, 12
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi = 4.3 - y
+    assert oracle.area_positive(phi, False, False, False) == pytest.approx(nx * 4.3, abs=1e-12)
+    assert oracle.area_positive(phi, True, False, False) == pytest.approx(nx * 4.8, abs=1e-12)
+    n, R = 128, 30.0
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    disc = R - np.hypot(x - 64.3, y - 63.7)
+    A = oracle.area_positive(disc, False, False, True)
+    assert abs(A - math.pi * R * R) / (math.pi * R * R) < 2e-4
+
+
+def test_contact_diagnostics_on_exact_cap():
+    """A circular cap (eq. a: L = 2R sin(theta), H = R(1 - cos(theta))) written as a
+    signed-distance field above a wall at y = -1/2 gives width, height and
+    2 atan(2H/L) close to the geometry."""
+    nx, ny, Rc = 256, 128, 40.0
+    for th in (60.0, 90.0, 120.0):
+        t = math.radians(th)
+        yc = -0.5 - Rc * math.cos(t)
+        y, x = np.mgrid[0:ny, 0:nx].astype(float)
+        phi = Rc - np.hypot(x - nx / 2, y - yc)
+        L, H, ang = oracle.contact(phi)
+        assert H == pytest.approx(Rc * (1 - math.cos(t)), abs=0.05)
+        assert L == pytest.approx(2 * Rc * math.sin(t), rel=0.005)
+        assert ang == pytest.approx(th, abs=0.5)
+
+
+def test_young_contact_angle_sec43():
+    """Wetting boundary condition (eq. boundary with eq8): a clean sessile drop
+    relaxes to Young's angle theta0 (eq. a gives the cap); at R0 = 12, eps = 4 the
+    apparent angle lands within 2.5 deg and on the correct side of 90 deg."""
+    for th in (60.0, 120.0):
+        cfg = inputs.sessile_drop(nx=64, ny=32, R=12.0, theta0_deg=th, psi_b=0.0)
+        cfg["bc_top"] = inputs.NOSLIP
+        s = sim(cfg)
+        s.step(12000)
+        inv = s.invariants()
+        assert inv["theta_app_deg"] == pytest.approx(th, abs=2.5)
+        assert (inv["theta_app_deg"] - 90.0) * (th - 90.0) > 0
