@@ -1,0 +1,190 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) lattice Boltzmann library for the
+ * thermodynamically consistent, conservative Allen-Cahn / Navier-Stokes
+ * surfactant model with solid adsorption (Huang, Chai, Liu, Huang).
+ *
+ * One time step advances three coupled D2Q9 populations in lattice units
+ * (dx = dt = 1, c_s^2 = 1/3):
+ *   f  hydrodynamics, pressure-based equilibrium      (Sec. 3, f_eq of lattice 1)
+ *   g  phase field phi, conservative Allen-Cahn with the weighted nonlinear
+ *      Lagrange multiplier lambda_phi h_phi'(phi)     (Sec. 2.1, eq15 and AC_phi)
+ *   h  surfactant psi, linear constraint mubar_psi    (Sec. 2.1, AC_psi)
+ * with the chemical potentials (eq_muphi, eq_mupsi), the potential-form
+ * surface-tension / Marangoni force F = -phi grad mu_phi - psi grad mu_psi + G
+ * (eq_Fs0), the isotropic gradient and Laplacian stencils and backward time
+ * differences (end of Sec. 3), the wetting and solid-adsorption natural
+ * boundary conditions (Sec. 2.1, eq "boundary", wall energy eq8) and the two
+ * global FP64 reductions that set the multipliers every step.
+ *
+ * Conventions for every entry point:
+ *  - Return value: LBM_OK (0) or a negative lbm_status.  lbm_last_error()
+ *    gives a message owned by the handle, valid until the next call on it.
+ *  - Host pointers are caller-owned; the library reads or writes exactly the
+ *    stated number of elements and keeps no reference after returning.
+ *  - Fields crossing the boundary are FP64, row-major [ny][nx], x fastest,
+ *    whatever the storage precision; node (x, y) sits at position (x, y), the
+ *    bottom wall at y = -1/2 and the top wall at y = ny - 1/2.
+ *  - Calls on one handle are ordered on its HIP stream.  One handle must not
+ *    be used from two host threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+typedef struct lbm_handle lbm_handle; /* opaque, owned by the library */
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_ARG = -1,          /* invalid argument or parameter set */
+  LBM_E_UNSUPPORTED = -2,  /* valid request this build does not implement */
+  LBM_E_OOM = -3,          /* device or host allocation failed */
+  LBM_E_DEVICE = -4,       /* no usable gfx950 device, or a HIP runtime error */
+  LBM_E_NONFINITE = -5,    /* a non-finite value appeared in the fields */
+  LBM_E_RANGE = -6,        /* psi left the open interval (0, 1) */
+  LBM_E_STATE = -7         /* call not allowed in the handle's current state */
+} lbm_status;
+
+/* Boundary kinds for the bottom and top walls; x is always periodic.
+ *  PERIODIC  periodic in y (both walls must then be PERIODIC)
+ *  WALL_WET  half-way bounce-back no-slip wall (tangential speed u_wall_*)
+ *            carrying the wetting and solid-adsorption conditions
+ *  NOSLIP    half-way bounce-back no-slip wall (tangential speed u_wall_*),
+ *            zero normal flux of phi and psi
+ *  FREESLIP  specular reflection for f, zero normal flux of phi and psi */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL_WET = 1, LBM_BC_NOSLIP = 2, LBM_BC_FREESLIP = 3 };
+/* Storage precision of the populations.  Collisions run in FP64 (FP64) or
+ * FP32 (FP32, FP16_SHIFTED); the multiplier sums are always FP64. */
+enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_SHIFTED = 2 };
+/* Constraint for phi: weighted nonlinear map h = 1/2 + g(phi) (AC_phi) or the
+ * classical linear map h = phi. */
+enum { LBM_CONSTRAINT_NONLINEAR = 0, LBM_CONSTRAINT_LINEAR = 1 };
+/* Initial geometry: drop (liquid disc of radius R0 at (x0,y0)), slab (liquid
+ * for |x - x0| < a/2), bubble (gas disc).  The profile is the equilibrium
+ * phi_b tanh(2 phi_b sqrt(1 - psi_b) d / eps) of Sec. 2.2, d the signed
+ * distance (minimum image in periodic directions), psi = psi_b, u = 0, p = 0. */
+enum { LBM_INIT_DROP = 0, LBM_INIT_SLAB = 1, LBM_INIT_BUBBLE = 2 };
+
+/* Model parameters in lattice units, named as in Sec. 2 and Sec. 3.
+ * Entries marked "derive" take the stated default when set to the sentinel. */
+typedef struct {
+  int32_t abi_version;      /* must be LBM_ABI_VERSION */
+  int32_t nx, ny;           /* grid, both >= 3 */
+  int32_t bc_bottom, bc_top;
+  int32_t precision;
+  int32_t constraint_phi;
+  int32_t init_kind;
+  int32_t adv_raw;          /* 0 (default): phi and psi are advected by the mean (u(n) + u(n-1))/2 of the
+                               velocity of this and the previous step; 1: by u(n) itself (literal
+                               reading, excites the D2Q9 staggered-momentum mode on long runs) */
+  int32_t reserved;         /* must be 0 */
+  double sigma_gl0, eps;    /* clean gas-liquid tension, thickness: kappa = 3 eps sigma/8, beta = 3 sigma/(4 eps) */
+  double M_phi, M_psi;      /* mobilities (>= 0) */
+  double lambda_s;          /* psi gradient coefficient; < 0 derive: kappa/2 with a wetting wall, else 0 */
+  double kBT, W;            /* <= 0 derive: kBT = 4 beta Pi, W = 4 beta / Ex */
+  double Ex, Pi;            /* solubility and entropy groups (Sec. 4) */
+  double psi_b;             /* bulk surfactant in [0,1); 0 switches the surfactant off */
+  double phi_b;             /* <= 0 derive: phi_b^2 = 1 - W psi_b / (4 beta (1 - psi_b)) (Sec. 2.2) */
+  double theta0_deg;        /* clean Young angle, (0,180) on a wetting wall */
+  double sigma_sg0, sigma_sl0; /* < 0 derive: difference sigma cos theta0, sum 16 sigma / 15 */
+  double beta_sg, beta_sl;  /* Langmuir-Szyszkowski elasticities (eq "langmuir") */
+  double rho_l, rho_g, mu_l, mu_g; /* rho and dynamic viscosity linear in (1 + phi/phi_b)/2 */
+  double gx, gy;            /* body acceleration, G = rho (gx, gy) */
+  double u_wall_bottom, u_wall_top; /* tangential speed of no-slip walls */
+  double eta_phi, eta_psi;  /* <= 0 derive: eta = D / (c_s^2 (1/s1 - 1/2)), D_phi = M_phi kappa, D_psi = M_psi lambda_s + M0 */
+  double M0;                /* < 0 derive: 0 if lambda_s > 0, else M_phi kappa */
+  double s_f[5], s_g[5], s_h[5]; /* MRT rates by moment order 0..4 (<= 0: 1); s_f[2] <= 0: local 1/(3 mu/rho + 1/2) */
+  double x0, y0, R0, a, b;  /* initial geometry */
+} lbm_params;
+
+typedef struct {
+  int64_t step;             /* completed steps */
+  int64_t nonfinite;        /* nodes with a non-finite phi, psi, u or p */
+  int64_t psi_out_of_range; /* nodes with psi outside (0,1) (surfactant runs) */
+  int64_t cap_violations;   /* wetting-wall nodes where 1 + beta_sa ln(1 - psi) <= 1/2 (Remark 1) */
+  double mass_psi;          /* sum psi, conserved by the linear constraint */
+  double m_phi_h;           /* sum (1/2 + g(phi)), the nonlinear phase measure */
+  double sum_phi;           /* sum phi */
+  double area_phi_pos;      /* area of phi > 0, two-triangle reconstruction (Sec. 4.1) */
+  double kinetic;           /* sum rho |u|^2 / 2 */
+  double free_energy;       /* discrete E_f (eq1) including the wall energy */
+  double umax;              /* max |u| */
+  double lambda_phi;        /* multiplier of the current state (eq15 with h_phi) */
+  double mubar_psi;         /* mean chemical potential of the current state */
+  double contact_width;     /* bottom wall: length of phi > 0 on the first two rows, extrapolated to the wall */
+  double cap_height;        /* bottom wall: highest phi = 0 crossing above the wall */
+  double theta_app_deg;     /* 2 atan(2 H / L), 180 when detached (L = 0) */
+} lbm_invariants;
+
+/* Field mask bits for lbm_fetch_fields / lbm_load_fields; planes are laid
+ * out one after another in increasing bit order. */
+enum { LBM_F_PHI = 1, LBM_F_PSI = 2, LBM_F_UX = 4, LBM_F_UY = 8, LBM_F_P = 16,
+       LBM_F_RHO = 32, LBM_F_MU_PHI = 64, LBM_F_MU_PSI = 128 };
+
+/* Number of derived constants reported by lbm_derived, in this order:
+ * kappa, beta, W, kBT, phi_b, sigma_sg0, sigma_sl0, lambda_s, M0, eta_phi, eta_psi, psi_c. */
+#define LBM_N_DERIVED 12
+
+/* Bytes of device memory a handle with these parameters needs. */
+int lbm_required_bytes(const lbm_params* p, size_t* bytes);
+
+/* Validate p, derive the lattice constants, place the state and build the
+ * initial fields (Sec. 2.2 profile, equilibrium populations, u = 0, p = 0).
+ * dev_buf: NULL to let the library allocate, or caller-owned device memory of
+ * at least lbm_required_bytes (it must outlive the handle; never freed here).
+ * hip_stream: a hipStream_t to order all work on, or NULL for a library
+ * stream.  On error *out is NULL and the status says why (LBM_E_ARG for a bad
+ * parameter set; the message is available from lbm_last_error(NULL)). */
+int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_stream, lbm_handle** out);
+
+/* Enqueue n time steps (n >= 0).  Asynchronous: returns once the work is on
+ * the stream.  Faults in the fields surface at the next synchronising call. */
+int lbm_step(lbm_handle* h, int64_t n);
+
+/* Diagnostics of the current state (FP64 sums on the device), then one small
+ * device-to-host copy; synchronises the stream.  Returns LBM_E_NONFINITE or
+ * LBM_E_RANGE (with *out filled) when the fields are unhealthy. */
+int lbm_reduce_invariants(lbm_handle* h, lbm_invariants* out);
+
+/* Macroscopic fields of the current state (time n, before its collision) as
+ * FP64 [popcount(mask)][ny][nx]; n_doubles must be at least that size.
+ * Synchronises the stream. */
+int lbm_fetch_fields(lbm_handle* h, uint32_t mask, double* host, size_t n_doubles);
+
+/* Replace the state by equilibrium populations of the given fields: mask must
+ * contain LBM_F_PHI and LBM_F_PSI, and may contain LBM_F_UX | LBM_F_UY;
+ * pressure is set to 0 and the backward-difference history restarts. */
+int lbm_load_fields(lbm_handle* h, uint32_t mask, const double* host, size_t n_doubles);
+
+/* Raw state for checkpoint / restart: populations, history planes, scalars
+ * and the step count.  lbm_state_bytes gives the size; load_state only
+ * accepts a blob from a handle with identical parameters. */
+int lbm_state_bytes(lbm_handle* h, size_t* bytes);
+int lbm_save_state(lbm_handle* h, void* host, size_t bytes);
+int lbm_load_state(lbm_handle* h, const void* host, size_t bytes);
+
+/* Derived lattice constants (LBM_N_DERIVED doubles, order above). */
+int lbm_derived(lbm_handle* h, double* out);
+
+/* Populations of the current state as FP64 [27][ny][nx] (f0..f8, g0..g8,
+ * h0..h8, post-streaming at time n).  Synchronises the stream. */
+int lbm_fetch_populations(lbm_handle* h, double* host, size_t n_doubles);
+
+/* Release the handle and any library-owned device memory and stream. */
+int lbm_destroy(lbm_handle* h);
+
+/* Message of the last failed call on h (or of the last failed lbm_init when
+ * h is NULL).  Never NULL. */
+const char* lbm_last_error(const lbm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,77 @@
+// lbm_internal.h -- device-side parameter block and launcher interface shared
+// by the C-ABI host code (lbm_capi.cpp) and the gfx950 kernels (lbm_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace lbm {
+
+// Everything a kernel needs, derived once on the host (lattice units, FP64).
+struct DevParams {
+  int nx, ny, N;
+  int periodic_y, bc_bottom, bc_top;
+  int surf;        // surfactant lattice active
+  int linear;      // linear constraint h = phi
+  int adv_raw;     // advect phi/psi with u(n) instead of (u(n) + u(n-1))/2
+  int s2_local;    // f viscosity rate from the local dynamic viscosity
+  int wet_bottom, wet_top;
+  double kappa, beta, W, kBT, phib, inv_phib, lambda_s, M0, M_phi, M_psi, eta_phi, eta_psi;
+  double rho_l, rho_g, mu_l, mu_g, gx, gy, uw_bottom, uw_top;
+  double sig_cos;  // sigma_gl0 cos(theta0)
+  double dsb;      // sigma_sg0 beta_sg - sigma_sl0 beta_sl
+  double msb;      // sigma_sg0 beta_sg + sigma_sl0 beta_sl
+  double fw0;      // (sigma_sg0 + sigma_sl0) / 2
+  double beta_sg, beta_sl;
+  double sf[5], sg[5], sh[5];
+  double x0, y0, R0, a;
+  double psi_b, init_scale;  // init_scale = 2 phi_b sqrt(1 - psi_b) / eps
+  int init_kind;
+};
+
+// FP64 multiplier state kept on the device.
+struct DevScalars {
+  double lambda_phi, mubar_psi;  // multipliers of the current step
+};
+
+// FP64 invariant accumulators per block: mass_psi, m_phi_h, sum_phi, area,
+// kinetic, free_energy, umax (max), nonfinite, psi_out_of_range, cap_violations;
+// the final vector adds contact width, cap height and apparent angle.
+constexpr int kInvValues = 10;
+constexpr int kInvOut = kInvValues + 3;
+
+// Device buffers of one simulation (all planes N elements, x fastest).
+struct DevState {
+  int precision;           // LBM_FP64 / LBM_FP32 / LBM_FP16_SHIFTED
+  void* pops[2];           // 27 planes each, storage type
+  void* phipsi[2];         // 2 planes each (phi, psi), compute type
+  void* mu;                // 2 planes (mu_phi, mu_psi), compute type
+  void* uhist[2];          // 4 planes each (ux, uy, vx, vy): velocity and advecting velocity, compute type
+  void* Rhist[2];          // 2 planes each (R_phi, R_psi), compute type
+  double* partials;        // reduction partials [kRedBlocks][3]
+  double* inv_partials;    // invariant partials [kRedBlocks][kInvValues]
+  double* inv_out;         // final invariants [kInvOut]
+  double* contact;         // [nx] column heights + 2 x [nx] edge fractions (rows 0 and 1)
+  DevScalars* scalars;
+  double* field_buf;       // FP64 staging for fetch/load, [27][N]
+  int cur;                 // index of the current population buffer
+  int hcur;                // phi/psi and history buffer written by the next step
+};
+
+constexpr int kBlock = 256;
+constexpr int kRedBlocks = 1024;
+
+size_t storage_bytes(int precision);
+size_t compute_bytes(int precision);
+
+// Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the HIP status.
+hipError_t launch_init(const DevParams& p, DevState& s, hipStream_t stream);
+hipError_t launch_load(const DevParams& p, DevState& s, int with_u, hipStream_t stream);
+hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t stream);
+hipError_t launch_macro(const DevParams& p, DevState& s, hipStream_t stream);  // phi/psi, mu, multipliers of the current state
+hipError_t launch_invariants(const DevParams& p, DevState& s, hipStream_t stream);
+hipError_t launch_fetch(const DevParams& p, DevState& s, uint32_t mask, hipStream_t stream);
+hipError_t launch_fetch_pops(const DevParams& p, DevState& s, hipStream_t stream);
+
+}  // namespace lbm

@@ -1,0 +1,770 @@
+// lbm_kernels.hip -- gfx950 kernels of the coupled three-population lattice
+// Boltzmann step (phase field phi, surfactant psi, hydrodynamics f).
+//
+// Layout: structure of arrays.  Populations are 27 planes [f0..f8 g0..g8
+// h0..h8] of N = nx*ny nodes, x fastest; macroscopic planes likewise.  The
+// stored value of population i at node z is its post-collision value at z
+// ("pull" streaming): a step gathers f_i(x) = stored_i(x - c_i), so every
+// load and store of a wavefront touches 64 consecutive nodes of one plane.
+//
+// One step (Sec. 3 of the paper, readings in the design notes):
+//   k_moments      phi = sum g_i, psi = sum h_i                     (macroscopic recovery)
+//   k_mu_partials  mu_phi, mu_psi with the wall terms; per-block FP64 sums of
+//                  h'(phi) mu_phi, h'(phi)^2, mu_psi                (eq_muphi, eq_mupsi, eq15)
+//   k_multipliers  lambda_phi = S1/S2, mubar_psi = S3/N             (eq15, AC_psi)
+//   k_collide      force, velocity, pressure, sources, MRT collision of f, g, h,
+//                  wall corrections; writes post-collision populations
+//                  and the history for the backward differences
+// No MFMA: the step moves ~250 B/node in FP32 and does ~2 kflop/node, far
+// below the FP32 ridge of the chip, so HBM bandwidth bounds it.
+
+#include "lbm_internal.h"
+#include "../../include/lbm.h"
+
+#include <hip/hip_fp16.h>
+
+namespace lbm {
+namespace {
+
+// ---------------------------------------------------------------- D2Q9 tables
+// Directions: 0 rest, 1 (+x), 2 (+y), 3 (-x), 4 (-y), 5 (+x+y), 6 (-x+y),
+// 7 (-x-y), 8 (+x-y).  Written as constexpr functions so unrolled loops fold.
+__host__ __device__ constexpr int CX(int i) { return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0); }
+__host__ __device__ constexpr int CY(int i) { return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0); }
+__host__ __device__ constexpr int OPP(int i) { return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5); }
+__host__ __device__ constexpr int MIRY(int i) { return i == 2 ? 4 : i == 4 ? 2 : i == 5 ? 8 : i == 8 ? 5 : i == 6 ? 7 : i == 7 ? 6 : i; }
+template <class C> __device__ __forceinline__ constexpr C WQ(int i) { return i == 0 ? C(4.0 / 9.0) : (i <= 4 ? C(1.0 / 9.0) : C(1.0 / 36.0)); }
+static_assert(OPP(1) == 3 && OPP(2) == 4 && OPP(3) == 1 && OPP(4) == 2, "opp");
+static_assert(OPP(5) == 7 && OPP(6) == 8 && OPP(7) == 5 && OPP(8) == 6, "opp");
+
+__device__ __forceinline__ float lg(float v) { return logf(v); }
+__device__ __forceinline__ double lg(double v) { return log(v); }
+
+__device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// Neighbour x + (dx,dy) of (x,y) for the stencils.  Beyond a wall the ghost
+// reads the fluid node next to it in the same column (index returned) and
+// side tells which wall (-1 bottom, +1 top, 0 inside).
+struct Nb { int idx; int side; };
+__device__ __forceinline__ Nb nbr(const DevParams& p, int x, int y, int dx, int dy) {
+  int xx = wrap(x + dx, p.nx), yy = y + dy;
+  if (p.periodic_y) return {wrap(yy, p.ny) * p.nx + xx, 0};
+  if (yy < 0) return {y * p.nx + xx, -1};
+  if (yy >= p.ny) return {y * p.nx + xx, 1};
+  return {yy * p.nx + xx, 0};
+}
+__device__ __forceinline__ bool wet_side(const DevParams& p, int side) { return side < 0 ? p.wet_bottom : p.wet_top; }
+
+// Gather population i of lattice lat (0 f, 1 g, 2 h) at (x,y): the value that
+// left x - c_i last step.  Sources beyond a wall: half-way bounce-back (the
+// population that left x towards the wall), or for f at a free-slip wall the
+// specular image that left x - (c_x, 0).
+template <class S, class C>
+__device__ __forceinline__ C pull(const DevParams& p, const S* __restrict__ P, int lat, int i, int x, int y) {
+  const size_t N = (size_t)p.N;
+  int sx = wrap(x - CX(i), p.nx), sy = y - CY(i);
+  if (p.periodic_y) sy = wrap(sy, p.ny);
+  else if (sy < 0 || sy >= p.ny) {
+    int bc = sy < 0 ? p.bc_bottom : p.bc_top;
+    if (lat == 0 && bc == LBM_BC_FREESLIP) return (C)P[(size_t)(9 * lat + MIRY(i)) * N + (size_t)y * p.nx + sx];
+    return (C)P[(size_t)(9 * lat + OPP(i)) * N + (size_t)y * p.nx + x];
+  }
+  return (C)P[(size_t)(9 * lat + i) * N + (size_t)sy * p.nx + sx];
+}
+
+// ------------------------------------------------------------------- physics
+// Wall switching function g(phi) and g'(phi) with u = phi/phi_b (Sec. 2.1).
+template <class C> __device__ __forceinline__ C gsw(const DevParams& p, C ph) {
+  C u = ph * (C)p.inv_phib;
+  return C(0.75) * u - C(0.25) * u * u * u;
+}
+template <class C> __device__ __forceinline__ C gsw_d(const DevParams& p, C ph) {
+  C u = ph * (C)p.inv_phib;
+  return C(0.75) * (C)p.inv_phib * (C(1) - u * u);
+}
+template <class C> __device__ __forceinline__ C hprime(const DevParams& p, C ph) { return p.linear ? C(1) : gsw_d(p, ph); }
+template <class C> __device__ __forceinline__ C rho_of(const DevParams& p, C ph) {
+  return (C)p.rho_g + (C)(p.rho_l - p.rho_g) * C(0.5) * (C(1) + ph * (C)p.inv_phib);
+}
+template <class C> __device__ __forceinline__ C mud_of(const DevParams& p, C ph) {
+  return (C)p.mu_g + (C)(p.mu_l - p.mu_g) * C(0.5) * (C(1) + ph * (C)p.inv_phib);
+}
+// J_phi = -df_w/dphi, J_psi = -df_w/dpsi at a wall node (eq8, boundary).
+template <class C> __device__ __forceinline__ C Jphi(const DevParams& p, C ph, C ps) {
+  C a = (C)p.sig_cos;
+  if (p.surf) a += lg(C(1) - ps) * (C)p.dsb;
+  return a * gsw_d(p, ph);
+}
+template <class C> __device__ __forceinline__ C Jpsi(const DevParams& p, C ph, C ps) {
+  return -((C)p.dsb * gsw(p, ph) - C(0.5) * (C)p.msb) / (C(1) - ps);
+}
+
+// Laplacian pieces at (x,y): zero-flux part L0 of phi and psi, and the wall
+// terms T = sum over directions into a wetting wall of 2 w_i/c_s^2 J(column),
+// so that the Laplacian with wetting ghosts is L0 + T/kappa (phi) and
+// L0 + T/lambda_s (psi).
+template <class C> struct Lap { C l0p, l0s, Tp, Ts; };
+template <class C>
+__device__ __forceinline__ Lap<C> laplace(const DevParams& p, const C* __restrict__ phi, const C* __restrict__ psi, int x, int y) {
+  const int n = y * p.nx + x;
+  const C ph = phi[n], ps = psi[n];
+  Lap<C> r{C(0), C(0), C(0), C(0)};
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const Nb b = nbr(p, x, y, CX(i), CY(i));
+    const C w2 = C(6) * WQ<C>(i);  // 2 w_i / c_s^2
+    const C pn = phi[b.idx], sn = psi[b.idx];
+    r.l0p += w2 * (pn - ph);
+    r.l0s += w2 * (sn - ps);
+    if (b.side && wet_side(p, b.side)) {
+      r.Tp += w2 * Jphi(p, pn, sn);
+      if (p.surf) r.Ts += w2 * Jpsi(p, pn, sn);
+    }
+  }
+  return r;
+}
+
+// Chemical potentials (eq_muphi, eq_mupsi) from the local values and stencil.
+template <class C> __device__ __forceinline__ C mu_phi_of(const DevParams& p, C ph, C ps, const Lap<C>& L) {
+  return C(4) * (C)p.beta * (C(1) - ps) * (ph * ph * ph - ph) - (C)p.kappa * L.l0p - L.Tp + (C)p.W * ps * ph;
+}
+template <class C> __device__ __forceinline__ C mu_psi_of(const DevParams& p, C ph, C ps, const Lap<C>& L) {
+  if (!p.surf) return C(0);
+  const C q = C(1) - ph * ph;
+  return (C)p.kBT * lg(ps / (C(1) - ps)) - (C)p.lambda_s * L.l0s - L.Ts - (C)p.beta * q * q + C(0.5) * (C)p.W * ph * ph;
+}
+
+// Raw moments c_x^a c_y^b grouped by order: m00 m10 m01 m20 m11 m02 m21 m12 m22.
+template <class C> __device__ __forceinline__ void moments(const C* f, C* m) {
+  m[0] = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  m[1] = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+  m[2] = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  m[3] = f[1] + f[3] + f[5] + f[6] + f[7] + f[8];
+  m[4] = f[5] - f[6] + f[7] - f[8];
+  m[5] = f[2] + f[4] + f[5] + f[6] + f[7] + f[8];
+  m[6] = f[5] + f[6] - f[7] - f[8];
+  m[7] = f[5] - f[6] - f[7] + f[8];
+  m[8] = f[5] + f[6] + f[7] + f[8];
+}
+// Inverse of the raw-moment transform.
+template <class C> __device__ __forceinline__ void populations(const C* m, C* f) {
+  f[0] = m[0] - m[3] - m[5] + m[8];
+  f[1] = C(0.5) * (m[1] + m[3] - m[7] - m[8]);
+  f[2] = C(0.5) * (m[2] + m[5] - m[6] - m[8]);
+  f[3] = C(0.5) * (-m[1] + m[3] + m[7] - m[8]);
+  f[4] = C(0.5) * (-m[2] + m[5] + m[6] - m[8]);
+  f[5] = C(0.25) * (m[4] + m[6] + m[7] + m[8]);
+  f[6] = C(0.25) * (-m[4] + m[6] - m[7] + m[8]);
+  f[7] = C(0.25) * (m[4] - m[6] - m[7] + m[8]);
+  f[8] = C(0.25) * (-m[4] - m[6] + m[7] + m[8]);
+}
+
+// Pressure-based equilibrium of lattice 1 (Sec. 3), direction d.
+template <class C> __device__ __forceinline__ C feq_flow(int d, C pr, C rho, C ux, C uy) {
+  const C cu = C(CX(d)) * ux + C(CY(d)) * uy, uu = ux * ux + uy * uy;
+  const C su = C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu;
+  return C(3) * pr * (WQ<C>(d) - (d == 0 ? C(1) : C(0))) + rho * WQ<C>(d) * su;
+}
+// eta-weighted equilibrium of lattices 2 and 3 (Sec. 3), direction d.
+template <class C> __device__ __forceinline__ C feq_scalar(int d, C c, C eta, C cux, C cuy) {
+  if (d == 0) return c + (WQ<C>(0) - C(1)) * eta * c;
+  return WQ<C>(d) * eta * c + C(3) * WQ<C>(d) * (C(CX(d)) * cux + C(CY(d)) * cuy);
+}
+
+// Block-wide FP64 sum (wave64 shuffles, then LDS across the four waves);
+// the result is valid in thread 0.  Fixed order: bitwise reproducible.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+__device__ double block_reduce(double v, bool is_max) {
+  __shared__ double sh[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  v = is_max ? wave_max(v) : wave_sum(v);
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int k = 1; k < kBlock / 64; ++k) r = is_max ? fmax(r, sh[k]) : r + sh[k];
+    v = r;
+  }
+  __syncthreads();
+  return v;
+}
+
+// ------------------------------------------------------------------- kernels
+template <class S, class C>
+__global__ __launch_bounds__(kBlock) void k_moments(DevParams p, const S* __restrict__ P, C* __restrict__ phipsi) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= p.N) return;
+  const int x = n % p.nx, y = n / p.nx;
+  C a = C(0), b = C(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) a += pull<S, C>(p, P, 1, i, x, y);
+  if (p.surf) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) b += pull<S, C>(p, P, 2, i, x, y);
+  }
+  phipsi[n] = a;
+  phipsi[(size_t)p.N + n] = b;
+}
+
+template <class C>
+__global__ __launch_bounds__(kBlock) void k_mu_partials(DevParams p, const C* __restrict__ phipsi, C* __restrict__ mu,
+                                                        double* __restrict__ partials) {
+  const C* phi = phipsi;
+  const C* psi = phipsi + p.N;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int n = blockIdx.x * kBlock + threadIdx.x; n < p.N; n += gridDim.x * kBlock) {
+    const int x = n % p.nx, y = n / p.nx;
+    const C ph = phi[n], ps = psi[n];
+    const Lap<C> L = laplace(p, phi, psi, x, y);
+    const C mp = mu_phi_of(p, ph, ps, L), ms = mu_psi_of(p, ph, ps, L);
+    mu[n] = mp;
+    mu[(size_t)p.N + n] = ms;
+    const double hp = (double)hprime(p, ph);
+    s1 += hp * (double)mp;
+    s2 += hp * hp;
+    s3 += (double)ms;
+  }
+  s1 = block_reduce(s1, false);
+  s2 = block_reduce(s2, false);
+  s3 = block_reduce(s3, false);
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x + 0] = s1;
+    partials[3 * blockIdx.x + 1] = s2;
+    partials[3 * blockIdx.x + 2] = s3;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_multipliers(int nblk, int N, const double* __restrict__ partials,
+                                                        DevScalars* __restrict__ sc) {
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += kBlock)
+    for (int k = 0; k < 3; ++k) s[k] += partials[3 * b + k];
+  for (int k = 0; k < 3; ++k) s[k] = block_reduce(s[k], false);
+  if (threadIdx.x == 0) {
+    sc->lambda_phi = s[1] > 0.0 ? s[0] / s[1] : 0.0;
+    sc->mubar_psi = s[2] / (double)N;
+  }
+}
+
+// Force, velocity and pressure at (x,y) from the phi/psi and mu planes and the
+// gathered f (O5, O6 of the step).
+template <class C> struct Macro { C rho, ux, uy, pr, Fx, Fy, grx, gry; };
+template <class C>
+__device__ __forceinline__ Macro<C> macro_node(const DevParams& p, const C* __restrict__ phi, const C* __restrict__ psi,
+                                                const C* __restrict__ mup, const C* __restrict__ mus, const C* f, int x, int y) {
+  const int n = y * p.nx + x;
+  const C ph = phi[n], ps = psi[n];
+  Macro<C> M;
+  M.rho = rho_of(p, ph);
+  C grx = 0, gry = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const Nb b = nbr(p, x, y, CX(i), CY(i));
+    const C w3 = C(3) * WQ<C>(i);  // w_i / c_s^2
+    const C pn = phi[b.idx];
+    C rn;
+    if (b.side && wet_side(p, b.side)) rn = rho_of(p, pn + Jphi(p, pn, psi[b.idx]) / (C)p.kappa);
+    else rn = rho_of(p, pn);
+    grx += w3 * C(CX(i)) * rn;
+    gry += w3 * C(CY(i)) * rn;
+    const C mpn = mup[b.idx], msn = mus[b.idx];
+    gpx += w3 * C(CX(i)) * mpn;
+    gpy += w3 * C(CY(i)) * mpn;
+    gsx += w3 * C(CX(i)) * msn;
+    gsy += w3 * C(CY(i)) * msn;
+  }
+  M.grx = grx;
+  M.gry = gry;
+  M.Fx = -ph * gpx - ps * gsx + M.rho * (C)p.gx;
+  M.Fy = -ph * gpy - ps * gsy + M.rho * (C)p.gy;
+  const C jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+  const C jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  M.ux = (jx + C(0.5) * M.Fx) / M.rho;
+  M.uy = (jy + C(0.5) * M.Fy) / M.rho;
+  const C snz = f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  // c_s^2/(1 - w0) = 3/5, w0/(2 c_s^2) = 2/3
+  M.pr = C(0.6) * (snz + C(0.5) * (M.ux * grx + M.uy * gry) - M.rho * C(2.0 / 3.0) * (M.ux * M.ux + M.uy * M.uy));
+  return M;
+}
+
+template <class S, class C>
+__global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const S* __restrict__ Pin, S* __restrict__ Pout,
+                                                    const C* __restrict__ phipsi, const C* __restrict__ phipsi_h,
+                                                    const C* __restrict__ mu, const C* __restrict__ u_h, C* __restrict__ u_out,
+                                                    const C* __restrict__ R_h, C* __restrict__ R_out,
+                                                    const DevScalars* __restrict__ sc, int have_hist) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= p.N) return;
+  const size_t N = (size_t)p.N;
+  const int x = n % p.nx, y = n / p.nx;
+  const C* phi = phipsi;
+  const C* psi = phipsi + N;
+  const C ph = phi[n], ps = psi[n];
+
+  C f[9], g[9], h[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    f[i] = pull<S, C>(p, Pin, 0, i, x, y);
+    g[i] = pull<S, C>(p, Pin, 1, i, x, y);
+    h[i] = p.surf ? pull<S, C>(p, Pin, 2, i, x, y) : C(0);
+  }
+  const Macro<C> M = macro_node(p, phi, psi, mu, mu + N, f, x, y);
+  const C rho = M.rho, ux = M.ux, uy = M.uy;
+
+  // Sources (Sec. 3) with the wall-flux terms; multipliers from the reduction.
+  const Lap<C> L = laplace(p, phi, psi, x, y);
+  const C hp = hprime(p, ph);
+  const C lam = (C)sc->lambda_phi, mub = (C)sc->mubar_psi;
+  const C Rp = (C)p.M_phi * (C(-4) * (C)p.beta * (C(1) - ps) * (ph * ph * ph - ph) - (C)p.W * ps * ph + lam * hp) + (C)p.M_phi * L.Tp;
+  C Rs = C(0);
+  if (p.surf) {
+    const C q = C(1) - ph * ph;
+    Rs = -(C)p.M0 * L.l0s + (C)p.M_psi * (-(C)p.kBT * lg(ps / (C(1) - ps)) + (C)p.beta * q * q - C(0.5) * (C)p.W * ph * ph + mub)
+       + (C)p.M_psi * L.Ts;
+  }
+  // Velocity advecting phi and psi: mean of this and the previous step (removes
+  // the lattice's period-2 staggered momentum from the scalar transport), or
+  // u itself when adv_raw is set.  Backward differences are zero on the first step.
+  C vx = ux, vy = uy;
+  C dpx = 0, dpy = 0, dsx = 0, dsy = 0, dRp = 0, dRs = 0;
+  if (have_hist) {
+    if (!p.adv_raw) {
+      vx = C(0.5) * (ux + u_h[n]);
+      vy = C(0.5) * (uy + u_h[N + n]);
+    }
+    const C vxh = u_h[2 * N + n], vyh = u_h[3 * N + n], phh = phipsi_h[n], psh = phipsi_h[N + n];
+    dpx = ph * vx - phh * vxh;
+    dpy = ph * vy - phh * vyh;
+    dsx = ps * vx - psh * vxh;
+    dsy = ps * vy - psh * vyh;
+    dRp = Rp - R_h[n];
+    dRs = Rs - R_h[N + n];
+  }
+
+  // ---- lattice 1: MRT with the pressure-based equilibrium and A^1 forcing
+  {
+    C m[9], o[9];
+    moments(f, m);
+    const C uu = ux * ux + uy * uy, pr = M.pr;
+    const C meq[9] = {C(0), rho * ux, rho * uy, pr + rho * ux * ux, rho * ux * uy, pr + rho * uy * uy,
+                      rho * uy * C(1.0 / 3.0), rho * ux * C(1.0 / 3.0), (pr + rho * uu) * C(1.0 / 3.0)};
+    const C a = ux * M.grx + uy * M.gry;
+    const C mv[9] = {a, M.Fx, M.Fy, ux * M.grx + uy * M.gry * C(1.0 / 3.0), (ux * M.gry + uy * M.grx) * C(1.0 / 3.0),
+                     uy * M.gry + ux * M.grx * C(1.0 / 3.0), M.Fy * C(1.0 / 3.0), M.Fx * C(1.0 / 3.0), a * C(1.0 / 3.0)};
+    const C s2 = p.s2_local ? C(1) / (C(3) * mud_of(p, ph) / rho + C(0.5)) : (C)p.sf[2];
+    const C rt[9] = {(C)p.sf[0], (C)p.sf[1], (C)p.sf[1], s2, s2, s2, (C)p.sf[3], (C)p.sf[3], (C)p.sf[4]};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m[k] = m[k] - rt[k] * (m[k] - meq[k]) + (C(1) - C(0.5) * rt[k]) * mv[k];
+    populations(m, o);
+    // no-slip walls: moving-wall correction on the populations that will bounce back
+    const bool wb = !p.periodic_y && y == 0 && p.bc_bottom != LBM_BC_FREESLIP;
+    const bool wt = !p.periodic_y && y == p.ny - 1 && p.bc_top != LBM_BC_FREESLIP;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      C v = o[i];
+      if (wb && CY(i) < 0) v -= C(6) * WQ<C>(i) * rho * C(CX(i)) * (C)p.uw_bottom;
+      if (wt && CY(i) > 0) v -= C(6) * WQ<C>(i) * rho * C(CX(i)) * (C)p.uw_top;
+      Pout[(size_t)i * N + n] = (S)v;
+    }
+  }
+  // ---- lattices 2 and 3: eta-equilibria, A^k d_t(c u) forcing, w_i (R + R_t/2)
+  {
+    C m[9], o[9];
+    moments(g, m);
+    const C e = (C)p.eta_phi;
+    const C meq[9] = {ph, ph * vx, ph * vy, e * ph * C(1.0 / 3.0), C(0), e * ph * C(1.0 / 3.0),
+                      ph * vy * C(1.0 / 3.0), ph * vx * C(1.0 / 3.0), e * ph * C(1.0 / 9.0)};
+    const C mv[9] = {C(0), dpx, dpy, C(0), C(0), C(0), dpy * C(1.0 / 3.0), dpx * C(1.0 / 3.0), C(0)};
+    const C Rt = Rp + C(0.5) * dRp;
+    const C src[9] = {Rt, C(0), C(0), Rt * C(1.0 / 3.0), C(0), Rt * C(1.0 / 3.0), C(0), C(0), Rt * C(1.0 / 9.0)};
+    const C rt[9] = {(C)p.sg[0], (C)p.sg[1], (C)p.sg[1], (C)p.sg[2], (C)p.sg[2], (C)p.sg[2], (C)p.sg[3], (C)p.sg[3], (C)p.sg[4]};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m[k] = m[k] - rt[k] * (m[k] - meq[k]) + (C(1) - C(0.5) * rt[k]) * mv[k] + src[k];
+    populations(m, o);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Pout[(size_t)(9 + i) * N + n] = (S)o[i];
+  }
+  if (p.surf) {
+    C m[9], o[9];
+    moments(h, m);
+    const C e = (C)p.eta_psi;
+    const C meq[9] = {ps, ps * vx, ps * vy, e * ps * C(1.0 / 3.0), C(0), e * ps * C(1.0 / 3.0),
+                      ps * vy * C(1.0 / 3.0), ps * vx * C(1.0 / 3.0), e * ps * C(1.0 / 9.0)};
+    const C mv[9] = {C(0), dsx, dsy, C(0), C(0), C(0), dsy * C(1.0 / 3.0), dsx * C(1.0 / 3.0), C(0)};
+    const C Rt = Rs + C(0.5) * dRs;
+    const C src[9] = {Rt, C(0), C(0), Rt * C(1.0 / 3.0), C(0), Rt * C(1.0 / 3.0), C(0), C(0), Rt * C(1.0 / 9.0)};
+    const C rt[9] = {(C)p.sh[0], (C)p.sh[1], (C)p.sh[1], (C)p.sh[2], (C)p.sh[2], (C)p.sh[2], (C)p.sh[3], (C)p.sh[3], (C)p.sh[4]};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m[k] = m[k] - rt[k] * (m[k] - meq[k]) + (C(1) - C(0.5) * rt[k]) * mv[k] + src[k];
+    populations(m, o);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Pout[(size_t)(18 + i) * N + n] = (S)o[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Pout[(size_t)(18 + i) * N + n] = (S)C(0);
+  }
+  u_out[n] = ux;
+  u_out[N + n] = uy;
+  u_out[2 * N + n] = vx;
+  u_out[3 * N + n] = vy;
+  R_out[n] = Rp;
+  R_out[N + n] = Rs;
+}
+
+// Initial fields (Sec. 2.2 equilibrium profile) into the FP64 staging buffer.
+__global__ __launch_bounds__(kBlock) void k_init_fields(DevParams p, double* __restrict__ F) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= p.N) return;
+  const int x = n % p.nx, y = n / p.nx;
+  double dx = x - p.x0, dy = y - p.y0;
+  dx -= p.nx * floor(dx / p.nx + 0.5);
+  if (p.periodic_y) dy -= p.ny * floor(dy / p.ny + 0.5);
+  double d;
+  if (p.init_kind == LBM_INIT_SLAB) d = 0.5 * p.a - fabs(dx);
+  else if (p.init_kind == LBM_INIT_BUBBLE) d = sqrt(dx * dx + dy * dy) - p.R0;
+  else d = p.R0 - sqrt(dx * dx + dy * dy);
+  const size_t N = (size_t)p.N;
+  F[n] = p.phib * tanh(p.init_scale * d);
+  F[N + n] = p.surf ? p.psi_b : 0.0;
+  F[2 * N + n] = 0.0;
+  F[3 * N + n] = 0.0;
+}
+
+// Equilibrium populations of the staged fields (phi, psi, ux, uy), stored in
+// the pull layout: the stored value at z for direction j is the population
+// that a gather will deliver, i.e. the inverse of `pull`.
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_load(DevParams p, const double* __restrict__ F, int with_u, S* __restrict__ P) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= p.N) return;
+  const size_t N = (size_t)p.N;
+  const int x = n % p.nx, y = n / p.nx;
+#pragma unroll
+  for (int lat = 0; lat < 3; ++lat) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      // receiver node w and direction d whose gather reads stored_j(z)
+      int wx = wrap(x + CX(j), p.nx), wy = y + CY(j), d = j;
+      if (p.periodic_y) wy = wrap(wy, p.ny);
+      else if (wy < 0 || wy >= p.ny) {
+        const int bc = wy < 0 ? p.bc_bottom : p.bc_top;
+        if (lat == 0 && bc == LBM_BC_FREESLIP) { wy = y; d = MIRY(j); }
+        else { wx = x; wy = y; d = OPP(j); }
+      }
+      const size_t w = (size_t)wy * p.nx + wx;
+      const double ph = F[w], ps = p.surf ? F[N + w] : 0.0;
+      const double ux = with_u ? F[2 * N + w] : 0.0, uy = with_u ? F[3 * N + w] : 0.0;
+      double v;
+      if (lat == 0) v = with_u ? feq_flow<double>(d, 0.0, rho_of(p, ph), ux, uy) : 0.0;
+      else if (lat == 1) v = feq_scalar<double>(d, ph, p.eta_phi, ph * ux, ph * uy);
+      else v = p.surf ? feq_scalar<double>(d, ps, p.eta_psi, ps * ux, ps * uy) : 0.0;
+      P[(size_t)(9 * lat + j) * N + n] = (S)v;
+    }
+  }
+}
+
+// Macroscopic fields of the current state: phi psi ux uy p rho mu_phi mu_psi.
+template <class S, class C>
+__global__ __launch_bounds__(kBlock) void k_fields(DevParams p, const S* __restrict__ P, const C* __restrict__ phipsi,
+                                                   const C* __restrict__ mu, double* __restrict__ out) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= p.N) return;
+  const size_t N = (size_t)p.N;
+  const int x = n % p.nx, y = n / p.nx;
+  C f[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = pull<S, C>(p, P, 0, i, x, y);
+  const Macro<C> M = macro_node(p, phipsi, phipsi + N, mu, mu + N, f, x, y);
+  out[n] = (double)phipsi[n];
+  out[N + n] = (double)phipsi[N + n];
+  out[2 * N + n] = (double)M.ux;
+  out[3 * N + n] = (double)M.uy;
+  out[4 * N + n] = (double)M.pr;
+  out[5 * N + n] = (double)M.rho;
+  out[6 * N + n] = (double)mu[n];
+  out[7 * N + n] = (double)mu[N + n];
+}
+
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_pops(DevParams p, const S* __restrict__ P, double* __restrict__ out) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= p.N) return;
+  const int x = n % p.nx, y = n / p.nx;
+  for (int lat = 0; lat < 3; ++lat)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[(size_t)(9 * lat + i) * p.N + n] = pull<S, double>(p, P, lat, i, x, y);
+}
+
+// Positive fraction of a linear triangle / segment (two-triangle area, Sec. 4.1).
+__device__ double tri_frac(double a, double b, double c) {
+  const int np = (a > 0) + (b > 0) + (c > 0);
+  if (np == 3) return 1.0;
+  if (np == 0) return 0.0;
+  if (np == 1) {
+    const double pp = a > 0 ? a : (b > 0 ? b : c);
+    const double q = a > 0 ? b : (b > 0 ? c : a);
+    const double r = a > 0 ? c : (b > 0 ? a : b);
+    return pp * pp / ((pp - q) * (pp - r));
+  }
+  const double m = a <= 0 ? a : (b <= 0 ? b : c);
+  const double q = a <= 0 ? b : (b <= 0 ? c : a);
+  const double r = a <= 0 ? c : (b <= 0 ? a : b);
+  return 1.0 - m * m / ((m - q) * (m - r));
+}
+__device__ double seg_frac(double a, double b) {
+  if (a > 0 && b > 0) return 1.0;
+  if (a <= 0 && b <= 0) return 0.0;
+  return a > 0 ? a / (a - b) : b / (b - a);
+}
+
+constexpr int kInv = kInvValues;
+constexpr double kPi = 3.14159265358979323846;
+
+template <class S, class C>
+__global__ __launch_bounds__(kBlock) void k_invariants(DevParams p, const S* __restrict__ P, const C* __restrict__ phipsi,
+                                                       const C* __restrict__ mu, double* __restrict__ partials) {
+  const size_t N = (size_t)p.N;
+  const C* phi = phipsi;
+  const C* psi = phipsi + N;
+  double acc[kInv];
+  for (int k = 0; k < kInv; ++k) acc[k] = 0.0;
+  for (int n = blockIdx.x * kBlock + threadIdx.x; n < p.N; n += gridDim.x * kBlock) {
+    const int x = n % p.nx, y = n / p.nx;
+    C f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = pull<S, C>(p, P, 0, i, x, y);
+    const Macro<C> M = macro_node(p, phi, psi, mu, mu + N, f, x, y);
+    const double ph = phi[n], ps = psi[n], ux = M.ux, uy = M.uy, pr = M.pr, rho = M.rho;
+    if (!isfinite(ph) || !isfinite(ps) || !isfinite(ux) || !isfinite(uy) || !isfinite(pr)) acc[7] += 1.0;
+    if (p.surf && !(ps > 0.0 && ps < 1.0)) acc[8] += 1.0;
+    acc[0] += ps;
+    acc[1] += 0.5 + (double)gsw<double>(p, ph);
+    acc[2] += ph;
+    const double u2 = ux * ux + uy * uy;
+    acc[4] += 0.5 * rho * u2;
+    acc[6] = fmax(acc[6], sqrt(u2));
+    // free-energy density with isotropic gradients; wetting ghosts from the BCs
+    double gpx = 0, gpy = 0, gsx = 0, gsy = 0;
+    for (int i = 1; i < 9; ++i) {
+      const Nb b = nbr(p, x, y, CX(i), CY(i));
+      double vp = phi[b.idx], vs = psi[b.idx];
+      if (b.side && wet_side(p, b.side)) {
+        const double pn = vp, sn = vs;
+        vp = pn + Jphi<double>(p, pn, sn) / p.kappa;
+        if (p.surf && p.lambda_s > 0.0) vs = sn + Jpsi<double>(p, pn, sn) / p.lambda_s;
+      }
+      const double w3 = 3.0 * WQ<double>(i);
+      gpx += w3 * CX(i) * vp; gpy += w3 * CY(i) * vp;
+      gsx += w3 * CX(i) * vs; gsy += w3 * CY(i) * vs;
+    }
+    double e = p.beta * (ph * ph - 1.0) * (ph * ph - 1.0) + 0.5 * p.kappa * (gpx * gpx + gpy * gpy);
+    if (p.surf)
+      e += p.kBT * (ps * log(ps) + (1.0 - ps) * log(1.0 - ps)) + 0.5 * p.lambda_s * (gsx * gsx + gsy * gsy)
+         - p.beta * ps * (1.0 - ph * ph) * (1.0 - ph * ph) + 0.5 * p.W * ps * ph * ph;
+    // wall energy and Remark-1 regime on wetting-wall rows
+    const bool wall_row_b = !p.periodic_y && y == 0 && p.wet_bottom;
+    const bool wall_row_t = !p.periodic_y && y == p.ny - 1 && p.wet_top;
+    for (int w = 0; w < 2; ++w) {
+      if (!(w == 0 ? wall_row_b : wall_row_t)) continue;
+      const double l = p.surf ? log(1.0 - ps) : 0.0;
+      e += -(p.sig_cos + l * p.dsb) * (double)gsw<double>(p, ph) + 0.5 * l * p.msb + p.fw0;
+      if (p.surf) {
+        if (p.beta_sg > 0.0 && 1.0 + p.beta_sg * l <= 0.5) acc[9] += 1.0;
+        if (p.beta_sl > 0.0 && 1.0 + p.beta_sl * l <= 0.5) acc[9] += 1.0;
+      }
+    }
+    acc[5] += e;
+    // area of phi > 0: the cell whose lower-left corner is this node, and the
+    // half cells between a wall and the first row
+    const int x1 = x + 1 == p.nx ? 0 : x + 1;
+    if (p.periodic_y || y + 1 < p.ny) {
+      const int y1 = y + 1 == p.ny ? 0 : y + 1;
+      const double a = ph, b = phi[(size_t)y * p.nx + x1], c = phi[(size_t)y1 * p.nx + x1], d = phi[(size_t)y1 * p.nx + x];
+      acc[3] += 0.5 * tri_frac(a, b, c) + 0.5 * tri_frac(a, c, d);
+    }
+    if (!p.periodic_y && y == 0) acc[3] += 0.5 * seg_frac(ph, (double)phi[x1]);
+    if (!p.periodic_y && y == p.ny - 1) acc[3] += 0.5 * seg_frac(ph, (double)phi[(size_t)y * p.nx + x1]);
+  }
+  for (int k = 0; k < kInv; ++k) {
+    const double r = block_reduce(acc[k], k == 6);
+    if (threadIdx.x == 0) partials[(size_t)kInv * blockIdx.x + k] = r;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_inv_final(int nblk, const double* __restrict__ partials, double* __restrict__ out) {
+  for (int k = 0; k < kInv; ++k) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+      const double q = partials[(size_t)kInv * b + k];
+      v = k == 6 ? fmax(v, q) : v + q;
+    }
+    v = block_reduce(v, k == 6);
+    if (threadIdx.x == 0) out[k] = v;
+  }
+}
+
+// Contact diagnostics on the bottom wall (y = -1/2): per column, the height
+// above the wall of the first phi = 0 crossing of a liquid column, and the
+// positive fractions of the edges to the next column on the first and second
+// rows; the width is their sums extrapolated linearly to the wall.
+template <class C>
+__global__ __launch_bounds__(kBlock) void k_contact_cols(DevParams p, const C* __restrict__ phi, double* __restrict__ cols) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  if (x >= p.nx) return;
+  const int x1 = x + 1 == p.nx ? 0 : x + 1;
+  cols[p.nx + x] = seg_frac((double)phi[x], (double)phi[x1]);
+  cols[2 * p.nx + x] = seg_frac((double)phi[p.nx + x], (double)phi[p.nx + x1]);
+  double hx = 0.0;
+  if (phi[x] > C(0)) {
+    hx = p.ny - 0.5;
+    for (int y = 0; y + 1 < p.ny; ++y) {
+      const double a = phi[(size_t)y * p.nx + x], b = phi[(size_t)(y + 1) * p.nx + x];
+      if (a > 0 && b <= 0) { hx = y + a / (a - b) + 0.5; break; }
+    }
+  }
+  cols[x] = hx;
+}
+__global__ __launch_bounds__(kBlock) void k_contact_final(int nx, const double* __restrict__ cols, double* __restrict__ out) {
+  double L0 = 0.0, L1 = 0.0, H = 0.0;
+  for (int x = threadIdx.x; x < nx; x += kBlock) {
+    L0 += cols[nx + x];
+    L1 += cols[2 * nx + x];
+    H = fmax(H, cols[x]);
+  }
+  L0 = block_reduce(L0, false);
+  L1 = block_reduce(L1, false);
+  H = block_reduce(H, true);
+  if (threadIdx.x == 0) {
+    double L = L0 > 0.0 ? L0 + 0.5 * (L0 - L1) : 0.0;
+    if (L < 0.0) L = 0.0;
+    out[0] = L;
+    out[1] = H;
+    out[2] = L > 0.0 ? 2.0 * atan(2.0 * H / L) * 180.0 / kPi : 180.0;
+  }
+}
+
+inline int nblocks(int n) { return (n + kBlock - 1) / kBlock; }
+inline int red_blocks(int n) { int b = nblocks(n); return b < kRedBlocks ? b : kRedBlocks; }
+
+template <class S, class C>
+hipError_t step_impl(const DevParams& p, DevState& s, int have_hist, hipStream_t st) {
+  const size_t N = (size_t)p.N;
+  const S* Pin = (const S*)s.pops[s.cur];
+  S* Pout = (S*)s.pops[s.cur ^ 1];
+  C* pp = (C*)s.phipsi[s.hcur];
+  const C* pp_h = (const C*)s.phipsi[s.hcur ^ 1];
+  C* mu = (C*)s.mu;
+  const int rb = red_blocks(p.N);
+  hipLaunchKernelGGL((k_moments<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, Pin, pp);
+  hipLaunchKernelGGL((k_mu_partials<C>), dim3(rb), dim3(kBlock), 0, st, p, (const C*)pp, mu, s.partials);
+  hipLaunchKernelGGL(k_multipliers, dim3(1), dim3(kBlock), 0, st, rb, p.N, (const double*)s.partials, s.scalars);
+  hipLaunchKernelGGL((k_collide<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, Pin, Pout, (const C*)pp, pp_h,
+                     (const C*)mu, (const C*)s.uhist[s.hcur ^ 1], (C*)s.uhist[s.hcur], (const C*)s.Rhist[s.hcur ^ 1],
+                     (C*)s.Rhist[s.hcur], (const DevScalars*)s.scalars, have_hist);
+  (void)N;
+  s.cur ^= 1;
+  s.hcur ^= 1;
+  return hipGetLastError();
+}
+
+template <class S, class C>
+hipError_t macro_impl(const DevParams& p, DevState& s, hipStream_t st) {
+  C* pp = (C*)s.phipsi[s.hcur];
+  const int rb = red_blocks(p.N);
+  hipLaunchKernelGGL((k_moments<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur], pp);
+  hipLaunchKernelGGL((k_mu_partials<C>), dim3(rb), dim3(kBlock), 0, st, p, (const C*)pp, (C*)s.mu, s.partials);
+  hipLaunchKernelGGL(k_multipliers, dim3(1), dim3(kBlock), 0, st, rb, p.N, (const double*)s.partials, s.scalars);
+  return hipGetLastError();
+}
+
+template <class S, class C>
+hipError_t inv_impl(const DevParams& p, DevState& s, hipStream_t st) {
+  hipError_t e = macro_impl<S, C>(p, s, st);
+  if (e != hipSuccess) return e;
+  const int rb = red_blocks(p.N);
+  hipLaunchKernelGGL((k_invariants<S, C>), dim3(rb), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur],
+                     (const C*)s.phipsi[s.hcur], (const C*)s.mu, s.inv_partials);
+  hipLaunchKernelGGL(k_inv_final, dim3(1), dim3(kBlock), 0, st, rb, (const double*)s.inv_partials, s.inv_out);
+  if (!p.periodic_y) {
+    hipLaunchKernelGGL((k_contact_cols<C>), dim3(nblocks(p.nx)), dim3(kBlock), 0, st, p, (const C*)s.phipsi[s.hcur], s.contact);
+    hipLaunchKernelGGL(k_contact_final, dim3(1), dim3(kBlock), 0, st, p.nx, (const double*)s.contact, s.inv_out + kInv);
+  }
+  return hipGetLastError();
+}
+
+template <class S, class C>
+hipError_t fetch_impl(const DevParams& p, DevState& s, hipStream_t st) {
+  hipError_t e = macro_impl<S, C>(p, s, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fields<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur],
+                     (const C*)s.phipsi[s.hcur], (const C*)s.mu, s.field_buf);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t storage_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2); }
+size_t compute_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
+
+#define LBM_DISPATCH(prec, call64, call32)            \
+  switch (prec) {                                     \
+    case LBM_FP64: return call64;                     \
+    case LBM_FP32: return call32;                     \
+    default: return hipErrorInvalidValue;             \
+  }
+
+hipError_t launch_init(const DevParams& p, DevState& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_fields, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, s.field_buf);
+  return launch_load(p, s, 0, st);
+}
+
+hipError_t launch_load(const DevParams& p, DevState& s, int with_u, hipStream_t st) {
+  switch (s.precision) {
+    case LBM_FP64:
+      hipLaunchKernelGGL(k_load<double>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const double*)s.field_buf, with_u,
+                         (double*)s.pops[s.cur]);
+      break;
+    case LBM_FP32:
+      hipLaunchKernelGGL(k_load<float>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const double*)s.field_buf, with_u,
+                         (float*)s.pops[s.cur]);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st) {
+  LBM_DISPATCH(s.precision, (step_impl<double, double>(p, s, have_hist, st)), (step_impl<float, float>(p, s, have_hist, st)));
+}
+hipError_t launch_macro(const DevParams& p, DevState& s, hipStream_t st) {
+  LBM_DISPATCH(s.precision, (macro_impl<double, double>(p, s, st)), (macro_impl<float, float>(p, s, st)));
+}
+hipError_t launch_invariants(const DevParams& p, DevState& s, hipStream_t st) {
+  LBM_DISPATCH(s.precision, (inv_impl<double, double>(p, s, st)), (inv_impl<float, float>(p, s, st)));
+}
+hipError_t launch_fetch(const DevParams& p, DevState& s, uint32_t, hipStream_t st) {
+  LBM_DISPATCH(s.precision, (fetch_impl<double, double>(p, s, st)), (fetch_impl<float, float>(p, s, st)));
+}
+hipError_t launch_fetch_pops(const DevParams& p, DevState& s, hipStream_t st) {
+  switch (s.precision) {
+    case LBM_FP64:
+      hipLaunchKernelGGL(k_pops<double>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const double*)s.pops[s.cur], s.field_buf);
+      break;
+    case LBM_FP32:
+      hipLaunchKernelGGL(k_pops<float>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const float*)s.pops[s.cur], s.field_buf);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,230 @@
+"""Python binding of the gfx950 lattice Boltzmann library (include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``liblbm_hip.so``.  PyTorch supplies the device memory (one uint8 tensor
+per simulation, handed to ``lbm_init`` as ``dev_buf``) and the HIP stream.
+There is no CPU fallback: without the built library or a gfx950 device every
+entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+import torch  # noqa: F401  -- loads torch's HIP runtime first so one runtime serves both
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
+
+ABI_VERSION = 1
+PERIODIC, WALL_WET, NOSLIP, FREESLIP = 0, 1, 2, 3
+FP64, FP32, FP16_SHIFTED = 0, 1, 2
+NONLINEAR, LINEAR = 0, 1
+INIT_DROP, INIT_SLAB, INIT_BUBBLE = 0, 1, 2
+FIELD_NAMES = ["phi", "psi", "ux", "uy", "p", "rho", "mu_phi", "mu_psi"]
+DERIVED_NAMES = ["kappa", "beta", "W", "kBT", "phi_b", "sigma_sg0", "sigma_sl0",
+                 "lambda_s", "M0", "eta_phi", "eta_psi", "psi_c"]
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16_SHIFTED}
+STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_UNSUPPORTED", -3: "LBM_E_OOM", -4: "LBM_E_DEVICE",
+          -5: "LBM_E_NONFINITE", -6: "LBM_E_RANGE", -7: "LBM_E_STATE"}
+
+# Every symbol the header declares; the test suite checks the library exports them.
+EXPORTS = ["lbm_required_bytes", "lbm_init", "lbm_step", "lbm_reduce_invariants", "lbm_fetch_fields",
+           "lbm_load_fields", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_derived",
+           "lbm_fetch_populations", "lbm_destroy", "lbm_last_error"]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("bc_bottom", ctypes.c_int32), ("bc_top", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("constraint_phi", ctypes.c_int32), ("init_kind", ctypes.c_int32),
+        ("adv_raw", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("sigma_gl0", ctypes.c_double), ("eps", ctypes.c_double),
+        ("M_phi", ctypes.c_double), ("M_psi", ctypes.c_double), ("lambda_s", ctypes.c_double),
+        ("kBT", ctypes.c_double), ("W", ctypes.c_double), ("Ex", ctypes.c_double), ("Pi", ctypes.c_double),
+        ("psi_b", ctypes.c_double), ("phi_b", ctypes.c_double), ("theta0_deg", ctypes.c_double),
+        ("sigma_sg0", ctypes.c_double), ("sigma_sl0", ctypes.c_double),
+        ("beta_sg", ctypes.c_double), ("beta_sl", ctypes.c_double),
+        ("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double), ("mu_l", ctypes.c_double), ("mu_g", ctypes.c_double),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+        ("u_wall_bottom", ctypes.c_double), ("u_wall_top", ctypes.c_double),
+        ("eta_phi", ctypes.c_double), ("eta_psi", ctypes.c_double), ("M0", ctypes.c_double),
+        ("s_f", ctypes.c_double * 5), ("s_g", ctypes.c_double * 5), ("s_h", ctypes.c_double * 5),
+        ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("R0", ctypes.c_double),
+        ("a", ctypes.c_double), ("b", ctypes.c_double),
+    ]
+
+
+class Invariants(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("nonfinite", ctypes.c_int64), ("psi_out_of_range", ctypes.c_int64),
+        ("cap_violations", ctypes.c_int64),
+        ("mass_psi", ctypes.c_double), ("m_phi_h", ctypes.c_double), ("sum_phi", ctypes.c_double),
+        ("area_phi_pos", ctypes.c_double), ("kinetic", ctypes.c_double), ("free_energy", ctypes.c_double),
+        ("umax", ctypes.c_double), ("lambda_phi", ctypes.c_double), ("mubar_psi", ctypes.c_double),
+        ("contact_width", ctypes.c_double), ("cap_height", ctypes.c_double), ("theta_app_deg", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t
+        L.lbm_required_bytes.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(sz)]
+        L.lbm_init.argtypes = [ctypes.POINTER(Params), vp, sz, vp, ctypes.POINTER(vp)]
+        L.lbm_step.argtypes = [vp, ctypes.c_int64]
+        L.lbm_reduce_invariants.argtypes = [vp, ctypes.POINTER(Invariants)]
+        L.lbm_fetch_fields.argtypes = [vp, ctypes.c_uint32, dp, sz]
+        L.lbm_load_fields.argtypes = [vp, ctypes.c_uint32, dp, sz]
+        L.lbm_state_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.lbm_save_state.argtypes = [vp, vp, sz]
+        L.lbm_load_state.argtypes = [vp, vp, sz]
+        L.lbm_derived.argtypes = [vp, dp]
+        L.lbm_fetch_populations.argtypes = [vp, dp, sz]
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_last_error.argtypes = [vp]
+        L.lbm_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "lbm_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def make_params(cfg: dict, precision: int) -> Params:
+    """Map a configuration dictionary (paper_2609_26332_amd.inputs) onto lbm_params."""
+    p = Params()
+    defaults = dict(lambda_s=-1.0, kBT=0.0, W=0.0, Ex=0.5, Pi=1.35, phi_b=0.0, sigma_sg0=-1.0, sigma_sl0=-1.0,
+                    eta_phi=0.0, eta_psi=0.0, M0=-1.0, theta0_deg=90.0, rho_l=1.0, rho_g=1.0, mu_l=0.1, mu_g=0.1)
+    merged = dict(defaults)
+    merged.update(cfg)
+    names = {f for f, _ in Params._fields_}
+    for k, v in merged.items():
+        if k not in names:
+            continue
+        if k in ("s_f", "s_g", "s_h"):
+            setattr(p, k, (ctypes.c_double * 5)(*v))
+        else:
+            setattr(p, k, v)
+    p.abi_version = ABI_VERSION
+    p.precision = precision
+    return p
+
+
+def _check(rc: int, handle=None):
+    if rc != 0:
+        msg = lib().lbm_last_error(handle).decode()
+        raise LbmError(rc, msg)
+
+
+def required_bytes(cfg: dict, precision: str = "fp64") -> int:
+    p = make_params(cfg, PRECISIONS[precision])
+    n = ctypes.c_size_t()
+    _check(lib().lbm_required_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+class Sim:
+    """One simulation on the current HIP device.
+
+    Device memory comes from a torch uint8 tensor owned by this object and
+    work is ordered on torch's current stream (or the stream given)."""
+
+    def __init__(self, cfg: dict, precision: str = "fp64", stream: "torch.cuda.Stream | None" = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to torch; the lattice Boltzmann path has no CPU fallback")
+        self.cfg = dict(cfg)
+        self.precision = precision
+        self.params = make_params(cfg, PRECISIONS[precision])
+        self.nx, self.ny = self.params.nx, self.params.ny
+        nbytes = required_bytes(cfg, precision)
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = lib().lbm_init(ctypes.byref(self.params), ctypes.c_void_p(self.buffer.data_ptr()), nbytes,
+                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        _check(rc, None)
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        _check(lib().lbm_step(self._h, int(n)), self._h)
+
+    def invariants(self, check: bool = True) -> dict:
+        inv = Invariants()
+        rc = lib().lbm_reduce_invariants(self._h, ctypes.byref(inv))
+        if check:
+            _check(rc, self._h)
+        d = inv.as_dict()
+        d["status"] = rc
+        return d
+
+    def fields(self, names=None) -> dict:
+        names = names or FIELD_NAMES
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELD_NAMES.index(nm)
+        sel = [nm for nm in FIELD_NAMES if mask & (1 << FIELD_NAMES.index(nm))]
+        out = np.zeros((len(sel), self.ny, self.nx))
+        _check(lib().lbm_fetch_fields(self._h, mask, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size), self._h)
+        return {nm: out[k] for k, nm in enumerate(sel)}
+
+    def load_fields(self, phi, psi, ux=None, uy=None):
+        planes = [phi, psi] + ([ux, uy] if ux is not None else [])
+        arr = np.ascontiguousarray(np.stack([np.asarray(a, dtype=np.float64) for a in planes]))
+        mask = 1 | 2 | ((4 | 8) if ux is not None else 0)
+        _check(lib().lbm_load_fields(self._h, mask, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), arr.size), self._h)
+
+    def populations(self) -> np.ndarray:
+        out = np.zeros((27, self.ny, self.nx))
+        _check(lib().lbm_fetch_populations(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size), self._h)
+        return out
+
+    def derived(self) -> dict:
+        out = np.zeros(len(DERIVED_NAMES))
+        _check(lib().lbm_derived(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._h)
+        return dict(zip(DERIVED_NAMES, out.tolist()))
+
+    def save_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        _check(lib().lbm_state_bytes(self._h, ctypes.byref(n)), self._h)
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().lbm_save_state(self._h, buf, n.value), self._h)
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(lib().lbm_load_state(self._h, buf, len(blob)), self._h)

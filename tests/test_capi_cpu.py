@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI that need no GPU: the built library loads,
+exports every function include/lbm.h declares, validates parameter sets and
+refuses to run without a gfx950 device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+LIB = os.path.join(ROOT, "paper_2609_26332_amd", "liblbm_hip.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    if not os.path.exists(LIB):
+        pytest.fail("liblbm_hip.so is not built; run __graft_entry__.build()")
+    from paper_2609_26332_amd import lbm as binding
+
+    return binding
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lbm_init", "lbm_step", "lbm_reduce_invariants", "lbm_fetch_fields", "lbm_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lbm):
+    L = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert sorted(lbm.EXPORTS) == declared_functions()
+
+
+def test_param_struct_layout_matches_header(lbm):
+    # 10 int32 (40 bytes) then doubles: the binding must agree with the header
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct {", text.index("LBM_INIT_BUBBLE")):text.index("} lbm_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    n_int = sum(len(re.findall(r"[a-z_0-9]+(?:\[\d+\])?", decl.split(None, 1)[1]))
+                for decl in re.findall(r"int32_t[^;]+;", body))
+    n_dbl = 0
+    for decl in re.findall(r"double[^;]+;", body):
+        for item in decl[len("double"):].strip(" ;").split(","):
+            m = re.search(r"\[(\d+)\]", item)
+            n_dbl += int(m.group(1)) if m else 1
+    assert ctypes.sizeof(lbm.Params) == 4 * n_int + 8 * n_dbl
+    assert lbm.Params.sigma_gl0.offset == 4 * n_int
+
+
+def test_required_bytes_and_validation(lbm):
+    from paper_2609_26332_amd import inputs
+
+    cfg = inputs.stationary_drop()
+    n64 = lbm.required_bytes(cfg, "fp64")
+    n32 = lbm.required_bytes(cfg, "fp32")
+    N = 64 * 64
+    assert n64 > 2 * 27 * N * 8 and n32 > 2 * 27 * N * 4 and n64 > n32
+    bad = [dict(cfg, nx=2), dict(cfg, psi_b=1.0), dict(cfg, bc_bottom=inputs.WALL_WET),
+           dict(cfg, s_g=[1, 2.5, 1, 1, 1]), dict(cfg, sigma_gl0=0.0)]
+    wet = inputs.sessile_drop(nx=32, ny=16, R=5)
+    bad.append(dict(wet, theta0_deg=0.0))
+    bad.append(dict(wet, lambda_s=0.0))  # adsorbing wall needs lambda_s > 0
+    for b in bad:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.required_bytes(b, "fp64")
+        assert e.value.code == -1
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is present")
+def test_init_without_device_reports_device_error(lbm):
+    from paper_2609_26332_amd import inputs
+
+    p = lbm.make_params(inputs.stationary_drop(nx=16, ny=16, R=4), lbm.FP64)
+    h = ctypes.c_void_p()
+    rc = lbm.lib().lbm_init(ctypes.byref(p), None, 0, None, ctypes.byref(h))
+    assert rc == -4 and not h.value
+    assert b"device" in lbm.lib().lbm_last_error(None).lower()
