@@ -1,0 +1,127 @@
+#!/usr/bin/env python3
+"""Benchmark of the coupled three-lattice lattice Boltzmann step on one MI355X.
+
+Metric: MLUPS (million lattice-node updates per second; one update advances
+all three lattices f, g, h), with the achieved fraction of the HBM roofline,
+on the sessile-droplet-on-an-adsorbing-solid workload (256 x 128 D2Q9,
+half-way bounce-back wetting/adsorbing bottom wall, free-slip top, semicircle
+R0 = 40, psi_b = 0.02, theta0 = 60 deg, adsorption strength drawn from seed 2),
+FP32 storage with FP64 reductions.  A second, cache-exceeding grid (4096^2
+periodic drop, same physics family) is timed to show the HBM-bound regime.
+
+Prints one JSON line.  The FP64 CPU oracle is timed beside it on the host
+(bounded sample) as cpu_baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def gpu_run(cfg, precision, steps, warmup):
+    import torch
+    from paper_2609_26332_amd import lbm
+
+    sim = lbm.Sim(cfg, precision)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.timing_begin(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = sim.timing_end()
+    inv = sim.invariants(check=False)
+    N = cfg["nx"] * cfg["ny"]
+    return dict(sim=sim, wall=wall, kernels=kt, N=N, inv=inv, bytes_node=sim.bytes_per_node_step())
+
+
+def roofline(res):
+    """Achieved HBM bandwidth of the step kernels on their algorithmic bytes."""
+    kt = res["kernels"]
+    n = max(v[1] for v in kt.values())
+    step_ms = sum(v[0] for v in kt.values()) / n
+    dom = max(kt, key=lambda k: kt[k][0])
+    bytes_step = res["bytes_node"] * res["N"]
+    achieved = bytes_step / (step_ms * 1e-3) / 1e9
+    return {
+        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": "one step (%s)" % ", ".join(kt), "dominant_kernel": dom,
+        "bytes_per_node_step": res["bytes_node"], "nodes": res["N"],
+        "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in kt.items()},
+    }
+
+
+def cpu_baseline(cfg, budget_s=15.0):
+    import oracle
+
+    oracle.build(force=False)
+    s = oracle.OracleSim(cfg)
+    t0 = time.perf_counter()
+    s.step(10)
+    t1 = time.perf_counter()
+    per = max((t1 - t0) / 10, 1e-6)
+    n = max(10, int(budget_s / per))
+    t0 = time.perf_counter()
+    s.step(n)
+    dt = time.perf_counter() - t0
+    N = cfg["nx"] * cfg["ny"]
+    return {"value": round(N * n / dt / 1e6, 4), "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "%d steps of the same %dx%d workload after 10 warm-up steps, FP64 oracle, %.1f s"
+                      % (n, cfg["nx"], cfg["ny"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--large-steps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+    from paper_2609_26332_amd import inputs
+
+    cfg = inputs.sessile_drop()
+    res = gpu_run(cfg, args.precision, args.steps, args.warmup)
+    mlups = res["N"] * args.steps / res["wall"] / 1e6
+    out = {
+        "metric": "MLUPS (3 coupled lattices) + HBM roofline %",
+        "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(res["wall"] * 1e3 / args.steps, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "sessile drop on adsorbing solid, 256x128 D2Q9, FP32 storage, FP64 reductions",
+                   "nx": cfg["nx"], "ny": cfg["ny"], "theta0_deg": cfg["theta0_deg"], "psi_b": cfg["psi_b"],
+                   "beta_sg": round(cfg["beta_sg"], 6), "precision": args.precision},
+        "lattice_mlups": round(3 * mlups, 2),
+        "roofline": roofline(res),
+    }
+    if res["inv"]["nonfinite"]:
+        out["warning"] = "non-finite fields after the timed run"
+    if not args.no_large:
+        big = inputs.roofline_grid()
+        rb = gpu_run(big, args.precision, args.large_steps, 10)
+        rl = roofline(rb)
+        out["large_grid"] = {"workload": "periodic drop 4096x4096 (state beyond the on-die caches)",
+                             "mlups": round(rb["N"] * args.large_steps / rb["wall"] / 1e6, 1), "roofline": rl}
+        del rb
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

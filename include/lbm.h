@@ -149,8 +149,10 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
 int lbm_step(lbm_handle* h, int64_t n);
 
 /* Diagnostics of the current state (FP64 sums on the device), then one small
- * device-to-host copy; synchronises the stream.  Returns LBM_E_NONFINITE or
- * LBM_E_RANGE (with *out filled) when the fields are unhealthy. */
+ * device-to-host copy; synchronises the stream.  Returns LBM_E_RANGE when psi
+ * left (0,1), else LBM_E_NONFINITE when a field is not finite (*out filled in
+ * both cases); either latches the handle so that lbm_step returns LBM_E_STATE
+ * until lbm_load_fields or lbm_load_state replaces the state. */
 int lbm_reduce_invariants(lbm_handle* h, lbm_invariants* out);
 
 /* Macroscopic fields of the current state (time n, before its collision) as
@@ -176,6 +178,21 @@ int lbm_derived(lbm_handle* h, double* out);
 /* Populations of the current state as FP64 [27][ny][nx] (f0..f8, g0..g8,
  * h0..h8, post-streaming at time n).  Synchronises the stream. */
 int lbm_fetch_populations(lbm_handle* h, double* host, size_t n_doubles);
+
+/* Kernel timing with HIP events on the handle's stream.  lbm_timing_begin
+ * creates event pairs for up to max_steps steps; every following lbm_step
+ * brackets each of its kernels (LBM_K_* below) with an event pair until the
+ * pairs run out.  lbm_timing_end synchronises the stream and writes, per
+ * kernel kind, the summed duration in ms (ms[LBM_N_KERNELS]) and the number of
+ * launches timed (launches[LBM_N_KERNELS]); it releases the events. */
+enum { LBM_K_MOMENTS = 0, LBM_K_MU = 1, LBM_K_MULTIPLIERS = 2, LBM_K_COLLIDE = 3, LBM_N_KERNELS = 4 };
+int lbm_timing_begin(lbm_handle* h, int64_t max_steps);
+int lbm_timing_end(lbm_handle* h, double* ms, int64_t* launches);
+
+/* Bytes of HBM state one step of this handle must read and write per node:
+ * the 27 populations, the FP64 phi/psi planes and the velocity and source
+ * history (the algorithmic traffic of the step). */
+int lbm_bytes_per_node_step(lbm_handle* h, double* bytes);
 
 /* Release the handle and any library-owned device memory and stream. */
 int lbm_destroy(lbm_handle* h);

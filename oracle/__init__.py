@@ -106,6 +106,7 @@ def lib():
         L.orc_area_positive.restype = ctypes.c_double
         L.orc_area_positive.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_contact.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -212,3 +213,7 @@ def contact(phi: np.ndarray):
     w, h, t = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     lib().orc_contact(_dptr(phi), nx, ny, ctypes.byref(w), ctypes.byref(h), ctypes.byref(t))
     return w.value, h.value, t.value
+
+
+def threads() -> int:
+    return lib().orc_threads()

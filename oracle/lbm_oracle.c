@@ -27,6 +27,9 @@
 #include "lbm_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -775,4 +778,12 @@ void orc_mms_errors(orc_sim* s, double* e_phi, double* e_psi) {
     }
   *e_phi = sqrt(np / dp);
   *e_psi = sqrt(ns / ds);
+}
+
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -93,6 +93,8 @@ void     orc_mms_errors(orc_sim* s, double* e_phi, double* e_psi);
 /* Diagnostics on an arbitrary field (pinned on synthetic inputs). */
 double   orc_area_positive(const double* phi, int nx, int ny, int wall_bottom, int wall_top, int periodic_y);
 void     orc_contact(const double* phi, int nx, int ny, double* width, double* height, double* theta_deg);
+/* Number of OpenMP threads the node loops use (1 without OpenMP). */
+int      orc_threads(void);
 
 #ifdef __cplusplus
 }

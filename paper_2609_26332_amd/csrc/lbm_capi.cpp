@@ -45,8 +45,8 @@ Layout make_layout(const lbm_params& p) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
   L.pops = take(2 * 27 * N * sb);
-  L.phipsi = take(2 * 2 * N * cb);
-  L.mu = take(2 * N * cb);
+  L.phipsi = take(2 * 2 * N * sizeof(double));  // phi, psi: FP64 in every precision
+  L.mu = take(2 * N * sizeof(double));
   L.uhist = take(2 * 4 * N * cb);
   L.Rhist = take(2 * 2 * N * cb);
   L.partials = take(lbm::kRedBlocks * 3 * sizeof(double));
@@ -154,6 +154,7 @@ struct lbm_handle {
   int have_hist = 0;
   bool faulted = false;
   double derived[LBM_N_DERIVED];
+  lbm::StepTimer timer;
   std::string err = "no error";
 };
 
@@ -183,7 +184,7 @@ void carve(lbm_handle* h) {
   s.pops[0] = b + L.pops;
   s.pops[1] = b + L.pops + 27 * N * sb;
   s.phipsi[0] = b + L.phipsi;
-  s.phipsi[1] = b + L.phipsi + 2 * N * cb;
+  s.phipsi[1] = b + L.phipsi + 2 * N * sizeof(double);
   s.mu = b + L.mu;
   s.uhist[0] = b + L.uhist;
   s.uhist[1] = b + L.uhist + 4 * N * cb;
@@ -268,9 +269,9 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
 int lbm_step(lbm_handle* h, int64_t n) {
   if (!h) return fail(nullptr, LBM_E_ARG, "null handle");
   if (n < 0) return fail(h, LBM_E_ARG, "negative step count");
-  if (h->faulted) return fail(h, LBM_E_STATE, "state holds non-finite values; load a state or fields first");
+  if (h->faulted) return fail(h, LBM_E_STATE, "state holds non-finite or out-of-range values; load a state or fields first");
   for (int64_t k = 0; k < n; ++k) {
-    HIP_OR_FAIL(h, lbm::launch_step(h->dp, h->ds, h->have_hist, h->stream), "step kernels");
+    HIP_OR_FAIL(h, lbm::launch_step(h->dp, h->ds, h->have_hist, h->stream, &h->timer), "step kernels");
     h->have_hist = 1;
     h->step += 1;
   }
@@ -304,11 +305,15 @@ int lbm_reduce_invariants(lbm_handle* h, lbm_invariants* out) {
     out->cap_height = v[11];
     out->theta_app_deg = v[12];
   }
+  // psi outside (0,1) is the cause when both are present (ln(psi/(1-psi)) is then not finite)
+  if (out->psi_out_of_range > 0) {
+    h->faulted = true;
+    return fail(h, LBM_E_RANGE, "psi left (0,1)");
+  }
   if (out->nonfinite > 0) {
     h->faulted = true;
     return fail(h, LBM_E_NONFINITE, "non-finite values in the fields");
   }
-  if (out->psi_out_of_range > 0) return fail(h, LBM_E_RANGE, "psi left (0,1)");
   return LBM_OK;
 }
 
@@ -350,7 +355,7 @@ int lbm_state_bytes(lbm_handle* h, size_t* bytes) {
   if (!h || !bytes) return fail(h, LBM_E_ARG, "null argument");
   const size_t N = (size_t)h->dp.N;
   const size_t sb = lbm::storage_bytes(h->prm.precision), cb = lbm::compute_bytes(h->prm.precision);
-  *bytes = sizeof(StateHeader) + 27 * N * sb + 8 * N * cb;
+  *bytes = sizeof(StateHeader) + 27 * N * sb + 2 * N * sizeof(double) + 6 * N * cb;
   return LBM_OK;
 }
 
@@ -368,8 +373,8 @@ int lbm_save_state(lbm_handle* h, void* host, size_t bytes) {
   const int hp = h->ds.hcur ^ 1;  // history written by the last step
   HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.pops[h->ds.cur], 27 * N * sb, hipMemcpyDeviceToHost, h->stream), "save");
   o += 27 * N * sb;
-  HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.phipsi[hp], 2 * N * cb, hipMemcpyDeviceToHost, h->stream), "save");
-  o += 2 * N * cb;
+  HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.phipsi[hp], 2 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream), "save");
+  o += 2 * N * sizeof(double);
   HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.uhist[hp], 4 * N * cb, hipMemcpyDeviceToHost, h->stream), "save");
   o += 4 * N * cb;
   HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.Rhist[hp], 2 * N * cb, hipMemcpyDeviceToHost, h->stream), "save");
@@ -393,8 +398,8 @@ int lbm_load_state(lbm_handle* h, const void* host, size_t bytes) {
   const int hp = h->ds.hcur ^ 1;
   HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.pops[h->ds.cur], o, 27 * N * sb, hipMemcpyHostToDevice, h->stream), "load");
   o += 27 * N * sb;
-  HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.phipsi[hp], o, 2 * N * cb, hipMemcpyHostToDevice, h->stream), "load");
-  o += 2 * N * cb;
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.phipsi[hp], o, 2 * N * sizeof(double), hipMemcpyHostToDevice, h->stream), "load");
+  o += 2 * N * sizeof(double);
   HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.uhist[hp], o, 4 * N * cb, hipMemcpyHostToDevice, h->stream), "load");
   o += 4 * N * cb;
   HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.Rhist[hp], o, 2 * N * cb, hipMemcpyHostToDevice, h->stream), "load");
@@ -421,8 +426,65 @@ int lbm_fetch_populations(lbm_handle* h, double* host, size_t n_doubles) {
   return LBM_OK;
 }
 
+namespace {
+void release_timer(lbm_handle* h) {
+  if (!h->timer.ev) return;
+  for (int64_t k = 0; k < h->timer.max_steps * 8; ++k) (void)hipEventDestroy(h->timer.ev[k]);
+  delete[] h->timer.ev;
+  h->timer = lbm::StepTimer();
+}
+}  // namespace
+
+int lbm_timing_begin(lbm_handle* h, int64_t max_steps) {
+  if (!h) return fail(nullptr, LBM_E_ARG, "null handle");
+  if (max_steps <= 0 || max_steps > 1000000) return fail(h, LBM_E_ARG, "max_steps must lie in [1, 1e6]");
+  release_timer(h);
+  h->timer.ev = new hipEvent_t[max_steps * 8];
+  for (int64_t k = 0; k < max_steps * 8; ++k) {
+    hipError_t e = hipEventCreate(&h->timer.ev[k]);
+    if (e != hipSuccess) {
+      h->timer.max_steps = k / 8;  // destroy only what was created
+      for (int64_t j = 0; j < k; ++j) (void)hipEventDestroy(h->timer.ev[j]);
+      delete[] h->timer.ev;
+      h->timer = lbm::StepTimer();
+      return hip_fail(h, e, "hipEventCreate");
+    }
+  }
+  h->timer.max_steps = max_steps;
+  h->timer.used = 0;
+  return LBM_OK;
+}
+
+int lbm_timing_end(lbm_handle* h, double* ms, int64_t* launches) {
+  if (!h || !ms || !launches) return fail(h, LBM_E_ARG, "null argument");
+  if (!h->timer.ev) return fail(h, LBM_E_STATE, "lbm_timing_begin was not called");
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream), "synchronise");
+  for (int k = 0; k < LBM_N_KERNELS; ++k) { ms[k] = 0.0; launches[k] = 0; }
+  for (int64_t s = 0; s < h->timer.used; ++s)
+    for (int k = 0; k < LBM_N_KERNELS; ++k) {
+      float t = 0.f;
+      hipError_t e = hipEventElapsedTime(&t, h->timer.ev[(s * 4 + k) * 2], h->timer.ev[(s * 4 + k) * 2 + 1]);
+      if (e != hipSuccess) { release_timer(h); return hip_fail(h, e, "hipEventElapsedTime"); }
+      ms[k] += t;
+      launches[k] += 1;
+    }
+  release_timer(h);
+  return LBM_OK;
+}
+
+int lbm_bytes_per_node_step(lbm_handle* h, double* bytes) {
+  if (!h || !bytes) return fail(h, LBM_E_ARG, "null argument");
+  const double sb = (double)lbm::storage_bytes(h->prm.precision), cb = (double)lbm::compute_bytes(h->prm.precision);
+  const double planes_s = h->dp.surf ? 27.0 : 18.0;     // h lattice idle without surfactant
+  const double fp64_planes = h->dp.surf ? 2.0 : 1.0;    // phi (and psi) reference planes
+  // read + write of: populations, FP64 phi/psi, velocity/advecting-velocity history (4), source history (2)
+  *bytes = 2.0 * (planes_s * sb + fp64_planes * 8.0 + 4.0 * cb + 2.0 * cb);
+  return LBM_OK;
+}
+
 int lbm_destroy(lbm_handle* h) {
   if (!h) return LBM_OK;
+  release_timer(h);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->own_buf && h->buf) (void)hipFree(h->buf);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);

@@ -45,8 +45,8 @@ constexpr int kInvOut = kInvValues + 3;
 struct DevState {
   int precision;           // LBM_FP64 / LBM_FP32 / LBM_FP16_SHIFTED
   void* pops[2];           // 27 planes each, storage type
-  void* phipsi[2];         // 2 planes each (phi, psi), compute type
-  void* mu;                // 2 planes (mu_phi, mu_psi), compute type
+  void* phipsi[2];         // 2 planes each (phi, psi), FP64; also the shift reference of g_0, h_0
+  void* mu;                // 2 planes (mu_phi, mu_psi), FP64
   void* uhist[2];          // 4 planes each (ux, uy, vx, vy): velocity and advecting velocity, compute type
   void* Rhist[2];          // 2 planes each (R_phi, R_psi), compute type
   double* partials;        // reduction partials [kRedBlocks][3]
@@ -68,7 +68,12 @@ size_t compute_bytes(int precision);
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_init(const DevParams& p, DevState& s, hipStream_t stream);
 hipError_t launch_load(const DevParams& p, DevState& s, int with_u, hipStream_t stream);
-hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t stream);
+// Optional event pairs bracketing each kernel of a step (index by LBM_K_*).
+struct StepTimer {
+  hipEvent_t* ev = nullptr;  // [max_steps][4][2]
+  int64_t max_steps = 0, used = 0;
+};
+hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t stream, StepTimer* timer = nullptr);
 hipError_t launch_macro(const DevParams& p, DevState& s, hipStream_t stream);  // phi/psi, mu, multipliers of the current state
 hipError_t launch_invariants(const DevParams& p, DevState& s, hipStream_t stream);
 hipError_t launch_fetch(const DevParams& p, DevState& s, uint32_t mask, hipStream_t stream);

@@ -2,10 +2,20 @@
 // Boltzmann step (phase field phi, surfactant psi, hydrodynamics f).
 //
 // Layout: structure of arrays.  Populations are 27 planes [f0..f8 g0..g8
-// h0..h8] of N = nx*ny nodes, x fastest; macroscopic planes likewise.  The
-// stored value of population i at node z is its post-collision value at z
-// ("pull" streaming): a step gathers f_i(x) = stored_i(x - c_i), so every
-// load and store of a wavefront touches 64 consecutive nodes of one plane.
+// h0..h8] of N = nx*ny nodes, x fastest, in the storage type S; macroscopic
+// planes likewise.  The stored value of population i at node z is its
+// post-collision value at z ("pull" streaming): a step gathers
+// f_i(x) = stored_i(x - c_i), so every load and store of a wavefront touches 64
+// consecutive nodes of one plane.
+//
+// Precision design.  phi and psi are sums dominated by the rest populations
+// g_0 ~ phi and h_0 ~ psi, whose storage rounding would feed the Laplacian in
+// the chemical potential.  The rest populations are therefore stored shifted,
+// g_0 - phi(n) and h_0 - psi(n), against FP64 planes holding phi(n), psi(n);
+// the moving populations are small and stored as they are.  All macroscopic
+// work (phi, psi, stencils, chemical potentials, force, velocity, pressure,
+// sources, reductions) runs in FP64; the three MRT collisions run in the
+// compute type C of the storage precision (FP64 or FP32).
 //
 // One step (Sec. 3 of the paper, readings in the design notes):
 //   k_moments      phi = sum g_i, psi = sum h_i                     (macroscopic recovery)
@@ -15,16 +25,16 @@
 //   k_collide      force, velocity, pressure, sources, MRT collision of f, g, h,
 //                  wall corrections; writes post-collision populations
 //                  and the history for the backward differences
-// No MFMA: the step moves ~250 B/node in FP32 and does ~2 kflop/node, far
+// No MFMA: the step moves ~300 B/node in FP32 storage and does ~2 kflop/node,
 // below the FP32 ridge of the chip, so HBM bandwidth bounds it.
 
 #include "lbm_internal.h"
 #include "../../include/lbm.h"
 
-#include <hip/hip_fp16.h>
-
 namespace lbm {
 namespace {
+
+constexpr double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------- D2Q9 tables
 // Directions: 0 rest, 1 (+x), 2 (+y), 3 (-x), 4 (-y), 5 (+x+y), 6 (-x+y),
@@ -36,9 +46,6 @@ __host__ __device__ constexpr int MIRY(int i) { return i == 2 ? 4 : i == 4 ? 2 :
 template <class C> __device__ __forceinline__ constexpr C WQ(int i) { return i == 0 ? C(4.0 / 9.0) : (i <= 4 ? C(1.0 / 9.0) : C(1.0 / 36.0)); }
 static_assert(OPP(1) == 3 && OPP(2) == 4 && OPP(3) == 1 && OPP(4) == 2, "opp");
 static_assert(OPP(5) == 7 && OPP(6) == 8 && OPP(7) == 5 && OPP(8) == 6, "opp");
-
-__device__ __forceinline__ float lg(float v) { return logf(v); }
-__device__ __forceinline__ double lg(double v) { return log(v); }
 
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
@@ -58,7 +65,8 @@ __device__ __forceinline__ bool wet_side(const DevParams& p, int side) { return 
 // Gather population i of lattice lat (0 f, 1 g, 2 h) at (x,y): the value that
 // left x - c_i last step.  Sources beyond a wall: half-way bounce-back (the
 // population that left x towards the wall), or for f at a free-slip wall the
-// specular image that left x - (c_x, 0).
+// specular image that left x - (c_x, 0).  For i = 0 of g and h this is the
+// shifted value g_0 - phi(n) (h_0 - psi(n)).
 template <class S, class C>
 __device__ __forceinline__ C pull(const DevParams& p, const S* __restrict__ P, int lat, int i, int x, int y) {
   const size_t N = (size_t)p.N;
@@ -73,47 +81,46 @@ __device__ __forceinline__ C pull(const DevParams& p, const S* __restrict__ P, i
 }
 
 // ------------------------------------------------------------------- physics
-// Wall switching function g(phi) and g'(phi) with u = phi/phi_b (Sec. 2.1).
-template <class C> __device__ __forceinline__ C gsw(const DevParams& p, C ph) {
-  C u = ph * (C)p.inv_phib;
-  return C(0.75) * u - C(0.25) * u * u * u;
+// All in FP64.  Wall switching function g(phi) and g'(phi), u = phi/phi_b (Sec. 2.1).
+__device__ __forceinline__ double gsw(const DevParams& p, double ph) {
+  const double u = ph * p.inv_phib;
+  return 0.75 * u - 0.25 * u * u * u;
 }
-template <class C> __device__ __forceinline__ C gsw_d(const DevParams& p, C ph) {
-  C u = ph * (C)p.inv_phib;
-  return C(0.75) * (C)p.inv_phib * (C(1) - u * u);
+__device__ __forceinline__ double gsw_d(const DevParams& p, double ph) {
+  const double u = ph * p.inv_phib;
+  return 0.75 * p.inv_phib * (1.0 - u * u);
 }
-template <class C> __device__ __forceinline__ C hprime(const DevParams& p, C ph) { return p.linear ? C(1) : gsw_d(p, ph); }
-template <class C> __device__ __forceinline__ C rho_of(const DevParams& p, C ph) {
-  return (C)p.rho_g + (C)(p.rho_l - p.rho_g) * C(0.5) * (C(1) + ph * (C)p.inv_phib);
+__device__ __forceinline__ double hprime(const DevParams& p, double ph) { return p.linear ? 1.0 : gsw_d(p, ph); }
+__device__ __forceinline__ double rho_of(const DevParams& p, double ph) {
+  return p.rho_g + (p.rho_l - p.rho_g) * 0.5 * (1.0 + ph * p.inv_phib);
 }
-template <class C> __device__ __forceinline__ C mud_of(const DevParams& p, C ph) {
-  return (C)p.mu_g + (C)(p.mu_l - p.mu_g) * C(0.5) * (C(1) + ph * (C)p.inv_phib);
+__device__ __forceinline__ double mud_of(const DevParams& p, double ph) {
+  return p.mu_g + (p.mu_l - p.mu_g) * 0.5 * (1.0 + ph * p.inv_phib);
 }
 // J_phi = -df_w/dphi, J_psi = -df_w/dpsi at a wall node (eq8, boundary).
-template <class C> __device__ __forceinline__ C Jphi(const DevParams& p, C ph, C ps) {
-  C a = (C)p.sig_cos;
-  if (p.surf) a += lg(C(1) - ps) * (C)p.dsb;
+__device__ __forceinline__ double Jphi(const DevParams& p, double ph, double ps) {
+  double a = p.sig_cos;
+  if (p.surf) a += log(1.0 - ps) * p.dsb;
   return a * gsw_d(p, ph);
 }
-template <class C> __device__ __forceinline__ C Jpsi(const DevParams& p, C ph, C ps) {
-  return -((C)p.dsb * gsw(p, ph) - C(0.5) * (C)p.msb) / (C(1) - ps);
+__device__ __forceinline__ double Jpsi(const DevParams& p, double ph, double ps) {
+  return -(p.dsb * gsw(p, ph) - 0.5 * p.msb) / (1.0 - ps);
 }
 
 // Laplacian pieces at (x,y): zero-flux part L0 of phi and psi, and the wall
 // terms T = sum over directions into a wetting wall of 2 w_i/c_s^2 J(column),
 // so that the Laplacian with wetting ghosts is L0 + T/kappa (phi) and
 // L0 + T/lambda_s (psi).
-template <class C> struct Lap { C l0p, l0s, Tp, Ts; };
-template <class C>
-__device__ __forceinline__ Lap<C> laplace(const DevParams& p, const C* __restrict__ phi, const C* __restrict__ psi, int x, int y) {
+struct Lap { double l0p, l0s, Tp, Ts; };
+__device__ __forceinline__ Lap laplace(const DevParams& p, const double* __restrict__ phi, const double* __restrict__ psi, int x, int y) {
   const int n = y * p.nx + x;
-  const C ph = phi[n], ps = psi[n];
-  Lap<C> r{C(0), C(0), C(0), C(0)};
+  const double ph = phi[n], ps = psi[n];
+  Lap r{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const Nb b = nbr(p, x, y, CX(i), CY(i));
-    const C w2 = C(6) * WQ<C>(i);  // 2 w_i / c_s^2
-    const C pn = phi[b.idx], sn = psi[b.idx];
+    const double w2 = 6.0 * WQ<double>(i);  // 2 w_i / c_s^2
+    const double pn = phi[b.idx], sn = psi[b.idx];
     r.l0p += w2 * (pn - ph);
     r.l0s += w2 * (sn - ps);
     if (b.side && wet_side(p, b.side)) {
@@ -125,18 +132,18 @@ __device__ __forceinline__ Lap<C> laplace(const DevParams& p, const C* __restric
 }
 
 // Chemical potentials (eq_muphi, eq_mupsi) from the local values and stencil.
-template <class C> __device__ __forceinline__ C mu_phi_of(const DevParams& p, C ph, C ps, const Lap<C>& L) {
-  return C(4) * (C)p.beta * (C(1) - ps) * (ph * ph * ph - ph) - (C)p.kappa * L.l0p - L.Tp + (C)p.W * ps * ph;
+__device__ __forceinline__ double mu_phi_of(const DevParams& p, double ph, double ps, const Lap& L) {
+  return 4.0 * p.beta * (1.0 - ps) * (ph * ph * ph - ph) - p.kappa * L.l0p - L.Tp + p.W * ps * ph;
 }
-template <class C> __device__ __forceinline__ C mu_psi_of(const DevParams& p, C ph, C ps, const Lap<C>& L) {
-  if (!p.surf) return C(0);
-  const C q = C(1) - ph * ph;
-  return (C)p.kBT * lg(ps / (C(1) - ps)) - (C)p.lambda_s * L.l0s - L.Ts - (C)p.beta * q * q + C(0.5) * (C)p.W * ph * ph;
+__device__ __forceinline__ double mu_psi_of(const DevParams& p, double ph, double ps, const Lap& L) {
+  if (!p.surf) return 0.0;
+  const double q = 1.0 - ph * ph;
+  return p.kBT * log(ps / (1.0 - ps)) - p.lambda_s * L.l0s - L.Ts - p.beta * q * q + 0.5 * p.W * ph * ph;
 }
 
 // Raw moments c_x^a c_y^b grouped by order: m00 m10 m01 m20 m11 m02 m21 m12 m22.
-template <class C> __device__ __forceinline__ void moments(const C* f, C* m) {
-  m[0] = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+// m00 is not formed here: for g and h it is the exact phi / psi.
+template <class C> __device__ __forceinline__ void moments_noncons(const C* f, C* m) {
   m[1] = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
   m[2] = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
   m[3] = f[1] + f[3] + f[5] + f[6] + f[7] + f[8];
@@ -146,9 +153,8 @@ template <class C> __device__ __forceinline__ void moments(const C* f, C* m) {
   m[7] = f[5] - f[6] - f[7] + f[8];
   m[8] = f[5] + f[6] + f[7] + f[8];
 }
-// Inverse of the raw-moment transform.
-template <class C> __device__ __forceinline__ void populations(const C* m, C* f) {
-  f[0] = m[0] - m[3] - m[5] + m[8];
+// Inverse of the raw-moment transform for the moving directions 1..8.
+template <class C> __device__ __forceinline__ void moving_populations(const C* m, C* f) {
   f[1] = C(0.5) * (m[1] + m[3] - m[7] - m[8]);
   f[2] = C(0.5) * (m[2] + m[5] - m[6] - m[8]);
   f[3] = C(0.5) * (-m[1] + m[3] + m[7] - m[8]);
@@ -160,33 +166,30 @@ template <class C> __device__ __forceinline__ void populations(const C* m, C* f)
 }
 
 // Pressure-based equilibrium of lattice 1 (Sec. 3), direction d.
-template <class C> __device__ __forceinline__ C feq_flow(int d, C pr, C rho, C ux, C uy) {
-  const C cu = C(CX(d)) * ux + C(CY(d)) * uy, uu = ux * ux + uy * uy;
-  const C su = C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu;
-  return C(3) * pr * (WQ<C>(d) - (d == 0 ? C(1) : C(0))) + rho * WQ<C>(d) * su;
+__device__ __forceinline__ double feq_flow(int d, double pr, double rho, double ux, double uy) {
+  const double cu = CX(d) * ux + CY(d) * uy, uu = ux * ux + uy * uy;
+  const double su = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+  return 3.0 * pr * (WQ<double>(d) - (d == 0 ? 1.0 : 0.0)) + rho * WQ<double>(d) * su;
 }
-// eta-weighted equilibrium of lattices 2 and 3 (Sec. 3), direction d.
-template <class C> __device__ __forceinline__ C feq_scalar(int d, C c, C eta, C cux, C cuy) {
-  if (d == 0) return c + (WQ<C>(0) - C(1)) * eta * c;
-  return WQ<C>(d) * eta * c + C(3) * WQ<C>(d) * (C(CX(d)) * cux + C(CY(d)) * cuy);
+// eta-weighted equilibrium of lattices 2 and 3 (Sec. 3), moving direction d >= 1.
+__device__ __forceinline__ double feq_scalar_moving(int d, double c, double eta, double cux, double cuy) {
+  return WQ<double>(d) * eta * c + 3.0 * WQ<double>(d) * (CX(d) * cux + CY(d) * cuy);
 }
 
-// Block-wide FP64 sum (wave64 shuffles, then LDS across the four waves);
-// the result is valid in thread 0.  Fixed order: bitwise reproducible.
-__device__ __forceinline__ double wave_sum(double v) {
+// Block-wide FP64 reduction (wave64 shuffles, then LDS across the four
+// waves); the result is valid in thread 0.  Fixed order: bitwise reproducible.
+__device__ __forceinline__ double wave_red(double v, bool is_max) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_down(v, off, 64);
+    v = is_max ? fmax(v, o) : v + o;
+  }
   return v;
 }
 __device__ double block_reduce(double v, bool is_max) {
   __shared__ double sh[kBlock / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  v = is_max ? wave_max(v) : wave_sum(v);
+  v = wave_red(v, is_max);
   if (lane == 0) sh[wid] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -199,39 +202,42 @@ __device__ double block_reduce(double v, bool is_max) {
 }
 
 // ------------------------------------------------------------------- kernels
+// phi(n+1) = phi(n) + [stored g_0 shift + sum of the gathered moving g_i].
 template <class S, class C>
-__global__ __launch_bounds__(kBlock) void k_moments(DevParams p, const S* __restrict__ P, C* __restrict__ phipsi) {
+__global__ __launch_bounds__(kBlock) void k_moments(DevParams p, const S* __restrict__ P, const double* __restrict__ prev,
+                                                    double* __restrict__ phipsi) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= p.N) return;
   const int x = n % p.nx, y = n / p.nx;
   C a = C(0), b = C(0);
 #pragma unroll
   for (int i = 0; i < 9; ++i) a += pull<S, C>(p, P, 1, i, x, y);
+  phipsi[n] = prev[n] + (double)a;
   if (p.surf) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) b += pull<S, C>(p, P, 2, i, x, y);
+    phipsi[(size_t)p.N + n] = prev[(size_t)p.N + n] + (double)b;
+  } else {
+    phipsi[(size_t)p.N + n] = 0.0;
   }
-  phipsi[n] = a;
-  phipsi[(size_t)p.N + n] = b;
 }
 
-template <class C>
-__global__ __launch_bounds__(kBlock) void k_mu_partials(DevParams p, const C* __restrict__ phipsi, C* __restrict__ mu,
+__global__ __launch_bounds__(kBlock) void k_mu_partials(DevParams p, const double* __restrict__ phipsi, double* __restrict__ mu,
                                                         double* __restrict__ partials) {
-  const C* phi = phipsi;
-  const C* psi = phipsi + p.N;
+  const double* phi = phipsi;
+  const double* psi = phipsi + p.N;
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int n = blockIdx.x * kBlock + threadIdx.x; n < p.N; n += gridDim.x * kBlock) {
     const int x = n % p.nx, y = n / p.nx;
-    const C ph = phi[n], ps = psi[n];
-    const Lap<C> L = laplace(p, phi, psi, x, y);
-    const C mp = mu_phi_of(p, ph, ps, L), ms = mu_psi_of(p, ph, ps, L);
+    const double ph = phi[n], ps = psi[n];
+    const Lap L = laplace(p, phi, psi, x, y);
+    const double mp = mu_phi_of(p, ph, ps, L), ms = mu_psi_of(p, ph, ps, L);
     mu[n] = mp;
     mu[(size_t)p.N + n] = ms;
-    const double hp = (double)hprime(p, ph);
-    s1 += hp * (double)mp;
+    const double hp = hprime(p, ph);
+    s1 += hp * mp;
     s2 += hp * hp;
-    s3 += (double)ms;
+    s3 += ms;
   }
   s1 = block_reduce(s1, false);
   s2 = block_reduce(s2, false);
@@ -256,168 +262,173 @@ __global__ __launch_bounds__(kBlock) void k_multipliers(int nblk, int N, const d
 }
 
 // Force, velocity and pressure at (x,y) from the phi/psi and mu planes and the
-// gathered f (O5, O6 of the step).
-template <class C> struct Macro { C rho, ux, uy, pr, Fx, Fy, grx, gry; };
+// gathered f (O5, O6 of the step), in FP64.
+struct Macro { double rho, ux, uy, pr, Fx, Fy, grx, gry; };
 template <class C>
-__device__ __forceinline__ Macro<C> macro_node(const DevParams& p, const C* __restrict__ phi, const C* __restrict__ psi,
-                                                const C* __restrict__ mup, const C* __restrict__ mus, const C* f, int x, int y) {
+__device__ __forceinline__ Macro macro_node(const DevParams& p, const double* __restrict__ phi, const double* __restrict__ psi,
+                                            const double* __restrict__ mup, const double* __restrict__ mus, const C* f, int x, int y) {
   const int n = y * p.nx + x;
-  const C ph = phi[n], ps = psi[n];
-  Macro<C> M;
+  const double ph = phi[n], ps = psi[n];
+  Macro M;
   M.rho = rho_of(p, ph);
-  C grx = 0, gry = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0;
+  double grx = 0, gry = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const Nb b = nbr(p, x, y, CX(i), CY(i));
-    const C w3 = C(3) * WQ<C>(i);  // w_i / c_s^2
-    const C pn = phi[b.idx];
-    C rn;
-    if (b.side && wet_side(p, b.side)) rn = rho_of(p, pn + Jphi(p, pn, psi[b.idx]) / (C)p.kappa);
+    const double w3 = 3.0 * WQ<double>(i);  // w_i / c_s^2
+    const double pn = phi[b.idx];
+    double rn;
+    if (b.side && wet_side(p, b.side)) rn = rho_of(p, pn + Jphi(p, pn, psi[b.idx]) / p.kappa);
     else rn = rho_of(p, pn);
-    grx += w3 * C(CX(i)) * rn;
-    gry += w3 * C(CY(i)) * rn;
-    const C mpn = mup[b.idx], msn = mus[b.idx];
-    gpx += w3 * C(CX(i)) * mpn;
-    gpy += w3 * C(CY(i)) * mpn;
-    gsx += w3 * C(CX(i)) * msn;
-    gsy += w3 * C(CY(i)) * msn;
+    grx += w3 * CX(i) * rn;
+    gry += w3 * CY(i) * rn;
+    const double mpn = mup[b.idx], msn = mus[b.idx];
+    gpx += w3 * CX(i) * mpn;
+    gpy += w3 * CY(i) * mpn;
+    gsx += w3 * CX(i) * msn;
+    gsy += w3 * CY(i) * msn;
   }
   M.grx = grx;
   M.gry = gry;
-  M.Fx = -ph * gpx - ps * gsx + M.rho * (C)p.gx;
-  M.Fy = -ph * gpy - ps * gsy + M.rho * (C)p.gy;
-  const C jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-  const C jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-  M.ux = (jx + C(0.5) * M.Fx) / M.rho;
-  M.uy = (jy + C(0.5) * M.Fy) / M.rho;
-  const C snz = f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  M.Fx = -ph * gpx - ps * gsx + M.rho * p.gx;
+  M.Fy = -ph * gpy - ps * gsy + M.rho * p.gy;
+  const double jx = (double)(f[1] - f[3] + f[5] - f[6] - f[7] + f[8]);
+  const double jy = (double)(f[2] - f[4] + f[5] + f[6] - f[7] - f[8]);
+  M.ux = (jx + 0.5 * M.Fx) / M.rho;
+  M.uy = (jy + 0.5 * M.Fy) / M.rho;
+  const double snz = (double)(f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]);
   // c_s^2/(1 - w0) = 3/5, w0/(2 c_s^2) = 2/3
-  M.pr = C(0.6) * (snz + C(0.5) * (M.ux * grx + M.uy * gry) - M.rho * C(2.0 / 3.0) * (M.ux * M.ux + M.uy * M.uy));
+  M.pr = 0.6 * (snz + 0.5 * (M.ux * grx + M.uy * gry) - M.rho * (2.0 / 3.0) * (M.ux * M.ux + M.uy * M.uy));
   return M;
+}
+
+// MRT collision of a scalar lattice (g or h) in moment space, given the
+// gathered moving populations c[1..8], the exact zeroth moment c0 (phi or
+// psi), advecting velocity v, the backward difference dq of c0 v, the
+// source Rt = R + dR/2 and the rates; writes the shifted rest value
+// (post-collision c_0 minus c0) and the moving values.
+template <class C>
+__device__ __forceinline__ void collide_scalar(const C* c, C c0, C eta, C vx, C vy, C dqx, C dqy, C Rt,
+                                               const double* sr, C* o) {
+  C m[9];
+  moments_noncons(c, m);
+  const C third = C(1.0 / 3.0);
+  const C meq[9] = {c0, c0 * vx, c0 * vy, eta * c0 * third, C(0), eta * c0 * third, c0 * vy * third, c0 * vx * third,
+                    eta * c0 * C(1.0 / 9.0)};
+  const C mv[9] = {C(0), dqx, dqy, C(0), C(0), C(0), dqy * third, dqx * third, C(0)};
+  const C src[9] = {Rt, C(0), C(0), Rt * third, C(0), Rt * third, C(0), C(0), Rt * C(1.0 / 9.0)};
+  const C rt[9] = {(C)sr[0], (C)sr[1], (C)sr[1], (C)sr[2], (C)sr[2], (C)sr[2], (C)sr[3], (C)sr[3], (C)sr[4]};
+#pragma unroll
+  for (int k = 1; k < 9; ++k) m[k] = m[k] - rt[k] * (m[k] - meq[k]) + (C(1) - C(0.5) * rt[k]) * mv[k] + src[k];
+  moving_populations(m, o);
+  // rest population: m00 relaxes to c0 exactly, plus the source
+  o[0] = Rt - m[3] - m[5] + m[8];
 }
 
 template <class S, class C>
 __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const S* __restrict__ Pin, S* __restrict__ Pout,
-                                                    const C* __restrict__ phipsi, const C* __restrict__ phipsi_h,
-                                                    const C* __restrict__ mu, const C* __restrict__ u_h, C* __restrict__ u_out,
+                                                    const double* __restrict__ phipsi, const double* __restrict__ phipsi_h,
+                                                    const double* __restrict__ mu, const C* __restrict__ u_h, C* __restrict__ u_out,
                                                     const C* __restrict__ R_h, C* __restrict__ R_out,
                                                     const DevScalars* __restrict__ sc, int have_hist) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= p.N) return;
   const size_t N = (size_t)p.N;
   const int x = n % p.nx, y = n / p.nx;
-  const C* phi = phipsi;
-  const C* psi = phipsi + N;
-  const C ph = phi[n], ps = psi[n];
+  const double* phi = phipsi;
+  const double* psi = phipsi + N;
+  const double ph = phi[n], ps = psi[n];
 
   C f[9], g[9], h[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     f[i] = pull<S, C>(p, Pin, 0, i, x, y);
-    g[i] = pull<S, C>(p, Pin, 1, i, x, y);
-    h[i] = p.surf ? pull<S, C>(p, Pin, 2, i, x, y) : C(0);
+    g[i] = i ? pull<S, C>(p, Pin, 1, i, x, y) : C(0);
+    h[i] = (i && p.surf) ? pull<S, C>(p, Pin, 2, i, x, y) : C(0);
   }
-  const Macro<C> M = macro_node(p, phi, psi, mu, mu + N, f, x, y);
-  const C rho = M.rho, ux = M.ux, uy = M.uy;
+  const Macro M = macro_node<C>(p, phi, psi, mu, mu + N, f, x, y);
+  const double rho = M.rho, ux = M.ux, uy = M.uy;
 
   // Sources (Sec. 3) with the wall-flux terms; multipliers from the reduction.
-  const Lap<C> L = laplace(p, phi, psi, x, y);
-  const C hp = hprime(p, ph);
-  const C lam = (C)sc->lambda_phi, mub = (C)sc->mubar_psi;
-  const C Rp = (C)p.M_phi * (C(-4) * (C)p.beta * (C(1) - ps) * (ph * ph * ph - ph) - (C)p.W * ps * ph + lam * hp) + (C)p.M_phi * L.Tp;
-  C Rs = C(0);
+  const Lap L = laplace(p, phi, psi, x, y);
+  const double hp = hprime(p, ph);
+  const double Rp = p.M_phi * (-4.0 * p.beta * (1.0 - ps) * (ph * ph * ph - ph) - p.W * ps * ph + sc->lambda_phi * hp) + p.M_phi * L.Tp;
+  double Rs = 0.0;
   if (p.surf) {
-    const C q = C(1) - ph * ph;
-    Rs = -(C)p.M0 * L.l0s + (C)p.M_psi * (-(C)p.kBT * lg(ps / (C(1) - ps)) + (C)p.beta * q * q - C(0.5) * (C)p.W * ph * ph + mub)
-       + (C)p.M_psi * L.Ts;
+    const double q = 1.0 - ph * ph;
+    Rs = -p.M0 * L.l0s + p.M_psi * (-p.kBT * log(ps / (1.0 - ps)) + p.beta * q * q - 0.5 * p.W * ph * ph + sc->mubar_psi)
+       + p.M_psi * L.Ts;
   }
   // Velocity advecting phi and psi: mean of this and the previous step (removes
   // the lattice's period-2 staggered momentum from the scalar transport), or
   // u itself when adv_raw is set.  Backward differences are zero on the first step.
-  C vx = ux, vy = uy;
-  C dpx = 0, dpy = 0, dsx = 0, dsy = 0, dRp = 0, dRs = 0;
+  double vx = ux, vy = uy;
+  double dpx = 0, dpy = 0, dsx = 0, dsy = 0, dRp = 0, dRs = 0;
   if (have_hist) {
     if (!p.adv_raw) {
-      vx = C(0.5) * (ux + u_h[n]);
-      vy = C(0.5) * (uy + u_h[N + n]);
+      vx = 0.5 * (ux + (double)u_h[n]);
+      vy = 0.5 * (uy + (double)u_h[N + n]);
     }
-    const C vxh = u_h[2 * N + n], vyh = u_h[3 * N + n], phh = phipsi_h[n], psh = phipsi_h[N + n];
+    const double vxh = u_h[2 * N + n], vyh = u_h[3 * N + n], phh = phipsi_h[n], psh = phipsi_h[N + n];
     dpx = ph * vx - phh * vxh;
     dpy = ph * vy - phh * vyh;
     dsx = ps * vx - psh * vxh;
     dsy = ps * vy - psh * vyh;
-    dRp = Rp - R_h[n];
-    dRs = Rs - R_h[N + n];
+    dRp = Rp - (double)R_h[n];
+    dRs = Rs - (double)R_h[N + n];
   }
 
   // ---- lattice 1: MRT with the pressure-based equilibrium and A^1 forcing
   {
     C m[9], o[9];
-    moments(f, m);
-    const C uu = ux * ux + uy * uy, pr = M.pr;
-    const C meq[9] = {C(0), rho * ux, rho * uy, pr + rho * ux * ux, rho * ux * uy, pr + rho * uy * uy,
-                      rho * uy * C(1.0 / 3.0), rho * ux * C(1.0 / 3.0), (pr + rho * uu) * C(1.0 / 3.0)};
-    const C a = ux * M.grx + uy * M.gry;
-    const C mv[9] = {a, M.Fx, M.Fy, ux * M.grx + uy * M.gry * C(1.0 / 3.0), (ux * M.gry + uy * M.grx) * C(1.0 / 3.0),
-                     uy * M.gry + ux * M.grx * C(1.0 / 3.0), M.Fy * C(1.0 / 3.0), M.Fx * C(1.0 / 3.0), a * C(1.0 / 3.0)};
-    const C s2 = p.s2_local ? C(1) / (C(3) * mud_of(p, ph) / rho + C(0.5)) : (C)p.sf[2];
+    m[0] = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    moments_noncons(f, m);
+    const double uu = ux * ux + uy * uy, pr = M.pr;
+    const double third = 1.0 / 3.0;
+    const double a = ux * M.grx + uy * M.gry;
+    const C meq[9] = {C(0), (C)(rho * ux), (C)(rho * uy), (C)(pr + rho * ux * ux), (C)(rho * ux * uy), (C)(pr + rho * uy * uy),
+                      (C)(rho * uy * third), (C)(rho * ux * third), (C)((pr + rho * uu) * third)};
+    const C mv[9] = {(C)a, (C)M.Fx, (C)M.Fy, (C)(ux * M.grx + uy * M.gry * third), (C)((ux * M.gry + uy * M.grx) * third),
+                     (C)(uy * M.gry + ux * M.grx * third), (C)(M.Fy * third), (C)(M.Fx * third), (C)(a * third)};
+    const C s2 = p.s2_local ? (C)(1.0 / (3.0 * mud_of(p, ph) / rho + 0.5)) : (C)p.sf[2];
     const C rt[9] = {(C)p.sf[0], (C)p.sf[1], (C)p.sf[1], s2, s2, s2, (C)p.sf[3], (C)p.sf[3], (C)p.sf[4]};
 #pragma unroll
     for (int k = 0; k < 9; ++k) m[k] = m[k] - rt[k] * (m[k] - meq[k]) + (C(1) - C(0.5) * rt[k]) * mv[k];
-    populations(m, o);
+    moving_populations(m, o);
+    o[0] = m[0] - m[3] - m[5] + m[8];
     // no-slip walls: moving-wall correction on the populations that will bounce back
     const bool wb = !p.periodic_y && y == 0 && p.bc_bottom != LBM_BC_FREESLIP;
     const bool wt = !p.periodic_y && y == p.ny - 1 && p.bc_top != LBM_BC_FREESLIP;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       C v = o[i];
-      if (wb && CY(i) < 0) v -= C(6) * WQ<C>(i) * rho * C(CX(i)) * (C)p.uw_bottom;
-      if (wt && CY(i) > 0) v -= C(6) * WQ<C>(i) * rho * C(CX(i)) * (C)p.uw_top;
+      if (wb && CY(i) < 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_bottom);
+      if (wt && CY(i) > 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_top);
       Pout[(size_t)i * N + n] = (S)v;
     }
   }
-  // ---- lattices 2 and 3: eta-equilibria, A^k d_t(c u) forcing, w_i (R + R_t/2)
+  // ---- lattices 2 and 3: eta-equilibria, A^k d_t(c v) forcing, w_i (R + R_t/2)
   {
-    C m[9], o[9];
-    moments(g, m);
-    const C e = (C)p.eta_phi;
-    const C meq[9] = {ph, ph * vx, ph * vy, e * ph * C(1.0 / 3.0), C(0), e * ph * C(1.0 / 3.0),
-                      ph * vy * C(1.0 / 3.0), ph * vx * C(1.0 / 3.0), e * ph * C(1.0 / 9.0)};
-    const C mv[9] = {C(0), dpx, dpy, C(0), C(0), C(0), dpy * C(1.0 / 3.0), dpx * C(1.0 / 3.0), C(0)};
-    const C Rt = Rp + C(0.5) * dRp;
-    const C src[9] = {Rt, C(0), C(0), Rt * C(1.0 / 3.0), C(0), Rt * C(1.0 / 3.0), C(0), C(0), Rt * C(1.0 / 9.0)};
-    const C rt[9] = {(C)p.sg[0], (C)p.sg[1], (C)p.sg[1], (C)p.sg[2], (C)p.sg[2], (C)p.sg[2], (C)p.sg[3], (C)p.sg[3], (C)p.sg[4]};
-#pragma unroll
-    for (int k = 0; k < 9; ++k) m[k] = m[k] - rt[k] * (m[k] - meq[k]) + (C(1) - C(0.5) * rt[k]) * mv[k] + src[k];
-    populations(m, o);
+    C o[9];
+    collide_scalar<C>(g, (C)ph, (C)p.eta_phi, (C)vx, (C)vy, (C)dpx, (C)dpy, (C)(Rp + 0.5 * dRp), p.sg, o);
 #pragma unroll
     for (int i = 0; i < 9; ++i) Pout[(size_t)(9 + i) * N + n] = (S)o[i];
   }
   if (p.surf) {
-    C m[9], o[9];
-    moments(h, m);
-    const C e = (C)p.eta_psi;
-    const C meq[9] = {ps, ps * vx, ps * vy, e * ps * C(1.0 / 3.0), C(0), e * ps * C(1.0 / 3.0),
-                      ps * vy * C(1.0 / 3.0), ps * vx * C(1.0 / 3.0), e * ps * C(1.0 / 9.0)};
-    const C mv[9] = {C(0), dsx, dsy, C(0), C(0), C(0), dsy * C(1.0 / 3.0), dsx * C(1.0 / 3.0), C(0)};
-    const C Rt = Rs + C(0.5) * dRs;
-    const C src[9] = {Rt, C(0), C(0), Rt * C(1.0 / 3.0), C(0), Rt * C(1.0 / 3.0), C(0), C(0), Rt * C(1.0 / 9.0)};
-    const C rt[9] = {(C)p.sh[0], (C)p.sh[1], (C)p.sh[1], (C)p.sh[2], (C)p.sh[2], (C)p.sh[2], (C)p.sh[3], (C)p.sh[3], (C)p.sh[4]};
-#pragma unroll
-    for (int k = 0; k < 9; ++k) m[k] = m[k] - rt[k] * (m[k] - meq[k]) + (C(1) - C(0.5) * rt[k]) * mv[k] + src[k];
-    populations(m, o);
+    C o[9];
+    collide_scalar<C>(h, (C)ps, (C)p.eta_psi, (C)vx, (C)vy, (C)dsx, (C)dsy, (C)(Rs + 0.5 * dRs), p.sh, o);
 #pragma unroll
     for (int i = 0; i < 9; ++i) Pout[(size_t)(18 + i) * N + n] = (S)o[i];
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) Pout[(size_t)(18 + i) * N + n] = (S)C(0);
   }
-  u_out[n] = ux;
-  u_out[N + n] = uy;
-  u_out[2 * N + n] = vx;
-  u_out[3 * N + n] = vy;
-  R_out[n] = Rp;
-  R_out[N + n] = Rs;
+  u_out[n] = (C)ux;
+  u_out[N + n] = (C)uy;
+  u_out[2 * N + n] = (C)vx;
+  u_out[3 * N + n] = (C)vy;
+  R_out[n] = (C)Rp;
+  R_out[N + n] = (C)Rs;
 }
 
 // Initial fields (Sec. 2.2 equilibrium profile) into the FP64 staging buffer.
@@ -440,14 +451,18 @@ __global__ __launch_bounds__(kBlock) void k_init_fields(DevParams p, double* __r
 }
 
 // Equilibrium populations of the staged fields (phi, psi, ux, uy), stored in
-// the pull layout: the stored value at z for direction j is the population
-// that a gather will deliver, i.e. the inverse of `pull`.
+// the pull layout (the stored value at z for direction j is the population a
+// gather will deliver, the inverse of `pull`), with the rest populations of
+// g and h shifted by phi and psi, which go to the FP64 reference planes.
 template <class S>
-__global__ __launch_bounds__(kBlock) void k_load(DevParams p, const double* __restrict__ F, int with_u, S* __restrict__ P) {
+__global__ __launch_bounds__(kBlock) void k_load(DevParams p, const double* __restrict__ F, int with_u, S* __restrict__ P,
+                                                 double* __restrict__ ref) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= p.N) return;
   const size_t N = (size_t)p.N;
   const int x = n % p.nx, y = n / p.nx;
+  ref[n] = F[n];
+  ref[N + n] = p.surf ? F[N + n] : 0.0;
 #pragma unroll
   for (int lat = 0; lat < 3; ++lat) {
 #pragma unroll
@@ -464,9 +479,12 @@ __global__ __launch_bounds__(kBlock) void k_load(DevParams p, const double* __re
       const double ph = F[w], ps = p.surf ? F[N + w] : 0.0;
       const double ux = with_u ? F[2 * N + w] : 0.0, uy = with_u ? F[3 * N + w] : 0.0;
       double v;
-      if (lat == 0) v = with_u ? feq_flow<double>(d, 0.0, rho_of(p, ph), ux, uy) : 0.0;
-      else if (lat == 1) v = feq_scalar<double>(d, ph, p.eta_phi, ph * ux, ph * uy);
-      else v = p.surf ? feq_scalar<double>(d, ps, p.eta_psi, ps * ux, ps * uy) : 0.0;
+      if (lat == 0) v = with_u ? feq_flow(d, 0.0, rho_of(p, ph), ux, uy) : 0.0;
+      else {
+        const double c = lat == 1 ? ph : ps, eta = lat == 1 ? p.eta_phi : p.eta_psi;
+        v = d == 0 ? (WQ<double>(0) - 1.0) * eta * c : feq_scalar_moving(d, c, eta, c * ux, c * uy);
+        if (lat == 2 && !p.surf) v = 0.0;
+      }
       P[(size_t)(9 * lat + j) * N + n] = (S)v;
     }
   }
@@ -474,8 +492,8 @@ __global__ __launch_bounds__(kBlock) void k_load(DevParams p, const double* __re
 
 // Macroscopic fields of the current state: phi psi ux uy p rho mu_phi mu_psi.
 template <class S, class C>
-__global__ __launch_bounds__(kBlock) void k_fields(DevParams p, const S* __restrict__ P, const C* __restrict__ phipsi,
-                                                   const C* __restrict__ mu, double* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_fields(DevParams p, const S* __restrict__ P, const double* __restrict__ phipsi,
+                                                   const double* __restrict__ mu, double* __restrict__ out) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= p.N) return;
   const size_t N = (size_t)p.N;
@@ -483,25 +501,32 @@ __global__ __launch_bounds__(kBlock) void k_fields(DevParams p, const S* __restr
   C f[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) f[i] = pull<S, C>(p, P, 0, i, x, y);
-  const Macro<C> M = macro_node(p, phipsi, phipsi + N, mu, mu + N, f, x, y);
-  out[n] = (double)phipsi[n];
-  out[N + n] = (double)phipsi[N + n];
-  out[2 * N + n] = (double)M.ux;
-  out[3 * N + n] = (double)M.uy;
-  out[4 * N + n] = (double)M.pr;
-  out[5 * N + n] = (double)M.rho;
-  out[6 * N + n] = (double)mu[n];
-  out[7 * N + n] = (double)mu[N + n];
+  const Macro M = macro_node<C>(p, phipsi, phipsi + N, mu, mu + N, f, x, y);
+  out[n] = phipsi[n];
+  out[N + n] = phipsi[N + n];
+  out[2 * N + n] = M.ux;
+  out[3 * N + n] = M.uy;
+  out[4 * N + n] = M.pr;
+  out[5 * N + n] = M.rho;
+  out[6 * N + n] = mu[n];
+  out[7 * N + n] = mu[N + n];
 }
 
+// Populations of the current state (rest populations of g, h un-shifted).
 template <class S>
-__global__ __launch_bounds__(kBlock) void k_pops(DevParams p, const S* __restrict__ P, double* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_pops(DevParams p, const S* __restrict__ P, const double* __restrict__ ref,
+                                                 double* __restrict__ out) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= p.N) return;
+  const size_t N = (size_t)p.N;
   const int x = n % p.nx, y = n / p.nx;
   for (int lat = 0; lat < 3; ++lat)
 #pragma unroll
-    for (int i = 0; i < 9; ++i) out[(size_t)(9 * lat + i) * p.N + n] = pull<S, double>(p, P, lat, i, x, y);
+    for (int i = 0; i < 9; ++i) {
+      double v = pull<S, double>(p, P, lat, i, x, y);
+      if (i == 0 && lat > 0 && (lat == 1 || p.surf)) v += ref[(size_t)(lat - 1) * N + n];
+      out[(size_t)(9 * lat + i) * N + n] = v;
+    }
 }
 
 // Positive fraction of a linear triangle / segment (two-triangle area, Sec. 4.1).
@@ -527,14 +552,13 @@ __device__ double seg_frac(double a, double b) {
 }
 
 constexpr int kInv = kInvValues;
-constexpr double kPi = 3.14159265358979323846;
 
 template <class S, class C>
-__global__ __launch_bounds__(kBlock) void k_invariants(DevParams p, const S* __restrict__ P, const C* __restrict__ phipsi,
-                                                       const C* __restrict__ mu, double* __restrict__ partials) {
+__global__ __launch_bounds__(kBlock) void k_invariants(DevParams p, const S* __restrict__ P, const double* __restrict__ phipsi,
+                                                       const double* __restrict__ mu, double* __restrict__ partials) {
   const size_t N = (size_t)p.N;
-  const C* phi = phipsi;
-  const C* psi = phipsi + N;
+  const double* phi = phipsi;
+  const double* psi = phipsi + N;
   double acc[kInv];
   for (int k = 0; k < kInv; ++k) acc[k] = 0.0;
   for (int n = blockIdx.x * kBlock + threadIdx.x; n < p.N; n += gridDim.x * kBlock) {
@@ -542,12 +566,12 @@ __global__ __launch_bounds__(kBlock) void k_invariants(DevParams p, const S* __r
     C f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = pull<S, C>(p, P, 0, i, x, y);
-    const Macro<C> M = macro_node(p, phi, psi, mu, mu + N, f, x, y);
+    const Macro M = macro_node<C>(p, phi, psi, mu, mu + N, f, x, y);
     const double ph = phi[n], ps = psi[n], ux = M.ux, uy = M.uy, pr = M.pr, rho = M.rho;
     if (!isfinite(ph) || !isfinite(ps) || !isfinite(ux) || !isfinite(uy) || !isfinite(pr)) acc[7] += 1.0;
     if (p.surf && !(ps > 0.0 && ps < 1.0)) acc[8] += 1.0;
     acc[0] += ps;
-    acc[1] += 0.5 + (double)gsw<double>(p, ph);
+    acc[1] += 0.5 + gsw(p, ph);
     acc[2] += ph;
     const double u2 = ux * ux + uy * uy;
     acc[4] += 0.5 * rho * u2;
@@ -559,8 +583,8 @@ __global__ __launch_bounds__(kBlock) void k_invariants(DevParams p, const S* __r
       double vp = phi[b.idx], vs = psi[b.idx];
       if (b.side && wet_side(p, b.side)) {
         const double pn = vp, sn = vs;
-        vp = pn + Jphi<double>(p, pn, sn) / p.kappa;
-        if (p.surf && p.lambda_s > 0.0) vs = sn + Jpsi<double>(p, pn, sn) / p.lambda_s;
+        vp = pn + Jphi(p, pn, sn) / p.kappa;
+        if (p.surf && p.lambda_s > 0.0) vs = sn + Jpsi(p, pn, sn) / p.lambda_s;
       }
       const double w3 = 3.0 * WQ<double>(i);
       gpx += w3 * CX(i) * vp; gpy += w3 * CY(i) * vp;
@@ -576,7 +600,7 @@ __global__ __launch_bounds__(kBlock) void k_invariants(DevParams p, const S* __r
     for (int w = 0; w < 2; ++w) {
       if (!(w == 0 ? wall_row_b : wall_row_t)) continue;
       const double l = p.surf ? log(1.0 - ps) : 0.0;
-      e += -(p.sig_cos + l * p.dsb) * (double)gsw<double>(p, ph) + 0.5 * l * p.msb + p.fw0;
+      e += -(p.sig_cos + l * p.dsb) * gsw(p, ph) + 0.5 * l * p.msb + p.fw0;
       if (p.surf) {
         if (p.beta_sg > 0.0 && 1.0 + p.beta_sg * l <= 0.5) acc[9] += 1.0;
         if (p.beta_sl > 0.0 && 1.0 + p.beta_sl * l <= 0.5) acc[9] += 1.0;
@@ -591,8 +615,8 @@ __global__ __launch_bounds__(kBlock) void k_invariants(DevParams p, const S* __r
       const double a = ph, b = phi[(size_t)y * p.nx + x1], c = phi[(size_t)y1 * p.nx + x1], d = phi[(size_t)y1 * p.nx + x];
       acc[3] += 0.5 * tri_frac(a, b, c) + 0.5 * tri_frac(a, c, d);
     }
-    if (!p.periodic_y && y == 0) acc[3] += 0.5 * seg_frac(ph, (double)phi[x1]);
-    if (!p.periodic_y && y == p.ny - 1) acc[3] += 0.5 * seg_frac(ph, (double)phi[(size_t)y * p.nx + x1]);
+    if (!p.periodic_y && y == 0) acc[3] += 0.5 * seg_frac(ph, phi[x1]);
+    if (!p.periodic_y && y == p.ny - 1) acc[3] += 0.5 * seg_frac(ph, phi[(size_t)y * p.nx + x1]);
   }
   for (int k = 0; k < kInv; ++k) {
     const double r = block_reduce(acc[k], k == 6);
@@ -616,15 +640,14 @@ __global__ __launch_bounds__(kBlock) void k_inv_final(int nblk, const double* __
 // above the wall of the first phi = 0 crossing of a liquid column, and the
 // positive fractions of the edges to the next column on the first and second
 // rows; the width is their sums extrapolated linearly to the wall.
-template <class C>
-__global__ __launch_bounds__(kBlock) void k_contact_cols(DevParams p, const C* __restrict__ phi, double* __restrict__ cols) {
+__global__ __launch_bounds__(kBlock) void k_contact_cols(DevParams p, const double* __restrict__ phi, double* __restrict__ cols) {
   const int x = blockIdx.x * kBlock + threadIdx.x;
   if (x >= p.nx) return;
   const int x1 = x + 1 == p.nx ? 0 : x + 1;
-  cols[p.nx + x] = seg_frac((double)phi[x], (double)phi[x1]);
-  cols[2 * p.nx + x] = seg_frac((double)phi[p.nx + x], (double)phi[p.nx + x1]);
+  cols[p.nx + x] = seg_frac(phi[x], phi[x1]);
+  cols[2 * p.nx + x] = seg_frac(phi[p.nx + x], phi[p.nx + x1]);
   double hx = 0.0;
-  if (phi[x] > C(0)) {
+  if (phi[x] > 0.0) {
     hx = p.ny - 0.5;
     for (int y = 0; y + 1 < p.ny; ++y) {
       const double a = phi[(size_t)y * p.nx + x], b = phi[(size_t)(y + 1) * p.nx + x];
@@ -655,34 +678,56 @@ __global__ __launch_bounds__(kBlock) void k_contact_final(int nx, const double* 
 inline int nblocks(int n) { return (n + kBlock - 1) / kBlock; }
 inline int red_blocks(int n) { int b = nblocks(n); return b < kRedBlocks ? b : kRedBlocks; }
 
+// Event pair k of the current timed step (or nothing when not timing).
+struct TimedScope {
+  StepTimer* t;
+  int k;
+  hipStream_t st;
+  TimedScope(StepTimer* t_, int k_, hipStream_t st_) : t(t_), k(k_), st(st_) {
+    if (t) (void)hipEventRecord(t->ev[(t->used * 4 + k) * 2 + 0], st);
+  }
+  ~TimedScope() {
+    if (t) (void)hipEventRecord(t->ev[(t->used * 4 + k) * 2 + 1], st);
+  }
+};
+
 template <class S, class C>
-hipError_t step_impl(const DevParams& p, DevState& s, int have_hist, hipStream_t st) {
-  const size_t N = (size_t)p.N;
-  const S* Pin = (const S*)s.pops[s.cur];
-  S* Pout = (S*)s.pops[s.cur ^ 1];
-  C* pp = (C*)s.phipsi[s.hcur];
-  const C* pp_h = (const C*)s.phipsi[s.hcur ^ 1];
-  C* mu = (C*)s.mu;
+hipError_t macro_impl(const DevParams& p, DevState& s, hipStream_t st, StepTimer* t = nullptr) {
+  double* pp = (double*)s.phipsi[s.hcur];
+  const double* ref = (const double*)s.phipsi[s.hcur ^ 1];
   const int rb = red_blocks(p.N);
-  hipLaunchKernelGGL((k_moments<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, Pin, pp);
-  hipLaunchKernelGGL((k_mu_partials<C>), dim3(rb), dim3(kBlock), 0, st, p, (const C*)pp, mu, s.partials);
-  hipLaunchKernelGGL(k_multipliers, dim3(1), dim3(kBlock), 0, st, rb, p.N, (const double*)s.partials, s.scalars);
-  hipLaunchKernelGGL((k_collide<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, Pin, Pout, (const C*)pp, pp_h,
-                     (const C*)mu, (const C*)s.uhist[s.hcur ^ 1], (C*)s.uhist[s.hcur], (const C*)s.Rhist[s.hcur ^ 1],
-                     (C*)s.Rhist[s.hcur], (const DevScalars*)s.scalars, have_hist);
-  (void)N;
-  s.cur ^= 1;
-  s.hcur ^= 1;
+  {
+    TimedScope ts(t, LBM_K_MOMENTS, st);
+    hipLaunchKernelGGL((k_moments<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur], ref, pp);
+  }
+  {
+    TimedScope ts(t, LBM_K_MU, st);
+    hipLaunchKernelGGL(k_mu_partials, dim3(rb), dim3(kBlock), 0, st, p, (const double*)pp, (double*)s.mu, s.partials);
+  }
+  {
+    TimedScope ts(t, LBM_K_MULTIPLIERS, st);
+    hipLaunchKernelGGL(k_multipliers, dim3(1), dim3(kBlock), 0, st, rb, p.N, (const double*)s.partials, s.scalars);
+  }
   return hipGetLastError();
 }
 
 template <class S, class C>
-hipError_t macro_impl(const DevParams& p, DevState& s, hipStream_t st) {
-  C* pp = (C*)s.phipsi[s.hcur];
-  const int rb = red_blocks(p.N);
-  hipLaunchKernelGGL((k_moments<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur], pp);
-  hipLaunchKernelGGL((k_mu_partials<C>), dim3(rb), dim3(kBlock), 0, st, p, (const C*)pp, (C*)s.mu, s.partials);
-  hipLaunchKernelGGL(k_multipliers, dim3(1), dim3(kBlock), 0, st, rb, p.N, (const double*)s.partials, s.scalars);
+hipError_t step_impl(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer) {
+  StepTimer* t = (timer && timer->ev && timer->used < timer->max_steps) ? timer : nullptr;
+  hipError_t e = macro_impl<S, C>(p, s, st, t);
+  if (e != hipSuccess) return e;
+  const S* Pin = (const S*)s.pops[s.cur];
+  S* Pout = (S*)s.pops[s.cur ^ 1];
+  {
+    TimedScope ts(t, LBM_K_COLLIDE, st);
+    hipLaunchKernelGGL((k_collide<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, Pin, Pout,
+                       (const double*)s.phipsi[s.hcur], (const double*)s.phipsi[s.hcur ^ 1], (const double*)s.mu,
+                       (const C*)s.uhist[s.hcur ^ 1], (C*)s.uhist[s.hcur], (const C*)s.Rhist[s.hcur ^ 1],
+                       (C*)s.Rhist[s.hcur], (const DevScalars*)s.scalars, have_hist);
+  }
+  if (t) t->used += 1;
+  s.cur ^= 1;
+  s.hcur ^= 1;
   return hipGetLastError();
 }
 
@@ -692,10 +737,10 @@ hipError_t inv_impl(const DevParams& p, DevState& s, hipStream_t st) {
   if (e != hipSuccess) return e;
   const int rb = red_blocks(p.N);
   hipLaunchKernelGGL((k_invariants<S, C>), dim3(rb), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur],
-                     (const C*)s.phipsi[s.hcur], (const C*)s.mu, s.inv_partials);
+                     (const double*)s.phipsi[s.hcur], (const double*)s.mu, s.inv_partials);
   hipLaunchKernelGGL(k_inv_final, dim3(1), dim3(kBlock), 0, st, rb, (const double*)s.inv_partials, s.inv_out);
   if (!p.periodic_y) {
-    hipLaunchKernelGGL((k_contact_cols<C>), dim3(nblocks(p.nx)), dim3(kBlock), 0, st, p, (const C*)s.phipsi[s.hcur], s.contact);
+    hipLaunchKernelGGL(k_contact_cols, dim3(nblocks(p.nx)), dim3(kBlock), 0, st, p, (const double*)s.phipsi[s.hcur], s.contact);
     hipLaunchKernelGGL(k_contact_final, dim3(1), dim3(kBlock), 0, st, p.nx, (const double*)s.contact, s.inv_out + kInv);
   }
   return hipGetLastError();
@@ -706,7 +751,21 @@ hipError_t fetch_impl(const DevParams& p, DevState& s, hipStream_t st) {
   hipError_t e = macro_impl<S, C>(p, s, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fields<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur],
-                     (const C*)s.phipsi[s.hcur], (const C*)s.mu, s.field_buf);
+                     (const double*)s.phipsi[s.hcur], (const double*)s.mu, s.field_buf);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t load_impl(const DevParams& p, DevState& s, int with_u, hipStream_t st) {
+  hipLaunchKernelGGL(k_load<S>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const double*)s.field_buf, with_u,
+                     (S*)s.pops[s.cur], (double*)s.phipsi[s.hcur ^ 1]);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t pops_impl(const DevParams& p, DevState& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_pops<S>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur],
+                     (const double*)s.phipsi[s.hcur ^ 1], s.field_buf);
   return hipGetLastError();
 }
 
@@ -726,24 +785,12 @@ hipError_t launch_init(const DevParams& p, DevState& s, hipStream_t st) {
   hipLaunchKernelGGL(k_init_fields, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, s.field_buf);
   return launch_load(p, s, 0, st);
 }
-
 hipError_t launch_load(const DevParams& p, DevState& s, int with_u, hipStream_t st) {
-  switch (s.precision) {
-    case LBM_FP64:
-      hipLaunchKernelGGL(k_load<double>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const double*)s.field_buf, with_u,
-                         (double*)s.pops[s.cur]);
-      break;
-    case LBM_FP32:
-      hipLaunchKernelGGL(k_load<float>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const double*)s.field_buf, with_u,
-                         (float*)s.pops[s.cur]);
-      break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  LBM_DISPATCH(s.precision, (load_impl<double>(p, s, with_u, st)), (load_impl<float>(p, s, with_u, st)));
 }
-
-hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st) {
-  LBM_DISPATCH(s.precision, (step_impl<double, double>(p, s, have_hist, st)), (step_impl<float, float>(p, s, have_hist, st)));
+hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer) {
+  LBM_DISPATCH(s.precision, (step_impl<double, double>(p, s, have_hist, st, timer)),
+               (step_impl<float, float>(p, s, have_hist, st, timer)));
 }
 hipError_t launch_macro(const DevParams& p, DevState& s, hipStream_t st) {
   LBM_DISPATCH(s.precision, (macro_impl<double, double>(p, s, st)), (macro_impl<float, float>(p, s, st)));
@@ -755,16 +802,7 @@ hipError_t launch_fetch(const DevParams& p, DevState& s, uint32_t, hipStream_t s
   LBM_DISPATCH(s.precision, (fetch_impl<double, double>(p, s, st)), (fetch_impl<float, float>(p, s, st)));
 }
 hipError_t launch_fetch_pops(const DevParams& p, DevState& s, hipStream_t st) {
-  switch (s.precision) {
-    case LBM_FP64:
-      hipLaunchKernelGGL(k_pops<double>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const double*)s.pops[s.cur], s.field_buf);
-      break;
-    case LBM_FP32:
-      hipLaunchKernelGGL(k_pops<float>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const float*)s.pops[s.cur], s.field_buf);
-      break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  LBM_DISPATCH(s.precision, (pops_impl<double>(p, s, st)), (pops_impl<float>(p, s, st)));
 }
 
 }  // namespace lbm

@@ -33,7 +33,9 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_UNSUPPORTED", -3: "LBM_E_OOM"
 # Every symbol the header declares; the test suite checks the library exports them.
 EXPORTS = ["lbm_required_bytes", "lbm_init", "lbm_step", "lbm_reduce_invariants", "lbm_fetch_fields",
            "lbm_load_fields", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_derived",
-           "lbm_fetch_populations", "lbm_destroy", "lbm_last_error"]
+           "lbm_fetch_populations", "lbm_destroy", "lbm_last_error", "lbm_timing_begin", "lbm_timing_end",
+           "lbm_bytes_per_node_step"]
+KERNEL_NAMES = ["k_moments", "k_mu_partials", "k_multipliers", "k_collide"]
 
 
 class LbmError(RuntimeError):
@@ -101,6 +103,9 @@ def lib() -> ctypes.CDLL:
         L.lbm_derived.argtypes = [vp, dp]
         L.lbm_fetch_populations.argtypes = [vp, dp, sz]
         L.lbm_destroy.argtypes = [vp]
+        L.lbm_timing_begin.argtypes = [vp, ctypes.c_int64]
+        L.lbm_timing_end.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.lbm_bytes_per_node_step.argtypes = [vp, dp]
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -224,6 +229,20 @@ class Sim:
         buf = ctypes.create_string_buffer(n.value)
         _check(lib().lbm_save_state(self._h, buf, n.value), self._h)
         return buf.raw
+
+    def timing_begin(self, max_steps: int):
+        _check(lib().lbm_timing_begin(self._h, int(max_steps)), self._h)
+
+    def timing_end(self) -> dict:
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        _check(lib().lbm_timing_end(self._h, ms, n), self._h)
+        return {KERNEL_NAMES[k]: (ms[k], n[k]) for k in range(4)}
+
+    def bytes_per_node_step(self) -> float:
+        b = ctypes.c_double()
+        _check(lib().lbm_bytes_per_node_step(self._h, ctypes.byref(b)), self._h)
+        return b.value
 
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))

@@ -199,6 +199,9 @@ def test_error_paths(lbm):
     inv = g.invariants(check=False)
     assert inv["status"] == -6 and inv["psi_out_of_range"] >= 1
     with pytest.raises(lbm.LbmError) as e:
+        g.step(1)
+    assert e.value.code == -7
+    with pytest.raises(lbm.LbmError) as e:
         lbm.Sim(dict(cfg, nx=2), "fp64")
     assert e.value.code == -1
 
