@@ -181,11 +181,12 @@ int lbm_fetch_populations(lbm_handle* h, double* host, size_t n_doubles);
 
 /* Kernel timing with HIP events on the handle's stream.  lbm_timing_begin
  * creates event pairs for up to max_steps steps; every following lbm_step
- * brackets each of its kernels (LBM_K_* below) with an event pair until the
- * pairs run out.  lbm_timing_end synchronises the stream and writes, per
- * kernel kind, the summed duration in ms (ms[LBM_N_KERNELS]) and the number of
- * launches timed (launches[LBM_N_KERNELS]); it releases the events. */
-enum { LBM_K_MOMENTS = 0, LBM_K_MU = 1, LBM_K_MULTIPLIERS = 2, LBM_K_COLLIDE = 3, LBM_N_KERNELS = 4 };
+ * brackets each of its kernels (LBM_K_* below; one fused kernel per step) with
+ * an event pair until the pairs run out.  lbm_timing_end synchronises the
+ * stream and writes, per kernel kind, the summed duration in ms
+ * (ms[LBM_N_KERNELS]) and the number of launches timed
+ * (launches[LBM_N_KERNELS]); it releases the events. */
+enum { LBM_K_STEP = 0, LBM_N_KERNELS = 1 };
 int lbm_timing_begin(lbm_handle* h, int64_t max_steps);
 int lbm_timing_end(lbm_handle* h, double* ms, int64_t* launches);
 

@@ -23,6 +23,7 @@ struct StateHeader {
   int32_t precision, nx, ny, have_hist;
   int64_t step;
   uint64_t params_hash;
+  double pending[3];  // multipliers pending on the stored populations (lambda, mubar, weight)
 };
 
 uint64_t hash_bytes(const void* data, size_t n) {  // FNV-1a
@@ -35,7 +36,7 @@ uint64_t hash_bytes(const void* data, size_t n) {  // FNV-1a
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t pops, phipsi, mu, uhist, Rhist, partials, inv_partials, inv_out, contact, scalars, field_buf, total;
+  size_t pops, phipsi, mu, uhist, partials, inv_partials, inv_out, contact, scalars, counter, field_buf, total;
 };
 
 Layout make_layout(const lbm_params& p) {
@@ -47,13 +48,14 @@ Layout make_layout(const lbm_params& p) {
   L.pops = take(2 * 27 * N * sb);
   L.phipsi = take(2 * 2 * N * sizeof(double));  // phi, psi: FP64 in every precision
   L.mu = take(2 * N * sizeof(double));
-  L.uhist = take(2 * 4 * N * cb);
-  L.Rhist = take(2 * 2 * N * cb);
-  L.partials = take(lbm::kRedBlocks * 3 * sizeof(double));
+  L.uhist = take(2 * 6 * N * cb);  // u, v (advecting), R_phi, R_psi history, ping-pong
+  const size_t ntile = lbm::fused_tiles(p.nx, p.ny, 4);  // the most tiles any tile height gives
+  L.partials = take((ntile > (size_t)lbm::kRedBlocks ? ntile : (size_t)lbm::kRedBlocks) * 3 * sizeof(double));
   L.inv_partials = take(lbm::kRedBlocks * lbm::kInvValues * sizeof(double));
   L.inv_out = take(lbm::kInvOut * sizeof(double));
   L.contact = take(3 * (size_t)p.nx * sizeof(double));
-  L.scalars = take(sizeof(lbm::DevScalars));
+  L.scalars = take(3 * sizeof(lbm::DevScalars));
+  L.counter = take(sizeof(unsigned));
   L.field_buf = take(27 * N * sizeof(double));
   L.total = off;
   return L;
@@ -187,14 +189,15 @@ void carve(lbm_handle* h) {
   s.phipsi[1] = b + L.phipsi + 2 * N * sizeof(double);
   s.mu = b + L.mu;
   s.uhist[0] = b + L.uhist;
-  s.uhist[1] = b + L.uhist + 4 * N * cb;
-  s.Rhist[0] = b + L.Rhist;
-  s.Rhist[1] = b + L.Rhist + 2 * N * cb;
+  s.uhist[1] = b + L.uhist + 6 * N * cb;
   s.partials = (double*)(b + L.partials);
   s.inv_partials = (double*)(b + L.inv_partials);
   s.inv_out = (double*)(b + L.inv_out);
   s.contact = (double*)(b + L.contact);
   s.scalars = (lbm::DevScalars*)(b + L.scalars);
+  s.counter = (unsigned*)(b + L.counter);
+  s.scur = 0;
+  s.tile_rows = lbm::fused_tile_rows(h->dp.nx, h->dp.ny);
   s.field_buf = (double*)(b + L.field_buf);
   s.cur = 0;
   s.hcur = 0;
@@ -284,7 +287,7 @@ int lbm_reduce_invariants(lbm_handle* h, lbm_invariants* out) {
   double v[lbm::kInvOut] = {0};
   lbm::DevScalars sc;
   HIP_OR_FAIL(h, hipMemcpyAsync(v, h->ds.inv_out, sizeof(v), hipMemcpyDeviceToHost, h->stream), "copy invariants");
-  HIP_OR_FAIL(h, hipMemcpyAsync(&sc, h->ds.scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream), "copy multipliers");
+  HIP_OR_FAIL(h, hipMemcpyAsync(&sc, h->ds.scalars + 2, sizeof(sc), hipMemcpyDeviceToHost, h->stream), "copy multipliers");
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream), "synchronise");
   std::memset(out, 0, sizeof(*out));
   out->step = h->step;
@@ -366,7 +369,9 @@ int lbm_save_state(lbm_handle* h, void* host, size_t bytes) {
   if (!host || bytes < need) return fail(h, LBM_E_ARG, "state buffer too small");
   const size_t N = (size_t)h->dp.N;
   const size_t sb = lbm::storage_bytes(h->prm.precision), cb = lbm::compute_bytes(h->prm.precision);
-  StateHeader hd{kStateMagic, h->prm.precision, h->prm.nx, h->prm.ny, h->have_hist, h->step, hash_bytes(&h->prm, sizeof(h->prm))};
+  StateHeader hd{kStateMagic, h->prm.precision, h->prm.nx, h->prm.ny, h->have_hist, h->step, hash_bytes(&h->prm, sizeof(h->prm)), {0, 0, 0}};
+  HIP_OR_FAIL(h, hipMemcpyAsync(hd.pending, h->ds.scalars + h->ds.scur, sizeof(hd.pending), hipMemcpyDeviceToHost, h->stream), "save");
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream), "synchronise");
   char* o = (char*)host;
   std::memcpy(o, &hd, sizeof(hd));
   o += sizeof(hd);
@@ -375,9 +380,7 @@ int lbm_save_state(lbm_handle* h, void* host, size_t bytes) {
   o += 27 * N * sb;
   HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.phipsi[hp], 2 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream), "save");
   o += 2 * N * sizeof(double);
-  HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.uhist[hp], 4 * N * cb, hipMemcpyDeviceToHost, h->stream), "save");
-  o += 4 * N * cb;
-  HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.Rhist[hp], 2 * N * cb, hipMemcpyDeviceToHost, h->stream), "save");
+  HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.uhist[hp], 6 * N * cb, hipMemcpyDeviceToHost, h->stream), "save");
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream), "synchronise");
   return LBM_OK;
 }
@@ -400,9 +403,8 @@ int lbm_load_state(lbm_handle* h, const void* host, size_t bytes) {
   o += 27 * N * sb;
   HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.phipsi[hp], o, 2 * N * sizeof(double), hipMemcpyHostToDevice, h->stream), "load");
   o += 2 * N * sizeof(double);
-  HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.uhist[hp], o, 4 * N * cb, hipMemcpyHostToDevice, h->stream), "load");
-  o += 4 * N * cb;
-  HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.Rhist[hp], o, 2 * N * cb, hipMemcpyHostToDevice, h->stream), "load");
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.uhist[hp], o, 6 * N * cb, hipMemcpyHostToDevice, h->stream), "load");
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.scalars + h->ds.scur, hd.pending, sizeof(hd.pending), hipMemcpyHostToDevice, h->stream), "load");
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream), "synchronise");
   h->have_hist = hd.have_hist;
   h->step = hd.step;
@@ -429,7 +431,7 @@ int lbm_fetch_populations(lbm_handle* h, double* host, size_t n_doubles) {
 namespace {
 void release_timer(lbm_handle* h) {
   if (!h->timer.ev) return;
-  for (int64_t k = 0; k < h->timer.max_steps * 8; ++k) (void)hipEventDestroy(h->timer.ev[k]);
+  for (int64_t k = 0; k < h->timer.max_steps * 2 * LBM_N_KERNELS; ++k) (void)hipEventDestroy(h->timer.ev[k]);
   delete[] h->timer.ev;
   h->timer = lbm::StepTimer();
 }
@@ -439,11 +441,11 @@ int lbm_timing_begin(lbm_handle* h, int64_t max_steps) {
   if (!h) return fail(nullptr, LBM_E_ARG, "null handle");
   if (max_steps <= 0 || max_steps > 1000000) return fail(h, LBM_E_ARG, "max_steps must lie in [1, 1e6]");
   release_timer(h);
-  h->timer.ev = new hipEvent_t[max_steps * 8];
-  for (int64_t k = 0; k < max_steps * 8; ++k) {
+  const int64_t per_step = 2 * LBM_N_KERNELS;
+  h->timer.ev = new hipEvent_t[max_steps * per_step];
+  for (int64_t k = 0; k < max_steps * per_step; ++k) {
     hipError_t e = hipEventCreate(&h->timer.ev[k]);
     if (e != hipSuccess) {
-      h->timer.max_steps = k / 8;  // destroy only what was created
       for (int64_t j = 0; j < k; ++j) (void)hipEventDestroy(h->timer.ev[j]);
       delete[] h->timer.ev;
       h->timer = lbm::StepTimer();
@@ -463,7 +465,7 @@ int lbm_timing_end(lbm_handle* h, double* ms, int64_t* launches) {
   for (int64_t s = 0; s < h->timer.used; ++s)
     for (int k = 0; k < LBM_N_KERNELS; ++k) {
       float t = 0.f;
-      hipError_t e = hipEventElapsedTime(&t, h->timer.ev[(s * 4 + k) * 2], h->timer.ev[(s * 4 + k) * 2 + 1]);
+      hipError_t e = hipEventElapsedTime(&t, h->timer.ev[(s * LBM_N_KERNELS + k) * 2], h->timer.ev[(s * LBM_N_KERNELS + k) * 2 + 1]);
       if (e != hipSuccess) { release_timer(h); return hip_fail(h, e, "hipEventElapsedTime"); }
       ms[k] += t;
       launches[k] += 1;

@@ -30,9 +30,13 @@ struct DevParams {
   int init_kind;
 };
 
-// FP64 multiplier state kept on the device.
+// FP64 multiplier state kept on the device.  The fused step leaves the
+// multiplier terms of its own sources out of the stored populations and
+// applies them when the next step gathers them: cdef is the weight of that
+// pending term (1.5 from R + dR/2, or 1 on a first step; 0 when nothing is
+// pending, e.g. right after loading fields).
 struct DevScalars {
-  double lambda_phi, mubar_psi;  // multipliers of the current step
+  double lambda_phi, mubar_psi, cdef;
 };
 
 // FP64 invariant accumulators per block: mass_psi, m_phi_h, sum_phi, area,
@@ -47,22 +51,29 @@ struct DevState {
   void* pops[2];           // 27 planes each, storage type
   void* phipsi[2];         // 2 planes each (phi, psi), FP64; also the shift reference of g_0, h_0
   void* mu;                // 2 planes (mu_phi, mu_psi), FP64
-  void* uhist[2];          // 4 planes each (ux, uy, vx, vy): velocity and advecting velocity, compute type
-  void* Rhist[2];          // 2 planes each (R_phi, R_psi), compute type
+  void* uhist[2];          // 6 planes each: ux, uy, vx, vy (velocity and advecting velocity) and the
+                           // stored sources R_phi, R_psi (without their multiplier terms), compute type
   double* partials;        // reduction partials [kRedBlocks][3]
   double* inv_partials;    // invariant partials [kRedBlocks][kInvValues]
   double* inv_out;         // final invariants [kInvOut]
   double* contact;         // [nx] column heights + 2 x [nx] edge fractions (rows 0 and 1)
-  DevScalars* scalars;
+  DevScalars* scalars;     // [3]: pending multipliers (ping-pong by scur) and the diagnostic slot [2]
+  unsigned* counter;       // last-block-done counter of the fused step
   double* field_buf;       // FP64 staging for fetch/load, [27][N]
+  int scur;                // scalars[scur] holds the multipliers pending on the stored populations
+  int tile_rows;           // tile height of the fused step (4, 8 or 16); width is 64
   int cur;                 // index of the current population buffer
   int hcur;                // phi/psi and history buffer written by the next step
 };
 
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 1024;
+constexpr int kTileX = 64;
+constexpr int kMaxTiles = 1 << 22;   // partials of the fused step: [kMaxTiles][3] at most (grid <= 2^28 nodes at 64x16)
 
 size_t storage_bytes(int precision);
+int fused_tile_rows(int nx, int ny);  // tile height of the fused step for a grid
+size_t fused_tiles(int nx, int ny, int tile_rows);
 size_t compute_bytes(int precision);
 
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the HIP status.
@@ -70,7 +81,7 @@ hipError_t launch_init(const DevParams& p, DevState& s, hipStream_t stream);
 hipError_t launch_load(const DevParams& p, DevState& s, int with_u, hipStream_t stream);
 // Optional event pairs bracketing each kernel of a step (index by LBM_K_*).
 struct StepTimer {
-  hipEvent_t* ev = nullptr;  // [max_steps][4][2]
+  hipEvent_t* ev = nullptr;  // [max_steps][LBM_N_KERNELS][2]
   int64_t max_steps = 0, used = 0;
 };
 hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t stream, StepTimer* timer = nullptr);

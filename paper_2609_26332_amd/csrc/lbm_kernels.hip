@@ -22,7 +22,9 @@
 //   k_mu_partials  mu_phi, mu_psi with the wall terms; per-block FP64 sums of
 //                  h'(phi) mu_phi, h'(phi)^2, mu_psi                (eq_muphi, eq_mupsi, eq15)
 //   k_multipliers  lambda_phi = S1/S2, mubar_psi = S3/N             (eq15, AC_psi)
-//   k_collide      force, velocity, pressure, sources, MRT collision of f, g, h,
+//   k_step         fused step on 64 x TY tiles (see its comment): phi, psi,
+//                  chemical potentials, multiplier sums, force, velocity, pressure,
+//                  sources, MRT collision of f, g, h,
 //                  wall corrections; writes post-collision populations
 //                  and the history for the backward differences
 // No MFMA: the step moves ~300 B/node in FP32 storage and does ~2 kflop/node,
@@ -202,21 +204,37 @@ __device__ double block_reduce(double v, bool is_max) {
 }
 
 // ------------------------------------------------------------------- kernels
-// phi(n+1) = phi(n) + [stored g_0 shift + sum of the gathered moving g_i].
+// Node (x, y) of the source of gathered population i (its emitter): x - c_i
+// inside the fluid, the node itself for a bounce-back at a wall.
+__device__ __forceinline__ int emitter(const DevParams& p, int i, int x, int y) {
+  int sx = wrap(x - CX(i), p.nx), sy = y - CY(i);
+  if (p.periodic_y) sy = wrap(sy, p.ny);
+  else if (sy < 0 || sy >= p.ny) return y * p.nx + x;
+  return sy * p.nx + sx;
+}
+
+// phi(n+1) = phi(n) + [stored g_0 shift + sum of the gathered moving g_i]
+// + the pending multiplier term cdef M_phi lambda(n) sum_i w_i h'(phi(n)(emitter_i));
+// psi likewise with the uniform term cdef M_psi mubar(n).
 template <class S, class C>
 __global__ __launch_bounds__(kBlock) void k_moments(DevParams p, const S* __restrict__ P, const double* __restrict__ prev,
-                                                    double* __restrict__ phipsi) {
+                                                    const DevScalars* __restrict__ pend, double* __restrict__ phipsi) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= p.N) return;
   const int x = n % p.nx, y = n / p.nx;
+  const double lam = pend->cdef * p.M_phi * pend->lambda_phi;
   C a = C(0), b = C(0);
+  double corr = 0.0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) a += pull<S, C>(p, P, 1, i, x, y);
-  phipsi[n] = prev[n] + (double)a;
+  for (int i = 0; i < 9; ++i) {
+    a += pull<S, C>(p, P, 1, i, x, y);
+    corr += WQ<double>(i) * hprime(p, prev[emitter(p, i, x, y)]);
+  }
+  phipsi[n] = prev[n] + (double)a + lam * corr;
   if (p.surf) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) b += pull<S, C>(p, P, 2, i, x, y);
-    phipsi[(size_t)p.N + n] = prev[(size_t)p.N + n] + (double)b;
+    phipsi[(size_t)p.N + n] = prev[(size_t)p.N + n] + (double)b + pend->cdef * p.M_psi * pend->mubar_psi;
   } else {
     phipsi[(size_t)p.N + n] = 0.0;
   }
@@ -325,110 +343,322 @@ __device__ __forceinline__ void collide_scalar(const C* c, C c0, C eta, C vx, C 
   o[0] = Rt - m[3] - m[5] + m[8];
 }
 
-template <class S, class C>
-__global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const S* __restrict__ Pin, S* __restrict__ Pout,
-                                                    const double* __restrict__ phipsi, const double* __restrict__ phipsi_h,
-                                                    const double* __restrict__ mu, const C* __restrict__ u_h, C* __restrict__ u_out,
-                                                    const C* __restrict__ R_h, C* __restrict__ R_out,
-                                                    const DevScalars* __restrict__ sc, int have_hist) {
-  const int n = blockIdx.x * kBlock + threadIdx.x;
-  if (n >= p.N) return;
+// XCD-aware order of the tiles: the hardware hands consecutive workgroups to
+// the eight XCDs in turn; remapping gives each XCD one contiguous band of tiles
+// so that the halo rows a tile re-reads sit in that XCD's own L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb / 8, r = nb % 8, xcd = b % 8, idx = b / 8;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+__device__ __forceinline__ int modp(int a, int n) { a %= n; return a < 0 ? a + n : a; }
+
+struct StepArgs {
+  const void* Pin;
+  void* Pout;
+  const double* ref;        // phi(n-1), psi(n-1): FP64 planes, shift reference of the stored rest populations
+  double* out;              // phi(n), psi(n)
+  const void* hin;          // u, v (advecting), R_phi, R_psi of step n-1: 6 planes, compute type
+  void* hout;               // the same for step n
+  const DevScalars* pend;   // multipliers pending on Pin (from step n-1)
+  DevScalars* next;         // multipliers of step n, written by the last tile
+  double* partials;         // [ntiles][3]
+  unsigned* counter;
+  int have_hist, ntx, ntiles;
+};
+
+// One fused time step on a 64 x TY tile of nodes (256 threads):
+//  A  phi(n), psi(n) on the tile and a halo of 2 from the gathered g, h, the
+//     FP64 reference planes and the pending multiplier term (halo of 3 of
+//     phi(n-1) in LDS); the tile's values go to the output planes
+//  B  mu_phi, mu_psi on the tile and a halo of 1 (wall terms from the
+//     first fluid row); FP64 block sums of h' mu_phi, h'^2, mu_psi
+//  C  force, velocity, pressure, sources, collision of the tile nodes; the
+//     multiplier terms of this step's sources are left out of the stored
+//     populations and of the stored source history (deferred to step n+1)
+//  D  the last tile to finish reduces the block sums to lambda(n), mubar(n)
+template <class S, class C, int TY>
+__global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
+  constexpr int W3 = kTileX + 6, H3 = TY + 6, W2 = kTileX + 4, H2 = TY + 4, W1 = kTileX + 2, H1 = TY + 2;
+  __shared__ double sP3[H3][W3];                  // phi(n-1), halo 3
+  __shared__ double sPhi[H2][W2], sPsi[H2][W2];   // phi(n), psi(n), halo 2 (ghost rows mirrored)
+  __shared__ double sMp[H1][W1], sMs[H1][W1];     // mu_phi, mu_psi, halo 1 (ghost rows mirrored)
+  __shared__ int sLast;
+
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int X0 = (tile % a.ntx) * kTileX, Y0 = (tile / a.ntx) * TY;
   const size_t N = (size_t)p.N;
-  const int x = n % p.nx, y = n / p.nx;
-  const double* phi = phipsi;
-  const double* psi = phipsi + N;
-  const double ph = phi[n], ps = psi[n];
+  const S* Pin = (const S*)a.Pin;
+  S* Pout = (S*)a.Pout;
+  const double lam1 = a.pend->cdef * p.M_phi * a.pend->lambda_phi;   // pending term weights
+  const double mub1 = a.pend->cdef * p.M_psi * a.pend->mubar_psi;
+  auto fluid_row = [&](int gy) { return p.periodic_y || (gy >= 0 && gy < p.ny); };
+  auto row_of = [&](int gy) { return p.periodic_y ? modp(gy, p.ny) : (gy < 0 ? 0 : (gy >= p.ny ? p.ny - 1 : gy)); };
 
-  C f[9], g[9], h[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    f[i] = pull<S, C>(p, Pin, 0, i, x, y);
-    g[i] = i ? pull<S, C>(p, Pin, 1, i, x, y) : C(0);
-    h[i] = (i && p.surf) ? pull<S, C>(p, Pin, 2, i, x, y) : C(0);
+  // ---- A0: phi(n-1) on the halo-3 region (ghost rows: nearest fluid row)
+  for (int k = threadIdx.x; k < H3 * W3; k += kBlock) {
+    const int ly = k / W3, lx = k - ly * W3;
+    sP3[ly][lx] = a.ref[(size_t)row_of(Y0 - 3 + ly) * p.nx + modp(X0 - 3 + lx, p.nx)];
   }
-  const Macro M = macro_node<C>(p, phi, psi, mu, mu + N, f, x, y);
-  const double rho = M.rho, ux = M.ux, uy = M.uy;
+  __syncthreads();
 
-  // Sources (Sec. 3) with the wall-flux terms; multipliers from the reduction.
-  const Lap L = laplace(p, phi, psi, x, y);
-  const double hp = hprime(p, ph);
-  const double Rp = p.M_phi * (-4.0 * p.beta * (1.0 - ps) * (ph * ph * ph - ph) - p.W * ps * ph + sc->lambda_phi * hp) + p.M_phi * L.Tp;
-  double Rs = 0.0;
-  if (p.surf) {
-    const double q = 1.0 - ph * ph;
-    Rs = -p.M0 * L.l0s + p.M_psi * (-p.kBT * log(ps / (1.0 - ps)) + p.beta * q * q - 0.5 * p.W * ph * ph + sc->mubar_psi)
-       + p.M_psi * L.Ts;
-  }
-  // Velocity advecting phi and psi: mean of this and the previous step (removes
-  // the lattice's period-2 staggered momentum from the scalar transport), or
-  // u itself when adv_raw is set.  Backward differences are zero on the first step.
-  double vx = ux, vy = uy;
-  double dpx = 0, dpy = 0, dsx = 0, dsy = 0, dRp = 0, dRs = 0;
-  if (have_hist) {
-    if (!p.adv_raw) {
-      vx = 0.5 * (ux + (double)u_h[n]);
-      vy = 0.5 * (uy + (double)u_h[N + n]);
-    }
-    const double vxh = u_h[2 * N + n], vyh = u_h[3 * N + n], phh = phipsi_h[n], psh = phipsi_h[N + n];
-    dpx = ph * vx - phh * vxh;
-    dpy = ph * vy - phh * vyh;
-    dsx = ps * vx - psh * vxh;
-    dsy = ps * vy - psh * vyh;
-    dRp = Rp - (double)R_h[n];
-    dRs = Rs - (double)R_h[N + n];
-  }
-
-  // ---- lattice 1: MRT with the pressure-based equilibrium and A^1 forcing
-  {
-    C m[9], o[9];
-    m[0] = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-    moments_noncons(f, m);
-    const double uu = ux * ux + uy * uy, pr = M.pr;
-    const double third = 1.0 / 3.0;
-    const double a = ux * M.grx + uy * M.gry;
-    const C meq[9] = {C(0), (C)(rho * ux), (C)(rho * uy), (C)(pr + rho * ux * ux), (C)(rho * ux * uy), (C)(pr + rho * uy * uy),
-                      (C)(rho * uy * third), (C)(rho * ux * third), (C)((pr + rho * uu) * third)};
-    const C mv[9] = {(C)a, (C)M.Fx, (C)M.Fy, (C)(ux * M.grx + uy * M.gry * third), (C)((ux * M.gry + uy * M.grx) * third),
-                     (C)(uy * M.gry + ux * M.grx * third), (C)(M.Fy * third), (C)(M.Fx * third), (C)(a * third)};
-    const C s2 = p.s2_local ? (C)(1.0 / (3.0 * mud_of(p, ph) / rho + 0.5)) : (C)p.sf[2];
-    const C rt[9] = {(C)p.sf[0], (C)p.sf[1], (C)p.sf[1], s2, s2, s2, (C)p.sf[3], (C)p.sf[3], (C)p.sf[4]};
-#pragma unroll
-    for (int k = 0; k < 9; ++k) m[k] = m[k] - rt[k] * (m[k] - meq[k]) + (C(1) - C(0.5) * rt[k]) * mv[k];
-    moving_populations(m, o);
-    o[0] = m[0] - m[3] - m[5] + m[8];
-    // no-slip walls: moving-wall correction on the populations that will bounce back
-    const bool wb = !p.periodic_y && y == 0 && p.bc_bottom != LBM_BC_FREESLIP;
-    const bool wt = !p.periodic_y && y == p.ny - 1 && p.bc_top != LBM_BC_FREESLIP;
+  // ---- A: phi(n), psi(n) on the halo-2 region
+#pragma unroll 1
+  for (int k = threadIdx.x; k < H2 * W2; k += kBlock) {
+    const int ly = k / W2, lx = k - ly * W2;
+    const int gy = Y0 - 2 + ly;
+    if (!fluid_row(gy)) continue;
+    const int x = modp(X0 - 2 + lx, p.nx), y = row_of(gy);
+    C sg = C(0), sh = C(0);
+    double corr = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      C v = o[i];
-      if (wb && CY(i) < 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_bottom);
-      if (wt && CY(i) > 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_top);
-      Pout[(size_t)i * N + n] = (S)v;
+      sg += pull<S, C>(p, Pin, 1, i, x, y);
+      // emitter of g_i in LDS coordinates: x - c_i, or the node itself at a wall
+      const int sy = gy - CY(i);
+      const bool bb = !p.periodic_y && (sy < 0 || sy >= p.ny);
+      corr += WQ<double>(i) * hprime(p, bb ? sP3[ly + 1][lx + 1] : sP3[ly + 1 - CY(i)][lx + 1 - CX(i)]);
+    }
+    const size_t node = (size_t)y * p.nx + x;
+    const double ph = sP3[ly + 1][lx + 1] + (double)sg + lam1 * corr;
+    double ps = 0.0;
+    if (p.surf) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) sh += pull<S, C>(p, Pin, 2, i, x, y);
+      ps = a.ref[N + node] + (double)sh + mub1;
+    }
+    sPhi[ly][lx] = ph;
+    sPsi[ly][lx] = ps;
+    const int tx = lx - 2, ty = ly - 2;
+    if (tx >= 0 && tx < kTileX && ty >= 0 && ty < TY && X0 + tx < p.nx && Y0 + ty < p.ny) {
+      a.out[node] = ph;
+      a.out[N + node] = ps;
     }
   }
-  // ---- lattices 2 and 3: eta-equilibria, A^k d_t(c v) forcing, w_i (R + R_t/2)
-  {
-    C o[9];
-    collide_scalar<C>(g, (C)ph, (C)p.eta_phi, (C)vx, (C)vy, (C)dpx, (C)dpy, (C)(Rp + 0.5 * dRp), p.sg, o);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) Pout[(size_t)(9 + i) * N + n] = (S)o[i];
+  __syncthreads();
+  if (!p.periodic_y) {  // ghost rows take the nearest fluid row of the same column
+    for (int k = threadIdx.x; k < H2 * W2; k += kBlock) {
+      const int ly = k / W2, lx = k - ly * W2;
+      const int gy = Y0 - 2 + ly;
+      if (fluid_row(gy)) continue;
+      const int src = row_of(gy) - (Y0 - 2);
+      sPhi[ly][lx] = sPhi[src][lx];
+      sPsi[ly][lx] = sPsi[src][lx];
+    }
+    __syncthreads();
   }
-  if (p.surf) {
-    C o[9];
-    collide_scalar<C>(h, (C)ps, (C)p.eta_psi, (C)vx, (C)vy, (C)dsx, (C)dsy, (C)(Rs + 0.5 * dRs), p.sh, o);
+
+  // ---- B: chemical potentials on the halo-1 region, block sums on the tile
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 1
+  for (int k = threadIdx.x; k < H1 * W1; k += kBlock) {
+    const int ly = k / W1, lx = k - ly * W1;
+    const int gy = Y0 - 1 + ly;
+    if (!fluid_row(gy)) continue;
+    const int cy = ly + 1, cx = lx + 1;   // in sPhi
+    const double ph = sPhi[cy][cx], ps = sPsi[cy][cx];
+    Lap L{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Pout[(size_t)(18 + i) * N + n] = (S)o[i];
-  } else {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) Pout[(size_t)(18 + i) * N + n] = (S)C(0);
+    for (int i = 1; i < 9; ++i) {
+      const double w2 = 6.0 * WQ<double>(i);
+      const double pn = sPhi[cy + CY(i)][cx + CX(i)], sn = sPsi[cy + CY(i)][cx + CX(i)];
+      L.l0p += w2 * (pn - ph);
+      L.l0s += w2 * (sn - ps);
+      const int ny_ = gy + CY(i);
+      if (!p.periodic_y && (ny_ < 0 || ny_ >= p.ny) && wet_side(p, ny_ < 0 ? -1 : 1)) {
+        // fluid node next to the ghost: same row, column x + c_x
+        const double pf = sPhi[cy][cx + CX(i)], sf = sPsi[cy][cx + CX(i)];
+        L.Tp += w2 * Jphi(p, pf, sf);
+        if (p.surf) L.Ts += w2 * Jpsi(p, pf, sf);
+      }
+    }
+    const double mp = mu_phi_of(p, ph, ps, L), ms = mu_psi_of(p, ph, ps, L);
+    sMp[ly][lx] = mp;
+    sMs[ly][lx] = ms;
+    const int tx = lx - 1, ty = ly - 1;
+    if (tx >= 0 && tx < kTileX && ty >= 0 && ty < TY && X0 + tx < p.nx && Y0 + ty < p.ny) {
+      const double hp = hprime(p, ph);
+      s1 += hp * mp;
+      s2 += hp * hp;
+      s3 += ms;
+    }
   }
-  u_out[n] = (C)ux;
-  u_out[N + n] = (C)uy;
-  u_out[2 * N + n] = (C)vx;
-  u_out[3 * N + n] = (C)vy;
-  R_out[n] = (C)Rp;
-  R_out[N + n] = (C)Rs;
+  s1 = block_reduce(s1, false);
+  s2 = block_reduce(s2, false);
+  s3 = block_reduce(s3, false);
+  if (threadIdx.x == 0) {
+    a.partials[3 * (size_t)tile + 0] = s1;
+    a.partials[3 * (size_t)tile + 1] = s2;
+    a.partials[3 * (size_t)tile + 2] = s3;
+  }
+  if (!p.periodic_y) {
+    for (int k = threadIdx.x; k < H1 * W1; k += kBlock) {
+      const int ly = k / W1, lx = k - ly * W1;
+      const int gy = Y0 - 1 + ly;
+      if (fluid_row(gy)) continue;
+      const int src = row_of(gy) - (Y0 - 1);
+      sMp[ly][lx] = sMp[src][lx];
+      sMs[ly][lx] = sMs[src][lx];
+    }
+  }
+  __syncthreads();
+
+  // ---- C: collide the tile nodes
+  const int tx = threadIdx.x % kTileX;
+  const C* hin = (const C*)a.hin;
+  C* hout = (C*)a.hout;
+#pragma unroll 1
+  for (int ty = threadIdx.x / kTileX; ty < TY; ty += kBlock / kTileX) {
+    const int gx = X0 + tx, gy = Y0 + ty;
+    if (gx >= p.nx || gy >= p.ny) continue;
+    const int n = gy * p.nx + gx;
+    const int cy = ty + 2, cx = tx + 2;   // in sPhi
+    const double ph = sPhi[cy][cx], ps = sPsi[cy][cx];
+    const double ph0 = sP3[ty + 3][tx + 3];  // phi(n-1)
+
+    C f[9], g[9], h[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      f[i] = pull<S, C>(p, Pin, 0, i, gx, gy);
+      if (i == 0) { g[0] = C(0); h[0] = C(0); continue; }
+      const int sy = gy - CY(i);
+      const bool bb = !p.periodic_y && (sy < 0 || sy >= p.ny);
+      const double hpe = hprime(p, bb ? ph0 : sP3[ty + 3 - CY(i)][tx + 3 - CX(i)]);
+      g[i] = pull<S, C>(p, Pin, 1, i, gx, gy) + (C)(lam1 * WQ<double>(i) * hpe);
+      h[i] = p.surf ? pull<S, C>(p, Pin, 2, i, gx, gy) + (C)(mub1 * WQ<double>(i)) : C(0);
+    }
+    // gradients of rho (wetting ghosts), mu_phi, mu_psi; local Laplacian pieces
+    double grx = 0, gry = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0;
+    Lap L{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const double w3 = 3.0 * WQ<double>(i), w2 = 2.0 * w3;
+      const double pn = sPhi[cy + CY(i)][cx + CX(i)], sn = sPsi[cy + CY(i)][cx + CX(i)];
+      const int ny_ = gy + CY(i);
+      const bool ghost = !p.periodic_y && (ny_ < 0 || ny_ >= p.ny);
+      double rn;
+      if (ghost && wet_side(p, ny_ < 0 ? -1 : 1)) {
+        const double Jp = Jphi(p, pn, sn);
+        rn = rho_of(p, pn + Jp / p.kappa);
+        L.Tp += w2 * Jp;
+        if (p.surf) L.Ts += w2 * Jpsi(p, pn, sn);
+      } else {
+        rn = rho_of(p, pn);
+      }
+      L.l0s += w2 * (sn - ps);
+      grx += w3 * CX(i) * rn;
+      gry += w3 * CY(i) * rn;
+      const double mpn = sMp[ty + 1 + CY(i)][tx + 1 + CX(i)], msn = sMs[ty + 1 + CY(i)][tx + 1 + CX(i)];
+      gpx += w3 * CX(i) * mpn;
+      gpy += w3 * CY(i) * mpn;
+      gsx += w3 * CX(i) * msn;
+      gsy += w3 * CY(i) * msn;
+    }
+    const double rho = rho_of(p, ph);
+    const double Fx = -ph * gpx - ps * gsx + rho * p.gx, Fy = -ph * gpy - ps * gsy + rho * p.gy;
+    const double ux = ((double)(f[1] - f[3] + f[5] - f[6] - f[7] + f[8]) + 0.5 * Fx) / rho;
+    const double uy = ((double)(f[2] - f[4] + f[5] + f[6] - f[7] - f[8]) + 0.5 * Fy) / rho;
+    const double snz = (double)(f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]);
+    const double pr = 0.6 * (snz + 0.5 * (ux * grx + uy * gry) - rho * (2.0 / 3.0) * (ux * ux + uy * uy));
+
+    // sources without this step's multiplier terms (those are deferred)
+    const double Rp0 = p.M_phi * (-4.0 * p.beta * (1.0 - ps) * (ph * ph * ph - ph) - p.W * ps * ph) + p.M_phi * L.Tp;
+    double Rs0 = 0.0;
+    if (p.surf) {
+      const double q = 1.0 - ph * ph;
+      Rs0 = -p.M0 * L.l0s + p.M_psi * (-p.kBT * log(ps / (1.0 - ps)) + p.beta * q * q - 0.5 * p.W * ph * ph) + p.M_psi * L.Ts;
+    }
+    double vx = ux, vy = uy, dpx = 0, dpy = 0, dsx = 0, dsy = 0, Rtp = Rp0, Rts = Rs0;
+    if (a.have_hist) {
+      if (!p.adv_raw) {
+        vx = 0.5 * (ux + (double)hin[n]);
+        vy = 0.5 * (uy + (double)hin[N + n]);
+      }
+      const double vxh = hin[2 * N + n], vyh = hin[3 * N + n], ps0 = a.ref[N + n];
+      dpx = ph * vx - ph0 * vxh;
+      dpy = ph * vy - ph0 * vyh;
+      dsx = ps * vx - ps0 * vxh;
+      dsy = ps * vy - ps0 * vyh;
+      // R(n-1) in full: stored part plus its multiplier term
+      const double Rp_prev = (double)hin[4 * N + n] + p.M_phi * a.pend->lambda_phi * hprime(p, ph0);
+      const double Rs_prev = (double)hin[5 * N + n] + p.M_psi * a.pend->mubar_psi;
+      Rtp = 1.5 * Rp0 - 0.5 * Rp_prev;
+      Rts = 1.5 * Rs0 - 0.5 * Rs_prev;
+    }
+
+    // ---- lattice 1: MRT with the pressure-based equilibrium and A^1 forcing
+    {
+      C m[9], o[9];
+      m[0] = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+      moments_noncons(f, m);
+      const double uu = ux * ux + uy * uy, third = 1.0 / 3.0, av = ux * grx + uy * gry;
+      const C meq[9] = {C(0), (C)(rho * ux), (C)(rho * uy), (C)(pr + rho * ux * ux), (C)(rho * ux * uy), (C)(pr + rho * uy * uy),
+                        (C)(rho * uy * third), (C)(rho * ux * third), (C)((pr + rho * uu) * third)};
+      const C mv[9] = {(C)av, (C)Fx, (C)Fy, (C)(ux * grx + uy * gry * third), (C)((ux * gry + uy * grx) * third),
+                       (C)(uy * gry + ux * grx * third), (C)(Fy * third), (C)(Fx * third), (C)(av * third)};
+      const C s2 = p.s2_local ? (C)(1.0 / (3.0 * mud_of(p, ph) / rho + 0.5)) : (C)p.sf[2];
+      const C rt[9] = {(C)p.sf[0], (C)p.sf[1], (C)p.sf[1], s2, s2, s2, (C)p.sf[3], (C)p.sf[3], (C)p.sf[4]};
+#pragma unroll
+      for (int k = 0; k < 9; ++k) m[k] = m[k] - rt[k] * (m[k] - meq[k]) + (C(1) - C(0.5) * rt[k]) * mv[k];
+      moving_populations(m, o);
+      o[0] = m[0] - m[3] - m[5] + m[8];
+      const bool wb = !p.periodic_y && gy == 0 && p.bc_bottom != LBM_BC_FREESLIP;
+      const bool wt = !p.periodic_y && gy == p.ny - 1 && p.bc_top != LBM_BC_FREESLIP;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        C v = o[i];
+        if (wb && CY(i) < 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_bottom);
+        if (wt && CY(i) > 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_top);
+        Pout[(size_t)i * N + n] = (S)v;
+      }
+    }
+    {
+      C o[9];
+      collide_scalar<C>(g, (C)ph, (C)p.eta_phi, (C)vx, (C)vy, (C)dpx, (C)dpy, (C)Rtp, p.sg, o);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Pout[(size_t)(9 + i) * N + n] = (S)o[i];
+    }
+    if (p.surf) {
+      C o[9];
+      collide_scalar<C>(h, (C)ps, (C)p.eta_psi, (C)vx, (C)vy, (C)dsx, (C)dsy, (C)Rts, p.sh, o);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Pout[(size_t)(18 + i) * N + n] = (S)o[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Pout[(size_t)(18 + i) * N + n] = (S)C(0);
+    }
+    hout[n] = (C)ux;
+    hout[N + n] = (C)uy;
+    hout[2 * N + n] = (C)vx;
+    hout[3 * N + n] = (C)vy;
+    hout[4 * N + n] = (C)Rp0;
+    hout[5 * N + n] = (C)Rs0;
+  }
+
+  // ---- D: the last tile to finish forms lambda(n), mubar(n)
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(a.counter, 1u);
+    sLast = prev == (unsigned)(a.ntiles - 1);
+  }
+  __syncthreads();
+  if (sLast) {
+    __threadfence();
+    double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    for (int b = threadIdx.x; b < a.ntiles; b += kBlock) {
+      t1 += a.partials[3 * (size_t)b + 0];
+      t2 += a.partials[3 * (size_t)b + 1];
+      t3 += a.partials[3 * (size_t)b + 2];
+    }
+    t1 = block_reduce(t1, false);
+    t2 = block_reduce(t2, false);
+    t3 = block_reduce(t3, false);
+    if (threadIdx.x == 0) {
+      a.next->lambda_phi = t2 > 0.0 ? t1 / t2 : 0.0;
+      a.next->mubar_psi = t3 / (double)p.N;
+      a.next->cdef = a.have_hist ? 1.5 : 1.0;
+      atomicExch(a.counter, 0u);
+    }
+  }
 }
 
 // Initial fields (Sec. 2.2 equilibrium profile) into the FP64 staging buffer.
@@ -456,8 +686,15 @@ __global__ __launch_bounds__(kBlock) void k_init_fields(DevParams p, double* __r
 // g and h shifted by phi and psi, which go to the FP64 reference planes.
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_load(DevParams p, const double* __restrict__ F, int with_u, S* __restrict__ P,
-                                                 double* __restrict__ ref) {
+                                                 double* __restrict__ ref, DevScalars* __restrict__ pend,
+                                                 unsigned* __restrict__ counter) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n == 0) {
+    pend->lambda_phi = 0.0;
+    pend->mubar_psi = 0.0;
+    pend->cdef = 0.0;
+    *counter = 0u;
+  }
   if (n >= p.N) return;
   const size_t N = (size_t)p.N;
   const int x = n % p.nx, y = n / p.nx;
@@ -512,18 +749,22 @@ __global__ __launch_bounds__(kBlock) void k_fields(DevParams p, const S* __restr
   out[7 * N + n] = mu[N + n];
 }
 
-// Populations of the current state (rest populations of g, h un-shifted).
+// Populations of the current state: rest populations of g, h un-shifted and
+// the pending multiplier terms added.
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_pops(DevParams p, const S* __restrict__ P, const double* __restrict__ ref,
-                                                 double* __restrict__ out) {
+                                                 const DevScalars* __restrict__ pend, double* __restrict__ out) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= p.N) return;
   const size_t N = (size_t)p.N;
   const int x = n % p.nx, y = n / p.nx;
+  const double lam = pend->cdef * p.M_phi * pend->lambda_phi, mub = pend->cdef * p.M_psi * pend->mubar_psi;
   for (int lat = 0; lat < 3; ++lat)
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       double v = pull<S, double>(p, P, lat, i, x, y);
+      if (lat == 1) v += lam * WQ<double>(i) * hprime(p, ref[emitter(p, i, x, y)]);
+      if (lat == 2 && p.surf) v += mub * WQ<double>(i);
       if (i == 0 && lat > 0 && (lat == 1 || p.surf)) v += ref[(size_t)(lat - 1) * N + n];
       out[(size_t)(9 * lat + i) * N + n] = v;
     }
@@ -684,50 +925,65 @@ struct TimedScope {
   int k;
   hipStream_t st;
   TimedScope(StepTimer* t_, int k_, hipStream_t st_) : t(t_), k(k_), st(st_) {
-    if (t) (void)hipEventRecord(t->ev[(t->used * 4 + k) * 2 + 0], st);
+    if (t) (void)hipEventRecord(t->ev[(t->used * LBM_N_KERNELS + k) * 2 + 0], st);
   }
   ~TimedScope() {
-    if (t) (void)hipEventRecord(t->ev[(t->used * 4 + k) * 2 + 1], st);
+    if (t) (void)hipEventRecord(t->ev[(t->used * LBM_N_KERNELS + k) * 2 + 1], st);
   }
 };
 
+// Diagnostics of the current state: phi, psi (pending multiplier terms
+// applied), mu, and the multipliers of the current state in the diagnostic
+// scalar slot (the pending slot is left untouched).
 template <class S, class C>
-hipError_t macro_impl(const DevParams& p, DevState& s, hipStream_t st, StepTimer* t = nullptr) {
+hipError_t macro_impl(const DevParams& p, DevState& s, hipStream_t st) {
   double* pp = (double*)s.phipsi[s.hcur];
   const double* ref = (const double*)s.phipsi[s.hcur ^ 1];
   const int rb = red_blocks(p.N);
-  {
-    TimedScope ts(t, LBM_K_MOMENTS, st);
-    hipLaunchKernelGGL((k_moments<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur], ref, pp);
-  }
-  {
-    TimedScope ts(t, LBM_K_MU, st);
-    hipLaunchKernelGGL(k_mu_partials, dim3(rb), dim3(kBlock), 0, st, p, (const double*)pp, (double*)s.mu, s.partials);
-  }
-  {
-    TimedScope ts(t, LBM_K_MULTIPLIERS, st);
-    hipLaunchKernelGGL(k_multipliers, dim3(1), dim3(kBlock), 0, st, rb, p.N, (const double*)s.partials, s.scalars);
-  }
+  hipLaunchKernelGGL((k_moments<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur], ref,
+                     (const DevScalars*)(s.scalars + s.scur), pp);
+  hipLaunchKernelGGL(k_mu_partials, dim3(rb), dim3(kBlock), 0, st, p, (const double*)pp, (double*)s.mu, s.partials);
+  hipLaunchKernelGGL(k_multipliers, dim3(1), dim3(kBlock), 0, st, rb, p.N, (const double*)s.partials, s.scalars + 2);
   return hipGetLastError();
+}
+
+inline int tiles_x(const DevParams& p) { return (p.nx + kTileX - 1) / kTileX; }
+inline int tiles(const DevParams& p, int ty) { return tiles_x(p) * ((p.ny + ty - 1) / ty); }
+
+template <class S, class C, int TY>
+void launch_fused(const DevParams& p, DevState& s, int have_hist, hipStream_t st) {
+  StepArgs a;
+  a.Pin = s.pops[s.cur];
+  a.Pout = s.pops[s.cur ^ 1];
+  a.ref = (const double*)s.phipsi[s.hcur ^ 1];
+  a.out = (double*)s.phipsi[s.hcur];
+  a.hin = s.uhist[s.hcur ^ 1];
+  a.hout = s.uhist[s.hcur];
+  a.pend = s.scalars + s.scur;
+  a.next = s.scalars + (s.scur ^ 1);
+  a.partials = s.partials;
+  a.counter = s.counter;
+  a.have_hist = have_hist;
+  a.ntx = tiles_x(p);
+  a.ntiles = tiles(p, TY);
+  hipLaunchKernelGGL((k_step<S, C, TY>), dim3(a.ntiles), dim3(kBlock), 0, st, p, a);
 }
 
 template <class S, class C>
 hipError_t step_impl(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer) {
   StepTimer* t = (timer && timer->ev && timer->used < timer->max_steps) ? timer : nullptr;
-  hipError_t e = macro_impl<S, C>(p, s, st, t);
-  if (e != hipSuccess) return e;
-  const S* Pin = (const S*)s.pops[s.cur];
-  S* Pout = (S*)s.pops[s.cur ^ 1];
   {
-    TimedScope ts(t, LBM_K_COLLIDE, st);
-    hipLaunchKernelGGL((k_collide<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, Pin, Pout,
-                       (const double*)s.phipsi[s.hcur], (const double*)s.phipsi[s.hcur ^ 1], (const double*)s.mu,
-                       (const C*)s.uhist[s.hcur ^ 1], (C*)s.uhist[s.hcur], (const C*)s.Rhist[s.hcur ^ 1],
-                       (C*)s.Rhist[s.hcur], (const DevScalars*)s.scalars, have_hist);
+    TimedScope ts(t, LBM_K_STEP, st);
+    switch (s.tile_rows) {
+      case 4: launch_fused<S, C, 4>(p, s, have_hist, st); break;
+      case 8: launch_fused<S, C, 8>(p, s, have_hist, st); break;
+      default: launch_fused<S, C, 16>(p, s, have_hist, st); break;
+    }
   }
   if (t) t->used += 1;
   s.cur ^= 1;
   s.hcur ^= 1;
+  s.scur ^= 1;
   return hipGetLastError();
 }
 
@@ -758,20 +1014,29 @@ hipError_t fetch_impl(const DevParams& p, DevState& s, hipStream_t st) {
 template <class S>
 hipError_t load_impl(const DevParams& p, DevState& s, int with_u, hipStream_t st) {
   hipLaunchKernelGGL(k_load<S>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const double*)s.field_buf, with_u,
-                     (S*)s.pops[s.cur], (double*)s.phipsi[s.hcur ^ 1]);
+                     (S*)s.pops[s.cur], (double*)s.phipsi[s.hcur ^ 1], s.scalars + s.scur, s.counter);
   return hipGetLastError();
 }
 
 template <class S>
 hipError_t pops_impl(const DevParams& p, DevState& s, hipStream_t st) {
   hipLaunchKernelGGL(k_pops<S>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur],
-                     (const double*)s.phipsi[s.hcur ^ 1], s.field_buf);
+                     (const double*)s.phipsi[s.hcur ^ 1], (const DevScalars*)(s.scalars + s.scur), s.field_buf);
   return hipGetLastError();
 }
 
 }  // namespace
 
 size_t storage_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2); }
+size_t fused_tiles(int nx, int ny, int tile_rows) {
+  return (size_t)((nx + kTileX - 1) / kTileX) * (size_t)((ny + tile_rows - 1) / tile_rows);
+}
+// Tallest tile (less halo work per node) that still gives >= 8 workgroups per CU.
+int fused_tile_rows(int nx, int ny) {
+  if (fused_tiles(nx, ny, 16) >= 2048) return 16;
+  if (fused_tiles(nx, ny, 8) >= 2048) return 8;
+  return 4;
+}
 size_t compute_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 
 #define LBM_DISPATCH(prec, call64, call32)            \

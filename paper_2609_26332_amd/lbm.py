@@ -35,7 +35,7 @@ EXPORTS = ["lbm_required_bytes", "lbm_init", "lbm_step", "lbm_reduce_invariants"
            "lbm_load_fields", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_derived",
            "lbm_fetch_populations", "lbm_destroy", "lbm_last_error", "lbm_timing_begin", "lbm_timing_end",
            "lbm_bytes_per_node_step"]
-KERNEL_NAMES = ["k_moments", "k_mu_partials", "k_multipliers", "k_collide"]
+KERNEL_NAMES = ["k_step"]
 
 
 class LbmError(RuntimeError):
@@ -234,10 +234,11 @@ class Sim:
         _check(lib().lbm_timing_begin(self._h, int(max_steps)), self._h)
 
     def timing_end(self) -> dict:
-        ms = (ctypes.c_double * 4)()
-        n = (ctypes.c_int64 * 4)()
+        k = len(KERNEL_NAMES)
+        ms = (ctypes.c_double * k)()
+        n = (ctypes.c_int64 * k)()
         _check(lib().lbm_timing_end(self._h, ms, n), self._h)
-        return {KERNEL_NAMES[k]: (ms[k], n[k]) for k in range(4)}
+        return {KERNEL_NAMES[j]: (ms[j], n[j]) for j in range(k)}
 
     def bytes_per_node_step(self) -> float:
         b = ctypes.c_double()
