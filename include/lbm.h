@@ -84,7 +84,9 @@ typedef struct {
   int32_t adv_raw;          /* 0 (default): phi and psi are advected by the mean (u(n) + u(n-1))/2 of the
                                velocity of this and the previous step; 1: by u(n) itself (literal
                                reading, excites the D2Q9 staggered-momentum mode on long runs) */
-  int32_t reserved;         /* must be 0 */
+  int32_t tile_rows;        /* height of the 64-wide tiles of the fused step kernel: 0 chooses from the grid
+                               size, 4, 8 or 16 force it (a tuning knob: results differ only in the
+                               summation order of the global multiplier sums) */
   double sigma_gl0, eps;    /* clean gas-liquid tension, thickness: kappa = 3 eps sigma/8, beta = 3 sigma/(4 eps) */
   double M_phi, M_psi;      /* mobilities (>= 0) */
   double lambda_s;          /* psi gradient coefficient; < 0 derive: kappa/2 with a wetting wall, else 0 */
@@ -181,12 +183,13 @@ int lbm_fetch_populations(lbm_handle* h, double* host, size_t n_doubles);
 
 /* Kernel timing with HIP events on the handle's stream.  lbm_timing_begin
  * creates event pairs for up to max_steps steps; every following lbm_step
- * brackets each of its kernels (LBM_K_* below; one fused kernel per step) with
- * an event pair until the pairs run out.  lbm_timing_end synchronises the
+ * brackets each of its kernels (LBM_K_* below: the fused step kernel and the
+ * one-block reduction that forms the multipliers) with an event pair until the
+ * pairs run out.  lbm_timing_end synchronises the
  * stream and writes, per kernel kind, the summed duration in ms
  * (ms[LBM_N_KERNELS]) and the number of launches timed
  * (launches[LBM_N_KERNELS]); it releases the events. */
-enum { LBM_K_STEP = 0, LBM_N_KERNELS = 1 };
+enum { LBM_K_STEP = 0, LBM_K_FINISH = 1, LBM_N_KERNELS = 2 };
 int lbm_timing_begin(lbm_handle* h, int64_t max_steps);
 int lbm_timing_end(lbm_handle* h, double* ms, int64_t* launches);
 

@@ -36,7 +36,7 @@ uint64_t hash_bytes(const void* data, size_t n) {  // FNV-1a
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t pops, phipsi, mu, uhist, partials, inv_partials, inv_out, contact, scalars, counter, field_buf, total;
+  size_t pops, phipsi, mu, uhist, partials, inv_partials, inv_out, contact, scalars, field_buf, total;
 };
 
 Layout make_layout(const lbm_params& p) {
@@ -55,7 +55,6 @@ Layout make_layout(const lbm_params& p) {
   L.inv_out = take(lbm::kInvOut * sizeof(double));
   L.contact = take(3 * (size_t)p.nx * sizeof(double));
   L.scalars = take(3 * sizeof(lbm::DevScalars));
-  L.counter = take(sizeof(unsigned));
   L.field_buf = take(27 * N * sizeof(double));
   L.total = off;
   return L;
@@ -75,7 +74,8 @@ std::string derive(const lbm_params& p, lbm::DevParams& d, double* derived) {
   if (p.precision != LBM_FP64 && p.precision != LBM_FP32 && p.precision != LBM_FP16_SHIFTED) return "unknown precision";
   if (p.constraint_phi != LBM_CONSTRAINT_NONLINEAR && p.constraint_phi != LBM_CONSTRAINT_LINEAR) return "unknown constraint";
   if (p.init_kind < LBM_INIT_DROP || p.init_kind > LBM_INIT_BUBBLE) return "unknown init kind";
-  if ((p.adv_raw != 0 && p.adv_raw != 1) || p.reserved != 0) return "adv_raw must be 0 or 1 and reserved 0";
+  if (p.adv_raw != 0 && p.adv_raw != 1) return "adv_raw must be 0 or 1";
+  if (p.tile_rows != 0 && p.tile_rows != 4 && p.tile_rows != 8 && p.tile_rows != 16) return "tile_rows must be 0, 4, 8 or 16";
   if (!(p.sigma_gl0 > 0.0) || !(p.eps > 0.0)) return "sigma_gl0 and eps must be > 0";
   if (!(p.M_phi >= 0.0) || !(p.M_psi >= 0.0)) return "mobilities must be >= 0";
   if (!(p.psi_b >= 0.0 && p.psi_b < 1.0)) return "psi_b must lie in [0,1)";
@@ -195,9 +195,8 @@ void carve(lbm_handle* h) {
   s.inv_out = (double*)(b + L.inv_out);
   s.contact = (double*)(b + L.contact);
   s.scalars = (lbm::DevScalars*)(b + L.scalars);
-  s.counter = (unsigned*)(b + L.counter);
   s.scur = 0;
-  s.tile_rows = lbm::fused_tile_rows(h->dp.nx, h->dp.ny);
+  s.tile_rows = h->prm.tile_rows ? h->prm.tile_rows : lbm::fused_tile_rows(h->dp.nx, h->dp.ny, h->prm.precision);
   s.field_buf = (double*)(b + L.field_buf);
   s.cur = 0;
   s.hcur = 0;

@@ -58,7 +58,6 @@ struct DevState {
   double* inv_out;         // final invariants [kInvOut]
   double* contact;         // [nx] column heights + 2 x [nx] edge fractions (rows 0 and 1)
   DevScalars* scalars;     // [3]: pending multipliers (ping-pong by scur) and the diagnostic slot [2]
-  unsigned* counter;       // last-block-done counter of the fused step
   double* field_buf;       // FP64 staging for fetch/load, [27][N]
   int scur;                // scalars[scur] holds the multipliers pending on the stored populations
   int tile_rows;           // tile height of the fused step (4, 8 or 16); width is 64
@@ -72,7 +71,7 @@ constexpr int kTileX = 64;
 constexpr int kMaxTiles = 1 << 22;   // partials of the fused step: [kMaxTiles][3] at most (grid <= 2^28 nodes at 64x16)
 
 size_t storage_bytes(int precision);
-int fused_tile_rows(int nx, int ny);  // tile height of the fused step for a grid
+int fused_tile_rows(int nx, int ny, int precision);  // tile height of the fused step for a grid
 size_t fused_tiles(int nx, int ny, int tile_rows);
 size_t compute_bytes(int precision);
 

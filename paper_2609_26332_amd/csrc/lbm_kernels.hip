@@ -17,18 +17,23 @@
 // sources, reductions) runs in FP64; the three MRT collisions run in the
 // compute type C of the storage precision (FP64 or FP32).
 //
-// One step (Sec. 3 of the paper, readings in the design notes):
-//   k_moments      phi = sum g_i, psi = sum h_i                     (macroscopic recovery)
-//   k_mu_partials  mu_phi, mu_psi with the wall terms; per-block FP64 sums of
-//                  h'(phi) mu_phi, h'(phi)^2, mu_psi                (eq_muphi, eq_mupsi, eq15)
-//   k_multipliers  lambda_phi = S1/S2, mubar_psi = S3/N             (eq15, AC_psi)
-//   k_step         fused step on 64 x TY tiles (see its comment): phi, psi,
-//                  chemical potentials, multiplier sums, force, velocity, pressure,
-//                  sources, MRT collision of f, g, h,
-//                  wall corrections; writes post-collision populations
-//                  and the history for the backward differences
-// No MFMA: the step moves ~300 B/node in FP32 storage and does ~2 kflop/node,
-// below the FP32 ridge of the chip, so HBM bandwidth bounds it.
+// One step (Sec. 3 of the paper) is two launches:
+//   k_step         fused step on 64 x TY tiles (see its comment): phi, psi
+//                  (macroscopic recovery), chemical potentials with the wall
+//                  terms (eq_muphi, eq_mupsi), per-tile FP64 sums of
+//                  h'(phi) mu_phi, h'(phi)^2, mu_psi (eq15), force, velocity,
+//                  pressure, sources, MRT collision of f, g, h, wall
+//                  corrections; writes post-collision populations and the
+//                  history for the backward differences
+//   k_step_finish  lambda_phi = S1/S2, mubar_psi = S3/N            (eq15, AC_psi)
+// The multiplier terms of a step's sources are applied by the next step (or by
+// the diagnostic kernels below), so one pass over the grid suffices.
+// Diagnostics (fields, invariants) recompute the macroscopic state with
+//   k_moments      phi = sum g_i, psi = sum h_i plus the pending terms
+//   k_mu_partials  mu_phi, mu_psi and the multiplier sums
+//   k_multipliers  lambda_phi, mubar_psi of the current state
+// No MFMA: the step moves ~300 B/node in FP32 storage and does ~1.3k VALU
+// operations per node, no dense contraction; HBM bandwidth bounds it.
 
 #include "lbm_internal.h"
 #include "../../include/lbm.h"
@@ -362,118 +367,186 @@ struct StepArgs {
   const DevScalars* pend;   // multipliers pending on Pin (from step n-1)
   DevScalars* next;         // multipliers of step n, written by the last tile
   double* partials;         // [ntiles][3]
-  unsigned* counter;
   int have_hist, ntx, ntiles;
 };
 
-// One fused time step on a 64 x TY tile of nodes (256 threads):
+// lambda(n) = S1/S2, mubar(n) = S3/N from the per-tile partial sums of
+// k_step (eq15 and the psi constraint), in a fixed order: bitwise
+// reproducible.  A separate launch rather than a last-tile-done reduction
+// inside k_step: the agent-scope release fence that pattern needs on every
+// tile writes back the XCD's L2 and cost more than the whole step.
+__global__ __launch_bounds__(kBlock) void k_step_finish(const double* __restrict__ partials, int ntiles, int N,
+                                                        int have_hist, DevScalars* __restrict__ next) {
+  double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll 4
+  for (int b = threadIdx.x; b < ntiles; b += kBlock) {
+    t1 += partials[3 * (size_t)b + 0];
+    t2 += partials[3 * (size_t)b + 1];
+    t3 += partials[3 * (size_t)b + 2];
+  }
+  t1 = block_reduce(t1, false);
+  t2 = block_reduce(t2, false);
+  t3 = block_reduce(t3, false);
+  if (threadIdx.x == 0) {
+    next->lambda_phi = t2 > 0.0 ? t1 / t2 : 0.0;
+    next->mubar_psi = t3 / (double)N;
+    next->cdef = have_hist ? 1.5 : 1.0;
+  }
+}
+
+// Gather of population i of lattice lat at column x0 of row y, for a wave
+// whose lanes usually share y: the plane and row then form a wave-uniform
+// base pointer and only the column (xm = x0 - 1, xp = x0 + 1, wrapped) is
+// per lane, so each load is one scalar-base + 32-bit-offset access.  Wall
+// sources as in pull().
+template <class S, class C, bool WALLS>
+__device__ __forceinline__ C pull_row(const DevParams& p, const S* __restrict__ P, size_t N, int lat, int i, int y,
+                                      unsigned xm, unsigned x0, unsigned xp) {
+  const unsigned sx = CX(i) > 0 ? xm : (CX(i) < 0 ? xp : x0);
+  int sy = y - CY(i);
+  if (!WALLS) {
+    sy = sy < 0 ? sy + p.ny : (sy >= p.ny ? sy - p.ny : sy);
+  } else if (sy < 0 || sy >= p.ny) {
+    const int bc = sy < 0 ? p.bc_bottom : p.bc_top;
+    if (lat == 0 && bc == LBM_BC_FREESLIP) return (C)(P + (size_t)MIRY(i) * N + (size_t)y * p.nx)[sx];
+    return (C)(P + (size_t)(9 * lat + OPP(i)) * N + (size_t)y * p.nx)[x0];
+  }
+  return (C)(P + (size_t)(9 * lat + i) * N + (size_t)sy * p.nx)[sx];
+}
+
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// A wave-uniform value the optimiser cannot see through: what is derived from
+// it inside a loop stays in the loop instead of being hoisted into registers.
+template <class T> __device__ __forceinline__ T opaque(T v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+template <class T> __device__ __forceinline__ T opaque_v(T v) {   // the same for a value held in VGPRs
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// One fused time step on a 64 x TY tile of nodes (256 threads = 4 waves; a
+// wave works on whole rows, so row-dependent choices, walls included, are
+// wave-uniform):
+//  A0 h'(phi(n-1)) on the tile and a halo of 3 (ghost rows: nearest fluid row)
 //  A  phi(n), psi(n) on the tile and a halo of 2 from the gathered g, h, the
-//     FP64 reference planes and the pending multiplier term (halo of 3 of
-//     phi(n-1) in LDS); the tile's values go to the output planes
+//     FP64 reference planes and the pending multiplier term; the tile's
+//     values go to the output planes
 //  B  mu_phi, mu_psi on the tile and a halo of 1 (wall terms from the
 //     first fluid row); FP64 block sums of h' mu_phi, h'^2, mu_psi
 //  C  force, velocity, pressure, sources, collision of the tile nodes; the
 //     multiplier terms of this step's sources are left out of the stored
 //     populations and of the stored source history (deferred to step n+1)
-//  D  the last tile to finish reduces the block sums to lambda(n), mubar(n)
-template <class S, class C, int TY>
+// k_step_finish then reduces the block sums to lambda(n), mubar(n).
+template <class S, class C, int TY, bool WALLS>
 __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
   constexpr int W3 = kTileX + 6, H3 = TY + 6, W2 = kTileX + 4, H2 = TY + 4, W1 = kTileX + 2, H1 = TY + 2;
-  __shared__ double sP3[H3][W3];                  // phi(n-1), halo 3
-  __shared__ double sPhi[H2][W2], sPsi[H2][W2];   // phi(n), psi(n), halo 2 (ghost rows mirrored)
-  __shared__ double sMp[H1][W1], sMs[H1][W1];     // mu_phi, mu_psi, halo 1 (ghost rows mirrored)
-  __shared__ int sLast;
+  constexpr int NW = kBlock / 64;
+  __shared__ C sHp[H3][W3];          // h'(phi(n-1)), halo 3
+  __shared__ double2 sPP[H2][W2];    // (phi, psi)(n), halo 2 (ghost rows mirrored)
+  __shared__ double2 sMU[H1][W1];    // (mu_phi, mu_psi), halo 1 (ghost rows mirrored)
 
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int X0 = (tile % a.ntx) * kTileX, Y0 = (tile / a.ntx) * TY;
   const size_t N = (size_t)p.N;
-  const S* Pin = (const S*)a.Pin;
-  S* Pout = (S*)a.Pout;
-  const double lam1 = a.pend->cdef * p.M_phi * a.pend->lambda_phi;   // pending term weights
-  const double mub1 = a.pend->cdef * p.M_psi * a.pend->mubar_psi;
-  auto fluid_row = [&](int gy) { return p.periodic_y || (gy >= 0 && gy < p.ny); };
-  auto row_of = [&](int gy) { return p.periodic_y ? modp(gy, p.ny) : (gy < 0 ? 0 : (gy >= p.ny ? p.ny - 1 : gy)); };
+  const S* __restrict__ Pin = (const S*)a.Pin;
+  S* __restrict__ Pout = (S*)a.Pout;
+  const double* __restrict__ ref = a.ref;
+  const double lam1_ = a.pend->cdef * p.M_phi * a.pend->lambda_phi;   // pending term weights
+  const double mub1_ = a.pend->cdef * p.M_psi * a.pend->mubar_psi;
+  const int lane = threadIdx.x & 63;
+  const int wave = wave_uniform(threadIdx.x >> 6);
+  auto fluid_row = [&](int gy) { return !WALLS || (gy >= 0 && gy < p.ny); };
+  auto row_of = [&](int gy) { return WALLS ? (gy < 0 ? 0 : (gy >= p.ny ? p.ny - 1 : gy)) : modp(gy, p.ny); };
+  auto colm = [&](unsigned x) { return x == 0 ? (unsigned)p.nx - 1 : x - 1; };
+  auto colp = [&](unsigned x) { return x + 1 == (unsigned)p.nx ? 0u : x + 1; };
 
-  // ---- A0: phi(n-1) on the halo-3 region (ghost rows: nearest fluid row)
-  for (int k = threadIdx.x; k < H3 * W3; k += kBlock) {
-    const int ly = k / W3, lx = k - ly * W3;
-    sP3[ly][lx] = a.ref[(size_t)row_of(Y0 - 3 + ly) * p.nx + modp(X0 - 3 + lx, p.nx)];
+  // ---- A0 (unrolled: all of a thread's loads are in flight together)
+#pragma unroll
+  for (int r = 0; r < (H3 * W3 + kBlock - 1) / kBlock; ++r) {
+    const int k = threadIdx.x + r * kBlock;
+    if (k < H3 * W3) {
+      const int ly = k / W3, lx = k - ly * W3;
+      sHp[ly][lx] = (C)hprime(p, ref[(size_t)row_of(Y0 - 3 + ly) * p.nx + modp(X0 - 3 + lx, p.nx)]);
+    }
   }
   __syncthreads();
 
-  // ---- A: phi(n), psi(n) on the halo-2 region
-#pragma unroll 1
-  for (int k = threadIdx.x; k < H2 * W2; k += kBlock) {
-    const int ly = k / W2, lx = k - ly * W2;
-    const int gy = Y0 - 2 + ly;
-    if (!fluid_row(gy)) continue;
-    const int x = modp(X0 - 2 + lx, p.nx), y = row_of(gy);
-    C sg = C(0), sh = C(0);
-    double corr = 0.0;
+  // ---- A: node (lx, ly) of the halo-2 frame at fluid row y, column x
+  auto node_A = [&](int lx, int ly, int y, unsigned x) {
+    const unsigned xm = colm(x), xp = colp(x);
+    C sg = C(0), sh = C(0), corr = C(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      sg += pull<S, C>(p, Pin, 1, i, x, y);
+      sg += pull_row<S, C, WALLS>(p, Pin, N, 1, i, y, xm, x, xp);
       // emitter of g_i in LDS coordinates: x - c_i, or the node itself at a wall
-      const int sy = gy - CY(i);
-      const bool bb = !p.periodic_y && (sy < 0 || sy >= p.ny);
-      corr += WQ<double>(i) * hprime(p, bb ? sP3[ly + 1][lx + 1] : sP3[ly + 1 - CY(i)][lx + 1 - CX(i)]);
+      const int sy = y - CY(i);
+      const bool bb = WALLS && (sy < 0 || sy >= p.ny);
+      corr += WQ<C>(i) * (bb ? sHp[ly + 1][lx + 1] : sHp[ly + 1 - CY(i)][lx + 1 - CX(i)]);
     }
     const size_t node = (size_t)y * p.nx + x;
-    const double ph = sP3[ly + 1][lx + 1] + (double)sg + lam1 * corr;
+    const double ph = ref[node] + (double)sg + lam1_ * (double)corr;
     double ps = 0.0;
     if (p.surf) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) sh += pull<S, C>(p, Pin, 2, i, x, y);
-      ps = a.ref[N + node] + (double)sh + mub1;
+      for (int i = 0; i < 9; ++i) sh += pull_row<S, C, WALLS>(p, Pin, N, 2, i, y, xm, x, xp);
+      ps = ref[N + node] + (double)sh + mub1_;
     }
-    sPhi[ly][lx] = ph;
-    sPsi[ly][lx] = ps;
+    sPP[ly][lx] = make_double2(ph, ps);
     const int tx = lx - 2, ty = ly - 2;
     if (tx >= 0 && tx < kTileX && ty >= 0 && ty < TY && X0 + tx < p.nx && Y0 + ty < p.ny) {
       a.out[node] = ph;
       a.out[N + node] = ps;
     }
+  };
+  // columns X0-2 .. X0+61 as whole rows (one wave per row) ...
+  static_assert(H2 % NW == 0 && TY % NW == 0, "rows per wave");
+#pragma unroll
+  for (int r = 0; r < H2 / NW; ++r) {
+    const int ly = wave + r * NW, gy = Y0 - 2 + ly;
+    if (fluid_row(gy)) node_A(lane, ly, wave_uniform(row_of(gy)), (unsigned)modp(X0 - 2 + lane, p.nx));
+  }
+  // ... and the last four columns, X0+62 .. X0+65, four nodes per row
+#pragma unroll 1
+  for (int k = threadIdx.x; k < 4 * H2; k += kBlock) {
+    const int ly = k >> 2, lx = kTileX + (k & 3), gy = Y0 - 2 + ly;
+    if (fluid_row(gy)) node_A(lx, ly, row_of(gy), (unsigned)modp(X0 - 2 + lx, p.nx));
   }
   __syncthreads();
-  if (!p.periodic_y) {  // ghost rows take the nearest fluid row of the same column
+  if (WALLS) {  // ghost rows take the nearest fluid row of the same column
     for (int k = threadIdx.x; k < H2 * W2; k += kBlock) {
       const int ly = k / W2, lx = k - ly * W2;
       const int gy = Y0 - 2 + ly;
       if (fluid_row(gy)) continue;
-      const int src = row_of(gy) - (Y0 - 2);
-      sPhi[ly][lx] = sPhi[src][lx];
-      sPsi[ly][lx] = sPsi[src][lx];
+      sPP[ly][lx] = sPP[row_of(gy) - (Y0 - 2)][lx];
     }
     __syncthreads();
   }
 
-  // ---- B: chemical potentials on the halo-1 region, block sums on the tile
+  // ---- B: node (lx, ly) of the halo-1 frame at fluid row gy
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll 1
-  for (int k = threadIdx.x; k < H1 * W1; k += kBlock) {
-    const int ly = k / W1, lx = k - ly * W1;
-    const int gy = Y0 - 1 + ly;
-    if (!fluid_row(gy)) continue;
-    const int cy = ly + 1, cx = lx + 1;   // in sPhi
-    const double ph = sPhi[cy][cx], ps = sPsi[cy][cx];
+  auto node_B = [&](int lx, int ly, int gy) {
+    const int cy = ly + 1, cx = lx + 1;   // in sPP
+    const double2 c = sPP[cy][cx];
+    const double ph = c.x, ps = c.y;
     Lap L{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const double w2 = 6.0 * WQ<double>(i);
-      const double pn = sPhi[cy + CY(i)][cx + CX(i)], sn = sPsi[cy + CY(i)][cx + CX(i)];
-      L.l0p += w2 * (pn - ph);
-      L.l0s += w2 * (sn - ps);
+      const double2 nb = sPP[cy + CY(i)][cx + CX(i)];
+      L.l0p += w2 * (nb.x - ph);
+      L.l0s += w2 * (nb.y - ps);
       const int ny_ = gy + CY(i);
-      if (!p.periodic_y && (ny_ < 0 || ny_ >= p.ny) && wet_side(p, ny_ < 0 ? -1 : 1)) {
+      if (WALLS && (ny_ < 0 || ny_ >= p.ny) && wet_side(p, ny_ < 0 ? -1 : 1)) {
         // fluid node next to the ghost: same row, column x + c_x
-        const double pf = sPhi[cy][cx + CX(i)], sf = sPsi[cy][cx + CX(i)];
-        L.Tp += w2 * Jphi(p, pf, sf);
-        if (p.surf) L.Ts += w2 * Jpsi(p, pf, sf);
+        const double2 f = sPP[cy][cx + CX(i)];
+        L.Tp += w2 * Jphi(p, f.x, f.y);
+        if (p.surf) L.Ts += w2 * Jpsi(p, f.x, f.y);
       }
     }
     const double mp = mu_phi_of(p, ph, ps, L), ms = mu_psi_of(p, ph, ps, L);
-    sMp[ly][lx] = mp;
-    sMs[ly][lx] = ms;
+    sMU[ly][lx] = make_double2(mp, ms);
     const int tx = lx - 1, ty = ly - 1;
     if (tx >= 0 && tx < kTileX && ty >= 0 && ty < TY && X0 + tx < p.nx && Y0 + ty < p.ny) {
       const double hp = hprime(p, ph);
@@ -481,6 +554,16 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
       s2 += hp * hp;
       s3 += ms;
     }
+  };
+#pragma unroll 1
+  for (int ly = wave; ly < H1; ly += NW) {
+    const int gy = Y0 - 1 + ly;
+    if (fluid_row(gy)) node_B(lane, ly, wave_uniform(gy));
+  }
+#pragma unroll 1
+  for (int k = threadIdx.x; k < 2 * H1; k += kBlock) {
+    const int ly = k >> 1, lx = kTileX + (k & 1), gy = Y0 - 1 + ly;
+    if (fluid_row(gy)) node_B(lx, ly, gy);
   }
   s1 = block_reduce(s1, false);
   s2 = block_reduce(s2, false);
@@ -490,69 +573,77 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
     a.partials[3 * (size_t)tile + 1] = s2;
     a.partials[3 * (size_t)tile + 2] = s3;
   }
-  if (!p.periodic_y) {
+  if (WALLS) {
     for (int k = threadIdx.x; k < H1 * W1; k += kBlock) {
       const int ly = k / W1, lx = k - ly * W1;
       const int gy = Y0 - 1 + ly;
       if (fluid_row(gy)) continue;
-      const int src = row_of(gy) - (Y0 - 1);
-      sMp[ly][lx] = sMp[src][lx];
-      sMs[ly][lx] = sMs[src][lx];
+      sMU[ly][lx] = sMU[row_of(gy) - (Y0 - 1)][lx];
     }
   }
   __syncthreads();
 
-  // ---- C: collide the tile nodes
-  const int tx = threadIdx.x % kTileX;
-  const C* hin = (const C*)a.hin;
-  C* hout = (C*)a.hout;
-#pragma unroll 1
-  for (int ty = threadIdx.x / kTileX; ty < TY; ty += kBlock / kTileX) {
-    const int gx = X0 + tx, gy = Y0 + ty;
-    if (gx >= p.nx || gy >= p.ny) continue;
-    const int n = gy * p.nx + gx;
-    const int cy = ty + 2, cx = tx + 2;   // in sPhi
-    const double ph = sPhi[cy][cx], ps = sPsi[cy][cx];
-    const double ph0 = sP3[ty + 3][tx + 3];  // phi(n-1)
+  // ---- C: collide the tile nodes, one row per wave
+  const C* __restrict__ hin = (const C*)a.hin;
+  C* __restrict__ hout = (C*)a.hout;
+  const int tx = lane;
+  const unsigned x0 = (unsigned)min(X0 + tx, p.nx - 1);   // lanes past a ragged edge compute a copy, store nothing
+  const unsigned xm = colm(x0), xp = colp(x0);
+  const bool active = X0 + tx < p.nx;
+  // rho is affine in phi: grad rho = (d rho / d phi) grad phi (ghost values included)
+  const double drho = (p.rho_l - p.rho_g) * 0.5 * p.inv_phib;
+#pragma unroll 2
+  for (int r = 0; r < TY / NW; ++r) {
+    const int ty = wave + r * NW;
+    const int gy = wave_uniform(Y0 + ty);
+    if (gy >= p.ny) break;
+    const size_t row = (size_t)gy * p.nx;
+    // An opaque copy of N per row keeps the compiler from hoisting the 27 plane
+    // offsets (and everything derived from them) out of the row loop into registers.
+    const size_t N = opaque((size_t)p.N);
+    const double lam1 = opaque_v(lam1_), mub1 = opaque_v(mub1_);
+    double rf[5], rg[5], rh[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      rf[k] = opaque(p.sf[k]);
+      rg[k] = opaque(p.sg[k]);
+      rh[k] = opaque(p.sh[k]);
+    }
+    const int cy = ty + 2, cx = tx + 2;   // in sPP
+    const double2 c = sPP[cy][cx];
+    const double ph = c.x, ps = c.y;
+    const double2 mc = sMU[ty + 1][tx + 1];
+    const double ph0 = ref[row + x0];   // phi(n-1)
 
     C f[9], g[9], h[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      f[i] = pull<S, C>(p, Pin, 0, i, gx, gy);
+      f[i] = pull_row<S, C, WALLS>(p, Pin, N, 0, i, gy, xm, x0, xp);
       if (i == 0) { g[0] = C(0); h[0] = C(0); continue; }
       const int sy = gy - CY(i);
-      const bool bb = !p.periodic_y && (sy < 0 || sy >= p.ny);
-      const double hpe = hprime(p, bb ? ph0 : sP3[ty + 3 - CY(i)][tx + 3 - CX(i)]);
-      g[i] = pull<S, C>(p, Pin, 1, i, gx, gy) + (C)(lam1 * WQ<double>(i) * hpe);
-      h[i] = p.surf ? pull<S, C>(p, Pin, 2, i, gx, gy) + (C)(mub1 * WQ<double>(i)) : C(0);
+      const bool bb = WALLS && (sy < 0 || sy >= p.ny);
+      const C hpe = bb ? sHp[ty + 3][tx + 3] : sHp[ty + 3 - CY(i)][tx + 3 - CX(i)];
+      g[i] = pull_row<S, C, WALLS>(p, Pin, N, 1, i, gy, xm, x0, xp) + (C)(lam1 * WQ<double>(i) * (double)hpe);
+      h[i] = p.surf ? pull_row<S, C, WALLS>(p, Pin, N, 2, i, gy, xm, x0, xp) + (C)(mub1 * WQ<double>(i)) : C(0);
     }
-    // gradients of rho (wetting ghosts), mu_phi, mu_psi; local Laplacian pieces
-    double grx = 0, gry = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0;
-    Lap L{0.0, 0.0, 0.0, 0.0};
+    // gradients of phi (wetting ghosts), mu_phi, mu_psi; Laplacians of phi, psi
+    double gfx = 0, gfy = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0, l0p = 0, l0s = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const double w3 = 3.0 * WQ<double>(i), w2 = 2.0 * w3;
-      const double pn = sPhi[cy + CY(i)][cx + CX(i)], sn = sPsi[cy + CY(i)][cx + CX(i)];
+      const double2 nb = sPP[cy + CY(i)][cx + CX(i)];
       const int ny_ = gy + CY(i);
-      const bool ghost = !p.periodic_y && (ny_ < 0 || ny_ >= p.ny);
-      double rn;
-      if (ghost && wet_side(p, ny_ < 0 ? -1 : 1)) {
-        const double Jp = Jphi(p, pn, sn);
-        rn = rho_of(p, pn + Jp / p.kappa);
-        L.Tp += w2 * Jp;
-        if (p.surf) L.Ts += w2 * Jpsi(p, pn, sn);
-      } else {
-        rn = rho_of(p, pn);
-      }
-      L.l0s += w2 * (sn - ps);
-      grx += w3 * CX(i) * rn;
-      gry += w3 * CY(i) * rn;
-      const double mpn = sMp[ty + 1 + CY(i)][tx + 1 + CX(i)], msn = sMs[ty + 1 + CY(i)][tx + 1 + CX(i)];
-      gpx += w3 * CX(i) * mpn;
-      gpy += w3 * CY(i) * mpn;
-      gsx += w3 * CX(i) * msn;
-      gsy += w3 * CY(i) * msn;
+      double q = nb.x;
+      if (WALLS && (ny_ < 0 || ny_ >= p.ny) && wet_side(p, ny_ < 0 ? -1 : 1)) q += Jphi(p, nb.x, nb.y) / p.kappa;
+      l0p += w2 * (nb.x - ph);
+      l0s += w2 * (nb.y - ps);
+      if (CX(i)) gfx += (CX(i) * w3) * q;
+      if (CY(i)) gfy += (CY(i) * w3) * q;
+      const double2 mn = sMU[ty + 1 + CY(i)][tx + 1 + CX(i)];
+      if (CX(i)) { gpx += (CX(i) * w3) * mn.x; gsx += (CX(i) * w3) * mn.y; }
+      if (CY(i)) { gpy += (CY(i) * w3) * mn.x; gsy += (CY(i) * w3) * mn.y; }
     }
+    const double grx = drho * gfx, gry = drho * gfy;
     const double rho = rho_of(p, ph);
     const double Fx = -ph * gpx - ps * gsx + rho * p.gx, Fy = -ph * gpy - ps * gsy + rho * p.gy;
     const double ux = ((double)(f[1] - f[3] + f[5] - f[6] - f[7] + f[8]) + 0.5 * Fx) / rho;
@@ -560,27 +651,27 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
     const double snz = (double)(f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]);
     const double pr = 0.6 * (snz + 0.5 * (ux * grx + uy * gry) - rho * (2.0 / 3.0) * (ux * ux + uy * uy));
 
-    // sources without this step's multiplier terms (those are deferred)
-    const double Rp0 = p.M_phi * (-4.0 * p.beta * (1.0 - ps) * (ph * ph * ph - ph) - p.W * ps * ph) + p.M_phi * L.Tp;
-    double Rs0 = 0.0;
-    if (p.surf) {
-      const double q = 1.0 - ph * ph;
-      Rs0 = -p.M0 * L.l0s + p.M_psi * (-p.kBT * log(ps / (1.0 - ps)) + p.beta * q * q - 0.5 * p.W * ph * ph) + p.M_psi * L.Ts;
-    }
+    // Sources without this step's multiplier terms (those are deferred).  With
+    // the chemical potentials of phase B: R_phi = -M_phi (mu_phi + kappa L0(phi))
+    // and R_psi = -M_psi mu_psi - (M0 + M_psi lambda_s) L0(psi), identical to the
+    // bulk terms plus the wall terms of eq_muphi / eq_mupsi.
+    const double Rp0 = -p.M_phi * (mc.x + p.kappa * l0p);
+    const double Rs0 = p.surf ? -p.M_psi * mc.y - (p.M0 + p.M_psi * p.lambda_s) * l0s : 0.0;
     double vx = ux, vy = uy, dpx = 0, dpy = 0, dsx = 0, dsy = 0, Rtp = Rp0, Rts = Rs0;
     if (a.have_hist) {
+      const C* hr = hin + row;
       if (!p.adv_raw) {
-        vx = 0.5 * (ux + (double)hin[n]);
-        vy = 0.5 * (uy + (double)hin[N + n]);
+        vx = 0.5 * (ux + (double)hr[x0]);
+        vy = 0.5 * (uy + (double)hr[N + x0]);
       }
-      const double vxh = hin[2 * N + n], vyh = hin[3 * N + n], ps0 = a.ref[N + n];
+      const double vxh = hr[2 * N + x0], vyh = hr[3 * N + x0], ps0 = ref[N + row + x0];
       dpx = ph * vx - ph0 * vxh;
       dpy = ph * vy - ph0 * vyh;
       dsx = ps * vx - ps0 * vxh;
       dsy = ps * vy - ps0 * vyh;
       // R(n-1) in full: stored part plus its multiplier term
-      const double Rp_prev = (double)hin[4 * N + n] + p.M_phi * a.pend->lambda_phi * hprime(p, ph0);
-      const double Rs_prev = (double)hin[5 * N + n] + p.M_psi * a.pend->mubar_psi;
+      const double Rp_prev = (double)hr[4 * N + x0] + p.M_phi * a.pend->lambda_phi * hprime(p, ph0);
+      const double Rs_prev = (double)hr[5 * N + x0] + p.M_psi * a.pend->mubar_psi;
       Rtp = 1.5 * Rp0 - 0.5 * Rp_prev;
       Rts = 1.5 * Rs0 - 0.5 * Rs_prev;
     }
@@ -595,68 +686,48 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
                         (C)(rho * uy * third), (C)(rho * ux * third), (C)((pr + rho * uu) * third)};
       const C mv[9] = {(C)av, (C)Fx, (C)Fy, (C)(ux * grx + uy * gry * third), (C)((ux * gry + uy * grx) * third),
                        (C)(uy * gry + ux * grx * third), (C)(Fy * third), (C)(Fx * third), (C)(av * third)};
-      const C s2 = p.s2_local ? (C)(1.0 / (3.0 * mud_of(p, ph) / rho + 0.5)) : (C)p.sf[2];
-      const C rt[9] = {(C)p.sf[0], (C)p.sf[1], (C)p.sf[1], s2, s2, s2, (C)p.sf[3], (C)p.sf[3], (C)p.sf[4]};
+      const C s2 = p.s2_local ? (C)(1.0 / (3.0 * mud_of(p, ph) / rho + 0.5)) : (C)rf[2];
+      const C rt[9] = {(C)rf[0], (C)rf[1], (C)rf[1], s2, s2, s2, (C)rf[3], (C)rf[3], (C)rf[4]};
 #pragma unroll
       for (int k = 0; k < 9; ++k) m[k] = m[k] - rt[k] * (m[k] - meq[k]) + (C(1) - C(0.5) * rt[k]) * mv[k];
       moving_populations(m, o);
       o[0] = m[0] - m[3] - m[5] + m[8];
-      const bool wb = !p.periodic_y && gy == 0 && p.bc_bottom != LBM_BC_FREESLIP;
-      const bool wt = !p.periodic_y && gy == p.ny - 1 && p.bc_top != LBM_BC_FREESLIP;
+      const bool wb = WALLS && gy == 0 && p.bc_bottom != LBM_BC_FREESLIP;
+      const bool wt = WALLS && gy == p.ny - 1 && p.bc_top != LBM_BC_FREESLIP;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         C v = o[i];
         if (wb && CY(i) < 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_bottom);
         if (wt && CY(i) > 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_top);
-        Pout[(size_t)i * N + n] = (S)v;
+        if (active) (Pout + (size_t)i * N + row)[x0] = (S)v;
       }
     }
     {
       C o[9];
-      collide_scalar<C>(g, (C)ph, (C)p.eta_phi, (C)vx, (C)vy, (C)dpx, (C)dpy, (C)Rtp, p.sg, o);
+      collide_scalar<C>(g, (C)ph, (C)p.eta_phi, (C)vx, (C)vy, (C)dpx, (C)dpy, (C)Rtp, rg, o);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) Pout[(size_t)(9 + i) * N + n] = (S)o[i];
+      for (int i = 0; i < 9; ++i)
+        if (active) (Pout + (size_t)(9 + i) * N + row)[x0] = (S)o[i];
     }
-    if (p.surf) {
+    {
       C o[9];
-      collide_scalar<C>(h, (C)ps, (C)p.eta_psi, (C)vx, (C)vy, (C)dsx, (C)dsy, (C)Rts, p.sh, o);
+      if (p.surf) collide_scalar<C>(h, (C)ps, (C)p.eta_psi, (C)vx, (C)vy, (C)dsx, (C)dsy, (C)Rts, rh, o);
+      else {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) Pout[(size_t)(18 + i) * N + n] = (S)o[i];
-    } else {
+        for (int i = 0; i < 9; ++i) o[i] = C(0);
+      }
 #pragma unroll
-      for (int i = 0; i < 9; ++i) Pout[(size_t)(18 + i) * N + n] = (S)C(0);
+      for (int i = 0; i < 9; ++i)
+        if (active) (Pout + (size_t)(18 + i) * N + row)[x0] = (S)o[i];
     }
-    hout[n] = (C)ux;
-    hout[N + n] = (C)uy;
-    hout[2 * N + n] = (C)vx;
-    hout[3 * N + n] = (C)vy;
-    hout[4 * N + n] = (C)Rp0;
-    hout[5 * N + n] = (C)Rs0;
-  }
-
-  // ---- D: the last tile to finish forms lambda(n), mubar(n)
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(a.counter, 1u);
-    sLast = prev == (unsigned)(a.ntiles - 1);
-  }
-  __syncthreads();
-  if (sLast) {
-    __threadfence();
-    double t1 = 0.0, t2 = 0.0, t3 = 0.0;
-    for (int b = threadIdx.x; b < a.ntiles; b += kBlock) {
-      t1 += a.partials[3 * (size_t)b + 0];
-      t2 += a.partials[3 * (size_t)b + 1];
-      t3 += a.partials[3 * (size_t)b + 2];
-    }
-    t1 = block_reduce(t1, false);
-    t2 = block_reduce(t2, false);
-    t3 = block_reduce(t3, false);
-    if (threadIdx.x == 0) {
-      a.next->lambda_phi = t2 > 0.0 ? t1 / t2 : 0.0;
-      a.next->mubar_psi = t3 / (double)p.N;
-      a.next->cdef = a.have_hist ? 1.5 : 1.0;
-      atomicExch(a.counter, 0u);
+    if (active) {
+      C* ho = hout + row;
+      ho[x0] = (C)ux;
+      ho[N + x0] = (C)uy;
+      ho[2 * N + x0] = (C)vx;
+      ho[3 * N + x0] = (C)vy;
+      ho[4 * N + x0] = (C)Rp0;
+      ho[5 * N + x0] = (C)Rs0;
     }
   }
 }
@@ -686,14 +757,12 @@ __global__ __launch_bounds__(kBlock) void k_init_fields(DevParams p, double* __r
 // g and h shifted by phi and psi, which go to the FP64 reference planes.
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_load(DevParams p, const double* __restrict__ F, int with_u, S* __restrict__ P,
-                                                 double* __restrict__ ref, DevScalars* __restrict__ pend,
-                                                 unsigned* __restrict__ counter) {
+                                                 double* __restrict__ ref, DevScalars* __restrict__ pend) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n == 0) {
     pend->lambda_phi = 0.0;
     pend->mubar_psi = 0.0;
     pend->cdef = 0.0;
-    *counter = 0u;
   }
   if (n >= p.N) return;
   const size_t N = (size_t)p.N;
@@ -951,7 +1020,7 @@ inline int tiles_x(const DevParams& p) { return (p.nx + kTileX - 1) / kTileX; }
 inline int tiles(const DevParams& p, int ty) { return tiles_x(p) * ((p.ny + ty - 1) / ty); }
 
 template <class S, class C, int TY>
-void launch_fused(const DevParams& p, DevState& s, int have_hist, hipStream_t st) {
+void launch_fused(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* t) {
   StepArgs a;
   a.Pin = s.pops[s.cur];
   a.Pout = s.pops[s.cur ^ 1];
@@ -962,23 +1031,28 @@ void launch_fused(const DevParams& p, DevState& s, int have_hist, hipStream_t st
   a.pend = s.scalars + s.scur;
   a.next = s.scalars + (s.scur ^ 1);
   a.partials = s.partials;
-  a.counter = s.counter;
   a.have_hist = have_hist;
   a.ntx = tiles_x(p);
   a.ntiles = tiles(p, TY);
-  hipLaunchKernelGGL((k_step<S, C, TY>), dim3(a.ntiles), dim3(kBlock), 0, st, p, a);
+  {
+    TimedScope ts(t, LBM_K_STEP, st);
+    if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, TY, false>), dim3(a.ntiles), dim3(kBlock), 0, st, p, a);
+    else hipLaunchKernelGGL((k_step<S, C, TY, true>), dim3(a.ntiles), dim3(kBlock), 0, st, p, a);
+  }
+  {
+    TimedScope ts(t, LBM_K_FINISH, st);
+    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(kBlock), 0, st, (const double*)a.partials, a.ntiles, p.N, have_hist,
+                       a.next);
+  }
 }
 
 template <class S, class C>
 hipError_t step_impl(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer) {
   StepTimer* t = (timer && timer->ev && timer->used < timer->max_steps) ? timer : nullptr;
-  {
-    TimedScope ts(t, LBM_K_STEP, st);
-    switch (s.tile_rows) {
-      case 4: launch_fused<S, C, 4>(p, s, have_hist, st); break;
-      case 8: launch_fused<S, C, 8>(p, s, have_hist, st); break;
-      default: launch_fused<S, C, 16>(p, s, have_hist, st); break;
-    }
+  switch (s.tile_rows) {
+    case 4: launch_fused<S, C, 4>(p, s, have_hist, st, t); break;
+    case 8: launch_fused<S, C, 8>(p, s, have_hist, st, t); break;
+    default: launch_fused<S, C, 16>(p, s, have_hist, st, t); break;
   }
   if (t) t->used += 1;
   s.cur ^= 1;
@@ -1014,7 +1088,7 @@ hipError_t fetch_impl(const DevParams& p, DevState& s, hipStream_t st) {
 template <class S>
 hipError_t load_impl(const DevParams& p, DevState& s, int with_u, hipStream_t st) {
   hipLaunchKernelGGL(k_load<S>, dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const double*)s.field_buf, with_u,
-                     (S*)s.pops[s.cur], (double*)s.phipsi[s.hcur ^ 1], s.scalars + s.scur, s.counter);
+                     (S*)s.pops[s.cur], (double*)s.phipsi[s.hcur ^ 1], s.scalars + s.scur);
   return hipGetLastError();
 }
 
@@ -1031,11 +1105,12 @@ size_t storage_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precis
 size_t fused_tiles(int nx, int ny, int tile_rows) {
   return (size_t)((nx + kTileX - 1) / kTileX) * (size_t)((ny + tile_rows - 1) / tile_rows);
 }
-// Tallest tile (less halo work per node) that still gives >= 8 workgroups per CU.
-int fused_tile_rows(int nx, int ny) {
-  if (fused_tiles(nx, ny, 16) >= 2048) return 16;
-  if (fused_tiles(nx, ny, 8) >= 2048) return 8;
-  return 4;
+// Tile height from measurements on MI355X: small grids want many workgroups
+// (4 rows); large FP32 grids run best at 8 rows, large FP64 grids at 16 (the
+// halo work per node shrinks with the height; occupancy falls with it).
+int fused_tile_rows(int nx, int ny, int precision) {
+  if (precision == LBM_FP64) return fused_tiles(nx, ny, 16) >= 2048 ? 16 : 4;
+  return fused_tiles(nx, ny, 8) >= 4096 ? 8 : 4;
 }
 size_t compute_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 

@@ -35,7 +35,7 @@ EXPORTS = ["lbm_required_bytes", "lbm_init", "lbm_step", "lbm_reduce_invariants"
            "lbm_load_fields", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_derived",
            "lbm_fetch_populations", "lbm_destroy", "lbm_last_error", "lbm_timing_begin", "lbm_timing_end",
            "lbm_bytes_per_node_step"]
-KERNEL_NAMES = ["k_step"]
+KERNEL_NAMES = ["k_step", "k_step_finish"]
 
 
 class LbmError(RuntimeError):
@@ -49,7 +49,7 @@ class Params(ctypes.Structure):
         ("abi_version", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("bc_bottom", ctypes.c_int32), ("bc_top", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("constraint_phi", ctypes.c_int32), ("init_kind", ctypes.c_int32),
-        ("adv_raw", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("adv_raw", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
         ("sigma_gl0", ctypes.c_double), ("eps", ctypes.c_double),
         ("M_phi", ctypes.c_double), ("M_psi", ctypes.c_double), ("lambda_s", ctypes.c_double),
         ("kBT", ctypes.c_double), ("W", ctypes.c_double), ("Ex", ctypes.c_double), ("Pi", ctypes.c_double),

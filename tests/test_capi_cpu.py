@@ -64,7 +64,7 @@ def test_required_bytes_and_validation(lbm):
     n32 = lbm.required_bytes(cfg, "fp32")
     N = 64 * 64
     assert n64 > 2 * 27 * N * 8 and n32 > 2 * 27 * N * 4 and n64 > n32
-    bad = [dict(cfg, nx=2), dict(cfg, psi_b=1.0), dict(cfg, bc_bottom=inputs.WALL_WET),
+    bad = [dict(cfg, nx=2), dict(cfg, psi_b=1.0), dict(cfg, bc_bottom=inputs.WALL_WET), dict(cfg, tile_rows=5),
            dict(cfg, s_g=[1, 2.5, 1, 1, 1]), dict(cfg, sigma_gl0=0.0)]
     wet = inputs.sessile_drop(nx=32, ny=16, R=5)
     bad.append(dict(wet, theta0_deg=0.0))

@@ -79,6 +79,20 @@ def test_fp32_parity(lbm, name):
         assert_fields_close(gf, of, 1e-5, u_scale(cfg), p_scale(cfg), f"{name} fp32 step {step}")
 
 
+@pytest.mark.parametrize("rows", [4, 8, 16])
+def test_tile_heights(lbm, rows):
+    """Every tile height of the fused step kernel, on a periodic grid and on a
+    walled grid whose sizes are not multiples of the tile (ragged tiles in x
+    and y), in both storage precisions."""
+    cases = [dict(CASES["ragged_67x37_walls"], tile_rows=rows),
+             dict(inputs.stationary_drop(nx=150, ny=70, R=20.0), tile_rows=rows),
+             dict(CASES["shear_liquid_adsorption"], tile_rows=rows)]
+    for cfg in cases:
+        for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
+            for step, gf, of, _, _ in run_pair(lbm, cfg, prec, [3, 60]):
+                assert_fields_close(gf, of, tol, u_scale(cfg), p_scale(cfg), f"rows {rows} {prec} step {step}")
+
+
 def test_stationary_drop_1000_steps(lbm):
     """Plain method, FP64, 2-D periodic 64x64 stationary droplet, 1000 steps:
     fields within 1e-10, surfactant mass drift below 1e-12 relative."""
