@@ -394,27 +394,44 @@ __global__ __launch_bounds__(kBlock) void k_step_finish(const double* __restrict
   }
 }
 
-// Gather of population i of lattice lat at column x0 of row y, for a wave
-// whose lanes usually share y: the plane and row then form a wave-uniform
-// base pointer and only the column (xm = x0 - 1, xp = x0 + 1, wrapped) is
-// per lane, so each load is one scalar-base + 32-bit-offset access.  Wall
-// sources as in pull().
-template <class S, class C, bool WALLS>
-__device__ __forceinline__ C pull_row(const DevParams& p, const S* __restrict__ P, size_t N, int lat, int i, int y,
-                                      unsigned xm, unsigned x0, unsigned xp) {
-  const unsigned sx = CX(i) > 0 ? xm : (CX(i) < 0 ? xp : x0);
+// Element at byte offset b (32-bit, per lane) from a row base pointer (64-bit,
+// usually wave-uniform): the form the hardware addresses as a scalar base plus a
+// vector offset, with no 64-bit address arithmetic per lane.
+template <class T> __device__ __forceinline__ T* byte_at(T* base, unsigned b) { return (T*)((char*)base + b); }
+template <class T> __device__ __forceinline__ const T* byte_at(const T* base, unsigned b) {
+  return (const T*)((const char*)base + b);
+}
+
+// Gather of population i of lattice lat at the column whose byte offset (in
+// storage elements) is b0 in row y; bm, bp are the byte offsets of the
+// columns x - 1 and x + 1 (wrapped).  For a wave whose lanes share y the plane
+// and row form a wave-uniform base.  Wall sources as in pull().
+template <class S, class C, bool WALLS, int lat>
+__device__ __forceinline__ C pull_row(const DevParams& p, const S* __restrict__ P, size_t N, int i, int y,
+                                      unsigned bm, unsigned b0, unsigned bp) {
+  // f is gathered once per step (g and h twice: for phi/psi and for the
+  // collision), so its loads stream past the L2 instead of evicting g and h.
+  auto ld = [&](const S* rowbase, unsigned b) {
+    const S* q = byte_at(rowbase, b);
+    if constexpr (lat == 0) return (C)__builtin_nontemporal_load(q);
+    else return (C)*q;
+  };
+  const unsigned sb = CX(i) > 0 ? bm : (CX(i) < 0 ? bp : b0);
   int sy = y - CY(i);
   if (!WALLS) {
     sy = sy < 0 ? sy + p.ny : (sy >= p.ny ? sy - p.ny : sy);
   } else if (sy < 0 || sy >= p.ny) {
     const int bc = sy < 0 ? p.bc_bottom : p.bc_top;
-    if (lat == 0 && bc == LBM_BC_FREESLIP) return (C)(P + (size_t)MIRY(i) * N + (size_t)y * p.nx)[sx];
-    return (C)(P + (size_t)(9 * lat + OPP(i)) * N + (size_t)y * p.nx)[x0];
+    if (lat == 0 && bc == LBM_BC_FREESLIP) return ld(P + (size_t)MIRY(i) * N + (size_t)y * p.nx, sb);
+    return ld(P + (size_t)(9 * lat + OPP(i)) * N + (size_t)y * p.nx, b0);
   }
-  return (C)(P + (size_t)(9 * lat + i) * N + (size_t)sy * p.nx)[sx];
+  return ld(P + (size_t)(9 * lat + i) * N + (size_t)sy * p.nx, sb);
 }
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Outputs of a step are not read again by it: streaming stores keep them from
+// evicting the populations the tile's phases re-read from L2.
+template <class T> __device__ __forceinline__ void stream_store(T* p, T v) { __builtin_nontemporal_store(v, p); }
 // A wave-uniform value the optimiser cannot see through: what is derived from
 // it inside a loop stays in the loop instead of being hoisted into registers.
 template <class T> __device__ __forceinline__ T opaque(T v) {
@@ -475,29 +492,29 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
 
   // ---- A: node (lx, ly) of the halo-2 frame at fluid row y, column x
   auto node_A = [&](int lx, int ly, int y, unsigned x) {
-    const unsigned xm = colm(x), xp = colp(x);
+    const unsigned xm = colm(x) * sizeof(S), xs = x * sizeof(S), xp = colp(x) * sizeof(S), xd = x * sizeof(double);
     C sg = C(0), sh = C(0), corr = C(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      sg += pull_row<S, C, WALLS>(p, Pin, N, 1, i, y, xm, x, xp);
+      sg += pull_row<S, C, WALLS, 1>(p, Pin, N, i, y, xm, xs, xp);
       // emitter of g_i in LDS coordinates: x - c_i, or the node itself at a wall
       const int sy = y - CY(i);
       const bool bb = WALLS && (sy < 0 || sy >= p.ny);
       corr += WQ<C>(i) * (bb ? sHp[ly + 1][lx + 1] : sHp[ly + 1 - CY(i)][lx + 1 - CX(i)]);
     }
-    const size_t node = (size_t)y * p.nx + x;
-    const double ph = ref[node] + (double)sg + lam1_ * (double)corr;
+    const size_t row = (size_t)y * p.nx;
+    const double ph = *byte_at(ref + row, xd) + (double)sg + lam1_ * (double)corr;
     double ps = 0.0;
     if (p.surf) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) sh += pull_row<S, C, WALLS>(p, Pin, N, 2, i, y, xm, x, xp);
-      ps = ref[N + node] + (double)sh + mub1_;
+      for (int i = 0; i < 9; ++i) sh += pull_row<S, C, WALLS, 2>(p, Pin, N, i, y, xm, xs, xp);
+      ps = *byte_at(ref + N + row, xd) + (double)sh + mub1_;
     }
     sPP[ly][lx] = make_double2(ph, ps);
     const int tx = lx - 2, ty = ly - 2;
     if (tx >= 0 && tx < kTileX && ty >= 0 && ty < TY && X0 + tx < p.nx && Y0 + ty < p.ny) {
-      a.out[node] = ph;
-      a.out[N + node] = ps;
+      stream_store(byte_at(a.out + row, xd), ph);
+      stream_store(byte_at(a.out + N + row, xd), ps);
     }
   };
   // columns X0-2 .. X0+61 as whole rows (one wave per row) ...
@@ -588,7 +605,8 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
   C* __restrict__ hout = (C*)a.hout;
   const int tx = lane;
   const unsigned x0 = (unsigned)min(X0 + tx, p.nx - 1);   // lanes past a ragged edge compute a copy, store nothing
-  const unsigned xm = colm(x0), xp = colp(x0);
+  const unsigned xm = colm(x0) * sizeof(S), xs = x0 * sizeof(S), xp = colp(x0) * sizeof(S);
+  const unsigned xd = x0 * sizeof(double), xc = x0 * sizeof(C);
   const bool active = X0 + tx < p.nx;
   // rho is affine in phi: grad rho = (d rho / d phi) grad phi (ghost values included)
   const double drho = (p.rho_l - p.rho_g) * 0.5 * p.inv_phib;
@@ -613,18 +631,18 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
     const double2 c = sPP[cy][cx];
     const double ph = c.x, ps = c.y;
     const double2 mc = sMU[ty + 1][tx + 1];
-    const double ph0 = ref[row + x0];   // phi(n-1)
+    const double ph0 = *byte_at(ref + row, xd);   // phi(n-1)
 
     C f[9], g[9], h[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      f[i] = pull_row<S, C, WALLS>(p, Pin, N, 0, i, gy, xm, x0, xp);
+      f[i] = pull_row<S, C, WALLS, 0>(p, Pin, N, i, gy, xm, xs, xp);
       if (i == 0) { g[0] = C(0); h[0] = C(0); continue; }
       const int sy = gy - CY(i);
       const bool bb = WALLS && (sy < 0 || sy >= p.ny);
       const C hpe = bb ? sHp[ty + 3][tx + 3] : sHp[ty + 3 - CY(i)][tx + 3 - CX(i)];
-      g[i] = pull_row<S, C, WALLS>(p, Pin, N, 1, i, gy, xm, x0, xp) + (C)(lam1 * WQ<double>(i) * (double)hpe);
-      h[i] = p.surf ? pull_row<S, C, WALLS>(p, Pin, N, 2, i, gy, xm, x0, xp) + (C)(mub1 * WQ<double>(i)) : C(0);
+      g[i] = pull_row<S, C, WALLS, 1>(p, Pin, N, i, gy, xm, xs, xp) + (C)(lam1 * WQ<double>(i) * (double)hpe);
+      h[i] = p.surf ? pull_row<S, C, WALLS, 2>(p, Pin, N, i, gy, xm, xs, xp) + (C)(mub1 * WQ<double>(i)) : C(0);
     }
     // gradients of phi (wetting ghosts), mu_phi, mu_psi; Laplacians of phi, psi
     double gfx = 0, gfy = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0, l0p = 0, l0s = 0;
@@ -661,17 +679,17 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
     if (a.have_hist) {
       const C* hr = hin + row;
       if (!p.adv_raw) {
-        vx = 0.5 * (ux + (double)hr[x0]);
-        vy = 0.5 * (uy + (double)hr[N + x0]);
+        vx = 0.5 * (ux + (double)*byte_at(hr, xc));
+        vy = 0.5 * (uy + (double)*byte_at(hr + N, xc));
       }
-      const double vxh = hr[2 * N + x0], vyh = hr[3 * N + x0], ps0 = ref[N + row + x0];
+      const double vxh = *byte_at(hr + 2 * N, xc), vyh = *byte_at(hr + 3 * N, xc), ps0 = *byte_at(ref + N + row, xd);
       dpx = ph * vx - ph0 * vxh;
       dpy = ph * vy - ph0 * vyh;
       dsx = ps * vx - ps0 * vxh;
       dsy = ps * vy - ps0 * vyh;
       // R(n-1) in full: stored part plus its multiplier term
-      const double Rp_prev = (double)hr[4 * N + x0] + p.M_phi * a.pend->lambda_phi * hprime(p, ph0);
-      const double Rs_prev = (double)hr[5 * N + x0] + p.M_psi * a.pend->mubar_psi;
+      const double Rp_prev = (double)*byte_at(hr + 4 * N, xc) + p.M_phi * a.pend->lambda_phi * hprime(p, ph0);
+      const double Rs_prev = (double)*byte_at(hr + 5 * N, xc) + p.M_psi * a.pend->mubar_psi;
       Rtp = 1.5 * Rp0 - 0.5 * Rp_prev;
       Rts = 1.5 * Rs0 - 0.5 * Rs_prev;
     }
@@ -699,7 +717,7 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
         C v = o[i];
         if (wb && CY(i) < 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_bottom);
         if (wt && CY(i) > 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_top);
-        if (active) (Pout + (size_t)i * N + row)[x0] = (S)v;
+        if (active) stream_store(byte_at(Pout + (size_t)i * N + row, xs), (S)v);
       }
     }
     {
@@ -707,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
       collide_scalar<C>(g, (C)ph, (C)p.eta_phi, (C)vx, (C)vy, (C)dpx, (C)dpy, (C)Rtp, rg, o);
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        if (active) (Pout + (size_t)(9 + i) * N + row)[x0] = (S)o[i];
+        if (active) stream_store(byte_at(Pout + (size_t)(9 + i) * N + row, xs), (S)o[i]);
     }
     {
       C o[9];
@@ -718,16 +736,16 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
       }
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        if (active) (Pout + (size_t)(18 + i) * N + row)[x0] = (S)o[i];
+        if (active) stream_store(byte_at(Pout + (size_t)(18 + i) * N + row, xs), (S)o[i]);
     }
     if (active) {
       C* ho = hout + row;
-      ho[x0] = (C)ux;
-      ho[N + x0] = (C)uy;
-      ho[2 * N + x0] = (C)vx;
-      ho[3 * N + x0] = (C)vy;
-      ho[4 * N + x0] = (C)Rp0;
-      ho[5 * N + x0] = (C)Rs0;
+      stream_store(byte_at(ho, xc), (C)ux);
+      stream_store(byte_at(ho + N, xc), (C)uy);
+      stream_store(byte_at(ho + 2 * N, xc), (C)vx);
+      stream_store(byte_at(ho + 3 * N, xc), (C)vy);
+      stream_store(byte_at(ho + 4 * N, xc), (C)Rp0);
+      stream_store(byte_at(ho + 5 * N, xc), (C)Rs0);
     }
   }
 }
