@@ -49,7 +49,7 @@ Layout make_layout(const lbm_params& p) {
   L.phipsi = take(2 * 2 * N * sizeof(double));  // phi, psi: FP64 in every precision
   L.mu = take(2 * N * sizeof(double));
   L.uhist = take(2 * 6 * N * cb);  // u, v (advecting), R_phi, R_psi history, ping-pong
-  const size_t ntile = lbm::fused_tiles(p.nx, p.ny, 4);  // the most tiles any tile height gives
+  const size_t ntile = lbm::step_blocks(p.nx, p.ny, 4);  // the most workgroups any segment height gives
   L.partials = take((ntile > (size_t)lbm::kRedBlocks ? ntile : (size_t)lbm::kRedBlocks) * 3 * sizeof(double));
   L.inv_partials = take(lbm::kRedBlocks * lbm::kInvValues * sizeof(double));
   L.inv_out = take(lbm::kInvOut * sizeof(double));
@@ -75,7 +75,7 @@ std::string derive(const lbm_params& p, lbm::DevParams& d, double* derived) {
   if (p.constraint_phi != LBM_CONSTRAINT_NONLINEAR && p.constraint_phi != LBM_CONSTRAINT_LINEAR) return "unknown constraint";
   if (p.init_kind < LBM_INIT_DROP || p.init_kind > LBM_INIT_BUBBLE) return "unknown init kind";
   if (p.adv_raw != 0 && p.adv_raw != 1) return "adv_raw must be 0 or 1";
-  if (p.tile_rows != 0 && p.tile_rows != 4 && p.tile_rows != 8 && p.tile_rows != 16) return "tile_rows must be 0, 4, 8 or 16";
+  if (p.tile_rows < 0 || p.tile_rows % 4 != 0 || p.tile_rows > 4096) return "tile_rows must be 0 or a multiple of 4 up to 4096";
   if (!(p.sigma_gl0 > 0.0) || !(p.eps > 0.0)) return "sigma_gl0 and eps must be > 0";
   if (!(p.M_phi >= 0.0) || !(p.M_psi >= 0.0)) return "mobilities must be >= 0";
   if (!(p.psi_b >= 0.0 && p.psi_b < 1.0)) return "psi_b must lie in [0,1)";
@@ -196,7 +196,7 @@ void carve(lbm_handle* h) {
   s.contact = (double*)(b + L.contact);
   s.scalars = (lbm::DevScalars*)(b + L.scalars);
   s.scur = 0;
-  s.tile_rows = h->prm.tile_rows ? h->prm.tile_rows : lbm::fused_tile_rows(h->dp.nx, h->dp.ny, h->prm.precision);
+  s.tile_rows = h->prm.tile_rows ? h->prm.tile_rows : lbm::step_seg_rows(h->dp.nx, h->dp.ny);
   s.field_buf = (double*)(b + L.field_buf);
   s.cur = 0;
   s.hcur = 0;

@@ -60,19 +60,20 @@ struct DevState {
   DevScalars* scalars;     // [3]: pending multipliers (ping-pong by scur) and the diagnostic slot [2]
   double* field_buf;       // FP64 staging for fetch/load, [27][N]
   int scur;                // scalars[scur] holds the multipliers pending on the stored populations
-  int tile_rows;           // tile height of the fused step (4, 8 or 16); width is 64
+  int tile_rows;           // rows per workgroup segment of the step kernel (a multiple of 4)
   int cur;                 // index of the current population buffer
   int hcur;                // phi/psi and history buffer written by the next step
 };
 
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 1024;
-constexpr int kTileX = 64;
+constexpr int kStripW = 60;   // interior columns of a step workgroup (its 64 lanes add 2 halo columns a side)
+constexpr int NWAVE = kBlock / 64;
 constexpr int kMaxTiles = 1 << 22;   // partials of the fused step: [kMaxTiles][3] at most (grid <= 2^28 nodes at 64x16)
 
 size_t storage_bytes(int precision);
-int fused_tile_rows(int nx, int ny, int precision);  // tile height of the fused step for a grid
-size_t fused_tiles(int nx, int ny, int tile_rows);
+int step_seg_rows(int nx, int ny);                 // rows per workgroup segment of the step kernel
+size_t step_blocks(int nx, int ny, int seg_rows);  // workgroups of the step kernel
 size_t compute_bytes(int precision);
 
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the HIP status.

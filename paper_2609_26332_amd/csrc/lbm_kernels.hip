@@ -367,7 +367,7 @@ struct StepArgs {
   const DevScalars* pend;   // multipliers pending on Pin (from step n-1)
   DevScalars* next;         // multipliers of step n, written by the last tile
   double* partials;         // [ntiles][3]
-  int have_hist, ntx, ntiles;
+  int have_hist, nstrips, seg_rows, ntiles;
 };
 
 // lambda(n) = S1/S2, mubar(n) = S3/N from the per-tile partial sums of
@@ -443,29 +443,35 @@ template <class T> __device__ __forceinline__ T opaque_v(T v) {   // the same fo
   return v;
 }
 
-// One fused time step on a 64 x TY tile of nodes (256 threads = 4 waves; a
-// wave works on whole rows, so row-dependent choices, walls included, are
-// wave-uniform):
-//  A0 h'(phi(n-1)) on the tile and a halo of 3 (ghost rows: nearest fluid row)
-//  A  phi(n), psi(n) on the tile and a halo of 2 from the gathered g, h, the
-//     FP64 reference planes and the pending multiplier term; the tile's
-//     values go to the output planes
-//  B  mu_phi, mu_psi on the tile and a halo of 1 (wall terms from the
-//     first fluid row); FP64 block sums of h' mu_phi, h'^2, mu_psi
-//  C  force, velocity, pressure, sources, collision of the tile nodes; the
+// One fused time step for a strip of kStripW = 60 columns and a segment of
+// rows, swept upward (256 threads = 4 waves).  The 64 lanes of a wave cover the
+// columns X0-2 .. X0+61 of one row: the strip plus the two halo columns on
+// each side that the stencils need, so no phase needs a second pass for its
+// x halo.  Per iteration every wave handles one row of each phase:
+//  H  h'(phi(n-1)) of a row four iterations ahead of its use
+//  A  phi(n), psi(n) of row r+2 from the gathered g, h, the FP64 reference
+//     planes and the pending multiplier term (the segment's rows go to the
+//     output planes)
+//  B  mu_phi, mu_psi of row r+1 (wall terms from the first fluid row); FP64
+//     sums of h' mu_phi, h'^2, mu_psi over the segment's nodes
+//  C  force, velocity, pressure, sources and collision of row r; the
 //     multiplier terms of this step's sources are left out of the stored
 //     populations and of the stored source history (deferred to step n+1)
+// The rows live in LDS rings indexed by row: each halo row of the segment is
+// computed once, and the g, h gathered again by C were gathered by A one or
+// two iterations earlier (L2 hits).  At a wall the ghost rows beyond it hold
+// the nearest fluid row's values (computed again, not copied).
 // k_step_finish then reduces the block sums to lambda(n), mubar(n).
-template <class S, class C, int TY, bool WALLS>
+template <class S, class C, bool WALLS>
 __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
-  constexpr int W3 = kTileX + 6, H3 = TY + 6, W2 = kTileX + 4, H2 = TY + 4, W1 = kTileX + 2, H1 = TY + 2;
-  constexpr int NW = kBlock / 64;
-  __shared__ C sHp[H3][W3];          // h'(phi(n-1)), halo 3
-  __shared__ double2 sPP[H2][W2];    // (phi, psi)(n), halo 2 (ghost rows mirrored)
-  __shared__ double2 sMU[H1][W1];    // (mu_phi, mu_psi), halo 1 (ghost rows mirrored)
+  constexpr int RP = 16, RM = 8;           // ring rows: h' and (phi, psi); (mu_phi, mu_psi)
+  __shared__ C sHp[RP][kStripW + 6];       // h'(phi(n-1)), columns X0-3 .. X0+62
+  __shared__ double2 sPP[RP][64];          // (phi, psi)(n), columns X0-2 .. X0+61
+  __shared__ double2 sMU[RM][64];          // (mu_phi, mu_psi), columns X0-2 .. X0+61 (lanes 1..62 used)
 
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int X0 = (tile % a.ntx) * kTileX, Y0 = (tile / a.ntx) * TY;
+  const int X0 = (tile % a.nstrips) * kStripW, Y0 = (tile / a.nstrips) * a.seg_rows;
+  const int Yend = min(Y0 + a.seg_rows, p.ny);
   const size_t N = (size_t)p.N;
   const S* __restrict__ Pin = (const S*)a.Pin;
   S* __restrict__ Pout = (S*)a.Pout;
@@ -474,150 +480,114 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
   const double mub1_ = a.pend->cdef * p.M_psi * a.pend->mubar_psi;
   const int lane = threadIdx.x & 63;
   const int wave = wave_uniform(threadIdx.x >> 6);
-  auto fluid_row = [&](int gy) { return !WALLS || (gy >= 0 && gy < p.ny); };
+  // fluid row of a (possibly ghost or wrapped) row index
   auto row_of = [&](int gy) { return WALLS ? (gy < 0 ? 0 : (gy >= p.ny ? p.ny - 1 : gy)) : modp(gy, p.ny); };
+  // ring row of the stencil centre: at a wall a ghost row is its fluid row's copy
+  auto centre = [&](int gy) { return WALLS ? row_of(gy) : gy; };
   auto colm = [&](unsigned x) { return x == 0 ? (unsigned)p.nx - 1 : x - 1; };
   auto colp = [&](unsigned x) { return x + 1 == (unsigned)p.nx ? 0u : x + 1; };
+  const unsigned xcol = (unsigned)modp(X0 - 2 + lane, p.nx);   // this lane's column
+  // The phases take the lane and its column as arguments, opaque copies made per
+  // iteration: what they derive from them (byte offsets, LDS addresses) is then
+  // recomputed per row instead of being hoisted out of the sweep and held in
+  // registers for its whole length.
+  auto is_interior = [&](int ln) { return ln >= 2 && ln < kStripW + 2 && X0 + ln - 2 < p.nx; };
 
-  // ---- A0 (unrolled: all of a thread's loads are in flight together)
-#pragma unroll
-  for (int r = 0; r < (H3 * W3 + kBlock - 1) / kBlock; ++r) {
-    const int k = threadIdx.x + r * kBlock;
-    if (k < H3 * W3) {
-      const int ly = k / W3, lx = k - ly * W3;
-      sHp[ly][lx] = (C)hprime(p, ref[(size_t)row_of(Y0 - 3 + ly) * p.nx + modp(X0 - 3 + lx, p.nx)]);
+  // ---- H: h'(phi(n-1)) of row gy into ring slot gy; lanes 0 and 1 also take
+  // the outer columns X0-3 and X0+62
+  auto row_H = [&](int gy, int ln, unsigned x) {
+    const double* r = ref + (size_t)row_of(gy) * p.nx;
+    sHp[gy & (RP - 1)][ln + 1] = (C)hprime(p, *byte_at(r, x * (unsigned)sizeof(double)));
+    if (ln < 2) {
+      const int k = ln ? kStripW + 5 : 0;
+      sHp[gy & (RP - 1)][k] = (C)hprime(p, r[modp(X0 - 3 + k, p.nx)]);
     }
-  }
-  __syncthreads();
+  };
 
-  // ---- A: node (lx, ly) of the halo-2 frame at fluid row y, column x
-  auto node_A = [&](int lx, int ly, int y, unsigned x) {
-    const unsigned xm = colm(x) * sizeof(S), xs = x * sizeof(S), xp = colp(x) * sizeof(S), xd = x * sizeof(double);
+  // ---- A: (phi, psi)(n) of row gy into ring slot gy
+  auto row_A = [&](int gy, int ln, unsigned x) {
+    const int y = wave_uniform(row_of(gy)), yc = centre(gy);
+    const unsigned xs = x * sizeof(S), xsm = colm(x) * sizeof(S), xsp = colp(x) * sizeof(S), xd = x * sizeof(double);
     C sg = C(0), sh = C(0), corr = C(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      sg += pull_row<S, C, WALLS, 1>(p, Pin, N, i, y, xm, xs, xp);
-      // emitter of g_i in LDS coordinates: x - c_i, or the node itself at a wall
+      sg += pull_row<S, C, WALLS, 1>(p, Pin, N, i, y, xsm, xs, xsp);
+      // emitter of g_i: x - c_i, or the node itself at a wall
       const int sy = y - CY(i);
       const bool bb = WALLS && (sy < 0 || sy >= p.ny);
-      corr += WQ<C>(i) * (bb ? sHp[ly + 1][lx + 1] : sHp[ly + 1 - CY(i)][lx + 1 - CX(i)]);
+      corr += WQ<C>(i) * (bb ? sHp[yc & (RP - 1)][ln + 1] : sHp[(yc - CY(i)) & (RP - 1)][ln + 1 - CX(i)]);
     }
     const size_t row = (size_t)y * p.nx;
     const double ph = *byte_at(ref + row, xd) + (double)sg + lam1_ * (double)corr;
     double ps = 0.0;
     if (p.surf) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) sh += pull_row<S, C, WALLS, 2>(p, Pin, N, i, y, xm, xs, xp);
+      for (int i = 0; i < 9; ++i) sh += pull_row<S, C, WALLS, 2>(p, Pin, N, i, y, xsm, xs, xsp);
       ps = *byte_at(ref + N + row, xd) + (double)sh + mub1_;
     }
-    sPP[ly][lx] = make_double2(ph, ps);
-    const int tx = lx - 2, ty = ly - 2;
-    if (tx >= 0 && tx < kTileX && ty >= 0 && ty < TY && X0 + tx < p.nx && Y0 + ty < p.ny) {
+    sPP[gy & (RP - 1)][ln] = make_double2(ph, ps);
+    if (is_interior(ln) && gy >= Y0 && gy < Yend) {
       stream_store(byte_at(a.out + row, xd), ph);
       stream_store(byte_at(a.out + N + row, xd), ps);
     }
   };
-  // columns X0-2 .. X0+61 as whole rows (one wave per row) ...
-  static_assert(H2 % NW == 0 && TY % NW == 0, "rows per wave");
-#pragma unroll
-  for (int r = 0; r < H2 / NW; ++r) {
-    const int ly = wave + r * NW, gy = Y0 - 2 + ly;
-    if (fluid_row(gy)) node_A(lane, ly, wave_uniform(row_of(gy)), (unsigned)modp(X0 - 2 + lane, p.nx));
-  }
-  // ... and the last four columns, X0+62 .. X0+65, four nodes per row
-#pragma unroll 1
-  for (int k = threadIdx.x; k < 4 * H2; k += kBlock) {
-    const int ly = k >> 2, lx = kTileX + (k & 3), gy = Y0 - 2 + ly;
-    if (fluid_row(gy)) node_A(lx, ly, row_of(gy), (unsigned)modp(X0 - 2 + lx, p.nx));
-  }
-  __syncthreads();
-  if (WALLS) {  // ghost rows take the nearest fluid row of the same column
-    for (int k = threadIdx.x; k < H2 * W2; k += kBlock) {
-      const int ly = k / W2, lx = k - ly * W2;
-      const int gy = Y0 - 2 + ly;
-      if (fluid_row(gy)) continue;
-      sPP[ly][lx] = sPP[row_of(gy) - (Y0 - 2)][lx];
-    }
-    __syncthreads();
-  }
 
-  // ---- B: node (lx, ly) of the halo-1 frame at fluid row gy
+  // ---- B: (mu_phi, mu_psi) of row gy into ring slot gy (lanes 1..62)
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  auto node_B = [&](int lx, int ly, int gy) {
-    const int cy = ly + 1, cx = lx + 1;   // in sPP
-    const double2 c = sPP[cy][cx];
+  auto row_B = [&](int gy, int ln) {
+    const int y = wave_uniform(row_of(gy)), yc = centre(gy);
+    const int l = min(max(ln, 1), 62);   // lanes 0 and 63 have no neighbour column: computed, unused
+    const double2 c = sPP[yc & (RP - 1)][l];
     const double ph = c.x, ps = c.y;
     Lap L{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const double w2 = 6.0 * WQ<double>(i);
-      const double2 nb = sPP[cy + CY(i)][cx + CX(i)];
+      const double2 nb = sPP[(yc + CY(i)) & (RP - 1)][l + CX(i)];
       L.l0p += w2 * (nb.x - ph);
       L.l0s += w2 * (nb.y - ps);
-      const int ny_ = gy + CY(i);
+      const int ny_ = y + CY(i);
       if (WALLS && (ny_ < 0 || ny_ >= p.ny) && wet_side(p, ny_ < 0 ? -1 : 1)) {
         // fluid node next to the ghost: same row, column x + c_x
-        const double2 f = sPP[cy][cx + CX(i)];
+        const double2 f = sPP[yc & (RP - 1)][l + CX(i)];
         L.Tp += w2 * Jphi(p, f.x, f.y);
         if (p.surf) L.Ts += w2 * Jpsi(p, f.x, f.y);
       }
     }
     const double mp = mu_phi_of(p, ph, ps, L), ms = mu_psi_of(p, ph, ps, L);
-    sMU[ly][lx] = make_double2(mp, ms);
-    const int tx = lx - 1, ty = ly - 1;
-    if (tx >= 0 && tx < kTileX && ty >= 0 && ty < TY && X0 + tx < p.nx && Y0 + ty < p.ny) {
+    sMU[gy & (RM - 1)][ln] = make_double2(mp, ms);
+    if (is_interior(ln) && gy >= Y0 && gy < Yend) {
       const double hp = hprime(p, ph);
       s1 += hp * mp;
       s2 += hp * hp;
       s3 += ms;
     }
   };
-#pragma unroll 1
-  for (int ly = wave; ly < H1; ly += NW) {
-    const int gy = Y0 - 1 + ly;
-    if (fluid_row(gy)) node_B(lane, ly, wave_uniform(gy));
-  }
-#pragma unroll 1
-  for (int k = threadIdx.x; k < 2 * H1; k += kBlock) {
-    const int ly = k >> 1, lx = kTileX + (k & 1), gy = Y0 - 1 + ly;
-    if (fluid_row(gy)) node_B(lx, ly, gy);
-  }
-  s1 = block_reduce(s1, false);
-  s2 = block_reduce(s2, false);
-  s3 = block_reduce(s3, false);
-  if (threadIdx.x == 0) {
-    a.partials[3 * (size_t)tile + 0] = s1;
-    a.partials[3 * (size_t)tile + 1] = s2;
-    a.partials[3 * (size_t)tile + 2] = s3;
-  }
-  if (WALLS) {
-    for (int k = threadIdx.x; k < H1 * W1; k += kBlock) {
-      const int ly = k / W1, lx = k - ly * W1;
-      const int gy = Y0 - 1 + ly;
-      if (fluid_row(gy)) continue;
-      sMU[ly][lx] = sMU[row_of(gy) - (Y0 - 1)][lx];
-    }
-  }
-  __syncthreads();
 
-  // ---- C: collide the tile nodes, one row per wave
+  // ---- C: collide row gy (a fluid row of the segment)
   const C* __restrict__ hin = (const C*)a.hin;
   C* __restrict__ hout = (C*)a.hout;
-  const int tx = lane;
-  const unsigned x0 = (unsigned)min(X0 + tx, p.nx - 1);   // lanes past a ragged edge compute a copy, store nothing
-  const unsigned xm = colm(x0) * sizeof(S), xs = x0 * sizeof(S), xp = colp(x0) * sizeof(S);
-  const unsigned xd = x0 * sizeof(double), xc = x0 * sizeof(C);
-  const bool active = X0 + tx < p.nx;
-  // rho is affine in phi: grad rho = (d rho / d phi) grad phi (ghost values included)
-  const double drho = (p.rho_l - p.rho_g) * 0.5 * p.inv_phib;
-#pragma unroll 2
-  for (int r = 0; r < TY / NW; ++r) {
-    const int ty = wave + r * NW;
-    const int gy = wave_uniform(Y0 + ty);
-    if (gy >= p.ny) break;
+  // the gathers of a collision row, issued an iteration phase ahead of their use
+  auto gather_C = [&](int gy, unsigned x, C* f, C* g, C* h) {
+    const size_t N = opaque((size_t)p.N);
+    const unsigned xs = x * sizeof(S), xsm = colm(x) * sizeof(S), xsp = colp(x) * sizeof(S);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      f[i] = pull_row<S, C, WALLS, 0>(p, Pin, N, i, gy, xsm, xs, xsp);
+      g[i] = i ? pull_row<S, C, WALLS, 1>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
+      h[i] = (i && p.surf) ? pull_row<S, C, WALLS, 2>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
+    }
+  };
+  auto row_C = [&](int gy, int ln, unsigned x, C* f, C* g, C* h) {
     const size_t row = (size_t)gy * p.nx;
-    // An opaque copy of N per row keeps the compiler from hoisting the 27 plane
-    // offsets (and everything derived from them) out of the row loop into registers.
+    const int lc = min(max(ln, 2), kStripW + 1);   // halo lanes compute a copy and store nothing
+    const bool interior = is_interior(ln);
+    const unsigned xs = x * sizeof(S), xd = x * sizeof(double), xc = x * sizeof(C);
+    // rho is affine in phi: grad rho = (d rho / d phi) grad phi (ghost values included)
+    const double drho = (p.rho_l - p.rho_g) * 0.5 * p.inv_phib;
+    // An opaque copy of N and of the rates per row keeps the compiler from
+    // hoisting the plane offsets and converted constants out of the sweep
+    // loop into registers.
     const size_t N = opaque((size_t)p.N);
     const double lam1 = opaque_v(lam1_), mub1 = opaque_v(mub1_);
     double rf[5], rg[5], rh[5];
@@ -627,29 +597,26 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
       rg[k] = opaque(p.sg[k]);
       rh[k] = opaque(p.sh[k]);
     }
-    const int cy = ty + 2, cx = tx + 2;   // in sPP
-    const double2 c = sPP[cy][cx];
+    const double2 c = sPP[gy & (RP - 1)][lc];
     const double ph = c.x, ps = c.y;
-    const double2 mc = sMU[ty + 1][tx + 1];
+    const double2 mc = sMU[gy & (RM - 1)][lc];
     const double ph0 = *byte_at(ref + row, xd);   // phi(n-1)
 
-    C f[9], g[9], h[9];
+    // pending multiplier terms of the gathered g_i, h_i
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      f[i] = pull_row<S, C, WALLS, 0>(p, Pin, N, i, gy, xm, xs, xp);
-      if (i == 0) { g[0] = C(0); h[0] = C(0); continue; }
+    for (int i = 1; i < 9; ++i) {
       const int sy = gy - CY(i);
       const bool bb = WALLS && (sy < 0 || sy >= p.ny);
-      const C hpe = bb ? sHp[ty + 3][tx + 3] : sHp[ty + 3 - CY(i)][tx + 3 - CX(i)];
-      g[i] = pull_row<S, C, WALLS, 1>(p, Pin, N, i, gy, xm, xs, xp) + (C)(lam1 * WQ<double>(i) * (double)hpe);
-      h[i] = p.surf ? pull_row<S, C, WALLS, 2>(p, Pin, N, i, gy, xm, xs, xp) + (C)(mub1 * WQ<double>(i)) : C(0);
+      const C hpe = bb ? sHp[gy & (RP - 1)][lc + 1] : sHp[(gy - CY(i)) & (RP - 1)][lc + 1 - CX(i)];
+      g[i] += (C)(lam1 * WQ<double>(i) * (double)hpe);
+      if (p.surf) h[i] += (C)(mub1 * WQ<double>(i));
     }
     // gradients of phi (wetting ghosts), mu_phi, mu_psi; Laplacians of phi, psi
     double gfx = 0, gfy = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0, l0p = 0, l0s = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const double w3 = 3.0 * WQ<double>(i), w2 = 2.0 * w3;
-      const double2 nb = sPP[cy + CY(i)][cx + CX(i)];
+      const double2 nb = sPP[(gy + CY(i)) & (RP - 1)][lc + CX(i)];
       const int ny_ = gy + CY(i);
       double q = nb.x;
       if (WALLS && (ny_ < 0 || ny_ >= p.ny) && wet_side(p, ny_ < 0 ? -1 : 1)) q += Jphi(p, nb.x, nb.y) / p.kappa;
@@ -657,7 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
       l0s += w2 * (nb.y - ps);
       if (CX(i)) gfx += (CX(i) * w3) * q;
       if (CY(i)) gfy += (CY(i) * w3) * q;
-      const double2 mn = sMU[ty + 1 + CY(i)][tx + 1 + CX(i)];
+      const double2 mn = sMU[(gy + CY(i)) & (RM - 1)][lc + CX(i)];
       if (CX(i)) { gpx += (CX(i) * w3) * mn.x; gsx += (CX(i) * w3) * mn.y; }
       if (CY(i)) { gpy += (CY(i) * w3) * mn.x; gsy += (CY(i) * w3) * mn.y; }
     }
@@ -717,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
         C v = o[i];
         if (wb && CY(i) < 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_bottom);
         if (wt && CY(i) > 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_top);
-        if (active) stream_store(byte_at(Pout + (size_t)i * N + row, xs), (S)v);
+        if (interior) stream_store(byte_at(Pout + (size_t)i * N + row, xs), (S)v);
       }
     }
     {
@@ -725,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
       collide_scalar<C>(g, (C)ph, (C)p.eta_phi, (C)vx, (C)vy, (C)dpx, (C)dpy, (C)Rtp, rg, o);
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        if (active) stream_store(byte_at(Pout + (size_t)(9 + i) * N + row, xs), (S)o[i]);
+        if (interior) stream_store(byte_at(Pout + (size_t)(9 + i) * N + row, xs), (S)o[i]);
     }
     {
       C o[9];
@@ -736,9 +703,9 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
       }
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        if (active) stream_store(byte_at(Pout + (size_t)(18 + i) * N + row, xs), (S)o[i]);
+        if (interior) stream_store(byte_at(Pout + (size_t)(18 + i) * N + row, xs), (S)o[i]);
     }
-    if (active) {
+    if (interior) {
       C* ho = hout + row;
       stream_store(byte_at(ho, xc), (C)ux);
       stream_store(byte_at(ho + N, xc), (C)uy);
@@ -747,6 +714,37 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
       stream_store(byte_at(ho + 4 * N, xc), (C)Rp0);
       stream_store(byte_at(ho + 5 * N, xc), (C)Rs0);
     }
+  };
+
+  // ---- the sweep.  Iteration k collides rows Y0+4k .. Y0+4k+3 (k = -1 only
+  // fills the rings).  Ring lifetimes: H writes rows <= 15 ahead of the oldest
+  // h' row C still reads; A writes <= 10 rows ahead of the oldest (phi, psi)
+  // row C reads; B's writes follow the barrier after every wave's C.
+#pragma unroll 1
+  for (int j = wave; j < 10; j += NWAVE) row_H(Y0 - 3 + j, lane, xcol);   // rows Y0-3 .. Y0+6
+  __syncthreads();
+#pragma unroll 1
+  for (int k = -1; 4 * k < Yend - Y0; ++k) {
+    const int ln = opaque_v(lane);
+    const unsigned x = opaque_v(xcol);
+    const int rc = wave_uniform(Y0 + 4 * k + wave);
+    const bool collide = k >= 0 && rc < Yend;
+    C f[9], g[9], h[9];
+    if (collide) gather_C(rc, x, f, g, h);   // in flight during H, A, B and the barriers
+    if (k >= 0) row_H(Y0 + 4 * k + 7 + wave, ln, x);
+    row_A(Y0 + 4 * k + 2 + wave, ln, x);
+    __syncthreads();
+    if (k >= 0 || wave >= 2) row_B(Y0 + 4 * k + 1 + wave, ln);   // k = -1: rows Y0-1 and Y0 only
+    __syncthreads();
+    if (collide) row_C(rc, ln, x, f, g, h);
+  }
+  s1 = block_reduce(s1, false);
+  s2 = block_reduce(s2, false);
+  s3 = block_reduce(s3, false);
+  if (threadIdx.x == 0) {
+    a.partials[3 * (size_t)tile + 0] = s1;
+    a.partials[3 * (size_t)tile + 1] = s2;
+    a.partials[3 * (size_t)tile + 2] = s3;
   }
 }
 
@@ -1034,11 +1032,8 @@ hipError_t macro_impl(const DevParams& p, DevState& s, hipStream_t st) {
   return hipGetLastError();
 }
 
-inline int tiles_x(const DevParams& p) { return (p.nx + kTileX - 1) / kTileX; }
-inline int tiles(const DevParams& p, int ty) { return tiles_x(p) * ((p.ny + ty - 1) / ty); }
-
-template <class S, class C, int TY>
-void launch_fused(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* t) {
+template <class S, class C>
+void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* t) {
   StepArgs a;
   a.Pin = s.pops[s.cur];
   a.Pout = s.pops[s.cur ^ 1];
@@ -1050,12 +1045,13 @@ void launch_fused(const DevParams& p, DevState& s, int have_hist, hipStream_t st
   a.next = s.scalars + (s.scur ^ 1);
   a.partials = s.partials;
   a.have_hist = have_hist;
-  a.ntx = tiles_x(p);
-  a.ntiles = tiles(p, TY);
+  a.nstrips = (p.nx + kStripW - 1) / kStripW;
+  a.seg_rows = s.tile_rows;
+  a.ntiles = (int)step_blocks(p.nx, p.ny, s.tile_rows);
   {
     TimedScope ts(t, LBM_K_STEP, st);
-    if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, TY, false>), dim3(a.ntiles), dim3(kBlock), 0, st, p, a);
-    else hipLaunchKernelGGL((k_step<S, C, TY, true>), dim3(a.ntiles), dim3(kBlock), 0, st, p, a);
+    if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false>), dim3(a.ntiles), dim3(kBlock), 0, st, p, a);
+    else hipLaunchKernelGGL((k_step<S, C, true>), dim3(a.ntiles), dim3(kBlock), 0, st, p, a);
   }
   {
     TimedScope ts(t, LBM_K_FINISH, st);
@@ -1067,11 +1063,7 @@ void launch_fused(const DevParams& p, DevState& s, int have_hist, hipStream_t st
 template <class S, class C>
 hipError_t step_impl(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer) {
   StepTimer* t = (timer && timer->ev && timer->used < timer->max_steps) ? timer : nullptr;
-  switch (s.tile_rows) {
-    case 4: launch_fused<S, C, 4>(p, s, have_hist, st, t); break;
-    case 8: launch_fused<S, C, 8>(p, s, have_hist, st, t); break;
-    default: launch_fused<S, C, 16>(p, s, have_hist, st, t); break;
-  }
+  launch_step<S, C>(p, s, have_hist, st, t);
   if (t) t->used += 1;
   s.cur ^= 1;
   s.hcur ^= 1;
@@ -1120,15 +1112,17 @@ hipError_t pops_impl(const DevParams& p, DevState& s, hipStream_t st) {
 }  // namespace
 
 size_t storage_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2); }
-size_t fused_tiles(int nx, int ny, int tile_rows) {
-  return (size_t)((nx + kTileX - 1) / kTileX) * (size_t)((ny + tile_rows - 1) / tile_rows);
+size_t step_blocks(int nx, int ny, int seg_rows) {
+  return (size_t)((nx + kStripW - 1) / kStripW) * (size_t)((ny + seg_rows - 1) / seg_rows);
 }
-// Tile height from measurements on MI355X: small grids want many workgroups
-// (4 rows); large FP32 grids run best at 8 rows, large FP64 grids at 16 (the
-// halo work per node shrinks with the height; occupancy falls with it).
-int fused_tile_rows(int nx, int ny, int precision) {
-  if (precision == LBM_FP64) return fused_tiles(nx, ny, 16) >= 2048 ? 16 : 4;
-  return fused_tiles(nx, ny, 8) >= 4096 ? 8 : 4;
+// Rows per workgroup segment: long segments amortise the four extra phi/psi
+// rows and two extra mu rows each segment computes, but a grid needs enough
+// workgroups to fill the chip (on MI355X: best at 4096^2 with 32 rows, about
+// 8800 workgroups; small grids want the most workgroups, 4 rows).
+int step_seg_rows(int nx, int ny) {
+  int seg = 64;
+  while (seg > 4 && step_blocks(nx, ny, seg) < 8192) seg /= 2;
+  return seg;
 }
 size_t compute_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 
