@@ -147,7 +147,10 @@ int lbm_required_bytes(const lbm_params* p, size_t* bytes);
 int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_stream, lbm_handle** out);
 
 /* Enqueue n time steps (n >= 0).  Asynchronous: returns once the work is on
- * the stream.  Faults in the fields surface at the next synchronising call. */
+ * the stream.  Faults in the fields surface at the next synchronising call.
+ * Runs of 32 steps are replayed from a HIP graph the handle captures on first
+ * use (same kernels, same results bit for bit); steps while kernel timing is
+ * active are launched one by one. */
 int lbm_step(lbm_handle* h, int64_t n);
 
 /* Diagnostics of the current state (FP64 sums on the device), then one small

@@ -157,6 +157,8 @@ struct lbm_handle {
   bool faulted = false;
   double derived[LBM_N_DERIVED];
   lbm::StepTimer timer;
+  hipGraphExec_t graph = nullptr;  // kGraphSteps steps captured from buffer parity graph_parity
+  int graph_parity = 0;
   std::string err = "no error";
 };
 
@@ -268,14 +270,52 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
   return LBM_OK;
 }
 
+// Runs of steps are replayed from a captured HIP graph of kGraphSteps steps
+// (an even count, so the ping-pong buffers end where they started): one graph
+// launch instead of 2 kGraphSteps kernel launches.  Steps while kernel timing
+// is on, the first step (no history yet) and remainders run eagerly.
+constexpr int64_t kGraphSteps = 32;
+
+int capture_graph(lbm_handle* h) {
+  lbm::DevState s = h->ds;  // the capture advances a copy's buffer parity
+  hipGraph_t g = nullptr;
+  HIP_OR_FAIL(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "begin graph capture");
+  hipError_t e = hipSuccess;
+  for (int64_t k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = lbm::launch_step(h->dp, s, 1, h->stream, nullptr);
+  const hipError_t e_end = hipStreamEndCapture(h->stream, &g);
+  if (e == hipSuccess) e = e_end;
+  if (e == hipSuccess) e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->graph = nullptr;
+    return hip_fail(h, e, "graph capture of the step kernels");
+  }
+  h->graph_parity = h->ds.cur;
+  return LBM_OK;
+}
+
 int lbm_step(lbm_handle* h, int64_t n) {
   if (!h) return fail(nullptr, LBM_E_ARG, "null handle");
   if (n < 0) return fail(h, LBM_E_ARG, "negative step count");
   if (h->faulted) return fail(h, LBM_E_STATE, "state holds non-finite or out-of-range values; load a state or fields first");
-  for (int64_t k = 0; k < n; ++k) {
+  int64_t k = 0;
+  while (k < n) {
+    const bool timing = h->timer.ev && h->timer.used < h->timer.max_steps;
+    if (!timing && h->have_hist && n - k >= kGraphSteps && h->ds.cur == h->ds.hcur && h->ds.cur == h->ds.scur &&
+        (!h->graph || h->ds.cur == h->graph_parity)) {
+      if (!h->graph) {
+        const int rc = capture_graph(h);
+        if (rc) return rc;
+      }
+      HIP_OR_FAIL(h, hipGraphLaunch(h->graph, h->stream), "graph launch");
+      h->step += kGraphSteps;
+      k += kGraphSteps;
+      continue;
+    }
     HIP_OR_FAIL(h, lbm::launch_step(h->dp, h->ds, h->have_hist, h->stream, &h->timer), "step kernels");
     h->have_hist = 1;
     h->step += 1;
+    k += 1;
   }
   return LBM_OK;
 }
@@ -487,6 +527,7 @@ int lbm_destroy(lbm_handle* h) {
   if (!h) return LBM_OK;
   release_timer(h);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
   if (h->own_buf && h->buf) (void)hipFree(h->buf);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;

@@ -191,6 +191,26 @@ def test_deterministic_and_checkpoint_restart(lbm):
             assert np.array_equal(fa[k], fc[k]), (prec, k)
 
 
+def test_graph_replay_matches_eager(lbm):
+    """lbm_step(n) with n >= 32 replays a captured graph of 32 steps: the state
+    must equal, bit for bit, that of single eager steps, over several replays
+    with other device work (invariants, field fetches) between them, and after
+    an odd number of steps (the other buffer parity)."""
+    for cfg in (inputs.sessile_drop(nx=96, ny=48, R=16.0), inputs.stationary_drop()):
+        for prec in ("fp32", "fp64"):
+            a = lbm.Sim(cfg, prec)
+            b = lbm.Sim(cfg, prec)
+            for rep, n in enumerate((1, 64, 32, 33, 70, 40)):
+                a.step(n)
+                for _ in range(n):
+                    b.step(1)
+                fa, fb = a.fields(FIELDS), b.fields(FIELDS)
+                for k in FIELDS:
+                    assert np.array_equal(fa[k], fb[k]), (prec, rep, k)
+                ia, ib = a.invariants(), b.invariants()
+                assert ia["mass_psi"] == ib["mass_psi"] and ia["lambda_phi"] == ib["lambda_phi"]
+
+
 def test_error_paths(lbm):
     cfg = inputs.stationary_drop(nx=32, ny=32, R=8.0)
     g = lbm.Sim(cfg, "fp64")
