@@ -13,8 +13,10 @@ Prints one JSON line.  The FP64 CPU oracle is timed beside it on the host
 (bounded sample) as cpu_baseline.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -46,7 +48,30 @@ def gpu_run(cfg, precision, steps, warmup, kernel_steps):
     return dict(sim=sim, wall=wall, kernels=kt, N=N, inv=inv, bytes_node=sim.bytes_per_node_step())
 
 
-def roofline(res):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_26332_amd", "csrc", "lbm_kernels.hip")
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's
+    readings), or None when that summary was taken on other kernel source."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    if not m or m.group(1) != src:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*(.*)", text)
+    if not m:
+        return None
+    vals = dict(kv.split("=") for kv in m.group(1).replace(",", " ").split())
+    return float(vals[key]) if key in vals else None
+
+
+def roofline(res, key):
     """Achieved HBM bandwidth of the dominant kernel (the fused step kernel,
     which moves all of a step's algorithmic bytes) on those bytes, from its
     HIP-event durations on the stream it runs on."""
@@ -57,10 +82,22 @@ def roofline(res):
     achieved = bytes_launch / (dom_ms * 1e-3) / 1e9
     return {
         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(key),
         "kernel": dom, "bytes_per_node_step": res["bytes_node"], "nodes_per_launch": res["N"],
         "kernel_ms_per_launch": {k: round(v[0] / max(v[1], 1), 5) for k, v in kt.items()},
     }
+
+
+def copy_calibration():
+    import torch
+
+    x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "copies": 5}))
 
 
 def cpu_baseline(cfg, budget_s=15.0):
@@ -91,13 +128,25 @@ def main():
     ap.add_argument("--large-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--workload", default="both", choices=["both", "sessile", "large"],
+                    help="profiling aid: run one of the two workloads only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="profiling aid: five device copies of 1 GiB (the reference for the HBM byte counters), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on sharding)",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     from paper_2609_26332_amd import inputs
 
+    if args.workload == "large":
+        big = inputs.roofline_grid()
+        rb = gpu_run(big, args.precision, args.large_steps, 10, args.large_steps)
+        print(json.dumps({"workload": "periodic drop 4096x4096", "roofline": roofline(rb, "large_" + args.precision)}))
+        return
     cfg = inputs.sessile_drop()
     res = gpu_run(cfg, args.precision, args.steps, args.warmup, min(args.steps, 2000))
     mlups = res["N"] * args.steps / res["wall"] / 1e6
@@ -105,23 +154,24 @@ def main():
         "metric": "MLUPS (3 coupled lattices) + HBM roofline %",
         "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(res["wall"] * 1e3 / args.steps, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "sessile drop on adsorbing solid, 256x128 D2Q9, FP32 storage, FP64 reductions",
+        "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "sessile drop on adsorbing solid, 256x128 D2Q9, %s storage, FP64 reductions"
+                               % args.precision.upper(),
                    "nx": cfg["nx"], "ny": cfg["ny"], "theta0_deg": cfg["theta0_deg"], "psi_b": cfg["psi_b"],
                    "beta_sg": round(cfg["beta_sg"], 6), "precision": args.precision},
         "lattice_mlups": round(3 * mlups, 2),
-        "roofline": roofline(res),
+        "roofline": roofline(res, "sessile_" + args.precision),
     }
     if res["inv"]["nonfinite"]:
         out["warning"] = "non-finite fields after the timed run"
-    if not args.no_large:
+    if not args.no_large and args.workload == "both":
         big = inputs.roofline_grid()
         rb = gpu_run(big, args.precision, args.large_steps, 10, args.large_steps)
-        rl = roofline(rb)
+        rl = roofline(rb, "large_" + args.precision)
         out["large_grid"] = {"workload": "periodic drop 4096x4096 (state beyond the on-die caches)",
                              "mlups": round(rb["N"] * args.large_steps / rb["wall"] / 1e6, 1), "roofline": rl}
         del rb
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "both":
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
 
