@@ -45,7 +45,7 @@ Layout make_layout(const lbm_params& p) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
-  L.pops = take(2 * 27 * N * sb);
+  L.pops = take(2 * lbm::pops_bytes(p.precision, N));
   L.phipsi = take(2 * 2 * N * sizeof(double));  // phi, psi: FP64 in every precision
   L.mu = take(2 * N * sizeof(double));
   L.uhist = take(2 * 6 * N * cb);  // u, v (advecting), R_phi, R_psi history, ping-pong
@@ -186,7 +186,7 @@ void carve(lbm_handle* h) {
   lbm::DevState& s = h->ds;
   s.precision = h->prm.precision;
   s.pops[0] = b + L.pops;
-  s.pops[1] = b + L.pops + 27 * N * sb;
+  s.pops[1] = b + L.pops + lbm::pops_bytes(h->prm.precision, N);
   s.phipsi[0] = b + L.phipsi;
   s.phipsi[1] = b + L.phipsi + 2 * N * sizeof(double);
   s.mu = b + L.mu;
@@ -237,7 +237,6 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
   h->prm = *p;
   std::string why = derive(*p, h->dp, h->derived);
   if (!why.empty()) { delete h; return fail(nullptr, LBM_E_ARG, why); }
-  if (p->precision == LBM_FP16_SHIFTED) { delete h; return fail(nullptr, LBM_E_UNSUPPORTED, "FP16 shifted storage is not built in this version"); }
   int dc = check_device(why);
   if (dc != LBM_OK) { delete h; return fail(nullptr, dc, why); }
   h->lay = make_layout(*p);
@@ -397,7 +396,7 @@ int lbm_state_bytes(lbm_handle* h, size_t* bytes) {
   if (!h || !bytes) return fail(h, LBM_E_ARG, "null argument");
   const size_t N = (size_t)h->dp.N;
   const size_t sb = lbm::storage_bytes(h->prm.precision), cb = lbm::compute_bytes(h->prm.precision);
-  *bytes = sizeof(StateHeader) + 27 * N * sb + 2 * N * sizeof(double) + 6 * N * cb;
+  *bytes = sizeof(StateHeader) + lbm::pops_bytes(h->prm.precision, N) + 2 * N * sizeof(double) + 6 * N * cb;
   return LBM_OK;
 }
 
@@ -415,8 +414,8 @@ int lbm_save_state(lbm_handle* h, void* host, size_t bytes) {
   std::memcpy(o, &hd, sizeof(hd));
   o += sizeof(hd);
   const int hp = h->ds.hcur ^ 1;  // history written by the last step
-  HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.pops[h->ds.cur], 27 * N * sb, hipMemcpyDeviceToHost, h->stream), "save");
-  o += 27 * N * sb;
+  HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.pops[h->ds.cur], lbm::pops_bytes(h->prm.precision, N), hipMemcpyDeviceToHost, h->stream), "save");
+  o += lbm::pops_bytes(h->prm.precision, N);
   HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.phipsi[hp], 2 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream), "save");
   o += 2 * N * sizeof(double);
   HIP_OR_FAIL(h, hipMemcpyAsync(o, h->ds.uhist[hp], 6 * N * cb, hipMemcpyDeviceToHost, h->stream), "save");
@@ -438,8 +437,8 @@ int lbm_load_state(lbm_handle* h, const void* host, size_t bytes) {
   const size_t sb = lbm::storage_bytes(h->prm.precision), cb = lbm::compute_bytes(h->prm.precision);
   const char* o = (const char*)host + sizeof(hd);
   const int hp = h->ds.hcur ^ 1;
-  HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.pops[h->ds.cur], o, 27 * N * sb, hipMemcpyHostToDevice, h->stream), "load");
-  o += 27 * N * sb;
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.pops[h->ds.cur], o, lbm::pops_bytes(h->prm.precision, N), hipMemcpyHostToDevice, h->stream), "load");
+  o += lbm::pops_bytes(h->prm.precision, N);
   HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.phipsi[hp], o, 2 * N * sizeof(double), hipMemcpyHostToDevice, h->stream), "load");
   o += 2 * N * sizeof(double);
   HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.uhist[hp], o, 6 * N * cb, hipMemcpyHostToDevice, h->stream), "load");
@@ -518,8 +517,10 @@ int lbm_bytes_per_node_step(lbm_handle* h, double* bytes) {
   const double sb = (double)lbm::storage_bytes(h->prm.precision), cb = (double)lbm::compute_bytes(h->prm.precision);
   const double planes_s = h->dp.surf ? 27.0 : 18.0;     // h lattice idle without surfactant
   const double fp64_planes = h->dp.surf ? 2.0 : 1.0;    // phi (and psi) reference planes
+  // FP16 storage keeps the rest populations of g and h in FP32 planes
+  const double pops = h->prm.precision == LBM_FP16_SHIFTED ? (planes_s - fp64_planes) * sb + fp64_planes * 4.0 : planes_s * sb;
   // read + write of: populations, FP64 phi/psi, velocity/advecting-velocity history (4), source history (2)
-  *bytes = 2.0 * (planes_s * sb + fp64_planes * 8.0 + 4.0 * cb + 2.0 * cb);
+  *bytes = 2.0 * (pops + fp64_planes * 8.0 + 4.0 * cb + 2.0 * cb);
   return LBM_OK;
 }
 

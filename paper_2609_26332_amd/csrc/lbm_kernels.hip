@@ -35,6 +35,8 @@
 // No MFMA: the step moves ~300 B/node in FP32 storage and does ~1.3k VALU
 // operations per node, no dense contraction; HBM bandwidth bounds it.
 
+#include <type_traits>
+
 #include "lbm_internal.h"
 #include "../../include/lbm.h"
 
@@ -53,6 +55,61 @@ __host__ __device__ constexpr int MIRY(int i) { return i == 2 ? 4 : i == 4 ? 2 :
 template <class C> __device__ __forceinline__ constexpr C WQ(int i) { return i == 0 ? C(4.0 / 9.0) : (i <= 4 ? C(1.0 / 9.0) : C(1.0 / 36.0)); }
 static_assert(OPP(1) == 3 && OPP(2) == 4 && OPP(3) == 1 && OPP(4) == 2, "opp");
 static_assert(OPP(5) == 7 && OPP(6) == 8 && OPP(7) == 5 && OPP(8) == 6, "opp");
+
+// ------------------------------------------------------------ storage codec
+// FP16 ("shifted") storage keeps each population as its deviation from the
+// u-independent part of its equilibrium at the node that wrote it, scaled by
+// 2^10 into FP16's normal range: f_i (pressure based, already near zero) as
+// f_i 2^10; g_i as (g_i - wt_i phi(z)) 2^10 with wt_0 = 1 - (1 - w_0) eta_phi
+// and wt_i = w_i eta_phi, the rest-state equilibrium of Sec. 3; h_i likewise
+// with psi and eta_psi.  The reference phi(z), psi(z) is the FP64 plane the
+// writing step outputs, rounded to FP32 identically by writer and reader.
+// Decoding returns the FP32/FP64 storage convention: the rest populations of
+// g and h less phi (psi) of their own node, moving populations as they are.
+// FP32 and FP64 storage encode and decode as the identity.
+// Rounding to FP16 is coherent where the fields are uniform (every bulk node
+// rounds the same deviation the same way), which would drift the phi and psi
+// masses linearly in time.  So in FP16 storage the rest populations of g and h
+// live in two FP32 planes (after the 27 FP16 planes), in the FP32 convention,
+// and each writing node adds to its rest value the FP16 rounding residuals of
+// its eight moving populations: what a node stores then decodes to exactly its
+// post-collision zeroth moment (to FP32 rounding), and the masses are conserved.
+template <class S> inline constexpr bool kHalf = std::is_same<S, _Float16>::value;
+constexpr float kHalfScale = 1024.0f, kHalfInv = 1.0f / 1024.0f;
+__host__ __device__ constexpr size_t rest_offset(size_t N) { return (27 * N * 2 + 255) / 256 * 256; }   // bytes
+// FP32 rest plane of lattice lat (1 = g, 2 = h) in an FP16 population buffer
+__device__ __forceinline__ float* rest_plane(void* P, size_t N, int lat) {
+  return (float*)((char*)P + rest_offset(N)) + (size_t)(lat - 1) * N;
+}
+__device__ __forceinline__ const float* rest_plane(const void* P, size_t N, int lat) {
+  return (const float*)((const char*)P + rest_offset(N)) + (size_t)(lat - 1) * N;
+}
+
+// v: population in the FP32 convention; c: reference (phi or psi) of the writing node
+template <class S, class C>
+__device__ __forceinline__ S encode(const DevParams& p, int lat, int i, C v, C c) {
+  if constexpr (kHalf<S>) {
+    if (lat == 0) return (S)(v * kHalfScale);
+    const C eta = (C)(lat == 1 ? p.eta_phi : p.eta_psi);
+    const C shift = i == 0 ? C(1.0 - 4.0 / 9.0) * eta * c : -WQ<C>(i) * eta * c;
+    return (S)((v + shift) * kHalfScale);
+  } else {
+    return (S)v;
+  }
+}
+// t: stored value; c: reference of the node that wrote it (the emitter; the
+// node itself for i = 0 and at a bounce-back)
+template <class S, class C>
+__device__ __forceinline__ C decode(const DevParams& p, int lat, int i, S t, C c) {
+  if constexpr (kHalf<S>) {
+    const C v = (C)t * kHalfInv;
+    if (lat == 0) return v;
+    const C eta = (C)(lat == 1 ? p.eta_phi : p.eta_psi);
+    return i == 0 ? v - C(1.0 - 4.0 / 9.0) * eta * c : v + WQ<C>(i) * eta * c;
+  } else {
+    return (C)t;
+  }
+}
 
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
@@ -75,16 +132,28 @@ __device__ __forceinline__ bool wet_side(const DevParams& p, int side) { return 
 // specular image that left x - (c_x, 0).  For i = 0 of g and h this is the
 // shifted value g_0 - phi(n) (h_0 - psi(n)).
 template <class S, class C>
-__device__ __forceinline__ C pull(const DevParams& p, const S* __restrict__ P, int lat, int i, int x, int y) {
+__device__ __forceinline__ C pull(const DevParams& p, const S* __restrict__ P, int lat, int i, int x, int y,
+                                  const double* __restrict__ ref) {
   const size_t N = (size_t)p.N;
   int sx = wrap(x - CX(i), p.nx), sy = y - CY(i);
+  size_t at, em;   // element read and the node that wrote it
   if (p.periodic_y) sy = wrap(sy, p.ny);
-  else if (sy < 0 || sy >= p.ny) {
-    int bc = sy < 0 ? p.bc_bottom : p.bc_top;
-    if (lat == 0 && bc == LBM_BC_FREESLIP) return (C)P[(size_t)(9 * lat + MIRY(i)) * N + (size_t)y * p.nx + sx];
-    return (C)P[(size_t)(9 * lat + OPP(i)) * N + (size_t)y * p.nx + x];
+  if (!p.periodic_y && (sy < 0 || sy >= p.ny)) {
+    const int bc = sy < 0 ? p.bc_bottom : p.bc_top;
+    em = (size_t)y * p.nx + x;
+    if (lat == 0 && bc == LBM_BC_FREESLIP) at = (size_t)(9 * lat + MIRY(i)) * N + (size_t)y * p.nx + sx;
+    else at = (size_t)(9 * lat + OPP(i)) * N + em;
+  } else {
+    em = (size_t)sy * p.nx + sx;
+    at = (size_t)(9 * lat + i) * N + em;
   }
-  return (C)P[(size_t)(9 * lat + i) * N + (size_t)sy * p.nx + sx];
+  if constexpr (kHalf<S>) {
+    if (lat > 0 && i == 0) return (C)rest_plane(P, N, lat)[em];
+    const C c = lat ? (C)ref[(size_t)(lat - 1) * N + em] : C(0);
+    return decode<S, C>(p, lat, i, P[at], c);
+  } else {
+    return (C)P[at];
+  }
 }
 
 // ------------------------------------------------------------------- physics
@@ -232,13 +301,13 @@ __global__ __launch_bounds__(kBlock) void k_moments(DevParams p, const S* __rest
   double corr = 0.0;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    a += pull<S, C>(p, P, 1, i, x, y);
+    a += pull<S, C>(p, P, 1, i, x, y, prev);
     corr += WQ<double>(i) * hprime(p, prev[emitter(p, i, x, y)]);
   }
   phipsi[n] = prev[n] + (double)a + lam * corr;
   if (p.surf) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) b += pull<S, C>(p, P, 2, i, x, y);
+    for (int i = 0; i < 9; ++i) b += pull<S, C>(p, P, 2, i, x, y, prev);
     phipsi[(size_t)p.N + n] = prev[(size_t)p.N + n] + (double)b + pend->cdef * p.M_psi * pend->mubar_psi;
   } else {
     phipsi[(size_t)p.N + n] = 0.0;
@@ -416,6 +485,9 @@ __device__ __forceinline__ C pull_row(const DevParams& p, const S* __restrict__ 
     if constexpr (lat == 0) return (C)__builtin_nontemporal_load(q);
     else return (C)*q;
   };
+  if constexpr (kHalf<S> && lat > 0) {
+    if (i == 0) return (C)*byte_at(rest_plane(P, N, lat) + (size_t)y * p.nx, 2 * b0);
+  }
   const unsigned sb = CX(i) > 0 ? bm : (CX(i) < 0 ? bp : b0);
   int sy = y - CY(i);
   if (!WALLS) {
@@ -468,6 +540,8 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
   __shared__ C sHp[RP][kStripW + 6];       // h'(phi(n-1)), columns X0-3 .. X0+62
   __shared__ double2 sPP[RP][64];          // (phi, psi)(n), columns X0-2 .. X0+61
   __shared__ double2 sMU[RM][64];          // (mu_phi, mu_psi), columns X0-2 .. X0+61 (lanes 1..62 used)
+  constexpr bool H16 = kHalf<S>;
+  __shared__ float2 sRef[H16 ? RP : 1][H16 ? kStripW + 6 : 1];   // FP16 storage: (phi, psi)(n-1) as in sHp
 
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int X0 = (tile % a.nstrips) * kStripW, Y0 = (tile / a.nstrips) * a.seg_rows;
@@ -497,10 +571,14 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
   // the outer columns X0-3 and X0+62
   auto row_H = [&](int gy, int ln, unsigned x) {
     const double* r = ref + (size_t)row_of(gy) * p.nx;
-    sHp[gy & (RP - 1)][ln + 1] = (C)hprime(p, *byte_at(r, x * (unsigned)sizeof(double)));
+    const double ph = *byte_at(r, x * (unsigned)sizeof(double));
+    sHp[gy & (RP - 1)][ln + 1] = (C)hprime(p, ph);
+    if constexpr (H16) sRef[gy & (RP - 1)][ln + 1] = make_float2((float)ph, (float)*byte_at(r + N, x * (unsigned)sizeof(double)));
     if (ln < 2) {
       const int k = ln ? kStripW + 5 : 0;
-      sHp[gy & (RP - 1)][k] = (C)hprime(p, r[modp(X0 - 3 + k, p.nx)]);
+      const unsigned xk = (unsigned)modp(X0 - 3 + k, p.nx);
+      sHp[gy & (RP - 1)][k] = (C)hprime(p, r[xk]);
+      if constexpr (H16) sRef[gy & (RP - 1)][k] = make_float2((float)r[xk], (float)r[N + xk]);
     }
   };
 
@@ -509,21 +587,35 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
     const int y = wave_uniform(row_of(gy)), yc = centre(gy);
     const unsigned xs = x * sizeof(S), xsm = colm(x) * sizeof(S), xsp = colp(x) * sizeof(S), xd = x * sizeof(double);
     C sg = C(0), sh = C(0), corr = C(0);
+    const size_t row = (size_t)y * p.nx;
+    const double r0 = *byte_at(ref + row, xd), s0 = *byte_at(ref + N + row, xd);   // phi, psi(n-1) here
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      sg += pull_row<S, C, WALLS, 1>(p, Pin, N, i, y, xsm, xs, xsp);
       // emitter of g_i: x - c_i, or the node itself at a wall
       const int sy = y - CY(i);
       const bool bb = WALLS && (sy < 0 || sy >= p.ny);
-      corr += WQ<C>(i) * (bb ? sHp[yc & (RP - 1)][ln + 1] : sHp[(yc - CY(i)) & (RP - 1)][ln + 1 - CX(i)]);
+      const int er = bb ? yc & (RP - 1) : (yc - CY(i)) & (RP - 1), ec = bb ? ln + 1 : ln + 1 - CX(i);
+      const C t = pull_row<S, C, WALLS, 1>(p, Pin, N, i, y, xsm, xs, xsp);
+      if constexpr (H16) sg += i ? decode<S, C>(p, 1, i, (S)t, (C)sRef[er][ec].x) : t;   // rest: FP32 plane
+      else sg += t;
+      corr += WQ<C>(i) * sHp[er][ec];
     }
-    const size_t row = (size_t)y * p.nx;
-    const double ph = *byte_at(ref + row, xd) + (double)sg + lam1_ * (double)corr;
+    const double ph = r0 + (double)sg + lam1_ * (double)corr;
     double ps = 0.0;
     if (p.surf) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) sh += pull_row<S, C, WALLS, 2>(p, Pin, N, i, y, xsm, xs, xsp);
-      ps = *byte_at(ref + N + row, xd) + (double)sh + mub1_;
+      for (int i = 0; i < 9; ++i) {
+        const C t = pull_row<S, C, WALLS, 2>(p, Pin, N, i, y, xsm, xs, xsp);
+        if constexpr (H16) {
+          const int sy = y - CY(i);
+          const bool bb = WALLS && (sy < 0 || sy >= p.ny);
+          const int er = bb ? yc & (RP - 1) : (yc - CY(i)) & (RP - 1), ec = bb ? ln + 1 : ln + 1 - CX(i);
+          sh += i ? decode<S, C>(p, 2, i, (S)t, (C)sRef[er][ec].y) : t;
+        } else {
+          sh += t;
+        }
+      }
+      ps = s0 + (double)sh + mub1_;
     }
     sPP[gy & (RP - 1)][ln] = make_double2(ph, ps);
     if (is_interior(ln) && gy >= Y0 && gy < Yend) {
@@ -602,13 +694,22 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
     const double2 mc = sMU[gy & (RM - 1)][lc];
     const double ph0 = *byte_at(ref + row, xd);   // phi(n-1)
 
-    // pending multiplier terms of the gathered g_i, h_i
+    // decoded (FP16 storage) gathers plus the pending multiplier terms of g_i, h_i
+    if constexpr (H16) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = decode<S, C>(p, 0, i, (S)f[i], C(0));
+    }
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const int sy = gy - CY(i);
       const bool bb = WALLS && (sy < 0 || sy >= p.ny);
-      const C hpe = bb ? sHp[gy & (RP - 1)][lc + 1] : sHp[(gy - CY(i)) & (RP - 1)][lc + 1 - CX(i)];
-      g[i] += (C)(lam1 * WQ<double>(i) * (double)hpe);
+      const int er = bb ? gy & (RP - 1) : (gy - CY(i)) & (RP - 1), ec = bb ? lc + 1 : lc + 1 - CX(i);
+      if constexpr (H16) {
+        const float2 re = sRef[er][ec];
+        g[i] = decode<S, C>(p, 1, i, (S)g[i], (C)re.x);
+        if (p.surf) h[i] = decode<S, C>(p, 2, i, (S)h[i], (C)re.y);
+      }
+      g[i] += (C)(lam1 * WQ<double>(i) * (double)sHp[er][ec]);
       if (p.surf) h[i] += (C)(mub1 * WQ<double>(i));
     }
     // gradients of phi (wetting ghosts), mu_phi, mu_psi; Laplacians of phi, psi
@@ -684,26 +785,35 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
         C v = o[i];
         if (wb && CY(i) < 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_bottom);
         if (wt && CY(i) > 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_top);
-        if (interior) stream_store(byte_at(Pout + (size_t)i * N + row, xs), (S)v);
+        if (interior) stream_store(byte_at(Pout + (size_t)i * N + row, xs), encode<S, C>(p, 0, i, v, C(0)));
       }
     }
+    // store the populations of lattice lat (1 g, 2 h) with reference c
+    auto store_scalar = [&](int lat, const C* o, C c) {
+      if constexpr (H16) {
+        C rest = o[0];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+          const S t = encode<S, C>(p, lat, i, o[i], c);
+          rest += o[i] - decode<S, C>(p, lat, i, t, c);   // what the FP16 value loses
+          if (interior) stream_store(byte_at(Pout + (size_t)(9 * lat + i) * N + row, xs), t);
+        }
+        if (interior) stream_store(byte_at(rest_plane(Pout, N, lat) + row, 2 * xs), (float)rest);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+          if (interior) stream_store(byte_at(Pout + (size_t)(9 * lat + i) * N + row, xs), (S)o[i]);
+      }
+    };
     {
       C o[9];
       collide_scalar<C>(g, (C)ph, (C)p.eta_phi, (C)vx, (C)vy, (C)dpx, (C)dpy, (C)Rtp, rg, o);
-#pragma unroll
-      for (int i = 0; i < 9; ++i)
-        if (interior) stream_store(byte_at(Pout + (size_t)(9 + i) * N + row, xs), (S)o[i]);
+      store_scalar(1, o, (C)ph);
     }
-    {
+    if (p.surf) {   // without surfactant the h planes hold the zeros they were loaded with
       C o[9];
-      if (p.surf) collide_scalar<C>(h, (C)ps, (C)p.eta_psi, (C)vx, (C)vy, (C)dsx, (C)dsy, (C)Rts, rh, o);
-      else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) o[i] = C(0);
-      }
-#pragma unroll
-      for (int i = 0; i < 9; ++i)
-        if (interior) stream_store(byte_at(Pout + (size_t)(18 + i) * N + row, xs), (S)o[i]);
+      collide_scalar<C>(h, (C)ps, (C)p.eta_psi, (C)vx, (C)vy, (C)dsx, (C)dsy, (C)Rts, rh, o);
+      store_scalar(2, o, (C)ps);
     }
     if (interior) {
       C* ho = hout + row;
@@ -785,8 +895,11 @@ __global__ __launch_bounds__(kBlock) void k_load(DevParams p, const double* __re
   const int x = n % p.nx, y = n / p.nx;
   ref[n] = F[n];
   ref[N + n] = p.surf ? F[N + n] : 0.0;
+  using Ck = std::conditional_t<std::is_same<S, double>::value, double, float>;
 #pragma unroll
   for (int lat = 0; lat < 3; ++lat) {
+    const Ck cref = lat == 1 ? (Ck)F[n] : ((lat == 2 && p.surf) ? (Ck)F[N + n] : Ck(0));   // this node writes them
+    Ck rest = Ck(0), resid = Ck(0);
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
       // receiver node w and direction d whose gather reads stored_j(z)
@@ -807,7 +920,20 @@ __global__ __launch_bounds__(kBlock) void k_load(DevParams p, const double* __re
         v = d == 0 ? (WQ<double>(0) - 1.0) * eta * c : feq_scalar_moving(d, c, eta, c * ux, c * uy);
         if (lat == 2 && !p.surf) v = 0.0;
       }
-      P[(size_t)(9 * lat + j) * N + n] = (S)v;
+      if (kHalf<S> && lat > 0) {   // moving: FP16 with the residual kept for the FP32 rest value
+        if (j == 0) {
+          rest = (Ck)v;
+        } else {
+          const S t = encode<S, Ck>(p, lat, j, (Ck)v, cref);
+          resid += (Ck)v - decode<S, Ck>(p, lat, j, t, cref);
+          P[(size_t)(9 * lat + j) * N + n] = t;
+        }
+      } else {
+        P[(size_t)(9 * lat + j) * N + n] = encode<S, Ck>(p, lat, j, (Ck)v, cref);
+      }
+    }
+    if constexpr (kHalf<S>) {
+      if (lat > 0) rest_plane(P, N, lat)[n] = (float)(rest + resid);
     }
   }
 }
@@ -822,7 +948,7 @@ __global__ __launch_bounds__(kBlock) void k_fields(DevParams p, const S* __restr
   const int x = n % p.nx, y = n / p.nx;
   C f[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = pull<S, C>(p, P, 0, i, x, y);
+  for (int i = 0; i < 9; ++i) f[i] = pull<S, C>(p, P, 0, i, x, y, nullptr);
   const Macro M = macro_node<C>(p, phipsi, phipsi + N, mu, mu + N, f, x, y);
   out[n] = phipsi[n];
   out[N + n] = phipsi[N + n];
@@ -847,7 +973,7 @@ __global__ __launch_bounds__(kBlock) void k_pops(DevParams p, const S* __restric
   for (int lat = 0; lat < 3; ++lat)
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      double v = pull<S, double>(p, P, lat, i, x, y);
+      double v = (lat == 2 && !p.surf) ? 0.0 : pull<S, double>(p, P, lat, i, x, y, ref);
       if (lat == 1) v += lam * WQ<double>(i) * hprime(p, ref[emitter(p, i, x, y)]);
       if (lat == 2 && p.surf) v += mub * WQ<double>(i);
       if (i == 0 && lat > 0 && (lat == 1 || p.surf)) v += ref[(size_t)(lat - 1) * N + n];
@@ -891,7 +1017,7 @@ __global__ __launch_bounds__(kBlock) void k_invariants(DevParams p, const S* __r
     const int x = n % p.nx, y = n / p.nx;
     C f[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = pull<S, C>(p, P, 0, i, x, y);
+    for (int i = 0; i < 9; ++i) f[i] = pull<S, C>(p, P, 0, i, x, y, nullptr);
     const Macro M = macro_node<C>(p, phi, psi, mu, mu + N, f, x, y);
     const double ph = phi[n], ps = psi[n], ux = M.ux, uy = M.uy, pr = M.pr, rho = M.rho;
     if (!isfinite(ph) || !isfinite(ps) || !isfinite(ux) || !isfinite(uy) || !isfinite(pr)) acc[7] += 1.0;
@@ -1112,6 +1238,9 @@ hipError_t pops_impl(const DevParams& p, DevState& s, hipStream_t st) {
 }  // namespace
 
 size_t storage_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2); }
+size_t pops_bytes(int precision, size_t N) {
+  return precision == LBM_FP16_SHIFTED ? rest_offset(N) + 2 * N * sizeof(float) : 27 * N * storage_bytes(precision);
+}
 size_t step_blocks(int nx, int ny, int seg_rows) {
   return (size_t)((nx + kStripW - 1) / kStripW) * (size_t)((ny + seg_rows - 1) / seg_rows);
 }
@@ -1126,10 +1255,11 @@ int step_seg_rows(int nx, int ny) {
 }
 size_t compute_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 
-#define LBM_DISPATCH(prec, call64, call32)            \
+#define LBM_DISPATCH(prec, call64, call32, call16)    \
   switch (prec) {                                     \
     case LBM_FP64: return call64;                     \
     case LBM_FP32: return call32;                     \
+    case LBM_FP16_SHIFTED: return call16;             \
     default: return hipErrorInvalidValue;             \
   }
 
@@ -1138,23 +1268,29 @@ hipError_t launch_init(const DevParams& p, DevState& s, hipStream_t st) {
   return launch_load(p, s, 0, st);
 }
 hipError_t launch_load(const DevParams& p, DevState& s, int with_u, hipStream_t st) {
-  LBM_DISPATCH(s.precision, (load_impl<double>(p, s, with_u, st)), (load_impl<float>(p, s, with_u, st)));
+  LBM_DISPATCH(s.precision, (load_impl<double>(p, s, with_u, st)), (load_impl<float>(p, s, with_u, st)),
+               (load_impl<_Float16>(p, s, with_u, st)));
 }
 hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer) {
   LBM_DISPATCH(s.precision, (step_impl<double, double>(p, s, have_hist, st, timer)),
-               (step_impl<float, float>(p, s, have_hist, st, timer)));
+               (step_impl<float, float>(p, s, have_hist, st, timer)),
+               (step_impl<_Float16, float>(p, s, have_hist, st, timer)));
 }
 hipError_t launch_macro(const DevParams& p, DevState& s, hipStream_t st) {
-  LBM_DISPATCH(s.precision, (macro_impl<double, double>(p, s, st)), (macro_impl<float, float>(p, s, st)));
+  LBM_DISPATCH(s.precision, (macro_impl<double, double>(p, s, st)), (macro_impl<float, float>(p, s, st)),
+               (macro_impl<_Float16, float>(p, s, st)));
 }
 hipError_t launch_invariants(const DevParams& p, DevState& s, hipStream_t st) {
-  LBM_DISPATCH(s.precision, (inv_impl<double, double>(p, s, st)), (inv_impl<float, float>(p, s, st)));
+  LBM_DISPATCH(s.precision, (inv_impl<double, double>(p, s, st)), (inv_impl<float, float>(p, s, st)),
+               (inv_impl<_Float16, float>(p, s, st)));
 }
 hipError_t launch_fetch(const DevParams& p, DevState& s, uint32_t, hipStream_t st) {
-  LBM_DISPATCH(s.precision, (fetch_impl<double, double>(p, s, st)), (fetch_impl<float, float>(p, s, st)));
+  LBM_DISPATCH(s.precision, (fetch_impl<double, double>(p, s, st)), (fetch_impl<float, float>(p, s, st)),
+               (fetch_impl<_Float16, float>(p, s, st)));
 }
 hipError_t launch_fetch_pops(const DevParams& p, DevState& s, hipStream_t st) {
-  LBM_DISPATCH(s.precision, (pops_impl<double>(p, s, st)), (pops_impl<float>(p, s, st)));
+  LBM_DISPATCH(s.precision, (pops_impl<double>(p, s, st)), (pops_impl<float>(p, s, st)),
+               (pops_impl<_Float16>(p, s, st)));
 }
 
 }  // namespace lbm

@@ -93,6 +93,41 @@ def test_tile_heights(lbm, rows):
                 assert_fields_close(gf, of, tol, u_scale(cfg), p_scale(cfg), f"rows {rows} {prec} step {step}")
 
 
+# FP16 shifted storage: no parity bound is claimed; these are the measured
+# errors against the FP64 oracle with a margin of a few times (per field,
+# normalised as above), and the surfactant mass drift, which the FP32 rest
+# planes keep at the FP32 level.
+FP16_TOL = {"phi": 3e-4, "psi": 5e-3, "ux": 2e-2, "uy": 5e-2, "p": 2e-2, "mu_phi": 2e-2, "mu_psi": 5e-3}
+
+
+def fp16_errors(lbm, cfg, steps):
+    g = lbm.Sim(cfg, "fp16")
+    o = oracle.OracleSim(cfg)
+    m0 = g.invariants()["mass_psi"]
+    g.step(steps)
+    o.step(steps)
+    e = field_errors(g.fields(FIELDS), o.fields(FIELDS), u_scale(cfg), p_scale(cfg))
+    gi, oi = g.invariants(), o.invariants()
+    return e, gi, oi, m0
+
+
+@pytest.mark.parametrize("name,steps", [("stationary_drop_64", 1000), ("sessile_adsorbing_96x48", 600),
+                                        ("shear_ratio10_128x64", 300), ("ragged_67x37_walls", 300)])
+def test_fp16_shifted_storage_errors(lbm, name, steps):
+    cfg = CASES[name]
+    e, gi, oi, m0 = fp16_errors(lbm, cfg, steps)
+    print(name, "fp16 errors", {k: float("%.3g" % v) for k, v in e.items()})
+    bad = {k: v for k, v in e.items() if not v <= FP16_TOL[k]}
+    assert not bad, (name, bad, e)
+    assert gi["nonfinite"] == 0
+    if cfg["psi_b"] > 0:
+        assert abs(gi["mass_psi"] - m0) / m0 < 5e-6
+    assert gi["area_phi_pos"] == pytest.approx(oi["area_phi_pos"], rel=1e-4)
+    if cfg.get("bc_bottom", 0) == inputs.WALL_WET:
+        assert abs(gi["theta_app_deg"] - oi["theta_app_deg"]) < 0.02
+        assert gi["contact_width"] == pytest.approx(oi["contact_width"], abs=0.02)
+
+
 def test_stationary_drop_1000_steps(lbm):
     """Plain method, FP64, 2-D periodic 64x64 stationary droplet, 1000 steps:
     fields within 1e-10, surfactant mass drift below 1e-12 relative."""
@@ -173,7 +208,7 @@ def test_surfactant_mass_conservation_fp64(lbm):
 
 def test_deterministic_and_checkpoint_restart(lbm):
     cfg = inputs.sessile_drop(nx=80, ny=40, R=12.0)
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "fp16"):
         a = lbm.Sim(cfg, prec)
         a.step(37)
         blob = a.save_state()
@@ -197,7 +232,7 @@ def test_graph_replay_matches_eager(lbm):
     with other device work (invariants, field fetches) between them, and after
     an odd number of steps (the other buffer parity)."""
     for cfg in (inputs.sessile_drop(nx=96, ny=48, R=16.0), inputs.stationary_drop()):
-        for prec in ("fp32", "fp64"):
+        for prec in ("fp32", "fp64", "fp16"):
             a = lbm.Sim(cfg, prec)
             b = lbm.Sim(cfg, prec)
             for rep, n in enumerate((1, 64, 32, 33, 70, 40)):
