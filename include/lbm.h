@@ -208,6 +208,66 @@ int lbm_destroy(lbm_handle* h);
  * h is NULL).  Never NULL. */
 const char* lbm_last_error(const lbm_handle* h);
 
+/* ------------------------------------------------------------ batched sweep
+ * Many independent cases (each its own lbm_params: grid, physics, walls)
+ * advanced together: one kernel launch per step covers the workgroups of all
+ * cases, a second forms each case's multipliers (the per-case reductions of
+ * eq15 and the psi constraint).  The cases of a batch share one storage
+ * precision and one kind of y boundary (all walled or all periodic); their
+ * results equal, bit for bit, those of single handles with the same segment
+ * height.  A case can be retired (not stepped) and its slot refilled with new
+ * parameters of the same grid.  Runs of 32 steps replay from a HIP graph. */
+typedef struct lbm_batch lbm_batch; /* opaque, owned by the library */
+
+/* Device bytes for the batch's state (cases[0..count-1]); validates every case
+ * (LBM_E_ARG with the case index in the message). */
+int lbm_batch_required_bytes(const lbm_params* cases, int32_t count, size_t* bytes);
+
+/* Create a batch and initialise every case as lbm_init does.  seg_rows is the
+ * row-segment height of the step workgroups for all cases (a multiple of 4; 0
+ * chooses one from the total size); dev_buf / hip_stream as for lbm_init (the
+ * caller's buffer must hold lbm_batch_required_bytes, 256-byte aligned). */
+int lbm_batch_init(const lbm_params* cases, int32_t count, int32_t seg_rows, void* dev_buf, size_t buf_bytes,
+                   void* hip_stream, lbm_batch** out);
+
+/* Enqueue n steps of every active case (asynchronous, as lbm_step).  Returns
+ * LBM_E_STATE while an active case is latched faulted by a diagnostic. */
+int lbm_batch_step(lbm_batch* b, int64_t n);
+
+/* Activity of every case (active[count]: 0 retires a case, which then keeps
+ * its state; nonzero steps it).  Synchronises the stream. */
+int lbm_batch_set_active(lbm_batch* b, const int32_t* active);
+
+/* lbm_reduce_invariants for every case into out[count] (synchronises).
+ * Returns the first case's error code, after filling every entry. */
+int lbm_batch_reduce_invariants(lbm_batch* b, lbm_invariants* out);
+
+/* lbm_fetch_fields of case index (synchronises). */
+int lbm_batch_fetch_fields(lbm_batch* b, int32_t index, uint32_t mask, double* host, size_t n_doubles);
+
+/* Refill slot index with a new case: same nx, ny, precision and kind of y
+ * boundary; initialised as lbm_init does, and made active. */
+int lbm_batch_replace_case(lbm_batch* b, int32_t index, const lbm_params* p);
+
+/* Autotuner: times trial_steps steps of the batch for each segment height of
+ * {4, 8, 16, 32, 64}, keeps the fastest (written to *seg_rows_out) and puts
+ * every case back to its initial state.  Only before the first step. */
+int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, int32_t* seg_rows_out);
+
+/* Cases, segment height, workgroups of one step launch and total nodes. */
+int lbm_batch_info(lbm_batch* b, int32_t* count, int32_t* seg_rows, int32_t* workgroups, int64_t* nodes);
+
+/* Kernel timing of the batch's step and finishing kernels, as lbm_timing_*. */
+int lbm_batch_timing_begin(lbm_batch* b, int64_t max_steps);
+int lbm_batch_timing_end(lbm_batch* b, double* ms, int64_t* launches);
+
+/* Release the batch, its cases and any library-owned memory and stream. */
+int lbm_batch_destroy(lbm_batch* b);
+
+/* Message of the last failed call on b (of the last failed lbm_batch_init or
+ * lbm_batch_required_bytes when b is NULL).  Never NULL. */
+const char* lbm_batch_last_error(const lbm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,7 +36,7 @@ uint64_t hash_bytes(const void* data, size_t n) {  // FNV-1a
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t pops, phipsi, mu, uhist, partials, inv_partials, inv_out, contact, scalars, field_buf, total;
+  size_t pops, phipsi, mu, uhist, partials, inv_partials, inv_out, contact, scalars, dparams, field_buf, total;
 };
 
 Layout make_layout(const lbm_params& p) {
@@ -55,6 +55,7 @@ Layout make_layout(const lbm_params& p) {
   L.inv_out = take(lbm::kInvOut * sizeof(double));
   L.contact = take(3 * (size_t)p.nx * sizeof(double));
   L.scalars = take(3 * sizeof(lbm::DevScalars));
+  L.dparams = take(sizeof(lbm::DevParams));
   L.field_buf = take(27 * N * sizeof(double));
   L.total = off;
   return L;
@@ -197,6 +198,7 @@ void carve(lbm_handle* h) {
   s.inv_out = (double*)(b + L.inv_out);
   s.contact = (double*)(b + L.contact);
   s.scalars = (lbm::DevScalars*)(b + L.scalars);
+  s.dparams = (lbm::DevParams*)(b + L.dparams);
   s.scur = 0;
   s.tile_rows = h->prm.tile_rows ? h->prm.tile_rows : lbm::step_seg_rows(h->dp.nx, h->dp.ny);
   s.field_buf = (double*)(b + L.field_buf);
@@ -258,7 +260,8 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
     h->own_stream = true;
   }
   carve(h);
-  hipError_t e = lbm::launch_init(h->dp, h->ds, h->stream);
+  hipError_t e = hipMemcpyAsync(h->ds.dparams, &h->dp, sizeof(h->dp), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = lbm::launch_init(h->dp, h->ds, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     std::string msg = std::string("initialisation kernels: ") + hipGetErrorString(e);
@@ -538,3 +541,19 @@ int lbm_destroy(lbm_handle* h) {
 const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c_str() : g_init_error.c_str(); }
 
 }  // extern "C"
+
+namespace lbm {
+
+HandleView handle_view(lbm_handle* h) { return HandleView{&h->dp, &h->ds, &h->have_hist, &h->step, &h->faulted}; }
+
+int handle_reinit(lbm_handle* h) {
+  h->ds.cur = h->ds.hcur = h->ds.scur = 0;
+  hipError_t e = lbm::launch_init(h->dp, h->ds, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "initialisation kernels");
+  h->have_hist = 0;
+  h->step = 0;
+  h->faulted = false;
+  return LBM_OK;
+}
+
+}  // namespace lbm

@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+struct lbm_handle;   // the C ABI's opaque handle (lbm_capi.cpp)
+
 namespace lbm {
 
 // Everything a kernel needs, derived once on the host (lattice units, FP64).
@@ -59,10 +61,29 @@ struct DevState {
   double* contact;         // [nx] column heights + 2 x [nx] edge fractions (rows 0 and 1)
   DevScalars* scalars;     // [3]: pending multipliers (ping-pong by scur) and the diagnostic slot [2]
   double* field_buf;       // FP64 staging for fetch/load, [27][N]
+  DevParams* dparams;      // device copy of the parameter block (read by the step kernel)
   int scur;                // scalars[scur] holds the multipliers pending on the stored populations
   int tile_rows;           // rows per workgroup segment of the step kernel (a multiple of 4)
   int cur;                 // index of the current population buffer
   int hcur;                // phi/psi and history buffer written by the next step
+};
+
+// One case of a batch, as the batched step kernels see it (device memory).
+// The buffer parity selects, as cur = hcur = scur does for a single handle,
+// which population, phi/psi, history and multiplier buffers are current.
+struct BatchCase {
+  DevParams p;
+  void* pops[2];
+  double* phipsi[2];
+  void* uhist[2];
+  DevScalars* scalars;     // [3], as DevState::scalars
+  double* partials;
+  int nstrips, seg_rows, ntiles, tile_begin;   // workgroups tile_begin .. tile_begin + ntiles of the launch
+  int active;              // 0: retired, not stepped
+  int parity;
+  int have_hist;
+  int pad;
+  long long step;
 };
 
 constexpr int kBlock = 256;
@@ -86,9 +107,22 @@ struct StepTimer {
   int64_t max_steps = 0, used = 0;
 };
 hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t stream, StepTimer* timer = nullptr);
+hipError_t launch_step_batch(int precision, bool walls, const BatchCase* d_cases, const int* d_wg_case, int nwg, int count,
+                             hipStream_t stream, StepTimer* timer = nullptr);
 hipError_t launch_macro(const DevParams& p, DevState& s, hipStream_t stream);  // phi/psi, mu, multipliers of the current state
 hipError_t launch_invariants(const DevParams& p, DevState& s, hipStream_t stream);
 hipError_t launch_fetch(const DevParams& p, DevState& s, uint32_t mask, hipStream_t stream);
 hipError_t launch_fetch_pops(const DevParams& p, DevState& s, hipStream_t stream);
+
+// Access of the batch layer to the handles it is built from (lbm_capi.cpp).
+struct HandleView {
+  const DevParams* dp;
+  DevState* ds;
+  int* have_hist;
+  int64_t* step;
+  bool* faulted;
+};
+HandleView handle_view(lbm_handle* h);
+int handle_reinit(lbm_handle* h);   // back to the initial fields of its parameters, step 0
 
 }  // namespace lbm

@@ -444,8 +444,8 @@ struct StepArgs {
 // reproducible.  A separate launch rather than a last-tile-done reduction
 // inside k_step: the agent-scope release fence that pattern needs on every
 // tile writes back the XCD's L2 and cost more than the whole step.
-__global__ __launch_bounds__(kBlock) void k_step_finish(const double* __restrict__ partials, int ntiles, int N,
-                                                        int have_hist, DevScalars* __restrict__ next) {
+__device__ __forceinline__ void finish_body(const double* __restrict__ partials, int ntiles, int N, int have_hist,
+                                            DevScalars* __restrict__ next) {
   double t1 = 0.0, t2 = 0.0, t3 = 0.0;
 #pragma unroll 4
   for (int b = threadIdx.x; b < ntiles; b += kBlock) {
@@ -461,6 +461,11 @@ __global__ __launch_bounds__(kBlock) void k_step_finish(const double* __restrict
     next->mubar_psi = t3 / (double)N;
     next->cdef = have_hist ? 1.5 : 1.0;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_step_finish(const double* __restrict__ partials, int ntiles, int N,
+                                                        int have_hist, DevScalars* __restrict__ next) {
+  finish_body(partials, ntiles, N, have_hist, next);
 }
 
 // Element at byte offset b (32-bit, per lane) from a row base pointer (64-bit,
@@ -535,7 +540,7 @@ template <class T> __device__ __forceinline__ T opaque_v(T v) {   // the same fo
 // the nearest fluid row's values (computed again, not copied).
 // k_step_finish then reduces the block sums to lambda(n), mubar(n).
 template <class S, class C, bool WALLS>
-__global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
+__device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a, const int tile) {
   constexpr int RP = 16, RM = 8;           // ring rows: h' and (phi, psi); (mu_phi, mu_psi)
   __shared__ C sHp[RP][kStripW + 6];       // h'(phi(n-1)), columns X0-3 .. X0+62
   __shared__ double2 sPP[RP][64];          // (phi, psi)(n), columns X0-2 .. X0+61
@@ -543,7 +548,6 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
   constexpr bool H16 = kHalf<S>;
   __shared__ float2 sRef[H16 ? RP : 1][H16 ? kStripW + 6 : 1];   // FP16 storage: (phi, psi)(n-1) as in sHp
 
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int X0 = (tile % a.nstrips) * kStripW, Y0 = (tile / a.nstrips) * a.seg_rows;
   const int Yend = min(Y0 + a.seg_rows, p.ny);
   const size_t N = (size_t)p.N;
@@ -855,6 +859,58 @@ __global__ __launch_bounds__(kBlock) void k_step(DevParams p, StepArgs a) {
     a.partials[3 * (size_t)tile + 0] = s1;
     a.partials[3 * (size_t)tile + 1] = s2;
     a.partials[3 * (size_t)tile + 2] = s3;
+  }
+}
+
+// The parameter block is read from device memory (a copy the handle keeps),
+// as the batched kernel reads it: scalar loads on demand instead of a kernel
+// argument block held in (spilled) scalar registers, and the same code as the
+// batched step, hence the same results bit for bit.
+template <class S, class C, bool WALLS>
+__global__ __launch_bounds__(kBlock) void k_step(const DevParams* __restrict__ pp, StepArgs a) {
+  step_body<S, C, WALLS>(*pp, a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Batched step: one launch over the workgroups of every case of a batch
+// (wg_case maps a workgroup to its case); each case carries its own
+// parameters, buffers, buffer parity and activity, so retired cases are
+// skipped and a captured graph of the launch stays valid.
+template <class S, class C, bool WALLS>
+__global__ __launch_bounds__(kBlock) void k_step_batch(const BatchCase* __restrict__ cases, const int* __restrict__ wg_case) {
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = wave_uniform(wg_case[b]);
+  const BatchCase& bc = cases[c];
+  if (!bc.active) return;
+  const int par = bc.parity;
+  StepArgs a;
+  a.Pin = bc.pops[par];
+  a.Pout = bc.pops[par ^ 1];
+  a.ref = bc.phipsi[par ^ 1];
+  a.out = bc.phipsi[par];
+  a.hin = bc.uhist[par ^ 1];
+  a.hout = bc.uhist[par];
+  a.pend = bc.scalars + par;
+  a.next = bc.scalars + (par ^ 1);
+  a.partials = bc.partials;
+  a.have_hist = bc.have_hist;
+  a.nstrips = bc.nstrips;
+  a.seg_rows = bc.seg_rows;
+  a.ntiles = bc.ntiles;
+  step_body<S, C, WALLS>(bc.p, a, b - bc.tile_begin);
+}
+
+// One workgroup per case: the multipliers of the step just taken, then the
+// case's buffer parity flips.
+__global__ __launch_bounds__(kBlock) void k_step_finish_batch(BatchCase* __restrict__ cases) {
+  BatchCase& bc = cases[blockIdx.x];
+  if (!bc.active) return;
+  const int par = bc.parity, hh = bc.have_hist;
+  finish_body(bc.partials, bc.ntiles, bc.p.N, hh, bc.scalars + (par ^ 1));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bc.parity = par ^ 1;
+    bc.have_hist = 1;
+    bc.step += 1;
   }
 }
 
@@ -1176,8 +1232,8 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
   a.ntiles = (int)step_blocks(p.nx, p.ny, s.tile_rows);
   {
     TimedScope ts(t, LBM_K_STEP, st);
-    if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false>), dim3(a.ntiles), dim3(kBlock), 0, st, p, a);
-    else hipLaunchKernelGGL((k_step<S, C, true>), dim3(a.ntiles), dim3(kBlock), 0, st, p, a);
+    if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false>), dim3(a.ntiles), dim3(kBlock), 0, st, (const DevParams*)s.dparams, a);
+    else hipLaunchKernelGGL((k_step<S, C, true>), dim3(a.ntiles), dim3(kBlock), 0, st, (const DevParams*)s.dparams, a);
   }
   {
     TimedScope ts(t, LBM_K_FINISH, st);
@@ -1270,6 +1326,28 @@ hipError_t launch_init(const DevParams& p, DevState& s, hipStream_t st) {
 hipError_t launch_load(const DevParams& p, DevState& s, int with_u, hipStream_t st) {
   LBM_DISPATCH(s.precision, (load_impl<double>(p, s, with_u, st)), (load_impl<float>(p, s, with_u, st)),
                (load_impl<_Float16>(p, s, with_u, st)));
+}
+template <class S, class C>
+hipError_t batch_step_impl(bool walls, const BatchCase* d_cases, const int* d_wg_case, int nwg, int count, hipStream_t st,
+                           StepTimer* timer) {
+  StepTimer* t = (timer && timer->ev && timer->used < timer->max_steps) ? timer : nullptr;
+  {
+    TimedScope ts(t, LBM_K_STEP, st);
+    if (walls) hipLaunchKernelGGL((k_step_batch<S, C, true>), dim3(nwg), dim3(kBlock), 0, st, d_cases, d_wg_case);
+    else hipLaunchKernelGGL((k_step_batch<S, C, false>), dim3(nwg), dim3(kBlock), 0, st, d_cases, d_wg_case);
+  }
+  {
+    TimedScope ts(t, LBM_K_FINISH, st);
+    hipLaunchKernelGGL(k_step_finish_batch, dim3(count), dim3(kBlock), 0, st, (BatchCase*)d_cases);
+  }
+  if (t) t->used += 1;
+  return hipGetLastError();
+}
+hipError_t launch_step_batch(int precision, bool walls, const BatchCase* d_cases, const int* d_wg_case, int nwg, int count,
+                             hipStream_t st, StepTimer* timer) {
+  LBM_DISPATCH(precision, (batch_step_impl<double, double>(walls, d_cases, d_wg_case, nwg, count, st, timer)),
+               (batch_step_impl<float, float>(walls, d_cases, d_wg_case, nwg, count, st, timer)),
+               (batch_step_impl<_Float16, float>(walls, d_cases, d_wg_case, nwg, count, st, timer)));
 }
 hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer) {
   LBM_DISPATCH(s.precision, (step_impl<double, double>(p, s, have_hist, st, timer)),

@@ -34,7 +34,11 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_UNSUPPORTED", -3: "LBM_E_OOM"
 EXPORTS = ["lbm_required_bytes", "lbm_init", "lbm_step", "lbm_reduce_invariants", "lbm_fetch_fields",
            "lbm_load_fields", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_derived",
            "lbm_fetch_populations", "lbm_destroy", "lbm_last_error", "lbm_timing_begin", "lbm_timing_end",
-           "lbm_bytes_per_node_step"]
+           "lbm_bytes_per_node_step",
+           "lbm_batch_required_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_set_active",
+           "lbm_batch_reduce_invariants", "lbm_batch_fetch_fields", "lbm_batch_replace_case", "lbm_batch_autotune",
+           "lbm_batch_info", "lbm_batch_timing_begin", "lbm_batch_timing_end", "lbm_batch_destroy",
+           "lbm_batch_last_error"]
 KERNEL_NAMES = ["k_step", "k_step_finish"]
 
 
@@ -108,8 +112,23 @@ def lib() -> ctypes.CDLL:
         L.lbm_bytes_per_node_step.argtypes = [vp, dp]
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = ctypes.c_char_p
+        i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+        L.lbm_batch_required_bytes.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(sz)]
+        L.lbm_batch_init.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32, vp, sz, vp, ctypes.POINTER(vp)]
+        L.lbm_batch_step.argtypes = [vp, ctypes.c_int64]
+        L.lbm_batch_set_active.argtypes = [vp, i32p]
+        L.lbm_batch_reduce_invariants.argtypes = [vp, ctypes.POINTER(Invariants)]
+        L.lbm_batch_fetch_fields.argtypes = [vp, ctypes.c_int32, ctypes.c_uint32, dp, sz]
+        L.lbm_batch_replace_case.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Params)]
+        L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int32, i32p]
+        L.lbm_batch_info.argtypes = [vp, i32p, i32p, i32p, i64p]
+        L.lbm_batch_timing_begin.argtypes = [vp, ctypes.c_int64]
+        L.lbm_batch_timing_end.argtypes = [vp, dp, i64p]
+        L.lbm_batch_destroy.argtypes = [vp]
+        L.lbm_batch_last_error.argtypes = [vp]
+        L.lbm_batch_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name != "lbm_last_error":
+            if name not in ("lbm_last_error", "lbm_batch_last_error"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -248,3 +267,97 @@ class Sim:
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(lib().lbm_load_state(self._h, buf, len(blob)), self._h)
+
+
+def _bcheck(rc: int, b=None):
+    if rc != 0:
+        raise LbmError(rc, lib().lbm_batch_last_error(b).decode())
+
+
+class Batch:
+    """Independent cases advanced together (the batched sweep of the C ABI).
+
+    cfgs: configuration dictionaries (inputs.py); all share the storage
+    precision and the kind of y boundary.  seg_rows as lbm_batch_init (0: auto).
+    Device memory is one torch uint8 tensor; work runs on torch's current
+    stream (or the stream given)."""
+
+    def __init__(self, cfgs: list, precision: str = "fp32", seg_rows: int = 0, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to torch; the lattice Boltzmann path has no CPU fallback")
+        self.cfgs = [dict(c) for c in cfgs]
+        self.precision = precision
+        n = len(cfgs)
+        self.params = (Params * n)(*[make_params(c, PRECISIONS[precision]) for c in cfgs])
+        nbytes = ctypes.c_size_t()
+        _bcheck(lib().lbm_batch_required_bytes(self.params, n, ctypes.byref(nbytes)))
+        self.buffer = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        b = ctypes.c_void_p()
+        _bcheck(lib().lbm_batch_init(self.params, n, int(seg_rows), ctypes.c_void_p(self.buffer.data_ptr()), nbytes.value,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(b)))
+        self._b = b
+        self.count = n
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().lbm_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        _bcheck(lib().lbm_batch_step(self._b, int(n)), self._b)
+
+    def set_active(self, active):
+        arr = (ctypes.c_int32 * self.count)(*[1 if a else 0 for a in active])
+        _bcheck(lib().lbm_batch_set_active(self._b, arr), self._b)
+
+    def invariants(self, check: bool = True) -> list:
+        inv = (Invariants * self.count)()
+        rc = lib().lbm_batch_reduce_invariants(self._b, inv)
+        if check:
+            _bcheck(rc, self._b)
+        return [x.as_dict() for x in inv]
+
+    def fields(self, index: int, names=("phi", "psi")) -> dict:
+        cfg = self.cfgs[index]
+        nx, ny = cfg["nx"], cfg["ny"]
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELD_NAMES.index(nm)
+        order = [nm for nm in FIELD_NAMES if mask & (1 << FIELD_NAMES.index(nm))]
+        out = np.empty(len(order) * nx * ny, dtype=np.float64)
+        _bcheck(lib().lbm_batch_fetch_fields(self._b, int(index), mask,
+                                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size), self._b)
+        return {nm: out[k * nx * ny:(k + 1) * nx * ny].reshape(ny, nx) for k, nm in enumerate(order)}
+
+    def replace_case(self, index: int, cfg: dict):
+        p = make_params(cfg, PRECISIONS[self.precision])
+        _bcheck(lib().lbm_batch_replace_case(self._b, int(index), ctypes.byref(p)), self._b)
+        self.cfgs[index] = dict(cfg)
+
+    def autotune(self, trial_steps: int = 20) -> int:
+        seg = ctypes.c_int32()
+        _bcheck(lib().lbm_batch_autotune(self._b, int(trial_steps), ctypes.byref(seg)), self._b)
+        return seg.value
+
+    def info(self) -> dict:
+        c, s, w, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _bcheck(lib().lbm_batch_info(self._b, ctypes.byref(c), ctypes.byref(s), ctypes.byref(w), ctypes.byref(n)), self._b)
+        return dict(count=c.value, seg_rows=s.value, workgroups=w.value, nodes=n.value)
+
+    def timing_begin(self, max_steps: int):
+        _bcheck(lib().lbm_batch_timing_begin(self._b, int(max_steps)), self._b)
+
+    def timing_end(self) -> dict:
+        k = len(KERNEL_NAMES)
+        ms = (ctypes.c_double * k)()
+        n = (ctypes.c_int64 * k)()
+        _bcheck(lib().lbm_batch_timing_end(self._b, ms, n), self._b)
+        return {KERNEL_NAMES[j]: (ms[j], n[j]) for j in range(k)}
+

@@ -84,3 +84,29 @@ def test_init_without_device_reports_device_error(lbm):
     rc = lbm.lib().lbm_init(ctypes.byref(p), None, 0, None, ctypes.byref(h))
     assert rc == -4 and not h.value
     assert b"device" in lbm.lib().lbm_last_error(None).lower()
+
+
+def test_batch_validation(lbm):
+    """Batch argument checks happen on the host (no device needed)."""
+    import ctypes
+
+    from paper_2609_26332_amd import inputs
+
+    wall = inputs.sessile_drop(nx=64, ny=32, R=10.0)
+    per = inputs.stationary_drop(nx=32, ny=32, R=8.0)
+    L = lbm.lib()
+    n = ctypes.c_size_t()
+    arr = (lbm.Params * 2)(lbm.make_params(wall, lbm.FP32), lbm.make_params(per, lbm.FP32))
+    assert L.lbm_batch_required_bytes(arr, 2, ctypes.byref(n)) == -1
+    assert b"periodic" in L.lbm_batch_last_error(None)
+    arr = (lbm.Params * 2)(lbm.make_params(wall, lbm.FP32), lbm.make_params(wall, lbm.FP64))
+    assert L.lbm_batch_required_bytes(arr, 2, ctypes.byref(n)) == -1
+    arr = (lbm.Params * 2)(lbm.make_params(wall, lbm.FP32), lbm.make_params(dict(wall, nx=2), lbm.FP32))
+    assert L.lbm_batch_required_bytes(arr, 2, ctypes.byref(n)) == -1
+    assert b"case 1" in L.lbm_batch_last_error(None)
+    arr = (lbm.Params * 2)(lbm.make_params(wall, lbm.FP32), lbm.make_params(dict(wall, nx=96, ny=48, R0=14.0), lbm.FP32))
+    assert L.lbm_batch_required_bytes(arr, 2, ctypes.byref(n)) == 0
+    single = ctypes.c_size_t()
+    assert L.lbm_required_bytes(ctypes.byref(arr[0]), ctypes.byref(single)) == 0
+    assert n.value > single.value
+    assert L.lbm_batch_required_bytes(arr, 0, ctypes.byref(n)) == -1

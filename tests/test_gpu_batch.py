@@ -1,0 +1,121 @@
+"""Batched sweep (lbm_batch_*): many cases in one launch per step.
+
+A batch must reproduce, bit for bit, single handles of the same cases with the
+same segment height (same kernels body, same reduction order), keep retired
+cases frozen, refill a slot with a new case, and match the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_26332_amd import inputs
+from tests.parity import FIELDS, assert_fields_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2609_26332_amd import lbm as binding
+
+    return binding
+
+
+def sweep_like_cases():
+    """Walled cases of uneven sizes and parameters in the spirit of the sweep
+    distribution, small enough for quick tests (ragged in x and y)."""
+    out = []
+    for nx, ny, R, th, s, psi_b, Ca in ((64, 32, 10.0, 45.0, 0.1, 0.01, 0.0), (96, 48, 15.0, 120.0, 0.4, 0.03, 0.1),
+                                        (70, 37, 11.0, 90.0, 0.25, 0.02, 0.2), (128, 64, 20.0, 60.0, 0.0, 0.005, 0.05),
+                                        (80, 40, 13.0, 140.0, 0.5, 0.05, 0.15)):
+        cfg = inputs.sessile_drop(nx=nx, ny=ny, R=R, theta0_deg=th, psi_b=psi_b)
+        cfg.update(beta_sg=s, beta_sl=0.01, bc_top=inputs.NOSLIP, u_wall_top=Ca * 0.01 / 0.1)
+        out.append(cfg)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp16"])
+def test_batch_equals_single_handles(lbm, prec):
+    cases = sweep_like_cases()
+    b = lbm.Batch(cases, prec, seg_rows=8)
+    singles = [lbm.Sim(dict(c, tile_rows=8), prec) for c in cases]
+    b.step(40)   # one graph replay and eight launched steps
+    for s in singles:
+        s.step(40)
+    for k, s in enumerate(singles):
+        fb, fs = b.fields(k, FIELDS), s.fields(FIELDS)
+        for nm in FIELDS:
+            assert np.array_equal(fb[nm], fs[nm]), (prec, k, nm, np.abs(fb[nm] - fs[nm]).max())
+    ib, = [b.invariants()]
+    for k, s in enumerate(singles):
+        i1 = s.invariants()
+        for key in ("mass_psi", "sum_phi", "lambda_phi", "mubar_psi", "theta_app_deg"):
+            assert ib[k][key] == i1[key], (k, key)
+    # retire case 1: it keeps its state while the others advance
+    frozen = b.fields(1, FIELDS)
+    b.set_active([1, 0, 1, 1, 1])
+    b.step(35)
+    for k, s in enumerate(singles):
+        if k == 1:
+            continue
+        s.step(35)
+        fb, fs = b.fields(k, FIELDS), s.fields(FIELDS)
+        for nm in FIELDS:
+            assert np.array_equal(fb[nm], fs[nm]), (prec, "after retire", k, nm)
+    f1 = b.fields(1, FIELDS)
+    for nm in FIELDS:
+        assert np.array_equal(f1[nm], frozen[nm]), nm
+    # and reactivated it continues as a single handle would
+    b.set_active([1, 1, 1, 1, 1])
+    b.step(3)
+    singles[1].step(3)
+    fb, fs = b.fields(1, FIELDS), singles[1].fields(FIELDS)
+    for nm in FIELDS:
+        assert np.array_equal(fb[nm], fs[nm]), ("reactivated", nm)
+
+
+def test_batch_replace_case(lbm):
+    cases = sweep_like_cases()
+    b = lbm.Batch(cases, "fp32", seg_rows=4)
+    b.step(10)
+    new = dict(cases[2], theta0_deg=30.0, psi_b=0.04)
+    b.replace_case(2, new)
+    b.step(33)
+    s = lbm.Sim(dict(new, tile_rows=4), "fp32")
+    s.step(33)
+    fb, fs = b.fields(2, FIELDS), s.fields(FIELDS)
+    for nm in FIELDS:
+        assert np.array_equal(fb[nm], fs[nm]), nm
+    with pytest.raises(lbm.LbmError):
+        b.replace_case(2, dict(new, nx=72))
+
+
+def test_batch_fp64_matches_oracle(lbm):
+    cases = sweep_like_cases()[:3]
+    b = lbm.Batch(cases, "fp64", seg_rows=0)
+    b.step(64)
+    for k, cfg in enumerate(cases):
+        o = oracle.OracleSim(cfg)
+        o.step(64)
+        u = max(1e-5, abs(cfg.get("u_wall_top", 0.0)) * 1e-3)
+        assert_fields_close(b.fields(k, FIELDS), o.fields(FIELDS), 1e-10, u, 1e-3 * 0.01 / cfg["R0"], f"batch case {k}")
+
+
+def test_batch_autotune_restores_initial_state(lbm):
+    cases = sweep_like_cases()
+    b = lbm.Batch(cases, "fp32", seg_rows=4)
+    f0 = [b.fields(k, ["phi", "psi"]) for k in range(len(cases))]
+    seg = b.autotune(trial_steps=4)
+    assert seg in (4, 8, 16, 32, 64)
+    assert b.info()["seg_rows"] == seg
+    for k in range(len(cases)):
+        f = b.fields(k, ["phi", "psi"])
+        assert np.array_equal(f["phi"], f0[k]["phi"]) and np.array_equal(f["psi"], f0[k]["psi"]), k
+    b.step(5)
+    s = lbm.Sim(dict(cases[3], tile_rows=seg), "fp32")
+    s.step(5)
+    assert np.array_equal(b.fields(3, ["phi"])["phi"], s.fields(["phi"])["phi"])
