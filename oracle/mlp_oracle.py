@@ -85,7 +85,10 @@ def gradient(theta, X, T, M, bf16: bool = False, layers=LAYERS) -> np.ndarray:
     """d loss / d theta by the chain rule through the layers (backpropagation).
     In bf16 mode the weight gradient is taken with respect to the master
     (unrounded) weights through the rounding (straight-through), i.e. using
-    the rounded operands of the forward pass."""
+    the rounded operands of the forward pass, and the back-propagated signal
+    dz enters both of its products (dz W^T and a^T dz) rounded to bfloat16 as
+    well, as the GPU path's matrix-core operands are; the bias gradient sums
+    the unrounded dz."""
     Y, cache = forward(theta, X, bf16, layers)
     denom = max(float(np.sum(M)), 1.0)
     dz = 2.0 * M * (Y - T) / denom
@@ -94,11 +97,12 @@ def gradient(theta, X, T, M, bf16: bool = False, layers=LAYERS) -> np.ndarray:
         ain, Wq, z = cache[k]
         if k < len(cache) - 1:
             dz = dz * gelu_grad(z)
-        dW = ain.T @ dz
+        dzq = round_bf16(dz) if bf16 else dz
+        dW = ain.T @ dzq
         db = dz.sum(axis=0)
         grads.append((dW, db))
         if k > 0:
-            dz = dz @ Wq.T      # gradient w.r.t. the previous layer's output
+            dz = dzq @ Wq.T     # gradient w.r.t. the previous layer's output
     g = []
     for dW, db in reversed(grads):
         g.append(dW.ravel())

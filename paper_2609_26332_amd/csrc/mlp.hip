@@ -1,0 +1,510 @@
+// mlp.hip -- gfx950 kernels and C ABI (include/mlp.h) of the surrogate MLP:
+// 5 -> 256 -> 256 -> 256 -> 2, exact GELU, ensemble of members.
+//
+// Every matrix product is one kernel, k_gemm: a 64 x 64 output tile per
+// workgroup of four waves, each wave a 32 x 32 block of 2 x 2 matrix-core
+// tiles (v_mfma_f32_16x16x32_bf16: bfloat16 operands, FP32 accumulation),
+// operands staged through LDS with zero padding at the edges, strided so the
+// same kernel forms X W, dZ W^T and A^T dZ; epilogues add the bias and apply
+// GELU (storing the FP32 pre-activation for the backward pass and the
+// bfloat16 activation for the next product) or its derivative.  The biases,
+// the loss, the column sums of the bias gradients and Adam run in FP32.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/mlp.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kIn = 5, kHid = 256, kOut = 2, kLayers = 4;
+constexpr int kDims[kLayers + 1] = {kIn, kHid, kHid, kHid, kOut};
+constexpr int kParams = kIn * kHid + kHid + 2 * (kHid * kHid + kHid) + kHid * kOut + kOut;   // 133634
+constexpr int kThreads = 256;
+constexpr int kRed = 256;   // partial sums of the loss
+
+__host__ __device__ constexpr int w_off(int l) {   // offset of W_l (l = 0..3) in a parameter vector
+  int o = 0;
+  for (int k = 0; k < l; ++k) o += kDims[k] * kDims[k + 1] + kDims[k + 1];
+  return o;
+}
+__host__ __device__ constexpr int b_off(int l) { return w_off(l) + kDims[l] * kDims[l + 1]; }
+static_assert(w_off(kLayers) == kParams, "layout");
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+enum { EPI_STORE = 0, EPI_BIAS_GELU = 1, EPI_BIAS = 2, EPI_DGELU = 3 };
+
+// C(m, n) = sum_k A(m, k) B(k, n) with A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn].
+struct Gemm {
+  const __bf16* A;
+  long long sam, sak;
+  const __bf16* B;
+  long long sbk, sbn;
+  int M, N, K, epi;
+  float* C;          // FP32 result (after the epilogue), row stride scm
+  long long scm;
+  __bf16* Cb;        // bfloat16 copy: GELU(z) (EPI_BIAS_GELU) or the scaled result (EPI_DGELU)
+  const float* bias; // [N]
+  const float* Zp;   // EPI_DGELU: pre-activation multiplied in through GELU', same layout as C
+};
+
+constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;   // LDS rows padded to 80 bytes (16-byte aligned fragments)
+
+__global__ __launch_bounds__(kThreads) void k_gemm(Gemm g) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[TM][LDK];   // [m][k]
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[TN][LDK];   // [n][k]: a lane's 8 k values are contiguous
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int r = t >> 2, kq = (t & 3) * 8;   // staging: row / column r, k offsets kq .. kq+7
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+    const int m = m0 + r, n = n0 + r;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + kq + j;
+      As[r][kq + j] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : (__bf16)0.0f;
+      Bs[r][kq + j] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : (__bf16)0.0f;
+    }
+    __syncthreads();
+    // matrix-core fragments: lane l holds row (l mod 16) and k = 8 (l / 16) .. +7
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) {
+        const bf16x8 a = *(const bf16x8*)&As[wm + bm * 16 + (lane & 15)][(lane >> 4) * 8];
+        const bf16x8 b = *(const bf16x8*)&Bs[wn + bn * 16 + (lane & 15)][(lane >> 4) * 8];
+        acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[bm][bn], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+  // result tile: lane l holds column (l mod 16), rows 4 (l / 16) .. +3
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = m0 + wm + bm * 16 + (lane >> 4) * 4 + j, n = n0 + wn + bn * 16 + (lane & 15);
+        if (m >= g.M || n >= g.N) continue;
+        const long long at = m * g.scm + n;
+        float v = acc[bm][bn][j];
+        if (g.epi == EPI_BIAS_GELU) {
+          v += g.bias[n];
+          g.C[at] = v;
+          g.Cb[at] = (__bf16)gelu(v);
+        } else if (g.epi == EPI_BIAS) {
+          g.C[at] = v + g.bias[n];
+        } else if (g.epi == EPI_DGELU) {
+          v *= gelu_d(g.Zp[at]);
+          g.C[at] = v;
+          g.Cb[at] = (__bf16)v;
+        } else {
+          g.C[at] = v;
+        }
+      }
+}
+
+__global__ __launch_bounds__(kThreads) void k_cast_bf16(const float* __restrict__ src, __bf16* __restrict__ dst, int n) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) dst[i] = (__bf16)src[i];
+}
+
+__device__ float block_sum(float v) {
+  __shared__ float sh[kThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = 0.f;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kThreads / 64; ++k) r += sh[k];
+  __syncthreads();
+  return r;   // valid in thread 0
+}
+
+// 1 / max(sum of the mask, 1), one workgroup
+__global__ __launch_bounds__(kThreads) void k_mask_norm(const float* __restrict__ m, int n2, float* __restrict__ inv) {
+  float s = 0.f;
+  for (int i = threadIdx.x; i < n2; i += kThreads) s += m[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) *inv = 1.0f / fmaxf(s, 1.0f);
+}
+
+// dY = 2 m (y - t) / sum(m) in FP32 and bfloat16; per-workgroup partial sums of m (y - t)^2
+__global__ __launch_bounds__(kThreads) void k_dy(const float* __restrict__ y, const float* __restrict__ t,
+                                                 const float* __restrict__ m, int n2, const float* __restrict__ inv,
+                                                 float* __restrict__ dy, __bf16* __restrict__ dyb, float* __restrict__ part) {
+  float s = 0.f;
+  const float sc = 2.0f * *inv;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n2; i += gridDim.x * kThreads) {
+    const float r = y[i] - t[i];
+    s += m[i] * r * r;
+    const float d = sc * m[i] * r;
+    dy[i] = d;
+    dyb[i] = (__bf16)d;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_loss_final(const float* __restrict__ part, int nb, const float* __restrict__ inv,
+                                                         float* __restrict__ loss) {
+  float s = 0.f;
+  for (int i = threadIdx.x; i < nb; i += kThreads) s += part[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) *loss = s * *inv;
+}
+
+// db[j] = sum over rows of dz[row][j]
+__global__ __launch_bounds__(kThreads) void k_colsum(const float* __restrict__ dz, int rows, int cols, float* __restrict__ db) {
+  const int j = blockIdx.x * kThreads + threadIdx.x;
+  if (j >= cols) return;
+  float s = 0.f;
+  for (int i = 0; i < rows; ++i) s += dz[(long long)i * cols + j];
+  db[j] = s;
+}
+
+// Adam on the FP32 master parameters, then their bfloat16 copy
+__global__ __launch_bounds__(kThreads) void k_adam(float* __restrict__ th, float* __restrict__ mo, float* __restrict__ ve,
+                                                   const float* __restrict__ g, __bf16* __restrict__ thb, int n, float lr,
+                                                   float c1, float c2) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float m = 0.9f * mo[i] + 0.1f * gi;
+  const float v = 0.999f * ve[i] + 0.001f * gi * gi;
+  mo[i] = m;
+  ve[i] = v;
+  const float x = th[i] - lr * (m / c1) / (sqrtf(v / c2) + 1e-8f);
+  th[i] = x;
+  thb[i] = (__bf16)x;
+}
+
+// ensemble mean and population standard deviation over members
+__global__ __launch_bounds__(kThreads) void k_ens(const float* __restrict__ ys, int members, int n2, float* __restrict__ mean,
+                                                  float* __restrict__ sd) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n2) return;
+  float s = 0.f;
+  for (int k = 0; k < members; ++k) s += ys[(long long)k * n2 + i];
+  const float mu = s / members;
+  float q = 0.f;
+  for (int k = 0; k < members; ++k) {
+    const float d = ys[(long long)k * n2 + i] - mu;
+    q += d * d;
+  }
+  mean[i] = mu;
+  sd[i] = sqrtf(q / members);
+}
+
+size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
+int nblk(long long n) { return (int)((n + kThreads - 1) / kThreads); }
+
+std::string g_mlp_error = "no error";
+
+}  // namespace
+
+struct mlp_handle {
+  int members = 0, max_batch = 0;
+  void* buf = nullptr;
+  bool own_buf = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // per member [members][kParams]
+  float *master = nullptr, *mom = nullptr, *vel = nullptr, *grad = nullptr;
+  __bf16* wbf = nullptr;
+  std::vector<int> adam_t;
+  // activations for max_batch samples
+  __bf16* xb = nullptr;
+  float* Z[3] = {nullptr, nullptr, nullptr};   // pre-activations of the hidden layers
+  __bf16* A[3] = {nullptr, nullptr, nullptr};  // their bfloat16 GELU outputs
+  float* y = nullptr;                          // outputs [B][2]
+  float* ys = nullptr;                         // ensemble outputs [members][B][2]
+  float *dy = nullptr, *dzf[2] = {nullptr, nullptr};
+  __bf16 *dyb = nullptr, *dzb[2] = {nullptr, nullptr};
+  float *part = nullptr, *inv = nullptr, *loss = nullptr;
+  std::string err = "no error";
+};
+
+namespace {
+
+struct MlpLayout {
+  size_t master, mom, vel, grad, wbf, xb, Z, A, y, ys, dy, dyb, dzf, dzb, part, inv, loss, total;
+};
+
+MlpLayout mlp_layout(int members, int B) {
+  MlpLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += al256(bytes); return o; };
+  const size_t P = (size_t)members * kParams;
+  L.master = take(P * 4);
+  L.mom = take(P * 4);
+  L.vel = take(P * 4);
+  L.grad = take(P * 4);
+  L.wbf = take(P * 2);
+  L.xb = take((size_t)B * kIn * 2);
+  L.Z = take(3 * (size_t)B * kHid * 4);
+  L.A = take(3 * (size_t)B * kHid * 2);
+  L.y = take((size_t)B * kOut * 4);
+  L.ys = take((size_t)members * B * kOut * 4);
+  L.dy = take((size_t)B * kOut * 4);
+  L.dyb = take((size_t)B * kOut * 2);
+  L.dzf = take(2 * (size_t)B * kHid * 4);
+  L.dzb = take(2 * (size_t)B * kHid * 2);
+  L.part = take(kRed * 4);
+  L.inv = take(4);
+  L.loss = take(4);
+  L.total = off;
+  return L;
+}
+
+int mfail(mlp_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_mlp_error = msg;
+  return code;
+}
+#define MHIP(h, expr, where)                                                                             \
+  do {                                                                                                   \
+    hipError_t e_ = (expr);                                                                              \
+    if (e_ != hipSuccess) return mfail(h, -4, std::string(where) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+void gemm(hipStream_t st, const __bf16* A, long long sam, long long sak, const __bf16* B, long long sbk, long long sbn,
+          int M, int N, int K, int epi, float* C, long long scm, __bf16* Cb, const float* bias, const float* Zp) {
+  Gemm g{A, sam, sak, B, sbk, sbn, M, N, K, epi, C, scm, Cb, bias, Zp};
+  hipLaunchKernelGGL(k_gemm, dim3((N + TN - 1) / TN, (M + TM - 1) / TM), dim3(kThreads), 0, st, g);
+}
+
+// forward of one member on n inputs already in h->xb; outputs to y
+void forward(mlp_handle* h, int member, int n, float* y) {
+  const __bf16* W = h->wbf + (size_t)member * kParams;
+  const float* P = h->master + (size_t)member * kParams;
+  const __bf16* a = h->xb;
+  int in = kIn;
+  for (int l = 0; l < 3; ++l) {
+    gemm(h->stream, a, in, 1, W + w_off(l), kHid, 1, n, kHid, in, EPI_BIAS_GELU, h->Z[l], kHid, h->A[l], P + b_off(l), nullptr);
+    a = h->A[l];
+    in = kHid;
+  }
+  gemm(h->stream, a, kHid, 1, W + w_off(3), kOut, 1, n, kOut, kHid, EPI_BIAS, y, kOut, nullptr, P + b_off(3), nullptr);
+}
+
+// loss and gradient of one member (x already in xb); gradient into h->grad[member]
+void backward(mlp_handle* h, int member, const float* t, const float* m, int n) {
+  const __bf16* W = h->wbf + (size_t)member * kParams;
+  float* G = h->grad + (size_t)member * kParams;
+  hipLaunchKernelGGL(k_mask_norm, dim3(1), dim3(kThreads), 0, h->stream, m, n * kOut, h->inv);
+  hipLaunchKernelGGL(k_dy, dim3(kRed), dim3(kThreads), 0, h->stream, h->y, t, m, n * kOut, h->inv, h->dy, h->dyb, h->part);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kThreads), 0, h->stream, h->part, kRed, h->inv, h->loss);
+  // layer 3 (output): dW = A2^T dY, db = sum dY, dZ2 = (dY W3^T) . GELU'(Z2)
+  const float* dzf = h->dy;
+  const __bf16* dzb = h->dyb;
+  int out = kOut;
+  for (int l = 3; l >= 0; --l) {
+    const int in = kDims[l];
+    const __bf16* ain = l ? h->A[l - 1] : h->xb;
+    gemm(h->stream, ain, 1, in, dzb, out, 1, in, out, n, EPI_STORE, G + w_off(l), out, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_colsum, dim3(nblk(out)), dim3(kThreads), 0, h->stream, dzf, n, out, G + b_off(l));
+    if (l > 0) {
+      float* nf = h->dzf[l & 1];
+      __bf16* nb = h->dzb[l & 1];
+      gemm(h->stream, dzb, out, 1, W + w_off(l), 1, out, n, in, out, EPI_DGELU, nf, in, nb, nullptr, h->Z[l - 1]);
+      dzf = nf;
+      dzb = nb;
+      out = in;
+    }
+  }
+}
+
+int check(mlp_handle* h, int member, int n) {
+  if (!h) return mfail(nullptr, -1, "null handle");
+  if (member < 0 || member >= h->members) return mfail(h, -1, "member out of range");
+  if (n <= 0 || n > h->max_batch) return mfail(h, -1, "n must lie in [1, max_batch]");
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mlp_param_count(void) { return kParams; }
+
+int mlp_required_bytes(int32_t members, int32_t max_batch, size_t* bytes) {
+  if (!bytes || members <= 0 || members > 64 || max_batch <= 0 || max_batch > (1 << 22))
+    return mfail(nullptr, -1, "members must lie in [1, 64] and max_batch in [1, 2^22]");
+  *bytes = mlp_layout(members, max_batch).total;
+  return 0;
+}
+
+int mlp_init(int32_t members, int32_t max_batch, void* dev_buf, size_t buf_bytes, void* hip_stream, mlp_handle** out) {
+  if (!out) return mfail(nullptr, -1, "null output handle");
+  *out = nullptr;
+  size_t need = 0;
+  int rc = mlp_required_bytes(members, max_batch, &need);
+  if (rc) return rc;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+      std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return mfail(nullptr, -4, "no gfx950 device");
+  mlp_handle* h = new mlp_handle();
+  h->members = members;
+  h->max_batch = max_batch;
+  if (dev_buf) {
+    if (buf_bytes < need || ((uintptr_t)dev_buf & 255)) { delete h; return mfail(nullptr, -1, "dev_buf too small or not 256-byte aligned"); }
+    h->buf = dev_buf;
+  } else {
+    if (hipMalloc(&h->buf, need) != hipSuccess) { delete h; return mfail(nullptr, -3, "hipMalloc failed"); }
+    h->own_buf = true;
+  }
+  if (hip_stream) h->stream = (hipStream_t)hip_stream;
+  else {
+    if (hipStreamCreate(&h->stream) != hipSuccess) {
+      if (h->own_buf) (void)hipFree(h->buf);
+      delete h;
+      return mfail(nullptr, -4, "hipStreamCreate failed");
+    }
+    h->own_stream = true;
+  }
+  const MlpLayout L = mlp_layout(members, max_batch);
+  char* b = (char*)h->buf;
+  const size_t B = (size_t)max_batch;
+  h->master = (float*)(b + L.master);
+  h->mom = (float*)(b + L.mom);
+  h->vel = (float*)(b + L.vel);
+  h->grad = (float*)(b + L.grad);
+  h->wbf = (__bf16*)(b + L.wbf);
+  h->xb = (__bf16*)(b + L.xb);
+  for (int l = 0; l < 3; ++l) {
+    h->Z[l] = (float*)(b + L.Z) + l * B * kHid;
+    h->A[l] = (__bf16*)(b + L.A) + l * B * kHid;
+  }
+  h->y = (float*)(b + L.y);
+  h->ys = (float*)(b + L.ys);
+  h->dy = (float*)(b + L.dy);
+  h->dyb = (__bf16*)(b + L.dyb);
+  for (int k = 0; k < 2; ++k) {
+    h->dzf[k] = (float*)(b + L.dzf) + k * B * kHid;
+    h->dzb[k] = (__bf16*)(b + L.dzb) + k * B * kHid;
+  }
+  h->part = (float*)(b + L.part);
+  h->inv = (float*)(b + L.inv);
+  h->loss = (float*)(b + L.loss);
+  h->adam_t.assign(members, 0);
+  hipError_t e = hipMemsetAsync(h->buf, 0, L.xb, h->stream);   // parameters, moments, gradients, bf16 copies
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    mlp_destroy(h);
+    return mfail(nullptr, -4, std::string("initialisation: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return 0;
+}
+
+int mlp_set_params(mlp_handle* h, int32_t member, const float* params_host) {
+  int rc = check(h, member, 1);
+  if (rc) return rc;
+  if (!params_host) return mfail(h, -1, "null parameters");
+  const size_t o = (size_t)member * kParams;
+  MHIP(h, hipMemcpyAsync(h->master + o, params_host, kParams * 4, hipMemcpyHostToDevice, h->stream), "copy parameters");
+  MHIP(h, hipMemsetAsync(h->mom + o, 0, kParams * 4, h->stream), "reset moments");
+  MHIP(h, hipMemsetAsync(h->vel + o, 0, kParams * 4, h->stream), "reset moments");
+  hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(kParams)), dim3(kThreads), 0, h->stream, h->master + o, h->wbf + o, kParams);
+  MHIP(h, hipGetLastError(), "cast kernel");
+  MHIP(h, hipStreamSynchronize(h->stream), "synchronise");
+  h->adam_t[member] = 0;
+  return 0;
+}
+
+int mlp_get_params(mlp_handle* h, int32_t member, float* params_host) {
+  int rc = check(h, member, 1);
+  if (rc) return rc;
+  if (!params_host) return mfail(h, -1, "null parameters");
+  MHIP(h, hipMemcpyAsync(params_host, h->master + (size_t)member * kParams, kParams * 4, hipMemcpyDeviceToHost, h->stream), "copy parameters");
+  MHIP(h, hipStreamSynchronize(h->stream), "synchronise");
+  return 0;
+}
+
+int mlp_forward(mlp_handle* h, int32_t member, const float* x_dev, int32_t n, float* y_dev) {
+  int rc = check(h, member, n);
+  if (rc) return rc;
+  if (!x_dev || !y_dev) return mfail(h, -1, "null argument");
+  hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)n * kIn)), dim3(kThreads), 0, h->stream, x_dev, h->xb, n * kIn);
+  forward(h, member, n, y_dev);
+  MHIP(h, hipGetLastError(), "forward kernels");
+  return 0;
+}
+
+int mlp_loss_grad(mlp_handle* h, int32_t member, const float* x_dev, const float* t_dev, const float* m_dev, int32_t n,
+                  float* loss_host, float* grad_host) {
+  int rc = check(h, member, n);
+  if (rc) return rc;
+  if (!x_dev || !t_dev || !m_dev) return mfail(h, -1, "null argument");
+  hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)n * kIn)), dim3(kThreads), 0, h->stream, x_dev, h->xb, n * kIn);
+  forward(h, member, n, h->y);
+  backward(h, member, t_dev, m_dev, n);
+  MHIP(h, hipGetLastError(), "training kernels");
+  if (loss_host) MHIP(h, hipMemcpyAsync(loss_host, h->loss, 4, hipMemcpyDeviceToHost, h->stream), "copy loss");
+  if (grad_host)
+    MHIP(h, hipMemcpyAsync(grad_host, h->grad + (size_t)member * kParams, kParams * 4, hipMemcpyDeviceToHost, h->stream), "copy gradient");
+  MHIP(h, hipStreamSynchronize(h->stream), "synchronise");
+  return 0;
+}
+
+int mlp_train_step(mlp_handle* h, int32_t member, const float* x_dev, const float* t_dev, const float* m_dev, int32_t n,
+                   float lr, float* loss_host) {
+  int rc = check(h, member, n);
+  if (rc) return rc;
+  if (!x_dev || !t_dev || !m_dev || !(lr > 0.f)) return mfail(h, -1, "null argument or non-positive rate");
+  hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)n * kIn)), dim3(kThreads), 0, h->stream, x_dev, h->xb, n * kIn);
+  forward(h, member, n, h->y);
+  backward(h, member, t_dev, m_dev, n);
+  const int t = ++h->adam_t[member];
+  const float c1 = 1.0f - std::pow(0.9f, (float)t), c2 = 1.0f - std::pow(0.999f, (float)t);
+  const size_t o = (size_t)member * kParams;
+  hipLaunchKernelGGL(k_adam, dim3(nblk(kParams)), dim3(kThreads), 0, h->stream, h->master + o, h->mom + o, h->vel + o,
+                     (const float*)(h->grad + o), h->wbf + o, kParams, lr, c1, c2);
+  MHIP(h, hipGetLastError(), "training kernels");
+  if (loss_host) {
+    MHIP(h, hipMemcpyAsync(loss_host, h->loss, 4, hipMemcpyDeviceToHost, h->stream), "copy loss");
+    MHIP(h, hipStreamSynchronize(h->stream), "synchronise");
+  }
+  return 0;
+}
+
+int mlp_predict_ensemble(mlp_handle* h, const float* x_dev, int32_t n, float* mean_dev, float* std_dev) {
+  int rc = check(h, 0, n);
+  if (rc) return rc;
+  if (!x_dev || !mean_dev || !std_dev) return mfail(h, -1, "null argument");
+  hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)n * kIn)), dim3(kThreads), 0, h->stream, x_dev, h->xb, n * kIn);
+  for (int k = 0; k < h->members; ++k) forward(h, k, n, h->ys + (size_t)k * n * kOut);
+  hipLaunchKernelGGL(k_ens, dim3(nblk((long long)n * kOut)), dim3(kThreads), 0, h->stream, (const float*)h->ys, h->members,
+                     n * kOut, mean_dev, std_dev);
+  MHIP(h, hipGetLastError(), "ensemble kernels");
+  return 0;
+}
+
+int mlp_destroy(mlp_handle* h) {
+  if (!h) return 0;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->own_buf && h->buf) (void)hipFree(h->buf);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return 0;
+}
+
+const char* mlp_last_error(const mlp_handle* h) { return h ? h->err.c_str() : g_mlp_error.c_str(); }
+
+}  // extern "C"

@@ -9,13 +9,14 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lbm.h")
+MLP_HEADER = os.path.join(ROOT, "include", "mlp.h")
 LIB = os.path.join(ROOT, "paper_2609_26332_amd", "liblbm_hip.so")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER, prefix="lbm_"):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -38,6 +39,12 @@ def test_library_exports_every_declared_symbol(lbm):
     for name in declared_functions():
         assert hasattr(L, name), name
     assert sorted(lbm.EXPORTS) == declared_functions()
+    from paper_2609_26332_amd import surrogate
+    mlp_names = declared_functions(MLP_HEADER, "mlp_")
+    assert sorted(surrogate.EXPORTS) == mlp_names
+    for name in mlp_names:
+        assert hasattr(L, name), name
+    assert L.mlp_param_count() == 133634
 
 
 def test_param_struct_layout_matches_header(lbm):
