@@ -168,10 +168,12 @@ class Surrogate:
 
     def fit(self, X, angle, tau, tau_mask, epochs: int = 400, batch: int = 256, lr: float = 1e-3, seed: int = 0,
             log=None):
+        """The angle output learns the standardised shift from the clean angle,
+        theta_app - theta0 (a few degrees), rather than theta_app itself."""
         Xs = self.scale_inputs(X)
-        angle = np.asarray(angle, dtype=np.float64)
-        self.angle_mu, self.angle_sd = float(angle.mean()), float(angle.std() + 1e-12)
-        T = np.stack([(angle - self.angle_mu) / self.angle_sd, np.asarray(tau, dtype=np.float64)], 1).astype(np.float32)
+        shift = np.asarray(angle, dtype=np.float64) - np.asarray(X, dtype=np.float64)[:, 0]
+        self.angle_mu, self.angle_sd = float(shift.mean()), float(shift.std() + 1e-12)
+        T = np.stack([(shift - self.angle_mu) / self.angle_sd, np.asarray(tau, dtype=np.float64)], 1).astype(np.float32)
         Mk = np.stack([np.ones(len(angle)), np.asarray(tau_mask, dtype=np.float64)], 1).astype(np.float32)
         n = len(angle)
         losses = []
@@ -198,7 +200,7 @@ class Surrogate:
         """Ensemble mean and spread of (angle in degrees, tau) per case."""
         mean, sd = self.net.predict(self.scale_inputs(X))
         mean, sd = mean.cpu().numpy().astype(np.float64), sd.cpu().numpy().astype(np.float64)
-        angle = mean[:, 0] * self.angle_sd + self.angle_mu
+        angle = np.asarray(X, dtype=np.float64)[:, 0] + mean[:, 0] * self.angle_sd + self.angle_mu
         angle_sd = sd[:, 0] * self.angle_sd
         return angle, angle_sd, mean[:, 1], sd[:, 1]
 
