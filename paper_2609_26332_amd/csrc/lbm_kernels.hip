@@ -535,9 +535,10 @@ template <class T> __device__ __forceinline__ T opaque_v(T v) {   // the same fo
 //     multiplier terms of this step's sources are left out of the stored
 //     populations and of the stored source history (deferred to step n+1)
 // The rows live in LDS rings indexed by row: each halo row of the segment is
-// computed once, and the g, h gathered again by C were gathered by A one or
-// two iterations earlier (L2 hits).  At a wall the ghost rows beyond it hold
-// the nearest fluid row's values (computed again, not copied).
+// computed once, and the g_i, h_i (i >= 1) that A gathers for a row of the
+// segment wait in LDS (as stored) for that row's collision, so C gathers
+// only f from memory.  At a wall the ghost rows beyond it hold the nearest
+// fluid row's values (computed again, not copied).
 // k_step_finish then reduces the block sums to lambda(n), mubar(n).
 template <class S, class C, bool WALLS>
 __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a, const int tile) {
@@ -547,9 +548,19 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   __shared__ double2 sMU[RM][64];          // (mu_phi, mu_psi), columns X0-2 .. X0+61 (lanes 1..62 used)
   constexpr bool H16 = kHalf<S>;
   __shared__ float2 sRef[H16 ? RP : 1][H16 ? kStripW + 6 : 1];   // FP16 storage: (phi, psi)(n-1) as in sHp
+  // g_1..g_8, h_1..h_8 of a segment row from A to C, in storage form (FP32
+  // and FP16 storage; FP64 would need more LDS than two workgroups per CU
+  // leave, and C gathers them again).  Six slots: the row wave w's A handles
+  // at iteration k (Y0+4k+2+w) takes the slot of the row its C handled at
+  // iteration k-1 (Y0+4k-4+w), which no other wave reads; C reads a row at
+  // least one barrier after A wrote it.
+  constexpr bool GH = sizeof(S) <= 4;
+  constexpr int RS = 6;
+  __shared__ S sGH[GH ? RS : 1][GH ? 16 : 1][64];
 
   const int X0 = (tile % a.nstrips) * kStripW, Y0 = (tile / a.nstrips) * a.seg_rows;
   const int Yend = min(Y0 + a.seg_rows, p.ny);
+  auto gh_slot = [&](int gy) { return (gy - Y0 + 2 * RS) % RS; };   // gy >= Y0 - 2
   const size_t N = (size_t)p.N;
   const S* __restrict__ Pin = (const S*)a.Pin;
   S* __restrict__ Pout = (S*)a.Pout;
@@ -572,44 +583,70 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   auto is_interior = [&](int ln) { return ln >= 2 && ln < kStripW + 2 && X0 + ln - 2 < p.nx; };
 
   // ---- H: h'(phi(n-1)) of row gy into ring slot gy; lanes 0 and 1 also take
-  // the outer columns X0-3 and X0+62
-  auto row_H = [&](int gy, int ln, unsigned x) {
+  // the outer columns X0-3 and X0+62.  gather_H loads (phi, psi)(n-1) of the
+  // lane's column into v[0], v[1] and of the outer column into v[2], v[3]
+  // (psi for FP16 storage only); row_H fills the rings.
+  auto gather_H = [&](int gy, int ln, unsigned x, double* v) {
     const double* r = ref + (size_t)row_of(gy) * p.nx;
-    const double ph = *byte_at(r, x * (unsigned)sizeof(double));
-    sHp[gy & (RP - 1)][ln + 1] = (C)hprime(p, ph);
-    if constexpr (H16) sRef[gy & (RP - 1)][ln + 1] = make_float2((float)ph, (float)*byte_at(r + N, x * (unsigned)sizeof(double)));
+    v[0] = *byte_at(r, x * (unsigned)sizeof(double));
+    if constexpr (H16) v[1] = *byte_at(r + N, x * (unsigned)sizeof(double));
+    if (ln < 2) {
+      const unsigned xk = (unsigned)modp(X0 - 3 + (ln ? kStripW + 5 : 0), p.nx);
+      v[2] = r[xk];
+      if constexpr (H16) v[3] = r[N + xk];
+    }
+  };
+  auto row_H = [&](int gy, int ln, const double* v) {
+    sHp[gy & (RP - 1)][ln + 1] = (C)hprime(p, v[0]);
+    if constexpr (H16) sRef[gy & (RP - 1)][ln + 1] = make_float2((float)v[0], (float)v[1]);
     if (ln < 2) {
       const int k = ln ? kStripW + 5 : 0;
-      const unsigned xk = (unsigned)modp(X0 - 3 + k, p.nx);
-      sHp[gy & (RP - 1)][k] = (C)hprime(p, r[xk]);
-      if constexpr (H16) sRef[gy & (RP - 1)][k] = make_float2((float)r[xk], (float)r[N + xk]);
+      sHp[gy & (RP - 1)][k] = (C)hprime(p, v[2]);
+      if constexpr (H16) sRef[gy & (RP - 1)][k] = make_float2((float)v[2], (float)v[3]);
     }
   };
 
   // ---- A: (phi, psi)(n) of row gy into ring slot gy
-  auto row_A = [&](int gy, int ln, unsigned x) {
-    const int y = wave_uniform(row_of(gy)), yc = centre(gy);
+  // gather_A loads the streamed g, h of the row (tg, th) and (phi, psi)(n-1)
+  // of the node (r0[0], r0[1]); row_A sums them.
+  auto gather_A = [&](int gy, unsigned x, C* tg, C* th, double* r0) {
+    const int y = wave_uniform(row_of(gy));
     const unsigned xs = x * sizeof(S), xsm = colm(x) * sizeof(S), xsp = colp(x) * sizeof(S), xd = x * sizeof(double);
+    const size_t row = (size_t)y * p.nx;
+    r0[0] = *byte_at(ref + row, xd);
+    r0[1] = *byte_at(ref + N + row, xd);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      tg[i] = pull_row<S, C, WALLS, 1>(p, Pin, N, i, y, xsm, xs, xsp);
+      th[i] = p.surf ? pull_row<S, C, WALLS, 2>(p, Pin, N, i, y, xsm, xs, xsp) : C(0);
+    }
+  };
+  auto row_A = [&](int gy, int ln, unsigned x, const C* tg, const C* th, const double* r0) {
+    const int y = wave_uniform(row_of(gy)), yc = centre(gy);
+    const bool keep = GH && gy >= Y0 && gy < Yend;   // a row C collides
+    const int ks = gh_slot(gy);
+    const unsigned xd = x * sizeof(double);
     C sg = C(0), sh = C(0), corr = C(0);
     const size_t row = (size_t)y * p.nx;
-    const double r0 = *byte_at(ref + row, xd), s0 = *byte_at(ref + N + row, xd);   // phi, psi(n-1) here
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       // emitter of g_i: x - c_i, or the node itself at a wall
       const int sy = y - CY(i);
       const bool bb = WALLS && (sy < 0 || sy >= p.ny);
       const int er = bb ? yc & (RP - 1) : (yc - CY(i)) & (RP - 1), ec = bb ? ln + 1 : ln + 1 - CX(i);
-      const C t = pull_row<S, C, WALLS, 1>(p, Pin, N, i, y, xsm, xs, xsp);
+      const C t = tg[i];
+      if (i && keep) sGH[ks][i - 1][ln] = (S)t;
       if constexpr (H16) sg += i ? decode<S, C>(p, 1, i, (S)t, (C)sRef[er][ec].x) : t;   // rest: FP32 plane
       else sg += t;
       corr += WQ<C>(i) * sHp[er][ec];
     }
-    const double ph = r0 + (double)sg + lam1_ * (double)corr;
+    const double ph = r0[0] + (double)sg + lam1_ * (double)corr;
     double ps = 0.0;
     if (p.surf) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const C t = pull_row<S, C, WALLS, 2>(p, Pin, N, i, y, xsm, xs, xsp);
+        const C t = th[i];
+        if (i && keep) sGH[ks][7 + i][ln] = (S)t;
         if constexpr (H16) {
           const int sy = y - CY(i);
           const bool bb = WALLS && (sy < 0 || sy >= p.ny);
@@ -619,7 +656,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
           sh += t;
         }
       }
-      ps = s0 + (double)sh + mub1_;
+      ps = r0[1] + (double)sh + mub1_;
     }
     sPP[gy & (RP - 1)][ln] = make_double2(ph, ps);
     if (is_interior(ln) && gy >= Y0 && gy < Yend) {
@@ -663,15 +700,18 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   // ---- C: collide row gy (a fluid row of the segment)
   const C* __restrict__ hin = (const C*)a.hin;
   C* __restrict__ hout = (C*)a.hout;
-  // the gathers of a collision row, issued an iteration phase ahead of their use
+  // the gathers of a collision row (f; g and h unless they come from A
+  // through LDS), issued an iteration phase ahead of their use
   auto gather_C = [&](int gy, unsigned x, C* f, C* g, C* h) {
     const size_t N = opaque((size_t)p.N);
     const unsigned xs = x * sizeof(S), xsm = colm(x) * sizeof(S), xsp = colp(x) * sizeof(S);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       f[i] = pull_row<S, C, WALLS, 0>(p, Pin, N, i, gy, xsm, xs, xsp);
-      g[i] = i ? pull_row<S, C, WALLS, 1>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
-      h[i] = (i && p.surf) ? pull_row<S, C, WALLS, 2>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
+      if constexpr (!GH) {
+        g[i] = i ? pull_row<S, C, WALLS, 1>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
+        h[i] = (i && p.surf) ? pull_row<S, C, WALLS, 2>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
+      }
     }
   };
   auto row_C = [&](int gy, int ln, unsigned x, C* f, C* g, C* h) {
@@ -698,6 +738,15 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     const double2 mc = sMU[gy & (RM - 1)][lc];
     const double ph0 = *byte_at(ref + row, xd);   // phi(n-1)
 
+    if constexpr (GH) {
+      g[0] = h[0] = C(0);
+      const int ks = gh_slot(gy);
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        g[i] = (C)sGH[ks][i - 1][ln];
+        h[i] = p.surf ? (C)sGH[ks][7 + i][ln] : C(0);
+      }
+    }
     // decoded (FP16 storage) gathers plus the pending multiplier terms of g_i, h_i
     if constexpr (H16) {
 #pragma unroll
@@ -835,7 +884,11 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   // h' row C still reads; A writes <= 10 rows ahead of the oldest (phi, psi)
   // row C reads; B's writes follow the barrier after every wave's C.
 #pragma unroll 1
-  for (int j = wave; j < 10; j += NWAVE) row_H(Y0 - 3 + j, lane, xcol);   // rows Y0-3 .. Y0+6
+  for (int j = wave; j < 10; j += NWAVE) {   // rows Y0-3 .. Y0+6
+    double v[4];
+    gather_H(Y0 - 3 + j, lane, xcol, v);
+    row_H(Y0 - 3 + j, lane, v);
+  }
   __syncthreads();
 #pragma unroll 1
   for (int k = -1; 4 * k < Yend - Y0; ++k) {
@@ -843,10 +896,22 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     const unsigned x = opaque_v(xcol);
     const int rc = wave_uniform(Y0 + 4 * k + wave);
     const bool collide = k >= 0 && rc < Yend;
-    C f[9], g[9], h[9];
-    if (collide) gather_C(rc, x, f, g, h);   // in flight during H, A, B and the barriers
-    if (k >= 0) row_H(Y0 + 4 * k + 7 + wave, ln, x);
-    row_A(Y0 + 4 * k + 2 + wave, ln, x);
+    const int ra = rc + 2, rh = rc + 7;
+    // All loads of the iteration are issued here, in the order of their use
+    // (their counter drains in order): A's and H's gathers, then C's, which
+    // stay in flight during A, H, B and the barriers.  H may follow A: A reads
+    // h' of rows up to ra + 1, written by earlier iterations.  FP64 (whose C
+    // also gathers g and h) gathers A's populations in A itself, to stay at
+    // two waves per SIMD.
+    constexpr bool preA = GH;
+    C f[9], g[9], h[9], tg[9], th[9];
+    double r0[2], v[4];
+    if (preA) gather_A(ra, x, tg, th, r0);
+    if (k >= 0) gather_H(rh, ln, x, v);
+    if (collide) gather_C(rc, x, f, g, h);
+    if (!preA) gather_A(ra, x, tg, th, r0);
+    row_A(ra, ln, x, tg, th, r0);
+    if (k >= 0) row_H(rh, ln, v);
     __syncthreads();
     if (k >= 0 || wave >= 2) row_B(Y0 + 4 * k + 1 + wave, ln);   // k = -1: rows Y0-1 and Y0 only
     __syncthreads();

@@ -169,12 +169,15 @@ class Surrogate:
     def fit(self, X, angle, tau, tau_mask, epochs: int = 400, batch: int = 256, lr: float = 1e-3, seed: int = 0,
             log=None):
         """The angle output learns the standardised shift from the clean angle,
-        theta_app - theta0 (a few degrees), rather than theta_app itself."""
+        theta_app - theta0 (a few degrees), rather than theta_app itself.  A case
+        without an angle (NaN: the drop detached) is masked out of that output."""
         Xs = self.scale_inputs(X)
         shift = np.asarray(angle, dtype=np.float64) - np.asarray(X, dtype=np.float64)[:, 0]
-        self.angle_mu, self.angle_sd = float(shift.mean()), float(shift.std() + 1e-12)
-        T = np.stack([(shift - self.angle_mu) / self.angle_sd, np.asarray(tau, dtype=np.float64)], 1).astype(np.float32)
-        Mk = np.stack([np.ones(len(angle)), np.asarray(tau_mask, dtype=np.float64)], 1).astype(np.float32)
+        has = np.isfinite(shift)
+        self.angle_mu, self.angle_sd = float(shift[has].mean()), float(shift[has].std() + 1e-12)
+        T = np.stack([np.where(has, (shift - self.angle_mu) / self.angle_sd, 0.0), np.asarray(tau, dtype=np.float64)],
+                     1).astype(np.float32)
+        Mk = np.stack([has.astype(np.float64), np.asarray(tau_mask, dtype=np.float64)], 1).astype(np.float32)
         n = len(angle)
         losses = []
         for k in range(self.members):
