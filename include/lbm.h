@@ -44,7 +44,7 @@ typedef struct lbm_handle lbm_handle; /* opaque, owned by the library */
 typedef enum {
   LBM_OK = 0,
   LBM_E_ARG = -1,          /* invalid argument or parameter set */
-  LBM_E_UNSUPPORTED = -2,  /* valid request this build does not implement */
+  LBM_E_UNSUPPORTED = -2,  /* valid request this library does not implement */
   LBM_E_OOM = -3,          /* device or host allocation failed */
   LBM_E_DEVICE = -4,       /* no usable gfx950 device, or a HIP runtime error */
   LBM_E_NONFINITE = -5,    /* a non-finite value appeared in the fields */
@@ -200,6 +200,23 @@ int lbm_timing_end(lbm_handle* h, double* ms, int64_t* launches);
  * the 27 populations, the FP64 phi/psi planes and the velocity and source
  * history (the algorithmic traffic of the step). */
 int lbm_bytes_per_node_step(lbm_handle* h, double* bytes);
+
+/* Achievable-bandwidth probe (a measurement aid for the roofline; not part of
+ * the method).  One kernel moves, per node of an nx x ny periodic grid, exactly
+ * the bytes lbm_bytes_per_node_step counts for a step with surfactant in the
+ * given storage precision, in the step's access pattern and without its
+ * arithmetic: the 27 populations pulled from the neighbours that streaming
+ * reads (FP16 storage: the rest populations of g and h from FP32 planes), six
+ * history planes in the collision type and two FP64 planes, each read once
+ * and written once.  lbm_probe_bytes gives the device bytes the probe needs
+ * (nx * ny <= 2^28); lbm_probe_stream runs it on dev_buf (caller-owned,
+ * 256-byte aligned, contents overwritten) on hip_stream (NULL: the null
+ * stream): two warm-up launches, then `reps` launches (1..10000) timed with
+ * HIP events; *ms_out is their mean duration.  It synchronises the stream.
+ * Errors go to lbm_last_error(NULL). */
+int lbm_probe_bytes(int32_t nx, int32_t ny, int32_t precision, size_t* bytes);
+int lbm_probe_stream(int32_t nx, int32_t ny, int32_t precision, int32_t reps, void* dev_buf, size_t buf_bytes,
+                     void* hip_stream, float* ms_out);
 
 /* Release the handle and any library-owned device memory and stream. */
 int lbm_destroy(lbm_handle* h);

@@ -18,8 +18,15 @@
  *   O8  MRT collision of the three populations                 (Sec. 3, unified MRT LBE)
  *   O9  streaming with periodic / bounce-back / moving / free-slip walls
  *   O10 history for the backward differences
- * Points the paper leaves open are resolved by the readings listed in the
- * design notes (wall discretisation, rates, eta, M0, rho(phi), first step).
+ * Where the paper leaves a point open it is read as follows: D2Q9 with raw
+ * moments grouped by order; relaxation rates not tied to transport are 1,
+ * the f shear rate follows the local viscosity, g and h use s1 = 1 so that
+ * eta = 6 D; M0 = 0 when lambda_s > 0, else M_phi kappa; rho and mu are
+ * linear in (1 + phi/phi_b)/2; every lattice bounces back half-way at a
+ * wall, whose ghost row carries phi + J_phi/kappa and whose flux J_psi enters
+ * mu_psi and the source; on the first step the backward differences vanish;
+ * phi and psi are advected by the mean of the velocities of this and the
+ * previous step (adv_raw selects the step's own velocity).
  *
  * Plain loops, FP64, a generic 9x9 moment matrix and its numerically computed
  * inverse; global sums are sequential in row-major order.

@@ -6,7 +6,7 @@
  * the test suite, the smoke entry point and the CPU-baseline leg of the
  * benchmark may load it.  It shares no code, header, table or constant with
  * the HIP library; both follow the paper (model: Section 2, scheme: Section 3)
- * and the readings of it recorded in the design notes.
+ * and the same readings of its open points (listed in lbm_oracle.c).
  *
  * Units: lattice units throughout (dx = dt = 1, c_s^2 = 1/3).
  * Layout of every field handed in or out: FP64, row-major [ny][nx], x fastest.

@@ -544,6 +544,8 @@ const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c_str() : g_
 
 namespace lbm {
 
+int set_init_error(int code, const std::string& msg) { return fail(nullptr, code, msg); }
+
 HandleView handle_view(lbm_handle* h) { return HandleView{&h->dp, &h->ds, &h->have_hist, &h->step, &h->faulted}; }
 
 int handle_reinit(lbm_handle* h) {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 struct lbm_handle;   // the C ABI's opaque handle (lbm_capi.cpp)
 
@@ -97,6 +98,7 @@ size_t pops_bytes(int precision, size_t N);   // one population buffer (FP16: 27
 int step_seg_rows(int nx, int ny);                 // rows per workgroup segment of the step kernel
 size_t step_blocks(int nx, int ny, int seg_rows);  // workgroups of the step kernel
 size_t compute_bytes(int precision);
+int set_init_error(int code, const std::string& msg);   // message for lbm_last_error(NULL); returns code
 
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_init(const DevParams& p, DevState& s, hipStream_t stream);

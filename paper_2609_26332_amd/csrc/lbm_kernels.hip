@@ -1367,11 +1367,11 @@ size_t step_blocks(int nx, int ny, int seg_rows) {
 }
 // Rows per workgroup segment: long segments amortise the four extra phi/psi
 // rows and two extra mu rows each segment computes, but a grid needs enough
-// workgroups to fill the chip (on MI355X: best at 4096^2 with 32 rows, about
-// 8800 workgroups; small grids want the most workgroups, 4 rows).
+// workgroups to fill the chip (on MI355X: best at 4096^2 with 16 rows, about
+// 17700 workgroups; small grids want the most workgroups, 4 rows).
 int step_seg_rows(int nx, int ny) {
   int seg = 64;
-  while (seg > 4 && step_blocks(nx, ny, seg) < 8192) seg /= 2;
+  while (seg > 4 && step_blocks(nx, ny, seg) < 16384) seg /= 2;
   return seg;
 }
 size_t compute_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }

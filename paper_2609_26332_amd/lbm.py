@@ -34,7 +34,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_UNSUPPORTED", -3: "LBM_E_OOM"
 EXPORTS = ["lbm_required_bytes", "lbm_init", "lbm_step", "lbm_reduce_invariants", "lbm_fetch_fields",
            "lbm_load_fields", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_derived",
            "lbm_fetch_populations", "lbm_destroy", "lbm_last_error", "lbm_timing_begin", "lbm_timing_end",
-           "lbm_bytes_per_node_step",
+           "lbm_bytes_per_node_step", "lbm_probe_bytes", "lbm_probe_stream",
            "lbm_batch_required_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_set_active",
            "lbm_batch_reduce_invariants", "lbm_batch_fetch_fields", "lbm_batch_replace_case", "lbm_batch_autotune",
            "lbm_batch_info", "lbm_batch_timing_begin", "lbm_batch_timing_end", "lbm_batch_destroy",
@@ -110,6 +110,9 @@ def lib() -> ctypes.CDLL:
         L.lbm_timing_begin.argtypes = [vp, ctypes.c_int64]
         L.lbm_timing_end.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
         L.lbm_bytes_per_node_step.argtypes = [vp, dp]
+        L.lbm_probe_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(sz)]
+        L.lbm_probe_stream.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, sz, vp,
+                                       ctypes.POINTER(ctypes.c_float)]
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = ctypes.c_char_p
         i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
@@ -267,6 +270,27 @@ class Sim:
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(lib().lbm_load_state(self._h, buf, len(blob)), self._h)
+
+
+def probe_stream(nx: int, ny: int, precision: str = "fp32", reps: int = 20) -> dict:
+    """Mean time of the bandwidth probe (lbm_probe_stream: the step's memory
+    traffic without its arithmetic) on an nx x ny grid, with the bytes it moves
+    per node and the resulting rate."""
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible to torch; the probe has no CPU fallback")
+    prec = PRECISIONS[precision]
+    L = lib()
+    nb = ctypes.c_size_t()
+    _check(L.lbm_probe_bytes(nx, ny, prec, ctypes.byref(nb)))
+    buf = torch.zeros(nb.value, dtype=torch.uint8, device="cuda")
+    ms = ctypes.c_float()
+    st = torch.cuda.current_stream()
+    _check(L.lbm_probe_stream(nx, ny, prec, reps, ctypes.c_void_p(buf.data_ptr()), nb.value,
+                              ctypes.c_void_p(st.cuda_stream), ctypes.byref(ms)))
+    per_node = {"fp64": 560.0, "fp32": 296.0, "fp16": 196.0}[precision]
+    return dict(ms=ms.value, bytes_per_node=per_node, gbs=per_node * nx * ny / ms.value / 1e6)
 
 
 def _bcheck(rc: int, b=None):

@@ -293,3 +293,18 @@ def test_load_fields_matches_oracle(lbm):
     g.step(50)
     o.step(50)
     assert_fields_close(g.fields(FIELDS), o.fields(FIELDS), 1e-10, 1e-6, 1e-7, "loaded")
+
+
+def test_bandwidth_probe_moves_the_step_bytes(lbm):
+    """The probe behind the roofline's pattern ceiling moves per node exactly
+    the algorithmic bytes the step reports, in every storage precision, and
+    times a ragged grid (not a multiple of its 64 x 4 blocks)."""
+    cfg = inputs.sessile_drop()
+    for prec in ("fp64", "fp32", "fp16"):
+        sim = lbm.Sim(cfg, prec)
+        r = lbm.probe_stream(250, 131, prec, reps=3)
+        assert r["bytes_per_node"] == sim.bytes_per_node_step()
+        assert r["ms"] > 0.0 and 0.0 < r["gbs"] < 20000.0
+        sim.close()
+    with pytest.raises(lbm.LbmError):
+        lbm.probe_stream(0, 16, "fp32")
