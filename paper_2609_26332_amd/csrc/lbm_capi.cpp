@@ -36,7 +36,7 @@ uint64_t hash_bytes(const void* data, size_t n) {  // FNV-1a
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t pops, phipsi, mu, uhist, partials, inv_partials, inv_out, contact, scalars, dparams, field_buf, total;
+  size_t pops, phipsi, mu, uhist, partials, step_partials, inv_partials, inv_out, contact, scalars, dparams, field_buf, total;
 };
 
 Layout make_layout(const lbm_params& p) {
@@ -51,6 +51,7 @@ Layout make_layout(const lbm_params& p) {
   L.uhist = take(2 * 6 * N * cb);  // u, v (advecting), R_phi, R_psi history, ping-pong
   const size_t ntile = lbm::step_blocks(p.nx, p.ny, 4);  // the most workgroups any segment height gives
   L.partials = take((ntile > (size_t)lbm::kRedBlocks ? ntile : (size_t)lbm::kRedBlocks) * 3 * sizeof(double));
+  L.step_partials = take(2 * ntile * 3 * sizeof(double));
   L.inv_partials = take(lbm::kRedBlocks * lbm::kInvValues * sizeof(double));
   L.inv_out = take(lbm::kInvOut * sizeof(double));
   L.contact = take(3 * (size_t)p.nx * sizeof(double));
@@ -194,6 +195,11 @@ void carve(lbm_handle* h) {
   s.uhist[0] = b + L.uhist;
   s.uhist[1] = b + L.uhist + 6 * N * cb;
   s.partials = (double*)(b + L.partials);
+  {
+    const size_t ntile = lbm::step_blocks(h->dp.nx, h->dp.ny, 4);
+    s.step_partials[0] = (double*)(b + L.step_partials);
+    s.step_partials[1] = s.step_partials[0] + 3 * ntile;
+  }
   s.inv_partials = (double*)(b + L.inv_partials);
   s.inv_out = (double*)(b + L.inv_out);
   s.contact = (double*)(b + L.contact);
@@ -283,7 +289,14 @@ int capture_graph(lbm_handle* h) {
   hipGraph_t g = nullptr;
   HIP_OR_FAIL(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "begin graph capture");
   hipError_t e = hipSuccess;
-  for (int64_t k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = lbm::launch_step(h->dp, s, 1, h->stream, nullptr);
+  // On grids of few workgroups the captured steps after the first reduce the
+  // previous step's multiplier sums themselves: one k_step_finish per graph
+  // (after the last step) instead of one per step.
+  const bool fuse = lbm::step_blocks(h->dp.nx, h->dp.ny, s.tile_rows) <= (size_t)lbm::kFuseTiles;
+  for (int64_t k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
+    const int f = fuse ? ((k > 0 ? lbm::kFusePrev : 0) | (k + 1 < kGraphSteps ? lbm::kFuseNext : 0)) : 0;
+    e = lbm::launch_step(h->dp, s, 1, h->stream, nullptr, f);
+  }
   const hipError_t e_end = hipStreamEndCapture(h->stream, &g);
   if (e == hipSuccess) e = e_end;
   if (e == hipSuccess) e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);

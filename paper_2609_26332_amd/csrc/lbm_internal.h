@@ -56,7 +56,8 @@ struct DevState {
   void* mu;                // 2 planes (mu_phi, mu_psi), FP64
   void* uhist[2];          // 6 planes each: ux, uy, vx, vy (velocity and advecting velocity) and the
                            // stored sources R_phi, R_psi (without their multiplier terms), compute type
-  double* partials;        // reduction partials [kRedBlocks][3]
+  double* partials;        // reduction partials [kRedBlocks][3] (diagnostics; the batched step)
+  double* step_partials[2];  // the single-handle step's sums [ntiles][3], by population parity cur
   double* inv_partials;    // invariant partials [kRedBlocks][kInvValues]
   double* inv_out;         // final invariants [kInvOut]
   double* contact;         // [nx] column heights + 2 x [nx] edge fractions (rows 0 and 1)
@@ -108,7 +109,13 @@ struct StepTimer {
   hipEvent_t* ev = nullptr;  // [max_steps][LBM_N_KERNELS][2]
   int64_t max_steps = 0, used = 0;
 };
-hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t stream, StepTimer* timer = nullptr);
+// fuse: kFusePrev -- the step reduces the previous step's sums itself (that
+// step ran with kFuseNext, i.e. without k_step_finish); only for consecutive
+// steps with a history and at most kFuseTiles workgroups.
+enum { kFusePrev = 1, kFuseNext = 2 };
+constexpr int kFuseTiles = 1024;
+hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t stream, StepTimer* timer = nullptr,
+                       int fuse = 0);
 hipError_t launch_step_batch(int precision, bool walls, const BatchCase* d_cases, const int* d_wg_case, int nwg, int count,
                              hipStream_t stream, StepTimer* timer = nullptr);
 hipError_t launch_macro(const DevParams& p, DevState& s, hipStream_t stream);  // phi/psi, mu, multipliers of the current state

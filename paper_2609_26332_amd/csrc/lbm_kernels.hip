@@ -437,6 +437,12 @@ struct StepArgs {
   DevScalars* next;         // multipliers of step n, written by the last tile
   double* partials;         // [ntiles][3]
   int have_hist, nstrips, seg_rows, ntiles;
+  // Non-null: the multipliers pending on Pin are reduced here, by every
+  // workgroup, from step n-1's partials ([ntiles][3], the same tiling; step
+  // n-1 had a history iff prev_have_hist) instead of being read from pend;
+  // k_step_finish did not run for step n-1.
+  const double* prev_partials;
+  int prev_have_hist;
 };
 
 // lambda(n) = S1/S2, mubar(n) = S3/N from the per-tile partial sums of
@@ -444,8 +450,11 @@ struct StepArgs {
 // reproducible.  A separate launch rather than a last-tile-done reduction
 // inside k_step: the agent-scope release fence that pattern needs on every
 // tile writes back the XCD's L2 and cost more than the whole step.
-__device__ __forceinline__ void finish_body(const double* __restrict__ partials, int ntiles, int N, int have_hist,
-                                            DevScalars* __restrict__ next) {
+// lambda(n) = S1/S2 and mubar(n) = S3/N from the per-workgroup sums, in a
+// fixed order (every thread of the block gets the result); cdef weights the
+// multiplier terms step n+1 applies (1.5 from R + dR/2, 1 on a first step).
+__device__ __forceinline__ DevScalars multipliers_of(const double* __restrict__ partials, int ntiles, int N,
+                                                    int have_hist) {
   double t1 = 0.0, t2 = 0.0, t3 = 0.0;
 #pragma unroll 4
   for (int b = threadIdx.x; b < ntiles; b += kBlock) {
@@ -456,11 +465,19 @@ __device__ __forceinline__ void finish_body(const double* __restrict__ partials,
   t1 = block_reduce(t1, false);
   t2 = block_reduce(t2, false);
   t3 = block_reduce(t3, false);
+  __shared__ DevScalars res;   // block_reduce leaves the sums in thread 0 only
   if (threadIdx.x == 0) {
-    next->lambda_phi = t2 > 0.0 ? t1 / t2 : 0.0;
-    next->mubar_psi = t3 / (double)N;
-    next->cdef = have_hist ? 1.5 : 1.0;
+    res.lambda_phi = t2 > 0.0 ? t1 / t2 : 0.0;
+    res.mubar_psi = t3 / (double)N;
+    res.cdef = have_hist ? 1.5 : 1.0;
   }
+  __syncthreads();
+  return res;
+}
+__device__ __forceinline__ void finish_body(const double* __restrict__ partials, int ntiles, int N, int have_hist,
+                                            DevScalars* __restrict__ next) {
+  const DevScalars r = multipliers_of(partials, ntiles, N, have_hist);
+  if (threadIdx.x == 0) *next = r;
 }
 
 __global__ __launch_bounds__(kBlock) void k_step_finish(const double* __restrict__ partials, int ntiles, int N,
@@ -565,8 +582,11 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   const S* __restrict__ Pin = (const S*)a.Pin;
   S* __restrict__ Pout = (S*)a.Pout;
   const double* __restrict__ ref = a.ref;
-  const double lam1_ = a.pend->cdef * p.M_phi * a.pend->lambda_phi;   // pending term weights
-  const double mub1_ = a.pend->cdef * p.M_psi * a.pend->mubar_psi;
+  // multipliers pending on Pin: reduced here from the previous step's sums
+  // (small grids inside a captured run of steps) or as k_step_finish left them
+  const DevScalars pend = a.prev_partials ? multipliers_of(a.prev_partials, a.ntiles, p.N, a.prev_have_hist) : *a.pend;
+  const double lam1_ = pend.cdef * p.M_phi * pend.lambda_phi;   // pending term weights
+  const double mub1_ = pend.cdef * p.M_psi * pend.mubar_psi;
   const int lane = threadIdx.x & 63;
   const int wave = wave_uniform(threadIdx.x >> 6);
   // fluid row of a (possibly ghost or wrapped) row index
@@ -809,8 +829,8 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       dsx = ps * vx - ps0 * vxh;
       dsy = ps * vy - ps0 * vyh;
       // R(n-1) in full: stored part plus its multiplier term
-      const double Rp_prev = (double)*byte_at(hr + 4 * N, xc) + p.M_phi * a.pend->lambda_phi * hprime(p, ph0);
-      const double Rs_prev = (double)*byte_at(hr + 5 * N, xc) + p.M_psi * a.pend->mubar_psi;
+      const double Rp_prev = (double)*byte_at(hr + 4 * N, xc) + p.M_phi * pend.lambda_phi * hprime(p, ph0);
+      const double Rs_prev = (double)*byte_at(hr + 5 * N, xc) + p.M_psi * pend.mubar_psi;
       Rtp = 1.5 * Rp0 - 0.5 * Rp_prev;
       Rts = 1.5 * Rs0 - 0.5 * Rs_prev;
     }
@@ -961,6 +981,8 @@ __global__ __launch_bounds__(kBlock) void k_step_batch(const BatchCase* __restri
   a.nstrips = bc.nstrips;
   a.seg_rows = bc.seg_rows;
   a.ntiles = bc.ntiles;
+  a.prev_partials = nullptr;
+  a.prev_have_hist = 0;
   step_body<S, C, WALLS>(bc.p, a, b - bc.tile_begin);
 }
 
@@ -1280,7 +1302,7 @@ hipError_t macro_impl(const DevParams& p, DevState& s, hipStream_t st) {
 }
 
 template <class S, class C>
-void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* t) {
+void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* t, int fuse) {
   StepArgs a;
   a.Pin = s.pops[s.cur];
   a.Pout = s.pops[s.cur ^ 1];
@@ -1290,17 +1312,19 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
   a.hout = s.uhist[s.hcur];
   a.pend = s.scalars + s.scur;
   a.next = s.scalars + (s.scur ^ 1);
-  a.partials = s.partials;
+  a.partials = s.step_partials[s.cur];
   a.have_hist = have_hist;
   a.nstrips = (p.nx + kStripW - 1) / kStripW;
   a.seg_rows = s.tile_rows;
   a.ntiles = (int)step_blocks(p.nx, p.ny, s.tile_rows);
+  a.prev_partials = (fuse & kFusePrev) ? s.step_partials[s.cur ^ 1] : nullptr;
+  a.prev_have_hist = 1;
   {
     TimedScope ts(t, LBM_K_STEP, st);
     if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false>), dim3(a.ntiles), dim3(kBlock), 0, st, (const DevParams*)s.dparams, a);
     else hipLaunchKernelGGL((k_step<S, C, true>), dim3(a.ntiles), dim3(kBlock), 0, st, (const DevParams*)s.dparams, a);
   }
-  {
+  if (!(fuse & kFuseNext)) {
     TimedScope ts(t, LBM_K_FINISH, st);
     hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(kBlock), 0, st, (const double*)a.partials, a.ntiles, p.N, have_hist,
                        a.next);
@@ -1308,9 +1332,9 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
 }
 
 template <class S, class C>
-hipError_t step_impl(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer) {
+hipError_t step_impl(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer, int fuse) {
   StepTimer* t = (timer && timer->ev && timer->used < timer->max_steps) ? timer : nullptr;
-  launch_step<S, C>(p, s, have_hist, st, t);
+  launch_step<S, C>(p, s, have_hist, st, t, fuse);
   if (t) t->used += 1;
   s.cur ^= 1;
   s.hcur ^= 1;
@@ -1414,10 +1438,10 @@ hipError_t launch_step_batch(int precision, bool walls, const BatchCase* d_cases
                (batch_step_impl<float, float>(walls, d_cases, d_wg_case, nwg, count, st, timer)),
                (batch_step_impl<_Float16, float>(walls, d_cases, d_wg_case, nwg, count, st, timer)));
 }
-hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer) {
-  LBM_DISPATCH(s.precision, (step_impl<double, double>(p, s, have_hist, st, timer)),
-               (step_impl<float, float>(p, s, have_hist, st, timer)),
-               (step_impl<_Float16, float>(p, s, have_hist, st, timer)));
+hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer, int fuse) {
+  LBM_DISPATCH(s.precision, (step_impl<double, double>(p, s, have_hist, st, timer, fuse)),
+               (step_impl<float, float>(p, s, have_hist, st, timer, fuse)),
+               (step_impl<_Float16, float>(p, s, have_hist, st, timer, fuse)));
 }
 hipError_t launch_macro(const DevParams& p, DevState& s, hipStream_t st) {
   LBM_DISPATCH(s.precision, (macro_impl<double, double>(p, s, st)), (macro_impl<float, float>(p, s, st)),

@@ -174,9 +174,13 @@ class Sim:
     """One simulation on the current HIP device.
 
     Device memory comes from a torch uint8 tensor owned by this object and
-    work is ordered on torch's current stream (or the stream given)."""
+    work is ordered on torch's current stream (or the stream given).  `fill`,
+    if given, is a byte value written over that memory before lbm_init (the
+    tests fill it with 0xFF, a NaN in every floating-point format, to show that
+    nothing reads state the library has not written)."""
 
-    def __init__(self, cfg: dict, precision: str = "fp64", stream: "torch.cuda.Stream | None" = None):
+    def __init__(self, cfg: dict, precision: str = "fp64", stream: "torch.cuda.Stream | None" = None,
+                 fill: "int | None" = None):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible to torch; the lattice Boltzmann path has no CPU fallback")
         self.cfg = dict(cfg)
@@ -186,6 +190,9 @@ class Sim:
         nbytes = required_bytes(cfg, precision)
         self.buffer = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        if fill is not None:
+            with torch.cuda.stream(self.stream):
+                self.buffer.fill_(int(fill))
         h = ctypes.c_void_p()
         rc = lib().lbm_init(ctypes.byref(self.params), ctypes.c_void_p(self.buffer.data_ptr()), nbytes,
                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
@@ -306,7 +313,7 @@ class Batch:
     Device memory is one torch uint8 tensor; work runs on torch's current
     stream (or the stream given)."""
 
-    def __init__(self, cfgs: list, precision: str = "fp32", seg_rows: int = 0, stream=None):
+    def __init__(self, cfgs: list, precision: str = "fp32", seg_rows: int = 0, stream=None, fill: "int | None" = None):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible to torch; the lattice Boltzmann path has no CPU fallback")
         self.cfgs = [dict(c) for c in cfgs]
@@ -317,6 +324,9 @@ class Batch:
         _bcheck(lib().lbm_batch_required_bytes(self.params, n, ctypes.byref(nbytes)))
         self.buffer = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        if fill is not None:   # as Sim's fill
+            with torch.cuda.stream(self.stream):
+                self.buffer.fill_(int(fill))
         b = ctypes.c_void_p()
         _bcheck(lib().lbm_batch_init(self.params, n, int(seg_rows), ctypes.c_void_p(self.buffer.data_ptr()), nbytes.value,
                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(b)))
