@@ -692,6 +692,17 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     const int l = min(max(ln, 1), 62);   // lanes 0 and 63 have no neighbour column: computed, unused
     const double2 c = sPP[yc & (RP - 1)][l];
     const double ph = c.x, ps = c.y;
+    // Next to a wetting wall the wall values J of this row's columns l - 1,
+    // l, l + 1 enter: each lane evaluates them at its own column, the
+    // neighbours' come by lane shuffle (the row is wave-uniform).
+    const int wside = !WALLS ? 0 : (y == 0 ? -1 : (y == p.ny - 1 ? 1 : 0));
+    const bool wet = wside != 0 && wet_side(p, wside);
+    double jp = 0.0, js = 0.0;
+    if (wet) {
+      const double2 o = sPP[yc & (RP - 1)][ln];
+      jp = Jphi(p, o.x, o.y);
+      if (p.surf) js = Jpsi(p, o.x, o.y);
+    }
     Lap L{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
@@ -699,12 +710,9 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       const double2 nb = sPP[(yc + CY(i)) & (RP - 1)][l + CX(i)];
       L.l0p += w2 * (nb.x - ph);
       L.l0s += w2 * (nb.y - ps);
-      const int ny_ = y + CY(i);
-      if (WALLS && (ny_ < 0 || ny_ >= p.ny) && wet_side(p, ny_ < 0 ? -1 : 1)) {
-        // fluid node next to the ghost: same row, column x + c_x
-        const double2 f = sPP[yc & (RP - 1)][l + CX(i)];
-        L.Tp += w2 * Jphi(p, f.x, f.y);
-        if (p.surf) L.Ts += w2 * Jpsi(p, f.x, f.y);
+      if (wet && CY(i) == wside) {   // the fluid node next to the ghost: column x + c_x of this row
+        L.Tp += w2 * __shfl(jp, l + CX(i));
+        if (p.surf) L.Ts += w2 * __shfl(js, l + CX(i));
       }
     }
     const double mp = mu_phi_of(p, ph, ps, L), ms = mu_psi_of(p, ph, ps, L);
@@ -785,15 +793,24 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       g[i] += (C)(lam1 * WQ<double>(i) * (double)sHp[er][ec]);
       if (p.surf) h[i] += (C)(mub1 * WQ<double>(i));
     }
-    // gradients of phi (wetting ghosts), mu_phi, mu_psi; Laplacians of phi, psi
+    // gradients of phi (wetting ghosts), mu_phi, mu_psi; Laplacians of phi, psi.
+    // Next to a wetting wall the ghost row's phi takes J_phi / kappa: each lane
+    // evaluates J_phi at its own column of the ghost row, the neighbours' come
+    // by lane shuffle.
+    const int wside = !WALLS ? 0 : (gy == 0 ? -1 : (gy == p.ny - 1 ? 1 : 0));
+    const bool wet = wside != 0 && wet_side(p, wside);
+    double jg = 0.0;
+    if (wet) {
+      const double2 o = sPP[(gy + wside) & (RP - 1)][ln];
+      jg = Jphi(p, o.x, o.y);
+    }
     double gfx = 0, gfy = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0, l0p = 0, l0s = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const double w3 = 3.0 * WQ<double>(i), w2 = 2.0 * w3;
       const double2 nb = sPP[(gy + CY(i)) & (RP - 1)][lc + CX(i)];
-      const int ny_ = gy + CY(i);
       double q = nb.x;
-      if (WALLS && (ny_ < 0 || ny_ >= p.ny) && wet_side(p, ny_ < 0 ? -1 : 1)) q += Jphi(p, nb.x, nb.y) / p.kappa;
+      if (wet && CY(i) == wside) q += __shfl(jg, lc + CX(i)) / p.kappa;
       l0p += w2 * (nb.x - ph);
       l0s += w2 * (nb.y - ps);
       if (CX(i)) gfx += (CX(i) * w3) * q;
@@ -947,12 +964,21 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   }
 }
 
+// Workgroups per CU a step kernel is compiled for (MINB): the walled FP32 and
+// FP16 variants need a few more registers than three workgroups (12 waves)
+// per CU leave.  Compiled for three, they spill about a dozen values: faster
+// on grids of more workgroups than CUs (a 512 x 256 sheared drop: 24.4
+// against 30.5 us per step), slower when each CU holds one workgroup anyway
+// (the 256 x 128 sessile drop: 16.1 against 15.2 us).  The launch picks.
+template <class S> inline constexpr int kStepMinBlocks = sizeof(S) <= 4 ? 3 : 1;
+constexpr int kOccupancyTiles = 256;   // CUs of the MI355X
+
 // The parameter block is read from device memory (a copy the handle keeps),
 // as the batched kernel reads it: scalar loads on demand instead of a kernel
 // argument block held in (spilled) scalar registers, and the same code as the
 // batched step, hence the same results bit for bit.
-template <class S, class C, bool WALLS>
-__global__ __launch_bounds__(kBlock) void k_step(const DevParams* __restrict__ pp, StepArgs a) {
+template <class S, class C, bool WALLS, int MINB>
+__global__ __launch_bounds__(kBlock, MINB) void k_step(const DevParams* __restrict__ pp, StepArgs a) {
   step_body<S, C, WALLS>(*pp, a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
@@ -961,7 +987,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const DevParams* __restrict__ p
 // parameters, buffers, buffer parity and activity, so retired cases are
 // skipped and a captured graph of the launch stays valid.
 template <class S, class C, bool WALLS>
-__global__ __launch_bounds__(kBlock) void k_step_batch(const BatchCase* __restrict__ cases, const int* __restrict__ wg_case) {
+__global__ __launch_bounds__(kBlock, WALLS ? kStepMinBlocks<S> : 1) void k_step_batch(const BatchCase* __restrict__ cases,
+                                                                                    const int* __restrict__ wg_case) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int c = wave_uniform(wg_case[b]);
   const BatchCase& bc = cases[c];
@@ -1321,8 +1348,11 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
   a.prev_have_hist = 1;
   {
     TimedScope ts(t, LBM_K_STEP, st);
-    if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false>), dim3(a.ntiles), dim3(kBlock), 0, st, (const DevParams*)s.dparams, a);
-    else hipLaunchKernelGGL((k_step<S, C, true>), dim3(a.ntiles), dim3(kBlock), 0, st, (const DevParams*)s.dparams, a);
+    const DevParams* dp = (const DevParams*)s.dparams;
+    if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
+    else if (a.ntiles > kOccupancyTiles)
+      hipLaunchKernelGGL((k_step<S, C, true, kStepMinBlocks<S>>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
+    else hipLaunchKernelGGL((k_step<S, C, true, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
   }
   if (!(fuse & kFuseNext)) {
     TimedScope ts(t, LBM_K_FINISH, st);
