@@ -434,7 +434,7 @@ struct StepArgs {
   const void* hin;          // u, v (advecting), R_phi, R_psi of step n-1: 6 planes, compute type
   void* hout;               // the same for step n
   const DevScalars* pend;   // multipliers pending on Pin (from step n-1)
-  DevScalars* next;         // multipliers of step n, written by the last tile
+  DevScalars* next;         // multipliers of step n, written by k_step_finish
   double* partials;         // [ntiles][3]
   int have_hist, nstrips, seg_rows, ntiles;
   // Non-null: the multipliers pending on Pin are reduced here, by every
@@ -556,7 +556,8 @@ template <class T> __device__ __forceinline__ T opaque_v(T v) {   // the same fo
 // segment wait in LDS (as stored) for that row's collision, so C gathers
 // only f from memory.  At a wall the ghost rows beyond it hold the nearest
 // fluid row's values (computed again, not copied).
-// k_step_finish then reduces the block sums to lambda(n), mubar(n).
+// k_step_finish then reduces the block sums to lambda(n), mubar(n) (or, on
+// small grids inside a captured run, the next step's workgroups do).
 template <class S, class C, bool WALLS>
 __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a, const int tile) {
   constexpr int RP = 16, RM = 8;           // ring rows: h' and (phi, psi); (mu_phi, mu_psi)

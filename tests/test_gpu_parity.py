@@ -128,6 +128,19 @@ def test_fp16_shifted_storage_errors(lbm, name, steps):
         assert gi["contact_width"] == pytest.approx(oi["contact_width"], abs=0.02)
 
 
+def test_fp16_walls_many_workgroups(lbm):
+    """FP16 storage on the full 512x256 sheared drop: 576 workgroups, more than
+    the chip has CUs, so the walled step built for three workgroups per CU
+    runs (the FP32 build is covered by the full-size FP32 test)."""
+    cfg = inputs.shear_drop(Ca=0.2)
+    e, gi, oi, m0 = fp16_errors(lbm, cfg, 150)
+    print("shear 512x256 fp16 errors", {k: float("%.3g" % v) for k, v in e.items()})
+    bad = {k: v for k, v in e.items() if not v <= FP16_TOL[k]}
+    assert not bad, (bad, e)
+    assert gi["nonfinite"] == 0
+    assert abs(gi["mass_psi"] - m0) / m0 < 5e-6
+
+
 def test_stationary_drop_1000_steps(lbm):
     """Plain method, FP64, 2-D periodic 64x64 stationary droplet, 1000 steps:
     fields within 1e-10, surfactant mass drift below 1e-12 relative."""
