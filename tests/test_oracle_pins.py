@@ -324,3 +324,56 @@ def test_young_contact_angle_sec43():
         inv = s.invariants()
         assert inv["theta_app_deg"] == pytest.approx(th, abs=2.5)
         assert (inv["theta_app_deg"] - 90.0) * (th - 90.0) > 0
+
+
+def test_laplacian_exact_on_quadratic_field_sec3():
+    """The isotropic 9-point Laplacian (end of Sec. 3) is exact on quadratic
+    fields: loading phi = a x^2 + b y^2 + c x y + linear terms with psi = 0,
+    mu_phi - 4 beta (phi^3 - phi) = -kappa (2a + 2b) at every node away from
+    the periodic seam.  A wrong weight, a dropped diagonal or an asymmetric
+    pair of directions (which the xy term would expose) breaks it."""
+    cfg = inputs.stationary_drop(nx=32, ny=32, psi_b=0.0)
+    s = sim(cfg)
+    d = s.derived()
+    y, x = np.mgrid[0:32, 0:32].astype(float)
+    a, b, c = 1.3e-4, -0.7e-4, 0.9e-4
+    phi = 0.2 + a * (x - 15.5) ** 2 + b * (y - 16.2) ** 2 + c * (x - 15.5) * (y - 16.2) + 2e-3 * x - 1e-3 * y
+    s.load_fields(phi, np.zeros_like(phi))
+    f = s.fields(["phi", "mu_phi"])
+    lap = (f["mu_phi"] - 4.0 * d["beta"] * (f["phi"] ** 3 - f["phi"])) / (-d["kappa"])
+    assert np.abs(lap[2:-2, 2:-2] - 2.0 * (a + b)).max() < 1e-9 * abs(2.0 * (a + b))
+
+
+def test_total_energy_decreases_sec24():
+    """Energy-dissipation law (Sec. 2.4, Theorem 1): in a closed domain (no-slip
+    walls, periodic in x) without gravity the free energy, wall energy included,
+    plus the kinetic energy never increases while a surfactant-laden sessile
+    drop relaxes towards its angle."""
+    cfg = inputs.sessile_drop(nx=64, ny=32, R=12.0, theta0_deg=60.0, psi_b=0.02)
+    cfg["bc_top"] = inputs.NOSLIP
+    s = sim(cfg)
+    E = []
+    for _ in range(30):
+        inv = s.invariants()
+        E.append(inv["free_energy"] + inv["kinetic"])
+        s.step(100)
+    d = np.diff(E)
+    assert (d <= 0.0).all(), d.max()
+    assert E[-1] < E[0]
+
+
+def test_adsorption_shifts_contact_angle_sec44():
+    """Preferential adsorption (Sec. 4.4): surfactant adsorbing preferentially at
+    the solid-liquid interface (beta_sl > beta_sg) lowers the contact angle
+    below the clean one (hydrophilization), preferential solid-gas adsorption
+    raises it (autophobing).  The size follows an approximate modified Young
+    law, so only the direction is pinned."""
+    ang = {}
+    for tag, kw in (("clean", dict(psi_b=0.0)), ("sg", dict(psi_b=0.05, beta_sg=0.5, beta_sl=0.01)),
+                    ("sl", dict(psi_b=0.05, beta_sg=0.01, beta_sl=0.5))):
+        cfg = inputs.sessile_drop(nx=64, ny=32, R=12.0, theta0_deg=90.0, **kw)
+        cfg["bc_top"] = inputs.NOSLIP
+        s = sim(cfg)
+        s.step(8000)
+        ang[tag] = s.invariants()["theta_app_deg"]
+    assert ang["sl"] < ang["clean"] - 0.3 < ang["sg"] - 0.6, ang
