@@ -277,6 +277,23 @@ __device__ double block_reduce(double v, bool is_max) {
   return v;
 }
 
+// block_reduce's sum for blocks of kBlock or more threads: threads from kBlock
+// on contribute nothing, and the sum is formed as a kBlock block forms it.
+__device__ double block_sum_first(double v) {
+  __shared__ double sh[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  v = wave_red(v, false);
+  if (lane == 0 && wid < kBlock / 64) sh[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int k = 1; k < kBlock / 64; ++k) r = r + sh[k];
+    v = r;
+  }
+  __syncthreads();
+  return v;
+}
+
 // ------------------------------------------------------------------- kernels
 // Node (x, y) of the source of gathered population i (its emitter): x - c_i
 // inside the fluid, the node itself for a bounce-back at a wall.
@@ -456,16 +473,18 @@ struct StepArgs {
 __device__ __forceinline__ DevScalars multipliers_of(const double* __restrict__ partials, int ntiles, int N,
                                                     int have_hist) {
   double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  if (threadIdx.x < kBlock) {   // larger blocks: the first kBlock threads, as k_step_finish
 #pragma unroll 4
-  for (int b = threadIdx.x; b < ntiles; b += kBlock) {
-    t1 += partials[3 * (size_t)b + 0];
-    t2 += partials[3 * (size_t)b + 1];
-    t3 += partials[3 * (size_t)b + 2];
+    for (int b = threadIdx.x; b < ntiles; b += kBlock) {
+      t1 += partials[3 * (size_t)b + 0];
+      t2 += partials[3 * (size_t)b + 1];
+      t3 += partials[3 * (size_t)b + 2];
+    }
   }
-  t1 = block_reduce(t1, false);
-  t2 = block_reduce(t2, false);
-  t3 = block_reduce(t3, false);
-  __shared__ DevScalars res;   // block_reduce leaves the sums in thread 0 only
+  t1 = block_sum_first(t1);
+  t2 = block_sum_first(t2);
+  t3 = block_sum_first(t3);
+  __shared__ DevScalars res;   // the sums are in thread 0 only
   if (threadIdx.x == 0) {
     res.lambda_phi = t2 > 0.0 ? t1 / t2 : 0.0;
     res.mubar_psi = t3 / (double)N;
@@ -558,7 +577,7 @@ template <class T> __device__ __forceinline__ T opaque_v(T v) {   // the same fo
 // fluid row's values (computed again, not copied).
 // k_step_finish then reduces the block sums to lambda(n), mubar(n) (or, on
 // small grids inside a captured run, the next step's workgroups do).
-template <class S, class C, bool WALLS>
+template <class S, class C, bool WALLS, bool ONESHOT = false>
 __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a, const int tile) {
   constexpr int RP = 16, RM = 8;           // ring rows: h' and (phi, psi); (mu_phi, mu_psi)
   __shared__ C sHp[RP][kStripW + 6];       // h'(phi(n-1)), columns X0-3 .. X0+62
@@ -917,6 +936,52 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     }
   };
 
+  if constexpr (ONESHOT) {
+    // ---- one tile of four rows [Y0, Yend) with eight waves (small grids):
+    // every phase takes all its rows at once -- wave w: h' of rows Y0-3+w
+    // (and Y0+5+w for w < 2), phi, psi of row Y0-2+w, mu of row Y0-1+w
+    // (w < 6), the collision of row Y0+w (w < 4) -- and every load is issued
+    // before the first wait.  The phases are those of the sweep on the same
+    // rows, and the tile's sums are added in the order of the sweep's waves
+    // (rows Y0+1, Y0+2, Y0+3, Y0), so the results equal the sweep's bit for bit.
+    constexpr bool preA = GH;
+    C f[9], g[9], h[9], tg[9], th[9];
+    double r0[2], v0[4], v1[4];
+    const int rc = Y0 + wave;
+    const bool collide = wave < 4 && rc < Yend;
+    gather_H(Y0 - 3 + wave, lane, xcol, v0);
+    if (wave < 2) gather_H(Y0 + 5 + wave, lane, xcol, v1);
+    if (preA) gather_A(Y0 - 2 + wave, xcol, tg, th, r0);
+    if (collide) gather_C(rc, xcol, f, g, h);
+    row_H(Y0 - 3 + wave, lane, v0);
+    if (wave < 2) row_H(Y0 + 5 + wave, lane, v1);
+    __syncthreads();
+    if (!preA) gather_A(Y0 - 2 + wave, xcol, tg, th, r0);
+    row_A(Y0 - 2 + wave, lane, xcol, tg, th, r0);
+    __syncthreads();
+    if (wave < 6) row_B(Y0 - 1 + wave, lane);
+    __syncthreads();
+    if (collide) row_C(rc, lane, xcol, f, g, h);
+    __shared__ double sR[3][8];
+    const double q[3] = {wave_red(s1, false), wave_red(s2, false), wave_red(s3, false)};
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sR[c][wave] = q[c];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double r = sR[c][2];   // rows Y0+1, Y0+2, Y0+3, Y0 are those of waves 2, 3, 4, 1
+        r = r + sR[c][3];
+        r = r + sR[c][4];
+        r = r + sR[c][1];
+        a.partials[3 * (size_t)tile + c] = r;
+      }
+    }
+    return;
+  }
+
   // ---- the sweep.  Iteration k collides rows Y0+4k .. Y0+4k+3 (k = -1 only
   // fills the rings).  Ring lifetimes: H writes rows <= 15 ahead of the oldest
   // h' row C still reads; A writes <= 10 rows ahead of the oldest (phi, psi)
@@ -981,6 +1046,13 @@ constexpr int kOccupancyTiles = 256;   // CUs of the MI355X
 template <class S, class C, bool WALLS, int MINB>
 __global__ __launch_bounds__(kBlock, MINB) void k_step(const DevParams* __restrict__ pp, StepArgs a) {
   step_body<S, C, WALLS>(*pp, a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Small grids (at most one workgroup of four rows per CU): the one-shot
+// schedule of a tile with eight waves.
+template <class S, class C, bool WALLS>
+__global__ __launch_bounds__(2 * kBlock) void k_step_small(const DevParams* __restrict__ pp, StepArgs a) {
+  step_body<S, C, WALLS, true>(*pp, a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Batched step: one launch over the workgroups of every case of a batch
@@ -1350,7 +1422,10 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
   {
     TimedScope ts(t, LBM_K_STEP, st);
     const DevParams* dp = (const DevParams*)s.dparams;
-    if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
+    if (a.seg_rows == 4 && a.ntiles <= kOccupancyTiles) {   // small grid: one-shot tiles
+      if (p.periodic_y) hipLaunchKernelGGL((k_step_small<S, C, false>), dim3(a.ntiles), dim3(2 * kBlock), 0, st, dp, a);
+      else hipLaunchKernelGGL((k_step_small<S, C, true>), dim3(a.ntiles), dim3(2 * kBlock), 0, st, dp, a);
+    } else if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
     else if (a.ntiles > kOccupancyTiles)
       hipLaunchKernelGGL((k_step<S, C, true, kStepMinBlocks<S>>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
     else hipLaunchKernelGGL((k_step<S, C, true, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
