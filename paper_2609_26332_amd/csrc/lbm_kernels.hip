@@ -602,11 +602,17 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   const S* __restrict__ Pin = (const S*)a.Pin;
   S* __restrict__ Pout = (S*)a.Pout;
   const double* __restrict__ ref = a.ref;
-  // multipliers pending on Pin: reduced here from the previous step's sums
-  // (small grids inside a captured run of steps) or as k_step_finish left them
-  const DevScalars pend = a.prev_partials ? multipliers_of(a.prev_partials, a.ntiles, p.N, a.prev_have_hist) : *a.pend;
-  const double lam1_ = pend.cdef * p.M_phi * pend.lambda_phi;   // pending term weights
-  const double mub1_ = pend.cdef * p.M_psi * pend.mubar_psi;
+  // The multipliers pending on Pin and their weights in the pending terms,
+  // set by set_pend() before phase A first runs: reduced from the previous
+  // step's sums (small grids inside a captured run) or as k_step_finish left
+  // them.
+  DevScalars pend;
+  double lam1_ = 0.0, mub1_ = 0.0;
+  auto set_pend = [&]() {
+    pend = a.prev_partials ? multipliers_of(a.prev_partials, a.ntiles, p.N, a.prev_have_hist) : *a.pend;
+    lam1_ = pend.cdef * p.M_phi * pend.lambda_phi;
+    mub1_ = pend.cdef * p.M_psi * pend.mubar_psi;
+  };
   const int lane = threadIdx.x & 63;
   const int wave = wave_uniform(threadIdx.x >> 6);
   // fluid row of a (possibly ghost or wrapped) row index
@@ -953,6 +959,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     if (wave < 2) gather_H(Y0 + 5 + wave, lane, xcol, v1);
     if (preA) gather_A(Y0 - 2 + wave, xcol, tg, th, r0);
     if (collide) gather_C(rc, xcol, f, g, h);
+    set_pend();   // its loads (if any) are in flight with the gathers
     row_H(Y0 - 3 + wave, lane, v0);
     if (wave < 2) row_H(Y0 + 5 + wave, lane, v1);
     __syncthreads();
@@ -982,6 +989,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     return;
   }
 
+  set_pend();
   // ---- the sweep.  Iteration k collides rows Y0+4k .. Y0+4k+3 (k = -1 only
   // fills the rings).  Ring lifetimes: H writes rows <= 15 ahead of the oldest
   // h' row C still reads; A writes <= 10 rows ahead of the oldest (phi, psi)
