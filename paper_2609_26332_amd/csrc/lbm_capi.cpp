@@ -41,7 +41,7 @@ struct Layout {
 
 Layout make_layout(const lbm_params& p) {
   const size_t N = (size_t)p.nx * (size_t)p.ny;
-  const size_t sb = lbm::storage_bytes(p.precision), cb = lbm::compute_bytes(p.precision);
+  const size_t cb = lbm::compute_bytes(p.precision);
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
@@ -184,7 +184,7 @@ void carve(lbm_handle* h) {
   char* b = (char*)h->buf;
   const Layout& L = h->lay;
   const size_t N = (size_t)h->dp.N;
-  const size_t sb = lbm::storage_bytes(h->prm.precision), cb = lbm::compute_bytes(h->prm.precision);
+  const size_t cb = lbm::compute_bytes(h->prm.precision);
   lbm::DevState& s = h->ds;
   s.precision = h->prm.precision;
   s.pops[0] = b + L.pops;
@@ -411,7 +411,7 @@ int lbm_load_fields(lbm_handle* h, uint32_t mask, const double* host, size_t n_d
 int lbm_state_bytes(lbm_handle* h, size_t* bytes) {
   if (!h || !bytes) return fail(h, LBM_E_ARG, "null argument");
   const size_t N = (size_t)h->dp.N;
-  const size_t sb = lbm::storage_bytes(h->prm.precision), cb = lbm::compute_bytes(h->prm.precision);
+  const size_t cb = lbm::compute_bytes(h->prm.precision);
   *bytes = sizeof(StateHeader) + lbm::pops_bytes(h->prm.precision, N) + 2 * N * sizeof(double) + 6 * N * cb;
   return LBM_OK;
 }
@@ -422,7 +422,7 @@ int lbm_save_state(lbm_handle* h, void* host, size_t bytes) {
   if (rc) return rc;
   if (!host || bytes < need) return fail(h, LBM_E_ARG, "state buffer too small");
   const size_t N = (size_t)h->dp.N;
-  const size_t sb = lbm::storage_bytes(h->prm.precision), cb = lbm::compute_bytes(h->prm.precision);
+  const size_t cb = lbm::compute_bytes(h->prm.precision);
   StateHeader hd{kStateMagic, h->prm.precision, h->prm.nx, h->prm.ny, h->have_hist, h->step, hash_bytes(&h->prm, sizeof(h->prm)), {0, 0, 0}};
   HIP_OR_FAIL(h, hipMemcpyAsync(hd.pending, h->ds.scalars + h->ds.scur, sizeof(hd.pending), hipMemcpyDeviceToHost, h->stream), "save");
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream), "synchronise");
@@ -450,7 +450,7 @@ int lbm_load_state(lbm_handle* h, const void* host, size_t bytes) {
       hd.params_hash != hash_bytes(&h->prm, sizeof(h->prm)))
     return fail(h, LBM_E_ARG, "state blob does not match this handle's parameters");
   const size_t N = (size_t)h->dp.N;
-  const size_t sb = lbm::storage_bytes(h->prm.precision), cb = lbm::compute_bytes(h->prm.precision);
+  const size_t cb = lbm::compute_bytes(h->prm.precision);
   const char* o = (const char*)host + sizeof(hd);
   const int hp = h->ds.hcur ^ 1;
   HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.pops[h->ds.cur], o, lbm::pops_bytes(h->prm.precision, N), hipMemcpyHostToDevice, h->stream), "load");
