@@ -137,3 +137,32 @@ def test_batch_no_read_of_unwritten_state(lbm):
             assert np.array_equal(fa[name], fb[name]), (k, name)
     a.close()
     b.close()
+
+
+def test_full_sweep_batch_in_bench_configuration(lbm):
+    """The batched sweep at its full size and as bench.py runs it: the 512 cases
+    of the sweep distribution (seed 2000, grids 64x32 .. 368x184), FP32 storage,
+    the batch's own autotuned segment height, 100 graph-replayed steps.  Every
+    case stays finite and keeps its surfactant mass; three cases (the smallest,
+    a middle and the largest grid) match the FP64 oracle node by node within
+    the FP32 tolerance."""
+    from paper_2609_26332_amd import sweep
+
+    cases = sweep.batch_cases(2000, 512)
+    b = lbm.Batch(cases, "fp32")
+    b.autotune(trial_steps=4)
+    m0 = [v["mass_psi"] for v in b.invariants(check=False)]
+    b.step(100)
+    inv = b.invariants(check=False)
+    assert sum(v["nonfinite"] for v in inv) == 0
+    drift = max(abs(v["mass_psi"] - m) / m for v, m in zip(inv, m0))
+    assert drift < 1e-5, drift
+    sizes = [c["nx"] * c["ny"] for c in cases]
+    order = sorted(range(len(cases)), key=lambda k: sizes[k])
+    for k in (order[0], order[len(order) // 2], order[-1]):
+        cfg = cases[k]
+        o = oracle.OracleSim(cfg)
+        o.step(100)
+        u = 1e-3 * max(cfg.get("sigma_gl0", 0.01) / cfg.get("mu_l", 0.1), abs(cfg.get("u_wall_top", 0.0)))
+        assert_fields_close(b.fields(k, FIELDS), o.fields(FIELDS), 1e-5, u, 1e-3 * 0.01 / cfg["R0"], f"sweep case {k}")
+    b.close()
