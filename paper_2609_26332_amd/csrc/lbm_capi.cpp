@@ -212,7 +212,7 @@ void carve(lbm_handle* h) {
   s.hcur = 0;
 }
 
-int check_device(std::string& why) {
+int check_device(std::string& why, int* cus = nullptr) {
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) { why = "no HIP device"; return LBM_E_DEVICE; }
   int dev = 0;
@@ -220,6 +220,7 @@ int check_device(std::string& why) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) { why = "hipGetDeviceProperties failed"; return LBM_E_DEVICE; }
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) { why = std::string("device is ") + prop.gcnArchName + ", not gfx950"; return LBM_E_DEVICE; }
+  if (cus) *cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   return LBM_OK;
 }
 
@@ -245,7 +246,8 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
   h->prm = *p;
   std::string why = derive(*p, h->dp, h->derived);
   if (!why.empty()) { delete h; return fail(nullptr, LBM_E_ARG, why); }
-  int dc = check_device(why);
+  int cus = 256;
+  int dc = check_device(why, &cus);
   if (dc != LBM_OK) { delete h; return fail(nullptr, dc, why); }
   h->lay = make_layout(*p);
   if (dev_buf) {
@@ -266,6 +268,7 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
     h->own_stream = true;
   }
   carve(h);
+  h->ds.cus = cus;
   hipError_t e = hipMemcpyAsync(h->ds.dparams, &h->dp, sizeof(h->dp), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = lbm::launch_init(h->dp, h->ds, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

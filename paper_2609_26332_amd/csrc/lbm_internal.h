@@ -66,6 +66,7 @@ struct DevState {
   DevParams* dparams;      // device copy of the parameter block (read by the step kernel)
   int scur;                // scalars[scur] holds the multipliers pending on the stored populations
   int tile_rows;           // rows per workgroup segment of the step kernel (a multiple of 4)
+  int cus = 256;           // compute units of the device (the step kernel's variant choice)
   int cur;                 // index of the current population buffer
   int hcur;                // phi/psi and history buffer written by the next step
 };

@@ -1045,7 +1045,6 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
 // against 30.5 us per step), slower when each CU holds one workgroup anyway
 // (the 256 x 128 sessile drop: 16.1 against 15.2 us).  The launch picks.
 template <class S> inline constexpr int kStepMinBlocks = sizeof(S) <= 4 ? 3 : 1;
-constexpr int kOccupancyTiles = 256;   // CUs of the MI355X
 
 // The parameter block is read from device memory (a copy the handle keeps),
 // as the batched kernel reads it: scalar loads on demand instead of a kernel
@@ -1430,11 +1429,13 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
   {
     TimedScope ts(t, LBM_K_STEP, st);
     const DevParams* dp = (const DevParams*)s.dparams;
-    if (a.seg_rows == 4 && a.ntiles <= kOccupancyTiles) {   // small grid: one-shot tiles
+    // the choice depends on the number of workgroups against the device's CUs
+    // (256 on an MI355X); every variant gives the same results
+    if (a.seg_rows == 4 && a.ntiles <= s.cus) {   // small grid: one-shot tiles
       if (p.periodic_y) hipLaunchKernelGGL((k_step_small<S, C, false>), dim3(a.ntiles), dim3(2 * kBlock), 0, st, dp, a);
       else hipLaunchKernelGGL((k_step_small<S, C, true>), dim3(a.ntiles), dim3(2 * kBlock), 0, st, dp, a);
     } else if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
-    else if (a.ntiles > kOccupancyTiles)
+    else if (a.ntiles > s.cus)
       hipLaunchKernelGGL((k_step<S, C, true, kStepMinBlocks<S>>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
     else hipLaunchKernelGGL((k_step<S, C, true, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
   }
