@@ -577,7 +577,10 @@ template <class T> __device__ __forceinline__ T opaque_v(T v) {   // the same fo
 // fluid row's values (computed again, not copied).
 // k_step_finish then reduces the block sums to lambda(n), mubar(n) (or, on
 // small grids inside a captured run, the next step's workgroups do).
-template <class S, class C, bool WALLS, bool ONESHOT = false>
+// Schedules of step_body: the sweep, or one tile of four rows in one pass with
+// eight waves (kOneShot8) or four (kOneShot4).
+enum { kSweep = 0, kOneShot8 = 1, kOneShot4 = 2 };
+template <class S, class C, bool WALLS, int SCHED = kSweep>
 __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a, const int tile) {
   constexpr int RP = 16, RM = 8;           // ring rows: h' and (phi, psi); (mu_phi, mu_psi)
   __shared__ C sHp[RP][kStripW + 6];       // h'(phi(n-1)), columns X0-3 .. X0+62
@@ -942,7 +945,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     }
   };
 
-  if constexpr (ONESHOT) {
+  if constexpr (SCHED == kOneShot8) {
     // ---- one tile of four rows [Y0, Yend) with eight waves (small grids):
     // every phase takes all its rows at once -- wave w: h' of rows Y0-3+w
     // (and Y0+5+w for w < 2), phi, psi of row Y0-2+w, mu of row Y0-1+w
@@ -985,6 +988,51 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
         r = r + sR[c][1];
         a.partials[3 * (size_t)tile + c] = r;
       }
+    }
+    return;
+  }
+
+  if constexpr (SCHED == kOneShot4) {
+    // ---- one tile of four rows with four waves, each taking in every phase
+    // the rows the sweep gives it for a 4-row segment (h' rows Y0-3+w, Y0+1+w,
+    // Y0+5+w (w < 2); phi, psi rows Y0-2+w and Y0+2+w; mu rows Y0-3+w (w >= 2)
+    // and Y0+1+w; the collision of row Y0+w), in the same order, but with all
+    // loads issued before the first wait and no pipelining across rows: the
+    // same results bit for bit, three dependent phases less.
+    constexpr bool preA = GH;
+    C f[9], g[9], h[9], tg0[9], th0[9], tg1[9], th1[9];
+    double r00[2], r01[2], v0[4], v1[4], v2[4];
+    const int rc = Y0 + wave;
+    const bool collide = rc < Yend;
+    gather_H(Y0 - 3 + wave, lane, xcol, v0);
+    gather_H(Y0 + 1 + wave, lane, xcol, v1);
+    if (wave < 2) gather_H(Y0 + 5 + wave, lane, xcol, v2);
+    if (preA) {
+      gather_A(Y0 - 2 + wave, xcol, tg0, th0, r00);
+      gather_A(Y0 + 2 + wave, xcol, tg1, th1, r01);
+    }
+    if (collide) gather_C(rc, xcol, f, g, h);
+    set_pend();   // its loads (if any) are in flight with the gathers
+    row_H(Y0 - 3 + wave, lane, v0);
+    row_H(Y0 + 1 + wave, lane, v1);
+    if (wave < 2) row_H(Y0 + 5 + wave, lane, v2);
+    __syncthreads();
+    if (!preA) gather_A(Y0 - 2 + wave, xcol, tg0, th0, r00);
+    row_A(Y0 - 2 + wave, lane, xcol, tg0, th0, r00);
+    if (!preA) gather_A(Y0 + 2 + wave, xcol, tg1, th1, r01);
+    row_A(Y0 + 2 + wave, lane, xcol, tg1, th1, r01);
+    __syncthreads();
+    if (wave >= 2) row_B(Y0 - 3 + wave, lane);
+    row_B(Y0 + 1 + wave, lane);
+    __syncthreads();
+    if (collide) row_C(rc, lane, xcol, f, g, h);
+    s1 = block_reduce(s1, false);
+    s2 = block_reduce(s2, false);
+    s3 = block_reduce(s3, false);
+    if (threadIdx.x == 0) {
+      a.partials[3 * (size_t)tile + 0] = s1;
+      a.partials[3 * (size_t)tile + 1] = s2;
+      a.partials[3 * (size_t)tile + 2] = s3;
     }
     return;
   }
@@ -1059,7 +1107,12 @@ __global__ __launch_bounds__(kBlock, MINB) void k_step(const DevParams* __restri
 // schedule of a tile with eight waves.
 template <class S, class C, bool WALLS>
 __global__ __launch_bounds__(2 * kBlock) void k_step_small(const DevParams* __restrict__ pp, StepArgs a) {
-  step_body<S, C, WALLS, true>(*pp, a, xcd_tile(blockIdx.x, gridDim.x));
+  step_body<S, C, WALLS, kOneShot8>(*pp, a, xcd_tile(blockIdx.x, gridDim.x));
+}
+// Grids of up to three such workgroups per CU: the same tile with four waves.
+template <class S, class C, bool WALLS>
+__global__ __launch_bounds__(kBlock, kStepMinBlocks<S>) void k_step_mid(const DevParams* __restrict__ pp, StepArgs a) {
+  step_body<S, C, WALLS, kOneShot4>(*pp, a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Batched step: one launch over the workgroups of every case of a batch
@@ -1434,6 +1487,9 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
     if (a.seg_rows == 4 && a.ntiles <= s.cus) {   // small grid: one-shot tiles
       if (p.periodic_y) hipLaunchKernelGGL((k_step_small<S, C, false>), dim3(a.ntiles), dim3(2 * kBlock), 0, st, dp, a);
       else hipLaunchKernelGGL((k_step_small<S, C, true>), dim3(a.ntiles), dim3(2 * kBlock), 0, st, dp, a);
+    } else if (a.seg_rows == 4 && a.ntiles <= kStepMinBlocks<S> * s.cus) {   // mid-size grid
+      if (p.periodic_y) hipLaunchKernelGGL((k_step_mid<S, C, false>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
+      else hipLaunchKernelGGL((k_step_mid<S, C, true>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
     } else if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
     else if (a.ntiles > s.cus)
       hipLaunchKernelGGL((k_step<S, C, true, kStepMinBlocks<S>>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);

@@ -166,3 +166,22 @@ def test_full_sweep_batch_in_bench_configuration(lbm):
         u = 1e-3 * max(cfg.get("sigma_gl0", 0.01) / cfg.get("mu_l", 0.1), abs(cfg.get("u_wall_top", 0.0)))
         assert_fields_close(b.fields(k, FIELDS), o.fields(FIELDS), 1e-5, u, 1e-3 * 0.01 / cfg["R0"], f"sweep case {k}")
     b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_one_pass_tiles_equal_the_sweep(lbm, prec):
+    """A single handle on a grid of 4-row segments runs the one-pass tile
+    kernels (eight waves up to one workgroup per CU, four waves up to three),
+    a batch of the same case the row sweep: the results agree bit for bit."""
+    for cfg in (inputs.sessile_drop(), inputs.shear_drop(Ca=0.2)):
+        s = lbm.Sim(dict(cfg, tile_rows=4), prec)
+        b = lbm.Batch([cfg], prec, seg_rows=4)
+        assert b.info()["seg_rows"] == 4
+        for n in (1, 40):
+            s.step(n)
+            b.step(n)
+        fs, fb = s.fields(FIELDS), b.fields(0, FIELDS)
+        for k in FIELDS:
+            assert np.array_equal(fs[k], fb[k]), (cfg["nx"], prec, k)
+        s.close()
+        b.close()
