@@ -342,3 +342,16 @@ def test_no_read_of_unwritten_state(lbm, prec):
                 assert np.array_equal(fa[k], fb[k]), (prec, n, k)
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_ragged_mid_size_grid(lbm, prec, tol):
+    """A ragged walled grid of 567 four-row workgroups (500 x 250: the last
+    strip 20 columns wide, the last segment two rows high), which the
+    four-wave tile kernel takes in FP32 (the sweep in FP64), against the oracle."""
+    cfg = inputs.shear_drop(nx=500, ny=250, R=50.0, Ca=0.2)
+    g = lbm.Sim(cfg, prec)
+    o = oracle.OracleSim(cfg)
+    g.step(60)
+    o.step(60)
+    assert_fields_close(g.fields(FIELDS), o.fields(FIELDS), tol, u_scale(cfg), p_scale(cfg), f"500x250 {prec}")
