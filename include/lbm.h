@@ -149,8 +149,12 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
 /* Enqueue n time steps (n >= 0).  Asynchronous: returns once the work is on
  * the stream.  Faults in the fields surface at the next synchronising call.
  * Runs of 32 steps are replayed from a HIP graph the handle captures on first
- * use (same kernels, same results bit for bit); steps while kernel timing is
- * active are launched one by one. */
+ * use (same results bit for bit; on grids of at most 1024 workgroups the
+ * captured steps reduce the previous step's multiplier sums themselves, in
+ * the same order); steps while kernel timing is active are launched one by
+ * one.  The step kernel's schedule (row sweep, or one-pass 4-row tiles on
+ * grids of few workgroups per CU) depends on the grid and tile_rows, never the
+ * results. */
 int lbm_step(lbm_handle* h, int64_t n);
 
 /* Diagnostics of the current state (FP64 sums on the device), then one small
