@@ -152,9 +152,10 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
  * use (same results bit for bit; on grids of at most 1024 workgroups the
  * captured steps reduce the previous step's multiplier sums themselves, in
  * the same order); steps while kernel timing is active are launched one by
- * one.  The step kernel's schedule (row sweep, or one-pass 4-row tiles on
- * grids of few workgroups per CU) depends on the grid and tile_rows, never the
- * results. */
+ * one.  For a given tile_rows the step kernel's schedule (row sweep, or
+ * one-pass 4-row tiles on grids of few workgroups per CU) does not change the
+ * results; tile_rows itself groups the multiplier sums, so it changes their
+ * last bits. */
 int lbm_step(lbm_handle* h, int64_t n);
 
 /* Diagnostics of the current state (FP64 sums on the device), then one small
