@@ -81,11 +81,17 @@ def sessile_drop(nx: int = 256, ny: int = 128, R: float = 40.0, theta0_deg: floa
 def shear_drop(nx: int = 512, ny: int = 256, R: float = 64.0, Ca: float = 0.1,
                betas=(0.9, 0.01), psi_b: float = 0.01, **kw) -> dict:
     """Droplet under shear: top wall moving at u_w = Ca sigma0 / mu_l, density
-    and viscosity ratio 10, theta0 = 90 deg, adsorption on the bottom wall."""
-    mu_l = 0.1
+    and viscosity ratio 10, theta0 = 90 deg, adsorption on the bottom wall.
+
+    Units of the gas, as in the paper's high-density-ratio tests (Sec. 4):
+    rho_g = 1, mu_g = 0.1, rho_l = 10, mu_l = 1, so nu = 0.1 in both phases.
+    The same ratios with rho_g = 0.1 are unstable at sigma0 = 0.01 and W = 4:
+    the capillary stiffness of phi makes a grid-scale compression mode
+    oscillate at about one radian per step in the light phase."""
+    mu_l = 1.0
     cfg = _base(nx=nx, ny=ny, bc_bottom=WALL_WET, bc_top=NOSLIP, psi_b=psi_b,
                 theta0_deg=90.0, beta_sg=betas[0], beta_sl=betas[1],
-                rho_l=1.0, rho_g=0.1, mu_l=mu_l, mu_g=0.01,
+                rho_l=10.0, rho_g=1.0, mu_l=mu_l, mu_g=0.1,
                 u_wall_top=Ca * 0.01 / mu_l, x0=nx / 4.0, y0=-0.5, R0=R)
     cfg.update(kw)
     return cfg
