@@ -945,23 +945,263 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     }
   };
 
+  // ---- C split over two waves per row (the eight-wave tile): wave w < 4 takes
+  // the force, velocity, pressure and f collision of row Y0 + w, wave w + 4 the
+  // g and h collisions of the same row, so that every SIMD interleaves two
+  // waves through the heaviest phase.  The velocity goes through LDS across
+  // one barrier that every wave of the workgroup reaches once (active or not).
+  // The arithmetic is row_C's, term for term.
+  __shared__ double2 sU[SCHED == kOneShot8 ? 4 : 1][SCHED == kOneShot8 ? 64 : 1];
+  auto gather_Cf = [&](int gy, unsigned x, C* f) {
+    const size_t N = opaque((size_t)p.N);
+    const unsigned xs = x * sizeof(S), xsm = colm(x) * sizeof(S), xsp = colp(x) * sizeof(S);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = pull_row<S, C, WALLS, 0>(p, Pin, N, i, gy, xsm, xs, xsp);
+  };
+  // g, h of a collision row (FP64 storage: FP32 and FP16 keep A's in LDS) and
+  // the history the row reads: phi, psi(n-1); u, v and the stored R of step n-1
+  auto gather_Cgh = [&](int gy, unsigned x, C* g, C* h, double* hv) {
+    const size_t N = opaque((size_t)p.N);
+    const unsigned xs = x * sizeof(S), xsm = colm(x) * sizeof(S), xsp = colp(x) * sizeof(S);
+    if constexpr (!GH) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        g[i] = i ? pull_row<S, C, WALLS, 1>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
+        h[i] = (i && p.surf) ? pull_row<S, C, WALLS, 2>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
+      }
+    }
+    const size_t row = (size_t)gy * p.nx;
+    const unsigned xd = x * sizeof(double), xc = x * sizeof(C);
+    hv[0] = *byte_at(ref + row, xd);
+    if (a.have_hist) {
+      const C* hr = hin + row;
+      hv[1] = (double)*byte_at(hr, xc);
+      hv[2] = (double)*byte_at(hr + N, xc);
+      hv[3] = (double)*byte_at(hr + 2 * N, xc);
+      hv[4] = (double)*byte_at(hr + 3 * N, xc);
+      hv[5] = *byte_at(ref + N + row, xd);
+      hv[6] = (double)*byte_at(hr + 4 * N, xc);
+      hv[7] = (double)*byte_at(hr + 5 * N, xc);
+    }
+  };
+  auto row_Cf = [&](bool active, int gy, int ln, unsigned x, C* f) {
+    const size_t row = (size_t)gy * p.nx;
+    const int lc = min(max(ln, 2), kStripW + 1);
+    const bool interior = is_interior(ln);
+    const unsigned xs = x * sizeof(S), xc = x * sizeof(C);
+    const size_t N = opaque((size_t)p.N);
+    double ph = 0.0, rho = 1.0, ux = 0.0, uy = 0.0, pr = 0.0, Fx = 0.0, Fy = 0.0, grx = 0.0, gry = 0.0;
+    if (active) {
+      const double drho = (p.rho_l - p.rho_g) * 0.5 * p.inv_phib;
+      const double2 c = sPP[gy & (RP - 1)][lc];
+      ph = c.x;
+      const double ps = c.y;
+      if constexpr (H16) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = decode<S, C>(p, 0, i, (S)f[i], C(0));
+      }
+      const int wside = !WALLS ? 0 : (gy == 0 ? -1 : (gy == p.ny - 1 ? 1 : 0));
+      const bool wet = wside != 0 && wet_side(p, wside);
+      double jg = 0.0;
+      if (wet) {
+        const double2 o = sPP[(gy + wside) & (RP - 1)][ln];
+        jg = Jphi(p, o.x, o.y);
+      }
+      double gfx = 0, gfy = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const double w3 = 3.0 * WQ<double>(i);
+        const double2 nb = sPP[(gy + CY(i)) & (RP - 1)][lc + CX(i)];
+        double q = nb.x;
+        if (wet && CY(i) == wside) q += __shfl(jg, lc + CX(i)) / p.kappa;
+        if (CX(i)) gfx += (CX(i) * w3) * q;
+        if (CY(i)) gfy += (CY(i) * w3) * q;
+        const double2 mn = sMU[(gy + CY(i)) & (RM - 1)][lc + CX(i)];
+        if (CX(i)) { gpx += (CX(i) * w3) * mn.x; gsx += (CX(i) * w3) * mn.y; }
+        if (CY(i)) { gpy += (CY(i) * w3) * mn.x; gsy += (CY(i) * w3) * mn.y; }
+      }
+      grx = drho * gfx;
+      gry = drho * gfy;
+      rho = rho_of(p, ph);
+      Fx = -ph * gpx - ps * gsx + rho * p.gx;
+      Fy = -ph * gpy - ps * gsy + rho * p.gy;
+      ux = ((double)(f[1] - f[3] + f[5] - f[6] - f[7] + f[8]) + 0.5 * Fx) / rho;
+      uy = ((double)(f[2] - f[4] + f[5] + f[6] - f[7] - f[8]) + 0.5 * Fy) / rho;
+      const double snz = (double)(f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]);
+      pr = 0.6 * (snz + 0.5 * (ux * grx + uy * gry) - rho * (2.0 / 3.0) * (ux * ux + uy * uy));
+      sU[gy - Y0][ln] = make_double2(ux, uy);
+    }
+    __syncthreads();
+    if (!active) return;
+    double rf[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) rf[k] = opaque(p.sf[k]);
+    C m[9], o[9];
+    m[0] = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    moments_noncons(f, m);
+    const double uu = ux * ux + uy * uy, third = 1.0 / 3.0, av = ux * grx + uy * gry;
+    const C meq[9] = {C(0), (C)(rho * ux), (C)(rho * uy), (C)(pr + rho * ux * ux), (C)(rho * ux * uy), (C)(pr + rho * uy * uy),
+                      (C)(rho * uy * third), (C)(rho * ux * third), (C)((pr + rho * uu) * third)};
+    const C mv[9] = {(C)av, (C)Fx, (C)Fy, (C)(ux * grx + uy * gry * third), (C)((ux * gry + uy * grx) * third),
+                     (C)(uy * gry + ux * grx * third), (C)(Fy * third), (C)(Fx * third), (C)(av * third)};
+    const C s2 = p.s2_local ? (C)(1.0 / (3.0 * mud_of(p, ph) / rho + 0.5)) : (C)rf[2];
+    const C rt[9] = {(C)rf[0], (C)rf[1], (C)rf[1], s2, s2, s2, (C)rf[3], (C)rf[3], (C)rf[4]};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m[k] = m[k] - rt[k] * (m[k] - meq[k]) + (C(1) - C(0.5) * rt[k]) * mv[k];
+    moving_populations(m, o);
+    o[0] = m[0] - m[3] - m[5] + m[8];
+    const bool wb = WALLS && gy == 0 && p.bc_bottom != LBM_BC_FREESLIP;
+    const bool wt = WALLS && gy == p.ny - 1 && p.bc_top != LBM_BC_FREESLIP;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      C v = o[i];
+      if (wb && CY(i) < 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_bottom);
+      if (wt && CY(i) > 0) v -= (C)(6.0 * WQ<double>(i) * rho * CX(i) * p.uw_top);
+      if (interior) stream_store(byte_at(Pout + (size_t)i * N + row, xs), encode<S, C>(p, 0, i, v, C(0)));
+    }
+    if (interior) {
+      C* ho = hout + row;
+      stream_store(byte_at(ho, xc), (C)ux);
+      stream_store(byte_at(ho + N, xc), (C)uy);
+    }
+  };
+  auto row_Cgh = [&](bool active, int gy, int ln, unsigned x, C* g, C* h, const double* hv) {
+    const size_t row = (size_t)gy * p.nx;
+    const int lc = min(max(ln, 2), kStripW + 1);
+    const bool interior = is_interior(ln);
+    const unsigned xs = x * sizeof(S), xc = x * sizeof(C);
+    const size_t N = opaque((size_t)p.N);
+    double ph = 0.0, ps = 0.0, ph0 = 0.0, Rp0 = 0.0, Rs0 = 0.0, Rtp = 0.0, Rts = 0.0;
+    double uxh = 0.0, uyh = 0.0, vxh = 0.0, vyh = 0.0, ps0 = 0.0;
+    if (active) {
+      const double lam1 = opaque_v(lam1_), mub1 = opaque_v(mub1_);
+      const double2 c = sPP[gy & (RP - 1)][lc];
+      ph = c.x;
+      ps = c.y;
+      const double2 mc = sMU[gy & (RM - 1)][lc];
+      ph0 = hv[0];
+      if constexpr (GH) {
+        g[0] = h[0] = C(0);
+        const int ks = gh_slot(gy);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+          g[i] = (C)sGH[ks][i - 1][ln];
+          h[i] = p.surf ? (C)sGH[ks][7 + i][ln] : C(0);
+        }
+      }
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const int sy = gy - CY(i);
+        const bool bb = WALLS && (sy < 0 || sy >= p.ny);
+        const int er = bb ? gy & (RP - 1) : (gy - CY(i)) & (RP - 1), ec = bb ? lc + 1 : lc + 1 - CX(i);
+        if constexpr (H16) {
+          const float2 re = sRef[er][ec];
+          g[i] = decode<S, C>(p, 1, i, (S)g[i], (C)re.x);
+          if (p.surf) h[i] = decode<S, C>(p, 2, i, (S)h[i], (C)re.y);
+        }
+        g[i] += (C)(lam1 * WQ<double>(i) * (double)sHp[er][ec]);
+        if (p.surf) h[i] += (C)(mub1 * WQ<double>(i));
+      }
+      double l0p = 0, l0s = 0;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const double w3 = 3.0 * WQ<double>(i), w2 = 2.0 * w3;
+        const double2 nb = sPP[(gy + CY(i)) & (RP - 1)][lc + CX(i)];
+        l0p += w2 * (nb.x - ph);
+        l0s += w2 * (nb.y - ps);
+      }
+      Rp0 = -p.M_phi * (mc.x + p.kappa * l0p);
+      Rs0 = p.surf ? -p.M_psi * mc.y - (p.M0 + p.M_psi * p.lambda_s) * l0s : 0.0;
+      Rtp = Rp0;
+      Rts = Rs0;
+      if (a.have_hist) {
+        uxh = hv[1];
+        uyh = hv[2];
+        vxh = hv[3];
+        vyh = hv[4];
+        ps0 = hv[5];
+        const double Rp_prev = hv[6] + p.M_phi * pend.lambda_phi * hprime(p, ph0);
+        const double Rs_prev = hv[7] + p.M_psi * pend.mubar_psi;
+        Rtp = 1.5 * Rp0 - 0.5 * Rp_prev;
+        Rts = 1.5 * Rs0 - 0.5 * Rs_prev;
+      }
+    }
+    __syncthreads();
+    if (!active) return;
+    const double2 u = sU[gy - Y0][ln];
+    const double ux = u.x, uy = u.y;
+    double vx = ux, vy = uy, dpx = 0, dpy = 0, dsx = 0, dsy = 0;
+    if (a.have_hist) {
+      if (!p.adv_raw) {
+        vx = 0.5 * (ux + uxh);
+        vy = 0.5 * (uy + uyh);
+      }
+      dpx = ph * vx - ph0 * vxh;
+      dpy = ph * vy - ph0 * vyh;
+      dsx = ps * vx - ps0 * vxh;
+      dsy = ps * vy - ps0 * vyh;
+    }
+    double rg[5], rh[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      rg[k] = opaque(p.sg[k]);
+      rh[k] = opaque(p.sh[k]);
+    }
+    auto store_lat = [&](int lat, const C* o, C cref) {
+      if constexpr (H16) {
+        C rest = o[0];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+          const S t = encode<S, C>(p, lat, i, o[i], cref);
+          rest += o[i] - decode<S, C>(p, lat, i, t, cref);
+          if (interior) stream_store(byte_at(Pout + (size_t)(9 * lat + i) * N + row, xs), t);
+        }
+        if (interior) stream_store(byte_at(rest_plane(Pout, N, lat) + row, 2 * xs), (float)rest);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+          if (interior) stream_store(byte_at(Pout + (size_t)(9 * lat + i) * N + row, xs), (S)o[i]);
+      }
+    };
+    {
+      C o[9];
+      collide_scalar<C>(g, (C)ph, (C)p.eta_phi, (C)vx, (C)vy, (C)dpx, (C)dpy, (C)Rtp, rg, o);
+      store_lat(1, o, (C)ph);
+    }
+    if (p.surf) {
+      C o[9];
+      collide_scalar<C>(h, (C)ps, (C)p.eta_psi, (C)vx, (C)vy, (C)dsx, (C)dsy, (C)Rts, rh, o);
+      store_lat(2, o, (C)ps);
+    }
+    if (interior) {
+      C* ho = hout + row;
+      stream_store(byte_at(ho + 2 * N, xc), (C)vx);
+      stream_store(byte_at(ho + 3 * N, xc), (C)vy);
+      stream_store(byte_at(ho + 4 * N, xc), (C)Rp0);
+      stream_store(byte_at(ho + 5 * N, xc), (C)Rs0);
+    }
+  };
+
   if constexpr (SCHED == kOneShot8) {
     // ---- one tile of four rows [Y0, Yend) with eight waves (small grids):
     // every phase takes all its rows at once -- wave w: h' of rows Y0-3+w
     // (and Y0+5+w for w < 2), phi, psi of row Y0-2+w, mu of row Y0-1+w
-    // (w < 6), the collision of row Y0+w (w < 4) -- and every load is issued
+    // (w < 6), the collision of row Y0+(w&3) split between waves w and w+4 -- and every load is issued
     // before the first wait.  The phases are those of the sweep on the same
     // rows, and the tile's sums are added in the order of the sweep's waves
     // (rows Y0+1, Y0+2, Y0+3, Y0), so the results equal the sweep's bit for bit.
     constexpr bool preA = GH;
     C f[9], g[9], h[9], tg[9], th[9];
-    double r0[2], v0[4], v1[4];
-    const int rc = Y0 + wave;
-    const bool collide = wave < 4 && rc < Yend;
+    double r0[2], v0[4], v1[4], hv[8];
+    const int rc = Y0 + (wave & 3);   // the collision row of this wave's half of C
+    const bool collide = rc < Yend, fwave = wave < 4;
     gather_H(Y0 - 3 + wave, lane, xcol, v0);
     if (wave < 2) gather_H(Y0 + 5 + wave, lane, xcol, v1);
     if (preA) gather_A(Y0 - 2 + wave, xcol, tg, th, r0);
-    if (collide) gather_C(rc, xcol, f, g, h);
+    if (collide) {
+      if (fwave) gather_Cf(rc, xcol, f);
+      else gather_Cgh(rc, xcol, g, h, hv);
+    }
     set_pend();   // its loads (if any) are in flight with the gathers
     row_H(Y0 - 3 + wave, lane, v0);
     if (wave < 2) row_H(Y0 + 5 + wave, lane, v1);
@@ -971,7 +1211,8 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     __syncthreads();
     if (wave < 6) row_B(Y0 - 1 + wave, lane);
     __syncthreads();
-    if (collide) row_C(rc, lane, xcol, f, g, h);
+    if (fwave) row_Cf(collide, rc, lane, xcol, f);
+    else row_Cgh(collide, rc, lane, xcol, g, h, hv);
     __shared__ double sR[3][8];
     const double q[3] = {wave_red(s1, false), wave_red(s2, false), wave_red(s3, false)};
     if (lane == 0) {
