@@ -135,6 +135,7 @@ std::string derive(const lbm_params& p, lbm::DevParams& d, double* derived) {
   d.s2_local = !(p.s_f[2] > 0.0);
   d.x0 = p.x0; d.y0 = p.y0; d.R0 = p.R0; d.a = p.a;
   d.psi_b = p.psi_b;
+  d.mu_ref = d.surf ? kBT * std::log(p.psi_b / (1.0 - p.psi_b)) - beta * (1.0 - phib * phib) * (1.0 - phib * phib) + 0.5 * W * phib * phib : 0.0;
   d.init_scale = 2.0 * phib * (d.surf ? std::sqrt(1.0 - p.psi_b) : 1.0) / p.eps;
   d.init_kind = p.init_kind;
   const double psi_c = std::exp(-(beta + 0.5 * W) / kBT);

@@ -30,13 +30,20 @@ struct DevParams {
   double sf[5], sg[5], sh[5];
   double x0, y0, R0, a;
   double psi_b, init_scale;  // init_scale = 2 phi_b sqrt(1 - psi_b) / eps
+  // Reference surfactant potential: mu_psi of the bulk of the initial state.
+  // Each step's collision carries M_psi mu_ref in its psi source, so that the
+  // deferred multiplier term is only M_psi (mubar - mu_ref): the same total in
+  // exact arithmetic (a uniform source c adds w_i c to every population,
+  // before or after the next gather), but populations of the size of the
+  // sources' departure from equilibrium instead of M_psi mu_psi itself.
+  double mu_ref;
   int init_kind;
 };
 
 // FP64 multiplier state kept on the device.  The fused step leaves the
-// multiplier terms of its own sources out of the stored populations and
-// applies them when the next step gathers them: cdef is the weight of that
-// pending term (1.5 from R + dR/2, or 1 on a first step; 0 when nothing is
+// multiplier terms of its own sources (for psi: their part beyond M_psi mu_ref)
+// out of the stored populations and applies them when the next step gathers
+// them: cdef is the weight of that pending term (1.5 from R + dR/2, or 1 on a first step; 0 when nothing is
 // pending, e.g. right after loading fields).
 struct DevScalars {
   double lambda_phi, mubar_psi, cdef;

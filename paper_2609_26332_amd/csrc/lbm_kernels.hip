@@ -306,7 +306,7 @@ __device__ __forceinline__ int emitter(const DevParams& p, int i, int x, int y) 
 
 // phi(n+1) = phi(n) + [stored g_0 shift + sum of the gathered moving g_i]
 // + the pending multiplier term cdef M_phi lambda(n) sum_i w_i h'(phi(n)(emitter_i));
-// psi likewise with the uniform term cdef M_psi mubar(n).
+// psi likewise with the uniform term cdef M_psi (mubar(n) - mu_ref).
 template <class S, class C>
 __global__ __launch_bounds__(kBlock) void k_moments(DevParams p, const S* __restrict__ P, const double* __restrict__ prev,
                                                     const DevScalars* __restrict__ pend, double* __restrict__ phipsi) {
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(DevParams p, const S* __rest
   if (p.surf) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) b += pull<S, C>(p, P, 2, i, x, y, prev);
-    phipsi[(size_t)p.N + n] = prev[(size_t)p.N + n] + (double)b + pend->cdef * p.M_psi * pend->mubar_psi;
+    phipsi[(size_t)p.N + n] = prev[(size_t)p.N + n] + (double)b + pend->cdef * p.M_psi * (pend->mubar_psi - p.mu_ref);
   } else {
     phipsi[(size_t)p.N + n] = 0.0;
   }
@@ -614,7 +614,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   auto set_pend = [&]() {
     pend = a.prev_partials ? multipliers_of(a.prev_partials, a.ntiles, p.N, a.prev_have_hist) : *a.pend;
     lam1_ = pend.cdef * p.M_phi * pend.lambda_phi;
-    mub1_ = pend.cdef * p.M_psi * pend.mubar_psi;
+    mub1_ = pend.cdef * p.M_psi * (pend.mubar_psi - p.mu_ref);
   };
   const int lane = threadIdx.x & 63;
   const int wave = wave_uniform(threadIdx.x >> 6);
@@ -862,7 +862,9 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     // bulk terms plus the wall terms of eq_muphi / eq_mupsi.
     const double Rp0 = -p.M_phi * (mc.x + p.kappa * l0p);
     const double Rs0 = p.surf ? -p.M_psi * mc.y - (p.M0 + p.M_psi * p.lambda_s) * l0s : 0.0;
-    double vx = ux, vy = uy, dpx = 0, dpy = 0, dsx = 0, dsy = 0, Rtp = Rp0, Rts = Rs0;
+    // the psi source the collision carries includes M_psi mu_ref (the rest of the multiplier term is pending)
+    const double Rs0c = p.surf ? Rs0 + p.M_psi * p.mu_ref : 0.0;
+    double vx = ux, vy = uy, dpx = 0, dpy = 0, dsx = 0, dsy = 0, Rtp = Rp0, Rts = Rs0c;
     if (a.have_hist) {
       const C* hr = hin + row;
       if (!p.adv_raw) {
@@ -878,7 +880,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       const double Rp_prev = (double)*byte_at(hr + 4 * N, xc) + p.M_phi * pend.lambda_phi * hprime(p, ph0);
       const double Rs_prev = (double)*byte_at(hr + 5 * N, xc) + p.M_psi * pend.mubar_psi;
       Rtp = 1.5 * Rp0 - 0.5 * Rp_prev;
-      Rts = 1.5 * Rs0 - 0.5 * Rs_prev;
+      Rts = 1.5 * Rs0c - 0.5 * Rs_prev;
     }
 
     // ---- lattice 1: MRT with the pressure-based equilibrium and A^1 forcing
@@ -1112,8 +1114,9 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       }
       Rp0 = -p.M_phi * (mc.x + p.kappa * l0p);
       Rs0 = p.surf ? -p.M_psi * mc.y - (p.M0 + p.M_psi * p.lambda_s) * l0s : 0.0;
+      const double Rs0c = p.surf ? Rs0 + p.M_psi * p.mu_ref : 0.0;   // as in row_C
       Rtp = Rp0;
-      Rts = Rs0;
+      Rts = Rs0c;
       if (a.have_hist) {
         uxh = hv[1];
         uyh = hv[2];
@@ -1123,7 +1126,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
         const double Rp_prev = hv[6] + p.M_phi * pend.lambda_phi * hprime(p, ph0);
         const double Rs_prev = hv[7] + p.M_psi * pend.mubar_psi;
         Rtp = 1.5 * Rp0 - 0.5 * Rp_prev;
-        Rts = 1.5 * Rs0 - 0.5 * Rs_prev;
+        Rts = 1.5 * Rs0c - 0.5 * Rs_prev;
       }
     }
     __syncthreads();
@@ -1513,7 +1516,7 @@ __global__ __launch_bounds__(kBlock) void k_pops(DevParams p, const S* __restric
   if (n >= p.N) return;
   const size_t N = (size_t)p.N;
   const int x = n % p.nx, y = n / p.nx;
-  const double lam = pend->cdef * p.M_phi * pend->lambda_phi, mub = pend->cdef * p.M_psi * pend->mubar_psi;
+  const double lam = pend->cdef * p.M_phi * pend->lambda_phi, mub = pend->cdef * p.M_psi * (pend->mubar_psi - p.mu_ref);
   for (int lat = 0; lat < 3; ++lat)
 #pragma unroll
     for (int i = 0; i < 9; ++i) {

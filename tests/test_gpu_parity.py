@@ -97,7 +97,7 @@ def test_tile_heights(lbm, rows):
 # errors against the FP64 oracle with a margin of a few times (per field,
 # normalised as above), and the surfactant mass drift, which the FP32 rest
 # planes keep at the FP32 level.
-FP16_TOL = {"phi": 3e-4, "psi": 5e-3, "ux": 2e-2, "uy": 5e-2, "p": 2e-2, "mu_phi": 2e-2, "mu_psi": 5e-3}
+FP16_TOL = {"phi": 3e-4, "psi": 5e-5, "ux": 2e-2, "uy": 5e-2, "p": 2e-2, "mu_phi": 2e-2, "mu_psi": 5e-5}
 
 
 def fp16_errors(lbm, cfg, steps):
@@ -121,7 +121,7 @@ def test_fp16_shifted_storage_errors(lbm, name, steps):
     assert not bad, (name, bad, e)
     assert gi["nonfinite"] == 0
     if cfg["psi_b"] > 0:
-        assert abs(gi["mass_psi"] - m0) / m0 < 5e-6
+        assert abs(gi["mass_psi"] - m0) / m0 < 1e-6
     assert gi["area_phi_pos"] == pytest.approx(oi["area_phi_pos"], rel=1e-4)
     if cfg.get("bc_bottom", 0) == inputs.WALL_WET:
         assert abs(gi["theta_app_deg"] - oi["theta_app_deg"]) < 0.02
@@ -138,7 +138,7 @@ def test_fp16_walls_many_workgroups(lbm):
     bad = {k: v for k, v in e.items() if not v <= FP16_TOL[k]}
     assert not bad, (bad, e)
     assert gi["nonfinite"] == 0
-    assert abs(gi["mass_psi"] - m0) / m0 < 5e-6
+    assert abs(gi["mass_psi"] - m0) / m0 < 1e-6
 
 
 def test_stationary_drop_1000_steps(lbm):
@@ -217,6 +217,21 @@ def test_surfactant_mass_conservation_fp64(lbm):
     m0 = g.invariants()["mass_psi"]
     g.step(3000)
     assert abs(g.invariants()["mass_psi"] - m0) / m0 < 1e-12
+
+
+def test_surfactant_mass_fp64_long_run(lbm):
+    """FP64 storage on the full 512x256 sheared drop for 2e4 steps: the psi
+    mass drifts by less than 3e-13 (measured 1.2e-13).  The collision carries
+    M_psi mu_ref of the psi source, so only the multiplier's departure from
+    mu_ref is deferred; deferring all of M_psi mubar made every bulk node round
+    a source of 2e-3 the same way, a drift of 5.8e-13 over these steps."""
+    cfg = inputs.shear_drop(Ca=0.2)
+    g = lbm.Sim(cfg, "fp64")
+    m0 = g.invariants()["mass_psi"]
+    g.step(20000)
+    iv = g.invariants()
+    assert iv["nonfinite"] == 0
+    assert abs(iv["mass_psi"] - m0) / m0 < 3e-13
 
 
 def test_deterministic_and_checkpoint_restart(lbm):
@@ -383,4 +398,4 @@ def test_sheared_drop_long_run(lbm):
     assert len(c0) == len(c1) == 2
     assert 0.0 < c1.mean() - c0.mean() < 1.0, (c0, c1)
     assert np.all(np.abs(c1 - c0) < 1.0), (c0, c1)
-    assert abs(iv["mass_psi"] - m0) / m0 < 1e-5   # FP32 storage: 1.1e-6 measured
+    assert abs(iv["mass_psi"] - m0) / m0 < 1e-5   # the FP32 storage level
