@@ -85,7 +85,8 @@ typedef struct {
                                velocity of this and the previous step; 1: by u(n) itself (literal
                                reading, excites the D2Q9 staggered-momentum mode on long runs) */
   int32_t tile_rows;        /* height of the 64-wide tiles of the fused step kernel: 0 chooses from the grid
-                               size, 4, 8 or 16 force it (a tuning knob: results differ only in the
+                               size and precision (4 to 16 rows, up to 32 in FP64), a multiple of 4
+                               up to 4096 forces it (a tuning knob: results differ only in the
                                summation order of the global multiplier sums) */
   double sigma_gl0, eps;    /* clean gas-liquid tension, thickness: kappa = 3 eps sigma/8, beta = 3 sigma/(4 eps) */
   double M_phi, M_psi;      /* mobilities (>= 0) */

@@ -207,7 +207,7 @@ void carve(lbm_handle* h) {
   s.scalars = (lbm::DevScalars*)(b + L.scalars);
   s.dparams = (lbm::DevParams*)(b + L.dparams);
   s.scur = 0;
-  s.tile_rows = h->prm.tile_rows ? h->prm.tile_rows : lbm::step_seg_rows(h->dp.nx, h->dp.ny);
+  s.tile_rows = h->prm.tile_rows ? h->prm.tile_rows : lbm::step_seg_rows(h->dp.nx, h->dp.ny, h->prm.precision);
   s.field_buf = (double*)(b + L.field_buf);
   s.cur = 0;
   s.hcur = 0;

@@ -104,7 +104,7 @@ constexpr int kMaxTiles = 1 << 22;   // partials of the fused step: [kMaxTiles][
 
 size_t storage_bytes(int precision);
 size_t pops_bytes(int precision, size_t N);   // one population buffer (FP16: 27 FP16 planes + 2 FP32 rest planes)
-int step_seg_rows(int nx, int ny);                 // rows per workgroup segment of the step kernel
+int step_seg_rows(int nx, int ny, int precision);                 // rows per workgroup segment of the step kernel
 size_t step_blocks(int nx, int ny, int seg_rows);  // workgroups of the step kernel
 size_t compute_bytes(int precision);
 int set_init_error(int code, const std::string& msg);   // message for lbm_last_error(NULL); returns code

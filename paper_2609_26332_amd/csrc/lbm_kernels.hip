@@ -1806,11 +1806,17 @@ size_t step_blocks(int nx, int ny, int seg_rows) {
 }
 // Rows per workgroup segment: long segments amortise the four extra phi/psi
 // rows and two extra mu rows each segment computes, but a grid needs enough
-// workgroups to fill the chip (on MI355X: best at 4096^2 with 16 rows, about
-// 17700 workgroups; small grids want the most workgroups, 4 rows).
-int step_seg_rows(int nx, int ny) {
-  int seg = 64;
-  while (seg > 4 && step_blocks(nx, ny, seg) < 16384) seg /= 2;
+// workgroups to fill the chip.  The tallest segment up to 16 rows (FP32, FP16)
+// or 32 rows (FP64, whose step holds two workgroups per CU instead of three)
+// that still gives 2048 workgroups; small grids get 4 rows and the one-pass
+// tile kernels.  Measured on MI355X (periodic drop, ms per step, rows in
+// brackets): FP32 1024^2 0.104 (8) against 0.121 (4), 2048^2 0.403 (16) /
+// 0.400 (8) / 0.442 (4), 3072^2 0.924 (16), 4096^2 1.53 (16) against 1.60
+// (32); FP64 1024^2 0.173 (8) against 0.192 (4), 2048^2 0.611 (32), 3072^2
+// 1.43 (32), 4096^2 2.36 (32) against 2.45 (16) and 2.50 (64).
+int step_seg_rows(int nx, int ny, int precision) {
+  int seg = precision == LBM_FP64 ? 32 : 16;
+  while (seg > 4 && step_blocks(nx, ny, seg) < 2048) seg /= 2;
   return seg;
 }
 size_t compute_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }

@@ -201,7 +201,7 @@ def test_full_size_sessile_and_shear_fp32(lbm):
 
 
 def test_many_tiles_one_megacell(lbm):
-    """1024 x 1024 periodic grid (4096 blocks of the step kernels), two steps."""
+    """1024 x 1024 periodic grid (2304 workgroups of 8-row segments by default), two steps."""
     cfg = inputs.stationary_drop(nx=1024, ny=1024, R=200.0)
     for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
         g = lbm.Sim(cfg, prec)
