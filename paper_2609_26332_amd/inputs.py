@@ -59,6 +59,19 @@ def stationary_drop(nx: int = 64, ny: int = 64, R: float = 16.0, psi_b: float = 
                  x0=nx / 2.0, y0=ny / 2.0, R0=R, **kw)
 
 
+def static_drop_ratio1000(nx: int = 128, ny: int = 128, R: float = 32.0, psi_b: float = 0.01, **kw) -> dict:
+    """Periodic surfactant-laden drop at the density and viscosity ratios of
+    the paper's static-drop test (Sec. 4.2: rho_l/rho_g = 1000, mu_l/mu_g =
+    100, light phase at unit density with mu_g = 0.1, sigma0 = 0.001; its
+    W = 8 beta and k_B T = 5.4 beta are the defaults here), in lattice units:
+    interface width 4, mobilities 0.05, nu_g = 0.1 and nu_l = 0.01."""
+    cfg = _base(nx=nx, ny=ny, bc_bottom=PERIODIC, bc_top=PERIODIC, psi_b=psi_b,
+                sigma_gl0=1e-3, rho_l=1000.0, rho_g=1.0, mu_l=10.0, mu_g=0.1,
+                x0=nx / 2.0, y0=ny / 2.0, R0=R)
+    cfg.update(kw)
+    return cfg
+
+
 def adsorption_strength(seed: int) -> float:
     """Adsorption strength drawn U[0, 0.5) from the seed (first SplitMix64 draw)."""
     return SplitMix64(seed).uniform(0.0, 0.5)

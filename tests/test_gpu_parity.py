@@ -61,6 +61,7 @@ CASES = {
     "literal_advection": inputs.stationary_drop(nx=40, ny=40, R=10.0, adv_raw=1),
     "slab_gravity": dict(inputs.flat_slab(nx=64, ny=8, width=30.0, psi_b=0.02), gx=1e-6),
     "shear_liquid_adsorption": inputs.shear_drop(nx=96, ny=48, R=14.0, Ca=0.1, betas=(0.01, 0.9)),
+    "static_ratio1000_64": inputs.static_drop_ratio1000(nx=64, ny=64, R=16.0),
 }
 
 
@@ -72,7 +73,7 @@ def test_fp64_parity(lbm, name):
 
 
 @pytest.mark.parametrize("name", ["stationary_drop_64", "sessile_adsorbing_96x48", "shear_ratio10_128x64",
-                                  "ragged_67x37_walls", "clean_bubble_freeslip"])
+                                  "ragged_67x37_walls", "clean_bubble_freeslip", "static_ratio1000_64"])
 def test_fp32_parity(lbm, name):
     cfg = CASES[name]
     for step, gf, of, _, _ in run_pair(lbm, cfg, "fp32", [1, 20, 300]):
@@ -399,3 +400,35 @@ def test_sheared_drop_long_run(lbm):
     assert 0.0 < c1.mean() - c0.mean() < 1.0, (c0, c1)
     assert np.all(np.abs(c1 - c0) < 1.0), (c0, c1)
     assert abs(iv["mass_psi"] - m0) / m0 < 1e-5   # the FP32 storage level
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_static_drop_ratio1000_equilibrium(lbm, prec):
+    """The paper's static-drop ratios (rho 1000:1, mu 100:1, sigma0 = 0.001; the
+    light phase at unit density), 128^2, R = 32, 3e4 steps against the same drop
+    at ratio 1 in FP64: a static equilibrium does not depend on the densities,
+    so the multiplier lambda_phi, the pressure jump and the bulk surfactant
+    agree (measured: 0.9475 and 0.9476 sigma0/R, 0.853 sigma0/R, 0.009438
+    both); the spurious currents stay below 1e-7 (measured 7e-8, against
+    1.4e-6 at ratio 1, whose liquid is 100 times less viscous)."""
+    R = 32.0
+
+    def run(cfg, p):
+        g = lbm.Sim(cfg, p)
+        m0 = g.invariants()["mass_psi"]
+        g.step(30000)
+        iv = g.invariants()
+        f = g.fields(["phi", "p", "psi"])
+        dp = f["p"][f["phi"] > 0.9].mean() - f["p"][f["phi"] < -0.9].mean()
+        return iv, dp, float(np.median(f["psi"][f["phi"] < -0.95])), (iv["mass_psi"] - m0) / m0
+
+    hi, dp_hi, ps_hi, dm = run(inputs.static_drop_ratio1000(), prec)
+    lo, dp_lo, ps_lo, _ = run(inputs.static_drop_ratio1000(rho_l=1.0, mu_l=0.1), "fp64")
+    sR = 1e-3 / R
+    assert hi["nonfinite"] == 0 and hi["psi_out_of_range"] == 0
+    assert hi["lambda_phi"] == pytest.approx(lo["lambda_phi"], rel=1e-3)
+    assert 0.93 * sR < hi["lambda_phi"] < 0.96 * sR          # surfactant lowers the tension below sigma0 / R
+    assert dp_hi == pytest.approx(dp_lo, rel=1e-2)
+    assert ps_hi == pytest.approx(ps_lo, rel=1e-4)
+    assert hi["umax"] < 1e-7
+    assert abs(dm) < 1e-6
