@@ -22,7 +22,7 @@
  * moments grouped by order; relaxation rates not tied to transport are 1,
  * the f shear rate follows the local viscosity, g and h use s1 = 1 so that
  * eta = 6 D; M0 = 0 when lambda_s > 0, else M_phi kappa; rho and mu are
- * linear in (1 + phi/phi_b)/2; every lattice bounces back half-way at a
+ * linear in (1 + phi/phi_b)/2 held to [0, 1]; every lattice bounces back half-way at a
  * wall, whose ghost row carries phi + J_phi/kappa and whose flux J_psi enters
  * mu_psi and the source; on the first step the backward differences vanish;
  * phi and psi are advected by the mean of the velocities of this and the
@@ -92,11 +92,18 @@ static double gsw_d(const orc_sim* s, double ph) {
 static double hprime(const orc_sim* s, double ph) {
   return s->p.constraint_phi == ORC_LINEAR ? 1.0 : gsw_d(s, ph);
 }
+/* Density and dynamic viscosity: linear in the liquid fraction (1 + phi/phi_b)/2,
+ * which is held to [0, 1] (the paper gives no rho(phi); unbounded, a phi just past
+ * -phi_b would drive the light phase's density through zero at large ratios). */
+static double liquid_frac(const orc_sim* s, double ph) {
+  double w = 0.5 * (1.0 + ph / s->phib);
+  return w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+}
 static double rho_of(const orc_sim* s, double ph) {
-  return s->p.rho_g + (s->p.rho_l - s->p.rho_g) * 0.5 * (1.0 + ph / s->phib);
+  return s->p.rho_g + (s->p.rho_l - s->p.rho_g) * liquid_frac(s, ph);
 }
 static double mud_of(const orc_sim* s, double ph) {
-  return s->p.mu_g + (s->p.mu_l - s->p.mu_g) * 0.5 * (1.0 + ph / s->phib);
+  return s->p.mu_g + (s->p.mu_l - s->p.mu_g) * liquid_frac(s, ph);
 }
 /* -df_w/dphi and -df_w/dpsi of the wall energy (eq8, boundary). */
 static double wall_Jphi(const orc_sim* s, double ph, double ps) {

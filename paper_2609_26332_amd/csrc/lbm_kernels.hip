@@ -167,11 +167,18 @@ __device__ __forceinline__ double gsw_d(const DevParams& p, double ph) {
   return 0.75 * p.inv_phib * (1.0 - u * u);
 }
 __device__ __forceinline__ double hprime(const DevParams& p, double ph) { return p.linear ? 1.0 : gsw_d(p, ph); }
+// Density and dynamic viscosity: linear in the liquid fraction (1 + phi/phi_b)/2
+// held to [0, 1], so that a phase field a little past -phi_b (a contact line,
+// the bulk shift of a curved interface) cannot take the light phase's density
+// through zero at large density ratios.
+__device__ __forceinline__ double liquid_frac(const DevParams& p, double ph) {
+  return fmin(fmax(0.5 * (1.0 + ph * p.inv_phib), 0.0), 1.0);
+}
 __device__ __forceinline__ double rho_of(const DevParams& p, double ph) {
-  return p.rho_g + (p.rho_l - p.rho_g) * 0.5 * (1.0 + ph * p.inv_phib);
+  return p.rho_g + (p.rho_l - p.rho_g) * liquid_frac(p, ph);
 }
 __device__ __forceinline__ double mud_of(const DevParams& p, double ph) {
-  return p.mu_g + (p.mu_l - p.mu_g) * 0.5 * (1.0 + ph * p.inv_phib);
+  return p.mu_g + (p.mu_l - p.mu_g) * liquid_frac(p, ph);
 }
 // J_phi = -df_w/dphi, J_psi = -df_w/dpsi at a wall node (eq8, boundary).
 __device__ __forceinline__ double Jphi(const DevParams& p, double ph, double ps) {
@@ -776,8 +783,6 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     const int lc = min(max(ln, 2), kStripW + 1);   // halo lanes compute a copy and store nothing
     const bool interior = is_interior(ln);
     const unsigned xs = x * sizeof(S), xd = x * sizeof(double), xc = x * sizeof(C);
-    // rho is affine in phi: grad rho = (d rho / d phi) grad phi (ghost values included)
-    const double drho = (p.rho_l - p.rho_g) * 0.5 * p.inv_phib;
     // An opaque copy of N and of the rates per row keeps the compiler from
     // hoisting the plane offsets and converted constants out of the sweep
     // loop into registers.
@@ -842,13 +847,14 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       if (wet && CY(i) == wside) q += __shfl(jg, lc + CX(i)) / p.kappa;
       l0p += w2 * (nb.x - ph);
       l0s += w2 * (nb.y - ps);
-      if (CX(i)) gfx += (CX(i) * w3) * q;
-      if (CY(i)) gfy += (CY(i) * w3) * q;
+      const double rq = rho_of(p, q);   // grad rho from the neighbours' densities (ghost phi at a wall)
+      if (CX(i)) gfx += (CX(i) * w3) * rq;
+      if (CY(i)) gfy += (CY(i) * w3) * rq;
       const double2 mn = sMU[(gy + CY(i)) & (RM - 1)][lc + CX(i)];
       if (CX(i)) { gpx += (CX(i) * w3) * mn.x; gsx += (CX(i) * w3) * mn.y; }
       if (CY(i)) { gpy += (CY(i) * w3) * mn.x; gsy += (CY(i) * w3) * mn.y; }
     }
-    const double grx = drho * gfx, gry = drho * gfy;
+    const double grx = gfx, gry = gfy;
     const double rho = rho_of(p, ph);
     const double Fx = -ph * gpx - ps * gsx + rho * p.gx, Fy = -ph * gpy - ps * gsy + rho * p.gy;
     const double ux = ((double)(f[1] - f[3] + f[5] - f[6] - f[7] + f[8]) + 0.5 * Fx) / rho;
@@ -994,7 +1000,6 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     const size_t N = opaque((size_t)p.N);
     double ph = 0.0, rho = 1.0, ux = 0.0, uy = 0.0, pr = 0.0, Fx = 0.0, Fy = 0.0, grx = 0.0, gry = 0.0;
     if (active) {
-      const double drho = (p.rho_l - p.rho_g) * 0.5 * p.inv_phib;
       const double2 c = sPP[gy & (RP - 1)][lc];
       ph = c.x;
       const double ps = c.y;
@@ -1016,14 +1021,15 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
         const double2 nb = sPP[(gy + CY(i)) & (RP - 1)][lc + CX(i)];
         double q = nb.x;
         if (wet && CY(i) == wside) q += __shfl(jg, lc + CX(i)) / p.kappa;
-        if (CX(i)) gfx += (CX(i) * w3) * q;
-        if (CY(i)) gfy += (CY(i) * w3) * q;
+        const double rq = rho_of(p, q);   // as in row_C
+        if (CX(i)) gfx += (CX(i) * w3) * rq;
+        if (CY(i)) gfy += (CY(i) * w3) * rq;
         const double2 mn = sMU[(gy + CY(i)) & (RM - 1)][lc + CX(i)];
         if (CX(i)) { gpx += (CX(i) * w3) * mn.x; gsx += (CX(i) * w3) * mn.y; }
         if (CY(i)) { gpy += (CY(i) * w3) * mn.x; gsy += (CY(i) * w3) * mn.y; }
       }
-      grx = drho * gfx;
-      gry = drho * gfy;
+      grx = gfx;
+      gry = gfy;
       rho = rho_of(p, ph);
       Fx = -ph * gpx - ps * gsx + rho * p.gx;
       Fy = -ph * gpy - ps * gsy + rho * p.gy;
