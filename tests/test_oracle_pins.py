@@ -377,3 +377,23 @@ def test_adsorption_shifts_contact_angle_sec44():
         s.step(8000)
         ang[tag] = s.invariants()["theta_app_deg"]
     assert ang["sl"] < ang["clean"] - 0.3 < ang["sg"] - 0.6, ang
+
+
+# ------------------------------------------------- density-ratio independence
+def test_static_equilibrium_independent_of_density_ratio_sec42():
+    """At rest the phase-field and surfactant equations do not see the density:
+    the 1000:1 static drop (Sec. 4.2's ratios) and the same drop at 1:1 reach the
+    same multipliers after 1500 steps, the density stays within [rho_g, rho_l]
+    (the liquid fraction is held to [0, 1] where phi passes -phi_b), and the
+    heavier, more viscous liquid carries smaller spurious currents."""
+    hi = sim(inputs.static_drop_ratio1000(nx=48, ny=48, R=12.0))
+    lo = sim(inputs.static_drop_ratio1000(nx=48, ny=48, R=12.0, rho_l=1.0, mu_l=0.1))
+    hi.step(1500)
+    lo.step(1500)
+    a, b = hi.invariants(), lo.invariants()
+    assert a["lambda_phi"] == pytest.approx(b["lambda_phi"], rel=1e-3)
+    assert a["mubar_psi"] == pytest.approx(b["mubar_psi"], rel=1e-4)
+    f = hi.fields(["rho", "phi"])
+    assert f["phi"].min() < -hi.derived()["phi_b"]      # the bulk does pass -phi_b ...
+    assert f["rho"].min() == 1.0 and f["rho"].max() <= 1000.0   # ... and the density is held
+    assert a["umax"] < 0.1 * b["umax"]
