@@ -477,28 +477,52 @@ struct StepArgs {
 // lambda(n) = S1/S2 and mubar(n) = S3/N from the per-workgroup sums, in a
 // fixed order (every thread of the block gets the result); cdef weights the
 // multiplier terms step n+1 applies (1.5 from R + dR/2, 1 on a first step).
-__device__ __forceinline__ DevScalars multipliers_of(const double* __restrict__ partials, int ntiles, int N,
-                                                    int have_hist) {
-  double t1 = 0.0, t2 = 0.0, t3 = 0.0;
-  if (threadIdx.x < kBlock) {   // larger blocks: the first kBlock threads, as k_step_finish
+// In two parts, so that a step can issue the loads of the previous step's
+// partial sums ahead of its own gathers and reduce them once those are in
+// flight: each thread's share (the first kBlock threads, as in k_step_finish),
+// then the block's three sums in one pass (each reduced as block_sum_first
+// reduces it) and the multipliers.
+__device__ __forceinline__ void multipliers_load(const double* __restrict__ partials, int ntiles, double* t) {
+  t[0] = t[1] = t[2] = 0.0;
+  if (threadIdx.x < kBlock) {
 #pragma unroll 4
     for (int b = threadIdx.x; b < ntiles; b += kBlock) {
-      t1 += partials[3 * (size_t)b + 0];
-      t2 += partials[3 * (size_t)b + 1];
-      t3 += partials[3 * (size_t)b + 2];
+      t[0] += partials[3 * (size_t)b + 0];
+      t[1] += partials[3 * (size_t)b + 1];
+      t[2] += partials[3 * (size_t)b + 2];
     }
   }
-  t1 = block_sum_first(t1);
-  t2 = block_sum_first(t2);
-  t3 = block_sum_first(t3);
-  __shared__ DevScalars res;   // the sums are in thread 0 only
+}
+__device__ __forceinline__ DevScalars multipliers_reduce(const double* t, int N, int have_hist) {
+  __shared__ double sh[3][kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const double w0 = wave_red(t[0], false), w1 = wave_red(t[1], false), w2 = wave_red(t[2], false);
+  if (lane == 0 && wid < kBlock / 64) {
+    sh[0][wid] = w0;
+    sh[1][wid] = w1;
+    sh[2][wid] = w2;
+  }
+  __syncthreads();
+  __shared__ DevScalars res;
   if (threadIdx.x == 0) {
-    res.lambda_phi = t2 > 0.0 ? t1 / t2 : 0.0;
-    res.mubar_psi = t3 / (double)N;
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r[c] = sh[c][0];
+      for (int k = 1; k < kBlock / 64; ++k) r[c] = r[c] + sh[c][k];
+    }
+    res.lambda_phi = r[1] > 0.0 ? r[0] / r[1] : 0.0;
+    res.mubar_psi = r[2] / (double)N;
     res.cdef = have_hist ? 1.5 : 1.0;
   }
   __syncthreads();
   return res;
+}
+__device__ __forceinline__ DevScalars multipliers_of(const double* __restrict__ partials, int ntiles, int N,
+                                                    int have_hist) {
+  double t[3];
+  multipliers_load(partials, ntiles, t);
+  return multipliers_reduce(t, N, have_hist);
 }
 __device__ __forceinline__ void finish_body(const double* __restrict__ partials, int ntiles, int N, int have_hist,
                                             DevScalars* __restrict__ next) {
@@ -616,12 +640,21 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   // set by set_pend() before phase A first runs: reduced from the previous
   // step's sums (small grids inside a captured run) or as k_step_finish left
   // them.
+  // pend_load() issues the loads, pend_set() reduces and sets the terms.
   DevScalars pend;
-  double lam1_ = 0.0, mub1_ = 0.0;
-  auto set_pend = [&]() {
-    pend = a.prev_partials ? multipliers_of(a.prev_partials, a.ntiles, p.N, a.prev_have_hist) : *a.pend;
+  double lam1_ = 0.0, mub1_ = 0.0, pt_[3];
+  auto pend_load = [&]() {
+    if (a.prev_partials) multipliers_load(a.prev_partials, a.ntiles, pt_);
+    else pend = *a.pend;
+  };
+  auto pend_set = [&]() {
+    if (a.prev_partials) pend = multipliers_reduce(pt_, p.N, a.prev_have_hist);
     lam1_ = pend.cdef * p.M_phi * pend.lambda_phi;
     mub1_ = pend.cdef * p.M_psi * (pend.mubar_psi - p.mu_ref);
+  };
+  auto set_pend = [&]() {
+    pend_load();
+    pend_set();
   };
   const int lane = threadIdx.x & 63;
   const int wave = wave_uniform(threadIdx.x >> 6);
@@ -1204,6 +1237,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     double r0[2], v0[4], v1[4], hv[8];
     const int rc = Y0 + (wave & 3);   // the collision row of this wave's half of C
     const bool collide = rc < Yend, fwave = wave < 4;
+    pend_load();   // first: the multipliers are reduced while the gathers are in flight
     gather_H(Y0 - 3 + wave, lane, xcol, v0);
     if (wave < 2) gather_H(Y0 + 5 + wave, lane, xcol, v1);
     if (preA) gather_A(Y0 - 2 + wave, xcol, tg, th, r0);
@@ -1211,7 +1245,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       if (fwave) gather_Cf(rc, xcol, f);
       else gather_Cgh(rc, xcol, g, h, hv);
     }
-    set_pend();   // its loads (if any) are in flight with the gathers
+    pend_set();
     row_H(Y0 - 3 + wave, lane, v0);
     if (wave < 2) row_H(Y0 + 5 + wave, lane, v1);
     __syncthreads();
@@ -1254,6 +1288,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     double r00[2], r01[2], v0[4], v1[4], v2[4];
     const int rc = Y0 + wave;
     const bool collide = rc < Yend;
+    pend_load();   // first, as in the eight-wave tile
     gather_H(Y0 - 3 + wave, lane, xcol, v0);
     gather_H(Y0 + 1 + wave, lane, xcol, v1);
     if (wave < 2) gather_H(Y0 + 5 + wave, lane, xcol, v2);
@@ -1262,7 +1297,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       gather_A(Y0 + 2 + wave, xcol, tg1, th1, r01);
     }
     if (collide) gather_C(rc, xcol, f, g, h);
-    set_pend();   // its loads (if any) are in flight with the gathers
+    pend_set();
     row_H(Y0 - 3 + wave, lane, v0);
     row_H(Y0 + 1 + wave, lane, v1);
     if (wave < 2) row_H(Y0 + 5 + wave, lane, v2);
