@@ -7,8 +7,8 @@
 // (x - c_i, y - c_i on a periodic grid; FP16 storage: the two rest
 // populations of g and h from FP32 planes), six history planes in the
 // collision type and two FP64 planes, each read once and written once, with
-// the step's non-temporal hints.  Thread (x, y) owns node (x, y); blocks of
-// 64 x 4 nodes.
+// the hints of the row sweep (non-temporal loads of f, plain loads and stores
+// otherwise).  Thread (x, y) owns node (x, y); blocks of 64 x 4 nodes.
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -55,23 +55,24 @@ __global__ __launch_bounds__(256) void k_probe(int nx, int ny, const S* __restri
     if (half && (i == 9 || i == 18)) {   // rest populations of g, h: FP32 planes, not streamed
       const int r = i / 9 - 1;
       acc += Rin[r * N + n];
-      __builtin_nontemporal_store(acc, Rout + r * N + n);
+      Rout[r * N + n] = acc;
       continue;
     }
     int sx = x - pcx(d), sy = y - pcy(d);
     sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
     sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
-    acc += (float)__builtin_nontemporal_load(Pin + (size_t)i * N + (size_t)sy * nx + sx);
-    __builtin_nontemporal_store((S)(0.5f * acc), Pout + (size_t)i * N + n);
+    const S* q = Pin + (size_t)i * N + (size_t)sy * nx + sx;
+    acc += (float)(i < 9 ? __builtin_nontemporal_load(q) : *q);   // f streams past the L2, as in the step
+    Pout[(size_t)i * N + n] = (S)(0.5f * acc);
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     acc += (float)hin[k * N + n];
-    __builtin_nontemporal_store((C)acc, hout + k * N + n);
+    hout[k * N + n] = (C)acc;
   }
   const double a = fin[n] + fin[N + n] + (double)acc;
-  __builtin_nontemporal_store(a, fout + n);
-  __builtin_nontemporal_store(0.5 * a, fout + N + n);
+  fout[n] = a;
+  fout[N + n] = 0.5 * a;
 }
 
 template <class S, class C>
