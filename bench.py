@@ -107,6 +107,25 @@ def roofline(res, key, cfg, precision):
     }
 
 
+def storage_line(cfg, precision, steps):
+    """The same grid in another storage: MLUPS and the step kernel's achieved
+    bandwidth on that storage's algorithmic bytes (HIP events), against the
+    peak."""
+    import torch
+
+    r = gpu_run(cfg, precision, steps, 10, steps)
+    kt = r["kernels"]
+    dom = max(kt, key=lambda k: kt[k][0])
+    ms = kt[dom][0] / max(kt[dom][1], 1)
+    gbs = r["bytes_node"] * r["N"] / (ms * 1e-3) / 1e9
+    out = {"mlups": round(r["N"] * steps / r["wall"] / 1e6, 1), "kernel": dom, "kernel_ms_per_launch": round(ms, 5),
+           "bytes_per_node_step": r["bytes_node"], "achieved": round(gbs, 2), "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del r
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_run(seed: int = 2000, count: int = 512, steps: int = 1024):
     """The batched sweep's step: `count` cases of the sweep distribution (uneven
     grids, angles, adsorption, surfactant load, shear) advanced together, one
@@ -275,6 +294,8 @@ def main():
                   % args.precision.upper(), mlups=round(rb["N"] * args.large_steps / rb["wall"] / 1e6, 1), **rl)
         out["roofline"] = rl
         del rb
+        if args.precision == "fp32":
+            out["roofline_other_storages"] = {prec: storage_line(big, prec, 40) for prec in ("fp64", "fp16")}
     if "roofline" not in out:   # the large grid was not run: the headline workload's kernel stands in
         out["roofline"] = head
     out["headline_kernel"] = dict(workload="the sessile workload above (state resident in the on-die caches)", **head)
