@@ -713,7 +713,7 @@ void orc_contact(const double* phi, int nx, int ny, double* width, double* heigh
 }
 
 void orc_invariants(orc_sim* s, orc_inv* out) {
-  int nx = s->nx, ny = s->ny, N = s->N;
+  int nx = s->nx, ny = s->ny;
   macro(s);
   memset(out, 0, sizeof(*out));
   out->step = s->step;

@@ -284,23 +284,6 @@ __device__ double block_reduce(double v, bool is_max) {
   return v;
 }
 
-// block_reduce's sum for blocks of kBlock or more threads: threads from kBlock
-// on contribute nothing, and the sum is formed as a kBlock block forms it.
-__device__ double block_sum_first(double v) {
-  __shared__ double sh[kBlock / 64];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  v = wave_red(v, false);
-  if (lane == 0 && wid < kBlock / 64) sh[wid] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = sh[0];
-    for (int k = 1; k < kBlock / 64; ++k) r = r + sh[k];
-    v = r;
-  }
-  __syncthreads();
-  return v;
-}
-
 // ------------------------------------------------------------------- kernels
 // Node (x, y) of the source of gathered population i (its emitter): x - c_i
 // inside the fluid, the node itself for a bounce-back at a wall.
@@ -480,8 +463,8 @@ struct StepArgs {
 // In two parts, so that a step can issue the loads of the previous step's
 // partial sums ahead of its own gathers and reduce them once those are in
 // flight: each thread's share (the first kBlock threads, as in k_step_finish),
-// then the block's three sums in one pass (each reduced as block_sum_first
-// reduces it) and the multipliers.
+// then the block's three sums in one pass (each: a wave reduction, then thread 0
+// adds the waves' results in wave order) and the multipliers.
 __device__ __forceinline__ void multipliers_load(const double* __restrict__ partials, int ntiles, double* t) {
   t[0] = t[1] = t[2] = 0.0;
   if (threadIdx.x < kBlock) {
