@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 
 typedef struct lbm_handle lbm_handle; /* opaque, owned by the library */
 
@@ -88,6 +88,12 @@ typedef struct {
                                size and precision (4 to 16 rows, up to 32 in FP64), a multiple of 4
                                up to 4096 forces it (a tuning knob: results differ only in the
                                summation order of the global multiplier sums) */
+  int32_t phi_hold;         /* 0 (default): lambda_phi as eq15 gives it, S1/S2, which holds d/dt of
+                               sum h_phi at zero in continuous time; the discrete step then lets sum h_phi
+                               drift (about 1e-7 of it per step in a 64^2 drop).  1: lambda_phi also
+                               returns sum h_phi to its value in the initial state (or the last
+                               lbm_load_fields), adding (m0 - S4)/(M_phi S2), S4 = sum h_phi now */
+  int32_t reserved;         /* set to 0 */
   double sigma_gl0, eps;    /* clean gas-liquid tension, thickness: kappa = 3 eps sigma/8, beta = 3 sigma/(4 eps) */
   double M_phi, M_psi;      /* mobilities (>= 0) */
   double lambda_s;          /* psi gradient coefficient; < 0 derive: kappa/2 with a wetting wall, else 0 */

@@ -72,6 +72,7 @@ struct orc_sim {
   double *Fx, *Fy, *grx, *gry, *Rphi, *Rpsi, *vx, *vy;
   double *Jphi_b, *Jpsi_b, *Jphi_t, *Jpsi_t; /* per-column wall fluxes */
   double lambda, mubar;
+  double m_ref;   /* sum of h_phi(phi) of the initial (or loaded) state */
 };
 
 /* ------------------------------------------------------------------ helpers */
@@ -87,6 +88,15 @@ static double gsw(const orc_sim* s, double ph) {
 static double gsw_d(const orc_sim* s, double ph) {
   double b = s->phib;
   return 3.0 / (4.0 * b) * (1.0 - ph * ph / (b * b));
+}
+/* h_phi(phi) itself: 1/2 + g (AC_phi) or phi. */
+static double hval(const orc_sim* s, double ph) {
+  return s->p.constraint_phi == ORC_LINEAR ? ph : 0.5 + gsw(s, ph);
+}
+static double sum_h(const orc_sim* s, const double* phi) {
+  double m = 0.0;
+  for (int n = 0; n < s->N; ++n) m += hval(s, phi[n]);
+  return m;
 }
 /* h_phi'(phi): weighted nonlinear constraint h = 1/2 + g (AC_phi) or linear h = phi. */
 static double hprime(const orc_sim* s, double ph) {
@@ -359,7 +369,7 @@ orc_sim* orc_create(const orc_params* p, char* err, int errlen) {
                      &s->Rphi, &s->Rpsi, &s->vx, &s->vy, &s->vx_h, &s->vy_h};
   for (size_t k = 0; k < sizeof(work) / sizeof(work[0]); ++k) *work[k] = zalloc(N);
   s->Jphi_b = zalloc(s->nx); s->Jpsi_b = zalloc(s->nx); s->Jphi_t = zalloc(s->nx); s->Jpsi_t = zalloc(s->nx);
-  init_fields(s);
+  init_fields(s);   /* also sets m_ref */
   return s;
 }
 
@@ -395,6 +405,7 @@ void orc_load_fields(orc_sim* s, const double* phi, const double* psi, const dou
     }
   }
   s->have_hist = 0;
+  s->m_ref = sum_h(s, phi);
 }
 
 void orc_get_populations(const orc_sim* s, double* out) {
@@ -454,14 +465,21 @@ static void macro(orc_sim* s) {
       else s->mu_psi[n] = 0.0;
     }
   /* O4: global multipliers, sequential FP64 sums in row-major order */
-  double S1 = 0.0, S2 = 0.0, S3 = 0.0;
+  double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
   for (int n = 0; n < N; ++n) {
     double hp = hprime(s, s->phi[n]);
     S1 += hp * s->mu_phi[n];
     S2 += hp * hp;
     S3 += s->mu_psi[n];
+    S4 += hval(s, s->phi[n]);
   }
   s->lambda = S2 > 0.0 ? S1 / S2 : 0.0;
+  /* Optional reading: eq15 keeps d/dt of sum h_phi at zero in continuous time,
+   * but the discrete step lets sum h_phi drift (the phi lattice's own diffusion
+   * is not the stencil Laplacian inside mu_phi that eq15 sees).  With phi_hold
+   * the multiplier also takes back the accumulated drift, (m_ref - S4) / (M S2),
+   * so that sum h_phi stays at its initial value as the paper states it does. */
+  if (s->p.phi_hold && S2 > 0.0 && s->p.M_phi > 0.0) s->lambda += (s->m_ref - S4) / (s->p.M_phi * S2);
   s->mubar = S3 / N;
   /* O5, O6: gradients, force, velocity, pressure */
 #pragma omp parallel for

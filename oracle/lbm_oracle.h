@@ -36,6 +36,9 @@ typedef struct {
   int32_t mms;            /* 1: manufactured-solution mode (Section 4.1), see orc_mms_* */
   int32_t adv_raw;        /* 1: advect phi, psi with the step's own velocity u (literal);
                              0: with the two-step mean (u(n) + u(n-1))/2 (default reading) */
+  int32_t phi_hold;       /* 1: the phi multiplier also returns sum h_phi to its initial value
+                             (see orc_step); 0: eq15 as printed (default) */
+  int32_t pad_;
   double sigma_gl0, eps;  /* clean tension and interface-thickness parameter */
   double M_phi, M_psi;    /* mobilities */
   double lambda_s;        /* psi gradient coefficient; <0: kappa/2 with a wetting wall, else 0 */

@@ -50,8 +50,8 @@ Layout make_layout(const lbm_params& p) {
   L.mu = take(2 * N * sizeof(double));
   L.uhist = take(2 * 6 * N * cb);  // u, v (advecting), R_phi, R_psi history, ping-pong
   const size_t ntile = lbm::step_blocks(p.nx, p.ny, 4);  // the most workgroups any segment height gives
-  L.partials = take((ntile > (size_t)lbm::kRedBlocks ? ntile : (size_t)lbm::kRedBlocks) * 3 * sizeof(double));
-  L.step_partials = take(2 * ntile * 3 * sizeof(double));
+  L.partials = take((ntile > (size_t)lbm::kRedBlocks ? ntile : (size_t)lbm::kRedBlocks) * lbm::kSums * sizeof(double));
+  L.step_partials = take(2 * ntile * lbm::kSums * sizeof(double));
   L.inv_partials = take(lbm::kRedBlocks * lbm::kInvValues * sizeof(double));
   L.inv_out = take(lbm::kInvOut * sizeof(double));
   L.contact = take(3 * (size_t)p.nx * sizeof(double));
@@ -77,6 +77,7 @@ std::string derive(const lbm_params& p, lbm::DevParams& d, double* derived) {
   if (p.constraint_phi != LBM_CONSTRAINT_NONLINEAR && p.constraint_phi != LBM_CONSTRAINT_LINEAR) return "unknown constraint";
   if (p.init_kind < LBM_INIT_DROP || p.init_kind > LBM_INIT_BUBBLE) return "unknown init kind";
   if (p.adv_raw != 0 && p.adv_raw != 1) return "adv_raw must be 0 or 1";
+  if (p.phi_hold != 0 && p.phi_hold != 1) return "phi_hold must be 0 or 1";
   if (p.tile_rows < 0 || p.tile_rows % 4 != 0 || p.tile_rows > 4096) return "tile_rows must be 0 or a multiple of 4 up to 4096";
   if (!(p.sigma_gl0 > 0.0) || !(p.eps > 0.0)) return "sigma_gl0 and eps must be > 0";
   if (!(p.M_phi >= 0.0) || !(p.M_psi >= 0.0)) return "mobilities must be >= 0";
@@ -97,6 +98,7 @@ std::string derive(const lbm_params& p, lbm::DevParams& d, double* derived) {
   d.surf = p.psi_b > 0.0;
   d.linear = p.constraint_phi == LBM_CONSTRAINT_LINEAR;
   d.adv_raw = p.adv_raw;
+  d.phi_hold = p.phi_hold;
   // interface coefficients of the Ginzburg-Landau energy
   const double kappa = 0.375 * p.eps * p.sigma_gl0, beta = 0.75 * p.sigma_gl0 / p.eps;
   const double W = p.W > 0.0 ? p.W : 4.0 * beta / (p.Ex > 0.0 ? p.Ex : 0.5);
@@ -199,7 +201,7 @@ void carve(lbm_handle* h) {
   {
     const size_t ntile = lbm::step_blocks(h->dp.nx, h->dp.ny, 4);
     s.step_partials[0] = (double*)(b + L.step_partials);
-    s.step_partials[1] = s.step_partials[0] + 3 * ntile;
+    s.step_partials[1] = s.step_partials[0] + lbm::kSums * ntile;
   }
   s.inv_partials = (double*)(b + L.inv_partials);
   s.inv_out = (double*)(b + L.inv_out);
@@ -239,6 +241,22 @@ int lbm_required_bytes(const lbm_params* p, size_t* bytes) {
   return LBM_OK;
 }
 
+// With phi_hold: m_ref := sum h_phi(phi) of the state the handle holds now (the
+// initial or a loaded one), from the invariant sums, written to the device copy
+// of the parameters.  Synchronises the handle's stream.
+static hipError_t set_m_ref(lbm_handle* h) {
+  if (!h->dp.phi_hold) return hipSuccess;
+  hipError_t e = lbm::launch_invariants(h->dp, h->ds, h->stream);
+  double v[lbm::kInvOut] = {0};
+  if (e == hipSuccess) e = hipMemcpyAsync(v, h->ds.inv_out, sizeof(v), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return e;
+  h->dp.m_ref = h->dp.linear ? v[2] : v[1];   // sum phi, or sum of 1/2 + g(phi)
+  e = hipMemcpyAsync(h->ds.dparams, &h->dp, sizeof(h->dp), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  return e;
+}
+
 int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_stream, lbm_handle** out) {
   if (!out) return fail(nullptr, LBM_E_ARG, "null output handle");
   *out = nullptr;
@@ -273,6 +291,7 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
   hipError_t e = hipMemcpyAsync(h->ds.dparams, &h->dp, sizeof(h->dp), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = lbm::launch_init(h->dp, h->ds, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = set_m_ref(h);
   if (e != hipSuccess) {
     std::string msg = std::string("initialisation kernels: ") + hipGetErrorString(e);
     lbm_destroy(h);
@@ -407,6 +426,7 @@ int lbm_load_fields(lbm_handle* h, uint32_t mask, const double* host, size_t n_d
     HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.field_buf + k * N, host + k * N, N * sizeof(double), hipMemcpyHostToDevice, h->stream), "copy fields");
   HIP_OR_FAIL(h, lbm::launch_load(h->dp, h->ds, (mask & vel) ? 1 : 0, h->stream), "load kernel");
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream), "synchronise");
+  HIP_OR_FAIL(h, set_m_ref(h), "constraint reference");
   h->have_hist = 0;
   h->faulted = false;
   return LBM_OK;
@@ -568,6 +588,7 @@ HandleView handle_view(lbm_handle* h) { return HandleView{&h->dp, &h->ds, &h->ha
 int handle_reinit(lbm_handle* h) {
   h->ds.cur = h->ds.hcur = h->ds.scur = 0;
   hipError_t e = lbm::launch_init(h->dp, h->ds, h->stream);
+  if (e == hipSuccess) e = set_m_ref(h);
   if (e != hipSuccess) return hip_fail(h, e, "initialisation kernels");
   h->have_hist = 0;
   h->step = 0;

@@ -37,6 +37,11 @@ struct DevParams {
   // before or after the next gather), but populations of the size of the
   // sources' departure from equilibrium instead of M_psi mu_psi itself.
   double mu_ref;
+  // With phi_hold the phi multiplier also returns sum h_phi(phi) to m_ref, its
+  // value in the initial (or last loaded) state: lambda = S1/S2 + (m_ref - S4) /
+  // (M_phi S2).  Off, lambda is eq15's S1/S2.
+  int phi_hold;
+  double m_ref;
   int init_kind;
 };
 
@@ -45,6 +50,10 @@ struct DevParams {
 // out of the stored populations and applies them when the next step gathers
 // them: cdef is the weight of that pending term (1.5 from R + dR/2, or 1 on a first step; 0 when nothing is
 // pending, e.g. right after loading fields).
+// Per-workgroup sums of a step: S1 = sum h'(phi) mu_phi, S2 = sum h'(phi)^2,
+// S3 = sum mu_psi, S4 = sum h_phi(phi).
+constexpr int kSums = 4;
+
 struct DevScalars {
   double lambda_phi, mubar_psi, cdef;
 };

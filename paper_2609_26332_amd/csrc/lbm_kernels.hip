@@ -174,6 +174,18 @@ __device__ __forceinline__ double hprime(const DevParams& p, double ph) { return
 __device__ __forceinline__ double liquid_frac(const DevParams& p, double ph) {
   return fmin(fmax(0.5 * (1.0 + ph * p.inv_phib), 0.0), 1.0);
 }
+// h_phi(phi): 1/2 + g(phi) (AC_phi) or phi (linear constraint).
+__device__ __forceinline__ double hval(const DevParams& p, double ph) {
+  if (p.linear) return ph;
+  const double u = ph * p.inv_phib;
+  return 0.5 + 0.75 * u - 0.25 * u * u * u;
+}
+// lambda_phi from the sums (eq15), with the optional return of sum h_phi to m_ref.
+__device__ __forceinline__ double lambda_of(const DevParams& p, double S1, double S2, double S4) {
+  double lam = S2 > 0.0 ? S1 / S2 : 0.0;
+  if (p.phi_hold && S2 > 0.0 && p.M_phi > 0.0) lam += (p.m_ref - S4) / (p.M_phi * S2);
+  return lam;
+}
 __device__ __forceinline__ double rho_of(const DevParams& p, double ph) {
   return p.rho_g + (p.rho_l - p.rho_g) * liquid_frac(p, ph);
 }
@@ -325,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_mu_partials(DevParams p, const doubl
                                                         double* __restrict__ partials) {
   const double* phi = phipsi;
   const double* psi = phipsi + p.N;
-  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
   for (int n = blockIdx.x * kBlock + threadIdx.x; n < p.N; n += gridDim.x * kBlock) {
     const int x = n % p.nx, y = n / p.nx;
     const double ph = phi[n], ps = psi[n];
@@ -337,26 +349,29 @@ __global__ __launch_bounds__(kBlock) void k_mu_partials(DevParams p, const doubl
     s1 += hp * mp;
     s2 += hp * hp;
     s3 += ms;
+    s4 += hval(p, ph);
   }
   s1 = block_reduce(s1, false);
   s2 = block_reduce(s2, false);
   s3 = block_reduce(s3, false);
+  s4 = block_reduce(s4, false);
   if (threadIdx.x == 0) {
-    partials[3 * blockIdx.x + 0] = s1;
-    partials[3 * blockIdx.x + 1] = s2;
-    partials[3 * blockIdx.x + 2] = s3;
+    partials[kSums * blockIdx.x + 0] = s1;
+    partials[kSums * blockIdx.x + 1] = s2;
+    partials[kSums * blockIdx.x + 2] = s3;
+    partials[kSums * blockIdx.x + 3] = s4;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_multipliers(int nblk, int N, const double* __restrict__ partials,
+__global__ __launch_bounds__(kBlock) void k_multipliers(DevParams p, int nblk, const double* __restrict__ partials,
                                                         DevScalars* __restrict__ sc) {
-  double s[3] = {0.0, 0.0, 0.0};
+  double s[kSums] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblk; b += kBlock)
-    for (int k = 0; k < 3; ++k) s[k] += partials[3 * b + k];
-  for (int k = 0; k < 3; ++k) s[k] = block_reduce(s[k], false);
+    for (int k = 0; k < kSums; ++k) s[k] += partials[kSums * b + k];
+  for (int k = 0; k < kSums; ++k) s[k] = block_reduce(s[k], false);
   if (threadIdx.x == 0) {
-    sc->lambda_phi = s[1] > 0.0 ? s[0] / s[1] : 0.0;
-    sc->mubar_psi = s[2] / (double)N;
+    sc->lambda_phi = lambda_of(p, s[0], s[1], s[3]);
+    sc->mubar_psi = s[2] / (double)p.N;
   }
 }
 
@@ -466,56 +481,57 @@ struct StepArgs {
 // then the block's three sums in one pass (each: a wave reduction, then thread 0
 // adds the waves' results in wave order) and the multipliers.
 __device__ __forceinline__ void multipliers_load(const double* __restrict__ partials, int ntiles, double* t) {
-  t[0] = t[1] = t[2] = 0.0;
+#pragma unroll
+  for (int c = 0; c < kSums; ++c) t[c] = 0.0;
   if (threadIdx.x < kBlock) {
 #pragma unroll 4
     for (int b = threadIdx.x; b < ntiles; b += kBlock) {
-      t[0] += partials[3 * (size_t)b + 0];
-      t[1] += partials[3 * (size_t)b + 1];
-      t[2] += partials[3 * (size_t)b + 2];
+#pragma unroll
+      for (int c = 0; c < kSums; ++c) t[c] += partials[kSums * (size_t)b + c];
     }
   }
 }
-__device__ __forceinline__ DevScalars multipliers_reduce(const double* t, int N, int have_hist) {
-  __shared__ double sh[3][kBlock / 64];
+__device__ __forceinline__ DevScalars multipliers_reduce(const double* t, const DevParams& p, int have_hist) {
+  __shared__ double sh[kSums][kBlock / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const double w0 = wave_red(t[0], false), w1 = wave_red(t[1], false), w2 = wave_red(t[2], false);
+  double w[kSums];
+#pragma unroll
+  for (int c = 0; c < kSums; ++c) w[c] = wave_red(t[c], false);
   if (lane == 0 && wid < kBlock / 64) {
-    sh[0][wid] = w0;
-    sh[1][wid] = w1;
-    sh[2][wid] = w2;
+#pragma unroll
+    for (int c = 0; c < kSums; ++c) sh[c][wid] = w[c];
   }
   __syncthreads();
   __shared__ DevScalars res;
   if (threadIdx.x == 0) {
-    double r[3];
+    double r[kSums];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < kSums; ++c) {
       r[c] = sh[c][0];
       for (int k = 1; k < kBlock / 64; ++k) r[c] = r[c] + sh[c][k];
     }
-    res.lambda_phi = r[1] > 0.0 ? r[0] / r[1] : 0.0;
-    res.mubar_psi = r[2] / (double)N;
+    res.lambda_phi = lambda_of(p, r[0], r[1], r[3]);
+    res.mubar_psi = r[2] / (double)p.N;
     res.cdef = have_hist ? 1.5 : 1.0;
   }
   __syncthreads();
   return res;
 }
-__device__ __forceinline__ DevScalars multipliers_of(const double* __restrict__ partials, int ntiles, int N,
+__device__ __forceinline__ DevScalars multipliers_of(const double* __restrict__ partials, int ntiles, const DevParams& p,
                                                     int have_hist) {
-  double t[3];
+  double t[kSums];
   multipliers_load(partials, ntiles, t);
-  return multipliers_reduce(t, N, have_hist);
+  return multipliers_reduce(t, p, have_hist);
 }
-__device__ __forceinline__ void finish_body(const double* __restrict__ partials, int ntiles, int N, int have_hist,
-                                            DevScalars* __restrict__ next) {
-  const DevScalars r = multipliers_of(partials, ntiles, N, have_hist);
+__device__ __forceinline__ void finish_body(const double* __restrict__ partials, int ntiles, const DevParams& p,
+                                            int have_hist, DevScalars* __restrict__ next) {
+  const DevScalars r = multipliers_of(partials, ntiles, p, have_hist);
   if (threadIdx.x == 0) *next = r;
 }
 
-__global__ __launch_bounds__(kBlock) void k_step_finish(const double* __restrict__ partials, int ntiles, int N,
-                                                        int have_hist, DevScalars* __restrict__ next) {
-  finish_body(partials, ntiles, N, have_hist, next);
+__global__ __launch_bounds__(kBlock) void k_step_finish(const DevParams* __restrict__ pp, const double* __restrict__ partials,
+                                                        int ntiles, int have_hist, DevScalars* __restrict__ next) {
+  finish_body(partials, ntiles, *pp, have_hist, next);
 }
 
 // Element at byte offset b (32-bit, per lane) from a row base pointer (64-bit,
@@ -636,13 +652,13 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   // them.
   // pend_load() issues the loads, pend_set() reduces and sets the terms.
   DevScalars pend;
-  double lam1_ = 0.0, mub1_ = 0.0, pt_[3];
+  double lam1_ = 0.0, mub1_ = 0.0, pt_[kSums];
   auto pend_load = [&]() {
     if (a.prev_partials) multipliers_load(a.prev_partials, a.ntiles, pt_);
     else pend = *a.pend;
   };
   auto pend_set = [&]() {
-    if (a.prev_partials) pend = multipliers_reduce(pt_, p.N, a.prev_have_hist);
+    if (a.prev_partials) pend = multipliers_reduce(pt_, p, a.prev_have_hist);
     lam1_ = pend.cdef * p.M_phi * pend.lambda_phi;
     mub1_ = pend.cdef * p.M_psi * (pend.mubar_psi - p.mu_ref);
   };
@@ -749,7 +765,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   };
 
   // ---- B: (mu_phi, mu_psi) of row gy into ring slot gy (lanes 1..62)
-  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
   auto row_B = [&](int gy, int ln) {
     const int y = wave_uniform(row_of(gy)), yc = centre(gy);
     const int l = min(max(ln, 1), 62);   // lanes 0 and 63 have no neighbour column: computed, unused
@@ -785,6 +801,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       s1 += hp * mp;
       s2 += hp * hp;
       s3 += ms;
+      s4 += hval(p, ph);
     }
   };
 
@@ -1250,21 +1267,21 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     __syncthreads();
     if (fwave) row_Cf(collide, rc, lane, xcol, f);
     else row_Cgh(collide, rc, lane, xcol, g, h, hv);
-    __shared__ double sR[3][8];
-    const double q[3] = {wave_red(s1, false), wave_red(s2, false), wave_red(s3, false)};
+    __shared__ double sR[kSums][8];
+    const double q[kSums] = {wave_red(s1, false), wave_red(s2, false), wave_red(s3, false), wave_red(s4, false)};
     if (lane == 0) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) sR[c][wave] = q[c];
+      for (int c = 0; c < kSums; ++c) sR[c][wave] = q[c];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < kSums; ++c) {
         double r = sR[c][2];   // rows Y0+1, Y0+2, Y0+3, Y0 are those of waves 2, 3, 4, 1
         r = r + sR[c][3];
         r = r + sR[c][4];
         r = r + sR[c][1];
-        a.partials[3 * (size_t)tile + c] = r;
+        a.partials[kSums * (size_t)tile + c] = r;
       }
     }
     return;
@@ -1308,10 +1325,12 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     s1 = block_reduce(s1, false);
     s2 = block_reduce(s2, false);
     s3 = block_reduce(s3, false);
+    s4 = block_reduce(s4, false);
     if (threadIdx.x == 0) {
-      a.partials[3 * (size_t)tile + 0] = s1;
-      a.partials[3 * (size_t)tile + 1] = s2;
-      a.partials[3 * (size_t)tile + 2] = s3;
+      a.partials[kSums * (size_t)tile + 0] = s1;
+      a.partials[kSums * (size_t)tile + 1] = s2;
+      a.partials[kSums * (size_t)tile + 2] = s3;
+      a.partials[kSums * (size_t)tile + 3] = s4;
     }
     return;
   }
@@ -1358,10 +1377,12 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   s1 = block_reduce(s1, false);
   s2 = block_reduce(s2, false);
   s3 = block_reduce(s3, false);
+  s4 = block_reduce(s4, false);
   if (threadIdx.x == 0) {
-    a.partials[3 * (size_t)tile + 0] = s1;
-    a.partials[3 * (size_t)tile + 1] = s2;
-    a.partials[3 * (size_t)tile + 2] = s3;
+    a.partials[kSums * (size_t)tile + 0] = s1;
+    a.partials[kSums * (size_t)tile + 1] = s2;
+    a.partials[kSums * (size_t)tile + 2] = s3;
+    a.partials[kSums * (size_t)tile + 3] = s4;
   }
 }
 
@@ -1431,7 +1452,7 @@ __global__ __launch_bounds__(kBlock) void k_step_finish_batch(BatchCase* __restr
   BatchCase& bc = cases[blockIdx.x];
   if (!bc.active) return;
   const int par = bc.parity, hh = bc.have_hist;
-  finish_body(bc.partials, bc.ntiles, bc.p.N, hh, bc.scalars + (par ^ 1));
+  finish_body(bc.partials, bc.ntiles, bc.p, hh, bc.scalars + (par ^ 1));
   __syncthreads();
   if (threadIdx.x == 0) {
     bc.parity = par ^ 1;
@@ -1736,7 +1757,7 @@ hipError_t macro_impl(const DevParams& p, DevState& s, hipStream_t st) {
   hipLaunchKernelGGL((k_moments<S, C>), dim3(nblocks(p.N)), dim3(kBlock), 0, st, p, (const S*)s.pops[s.cur], ref,
                      (const DevScalars*)(s.scalars + s.scur), pp);
   hipLaunchKernelGGL(k_mu_partials, dim3(rb), dim3(kBlock), 0, st, p, (const double*)pp, (double*)s.mu, s.partials);
-  hipLaunchKernelGGL(k_multipliers, dim3(1), dim3(kBlock), 0, st, rb, p.N, (const double*)s.partials, s.scalars + 2);
+  hipLaunchKernelGGL(k_multipliers, dim3(1), dim3(kBlock), 0, st, p, rb, (const double*)s.partials, s.scalars + 2);
   return hipGetLastError();
 }
 
@@ -1776,8 +1797,8 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
   }
   if (!(fuse & kFuseNext)) {
     TimedScope ts(t, LBM_K_FINISH, st);
-    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(kBlock), 0, st, (const double*)a.partials, a.ntiles, p.N, have_hist,
-                       a.next);
+    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(kBlock), 0, st, (const DevParams*)s.dparams, (const double*)a.partials,
+                       a.ntiles, have_hist, a.next);
   }
 }
 

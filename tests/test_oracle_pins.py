@@ -397,3 +397,24 @@ def test_static_equilibrium_independent_of_density_ratio_sec42():
     assert f["phi"].min() < -hi.derived()["phi_b"]      # the bulk does pass -phi_b ...
     assert f["rho"].min() == 1.0 and f["rho"].max() <= 1000.0   # ... and the density is held
     assert a["umax"] < 0.1 * b["umax"]
+
+
+
+# ---------------------------------------------- the phi constraint over time
+def test_phi_constraint_drift_and_hold_sec21():
+    """eq15's multiplier holds d/dt sum h_phi = 0 for the continuous equation;
+    in the discrete step sum h_phi drifts (the phi lattice carries the diffusion,
+    the multiplier sees the stencil Laplacian inside mu_phi).  With phi_hold the
+    multiplier also returns the drift and sum h_phi stays at round-off level of
+    its start, while lambda_phi keeps within 3% of sigma/R (Appendix A)."""
+    cfg = inputs.stationary_drop(psi_b=0.0)
+    out = {}
+    for hold in (0, 1):
+        s = sim(dict(cfg, phi_hold=hold))
+        m0 = s.invariants()["m_phi_h"]
+        s.step(10000)
+        iv = s.invariants()
+        out[hold] = (abs(iv["m_phi_h"] - m0) / m0, iv["lambda_phi"])
+    assert out[0][0] > 5e-4            # eq15 as printed drifts
+    assert out[1][0] < 2e-6            # held
+    assert out[1][1] == pytest.approx(0.01 / 16.0, rel=0.03)
