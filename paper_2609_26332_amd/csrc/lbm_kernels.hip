@@ -457,10 +457,10 @@ struct StepArgs {
   void* hout;               // the same for step n
   const DevScalars* pend;   // multipliers pending on Pin (from step n-1)
   DevScalars* next;         // multipliers of step n, written by k_step_finish
-  double* partials;         // [ntiles][3]
+  double* partials;         // [ntiles][kSums]: S1, S2, S3, S4 (S4 only under phi_hold, else 0)
   int have_hist, nstrips, seg_rows, ntiles;
   // Non-null: the multipliers pending on Pin are reduced here, by every
-  // workgroup, from step n-1's partials ([ntiles][3], the same tiling; step
+  // workgroup, from step n-1's partials ([ntiles][kSums], the same tiling; step
   // n-1 had a history iff prev_have_hist) instead of being read from pend;
   // k_step_finish did not run for step n-1.
   const double* prev_partials;
@@ -496,7 +496,8 @@ __device__ __forceinline__ DevScalars multipliers_reduce(const double* t, const 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double w[kSums];
 #pragma unroll
-  for (int c = 0; c < kSums; ++c) w[c] = wave_red(t[c], false);
+  for (int c = 0; c < kSums - 1; ++c) w[c] = wave_red(t[c], false);
+  w[kSums - 1] = p.phi_hold ? wave_red(t[kSums - 1], false) : 0.0;   // S4 serves the hold only
   if (lane == 0 && wid < kBlock / 64) {
 #pragma unroll
     for (int c = 0; c < kSums; ++c) sh[c][wid] = w[c];
@@ -801,7 +802,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       s1 += hp * mp;
       s2 += hp * hp;
       s3 += ms;
-      s4 += hval(p, ph);
+      if (p.phi_hold) s4 += hval(p, ph);   // S4 serves the hold only
     }
   };
 
@@ -1268,7 +1269,8 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     if (fwave) row_Cf(collide, rc, lane, xcol, f);
     else row_Cgh(collide, rc, lane, xcol, g, h, hv);
     __shared__ double sR[kSums][8];
-    const double q[kSums] = {wave_red(s1, false), wave_red(s2, false), wave_red(s3, false), wave_red(s4, false)};
+    const double q[kSums] = {wave_red(s1, false), wave_red(s2, false), wave_red(s3, false),
+                             p.phi_hold ? wave_red(s4, false) : 0.0};
     if (lane == 0) {
 #pragma unroll
       for (int c = 0; c < kSums; ++c) sR[c][wave] = q[c];
@@ -1325,7 +1327,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     s1 = block_reduce(s1, false);
     s2 = block_reduce(s2, false);
     s3 = block_reduce(s3, false);
-    s4 = block_reduce(s4, false);
+    if (p.phi_hold) s4 = block_reduce(s4, false);
     if (threadIdx.x == 0) {
       a.partials[kSums * (size_t)tile + 0] = s1;
       a.partials[kSums * (size_t)tile + 1] = s2;
@@ -1377,7 +1379,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   s1 = block_reduce(s1, false);
   s2 = block_reduce(s2, false);
   s3 = block_reduce(s3, false);
-  s4 = block_reduce(s4, false);
+  if (p.phi_hold) s4 = block_reduce(s4, false);
   if (threadIdx.x == 0) {
     a.partials[kSums * (size_t)tile + 0] = s1;
     a.partials[kSums * (size_t)tile + 1] = s2;
