@@ -47,7 +47,7 @@ class Params(ctypes.Structure):
         ("bc_bottom", ctypes.c_int32), ("bc_top", ctypes.c_int32),
         ("constraint_phi", ctypes.c_int32), ("init_kind", ctypes.c_int32),
         ("mms", ctypes.c_int32), ("adv_raw", ctypes.c_int32),
-        ("phi_hold", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("phi_hold", ctypes.c_int32), ("sat_cap", ctypes.c_int32),
         ("sigma_gl0", ctypes.c_double), ("eps", ctypes.c_double),
         ("M_phi", ctypes.c_double), ("M_psi", ctypes.c_double),
         ("lambda_s", ctypes.c_double), ("kBT", ctypes.c_double), ("W", ctypes.c_double),

@@ -115,19 +115,46 @@ static double rho_of(const orc_sim* s, double ph) {
 static double mud_of(const orc_sim* s, double ph) {
   return s->p.mu_g + (s->p.mu_l - s->p.mu_g) * liquid_frac(s, ph);
 }
+/* Remark 1: the factor by which surfactant lowers a solid-fluid tension,
+ * 1 + beta ln(1 - psi) (eq "langmuir"), held at 1/2 or more, and its psi
+ * derivative, -beta/(1 - psi) on the smooth side and zero where the hold acts.
+ * Used only with sat_cap; the default is the smooth form below. */
+static double sat_factor(double beta, double ps) {
+  double q = 1.0 + beta * log(1.0 - ps);
+  return q < 0.5 ? 0.5 : q;
+}
+static double sat_factor_d(double beta, double ps) {
+  double q = 1.0 + beta * log(1.0 - ps);
+  return q <= 0.5 ? 0.0 : -beta / (1.0 - ps);
+}
+/* The wall energy is f_w = (s_sg + s_sl)/2 - (s_sg - s_sl) g(phi), with
+ * s_sa = sigma_sa0 (factor of psi) and the clean difference sigma cos(theta0). */
+static double wall_diff_sat(const orc_sim* s, double ps) {
+  double cth = cos(s->p.theta0_deg * M_PI / 180.0);
+  return s->p.sigma_gl0 * cth + s->sg0 * (sat_factor(s->p.beta_sg, ps) - 1.0)
+       - s->sl0 * (sat_factor(s->p.beta_sl, ps) - 1.0);
+}
 /* -df_w/dphi and -df_w/dpsi of the wall energy (eq8, boundary). */
 static double wall_Jphi(const orc_sim* s, double ph, double ps) {
+  if (s->surf && s->p.sat_cap) return wall_diff_sat(s, ps) * gsw_d(s, ph);
   double cth = cos(s->p.theta0_deg * M_PI / 180.0);
   double a = s->p.sigma_gl0 * cth;
   if (s->surf) a += log(1.0 - ps) * (s->sg0 * s->p.beta_sg - s->sl0 * s->p.beta_sl);
   return a * gsw_d(s, ph);
 }
 static double wall_Jpsi(const orc_sim* s, double ph, double ps) {
+  if (s->p.sat_cap) {
+    double dsg = s->sg0 * sat_factor_d(s->p.beta_sg, ps), dsl = s->sl0 * sat_factor_d(s->p.beta_sl, ps);
+    return -(0.5 * (dsg + dsl) - (dsg - dsl) * gsw(s, ph));
+  }
   double d = s->sg0 * s->p.beta_sg - s->sl0 * s->p.beta_sl;
   double m = s->sg0 * s->p.beta_sg + s->sl0 * s->p.beta_sl;
   return -(d * gsw(s, ph) - 0.5 * m) / (1.0 - ps);
 }
 static double wall_fw(const orc_sim* s, double ph, double ps) {
+  if (s->surf && s->p.sat_cap)
+    return 0.5 * (s->sg0 * sat_factor(s->p.beta_sg, ps) + s->sl0 * sat_factor(s->p.beta_sl, ps))
+         - wall_diff_sat(s, ps) * gsw(s, ph);
   double cth = cos(s->p.theta0_deg * M_PI / 180.0);
   double l = s->surf ? log(1.0 - ps) : 0.0;
   double d = s->sg0 * s->p.beta_sg - s->sl0 * s->p.beta_sl;

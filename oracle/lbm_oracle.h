@@ -38,7 +38,8 @@ typedef struct {
                              0: with the two-step mean (u(n) + u(n-1))/2 (default reading) */
   int32_t phi_hold;       /* 1: the phi multiplier also returns sum h_phi to its initial value
                              (see orc_step); 0: eq15 as printed (default) */
-  int32_t pad_;
+  int32_t sat_cap;        /* 1: Remark-1 saturation, sigma_sa(psi) = sigma_sa0 max(1/2, 1 + beta_sa ln(1 - psi));
+                             0: the smooth Langmuir-Szyszkowski form the paper computes with (default) */
   double sigma_gl0, eps;  /* clean tension and interface-thickness parameter */
   double M_phi, M_psi;    /* mobilities */
   double lambda_s;        /* psi gradient coefficient; <0: kappa/2 with a wetting wall, else 0 */

@@ -379,6 +379,45 @@ def test_adsorption_shifts_contact_angle_sec44():
     assert ang["sl"] < ang["clean"] - 0.3 < ang["sg"] - 0.6, ang
 
 
+
+def test_saturated_wall_stops_adsorbing_remark1():
+    """Remark 1 (saturation): where 1 + beta_sg ln(1 - psi) falls below 1/2 the
+    solid-gas tension is held at half its clean value, so the wall energy no
+    longer depends on psi there and a gas-covered wall stops adsorbing.  A column
+    of gas at uniform psi_b = 0.1 on a wall with beta_sg = 6 (factor 0.37) and
+    beta_sl = 0 stays uniform with the saturation on, while the smooth form makes
+    the wall row adsorb.  Where the factor stays above 1/2 (beta_sg = 0.5) the two
+    forms give the same fields."""
+    base = inputs.sessile_drop(nx=8, ny=12, R=-1000.0, psi_b=0.1, beta_sg=6.0, beta_sl=0.0)
+    out = {}
+    for cap in (0, 1):
+        s = sim(dict(base, sat_cap=cap))
+        s.step(200)
+        out[cap] = s.fields(["phi", "psi"])
+    assert np.abs(out[1]["psi"] - 0.1).max() < 1e-12
+    assert out[0]["psi"][0].mean() - 0.1 > 1e-4
+    weak = dict(base, beta_sg=0.5)
+    runs = []
+    for cap in (0, 1):
+        s = sim(dict(weak, sat_cap=cap))
+        s.step(200)
+        runs.append(s.fields(["phi", "psi"]))
+    assert out[0]["psi"][0].mean() > runs[0]["psi"][0].mean() > 0.1
+    for k in ("phi", "psi"):
+        assert np.abs(runs[0][k] - runs[1][k]).max() < 1e-13
+    # a drop on the wall, below the saturation: the contact line exercises
+    # -df_w/dphi and the wall energy as well
+    drop = inputs.sessile_drop(nx=32, ny=16, R=7.0, theta0_deg=70.0, psi_b=0.05, beta_sg=0.5, beta_sl=0.2)
+    res = []
+    for cap in (0, 1):
+        s = sim(dict(drop, sat_cap=cap))
+        s.step(300)
+        res.append((s.fields(["phi", "psi"]), s.invariants()))
+    for k in ("phi", "psi"):
+        assert np.abs(res[0][0][k] - res[1][0][k]).max() < 1e-12
+    assert res[0][1]["free_energy"] == pytest.approx(res[1][1]["free_energy"], rel=1e-12)
+
+
 # ------------------------------------------------- density-ratio independence
 def test_static_equilibrium_independent_of_density_ratio_sec42():
     """At rest the phase-field and surfactant equations do not see the density:
