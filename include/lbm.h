@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 2
+#define LBM_ABI_VERSION 3
 
 typedef struct lbm_handle lbm_handle; /* opaque, owned by the library */
 
@@ -93,7 +93,11 @@ typedef struct {
                                drift (about 1e-7 of it per step in a 64^2 drop).  1: lambda_phi also
                                returns sum h_phi to its value in the initial state (or the last
                                lbm_load_fields), adding (m0 - S4)/(M_phi S2), S4 = sum h_phi now */
-  int32_t reserved;         /* set to 0 */
+  int32_t sat_cap;          /* Remark 1 (Sec. 2.1): 0 (default) the smooth Langmuir-Szyszkowski
+                               tensions sigma_sa0 (1 + beta_sa ln(1 - psi)) the paper computes with;
+                               1: each held at half its clean value or more, sigma_sa0 max(1/2,
+                               1 + beta_sa ln(1 - psi)), in the wall energy and both wall fluxes (the
+                               psi derivative is zero where the hold acts).  Other values: LBM_E_ARG */
   double sigma_gl0, eps;    /* clean gas-liquid tension, thickness: kappa = 3 eps sigma/8, beta = 3 sigma/(4 eps) */
   double M_phi, M_psi;      /* mobilities (>= 0) */
   double lambda_s;          /* psi gradient coefficient; < 0 derive: kappa/2 with a wetting wall, else 0 */

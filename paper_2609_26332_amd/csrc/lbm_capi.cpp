@@ -78,6 +78,7 @@ std::string derive(const lbm_params& p, lbm::DevParams& d, double* derived) {
   if (p.init_kind < LBM_INIT_DROP || p.init_kind > LBM_INIT_BUBBLE) return "unknown init kind";
   if (p.adv_raw != 0 && p.adv_raw != 1) return "adv_raw must be 0 or 1";
   if (p.phi_hold != 0 && p.phi_hold != 1) return "phi_hold must be 0 or 1";
+  if (p.sat_cap != 0 && p.sat_cap != 1) return "sat_cap must be 0 or 1";
   if (p.tile_rows < 0 || p.tile_rows % 4 != 0 || p.tile_rows > 4096) return "tile_rows must be 0 or a multiple of 4 up to 4096";
   if (!(p.sigma_gl0 > 0.0) || !(p.eps > 0.0)) return "sigma_gl0 and eps must be > 0";
   if (!(p.M_phi >= 0.0) || !(p.M_psi >= 0.0)) return "mobilities must be >= 0";
@@ -133,6 +134,7 @@ std::string derive(const lbm_params& p, lbm::DevParams& d, double* derived) {
   d.msb = sg0 * p.beta_sg + sl0 * p.beta_sl;
   d.fw0 = 0.5 * (sg0 + sl0);
   d.beta_sg = p.beta_sg; d.beta_sl = p.beta_sl;
+  d.sat_cap = p.sat_cap; d.sg0 = sg0; d.sl0 = sl0;
   for (int k = 0; k < 5; ++k) { d.sf[k] = rate(p.s_f[k]); d.sg[k] = rate(p.s_g[k]); d.sh[k] = rate(p.s_h[k]); }
   d.s2_local = !(p.s_f[2] > 0.0);
   d.x0 = p.x0; d.y0 = p.y0; d.R0 = p.R0; d.a = p.a;

@@ -27,6 +27,10 @@ struct DevParams {
   double msb;      // sigma_sg0 beta_sg + sigma_sl0 beta_sl
   double fw0;      // (sigma_sg0 + sigma_sl0) / 2
   double beta_sg, beta_sl;
+  // Remark 1: with sat_cap each solid-fluid tension sigma_sa0 (1 + beta_sa
+  // ln(1 - psi)) is held at sigma_sa0 / 2 or more.
+  int sat_cap;
+  double sg0, sl0;
   double sf[5], sg[5], sh[5];
   double x0, y0, R0, a;
   double psi_b, init_scale;  // init_scale = 2 phi_b sqrt(1 - psi_b) / eps

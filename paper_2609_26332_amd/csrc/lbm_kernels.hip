@@ -192,14 +192,31 @@ __device__ __forceinline__ double rho_of(const DevParams& p, double ph) {
 __device__ __forceinline__ double mud_of(const DevParams& p, double ph) {
   return p.mu_g + (p.mu_l - p.mu_g) * liquid_frac(p, ph);
 }
+// Wall energy f_w = (s_sg + s_sl)/2 - (s_sg - s_sl) g(phi) with s_sa =
+// sigma_sa0 (1 + beta_sa L), L = ln(1 - psi).  Under Remark 1's saturation each
+// beta_sa L is held at -1/2 or more; returns the surfactant parts of s_sg - s_sl
+// and of s_sg + s_sl.
+__device__ __forceinline__ double2 wall_surf_terms(const DevParams& p, double L) {
+  if (!p.sat_cap) return make_double2(L * p.dsb, L * p.msb);
+  const double a = p.sg0 * fmax(-0.5, p.beta_sg * L), b = p.sl0 * fmax(-0.5, p.beta_sl * L);
+  return make_double2(a - b, a + b);
+}
 // J_phi = -df_w/dphi, J_psi = -df_w/dpsi at a wall node (eq8, boundary).
 __device__ __forceinline__ double Jphi(const DevParams& p, double ph, double ps) {
   double a = p.sig_cos;
-  if (p.surf) a += log(1.0 - ps) * p.dsb;
+  if (p.surf) a += wall_surf_terms(p, log(1.0 - ps)).x;
   return a * gsw_d(p, ph);
 }
 __device__ __forceinline__ double Jpsi(const DevParams& p, double ph, double ps) {
-  return -(p.dsb * gsw(p, ph) - 0.5 * p.msb) / (1.0 - ps);
+  double d = p.dsb, m = p.msb;
+  if (p.sat_cap) {   // each tension's psi derivative vanishes where its hold acts
+    const double L = log(1.0 - ps);
+    const double cg = p.beta_sg * L > -0.5 ? p.sg0 * p.beta_sg : 0.0;
+    const double cl = p.beta_sl * L > -0.5 ? p.sl0 * p.beta_sl : 0.0;
+    d = cg - cl;
+    m = cg + cl;
+  }
+  return -(d * gsw(p, ph) - 0.5 * m) / (1.0 - ps);
 }
 
 // Laplacian pieces at (x,y): zero-flux part L0 of phi and psi, and the wall
@@ -1657,7 +1674,8 @@ __global__ __launch_bounds__(kBlock) void k_invariants(DevParams p, const S* __r
     for (int w = 0; w < 2; ++w) {
       if (!(w == 0 ? wall_row_b : wall_row_t)) continue;
       const double l = p.surf ? log(1.0 - ps) : 0.0;
-      e += -(p.sig_cos + l * p.dsb) * gsw(p, ph) + 0.5 * l * p.msb + p.fw0;
+      const double2 st = wall_surf_terms(p, l);
+      e += -(p.sig_cos + st.x) * gsw(p, ph) + 0.5 * st.y + p.fw0;
       if (p.surf) {
         if (p.beta_sg > 0.0 && 1.0 + p.beta_sg * l <= 0.5) acc[9] += 1.0;
         if (p.beta_sl > 0.0 && 1.0 + p.beta_sl * l <= 0.5) acc[9] += 1.0;

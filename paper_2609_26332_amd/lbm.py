@@ -18,7 +18,7 @@ import torch  # noqa: F401  -- loads torch's HIP runtime first so one runtime se
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 PERIODIC, WALL_WET, NOSLIP, FREESLIP = 0, 1, 2, 3
 FP64, FP32, FP16_SHIFTED = 0, 1, 2
 NONLINEAR, LINEAR = 0, 1
@@ -54,7 +54,7 @@ class Params(ctypes.Structure):
         ("bc_bottom", ctypes.c_int32), ("bc_top", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("constraint_phi", ctypes.c_int32), ("init_kind", ctypes.c_int32),
         ("adv_raw", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-        ("phi_hold", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("phi_hold", ctypes.c_int32), ("sat_cap", ctypes.c_int32),
         ("sigma_gl0", ctypes.c_double), ("eps", ctypes.c_double),
         ("M_phi", ctypes.c_double), ("M_psi", ctypes.c_double), ("lambda_s", ctypes.c_double),
         ("kBT", ctypes.c_double), ("W", ctypes.c_double), ("Ex", ctypes.c_double), ("Pi", ctypes.c_double),

@@ -64,6 +64,10 @@ CASES = {
     "static_ratio1000_64": inputs.static_drop_ratio1000(nx=64, ny=64, R=16.0),
     "phi_hold_wall_60": dict(inputs.sessile_drop(nx=96, ny=48, R=16.0, psi_b=0.0), phi_hold=1),
     "phi_hold_linear": inputs.stationary_drop(nx=48, ny=40, R=12.0, constraint_phi=inputs.LINEAR, phi_hold=1),
+    # Remark-1 saturation: psi_b = 0.1 and beta_sg = 4 put about half of the wall
+    # row past the hold (1 + beta_sg ln(1 - psi) <= 1/2), the rest below it
+    "saturation_wall": dict(inputs.sessile_drop(nx=96, ny=48, R=16.0, psi_b=0.1, beta_sg=4.0, beta_sl=0.01),
+                            sat_cap=1),
 }
 
 
@@ -75,7 +79,8 @@ def test_fp64_parity(lbm, name):
 
 
 @pytest.mark.parametrize("name", ["stationary_drop_64", "sessile_adsorbing_96x48", "shear_ratio10_128x64",
-                                  "ragged_67x37_walls", "clean_bubble_freeslip", "static_ratio1000_64"])
+                                  "ragged_67x37_walls", "clean_bubble_freeslip", "static_ratio1000_64",
+                                  "saturation_wall"])
 def test_fp32_parity(lbm, name):
     cfg = CASES[name]
     for step, gf, of, _, _ in run_pair(lbm, cfg, "fp32", [1, 20, 300]):
