@@ -7,7 +7,7 @@
  * load, capillary number, drop radius; scaled by the caller) to two outputs
  * (steady apparent contact angle and detachment time, standardised by the
  * caller).  Not part of the paper's method: a surrogate layer over the
- * lattice Boltzmann solver, which remains the fallback and the judge of its
+ * lattice Boltzmann solver, which remains the fallback and the arbiter of its
  * error.
  *
  * Numerics: every matrix product runs on the matrix cores as
