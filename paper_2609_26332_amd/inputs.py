@@ -110,6 +110,19 @@ def shear_drop(nx: int = 512, ny: int = 256, R: float = 64.0, Ca: float = 0.1,
     return cfg
 
 
+def spreading_drop(theta0_deg: float = 90.0, nx: int = 200, ny: int = 100, R: float = 35.0,
+                   psi_b: float = 0.0, **kw) -> dict:
+    """Drop spreading on a wetting wall at the density and viscosity ratios of
+    Sec. 4.3 (rho 1000:1, mu 100:1) in lattice units: a semicircle of radius R
+    centred on the wall, interface width 6, sigma0 = 0.01, light phase at unit
+    density with nu_g = 1, liquid nu_l = 0.1, no-slip top wall."""
+    cfg = sessile_drop(nx=nx, ny=ny, R=R, theta0_deg=theta0_deg, psi_b=psi_b)
+    cfg.update(eps=6.0, sigma_gl0=0.01, rho_l=1000.0, rho_g=1.0, mu_l=100.0, mu_g=1.0, bc_top=NOSLIP,
+               beta_sg=0.0, beta_sl=0.0)
+    cfg.update(kw)
+    return cfg
+
+
 def flat_slab(nx: int = 256, ny: int = 4, width: float = 128.0, psi_b: float = 0.0, **kw) -> dict:
     """Flat liquid slab across a periodic box (two planar interfaces)."""
     return _base(nx=nx, ny=ny, bc_bottom=PERIODIC, bc_top=PERIODIC, psi_b=psi_b,

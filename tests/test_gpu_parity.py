@@ -59,6 +59,11 @@ CASES = {
     "clean_bubble_freeslip": dict(inputs.sessile_drop(nx=64, ny=40, R=10.0, psi_b=0.0, theta0_deg=45.0),
                                   init_kind=inputs.INIT_BUBBLE, y0=20.0, bc_bottom=inputs.FREESLIP),
     "literal_advection": inputs.stationary_drop(nx=40, ny=40, R=10.0, adv_raw=1),
+    "literal_advection_walls": dict(inputs.sessile_drop(nx=96, ny=48, R=16.0), adv_raw=1),
+    # Sec. 4.3's ratios (rho 1000:1, mu 100:1) on a wetting wall, clean at 90 degrees
+    # and with an adsorbing wall at 60 degrees
+    "spreading_ratio1000_90": inputs.spreading_drop(90.0),
+    "spreading_ratio1000_60_adsorbing": inputs.spreading_drop(60.0, psi_b=0.01, beta_sg=0.3, beta_sl=0.01),
     "slab_gravity": dict(inputs.flat_slab(nx=64, ny=8, width=30.0, psi_b=0.02), gx=1e-6),
     "shear_liquid_adsorption": inputs.shear_drop(nx=96, ny=48, R=14.0, Ca=0.1, betas=(0.01, 0.9)),
     "static_ratio1000_64": inputs.static_drop_ratio1000(nx=64, ny=64, R=16.0),
@@ -80,7 +85,8 @@ def test_fp64_parity(lbm, name):
 
 @pytest.mark.parametrize("name", ["stationary_drop_64", "sessile_adsorbing_96x48", "shear_ratio10_128x64",
                                   "ragged_67x37_walls", "clean_bubble_freeslip", "static_ratio1000_64",
-                                  "saturation_wall"])
+                                  "saturation_wall", "literal_advection", "literal_advection_walls",
+                                  "spreading_ratio1000_90", "spreading_ratio1000_60_adsorbing"])
 def test_fp32_parity(lbm, name):
     cfg = CASES[name]
     for step, gf, of, _, _ in run_pair(lbm, cfg, "fp32", [1, 20, 300]):
