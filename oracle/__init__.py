@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
+_SRC3 = os.path.join(_HERE, "lbm3d_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 PERIODIC, WALL_WET, NOSLIP, FREESLIP = 0, 1, 2, 3
@@ -34,9 +35,10 @@ DERIVED_NAMES = ["kappa", "beta", "W", "kBT", "phi_b", "sigma_sg0", "sigma_sl0",
 
 def build(force: bool = True) -> str:
     """Compile the oracle with plain -O2, no FMA contraction (gcc, OpenMP loops)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in (_SRC, _SRC3))
+    if force or stale:
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
-               "-o", _LIB, _SRC, "-lm"]
+               "-o", _LIB, _SRC, _SRC3, "-lm"]
         subprocess.run(cmd, check=True, cwd=_HERE)
     return _LIB
 
@@ -108,6 +110,7 @@ def lib():
         L.orc_area_positive.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_contact.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp, dp]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_parallel.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -218,3 +221,152 @@ def contact(phi: np.ndarray):
 
 def threads() -> int:
     return lib().orc_threads()
+
+
+def set_parallel(on: bool) -> None:
+    """Switch the oracle's OpenMP node loops on (default) or off process-wide."""
+    lib().orc_set_parallel(1 if on else 0)
+
+
+# ------------------------------------------------------------------ 3-D
+FIELD_NAMES_3D = ["phi", "psi", "ux", "uy", "uz", "p", "rho", "mu_phi", "mu_psi"]
+
+
+class Params3(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("bc_bottom", ctypes.c_int32), ("bc_top", ctypes.c_int32),
+        ("constraint_phi", ctypes.c_int32), ("init_kind", ctypes.c_int32),
+        ("adv_raw", ctypes.c_int32), ("phi_hold", ctypes.c_int32),
+        ("sigma_gl0", ctypes.c_double), ("eps", ctypes.c_double),
+        ("M_phi", ctypes.c_double), ("M_psi", ctypes.c_double), ("lambda_s", ctypes.c_double),
+        ("kBT", ctypes.c_double), ("W", ctypes.c_double), ("Ex", ctypes.c_double), ("Pi", ctypes.c_double),
+        ("psi_b", ctypes.c_double), ("phi_b", ctypes.c_double),
+        ("theta0_deg", ctypes.c_double), ("sigma_sg0", ctypes.c_double), ("sigma_sl0", ctypes.c_double),
+        ("beta_sg", ctypes.c_double), ("beta_sl", ctypes.c_double),
+        ("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double), ("mu_l", ctypes.c_double), ("mu_g", ctypes.c_double),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("gz", ctypes.c_double),
+        ("u_wall_bottom", ctypes.c_double), ("u_wall_top", ctypes.c_double),
+        ("eta_phi", ctypes.c_double), ("eta_psi", ctypes.c_double), ("M0", ctypes.c_double),
+        ("s_f", ctypes.c_double * 5), ("s_g", ctypes.c_double * 5), ("s_h", ctypes.c_double * 5),
+        ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double),
+        ("R0", ctypes.c_double), ("a", ctypes.c_double),
+    ]
+
+
+class Invariants3(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("nonfinite", ctypes.c_int64), ("psi_out_of_range", ctypes.c_int64),
+        ("mass_psi", ctypes.c_double), ("m_phi_h", ctypes.c_double), ("sum_phi", ctypes.c_double),
+        ("kinetic", ctypes.c_double), ("umax", ctypes.c_double), ("lambda_phi", ctypes.c_double),
+        ("mubar_psi", ctypes.c_double), ("sum_R_psi", ctypes.c_double), ("orthogonality", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib3_ready = False
+
+
+def lib3():
+    global _lib3_ready
+    L = lib()
+    if not _lib3_ready:
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc3_create.restype = ctypes.c_void_p
+        L.orc3_create.argtypes = [ctypes.POINTER(Params3), ctypes.c_char_p, ctypes.c_int]
+        L.orc3_destroy.argtypes = [ctypes.c_void_p]
+        L.orc3_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.orc3_derived.argtypes = [ctypes.c_void_p, dp]
+        L.orc3_fields.argtypes = [ctypes.c_void_p, ctypes.c_uint32, dp]
+        L.orc3_invariants.argtypes = [ctypes.c_void_p, ctypes.POINTER(Invariants3)]
+        L.orc3_load_fields.argtypes = [ctypes.c_void_p, dp, dp, dp]
+        L.orc3_get_populations.argtypes = [ctypes.c_void_p, dp]
+        L.orc3_lattice.argtypes = [ctypes.POINTER(ctypes.c_int), dp]
+        _lib3_ready = True
+    return L
+
+
+def make_params3(cfg: dict) -> Params3:
+    p = Params3()
+    defaults = dict(lambda_s=-1.0, kBT=0.0, W=0.0, Ex=0.5, Pi=1.35, phi_b=0.0, sigma_sg0=-1.0, sigma_sl0=-1.0,
+                    eta_phi=0.0, eta_psi=0.0, M0=-1.0, theta0_deg=90.0, rho_l=1.0, rho_g=1.0, mu_l=0.1, mu_g=0.1)
+    merged = dict(defaults)
+    merged.update(cfg)
+    names = {f for f, _ in Params3._fields_}
+    for k, v in merged.items():
+        if k not in names:
+            continue
+        if k in ("s_f", "s_g", "s_h"):
+            setattr(p, k, (ctypes.c_double * 5)(*v))
+        else:
+            setattr(p, k, v)
+    return p
+
+
+class Oracle3Sim:
+    """One 3-D oracle simulation.  Fields are FP64 arrays of shape (nz, ny, nx)."""
+
+    def __init__(self, cfg: dict):
+        self.cfg = dict(cfg)
+        self.params = make_params3(cfg)
+        self.nx, self.ny, self.nz = self.params.nx, self.params.ny, self.params.nz
+        err = ctypes.create_string_buffer(256)
+        h = lib3().orc3_create(ctypes.byref(self.params), err, 256)
+        if not h:
+            raise ValueError(err.value.decode())
+        self._h = ctypes.c_void_p(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib3().orc3_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        lib3().orc3_step(self._h, int(n))
+
+    def derived(self) -> dict:
+        out = np.zeros(len(DERIVED_NAMES))
+        lib3().orc3_derived(self._h, _dptr(out))
+        return dict(zip(DERIVED_NAMES, out.tolist()))
+
+    def fields(self, names=None) -> dict:
+        names = names or FIELD_NAMES_3D
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELD_NAMES_3D.index(nm)
+        sel = [nm for nm in FIELD_NAMES_3D if mask & (1 << FIELD_NAMES_3D.index(nm))]
+        out = np.zeros((len(sel), self.nz, self.ny, self.nx))
+        lib3().orc3_fields(self._h, mask, _dptr(out))
+        return {nm: out[k] for k, nm in enumerate(sel)}
+
+    def invariants(self) -> dict:
+        inv = Invariants3()
+        lib3().orc3_invariants(self._h, ctypes.byref(inv))
+        return inv.as_dict()
+
+    def load_fields(self, phi, psi, u=None):
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        psi = np.ascontiguousarray(psi, dtype=np.float64)
+        up = _dptr(np.ascontiguousarray(u, dtype=np.float64)) if u is not None else None
+        lib3().orc3_load_fields(self._h, _dptr(phi), _dptr(psi), up)
+
+    def populations(self) -> np.ndarray:
+        out = np.zeros((57, self.nz, self.ny, self.nx))
+        lib3().orc3_get_populations(self._h, _dptr(out))
+        return out
+
+
+def lattice3():
+    """The oracle's D3Q19 velocities (19 x 3) and weights."""
+    c = (ctypes.c_int * 57)()
+    w = np.zeros(19)
+    lib3().orc3_lattice(c, _dptr(w))
+    return np.array(list(c)).reshape(19, 3), w

@@ -46,6 +46,7 @@
  * fork and join (smaller grids are faster on one thread); results do not
  * depend on it, every threaded loop writes per-node values only. */
 #define ORC_PAR_MIN_NODES 16384
+static int g_parallel = 1;   /* orc_set_parallel(0): every loop on the calling thread */
 /* D2Q9 velocities c_i, weights w_i, opposite and y-mirrored directions. */
 static const int EX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int EY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -474,7 +475,7 @@ static void macro(orc_sim* s) {
     }
   }
   /* O3: chemical potentials; Laplacian = zero-flux part L0 plus the wall term T */
-#pragma omp parallel for if (s->N >= ORC_PAR_MIN_NODES)
+#pragma omp parallel for if (g_parallel && s->N >= ORC_PAR_MIN_NODES)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       int n = y * nx + x;
@@ -513,7 +514,7 @@ static void macro(orc_sim* s) {
   if (s->p.phi_hold && S2 > 0.0 && s->p.M_phi > 0.0) s->lambda += (s->m_ref - S4) / (s->p.M_phi * S2);
   s->mubar = S3 / N;
   /* O5, O6: gradients, force, velocity, pressure */
-#pragma omp parallel for if (s->N >= ORC_PAR_MIN_NODES)
+#pragma omp parallel for if (g_parallel && s->N >= ORC_PAR_MIN_NODES)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       int n = y * nx + x;
@@ -575,7 +576,7 @@ static void step_once(orc_sim* s) {
   s->sumRpsi_last = sumR;
   s->orth_last = orth;
   /* O8: collisions */
-#pragma omp parallel for if (s->N >= ORC_PAR_MIN_NODES)
+#pragma omp parallel for if (g_parallel && s->N >= ORC_PAR_MIN_NODES)
   for (int n = 0; n < N; ++n) {
     double ph = s->phi[n], ps = s->psi[n], rho = s->rho[n], ux = s->ux[n], uy = s->uy[n];
     double x[Q], xe[Q], v[Q], out[Q], rates[Q];
@@ -842,6 +843,8 @@ void orc_mms_errors(orc_sim* s, double* e_phi, double* e_psi) {
   *e_phi = sqrt(np / dp);
   *e_psi = sqrt(ns / ds);
 }
+
+void orc_set_parallel(int on) { g_parallel = on ? 1 : 0; }
 
 int orc_threads(void) {
 #ifdef _OPENMP

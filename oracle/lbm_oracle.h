@@ -99,6 +99,9 @@ double   orc_area_positive(const double* phi, int nx, int ny, int wall_bottom, i
 void     orc_contact(const double* phi, int nx, int ny, double* width, double* height, double* theta_deg);
 /* Number of OpenMP threads the node loops use (1 without OpenMP). */
 int      orc_threads(void);
+/* 0: run every node loop on the calling thread (for timing one case per
+ * thread, or one thread alone); 1 (default): OpenMP on large grids. */
+void     orc_set_parallel(int on);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,153 @@
+"""Pins of the 3-D (D3Q19) FP64 oracle against what the paper and the
+mathematics fix.  The model of Sec. 2 holds for d = 2, 3 and the scheme of
+Sec. 3 is written for a general velocity set; these tests check the 3-D
+lattice, stencils and walls against closed forms, symmetries, conservation
+identities and the 3-D Laplace law (curvature 2/R of a sphere).  None compares
+the oracle with itself."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_26332_amd import inputs
+
+
+def cfg3(**kw):
+    c = inputs._base(nx=24, ny=24, nz=24, bc_bottom=inputs.PERIODIC, bc_top=inputs.PERIODIC, psi_b=0.01,
+                     x0=12.0, y0=12.0, z0=12.0, R0=7.0)
+    c.update(kw)
+    return c
+
+
+def test_d3q19_lattice_isotropy():
+    """D3Q19 weights 1/3, 1/18, 1/36: sum 1, second moment c_s^2 = 1/3 on the
+    diagonal and zero off it, fourth moments c_s^4 (1, 3) for the mixed and
+    pure ones (the isotropy the gradient and Laplacian stencils need), and
+    every direction has its opposite."""
+    c, w = oracle.lattice3()
+    assert w.sum() == pytest.approx(1.0, abs=1e-15)
+    for a in range(3):
+        for b in range(3):
+            m2 = (w * c[:, a] * c[:, b]).sum()
+            assert m2 == pytest.approx(1 / 3 if a == b else 0.0, abs=1e-15)
+    assert (w * c[:, 0] ** 4).sum() == pytest.approx(3 / 9, abs=1e-15)
+    assert (w * c[:, 0] ** 2 * c[:, 1] ** 2).sum() == pytest.approx(1 / 9, abs=1e-15)
+    assert (w[:, None] * c).sum(axis=0) == pytest.approx([0, 0, 0], abs=1e-15)
+    assert sorted(map(tuple, c)) == sorted(map(tuple, -c))
+
+
+def test_axis_permutation_symmetry():
+    """A periodic box is symmetric under a relabelling of the axes: the same
+    drop, off-centre in an uneven box, with x -> y -> z -> x relabelled gives
+    the relabelled fields and velocity components (to round-off) after 50
+    steps.  A wrong entry of the velocity table, a weight on the wrong
+    direction or a stencil summed over a subset of directions breaks it."""
+    a_cfg = cfg3(nx=20, ny=16, nz=12, x0=9.3, y0=7.1, z0=5.6, R0=5.0)
+    b_cfg = cfg3(nx=16, ny=12, nz=20, x0=7.1, y0=5.6, z0=9.3, R0=5.0)   # x' = y, y' = z, z' = x
+    a, b = oracle.Oracle3Sim(a_cfg), oracle.Oracle3Sim(b_cfg)
+    a.step(50)
+    b.step(50)
+    fa = a.fields(["phi", "psi", "ux", "uy", "uz", "p"])
+    fb = {k: np.transpose(v, (1, 2, 0)) for k, v in b.fields(["phi", "psi", "ux", "uy", "uz", "p"]).items()}
+    assert np.abs(fa["phi"] - fb["phi"]).max() < 1e-13
+    assert np.abs(fa["psi"] - fb["psi"]).max() < 1e-15
+    assert np.abs(fa["p"] - fb["p"]).max() < 1e-15
+    umax = np.abs(fa["ux"]).max()
+    assert umax > 1e-4
+    for ka, kb in (("ux", "uz"), ("uy", "ux"), ("uz", "uy")):
+        assert np.abs(fa[ka] - fb[kb]).max() < 1e-12 * umax
+
+
+def test_surfactant_mass_and_identities_3d():
+    """Sec. 4.1 (conserved psi to round-off) and the per-step identities of
+    the scheme in 3-D: sum R_psi = 0 and sum h'(mu - lambda h') = 0."""
+    o = oracle.Oracle3Sim(cfg3(psi_b=0.02))
+    i0 = o.invariants()
+    o.step(200)
+    i1 = o.invariants()
+    assert abs(i1["mass_psi"] - i0["mass_psi"]) / i0["mass_psi"] < 1e-12
+    assert abs(i1["sum_R_psi"]) < 1e-12
+    assert abs(i1["orthogonality"]) < 1e-12
+
+
+def test_linear_constraint_conserves_sum_phi_3d():
+    o = oracle.Oracle3Sim(cfg3(nx=16, ny=16, nz=16, x0=8.0, y0=8.0, z0=8.0, R0=5.0, constraint_phi=inputs.LINEAR))
+    s0 = o.invariants()["sum_phi"]
+    o.step(200)
+    assert abs(o.invariants()["sum_phi"] - s0) < 1e-10
+
+
+def test_flat_interface_tanh_profile_3d():
+    """Sec. 2.2: a clean flat interface relaxes to tanh(2 x / eps); a slab across
+    a box of 3 x 3 cells in y and z.  The discrete steady profile differs by
+    O((dx/eps)^2): below 2e-2 at eps = 4 and four times less at eps = 8, as on
+    D2Q9 (the x-projection of D3Q19 has the same weights)."""
+    errs = []
+    for eps, nx, steps in ((4.0, 64, 4000), (8.0, 128, 16000)):
+        o = oracle.Oracle3Sim(cfg3(nx=nx, ny=3, nz=3, x0=nx / 2, init_kind=inputs.INIT_SLAB, a=nx / 2, psi_b=0.0,
+                                   eps=eps))
+        o.step(steps)
+        phi = o.fields(["phi"])["phi"][1, 1]
+        x = np.arange(nx, dtype=float)
+        k = int(np.nonzero((phi[:-1] < 0) & (phi[1:] >= 0))[0][0])
+        x0 = k + phi[k] / (phi[k] - phi[k + 1])
+        near = np.abs(x - x0) < 3 * eps
+        errs.append(np.abs(phi[near] - np.tanh(2.0 * (x[near] - x0) / eps)).max())
+    assert errs[0] < 2e-2
+    assert 0.2 < errs[1] / errs[0] < 0.32, errs
+
+
+@pytest.mark.slow
+def test_laplace_sphere_appA():
+    """Appendix A in 3-D: the leading-order multiplier is -gamma phi_b c0 K
+    with the total curvature K = -2/R of a sphere, i.e. lambda_phi -> 2 sigma / R
+    (twice the 2-D value at the same radius).  A 24^3 box with R = 6: within
+    5% and approaching from below as R grows (R = 6 at 0.962, R = 8 at 0.976),
+    with the pressure higher inside."""
+    o = oracle.Oracle3Sim(cfg3(R0=6.0, psi_b=0.0))
+    o.step(1500)
+    iv = o.invariants()
+    assert iv["lambda_phi"] * 6.0 / 0.02 == pytest.approx(1.0, abs=0.05)
+    f = o.fields(["p", "phi"])
+    assert f["p"][12, 12, 12] - f["p"][0, 0, 0] > 0.5 * 0.02 / 6.0
+
+
+def test_poiseuille_between_walls_3d():
+    """Single-phase flow between half-way bounce-back walls in z driven by a body
+    force g_x: the parabola u = g z'(H - z') / (2 nu), z' = z + 1/2, H = nz,
+    exact for the half-way wall when (1/s2 - 1/2)(1/s3 - 1/2) = 3/16 (the
+    magic combination; here s2 = 1/(3 nu + 1/2) with nu = 0.1, s3 set from it)."""
+    nu = 0.1
+    s2 = 1.0 / (3 * nu + 0.5)
+    s3 = 1.0 / (3.0 / 16.0 / (1.0 / s2 - 0.5) + 0.5)
+    nz, gx = 12, 1e-6
+    c = cfg3(nx=4, ny=4, nz=nz, bc_bottom=inputs.NOSLIP, bc_top=inputs.NOSLIP, psi_b=0.0, R0=-100.0, z0=0.0,
+             gx=gx, s_f=[1.0, 1.0, 0.0, s3, 1.0], rho_l=1.0, rho_g=1.0, mu_l=nu, mu_g=nu)
+    o = oracle.Oracle3Sim(c)
+    o.step(6000)
+    u = o.fields(["ux"])["ux"][:, 2, 2]
+    zp = np.arange(nz) + 0.5
+    exact = gx * zp * (nz - zp) / (2 * nu)
+    assert np.abs(u - exact).max() < 1e-6 * exact.max()
+
+
+@pytest.mark.slow
+def test_young_contact_angle_3d():
+    """The wetting boundary condition on a 3-D wall: a clean hemispherical drop
+    on a wall with theta0 = 60 degrees relaxes toward a spherical cap whose
+    angle 2 atan(H / a) (height H, base radius a from the wetted area pi a^2 of
+    the first layer) is within 5 degrees of theta0 and clearly below 90."""
+    n, R = 32, 8.0
+    c = cfg3(nx=n, ny=n, nz=16, bc_bottom=inputs.WALL_WET, bc_top=inputs.NOSLIP, psi_b=0.0, theta0_deg=60.0,
+             x0=n / 2, y0=n / 2, z0=-0.5, R0=R)
+    o = oracle.Oracle3Sim(c)
+    o.step(3000)
+    phi = o.fields(["phi"])["phi"]
+    area = (phi[0] > 0).sum() + 0.0
+    a = math.sqrt(area / math.pi)
+    col = phi[:, n // 2, n // 2]
+    k = int(np.nonzero((col[:-1] > 0) & (col[1:] <= 0))[0][0])
+    H = k + col[k] / (col[k] - col[k + 1]) + 0.5
+    theta = 2.0 * math.degrees(math.atan(H / a))
+    assert theta == pytest.approx(60.0, abs=5.0), (theta, H, a)
