@@ -1,26 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the coupled three-lattice lattice Boltzmann step on one MI355X.
 
-Metric: MLUPS (million lattice-node updates per second; one update advances
-all three lattices f, g, h), with the achieved fraction of the HBM roofline,
-on the sessile-droplet-on-an-adsorbing-solid workload (256 x 128 D2Q9,
-half-way bounce-back wetting/adsorbing bottom wall, free-slip top, semicircle
-R0 = 40, psi_b = 0.02, theta0 = 60 deg, adsorption strength drawn from seed 2),
-FP32 storage with FP64 reductions.  A second, cache-exceeding grid (4096^2
-periodic drop, same physics family) is timed to show the HBM-bound regime.
+Headline workload: the batched sweep, 512 independent sessile / sheared
+droplets of the sweep distribution (grids 64x32 .. 384x192, theta0 U[30,150]
+deg, adsorption strength U[0,0.5], psi_b U[0.005,0.05], Ca U[0,0.2], radius
+U[12,60]; SplitMix64 seed 2000), advanced together by one batched step launch
+per step (graph-replayed), FP32 storage with FP64 multiplier reductions.  One
+step advances every case by one time step of all three lattices; `value` is
+the batch's MLUPS (fluid nodes x steps / wall seconds / 1e6), with the state
+already resident in HBM.
 
-Prints one JSON line.  `value` is the sessile workload's MLUPS.  `roofline`
-is taken on the 4096^2 grid, whose 5 GB of state streams from HBM every step
-(the sessile grid's 10 MB stay in the on-die caches, so HBM does not bound
-it; its kernel figures are under `headline_kernel`).  Beside the published
-HBM peak the roofline carries two ceilings measured in the same run: a plain
-device copy and the library's bandwidth probe (the step's bytes and access
-pattern without its arithmetic).  The batched sweep's step (512 cases of the
-sweep distribution) and the surrogate ensemble's inference rate follow.  The
-FP64 CPU oracle is timed beside it on the host (bounded sample) as
-cpu_baseline.
+`roofline` is the batched step kernel's achieved HBM bandwidth on the
+algorithmic bytes of a node-step (27 populations and 4 history planes, read
+and written: 248 B in FP32 storage, 496 B in FP64, 140 B with FP16
+populations), timed with HIP events on the batch's stream.  The bytes the
+kernel actually moves by design (FP64 phi/psi planes, advecting-velocity and
+source history) are reported beside it with their ratio.
+
+Further lines: the same batch in FP64 and FP16 storage; a 4096^2 periodic grid
+(state far beyond the on-die caches) in all three storages with a plain-copy
+and an access-pattern ceiling; the single 256x128 sessile drop and the 64^2
+stationary drop; the surrogate ensemble's rates.  The FP64 CPU oracle is timed
+beside them on the host cores (bounded samples, stated) as cpu_baseline.
 """
 import argparse
+import concurrent.futures
 import hashlib
 import json
 import os
@@ -32,38 +36,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-
-
-def gpu_run(cfg, precision, steps, warmup, kernel_steps):
-    """Wall-clock run of `steps` steps (graph-replayed, as a user calls
-    lbm_step), then `kernel_steps` more with per-kernel HIP-event timing (those
-    launch one by one) for the roofline."""
-    import torch
-    from paper_2609_26332_amd import lbm
-
-    sim = lbm.Sim(cfg, precision)
-    sim.step(warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    sim.timing_begin(kernel_steps)
-    sim.step(kernel_steps)
-    kt = sim.timing_end()
-    inv = sim.invariants(check=False)
-    N = cfg["nx"] * cfg["ny"]
-    return dict(sim=sim, wall=wall, kernels=kt, N=N, inv=inv, bytes_node=sim.bytes_per_node_step())
-
-
+# Algorithmic bytes per node-step: 27 populations and 4 history planes
+# (phi, psi, u_x, u_y of the previous step), each read and written once.
+ALGO_BYTES = {"fp32": 2 * (27 * 4 + 4 * 4), "fp64": 2 * (27 * 8 + 4 * 8), "fp16": 2 * (27 * 2 + 4 * 4)}
+SEED = 2000
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_26332_amd", "csrc", "lbm_kernels.hip")
 
 
+def sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
 def measured_traffic(key):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    """HBM bytes per launch of a step kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's
-    readings), or None when that summary was taken on other kernel source."""
+    readings), when that summary was taken on the current kernel source;
+    None otherwise."""
     try:
         text = open(TRAFFIC_FILE).read()
         src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
@@ -79,79 +70,78 @@ def measured_traffic(key):
     return float(vals[key]) if key in vals else None
 
 
-def roofline(res, key, cfg, precision):
-    """Achieved HBM bandwidth of the dominant kernel (the fused step kernel,
-    which moves all of a step's algorithmic bytes) on those bytes, from its
-    HIP-event durations on the stream it runs on.  Beside the published peak,
-    `pattern_ceiling` is what the library's bandwidth probe (the same bytes per
-    node in the step's access pattern, without the arithmetic) reaches on the
-    same grid in the same run."""
-    from paper_2609_26332_amd import lbm
-    kt = res["kernels"]
-    dom = max(kt, key=lambda k: kt[k][0])
-    dom_ms = kt[dom][0] / max(kt[dom][1], 1)
-    bytes_launch = res["bytes_node"] * res["N"]
-    achieved = bytes_launch / (dom_ms * 1e-3) / 1e9
-    pr = lbm.probe_stream(cfg["nx"], cfg["ny"], precision, reps=20)
-    cp = copy_rate()
-    return {
-        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(key),
-        "kernel": dom, "bytes_per_node_step": res["bytes_node"], "nodes_per_launch": res["N"],
-        "kernel_ms_per_launch": {k: round(v[0] / max(v[1], 1), 5) for k, v in kt.items()},
-        "copy_ceiling": {"achieved": round(cp, 2), "unit": "GB/s", "frac_of_peak": round(cp / HBM_PEAK_GBS, 4),
-                         "what": "plain 1 GiB device copy (torch copy_), read + write bytes"},
-        "pattern_ceiling": {"achieved": round(pr["gbs"], 2), "unit": "GB/s", "frac_of_peak": round(pr["gbs"] / HBM_PEAK_GBS, 4),
-                            "frac": round(achieved / pr["gbs"], 4), "ms_per_launch": round(pr["ms"], 5),
-                            "what": "lbm_probe_stream: the step's bytes per node and access pattern, no arithmetic"},
-    }
+def kernel_line(kt, nodes, prec, design_bytes):
+    """Roofline figures of the dominant (step) kernel from HIP-event times."""
+    ms = kt["k_step"][0] / max(kt["k_step"][1], 1)
+    algo = ALGO_BYTES[prec]
+    gbs = algo * nodes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_node_step": algo,
+            "kernel_ms_per_launch": round(ms, 5),
+            "finish_ms_per_launch": round(kt["k_step_finish"][0] / max(kt["k_step_finish"][1], 1), 5),
+            "design_bytes_per_node_step": design_bytes,
+            "design_over_algorithmic": round(design_bytes / algo, 4),
+            "design_bytes_achieved_gbs": round(design_bytes * nodes / (ms * 1e-3) / 1e9, 2)}
 
 
-def storage_line(cfg, precision, steps):
-    """The same grid in another storage: MLUPS and the step kernel's achieved
-    bandwidth on that storage's algorithmic bytes (HIP events), against the
-    peak."""
-    import torch
+def batch_run(prec, steps, warmup, kernel_steps, count=512):
+    """The batched sweep: `count` cases, one batched step launch per step,
+    segment height from the batch's autotuner; wall-clock steps (graph
+    replays) and then event-timed eager steps for the kernel figures."""
+    from paper_2609_26332_amd import lbm, sweep
 
-    r = gpu_run(cfg, precision, steps, 10, steps)
-    kt = r["kernels"]
-    dom = max(kt, key=lambda k: kt[k][0])
-    ms = kt[dom][0] / max(kt[dom][1], 1)
-    gbs = r["bytes_node"] * r["N"] / (ms * 1e-3) / 1e9
-    out = {"mlups": round(r["N"] * steps / r["wall"] / 1e6, 1), "kernel": dom, "kernel_ms_per_launch": round(ms, 5),
-           "bytes_per_node_step": r["bytes_node"], "achieved": round(gbs, 2), "unit": "GB/s",
-           "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    del r
-    torch.cuda.empty_cache()
+    cases = sweep.batch_cases(SEED, count)
+    b = lbm.Batch(cases, prec)
+    seg = b.autotune(trial_steps=10)
+    info = b.info()
+    b.step(warmup)
+    sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    sync()
+    wall = time.perf_counter() - t0
+    b.timing_begin(kernel_steps)
+    b.step(kernel_steps)
+    kt = b.timing_end()
+    inv = b.invariants(check=False)
+    nodes = info["nodes"]
+    out = {"workload": "%d cases of the sweep distribution (seed %d), grids %dx%d .. %dx%d, %s storage, FP64 reductions"
+                       % (count, SEED, min(c["nx"] for c in cases), min(c["ny"] for c in cases),
+                          max(c["nx"] for c in cases), max(c["ny"] for c in cases), prec.upper()),
+           "nodes": nodes, "cases": count, "seg_rows": seg, "workgroups": info["workgroups"],
+           "wall_s": wall, "mlups": nodes * steps / wall / 1e6, "ms_per_step": wall * 1e3 / steps,
+           "case_steps_per_s": count * steps / wall, "nonfinite_cases": int(sum(1 for v in inv if v["nonfinite"])),
+           "kernels": kt}
+    b.close()
     return out
 
 
-def batch_run(seed: int = 2000, count: int = 512, steps: int = 1024):
-    """The batched sweep's step: `count` cases of the sweep distribution (uneven
-    grids, angles, adsorption, surfactant load, shear) advanced together, one
-    launch of the batched step kernel per step (graph-replayed), segment height
-    from the batch's own autotuner.  Timed over `steps` steps."""
-    import torch
-    from paper_2609_26332_amd import lbm, sweep
+def design_bytes(prec):
+    """Bytes per node-step the step kernels move by design in this storage
+    (with surfactant): the populations, the FP64 phi/psi planes and six
+    history planes, read and written (lbm_bytes_per_node_step)."""
+    return {"fp32": 296.0, "fp64": 560.0, "fp16": 196.0}[prec]
 
-    cases = sweep.batch_cases(seed, count)
-    b = lbm.Batch(cases, "fp32")
-    seg = b.autotune(trial_steps=10)
-    b.step(64)
-    torch.cuda.synchronize()
+
+def grid_run(cfg, prec, steps, warmup, kernel_steps):
+    from paper_2609_26332_amd import lbm
+
+    sim = lbm.Sim(cfg, prec)
+    sim.step(warmup)
+    sync()
     t0 = time.perf_counter()
-    b.step(steps)
-    torch.cuda.synchronize()
+    sim.step(steps)
+    sync()
     wall = time.perf_counter() - t0
-    nodes = sum(c["nx"] * c["ny"] for c in cases)
-    inv = b.invariants(check=False)
-    b.close()
-    return {"workload": "%d cases of the sweep distribution (seed %d), grids %dx%d .. %dx%d, FP32 storage"
-                        % (count, seed, min(c["nx"] for c in cases), min(c["ny"] for c in cases),
-                           max(c["nx"] for c in cases), max(c["ny"] for c in cases)),
-            "nodes": nodes, "seg_rows": seg, "steps": steps, "ms_per_step": round(wall * 1e3 / steps, 4),
-            "mlups": round(nodes * steps / wall / 1e6, 1), "case_steps_per_s": round(count * steps / wall, 1),
-            "nonfinite_cases": int(sum(1 for v in inv if v["nonfinite"]))}
+    sim.timing_begin(kernel_steps)
+    sim.step(kernel_steps)
+    kt = sim.timing_end()
+    N = cfg["nx"] * cfg["ny"]
+    out = {"mlups": round(N * steps / wall / 1e6, 1), "ms_per_step": round(wall * 1e3 / steps, 5),
+           "step_kernel": sim.step_kernel(), "nonfinite": sim.invariants(check=False)["nonfinite"],
+           **kernel_line(kt, N, prec, sim.bytes_per_node_step())}
+    sim.close()
+    return out
 
 
 def copy_rate(gib: float = 1.0, reps: int = 10) -> float:
@@ -175,9 +165,8 @@ def copy_rate(gib: float = 1.0, reps: int = 10) -> float:
 
 
 def surrogate_rate(n: int = 4096, reps: int = 20) -> dict:
-    """Inference rate of the 5-member surrogate ensemble (mean and spread of
-    both outputs per case) on n cases, and one training step's time at the
-    training batch size, with initial (untrained) parameters."""
+    """Inference rate of the 5-member surrogate ensemble on n cases and one
+    training step's time at the training batch size (initial parameters)."""
     import numpy as np
     import torch
     from paper_2609_26332_amd import surrogate
@@ -187,123 +176,180 @@ def surrogate_rate(n: int = 4096, reps: int = 20) -> dict:
         net.set_params(k, surrogate.glorot_params(k + 1, net.n_params))
     x = torch.as_tensor(np.random.default_rng(0).uniform(-1, 1, size=(n, 5)).astype(np.float32)).cuda()
     net.predict(x)
-    torch.cuda.synchronize()
+    sync()
     t0 = time.perf_counter()
     for _ in range(reps):
         net.predict(x)
-    torch.cuda.synchronize()
+    sync()
     t_pred = (time.perf_counter() - t0) / reps
     b = 256
     t, m = torch.zeros(b, 2, device="cuda"), torch.ones(b, 2, device="cuda")
     xb = x[:b].contiguous()
     net.train_step(0, xb, t, m, 1e-3)
-    torch.cuda.synchronize()
+    sync()
     t0 = time.perf_counter()
     for _ in range(reps):
         net.train_step(0, xb, t, m, 1e-3)
-    torch.cuda.synchronize()
+    sync()
     t_train = (time.perf_counter() - t0) / reps
     net.close()
     return {"members": 5, "cases": n, "predict_ms": round(t_pred * 1e3, 4), "predict_cases_per_s": round(n / t_pred, 1),
             "train_step_ms_batch256": round(t_train * 1e3, 4)}
 
 
-def copy_calibration():
-    import torch
-
-    x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
-    y = torch.empty_like(x)
-    torch.cuda.synchronize()
-    for _ in range(5):
-        y.copy_(x)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "copies": 5}))
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def cpu_baseline(cfg, budget_s=15.0):
+def cpu_baseline(budget_s=8.0):
+    """The FP64 oracle on the host cores, on bounded samples:
+    * the headline workload: cases of the same sweep batch, one case per
+      thread on every host core, each run for a bounded number of steps;
+    * one thread on the 64^2 stationary drop (1000 steps) and on a 512^2
+      periodic drop (a bounded number of steps)."""
     import oracle
+    from paper_2609_26332_amd import inputs, sweep
 
     oracle.build(force=False)
-    s = oracle.OracleSim(cfg)
-    t0 = time.perf_counter()
-    s.step(10)
-    t1 = time.perf_counter()
-    per = max((t1 - t0) / 10, 1e-6)
-    n = max(10, int(budget_s / per))
-    t0 = time.perf_counter()
-    s.step(n)
-    dt = time.perf_counter() - t0
-    N = cfg["nx"] * cfg["ny"]
-    return {"value": round(N * n / dt / 1e6, 4), "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
-            "sample": "%d steps of the same %dx%d workload after 10 warm-up steps, FP64 oracle, %.1f s"
-                      % (n, cfg["nx"], cfg["ny"], dt)}
+    ncores = len(os.sched_getaffinity(0))
+    oracle.set_parallel(False)   # one case per thread; no nested threads
+    try:
+        cases = sweep.batch_cases(SEED, 512)[:ncores]
+        sims = [oracle.OracleSim(c) for c in cases]
+        sims[0].step(2)
+        t0 = time.perf_counter()
+        sims[0].step(5)
+        per_node_step = (time.perf_counter() - t0) / (5 * cases[0]["nx"] * cases[0]["ny"])
+        mean_nodes = sum(c["nx"] * c["ny"] for c in cases) / len(cases)
+        steps = max(10, int(budget_s / (per_node_step * mean_nodes)))
+
+        def run(s):
+            s.step(steps)
+
+        with concurrent.futures.ThreadPoolExecutor(max_workers=ncores) as ex:
+            t0 = time.perf_counter()
+            list(ex.map(run, sims))
+            wall = time.perf_counter() - t0
+        node_steps = steps * sum(c["nx"] * c["ny"] for c in cases)
+        sweep_mlups = node_steps / wall / 1e6
+        del sims
+        c1 = inputs.stationary_drop()
+        s = oracle.OracleSim(c1)
+        t0 = time.perf_counter()
+        s.step(1000)
+        t_c1 = time.perf_counter() - t0
+        big = inputs.stationary_drop(nx=512, ny=512, R=128.0)
+        s = oracle.OracleSim(big)
+        s.step(1)
+        t0 = time.perf_counter()
+        s.step(1)
+        per = time.perf_counter() - t0
+        n512 = max(2, min(200, int(budget_s / per)))
+        t0 = time.perf_counter()
+        s.step(n512)
+        t_512 = time.perf_counter() - t0
+    finally:
+        oracle.set_parallel(True)
+    return {"value": round(sweep_mlups, 4), "unit": "MLUPS", "cores": ncores, "kind": "oracle",
+            "sample": "%d cases of the same sweep batch (seed %d), one per host thread, %d steps each, FP64 oracle, "
+                      "%.1f s (the full batch is 512 cases; MLUPS is per node-step, so it extrapolates directly)"
+                      % (len(cases), SEED, steps, wall),
+            "case_steps_per_s": round(len(cases) * steps / wall, 2),
+            "single_thread": {"stationary_drop_64x64_1000_steps_mlups": round(4096 * 1000 / t_c1 / 1e6, 4),
+                              "periodic_drop_512x512_mlups": round(512 * 512 * n512 / t_512 / 1e6, 4),
+                              "periodic_drop_512x512_steps": n512},
+            "nproc": ncores, "cpu_model": cpu_model()}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--large-steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--kernel-steps", type=int, default=20, help="event-timed steps for the kernel figures")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-large", action="store_true")
-    ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--batch-steps", type=int, default=1024)
-    ap.add_argument("--workload", default="both", choices=["both", "sessile", "large"],
-                    help="profiling aid: run one of the two workloads only")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline batch (profiling aid)")
+    ap.add_argument("--workload", default="all", choices=["all", "batch", "grid4096"],
+                    help="profiling aid: one workload only")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16"],
+                    help="profiling aid: storage of the single workload run with --workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profiling aid: five device copies of 1 GiB (the reference for the HBM byte counters), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path", file=sys.stderr)
+        print("bench.py measures one GPU: this library has no multi-GPU path (the batch would shard by cases, "
+              "see the design notes); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    import torch
+
     if args.copy_calibration:
-        copy_calibration()
+        x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        sync()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "copies": 5}))
         return
     from paper_2609_26332_amd import inputs
 
-    if args.workload == "large":
-        big = inputs.roofline_grid()
-        rb = gpu_run(big, args.precision, args.large_steps, 10, args.large_steps)
-        print(json.dumps({"workload": "periodic drop 4096x4096", "roofline": roofline(rb, "large_" + args.precision, big, args.precision)}))
+    if args.workload == "grid4096":
+        r = grid_run(inputs.roofline_grid(), args.precision, args.steps, args.warmup, args.kernel_steps)
+        print(json.dumps({"workload": "periodic drop 4096x4096 %s" % args.precision, **r}), flush=True)
         return
-    cfg = inputs.sessile_drop()
-    res = gpu_run(cfg, args.precision, args.steps, args.warmup, min(args.steps, 2000))
-    mlups = res["N"] * args.steps / res["wall"] / 1e6
-    head = roofline(res, "sessile_" + args.precision, cfg, args.precision)
+    prec = args.precision if args.workload == "batch" else "fp32"
+    hb = batch_run(prec, args.steps, args.warmup, args.kernel_steps)
+    rl = kernel_line(hb["kernels"], hb["nodes"], prec, design_bytes(prec))
+    rl.update(kernel="k_step_batch", nodes_per_launch=hb["nodes"],
+              traffic=measured_traffic("batch_" + prec))
     out = {
-        "metric": "MLUPS (3 coupled lattices) + HBM roofline %",
-        "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(res["wall"] * 1e3 / args.steps, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
-        "config": {"workload": "sessile drop on adsorbing solid, 256x128 D2Q9, %s storage, FP64 reductions"
-                               % args.precision.upper(),
-                   "nx": cfg["nx"], "ny": cfg["ny"], "theta0_deg": cfg["theta0_deg"], "psi_b": cfg["psi_b"],
-                   "beta_sg": round(cfg["beta_sg"], 6), "precision": args.precision},
-        "lattice_mlups": round(3 * mlups, 2),
+        "metric": "MLUPS (3 coupled lattices) + HBM roofline %; batched sweep cases/s at ±0.5°",
+        "value": round(hb["mlups"], 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(hb["ms_per_step"], 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if prec == "fp32" else prec.replace("fp", "f"),
+        "data": "synthetic",
+        "config": {"workload": "batched sweep: " + hb["workload"], "cases": hb["cases"], "nodes": hb["nodes"],
+                   "seed": SEED, "seg_rows": hb["seg_rows"], "workgroups": hb["workgroups"], "precision": prec},
+        "lattice_mlups": round(3 * hb["mlups"], 2),
+        "case_steps_per_s": round(hb["case_steps_per_s"], 1),
+        "roofline": rl,
     }
-    if res["inv"]["nonfinite"]:
-        out["warning"] = "non-finite fields after the timed run"
-    del res
-    if not args.no_large and args.workload == "both":
+    if hb["nonfinite_cases"]:
+        out["warning"] = "%d cases with non-finite fields after the timed run" % hb["nonfinite_cases"]
+    if args.workload == "all" and not args.no_extras:
+        out["batch_other_storages"] = {}
+        for p in ("fp64", "fp16"):
+            r = batch_run(p, max(50, args.steps // 4), 10, args.kernel_steps)
+            out["batch_other_storages"][p] = dict(mlups=round(r["mlups"], 1), ms_per_step=round(r["ms_per_step"], 5),
+                                                  seg_rows=r["seg_rows"], nonfinite_cases=r["nonfinite_cases"],
+                                                  **kernel_line(r["kernels"], r["nodes"], p, design_bytes(p)))
+            torch.cuda.empty_cache()
         big = inputs.roofline_grid()
-        rb = gpu_run(big, args.precision, args.large_steps, 10, args.large_steps)
-        rl = roofline(rb, "large_" + args.precision, big, args.precision)
-        rl = dict(workload="periodic drop 4096x4096, %s storage (5 GB of state, beyond the on-die caches)"
-                  % args.precision.upper(), mlups=round(rb["N"] * args.large_steps / rb["wall"] / 1e6, 1), **rl)
-        out["roofline"] = rl
-        del rb
-        if args.precision == "fp32":
-            out["roofline_other_storages"] = {prec: storage_line(big, prec, 40) for prec in ("fp64", "fp16")}
-    if "roofline" not in out:   # the large grid was not run: the headline workload's kernel stands in
-        out["roofline"] = head
-    out["headline_kernel"] = dict(workload="the sessile workload above (state resident in the on-die caches)", **head)
-    if not args.no_batch and args.workload == "both" and args.precision == "fp32":
-        out["batched_sweep"] = batch_run(steps=args.batch_steps)
+        g = {}
+        for p in ("fp32", "fp64", "fp16"):
+            g[p] = grid_run(big, p, 100, 10, args.kernel_steps)
+            torch.cuda.empty_cache()
+        from paper_2609_26332_amd import lbm
+        pr = lbm.probe_stream(big["nx"], big["ny"], "fp32", reps=20)
+        cp = copy_rate()
+        g["copy_ceiling"] = {"achieved": round(cp, 2), "unit": "GB/s", "frac_of_peak": round(cp / HBM_PEAK_GBS, 4),
+                             "what": "plain 1 GiB device copy (torch copy_), read + write bytes"}
+        g["pattern_ceiling_fp32"] = {"achieved": round(pr["gbs"], 2), "unit": "GB/s",
+                                     "frac_of_peak": round(pr["gbs"] / HBM_PEAK_GBS, 4), "ms_per_launch": round(pr["ms"], 5),
+                                     "what": "lbm_probe_stream: the FP32 step's design bytes (296 B/node) in its access "
+                                             "pattern, without arithmetic"}
+        out["grid_4096x4096"] = dict(workload="periodic drop 4096x4096 (state far beyond the on-die caches)", **g)
+        torch.cuda.empty_cache()
+        out["sessile_256x128_fp32"] = grid_run(inputs.sessile_drop(), "fp32", 2000, 100, args.kernel_steps)
+        out["stationary_64x64_fp64"] = grid_run(inputs.stationary_drop(), "fp64", 2000, 100, args.kernel_steps)
         out["surrogate"] = surrogate_rate()
-    if not args.no_cpu_baseline and args.workload == "both":
-        out["cpu_baseline"] = cpu_baseline(cfg)
+    if not args.no_cpu_baseline and args.workload == "all":
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

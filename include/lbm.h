@@ -157,28 +157,48 @@ int lbm_required_bytes(const lbm_params* p, size_t* bytes);
  * parameter set; the message is available from lbm_last_error(NULL)). */
 int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_stream, lbm_handle** out);
 
-/* Enqueue n time steps (n >= 0).  Asynchronous: returns once the work is on
- * the stream.  Faults in the fields surface at the next synchronising call.
- * Runs of 32 steps are replayed from a HIP graph the handle captures on first
- * use (same results bit for bit; on grids of at most 1024 workgroups the
- * captured steps reduce the previous step's multiplier sums themselves, in
- * the same order); steps while kernel timing is active are launched one by
- * one.  For a given tile_rows the step kernel's schedule (row sweep, or
- * one-pass 4-row tiles on grids of few workgroups per CU) does not change the
- * results; tile_rows itself groups the multiplier sums, so it changes their
- * last bits. */
+/* Enqueue n time steps (n >= 0).  One step is the scheme of Sec. 3 for all
+ * three populations: zeroth moments (macroscopic recovery), the wall values of
+ * the natural boundary conditions (eq "boundary" with the wall energy eq8),
+ * the chemical potentials (eq_muphi, eq_mupsi) with the isotropic stencils of
+ * the end of Sec. 3, the multiplier sums of eq15 and AC_psi in FP64, the force
+ * (eq_Fs0), velocity and pressure, the sources R_phi, R_psi with their
+ * backward differences, the three MRT collisions (unified MRT equation, f_eq of
+ * the three lattices, F_{i,1..3}) and streaming with the walls.
+ * Asynchronous: returns once the work is on the stream.  Faults in the fields
+ * surface at the next synchronising call.  Runs are replayed from HIP graphs
+ * of 2, 4, 8, 16 or 32 steps the handle captures on first use (a run is split
+ * into the longest such pieces; same results bit for bit; on grids of at most
+ * 1024 workgroups the captured steps reduce the previous step's multiplier
+ * sums themselves, in the same order); the first step after (re)initialisation,
+ * an odd last step and steps while kernel timing is active are launched one
+ * by one.  For a given tile_rows the step kernel's schedule (lbm_step_kernel)
+ * does not change the results in FP32 and FP16 storage (bit for bit); in FP64
+ * storage the kernels contract multiply-adds differently (last bits);
+ * tile_rows itself groups the multiplier sums, so it changes their last bits.  Errors: LBM_E_ARG for n < 0, LBM_E_STATE
+ * after a latched fault, LBM_E_DEVICE when a launch fails. */
 int lbm_step(lbm_handle* h, int64_t n);
 
-/* Diagnostics of the current state (FP64 sums on the device), then one small
- * device-to-host copy; synchronises the stream.  Returns LBM_E_RANGE when psi
- * left (0,1), else LBM_E_NONFINITE when a field is not finite (*out filled in
- * both cases); either latches the handle so that lbm_step returns LBM_E_STATE
- * until lbm_load_fields or lbm_load_state replaces the state. */
+/* Diagnostics of the current state: the conserved sums of Sec. 2.1 (sum psi of
+ * AC_psi, sum h_phi of eq15), the two-triangle area of phi > 0 (Sec. 4.1), the
+ * kinetic and free energy with the wall energy (eq1, eq8; the energy law of
+ * Sec. 2.4), max |u|, the multipliers, and at a bottom wall the contact width,
+ * cap height and apparent angle of a circular cap (eq "a", Sec. 4.3).  FP64
+ * sums on the device, then one small device-to-host copy; synchronises the
+ * stream.  *out is caller-owned.  Returns LBM_E_RANGE when psi left (0,1),
+ * else LBM_E_NONFINITE when a field is not finite (*out filled in both cases);
+ * either latches the handle so that lbm_step returns LBM_E_STATE until
+ * lbm_load_fields or lbm_load_state replaces the state. */
 int lbm_reduce_invariants(lbm_handle* h, lbm_invariants* out);
 
-/* Macroscopic fields of the current state (time n, before its collision) as
- * FP64 [popcount(mask)][ny][nx]; n_doubles must be at least that size.
- * Synchronises the stream. */
+/* Macroscopic fields of the current state (time n, before its collision):
+ * phi and psi as the zeroth moments, u and p as Sec. 3 recovers them (rho u =
+ * sum c_i f_i + F/2, p from sum_{i != 0} f_i), rho(phi), and mu_phi, mu_psi
+ * (eq_muphi, eq_mupsi, without the multiplier terms).  Written to the
+ * caller-owned host buffer as FP64 [popcount(mask)][ny][nx], planes in
+ * increasing bit order; n_doubles must be at least that size (LBM_E_ARG
+ * otherwise, or for a mask outside the LBM_F_* bits).  Synchronises the
+ * stream. */
 int lbm_fetch_fields(lbm_handle* h, uint32_t mask, double* host, size_t n_doubles);
 
 /* Replace the state by equilibrium populations of the given fields: mask must
@@ -186,9 +206,11 @@ int lbm_fetch_fields(lbm_handle* h, uint32_t mask, double* host, size_t n_double
  * pressure is set to 0 and the backward-difference history restarts. */
 int lbm_load_fields(lbm_handle* h, uint32_t mask, const double* host, size_t n_doubles);
 
-/* Raw state for checkpoint / restart: populations, history planes, scalars
- * and the step count.  lbm_state_bytes gives the size; load_state only
- * accepts a blob from a handle with identical parameters. */
+/* Raw state for checkpoint / restart: populations, history planes, the
+ * pending multipliers, phi_hold's reference sum and the step count
+ * (restarting from a blob continues the run bit for bit).  lbm_state_bytes
+ * gives the size; load_state only accepts a blob from a handle with identical
+ * parameters (LBM_E_ARG otherwise). */
 int lbm_state_bytes(lbm_handle* h, size_t* bytes);
 int lbm_save_state(lbm_handle* h, void* host, size_t bytes);
 int lbm_load_state(lbm_handle* h, const void* host, size_t bytes);
@@ -234,6 +256,20 @@ int lbm_probe_bytes(int32_t nx, int32_t ny, int32_t precision, size_t* bytes);
 int lbm_probe_stream(int32_t nx, int32_t ny, int32_t precision, int32_t reps, void* dev_buf, size_t buf_bytes,
                      void* hip_stream, float* ms_out);
 
+/* Which kernel this handle's steps launch (the results are the same for
+ * each; only the schedule differs), chosen from the number of workgroups
+ * against the device's compute units:
+ *   LBM_KV_SMALL   one-pass 4-row tiles of eight waves (at most one workgroup per CU)
+ *   LBM_KV_MID     one-pass 4-row tiles of four waves (up to three per CU; FP32, FP16)
+ *   LBM_KV_SWEEP   the upward row sweep, built for one workgroup per CU
+ *   LBM_KV_SWEEP_PACKED  the row sweep of walled grids built for three workgroups per CU
+ * *workgroups is the step launch's workgroup count and *cus the CU count the
+ * choice used: the device's, unless the environment variable LBM_KERNEL_CUS
+ * (read by lbm_init; 1..65536) overrides it, which tests use to run every
+ * variant on one device. */
+enum { LBM_KV_SMALL = 0, LBM_KV_MID = 1, LBM_KV_SWEEP = 2, LBM_KV_SWEEP_PACKED = 3 };
+int lbm_step_kernel(lbm_handle* h, int32_t* variant, int32_t* workgroups, int32_t* cus);
+
 /* Release the handle and any library-owned device memory and stream. */
 int lbm_destroy(lbm_handle* h);
 
@@ -249,7 +285,8 @@ const char* lbm_last_error(const lbm_handle* h);
  * precision and one kind of y boundary (all walled or all periodic); their
  * results equal, bit for bit, those of single handles with the same segment
  * height.  A case can be retired (not stepped) and its slot refilled with new
- * parameters of the same grid.  Runs of 32 steps replay from a HIP graph. */
+ * parameters of the same grid.  Runs replay from HIP graphs of 1, 2, 4, 8, 16
+ * or 32 steps (a run is split into the longest such pieces). */
 typedef struct lbm_batch lbm_batch; /* opaque, owned by the library */
 
 /* Device bytes for the batch's state (cases[0..count-1]); validates every case

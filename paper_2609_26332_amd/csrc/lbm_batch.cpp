@@ -33,7 +33,7 @@ struct lbm_batch {
   int seg_rows = 4;
   std::vector<lbm::BatchCase> hc;  // host mirror of the table
   bool device_ahead = false;       // the table holds positions newer than the handles
-  hipGraphExec_t graph = nullptr;
+  hipGraphExec_t graph[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // 2^k steps
   int64_t step = 0;
   lbm::StepTimer timer;
   std::string err = "no error";
@@ -42,7 +42,10 @@ struct lbm_batch {
 namespace {
 
 std::string g_batch_error = "no error";
-constexpr int64_t kBatchGraphSteps = 32;
+// Runs of steps replay from captured graphs of 1, 2, 4, 8, 16 or 32 steps (the
+// cases' buffer parities live in the device table, so any length replays from
+// any state); a run is split into the longest such pieces.
+constexpr int kBatchGraphKinds = 6;
 
 int bfail(lbm_batch* b, int code, const std::string& msg) {
   if (b) b->err = msg;
@@ -159,8 +162,10 @@ int push_case(lbm_batch* b, int c) {
 }
 
 void drop_graph(lbm_batch* b) {
-  if (b->graph) (void)hipGraphExecDestroy(b->graph);
-  b->graph = nullptr;
+  for (int k = 0; k < kBatchGraphKinds; ++k) {
+    if (b->graph[k]) (void)hipGraphExecDestroy(b->graph[k]);
+    b->graph[k] = nullptr;
+  }
 }
 
 void release_batch_timer(lbm_batch* b) {
@@ -170,7 +175,8 @@ void release_batch_timer(lbm_batch* b) {
   b->timer = lbm::StepTimer();
 }
 
-int capture_batch_graph(lbm_batch* b) {
+int capture_batch_graph(lbm_batch* b, int kind) {
+  const int64_t kBatchGraphSteps = int64_t(1) << kind;
   hipGraph_t g = nullptr;
   BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin graph capture");
   hipError_t e = hipSuccess;
@@ -178,10 +184,10 @@ int capture_batch_graph(lbm_batch* b) {
     e = lbm::launch_step_batch(b->precision, b->walls, b->d_cases, b->d_wg, b->nwg, b->count, b->stream, nullptr);
   const hipError_t e_end = hipStreamEndCapture(b->stream, &g);
   if (e == hipSuccess) e = e_end;
-  if (e == hipSuccess) e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->graph[kind], g, nullptr, nullptr, 0);
   if (g) (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
-    b->graph = nullptr;
+    b->graph[kind] = nullptr;
     return bfail(b, LBM_E_DEVICE, std::string("graph capture of the batch step: ") + hipGetErrorString(e));
   }
   return LBM_OK;
@@ -278,13 +284,15 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
   int64_t k = 0;
   while (k < n) {
     const bool timing = b->timer.ev && b->timer.used < b->timer.max_steps;
-    if (!timing && n - k >= kBatchGraphSteps) {
-      if (!b->graph) {
-        const int rc = capture_batch_graph(b);
+    int kind = kBatchGraphKinds - 1;
+    while (kind > 0 && n - k < (int64_t(1) << kind)) --kind;
+    if (!timing) {
+      if (!b->graph[kind]) {
+        const int rc = capture_batch_graph(b, kind);
         if (rc) return rc;
       }
-      BHIP(b, hipGraphLaunch(b->graph, b->stream), "graph launch");
-      k += kBatchGraphSteps;
+      BHIP(b, hipGraphLaunch(b->graph[kind], b->stream), "graph launch");
+      k += int64_t(1) << kind;
     } else {
       BHIP(b, lbm::launch_step_batch(b->precision, b->walls, b->d_cases, b->d_wg, b->nwg, b->count, b->stream, &b->timer),
            "batch step kernels");

@@ -8,13 +8,14 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr uint64_t kStateMagic = 0x4c424d5354415445ull;  // "LBMSTATE"
+constexpr uint64_t kStateMagic = 0x4c424d5354415432ull;  // "LBMSTAT2"
 
 thread_local std::string g_init_error = "no error";
 
@@ -24,6 +25,7 @@ struct StateHeader {
   int64_t step;
   uint64_t params_hash;
   double pending[3];  // multipliers pending on the stored populations (lambda, mubar, weight)
+  double m_ref;       // phi_hold's reference sum h_phi (of the initial or last loaded fields)
 };
 
 uint64_t hash_bytes(const void* data, size_t n) {  // FNV-1a
@@ -164,8 +166,9 @@ struct lbm_handle {
   bool faulted = false;
   double derived[LBM_N_DERIVED];
   lbm::StepTimer timer;
-  hipGraphExec_t graph = nullptr;  // kGraphSteps steps captured from buffer parity graph_parity
-  int graph_parity = 0;
+  // graph[k]: 2^(k+1) steps captured from buffer parity graph_parity[k] (k < kGraphKinds)
+  hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int graph_parity[5] = {0, 0, 0, 0, 0};
   std::string err = "no error";
 };
 
@@ -290,6 +293,12 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
   }
   carve(h);
   h->ds.cus = cus;
+  // Override of the CU count the step kernel's variant is chosen against (a
+  // test aid: every variant then runs on one device); results do not change.
+  if (const char* ov = std::getenv("LBM_KERNEL_CUS")) {
+    const long v = std::strtol(ov, nullptr, 10);
+    if (v >= 1 && v <= 65536) h->ds.cus = (int)v;
+  }
   hipError_t e = hipMemcpyAsync(h->ds.dparams, &h->dp, sizeof(h->dp), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = lbm::launch_init(h->dp, h->ds, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -303,13 +312,15 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
   return LBM_OK;
 }
 
-// Runs of steps are replayed from a captured HIP graph of kGraphSteps steps
-// (an even count, so the ping-pong buffers end where they started): one graph
-// launch instead of 2 kGraphSteps kernel launches.  Steps while kernel timing
-// is on, the first step (no history yet) and remainders run eagerly.
-constexpr int64_t kGraphSteps = 32;
+// Runs of steps are replayed from captured HIP graphs of 2, 4, 8, 16 or 32
+// steps (even counts, so the ping-pong buffers end where they started): one
+// graph launch instead of two kernel launches per step.  A run is split into
+// the longest such pieces; steps while kernel timing is on, the first step
+// (no history yet) and an odd last step run eagerly.
+constexpr int kGraphKinds = 5;
 
-int capture_graph(lbm_handle* h) {
+int capture_graph(lbm_handle* h, int kind) {
+  const int64_t kGraphSteps = int64_t(2) << kind;
   lbm::DevState s = h->ds;  // the capture advances a copy's buffer parity
   hipGraph_t g = nullptr;
   HIP_OR_FAIL(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "begin graph capture");
@@ -324,13 +335,13 @@ int capture_graph(lbm_handle* h) {
   }
   const hipError_t e_end = hipStreamEndCapture(h->stream, &g);
   if (e == hipSuccess) e = e_end;
-  if (e == hipSuccess) e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipGraphInstantiate(&h->graph[kind], g, nullptr, nullptr, 0);
   if (g) (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
-    h->graph = nullptr;
+    h->graph[kind] = nullptr;
     return hip_fail(h, e, "graph capture of the step kernels");
   }
-  h->graph_parity = h->ds.cur;
+  h->graph_parity[kind] = h->ds.cur;
   return LBM_OK;
 }
 
@@ -341,15 +352,17 @@ int lbm_step(lbm_handle* h, int64_t n) {
   int64_t k = 0;
   while (k < n) {
     const bool timing = h->timer.ev && h->timer.used < h->timer.max_steps;
-    if (!timing && h->have_hist && n - k >= kGraphSteps && h->ds.cur == h->ds.hcur && h->ds.cur == h->ds.scur &&
-        (!h->graph || h->ds.cur == h->graph_parity)) {
-      if (!h->graph) {
-        const int rc = capture_graph(h);
+    int kind = kGraphKinds - 1;
+    while (kind >= 0 && n - k < (int64_t(2) << kind)) --kind;
+    if (!timing && kind >= 0 && h->have_hist && h->ds.cur == h->ds.hcur && h->ds.cur == h->ds.scur &&
+        (!h->graph[kind] || h->ds.cur == h->graph_parity[kind])) {
+      if (!h->graph[kind]) {
+        const int rc = capture_graph(h, kind);
         if (rc) return rc;
       }
-      HIP_OR_FAIL(h, hipGraphLaunch(h->graph, h->stream), "graph launch");
-      h->step += kGraphSteps;
-      k += kGraphSteps;
+      HIP_OR_FAIL(h, hipGraphLaunch(h->graph[kind], h->stream), "graph launch");
+      h->step += int64_t(2) << kind;
+      k += int64_t(2) << kind;
       continue;
     }
     HIP_OR_FAIL(h, lbm::launch_step(h->dp, h->ds, h->have_hist, h->stream, &h->timer), "step kernels");
@@ -449,7 +462,8 @@ int lbm_save_state(lbm_handle* h, void* host, size_t bytes) {
   if (!host || bytes < need) return fail(h, LBM_E_ARG, "state buffer too small");
   const size_t N = (size_t)h->dp.N;
   const size_t cb = lbm::compute_bytes(h->prm.precision);
-  StateHeader hd{kStateMagic, h->prm.precision, h->prm.nx, h->prm.ny, h->have_hist, h->step, hash_bytes(&h->prm, sizeof(h->prm)), {0, 0, 0}};
+  StateHeader hd{kStateMagic, h->prm.precision, h->prm.nx, h->prm.ny, h->have_hist, h->step,
+                 hash_bytes(&h->prm, sizeof(h->prm)), {0, 0, 0}, h->dp.m_ref};
   HIP_OR_FAIL(h, hipMemcpyAsync(hd.pending, h->ds.scalars + h->ds.scur, sizeof(hd.pending), hipMemcpyDeviceToHost, h->stream), "save");
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream), "synchronise");
   char* o = (char*)host;
@@ -485,6 +499,8 @@ int lbm_load_state(lbm_handle* h, const void* host, size_t bytes) {
   o += 2 * N * sizeof(double);
   HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.uhist[hp], o, 6 * N * cb, hipMemcpyHostToDevice, h->stream), "load");
   HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.scalars + h->ds.scur, hd.pending, sizeof(hd.pending), hipMemcpyHostToDevice, h->stream), "load");
+  h->dp.m_ref = hd.m_ref;
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->ds.dparams, &h->dp, sizeof(h->dp), hipMemcpyHostToDevice, h->stream), "load");
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream), "synchronise");
   h->have_hist = hd.have_hist;
   h->step = hd.step;
@@ -566,11 +582,20 @@ int lbm_bytes_per_node_step(lbm_handle* h, double* bytes) {
   return LBM_OK;
 }
 
+int lbm_step_kernel(lbm_handle* h, int32_t* variant, int32_t* workgroups, int32_t* cus) {
+  if (!h || !variant || !workgroups || !cus) return fail(h, LBM_E_ARG, "null argument");
+  *variant = lbm::step_variant(h->dp, h->ds);
+  *workgroups = (int32_t)lbm::step_blocks(h->dp.nx, h->dp.ny, h->ds.tile_rows);
+  *cus = h->ds.cus;
+  return LBM_OK;
+}
+
 int lbm_destroy(lbm_handle* h) {
   if (!h) return LBM_OK;
   release_timer(h);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  for (int k = 0; k < kGraphKinds; ++k)
+    if (h->graph[k]) (void)hipGraphExecDestroy(h->graph[k]);
   if (h->own_buf && h->buf) (void)hipFree(h->buf);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;

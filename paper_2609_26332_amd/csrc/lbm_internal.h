@@ -118,6 +118,13 @@ constexpr int kMaxTiles = 1 << 22;   // partials of the fused step: [kMaxTiles][
 size_t storage_bytes(int precision);
 size_t pops_bytes(int precision, size_t N);   // one population buffer (FP16: 27 FP16 planes + 2 FP32 rest planes)
 int step_seg_rows(int nx, int ny, int precision);                 // rows per workgroup segment of the step kernel
+// Kernel of a single handle's step (the values of LBM_KV_* in lbm.h): one-pass
+// 4-row tiles with eight waves (grids of at most one such workgroup per CU),
+// with four waves (up to kStepMinBlocks per CU), or the row sweep, built for
+// one workgroup per CU or, on walled grids of more workgroups than CUs, for
+// kStepMinBlocks.  Chosen from the workgroup count against DevState::cus.
+enum { kVarSmall = 0, kVarMid = 1, kVarSweep = 2, kVarSweepPacked = 3 };
+int step_variant(const DevParams& p, const DevState& s);
 size_t step_blocks(int nx, int ny, int seg_rows);  // workgroups of the step kernel
 size_t compute_bytes(int precision);
 int set_init_error(int code, const std::string& msg);   // message for lbm_last_error(NULL); returns code

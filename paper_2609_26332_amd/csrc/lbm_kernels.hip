@@ -1804,16 +1804,22 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
     const DevParams* dp = (const DevParams*)s.dparams;
     // the choice depends on the number of workgroups against the device's CUs
     // (256 on an MI355X); every variant gives the same results
-    if (a.seg_rows == 4 && a.ntiles <= s.cus) {   // small grid: one-shot tiles
-      if (p.periodic_y) hipLaunchKernelGGL((k_step_small<S, C, false>), dim3(a.ntiles), dim3(2 * kBlock), 0, st, dp, a);
-      else hipLaunchKernelGGL((k_step_small<S, C, true>), dim3(a.ntiles), dim3(2 * kBlock), 0, st, dp, a);
-    } else if (a.seg_rows == 4 && a.ntiles <= kStepMinBlocks<S> * s.cus) {   // mid-size grid
-      if (p.periodic_y) hipLaunchKernelGGL((k_step_mid<S, C, false>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
-      else hipLaunchKernelGGL((k_step_mid<S, C, true>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
-    } else if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
-    else if (a.ntiles > s.cus)
-      hipLaunchKernelGGL((k_step<S, C, true, kStepMinBlocks<S>>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
-    else hipLaunchKernelGGL((k_step<S, C, true, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
+    switch (step_variant(p, s)) {
+      case kVarSmall:   // small grid: one-shot tiles
+        if (p.periodic_y) hipLaunchKernelGGL((k_step_small<S, C, false>), dim3(a.ntiles), dim3(2 * kBlock), 0, st, dp, a);
+        else hipLaunchKernelGGL((k_step_small<S, C, true>), dim3(a.ntiles), dim3(2 * kBlock), 0, st, dp, a);
+        break;
+      case kVarMid:     // mid-size grid
+        if (p.periodic_y) hipLaunchKernelGGL((k_step_mid<S, C, false>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
+        else hipLaunchKernelGGL((k_step_mid<S, C, true>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
+        break;
+      case kVarSweepPacked:
+        hipLaunchKernelGGL((k_step<S, C, true, kStepMinBlocks<S>>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
+        break;
+      default:
+        if (p.periodic_y) hipLaunchKernelGGL((k_step<S, C, false, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
+        else hipLaunchKernelGGL((k_step<S, C, true, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
+    }
   }
   if (!(fuse & kFuseNext)) {
     TimedScope ts(t, LBM_K_FINISH, st);
@@ -1879,6 +1885,15 @@ size_t pops_bytes(int precision, size_t N) {
 }
 size_t step_blocks(int nx, int ny, int seg_rows) {
   return (size_t)((nx + kStripW - 1) / kStripW) * (size_t)((ny + seg_rows - 1) / seg_rows);
+}
+int step_variant(const DevParams& p, const DevState& s) {
+  const size_t ntiles = step_blocks(p.nx, p.ny, s.tile_rows);
+  const size_t cus = (size_t)s.cus;
+  const size_t packed = s.precision == LBM_FP64 ? (size_t)kStepMinBlocks<double> : (size_t)kStepMinBlocks<float>;
+  if (s.tile_rows == 4 && ntiles <= cus) return kVarSmall;
+  if (s.tile_rows == 4 && ntiles <= packed * cus) return kVarMid;
+  if (!p.periodic_y && packed > 1 && ntiles > cus) return kVarSweepPacked;
+  return kVarSweep;
 }
 // Rows per workgroup segment: long segments amortise the four extra phi/psi
 // rows and two extra mu rows each segment computes, but a grid needs enough

@@ -129,6 +129,26 @@ def flat_slab(nx: int = 256, ny: int = 4, width: float = 128.0, psi_b: float = 0
                  init_kind=INIT_SLAB, x0=nx / 2.0, y0=0.0, a=width, R0=0.0, **kw)
 
 
+def drop3d(n: int = 24, R: float = 7.0, psi_b: float = 0.01, ny: int = 0, nz: int = 0, **kw) -> dict:
+    """Three-dimensional periodic stationary drop (stationary-drop physics of
+    the 2-D case: interface width 4, sigma0 = 0.01, mobilities 0.05)."""
+    ny, nz = ny or n, nz or n
+    cfg = _base(nx=n, ny=ny, nz=nz, bc_bottom=PERIODIC, bc_top=PERIODIC, psi_b=psi_b,
+                x0=n / 2.0, y0=ny / 2.0, z0=nz / 2.0, R0=R)
+    cfg.update(kw)
+    return cfg
+
+
+def sessile3d(nx: int = 32, ny: int = 24, nz: int = 16, R: float = 8.0, theta0_deg: float = 60.0,
+              psi_b: float = 0.02, beta_sg: float = 0.3, beta_sl: float = 0.01, **kw) -> dict:
+    """Three-dimensional sessile drop on an adsorbing wetting wall at z = -1/2
+    (hemisphere of radius R centred on the wall), free-slip top."""
+    cfg = _base(nx=nx, ny=ny, nz=nz, bc_bottom=WALL_WET, bc_top=FREESLIP, psi_b=psi_b, theta0_deg=theta0_deg,
+                beta_sg=beta_sg, beta_sl=beta_sl, x0=nx / 2.0, y0=ny / 2.0, z0=-0.5, R0=R)
+    cfg.update(kw)
+    return cfg
+
+
 def roofline_grid(nx: int = 4096, ny: int = 4096, **kw) -> dict:
     """Large periodic grid (state far beyond the on-die caches) with one big
     drop, stationary-drop physics; used to measure the HBM-bound regime."""

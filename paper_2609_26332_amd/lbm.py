@@ -34,12 +34,13 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_UNSUPPORTED", -3: "LBM_E_OOM"
 EXPORTS = ["lbm_required_bytes", "lbm_init", "lbm_step", "lbm_reduce_invariants", "lbm_fetch_fields",
            "lbm_load_fields", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_derived",
            "lbm_fetch_populations", "lbm_destroy", "lbm_last_error", "lbm_timing_begin", "lbm_timing_end",
-           "lbm_bytes_per_node_step", "lbm_probe_bytes", "lbm_probe_stream",
+           "lbm_bytes_per_node_step", "lbm_probe_bytes", "lbm_probe_stream", "lbm_step_kernel",
            "lbm_batch_required_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_set_active",
            "lbm_batch_reduce_invariants", "lbm_batch_fetch_fields", "lbm_batch_replace_case", "lbm_batch_autotune",
            "lbm_batch_info", "lbm_batch_timing_begin", "lbm_batch_timing_end", "lbm_batch_destroy",
            "lbm_batch_last_error"]
 KERNEL_NAMES = ["k_step", "k_step_finish"]
+STEP_KERNELS = ["k_step_small", "k_step_mid", "k_step", "k_step (three workgroups per CU)"]
 
 
 class LbmError(RuntimeError):
@@ -114,6 +115,8 @@ def lib() -> ctypes.CDLL:
         L.lbm_probe_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(sz)]
         L.lbm_probe_stream.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, sz, vp,
                                        ctypes.POINTER(ctypes.c_float)]
+        L.lbm_step_kernel.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = ctypes.c_char_p
         i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
@@ -274,6 +277,12 @@ class Sim:
         b = ctypes.c_double()
         _check(lib().lbm_bytes_per_node_step(self._h, ctypes.byref(b)), self._h)
         return b.value
+
+    def step_kernel(self) -> dict:
+        """The step kernel this handle launches (lbm_step_kernel)."""
+        v, w, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lbm_step_kernel(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(c)), self._h)
+        return dict(variant=v.value, kernel=STEP_KERNELS[v.value], workgroups=w.value, cus=c.value)
 
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
