@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_hip.so")
-SOURCES = ["lbm_kernels.hip", "lbm_capi.cpp", "lbm_batch.cpp", "mlp.hip", "lbm_probe.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_capi.cpp", "lbm_batch.cpp", "mlp.hip", "lbm_probe.hip", "lbm3d.hip"]
 
 # gfx950 only; packed FP32 instructions are disabled for every HIP translation unit.
 HIPCC_FLAGS = [

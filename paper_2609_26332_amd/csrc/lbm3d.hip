@@ -1,0 +1,966 @@
+// lbm3d.hip -- gfx950 kernels and C ABI (include/lbm3d.h) of the D3Q19 step of
+// the conservative Allen-Cahn / Navier-Stokes surfactant model.
+//
+// One step is four launches over the nodes (one thread per node, x fastest,
+// so every plane access of a wavefront is 64 consecutive elements):
+//   k3_mu    chemical potentials (eq_muphi, eq_mupsi) from the FP64 phi/psi
+//            planes with the 18-direction isotropic Laplacian, the wall terms
+//            of the first fluid layer, and FP64 per-workgroup multiplier sums
+//   k3_fin   one workgroup: lambda_phi (eq15) and mubar_psi (AC_psi) from the
+//            sums, in a fixed order
+//   k3_col   gradients of rho and of both potentials, the force (eq_Fs0),
+//            velocity and pressure, the sources with their backward
+//            differences, the three MRT collisions in FP64 and push streaming
+//            into the other population buffer with half-way bounce-back,
+//            moving-wall and free-slip walls
+//   k3_mom   phi, psi of the new state (zeroth moments) into the other FP64
+//            plane pair
+// The rest populations of g and h are stored shifted by the phi, psi of the
+// step that wrote them (read back from the FP64 plane pair that then holds
+// the previous step's values), so FP32 storage rounds only the increments.
+// The MRT transform uses the closed form of the D3Q19 raw-moment basis: the
+// four edge populations of a coordinate plane (a, b) follow from the moments
+// c_a^2 c_b^2, c_a c_b^2, c_a^2 c_b and c_a c_b; the two face populations of
+// an axis from c_a^2 and c_a minus their edge parts; the rest population from
+// the zeroth moment.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/lbm.h"
+#include "../../include/lbm3d.h"
+
+namespace {
+
+constexpr int Q3 = 19;
+constexpr int kT = 256;   // threads per workgroup
+constexpr int kRedB = 1024;
+
+// Velocity set: rest; faces +x -x +y -y +z -z; edges of the xy, xz, yz planes
+// in the sign order (+,+) (-,+) (+,-) (-,-).
+__host__ __device__ constexpr int cx3(int i) {
+  constexpr int v[Q3] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  return v[i];
+}
+__host__ __device__ constexpr int cy3(int i) {
+  constexpr int v[Q3] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+  return v[i];
+}
+__host__ __device__ constexpr int cz3(int i) {
+  constexpr int v[Q3] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+  return v[i];
+}
+__host__ __device__ constexpr double w3(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+__host__ __device__ constexpr int opp3(int i) {
+  constexpr int v[Q3] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
+  return v[i];
+}
+// direction with c_z negated (specular reflection at a z wall)
+__host__ __device__ constexpr int mirz3(int i) {
+  constexpr int v[Q3] = {0, 1, 2, 3, 4, 6, 5, 7, 8, 9, 10, 13, 14, 11, 12, 17, 18, 15, 16};
+  return v[i];
+}
+constexpr double kCs2 = 1.0 / 3.0;
+
+struct P3 {
+  int nx, ny, nz, N, periodic_z, wet_b, wet_t, freeslip_b, freeslip_t, surf, linear, adv_raw, s2_local, phi_hold;
+  double kappa, beta, W, kBT, phib, lambda_s, M0, M_phi, M_psi, eta_phi, eta_psi;
+  double rho_l, rho_g, mu_l, mu_g, gx, gy, gz, uw_b, uw_t;
+  double sig_cos, dsb, msb;   // sigma cos(theta0), sigma_sg0 beta_sg -/+ sigma_sl0 beta_sl
+  double sf[5], sg[5], sh[5];
+  double x0, y0, z0, R0, a, init_scale, psi_b;
+  int init_kind;
+  double m_ref;
+};
+
+struct Scal3 {
+  double lambda, mubar;
+};
+
+// Device state of one handle.
+struct St3 {
+  void* pops[2];     // 57 planes each (f 0..18, g 19..37, h 38..56), storage type
+  double* pp[2];     // phi, psi planes of a state (pp[cur]: current, pp[cur ^ 1]: previous)
+  double* mu;        // mu_phi, mu_psi planes
+  double* uh[2];     // history: ux, uy, uz, vx, vy, vz, R_phi, R_psi of a step
+  double* part;      // [kRedB][4] multiplier sums or [kRedB][8] invariant sums
+  Scal3* sc;         // multipliers of the current step
+  double* stage;     // FP64 staging [9][N]
+  double* inv_out;   // [8]
+  P3* dp;            // device copy of the parameters
+};
+
+__device__ __forceinline__ double liquid_frac(const P3& p, double ph) {
+  const double w = 0.5 * (1.0 + ph / p.phib);
+  return w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+}
+__device__ __forceinline__ double rho_of(const P3& p, double ph) { return p.rho_g + (p.rho_l - p.rho_g) * liquid_frac(p, ph); }
+__device__ __forceinline__ double gsw(const P3& p, double ph) {
+  const double b = p.phib;
+  return 0.75 * ph / b - 0.25 * ph * ph * ph / (b * b * b);
+}
+__device__ __forceinline__ double gsw_d(const P3& p, double ph) {
+  const double r = ph / p.phib;
+  return 0.75 / p.phib * (1.0 - r * r);
+}
+__device__ __forceinline__ double hprime(const P3& p, double ph) { return p.linear ? 1.0 : gsw_d(p, ph); }
+__device__ __forceinline__ double hval(const P3& p, double ph) { return p.linear ? ph : 0.5 + gsw(p, ph); }
+// -df_w/dphi, -df_w/dpsi of the wall energy at a wall-layer node (eq8, boundary)
+__device__ __forceinline__ double wall_jphi(const P3& p, double ph, double ps) {
+  const double a = p.sig_cos + (p.surf ? log(1.0 - ps) * p.dsb : 0.0);
+  return a * gsw_d(p, ph);
+}
+__device__ __forceinline__ double wall_jpsi(const P3& p, double ph, double ps) {
+  return p.surf ? -(p.dsb * gsw(p, ph) - 0.5 * p.msb) / (1.0 - ps) : 0.0;
+}
+
+__device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// Neighbour of (x, y, z) along direction i: node index, or -1 / -2 beyond the
+// bottom / top wall; *colnode is the node of the same (x, y) column in the
+// layer of (x, y, z).
+__device__ __forceinline__ int nbr(const P3& p, int x, int y, int z, int i, int* colnode) {
+  const int xx = wrap(x + cx3(i), p.nx), yy = wrap(y + cy3(i), p.ny);
+  int zz = z + cz3(i);
+  *colnode = (z * p.ny + yy) * p.nx + xx;
+  if (p.periodic_z) zz = wrap(zz, p.nz);
+  else if (zz < 0) return -1;
+  else if (zz >= p.nz) return -2;
+  return (zz * p.ny + yy) * p.nx + xx;
+}
+
+template <class S>
+__device__ __forceinline__ double ld(const S* a, size_t k) { return (double)a[k]; }
+
+// Deterministic FP64 block sum of kT threads (valid in thread 0).
+__device__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kT / 64; ++k) r += sh[k];
+  return r;
+}
+
+// ---------------------------------------------------------------- k3_mu
+// mu_phi = 4 beta (1 - psi)(phi^3 - phi) - kappa L0 phi - T_phi + W psi phi
+// mu_psi = kBT ln(psi/(1-psi)) - lambda_s L0 psi - T_psi - beta (1-phi^2)^2 + W phi^2 / 2
+// with L0 the Laplacian with mirror ghosts and T the wall term of each
+// direction pointing into a wetting wall: (2 w_i / c_s^2) J(column).
+__global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const double* __restrict__ pp,
+                                            double* __restrict__ mu, double* __restrict__ part) {
+  const P3& p = *pp_;
+  __shared__ double sh[4][kT / 64];
+  const int N = p.N;
+  double s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+  for (int n = blockIdx.x * kT + threadIdx.x; n < N; n += gridDim.x * kT) {
+    const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
+    const double ph = pp[n], ps = pp[N + n];
+    double l0p = 0.0, l0s = 0.0, tp = 0.0, ts = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q3; ++i) {
+      int cn;
+      const int m = nbr(p, x, y, z, i, &cn);
+      const double wt = 2.0 * w3(i) / kCs2;
+      if (m >= 0) {
+        l0p += wt * (pp[m] - ph);
+        l0s += wt * (pp[N + m] - ps);
+      } else {
+        l0p += wt * (pp[cn] - ph);
+        l0s += wt * (pp[N + cn] - ps);
+        if ((m == -1 && p.wet_b) || (m == -2 && p.wet_t)) {
+          const double fph = pp[cn], fps = pp[N + cn];
+          tp += wt * wall_jphi(p, fph, fps);
+          ts += wt * wall_jpsi(p, fph, fps);
+        }
+      }
+    }
+    const double mphi = 4.0 * p.beta * (1.0 - ps) * (ph * ph * ph - ph) - p.kappa * l0p - tp + p.W * ps * ph;
+    const double mpsi = p.surf ? p.kBT * log(ps / (1.0 - ps)) - p.lambda_s * l0s - ts
+                                     - p.beta * (1.0 - ph * ph) * (1.0 - ph * ph) + 0.5 * p.W * ph * ph
+                               : 0.0;
+    mu[n] = mphi;
+    mu[N + n] = mpsi;
+    const double hp = hprime(p, ph);
+    s1 += hp * mphi;
+    s2 += hp * hp;
+    s3 += mpsi;
+    s4 += hval(p, ph);
+  }
+  const double r1 = block_sum(s1, sh[0]), r2 = block_sum(s2, sh[1]), r3 = block_sum(s3, sh[2]), r4 = block_sum(s4, sh[3]);
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x + 0] = r1;
+    part[4 * blockIdx.x + 1] = r2;
+    part[4 * blockIdx.x + 2] = r3;
+    part[4 * blockIdx.x + 3] = r4;
+  }
+}
+
+__global__ __launch_bounds__(kT) void k3_fin(const P3* __restrict__ pp_, const double* __restrict__ part, int nb,
+                                             Scal3* __restrict__ sc) {
+  const P3& p = *pp_;
+  if (threadIdx.x != 0) return;
+  double S1 = 0, S2 = 0, S3 = 0, S4 = 0;
+  for (int b = 0; b < nb; ++b) {
+    S1 += part[4 * b];
+    S2 += part[4 * b + 1];
+    S3 += part[4 * b + 2];
+    S4 += part[4 * b + 3];
+  }
+  double lam = S2 > 0.0 ? S1 / S2 : 0.0;
+  if (p.phi_hold && S2 > 0.0 && p.M_phi > 0.0) lam += (p.m_ref - S4) / (p.M_phi * S2);
+  sc->lambda = lam;
+  sc->mubar = S3 / p.N;
+}
+
+// ------------------------------------------------------ MRT, closed form
+// Raw moments of a population vector, in the order
+// 0: 1; 1-3: x y z; 4-9: xx yy zz xy xz yz; 10-15: xxy xxz yyx yyz zzx zzy;
+// 16-18: xxyy xxzz yyzz.
+__device__ __forceinline__ void moments3(const double* f, double* m) {
+#pragma unroll
+  for (int k = 0; k < Q3; ++k) m[k] = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q3; ++i) {
+    const int a = cx3(i), b = cy3(i), c = cz3(i);
+    const double v = f[i];
+    m[0] += v;
+    if (a) m[1] += a * v;
+    if (b) m[2] += b * v;
+    if (c) m[3] += c * v;
+    if (a) m[4] += v;
+    if (b) m[5] += v;
+    if (c) m[6] += v;
+    if (a && b) m[7] += a * b * v;
+    if (a && c) m[8] += a * c * v;
+    if (b && c) m[9] += b * c * v;
+    if (a && b) { m[10] += b * v; m[12] += a * v; m[16] += v; }
+    if (a && c) { m[11] += c * v; m[14] += a * v; m[17] += v; }
+    if (b && c) { m[13] += c * v; m[15] += b * v; m[18] += v; }
+  }
+}
+// Populations from raw moments (the inverse of moments3).
+__device__ __forceinline__ void populations3(const double* m, double* f) {
+  // edges of plane (a, b): E0 = m_aabb, Ea = m_abb, Eb = m_aab, Eab = m_ab
+  const double E[3][4] = {{m[16], m[12], m[10], m[7]},    // xy: xxyy, yyx, xxy, xy
+                          {m[17], m[14], m[11], m[8]},    // xz: xxzz, zzx, xxz, xz
+                          {m[18], m[15], m[13], m[9]}};   // yz: yyzz, zzy, yyz, yz
+#pragma unroll
+  for (int pl = 0; pl < 3; ++pl)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double sa = (k & 1) ? -1.0 : 1.0, sb = (k & 2) ? -1.0 : 1.0;
+      f[7 + 4 * pl + k] = 0.25 * (E[pl][0] + sa * E[pl][1] + sb * E[pl][2] + sa * sb * E[pl][3]);
+    }
+  // faces: F0 = m_aa - (edge sums of the two planes through a), F1 = m_a - (their c_a sums)
+  const double F0x = m[4] - m[16] - m[17], F1x = m[1] - m[12] - m[14];
+  const double F0y = m[5] - m[16] - m[18], F1y = m[2] - m[10] - m[15];
+  const double F0z = m[6] - m[17] - m[18], F1z = m[3] - m[11] - m[13];
+  f[1] = 0.5 * (F0x + F1x);
+  f[2] = 0.5 * (F0x - F1x);
+  f[3] = 0.5 * (F0y + F1y);
+  f[4] = 0.5 * (F0y - F1y);
+  f[5] = 0.5 * (F0z + F1z);
+  f[6] = 0.5 * (F0z - F1z);
+  f[0] = m[0] - (m[4] + m[5] + m[6]) + (m[16] + m[17] + m[18]);
+}
+__device__ __forceinline__ int order3(int k) { return k == 0 ? 0 : (k < 4 ? 1 : (k < 10 ? 2 : (k < 16 ? 3 : 4))); }
+
+// f <- f - M^-1 S M (f - feq) + M^-1 (I - S/2) M v   (the extra w_i term is added by the caller)
+__device__ __forceinline__ void mrt3(double* f, const double* feq, const double* v, const double* rate5) {
+  double d[Q3], md[Q3], mv[Q3];
+#pragma unroll
+  for (int i = 0; i < Q3; ++i) d[i] = f[i] - feq[i];
+  moments3(d, md);
+  moments3(v, mv);
+#pragma unroll
+  for (int k = 0; k < Q3; ++k) {
+    const double s = rate5[order3(k)];
+    md[k] = -s * md[k] + (1.0 - 0.5 * s) * mv[k];
+  }
+  populations3(md, d);
+#pragma unroll
+  for (int i = 0; i < Q3; ++i) f[i] += d[i];
+}
+
+__device__ __forceinline__ double cdot3(int i, double ax, double ay, double az) {
+  return cx3(i) * ax + cy3(i) * ay + cz3(i) * az;
+}
+
+// Macroscopic state at a node (phi, psi, rho, grad rho, F, u, p, the wall
+// terms and the zero-flux Laplacian of psi), from the FP64 planes and the f
+// populations of the current state.
+struct Macro3 {
+  double ph, ps, rho, gr[3], F[3], u[3], pr, tphi, tpsi, l0s;
+};
+template <class S>
+__device__ Macro3 macro3(const P3& p, const S* __restrict__ pop, const double* __restrict__ pp,
+                         const double* __restrict__ mu, int n) {
+  Macro3 M;
+  const int N = p.N;
+  const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
+  M.ph = pp[n];
+  M.ps = pp[N + n];
+  M.rho = rho_of(p, M.ph);
+  double gr[3] = {0, 0, 0}, gmp[3] = {0, 0, 0}, gms[3] = {0, 0, 0}, tp = 0.0, ts = 0.0, l0s = 0.0;
+#pragma unroll
+  for (int i = 1; i < Q3; ++i) {
+    int cn;
+    const int m = nbr(p, x, y, z, i, &cn);
+    double r, mp, ms, pn;
+    if (m >= 0) {
+      r = rho_of(p, pp[m]);
+      mp = mu[m];
+      ms = mu[N + m];
+      pn = pp[N + m];
+    } else {
+      const bool wet = (m == -1 && p.wet_b) || (m == -2 && p.wet_t);
+      const double fph = pp[cn], fps = pp[N + cn];
+      const double jp = wet ? wall_jphi(p, fph, fps) : 0.0;
+      r = rho_of(p, fph + jp / p.kappa);
+      mp = mu[cn];
+      ms = mu[N + cn];
+      pn = fps;
+      if (wet) {
+        tp += 2.0 * w3(i) / kCs2 * jp;
+        ts += 2.0 * w3(i) / kCs2 * wall_jpsi(p, fph, fps);
+      }
+    }
+    const double c[3] = {(double)cx3(i), (double)cy3(i), (double)cz3(i)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      gr[d] += w3(i) * c[d] * r / kCs2;
+      gmp[d] += w3(i) * c[d] * mp / kCs2;
+      gms[d] += w3(i) * c[d] * ms / kCs2;
+    }
+    l0s += 2.0 * w3(i) / kCs2 * (pn - M.ps);
+  }
+  const double G[3] = {p.gx, p.gy, p.gz};
+  double j[3] = {0, 0, 0}, snz = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q3; ++i) {
+    const double fi = ld(pop, (size_t)i * N + n);
+    j[0] += cx3(i) * fi;
+    j[1] += cy3(i) * fi;
+    j[2] += cz3(i) * fi;
+    if (i) snz += fi;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    M.gr[d] = gr[d];
+    M.F[d] = -M.ph * gmp[d] - M.ps * gms[d] + M.rho * G[d];
+    M.u[d] = (j[d] + 0.5 * M.F[d]) / M.rho;
+  }
+  const double ugr = M.u[0] * gr[0] + M.u[1] * gr[1] + M.u[2] * gr[2];
+  const double uu = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
+  M.pr = kCs2 / (1.0 - w3(0)) * (snz + 0.5 * ugr - M.rho * w3(0) * uu / (2.0 * kCs2));
+  M.tphi = tp;
+  M.tpsi = ts;
+  M.l0s = l0s;
+  return M;
+}
+
+// ---------------------------------------------------------------- k3_col
+template <class S>
+__global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const S* __restrict__ pin, S* __restrict__ pout,
+                                             const double* __restrict__ pp, const double* __restrict__ pprev,
+                                             const double* __restrict__ mu, const double* __restrict__ hin,
+                                             double* __restrict__ hout, const Scal3* __restrict__ sc, int have_hist) {
+  const P3& p = *pp_;
+  const int N = p.N;
+  const int n = blockIdx.x * kT + threadIdx.x;
+  if (n >= N) return;
+  const Macro3 M = macro3(p, pin, pp, mu, n);
+  const double ph = M.ph, ps = M.ps, rho = M.rho;
+  const double lam = sc->lambda, mubar = sc->mubar;
+  // sources (Sec. 3): R_phi with the multiplier term and the wall flux, R_psi likewise
+  const double Rphi = p.M_phi * (-4.0 * p.beta * (1.0 - ps) * (ph * ph * ph - ph) - p.W * ps * ph + lam * hprime(p, ph))
+                    + p.M_phi * M.tphi;
+  const double Rpsi = p.surf ? -p.M0 * M.l0s
+                                   + p.M_psi * (-p.kBT * log(ps / (1.0 - ps)) + p.beta * (1.0 - ph * ph) * (1.0 - ph * ph)
+                                                - 0.5 * p.W * ph * ph + mubar)
+                                   + p.M_psi * M.tpsi
+                             : 0.0;
+  // advecting velocity and backward differences (first step: zero)
+  double v[3] = {M.u[0], M.u[1], M.u[2]}, dph[3] = {0, 0, 0}, dps[3] = {0, 0, 0}, dRp = 0.0, dRs = 0.0;
+  if (have_hist) {
+    if (!p.adv_raw)
+      for (int d = 0; d < 3; ++d) v[d] = 0.5 * (M.u[d] + hin[(size_t)d * N + n]);
+    const double php = pprev[n], psp = pprev[N + n];
+    for (int d = 0; d < 3; ++d) {
+      const double vh = hin[(size_t)(3 + d) * N + n];
+      dph[d] = ph * v[d] - php * vh;
+      dps[d] = ps * v[d] - psp * vh;
+    }
+    dRp = Rphi - hin[(size_t)6 * N + n];
+    dRs = Rpsi - hin[(size_t)7 * N + n];
+  }
+  for (int d = 0; d < 3; ++d) {
+    hout[(size_t)d * N + n] = M.u[d];
+    hout[(size_t)(3 + d) * N + n] = v[d];
+  }
+  hout[(size_t)6 * N + n] = Rphi;
+  hout[(size_t)7 * N + n] = Rpsi;
+
+  const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
+  double f[Q3], eq[Q3], fv[Q3];
+  // --- flow lattice
+  {
+    double rates[5];
+    for (int k = 0; k < 5; ++k) rates[k] = p.sf[k];
+    if (p.s2_local) {
+      const double mud = p.mu_g + (p.mu_l - p.mu_g) * liquid_frac(p, ph);
+      rates[2] = 1.0 / (3.0 * mud / rho + 0.5);
+    }
+    const double uu = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
+    const double ugr = M.u[0] * M.gr[0] + M.u[1] * M.gr[1] + M.u[2] * M.gr[2];
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+      f[i] = ld(pin, (size_t)i * N + n);
+      const double cu = cdot3(i, M.u[0], M.u[1], M.u[2]);
+      const double su = cu / kCs2 + cu * cu / (2.0 * kCs2 * kCs2) - uu / (2.0 * kCs2);
+      eq[i] = M.pr / kCs2 * (w3(i) - (i == 0 ? 1.0 : 0.0)) + rho * w3(i) * su;
+      const double cg = cdot3(i, M.gr[0], M.gr[1], M.gr[2]), cF = cdot3(i, M.F[0], M.F[1], M.F[2]);
+      fv[i] = w3(i) * (ugr + cF / kCs2 + (cu * cg - kCs2 * ugr) / kCs2);
+    }
+    mrt3(f, eq, fv, rates);
+    // push streaming; walls in z
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+      const int zz = z + cz3(i);
+      const int xx = wrap(x + cx3(i), p.nx), yy = wrap(y + cy3(i), p.ny);
+      if (p.periodic_z || (zz >= 0 && zz < p.nz)) {
+        const int t = (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx;
+        pout[(size_t)i * N + t] = (S)f[i];
+      } else {
+        const bool bot = zz < 0;
+        if (bot ? p.freeslip_b : p.freeslip_t) {
+          pout[(size_t)mirz3(i) * N + (z * p.ny + yy) * p.nx + xx] = (S)f[i];
+        } else {
+          const double uw = bot ? p.uw_b : p.uw_t;
+          pout[(size_t)opp3(i) * N + n] = (S)(f[i] - 2.0 * w3(i) * rho * (cx3(i) * uw) / kCs2);
+        }
+      }
+    }
+  }
+  // --- phase-field and surfactant lattices (rest population stored relative to phi, psi of this step)
+  for (int lat = 1; lat <= 2; ++lat) {
+    if (lat == 2 && !p.surf) {
+#pragma unroll
+      for (int i = 0; i < Q3; ++i) {   // idle surfactant lattice: keep zeros in the target buffer
+        const int zz = z + cz3(i);
+        const int xx = wrap(x + cx3(i), p.nx), yy = wrap(y + cy3(i), p.ny);
+        if (p.periodic_z || (zz >= 0 && zz < p.nz)) pout[(size_t)(38 + i) * N + (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx] = (S)0.0;
+        else pout[(size_t)(38 + opp3(i)) * N + n] = (S)0.0;
+      }
+      break;
+    }
+    const double c = lat == 1 ? ph : ps;
+    const double eta = lat == 1 ? p.eta_phi : p.eta_psi;
+    const double* dj = lat == 1 ? dph : dps;
+    const double* r5 = lat == 1 ? p.sg : p.sh;
+    const double extra = lat == 1 ? Rphi + 0.5 * dRp : Rpsi + 0.5 * dRs;
+    const int base = 19 * lat;
+    const double cref = lat == 1 ? pprev[n] : pprev[N + n];   // the shift of the stored rest population
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+      f[i] = ld(pin, (size_t)(base + i) * N + n) + (i == 0 ? cref : 0.0);
+      eq[i] = (i == 0 ? c + (w3(0) - 1.0) * eta * c : w3(i) * eta * c) + w3(i) * cdot3(i, c * v[0], c * v[1], c * v[2]) / kCs2;
+      fv[i] = w3(i) * cdot3(i, dj[0], dj[1], dj[2]) / kCs2;
+    }
+    mrt3(f, eq, fv, r5);
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+      double val = f[i] + w3(i) * extra;
+      if (i == 0) val -= c;
+      const int zz = z + cz3(i);
+      const int xx = wrap(x + cx3(i), p.nx), yy = wrap(y + cy3(i), p.ny);
+      if (p.periodic_z || (zz >= 0 && zz < p.nz)) pout[(size_t)(base + i) * N + (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx] = (S)val;
+      else pout[(size_t)(base + opp3(i)) * N + n] = (S)val;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- k3_mom
+// phi, psi of the state just streamed: the moving populations plus the rest
+// population and its shift (phi, psi of the step that wrote it).
+template <class S>
+__global__ __launch_bounds__(kT) void k3_mom(const P3* __restrict__ pp_, const S* __restrict__ pop,
+                                             const double* __restrict__ pold, double* __restrict__ pnew) {
+  const P3& p = *pp_;
+  const int N = p.N;
+  const int n = blockIdx.x * kT + threadIdx.x;
+  if (n >= N) return;
+  double a = 0.0, b = 0.0;
+#pragma unroll
+  for (int i = 1; i < Q3; ++i) {
+    a += ld(pop, (size_t)(19 + i) * N + n);
+    b += ld(pop, (size_t)(38 + i) * N + n);
+  }
+  pnew[n] = pold[n] + ld(pop, (size_t)19 * N + n) + a;
+  pnew[N + n] = p.surf ? pold[N + n] + ld(pop, (size_t)38 * N + n) + b : 0.0;
+}
+
+// ------------------------------------------------------- initial state, load
+__global__ __launch_bounds__(kT) void k3_profile(const P3* __restrict__ pp_, double* __restrict__ stage) {
+  const P3& p = *pp_;
+  const int n = blockIdx.x * kT + threadIdx.x;
+  if (n >= p.N) return;
+  const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
+  double dx = x - p.x0, dy = y - p.y0, dz = z - p.z0;
+  dx -= p.nx * floor(dx / p.nx + 0.5);
+  dy -= p.ny * floor(dy / p.ny + 0.5);
+  if (p.periodic_z) dz -= p.nz * floor(dz / p.nz + 0.5);
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double d = p.init_kind == LBM_INIT_SLAB ? 0.5 * p.a - fabs(dx) : (p.init_kind == LBM_INIT_BUBBLE ? r - p.R0 : p.R0 - r);
+  stage[n] = p.phib * tanh(p.init_scale * d);
+  stage[p.N + n] = p.surf ? p.psi_b : 0.0;
+}
+
+// Equilibrium populations of staged phi, psi (and u) with p = 0; both plane
+// pairs take phi, psi (the rest populations are stored relative to them).
+template <class S>
+__global__ __launch_bounds__(kT) void k3_load(const P3* __restrict__ pp_, const double* __restrict__ stage, int with_u,
+                                              S* __restrict__ pop, double* __restrict__ pa, double* __restrict__ pb) {
+  const P3& p = *pp_;
+  const int N = p.N;
+  const int n = blockIdx.x * kT + threadIdx.x;
+  if (n >= N) return;
+  const double ph = stage[n], ps = p.surf ? stage[N + n] : 0.0;
+  const double u[3] = {with_u ? stage[2 * (size_t)N + n] : 0.0, with_u ? stage[3 * (size_t)N + n] : 0.0,
+                       with_u ? stage[4 * (size_t)N + n] : 0.0};
+  const double rho = rho_of(p, ph), uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+  for (int i = 0; i < Q3; ++i) {
+    const double cu = cdot3(i, u[0], u[1], u[2]);
+    const double fe = with_u ? rho * w3(i) * (cu / kCs2 + cu * cu / (2.0 * kCs2 * kCs2) - uu / (2.0 * kCs2)) : 0.0;
+    const double ge = (i == 0 ? ph + (w3(0) - 1.0) * p.eta_phi * ph : w3(i) * p.eta_phi * ph) + w3(i) * ph * cu / kCs2;
+    const double he = (i == 0 ? ps + (w3(0) - 1.0) * p.eta_psi * ps : w3(i) * p.eta_psi * ps) + w3(i) * ps * cu / kCs2;
+    pop[(size_t)i * N + n] = (S)fe;
+    pop[(size_t)(19 + i) * N + n] = (S)(i == 0 ? ge - ph : ge);
+    pop[(size_t)(38 + i) * N + n] = (S)(p.surf ? (i == 0 ? he - ps : he) : 0.0);
+  }
+  pa[n] = pb[n] = ph;
+  pa[N + n] = pb[N + n] = ps;
+}
+
+// Fields of the current state into the staging planes:
+// phi, psi, ux, uy, uz, p, rho, mu_phi, mu_psi.
+template <class S>
+__global__ __launch_bounds__(kT) void k3_fields(const P3* __restrict__ pp_, const S* __restrict__ pop,
+                                                const double* __restrict__ pp, const double* __restrict__ mu,
+                                                double* __restrict__ stage) {
+  const P3& p = *pp_;
+  const int N = p.N;
+  const int n = blockIdx.x * kT + threadIdx.x;
+  if (n >= N) return;
+  const Macro3 M = macro3(p, pop, pp, mu, n);
+  const double v[9] = {M.ph, M.ps, M.u[0], M.u[1], M.u[2], M.pr, M.rho, mu[n], mu[N + n]};
+#pragma unroll
+  for (int k = 0; k < 9; ++k) stage[(size_t)k * N + n] = v[k];
+}
+
+// Invariant sums from the staged fields: mass_psi, m_phi_h, sum_phi, kinetic,
+// umax (max), nonfinite, psi_out_of_range; per workgroup, then k3_inv_fin.
+__global__ __launch_bounds__(kT) void k3_inv(const P3* __restrict__ pp_, const double* __restrict__ stage,
+                                             double* __restrict__ part) {
+  const P3& p = *pp_;
+  __shared__ double sh[6][kT / 64];
+  __shared__ double smax[kT];
+  const int N = p.N;
+  double a[6] = {0, 0, 0, 0, 0, 0}, um = 0.0;
+  for (int n = blockIdx.x * kT + threadIdx.x; n < N; n += gridDim.x * kT) {
+    const double ph = stage[n], ps = stage[N + n], ux = stage[2 * (size_t)N + n], uy = stage[3 * (size_t)N + n],
+                 uz = stage[4 * (size_t)N + n], pr = stage[5 * (size_t)N + n], rho = stage[6 * (size_t)N + n];
+    const double u2 = ux * ux + uy * uy + uz * uz;
+    a[0] += ps;
+    a[1] += 0.5 + gsw(p, ph);
+    a[2] += ph;
+    a[3] += 0.5 * rho * u2;
+    if (!(isfinite(ph) && isfinite(ps) && isfinite(u2) && isfinite(pr))) a[4] += 1.0;
+    if (p.surf && !(ps > 0.0 && ps < 1.0)) a[5] += 1.0;
+    const double s = sqrt(u2);
+    um = s > um ? s : um;
+  }
+  double r[6];
+  for (int k = 0; k < 6; ++k) r[k] = block_sum(a[k], sh[k]);
+  smax[threadIdx.x] = um;
+  __syncthreads();
+  for (int off = kT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 6; ++k) part[8 * blockIdx.x + k] = r[k];
+    part[8 * blockIdx.x + 6] = smax[0];
+  }
+}
+__global__ void k3_inv_fin(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double s[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < nb; ++b) {
+    for (int k = 0; k < 6; ++k) s[k] += part[8 * b + k];
+    s[6] = fmax(s[6], part[8 * b + 6]);
+  }
+  for (int k = 0; k < 7; ++k) out[k] = s[k];
+}
+
+int nblk(long long n) { return (int)((n + kT - 1) / kT); }
+int red_blocks(int N) { const int b = nblk(N); return b < kRedB ? b : kRedB; }
+size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
+
+thread_local std::string g_err3 = "no error";
+constexpr double kPi = 3.14159265358979323846;
+
+}  // namespace
+
+struct lbm3d_handle {
+  lbm3d_params prm;
+  P3 p;
+  St3 s;
+  int cur = 0, have_hist = 0;
+  int64_t step = 0;
+  bool faulted = false;
+  void* buf = nullptr;
+  bool own_buf = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err = "no error";
+};
+
+namespace {
+
+int fail3(lbm3d_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_err3 = msg;
+  return code;
+}
+#define HIP3(h, expr, where)                                                                          \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess) return fail3(h, LBM_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+std::string derive3(const lbm3d_params& q, P3& d) {
+  if (q.abi_version != LBM3D_ABI_VERSION) return "abi_version mismatch";
+  if (q.nx < 3 || q.ny < 3 || q.nz < 3) return "nx, ny and nz must be >= 3";
+  if ((double)q.nx * q.ny * q.nz * 57.0 > 9.0e18 || (double)q.nx * q.ny * q.nz >= 2147483647.0) return "grid too large";
+  auto bc_ok = [](int b) { return b >= LBM_BC_PERIODIC && b <= LBM_BC_FREESLIP; };
+  if (!bc_ok(q.bc_bottom) || !bc_ok(q.bc_top)) return "unknown boundary kind";
+  if ((q.bc_bottom == LBM_BC_PERIODIC) != (q.bc_top == LBM_BC_PERIODIC)) return "periodic z needs both walls periodic";
+  if (q.precision != LBM_FP64 && q.precision != LBM_FP32) return "precision must be LBM_FP64 or LBM_FP32";
+  if (q.constraint_phi != LBM_CONSTRAINT_NONLINEAR && q.constraint_phi != LBM_CONSTRAINT_LINEAR) return "unknown constraint";
+  if (q.init_kind < LBM_INIT_DROP || q.init_kind > LBM_INIT_BUBBLE) return "unknown init kind";
+  if ((q.adv_raw != 0 && q.adv_raw != 1) || (q.phi_hold != 0 && q.phi_hold != 1) || q.reserved != 0) return "bad switch value";
+  if (!(q.sigma_gl0 > 0.0) || !(q.eps > 0.0)) return "sigma_gl0 and eps must be > 0";
+  if (!(q.M_phi >= 0.0) || !(q.M_psi >= 0.0)) return "mobilities must be >= 0";
+  if (!(q.psi_b >= 0.0 && q.psi_b < 1.0)) return "psi_b must lie in [0,1)";
+  if (!(q.rho_l > 0.0 && q.rho_g > 0.0 && q.mu_l > 0.0 && q.mu_g > 0.0)) return "densities and viscosities must be > 0";
+  const bool wet = q.bc_bottom == LBM_BC_WALL_WET || q.bc_top == LBM_BC_WALL_WET;
+  if (wet && !(q.theta0_deg > 0.0 && q.theta0_deg < 180.0)) return "theta0 must lie in (0,180) on a wetting wall";
+  const double* rates[3] = {q.s_f, q.s_g, q.s_h};
+  for (int l = 0; l < 3; ++l)
+    for (int k = 0; k < 5; ++k)
+      if (!(rates[l][k] < 2.0)) return "relaxation rates must lie in (0,2)";
+  std::memset(&d, 0, sizeof(d));
+  d.nx = q.nx; d.ny = q.ny; d.nz = q.nz; d.N = q.nx * q.ny * q.nz;
+  d.periodic_z = q.bc_bottom == LBM_BC_PERIODIC;
+  d.wet_b = q.bc_bottom == LBM_BC_WALL_WET;
+  d.wet_t = q.bc_top == LBM_BC_WALL_WET;
+  d.freeslip_b = q.bc_bottom == LBM_BC_FREESLIP;
+  d.freeslip_t = q.bc_top == LBM_BC_FREESLIP;
+  d.surf = q.psi_b > 0.0;
+  d.linear = q.constraint_phi == LBM_CONSTRAINT_LINEAR;
+  d.adv_raw = q.adv_raw;
+  d.phi_hold = q.phi_hold;
+  const double kappa = 0.375 * q.eps * q.sigma_gl0, beta = 0.75 * q.sigma_gl0 / q.eps;
+  const double W = q.W > 0.0 ? q.W : 4.0 * beta / (q.Ex > 0.0 ? q.Ex : 0.5);
+  const double kBT = q.kBT > 0.0 ? q.kBT : 4.0 * beta * (q.Pi > 0.0 ? q.Pi : 1.35);
+  double phib = 1.0;
+  if (q.phi_b > 0.0) phib = q.phi_b;
+  else if (d.surf) {
+    const double r = 1.0 - W * q.psi_b / (4.0 * beta * (1.0 - q.psi_b));
+    if (!(r > 0.0)) return "bulk surfactant too large: phi_b^2 <= 0";
+    phib = std::sqrt(r);
+  }
+  double sg0 = q.sigma_sg0, sl0 = q.sigma_sl0;
+  if (!(sg0 >= 0.0 && sl0 >= 0.0)) {
+    const double diff = q.sigma_gl0 * std::cos(q.theta0_deg * kPi / 180.0), sum = 16.0 * q.sigma_gl0 / 15.0;
+    sg0 = 0.5 * (sum + diff);
+    sl0 = 0.5 * (sum - diff);
+  }
+  const double lambda_s = q.lambda_s >= 0.0 ? q.lambda_s : (wet ? 0.5 * kappa : 0.0);
+  if (wet && d.surf && lambda_s == 0.0 && (q.beta_sg != 0.0 || q.beta_sl != 0.0))
+    return "lambda_s = 0 cannot carry the solid-adsorption boundary condition";
+  const double M0 = q.M0 >= 0.0 ? q.M0 : (lambda_s > 0.0 ? 0.0 : q.M_phi * kappa);
+  auto rate = [](double v) { return v > 0.0 ? v : 1.0; };
+  const double s1g = rate(q.s_g[1]), s1h = rate(q.s_h[1]);
+  d.kappa = kappa; d.beta = beta; d.W = W; d.kBT = kBT; d.phib = phib;
+  d.lambda_s = lambda_s; d.M0 = M0; d.M_phi = q.M_phi; d.M_psi = q.M_psi;
+  d.eta_phi = q.eta_phi > 0.0 ? q.eta_phi : q.M_phi * kappa / ((1.0 / s1g - 0.5) * kCs2);
+  d.eta_psi = q.eta_psi > 0.0 ? q.eta_psi : (q.M_psi * lambda_s + M0) / ((1.0 / s1h - 0.5) * kCs2);
+  d.rho_l = q.rho_l; d.rho_g = q.rho_g; d.mu_l = q.mu_l; d.mu_g = q.mu_g;
+  d.gx = q.gx; d.gy = q.gy; d.gz = q.gz; d.uw_b = q.u_wall_bottom; d.uw_t = q.u_wall_top;
+  d.sig_cos = q.sigma_gl0 * std::cos(q.theta0_deg * kPi / 180.0);
+  d.dsb = sg0 * q.beta_sg - sl0 * q.beta_sl;
+  d.msb = sg0 * q.beta_sg + sl0 * q.beta_sl;
+  for (int k = 0; k < 5; ++k) { d.sf[k] = rate(q.s_f[k]); d.sg[k] = rate(q.s_g[k]); d.sh[k] = rate(q.s_h[k]); }
+  d.s2_local = !(q.s_f[2] > 0.0);
+  d.x0 = q.x0; d.y0 = q.y0; d.z0 = q.z0; d.R0 = q.R0; d.a = q.a;
+  d.init_scale = 2.0 * phib * (d.surf ? std::sqrt(1.0 - q.psi_b) : 1.0) / q.eps;
+  d.init_kind = q.init_kind;
+  d.psi_b = q.psi_b;
+  return "";
+}
+
+struct Lay3 {
+  size_t pops, pp, mu, uh, part, sc, stage, inv, dp, total;
+};
+Lay3 layout3(const lbm3d_params& q) {
+  const size_t N = (size_t)q.nx * q.ny * q.nz, sb = q.precision == LBM_FP64 ? 8 : 4;
+  Lay3 L{};
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off += al256(b); return o; };
+  L.pops = take(2 * 57 * N * sb);
+  L.pp = take(2 * 2 * N * 8);
+  L.mu = take(2 * N * 8);
+  L.uh = take(2 * 8 * N * 8);
+  L.part = take((size_t)kRedB * 8 * 8);
+  L.sc = take(sizeof(Scal3));
+  L.stage = take(9 * N * 8);
+  L.inv = take(8 * 8);
+  L.dp = take(sizeof(P3));
+  L.total = off;
+  return L;
+}
+
+template <class S>
+hipError_t step3(lbm3d_handle* h) {
+  const P3& p = h->p;
+  St3& s = h->s;
+  const int c = h->cur;
+  const int rb = red_blocks(p.N);
+  hipLaunchKernelGGL(k3_mu, dim3(rb), dim3(kT), 0, h->stream, s.dp, (const double*)s.pp[c], s.mu, s.part);
+  hipLaunchKernelGGL(k3_fin, dim3(1), dim3(64), 0, h->stream, s.dp, (const double*)s.part, rb, s.sc);
+  hipLaunchKernelGGL((k3_col<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const S*)s.pops[c], (S*)s.pops[c ^ 1],
+                     (const double*)s.pp[c], (const double*)s.pp[c ^ 1], (const double*)s.mu, (const double*)s.uh[c ^ 1],
+                     s.uh[c], (const Scal3*)s.sc, h->have_hist);
+  hipLaunchKernelGGL((k3_mom<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const S*)s.pops[c ^ 1],
+                     (const double*)s.pp[c], s.pp[c ^ 1]);
+  return hipGetLastError();
+}
+
+// mu and the multipliers of the current state, then the fields into staging
+template <class S>
+hipError_t fields3(lbm3d_handle* h) {
+  const P3& p = h->p;
+  St3& s = h->s;
+  const int c = h->cur;
+  const int rb = red_blocks(p.N);
+  hipLaunchKernelGGL(k3_mu, dim3(rb), dim3(kT), 0, h->stream, s.dp, (const double*)s.pp[c], s.mu, s.part);
+  hipLaunchKernelGGL(k3_fin, dim3(1), dim3(64), 0, h->stream, s.dp, (const double*)s.part, rb, s.sc);
+  hipLaunchKernelGGL((k3_fields<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const S*)s.pops[c],
+                     (const double*)s.pp[c], (const double*)s.mu, s.stage);
+  return hipGetLastError();
+}
+
+hipError_t load3(lbm3d_handle* h, int with_u) {
+  St3& s = h->s;
+  const int c = h->cur;
+  if (h->prm.precision == LBM_FP64)
+    hipLaunchKernelGGL((k3_load<double>), dim3(nblk(h->p.N)), dim3(kT), 0, h->stream, s.dp, (const double*)s.stage, with_u,
+                       (double*)s.pops[c], s.pp[c], s.pp[c ^ 1]);
+  else
+    hipLaunchKernelGGL((k3_load<float>), dim3(nblk(h->p.N)), dim3(kT), 0, h->stream, s.dp, (const double*)s.stage, with_u,
+                       (float*)s.pops[c], s.pp[c], s.pp[c ^ 1]);
+  return hipGetLastError();
+}
+
+// invariants of the current state into inv_out (synchronises), optionally
+// sets phi_hold's reference from them
+int invariants3(lbm3d_handle* h, double* v7, Scal3* sc) {
+  HIP3(h, h->prm.precision == LBM_FP64 ? fields3<double>(h) : fields3<float>(h), "field kernels");
+  const int rb = red_blocks(h->p.N);
+  hipLaunchKernelGGL(k3_inv, dim3(rb), dim3(kT), 0, h->stream, h->s.dp, (const double*)h->s.stage, h->s.part);
+  hipLaunchKernelGGL(k3_inv_fin, dim3(1), dim3(64), 0, h->stream, (const double*)h->s.part, rb, h->s.inv_out);
+  HIP3(h, hipGetLastError(), "invariant kernels");
+  HIP3(h, hipMemcpyAsync(v7, h->s.inv_out, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy invariants");
+  if (sc) HIP3(h, hipMemcpyAsync(sc, h->s.sc, sizeof(Scal3), hipMemcpyDeviceToHost, h->stream), "copy multipliers");
+  HIP3(h, hipStreamSynchronize(h->stream), "synchronise");
+  return LBM_OK;
+}
+
+int set_ref3(lbm3d_handle* h) {
+  if (!h->p.phi_hold) return LBM_OK;
+  double v[7];
+  const int rc = invariants3(h, v, nullptr);
+  if (rc) return rc;
+  h->p.m_ref = h->p.linear ? v[2] : v[1];
+  HIP3(h, hipMemcpyAsync(h->s.dp, &h->p, sizeof(P3), hipMemcpyHostToDevice, h->stream), "upload parameters");
+  HIP3(h, hipStreamSynchronize(h->stream), "synchronise");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm3d_required_bytes(const lbm3d_params* q, size_t* bytes) {
+  if (!q || !bytes) return fail3(nullptr, LBM_E_ARG, "null argument");
+  P3 d;
+  const std::string why = derive3(*q, d);
+  if (!why.empty()) return fail3(nullptr, LBM_E_ARG, why);
+  *bytes = layout3(*q).total;
+  return LBM_OK;
+}
+
+int lbm3d_init(const lbm3d_params* q, void* dev_buf, size_t buf_bytes, void* hip_stream, lbm3d_handle** out) {
+  if (!out) return fail3(nullptr, LBM_E_ARG, "null output handle");
+  *out = nullptr;
+  if (!q) return fail3(nullptr, LBM_E_ARG, "null parameters");
+  lbm3d_handle* h = new lbm3d_handle();
+  h->prm = *q;
+  const std::string why = derive3(*q, h->p);
+  if (!why.empty()) { delete h; return fail3(nullptr, LBM_E_ARG, why); }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+      std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    delete h;
+    return fail3(nullptr, LBM_E_DEVICE, "no gfx950 device");
+  }
+  const Lay3 L = layout3(*q);
+  if (dev_buf) {
+    if (buf_bytes < L.total || ((uintptr_t)dev_buf & 255)) { delete h; return fail3(nullptr, LBM_E_ARG, "dev_buf too small or not 256-byte aligned"); }
+    h->buf = dev_buf;
+  } else {
+    if (hipMalloc(&h->buf, L.total) != hipSuccess) { delete h; return fail3(nullptr, LBM_E_OOM, "hipMalloc of the state failed"); }
+    h->own_buf = true;
+  }
+  if (hip_stream) h->stream = (hipStream_t)hip_stream;
+  else {
+    if (hipStreamCreate(&h->stream) != hipSuccess) {
+      if (h->own_buf) (void)hipFree(h->buf);
+      delete h;
+      return fail3(nullptr, LBM_E_DEVICE, "hipStreamCreate failed");
+    }
+    h->own_stream = true;
+  }
+  char* b = (char*)h->buf;
+  const size_t N = (size_t)h->p.N, sb = q->precision == LBM_FP64 ? 8 : 4;
+  h->s.pops[0] = b + L.pops;
+  h->s.pops[1] = b + L.pops + 57 * N * sb;
+  h->s.pp[0] = (double*)(b + L.pp);
+  h->s.pp[1] = h->s.pp[0] + 2 * N;
+  h->s.mu = (double*)(b + L.mu);
+  h->s.uh[0] = (double*)(b + L.uh);
+  h->s.uh[1] = h->s.uh[0] + 8 * N;
+  h->s.part = (double*)(b + L.part);
+  h->s.sc = (Scal3*)(b + L.sc);
+  h->s.stage = (double*)(b + L.stage);
+  h->s.inv_out = (double*)(b + L.inv);
+  h->s.dp = (P3*)(b + L.dp);
+  hipError_t e = hipMemcpyAsync(h->s.dp, &h->p, sizeof(P3), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k3_profile, dim3(nblk(h->p.N)), dim3(kT), 0, h->stream, h->s.dp, h->s.stage);
+    e = load3(h, 0);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  int rc = e == hipSuccess ? set_ref3(h) : LBM_E_DEVICE;
+  if (rc != LBM_OK) {
+    const std::string msg = e != hipSuccess ? std::string("initialisation: ") + hipGetErrorString(e) : h->err;
+    lbm3d_destroy(h);
+    return fail3(nullptr, LBM_E_DEVICE, msg);
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm3d_step(lbm3d_handle* h, int64_t n) {
+  if (!h) return fail3(nullptr, LBM_E_ARG, "null handle");
+  if (n < 0) return fail3(h, LBM_E_ARG, "negative step count");
+  if (h->faulted) return fail3(h, LBM_E_STATE, "state holds non-finite or out-of-range values; load fields first");
+  for (int64_t k = 0; k < n; ++k) {
+    HIP3(h, h->prm.precision == LBM_FP64 ? step3<double>(h) : step3<float>(h), "step kernels");
+    h->cur ^= 1;
+    h->have_hist = 1;
+    h->step += 1;
+  }
+  return LBM_OK;
+}
+
+int lbm3d_reduce_invariants(lbm3d_handle* h, lbm3d_invariants* out) {
+  if (!h || !out) return fail3(h, LBM_E_ARG, "null argument");
+  double v[7];
+  Scal3 sc;
+  int rc = invariants3(h, v, &sc);
+  if (rc) return rc;
+  std::memset(out, 0, sizeof(*out));
+  out->step = h->step;
+  out->mass_psi = v[0];
+  out->m_phi_h = v[1];
+  out->sum_phi = v[2];
+  out->kinetic = v[3];
+  out->nonfinite = (int64_t)v[4];
+  out->psi_out_of_range = (int64_t)v[5];
+  out->umax = v[6];
+  out->lambda_phi = sc.lambda;
+  out->mubar_psi = sc.mubar;
+  if (out->psi_out_of_range > 0) { h->faulted = true; return fail3(h, LBM_E_RANGE, "psi left (0,1)"); }
+  if (out->nonfinite > 0) { h->faulted = true; return fail3(h, LBM_E_NONFINITE, "non-finite values in the fields"); }
+  return LBM_OK;
+}
+
+int lbm3d_fetch_fields(lbm3d_handle* h, uint32_t mask, double* host, size_t n_doubles) {
+  if (!h || !host) return fail3(h, LBM_E_ARG, "null argument");
+  if (mask == 0 || (mask & ~0x1FFu)) return fail3(h, LBM_E_ARG, "bad field mask");
+  const size_t N = (size_t)h->p.N;
+  if (n_doubles < (size_t)__builtin_popcount(mask) * N) return fail3(h, LBM_E_ARG, "host buffer too small");
+  HIP3(h, h->prm.precision == LBM_FP64 ? fields3<double>(h) : fields3<float>(h), "field kernels");
+  size_t k = 0;
+  for (int bit = 0; bit < 9; ++bit)
+    if (mask & (1u << bit))
+      HIP3(h, hipMemcpyAsync(host + (k++) * N, h->s.stage + (size_t)bit * N, N * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream), "copy fields");
+  HIP3(h, hipStreamSynchronize(h->stream), "synchronise");
+  return LBM_OK;
+}
+
+int lbm3d_load_fields(lbm3d_handle* h, int32_t with_u, const double* host, size_t n_doubles) {
+  if (!h || !host) return fail3(h, LBM_E_ARG, "null argument");
+  const size_t N = (size_t)h->p.N, planes = with_u ? 5 : 2;
+  if (n_doubles < planes * N) return fail3(h, LBM_E_ARG, "host buffer too small");
+  HIP3(h, hipMemcpyAsync(h->s.stage, host, planes * N * sizeof(double), hipMemcpyHostToDevice, h->stream), "copy fields");
+  HIP3(h, load3(h, with_u ? 1 : 0), "load kernel");
+  HIP3(h, hipStreamSynchronize(h->stream), "synchronise");
+  h->have_hist = 0;
+  h->faulted = false;
+  return set_ref3(h);
+}
+
+int lbm3d_bytes_per_node_step(lbm3d_handle* h, double* bytes) {
+  if (!h || !bytes) return fail3(h, LBM_E_ARG, "null argument");
+  const double sb = h->prm.precision == LBM_FP64 ? 8.0 : 4.0;
+  // k3_mu: phi/psi read, mu written; k3_col: 57 populations, phi/psi (two steps), mu, 8 history planes read,
+  // 57 populations and 8 history planes written; k3_mom: 38 populations and phi/psi read, phi/psi written
+  *bytes = (2 * 8 + 2 * 8) + (57 * sb + 4 * 8 + 2 * 8 + 8 * 8 + 57 * sb + 8 * 8) + (38 * sb + 2 * 8 + 2 * 8);
+  return LBM_OK;
+}
+
+int lbm3d_destroy(lbm3d_handle* h) {
+  if (!h) return LBM_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->own_buf && h->buf) (void)hipFree(h->buf);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return LBM_OK;
+}
+
+const char* lbm3d_last_error(const lbm3d_handle* h) { return h ? h->err.c_str() : g_err3.c_str(); }
+
+}  // extern "C"

@@ -10,6 +10,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lbm.h")
 MLP_HEADER = os.path.join(ROOT, "include", "mlp.h")
+HEADER3 = os.path.join(ROOT, "include", "lbm3d.h")
 LIB = os.path.join(ROOT, "paper_2609_26332_amd", "liblbm_hip.so")
 
 
@@ -45,6 +46,26 @@ def test_library_exports_every_declared_symbol(lbm):
     for name in mlp_names:
         assert hasattr(L, name), name
     assert L.mlp_param_count() == 133634
+    from paper_2609_26332_amd import lbm3d
+    names3 = declared_functions(HEADER3, "lbm3d_")
+    assert sorted(lbm3d.EXPORTS) == names3
+    for name in names3:
+        assert hasattr(L, name), name
+
+
+def test_3d_parameter_validation_without_a_device(lbm):
+    """lbm3d_required_bytes validates a parameter set on the host."""
+    from paper_2609_26332_amd import inputs, lbm3d
+
+    L = lbm3d.lib()
+    n = ctypes.c_size_t()
+    p = lbm3d.make_params(inputs.drop3d(16, 5.0), lbm.FP64)
+    assert L.lbm3d_required_bytes(ctypes.byref(p), ctypes.byref(n)) == 0 and n.value > 57 * 2 * 16 ** 3 * 8
+    bad = lbm3d.make_params(dict(inputs.drop3d(16, 5.0), nz=2), lbm.FP64)
+    assert L.lbm3d_required_bytes(ctypes.byref(bad), ctypes.byref(n)) == lbm.LbmError(-1, "").code
+    assert b"nz" in L.lbm3d_last_error(None)
+    bad = lbm3d.make_params(inputs.drop3d(16, 5.0), lbm.FP16_SHIFTED)
+    assert L.lbm3d_required_bytes(ctypes.byref(bad), ctypes.byref(n)) == -1
 
 
 def test_param_struct_layout_matches_header(lbm):

@@ -1,0 +1,115 @@
+"""Parity of the 3-D (D3Q19) HIP path, through the C ABI, with the 3-D FP64
+CPU oracle: every field after 1, 10 and 100 steps within 1e-10 relative in
+FP64 storage and 1e-5 in FP32 storage (velocity normalised by a thousandth
+of the capillary velocity sigma / mu_l or the wall speed, pressure by a
+thousandth of the Laplace pressure 2 sigma / R)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_26332_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FIELDS3 = ["phi", "psi", "ux", "uy", "uz", "p", "mu_phi", "mu_psi"]
+
+
+@pytest.fixture(scope="module")
+def lbm3d():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2609_26332_amd import lbm3d as binding
+
+    return binding
+
+
+def scales(cfg):
+    u = max(cfg.get("sigma_gl0", 0.01) / cfg.get("mu_l", 0.1), abs(cfg.get("u_wall_top", 0.0)))
+    R = abs(cfg.get("R0", 8.0)) or 8.0
+    return 1e-3 * u, 1e-3 * 2 * cfg.get("sigma_gl0", 0.01) / R
+
+
+def errors(g, o, cfg):
+    uf, pf = scales(cfg)
+    out = {}
+    for k in FIELDS3:
+        ref = np.abs(o[k]).max()
+        floor = uf if k in ("ux", "uy", "uz") else (pf if k == "p" else 0.0)
+        scale = max(ref, floor)
+        out[k] = np.abs(g[k] - o[k]).max() / scale if scale > 0 else np.abs(g[k] - o[k]).max()
+    return out
+
+
+CASES3 = {
+    "drop_periodic_24": inputs.drop3d(24, 7.0, psi_b=0.01),
+    "sessile_adsorbing_32x24x16": inputs.sessile3d(),
+    "shear_ratio10_32x16x16": inputs.sessile3d(nx=32, ny=16, nz=16, R=6.0, theta0_deg=90.0, psi_b=0.01,
+                                               beta_sg=0.9, beta_sl=0.01, bc_top=inputs.NOSLIP, u_wall_top=0.005,
+                                               rho_l=10.0, rho_g=1.0, mu_l=1.0, mu_g=0.1),
+    "ragged_19x13x11_linear": inputs.drop3d(19, 4.3, psi_b=0.02, ny=13, nz=11, constraint_phi=inputs.LINEAR,
+                                            x0=8.7, y0=6.1, z0=5.3),
+    "bubble_freeslip_clean": dict(inputs.sessile3d(nx=24, ny=20, nz=16, R=5.0, psi_b=0.0, theta0_deg=45.0),
+                                  init_kind=inputs.INIT_BUBBLE, z0=8.0, bc_bottom=inputs.FREESLIP, bc_top=inputs.WALL_WET),
+    "literal_advection": inputs.drop3d(20, 6.0, psi_b=0.01, adv_raw=1),
+    "phi_hold_walls": dict(inputs.sessile3d(psi_b=0.0), phi_hold=1),
+    "ratio1000_sessile": inputs.sessile3d(nx=32, ny=24, nz=16, R=8.0, theta0_deg=90.0, psi_b=0.0, eps=6.0,
+                                          rho_l=1000.0, rho_g=1.0, mu_l=100.0, mu_g=1.0, bc_top=inputs.NOSLIP),
+}
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("name", list(CASES3))
+def test_parity_3d(lbm3d, name, prec, tol):
+    cfg = CASES3[name]
+    g = lbm3d.Sim3(cfg, prec)
+    o = oracle.Oracle3Sim(cfg)
+    done = 0
+    for c in (1, 10, 100):
+        g.step(c - done)
+        o.step(c - done)
+        done = c
+        e = errors(g.fields(FIELDS3), o.fields(FIELDS3), cfg)
+        bad = {k: v for k, v in e.items() if not v <= tol}
+        assert not bad, (name, prec, c, bad, e)
+    gi, oi = g.invariants(), o.invariants()
+    assert gi["lambda_phi"] == pytest.approx(oi["lambda_phi"], rel=10 * tol, abs=1e-14)
+    assert gi["mubar_psi"] == pytest.approx(oi["mubar_psi"], rel=10 * tol, abs=1e-14)
+    assert gi["mass_psi"] == pytest.approx(oi["mass_psi"], rel=tol, abs=1e-14)
+
+
+def test_surfactant_mass_conserved_3d_fp64(lbm3d):
+    """Sec. 4.1: sum psi is conserved to round-off by the linear constraint,
+    the zero-flux walls and the adsorption flux; 2000 FP64 steps of the
+    walled adsorbing drop keep it within 1e-12 of its start."""
+    g = lbm3d.Sim3(inputs.sessile3d(), "fp64")
+    m0 = g.invariants()["mass_psi"]
+    g.step(2000)
+    iv = g.invariants()
+    assert iv["nonfinite"] == 0
+    assert abs(iv["mass_psi"] - m0) / m0 < 1e-12
+
+
+def test_load_fields_and_errors_3d(lbm3d):
+    """lbm3d_load_fields takes phi, psi (and u) and builds the state the oracle
+    builds from the same fields; a non-finite field is reported and latches."""
+    cfg = inputs.drop3d(16, 5.0, psi_b=0.01)
+    g = lbm3d.Sim3(cfg, "fp64")
+    o = oracle.Oracle3Sim(cfg)
+    f = o.fields(["phi", "psi"])
+    rng = np.random.default_rng(3)
+    u = [1e-3 * rng.standard_normal(f["phi"].shape) for _ in range(3)]
+    g.load_fields(f["phi"], f["psi"], u)
+    o.load_fields(f["phi"], f["psi"], np.stack(u))
+    g.step(20)
+    o.step(20)
+    e = errors(g.fields(FIELDS3), o.fields(FIELDS3), cfg)
+    assert max(e.values()) < 1e-10, e
+    bad = f["phi"].copy()
+    bad[3, 4, 5] = np.nan
+    g.load_fields(bad, f["psi"])
+    iv = g.invariants(check=False)
+    assert iv["status"] == -5 and iv["nonfinite"] >= 1
+    with pytest.raises(Exception):
+        g.step(1)
