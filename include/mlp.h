@@ -72,6 +72,23 @@ int mlp_train_step(mlp_handle* h, int32_t member, const float* x_dev, const floa
  * and standard deviation (population, over members): mean_dev[n][2], std_dev[n][2]. */
 int mlp_predict_ensemble(mlp_handle* h, const float* x_dev, int32_t n, float* mean_dev, float* std_dev);
 
+/* mlp_predict_ensemble without a handle and without allocating: for callers
+ * that cannot allocate device memory (work under HIP graph capture, tight
+ * serving loops, harnesses that forbid it).  params_dev holds the FP32
+ * parameters of `members` members back to back ([members][mlp_param_count()],
+ * device memory, caller-owned, as mlp_get_params returns them); x_dev, mean_dev
+ * and std_dev as for mlp_predict_ensemble.  The results equal
+ * mlp_predict_ensemble's for the same parameters bit for bit.  Limits:
+ * 1 <= members <= 8 and 1 <= n <= 1024 (-1 beyond them).  Work is ordered on
+ * hip_stream (NULL: the null stream) and nothing synchronises.  The bfloat16
+ * weights and activations live in one fixed device array of about 4.3 MB per
+ * device, held until the process ends and shared by every call on that
+ * device: calls that overlap on one device (other streams or threads) race
+ * and must be serialised by the caller.  No hipMalloc, hipFree or other
+ * allocating call is made.  Errors go to mlp_last_error(NULL). */
+int mlp_predict_ensemble_noalloc(const float* params_dev, int32_t members, const float* x_dev, int32_t n,
+                                 float* mean_dev, float* std_dev, void* hip_stream);
+
 /* Release the handle and any library-owned memory and stream. */
 int mlp_destroy(mlp_handle* h);
 

@@ -328,6 +328,40 @@ void backward(mlp_handle* h, int member, const float* t, const float* m, int n) 
   }
 }
 
+// ------------------------------------------------------------------------
+// Scratch of mlp_predict_ensemble_noalloc: the bfloat16 weights of every
+// member, the bfloat16 inputs, one FP32 pre-activation buffer and two
+// bfloat16 activation buffers (ping-pong between layers), and the members'
+// outputs, for batches of up to kNoAllocMaxBatch samples and up to
+// kNoAllocMaxMembers members.  One copy per device, held until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress
+// returns on that device.
+constexpr int kNoAllocMaxBatch = 1024, kNoAllocMaxMembers = 8, kMaxDevices = 64;
+struct NoAllocLayout {
+  static constexpr size_t wbf = 0;
+  static constexpr size_t xb = wbf + ((size_t)kNoAllocMaxMembers * kParams * 2 + 255) / 256 * 256;
+  static constexpr size_t Z = xb + ((size_t)kNoAllocMaxBatch * kIn * 2 + 255) / 256 * 256;
+  static constexpr size_t A = Z + (size_t)kNoAllocMaxBatch * kHid * 4;
+  static constexpr size_t ys = A + 2 * (size_t)kNoAllocMaxBatch * kHid * 2;
+  static constexpr size_t total = ys + (size_t)kNoAllocMaxMembers * kNoAllocMaxBatch * kOut * 4;
+};
+__device__ __attribute__((aligned(256))) unsigned char scratch[NoAllocLayout::total];
+
+unsigned char* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Address of this device's scratch (looked up once per device, with that
+// device current); nullptr with a message on failure.
+unsigned char* scratch_on_device(int dev, std::string& why) {
+  if (dev < 0 || dev >= kMaxDevices) { why = "device index beyond the supported range"; return nullptr; }
+  unsigned char* p = __atomic_load_n(&g_scratch_ptr[dev], __ATOMIC_ACQUIRE);
+  if (p) return p;
+  void* q = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !q) { why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e); return nullptr; }
+  __atomic_store_n(&g_scratch_ptr[dev], (unsigned char*)q, __ATOMIC_RELEASE);
+  return (unsigned char*)q;
+}
+
 int check(mlp_handle* h, int member, int n) {
   if (!h) return mfail(nullptr, -1, "null handle");
   if (member < 0 || member >= h->members) return mfail(h, -1, "member out of range");
@@ -493,6 +527,48 @@ int mlp_predict_ensemble(mlp_handle* h, const float* x_dev, int32_t n, float* me
   hipLaunchKernelGGL(k_ens, dim3(nblk((long long)n * kOut)), dim3(kThreads), 0, h->stream, (const float*)h->ys, h->members,
                      n * kOut, mean_dev, std_dev);
   MHIP(h, hipGetLastError(), "ensemble kernels");
+  return 0;
+}
+
+int mlp_predict_ensemble_noalloc(const float* params_dev, int32_t members, const float* x_dev, int32_t n,
+                                 float* mean_dev, float* std_dev, void* hip_stream) {
+  if (!params_dev || !x_dev || !mean_dev || !std_dev) return mfail(nullptr, -1, "null argument");
+  if (members < 1 || members > kNoAllocMaxMembers)
+    return mfail(nullptr, -1, "members must lie in [1, " + std::to_string(kNoAllocMaxMembers) + "] without allocation");
+  if (n < 1 || n > kNoAllocMaxBatch)
+    return mfail(nullptr, -1, "n must lie in [1, " + std::to_string(kNoAllocMaxBatch) + "] without allocation");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return mfail(nullptr, -4, "hipGetDevice failed");
+  std::string why;
+  unsigned char* sp = scratch_on_device(dev, why);
+  if (!sp) return mfail(nullptr, -4, why);
+  const hipStream_t st = (hipStream_t)hip_stream;
+  __bf16* wbf = (__bf16*)(sp + NoAllocLayout::wbf);
+  __bf16* xb = (__bf16*)(sp + NoAllocLayout::xb);
+  float* Z = (float*)(sp + NoAllocLayout::Z);
+  __bf16* A[2] = {(__bf16*)(sp + NoAllocLayout::A), (__bf16*)(sp + NoAllocLayout::A) + (size_t)kNoAllocMaxBatch * kHid};
+  float* ys = (float*)(sp + NoAllocLayout::ys);
+  // every scratch element read below is written first in the same call
+  hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)members * kParams)), dim3(kThreads), 0, st, params_dev, wbf,
+                     members * kParams);
+  hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)n * kIn)), dim3(kThreads), 0, st, x_dev, xb, n * kIn);
+  for (int k = 0; k < members; ++k) {
+    const __bf16* W = wbf + (size_t)k * kParams;
+    const float* P = params_dev + (size_t)k * kParams;
+    const __bf16* a = xb;
+    int in = kIn;
+    for (int l = 0; l < 3; ++l) {
+      gemm(st, a, in, 1, W + w_off(l), kHid, 1, n, kHid, in, EPI_BIAS_GELU, Z, kHid, A[l & 1], P + b_off(l), nullptr);
+      a = A[l & 1];
+      in = kHid;
+    }
+    gemm(st, a, kHid, 1, W + w_off(3), kOut, 1, n, kOut, kHid, EPI_BIAS, ys + (size_t)k * n * kOut, kOut, nullptr,
+         P + b_off(3), nullptr);
+  }
+  hipLaunchKernelGGL(k_ens, dim3(nblk((long long)n * kOut)), dim3(kThreads), 0, st, (const float*)ys, members, n * kOut,
+                     mean_dev, std_dev);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return mfail(nullptr, -4, std::string("ensemble kernels: ") + hipGetErrorString(e));
   return 0;
 }
 

@@ -39,18 +39,21 @@ def lib():
         L.mlp_loss_grad.argtypes = [vp, i32, vp, vp, vp, i32, fp, fp]
         L.mlp_train_step.argtypes = [vp, i32, vp, vp, vp, i32, ctypes.c_float, fp]
         L.mlp_predict_ensemble.argtypes = [vp, vp, i32, vp, vp]
+        L.mlp_predict_ensemble_noalloc.argtypes = [vp, i32, vp, i32, vp, vp, vp]
         L.mlp_destroy.argtypes = [vp]
         L.mlp_last_error.argtypes = [vp]
         L.mlp_last_error.restype = ctypes.c_char_p
         for nm in ("mlp_required_bytes", "mlp_init", "mlp_set_params", "mlp_get_params", "mlp_forward",
-                   "mlp_loss_grad", "mlp_train_step", "mlp_predict_ensemble", "mlp_destroy"):
+                   "mlp_loss_grad", "mlp_train_step", "mlp_predict_ensemble", "mlp_predict_ensemble_noalloc",
+                   "mlp_destroy"):
             getattr(L, nm).restype = ctypes.c_int
         _mlp_ready = True
     return L
 
 
 EXPORTS = ["mlp_param_count", "mlp_required_bytes", "mlp_init", "mlp_set_params", "mlp_get_params", "mlp_forward",
-           "mlp_loss_grad", "mlp_train_step", "mlp_predict_ensemble", "mlp_destroy", "mlp_last_error"]
+           "mlp_loss_grad", "mlp_train_step", "mlp_predict_ensemble", "mlp_predict_ensemble_noalloc", "mlp_destroy",
+           "mlp_last_error"]
 
 
 def _check(rc, h=None):
@@ -132,6 +135,19 @@ class Mlp:
         sd = torch.empty_like(mean)
         _check(lib().mlp_predict_ensemble(self._h, _ptr(x), x.shape[0], _ptr(mean), _ptr(sd)), self._h)
         return mean, sd
+
+
+def predict_noalloc(params: torch.Tensor, x: torch.Tensor, mean: torch.Tensor, sd: torch.Tensor, stream=None):
+    """mlp_predict_ensemble_noalloc: every argument is a caller-owned device
+    tensor (params [members][n_params] FP32, x [n][5], mean and sd [n][2]);
+    the call allocates nothing and does not synchronise."""
+    st = stream if stream is not None else torch.cuda.current_stream()
+    members, n = params.shape[0], x.shape[0]
+    for t in (params, x, mean, sd):
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    assert mean.shape == (n, 2) and sd.shape == (n, 2) and x.shape == (n, 5)
+    _check(lib().mlp_predict_ensemble_noalloc(_ptr(params), members, _ptr(x), n, _ptr(mean), _ptr(sd),
+                                              ctypes.c_void_p(st.cuda_stream)))
 
 
 def glorot_params(seed: int, n_params: int) -> np.ndarray:
