@@ -237,7 +237,7 @@ class Params3(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("bc_bottom", ctypes.c_int32), ("bc_top", ctypes.c_int32),
         ("constraint_phi", ctypes.c_int32), ("init_kind", ctypes.c_int32),
-        ("adv_raw", ctypes.c_int32), ("phi_hold", ctypes.c_int32),
+        ("adv_raw", ctypes.c_int32), ("phi_hold", ctypes.c_int32), ("solid_wet", ctypes.c_int32),
         ("sigma_gl0", ctypes.c_double), ("eps", ctypes.c_double),
         ("M_phi", ctypes.c_double), ("M_psi", ctypes.c_double), ("lambda_s", ctypes.c_double),
         ("kBT", ctypes.c_double), ("W", ctypes.c_double), ("Ex", ctypes.c_double), ("Pi", ctypes.c_double),
@@ -284,6 +284,7 @@ def lib3():
         L.orc3_load_fields.argtypes = [ctypes.c_void_p, dp, dp, dp]
         L.orc3_get_populations.argtypes = [ctypes.c_void_p, dp]
         L.orc3_lattice.argtypes = [ctypes.POINTER(ctypes.c_int), dp]
+        L.orc3_set_solid.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
         _lib3_ready = True
     return L
 
@@ -357,6 +358,12 @@ class Oracle3Sim:
         psi = np.ascontiguousarray(psi, dtype=np.float64)
         up = _dptr(np.ascontiguousarray(u, dtype=np.float64)) if u is not None else None
         lib3().orc3_load_fields(self._h, _dptr(phi), _dptr(psi), up)
+
+    def set_solid(self, mask):
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        assert m.shape == (self.nz, self.ny, self.nx)
+        if lib3().orc3_set_solid(self._h, m.tobytes()) != 0:
+            raise ValueError("no fluid node left")
 
     def populations(self) -> np.ndarray:
         out = np.zeros((57, self.nz, self.ny, self.nx))

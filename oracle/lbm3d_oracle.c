@@ -28,6 +28,16 @@
  * linear in the liquid fraction held to [0, 1]; half-way bounce-back with a
  * ghost layer carrying phi + J_phi/kappa and the wall flux J_psi).
  *
+ * Complex walls (orc3_set_solid): nodes marked solid hold no fluid.  A link
+ * from a fluid node x to a solid node x + c_i is a half-way bounce-back wall for
+ * all three lattices, and the stencils see a ghost value there taken at x
+ * itself, link by link: mirror values for psi, mu_phi and mu_psi, and, on a
+ * wetting solid, phi(x) + J_phi(x)/kappa with the wall flux J of x's own phi and
+ * psi (eq. "boundary"); the wall term of a node is (2 w_i / c_s^2) J(x) summed
+ * over its links into the solid.  Sums and means run over fluid nodes.  (The
+ * flat z walls keep the column rule: a ghost takes the values of the fluid node
+ * in its own column.)
+ *
  * Plain loops, FP64, the generic 19x19 moment matrix and its numerically
  * computed inverse; global sums sequential in [z][y][x] order.
  */
@@ -41,7 +51,7 @@
 #include <string.h>
 
 #define Q 19
-#define PAR_MIN_NODES 16384
+#define PAR_MIN_NODES 4096   /* node loops on OpenMP threads from this size on (results do not depend on it) */
 
 static int CV[Q][3];
 static double WQ[Q];
@@ -108,6 +118,8 @@ struct orc3_sim {
   double *Fx, *Fy, *Fz, *grx, *gry, *grz, *Rphi, *Rpsi, *vx, *vy, *vz;
   double *Jphi_b, *Jpsi_b, *Jphi_t, *Jpsi_t;   /* per (x, y) column of the wall layer */
   double lambda, mubar, m_ref;
+  unsigned char* solid;   /* [N] 1 = solid node (orc3_set_solid), NULL: none */
+  int Nf;                 /* fluid nodes */
 };
 
 static int wrapi(int a, int n) { a %= n; return a < 0 ? a + n : a; }
@@ -152,13 +164,17 @@ static int nb(const orc3_sim* s, int x, int y, int z, int i, int* col) {
   if (s->periodic_z) zz = wrapi(zz, s->nz);
   else if (zz < 0) return -1;
   else if (zz >= s->nz) return -2;
-  return idx(s, xx, yy, zz);
+  int m = idx(s, xx, yy, zz);
+  if (s->solid && s->solid[m]) return -3;
+  return m;
 }
+static int is_solid(const orc3_sim* s, int n) { return s->solid && s->solid[n]; }
 /* value of a at x + c_i; beyond a wall the fluid node of the same column next
  * to it (mirror) */
 static double nb_mirror(const orc3_sim* s, const double* a, int x, int y, int z, int i) {
   int col, m = nb(s, x, y, z, i, &col);
   if (m >= 0) return a[m];
+  if (m == -3) return a[idx(s, x, y, z)];   /* link-wise mirror at a solid node */
   return a[z * s->nx * s->ny + col];
 }
 static double wall_T(const orc3_sim* s, const double* Jb, const double* Jt, int x, int y, int z) {
@@ -171,9 +187,24 @@ static double wall_T(const orc3_sim* s, const double* Jb, const double* Jt, int 
   }
   return t;
 }
+/* wall term of the links of (x, y, z) into solid nodes (wetting solids only) */
+static double solid_T(const orc3_sim* s, int x, int y, int z, double J) {
+  if (!s->solid || !s->p.solid_wet) return 0.0;
+  double t = 0.0;
+  for (int i = 1; i < Q; ++i) {
+    int col;
+    if (nb(s, x, y, z, i, &col) == -3) t += 2.0 * WQ[i] / CS2 * J;
+  }
+  return t;
+}
 static double nb_rho(const orc3_sim* s, int x, int y, int z, int i) {
   int col, m = nb(s, x, y, z, i, &col);
   if (m >= 0) return s->rho[m];
+  if (m == -3) {
+    int n = idx(s, x, y, z);
+    double ph = s->phi[n];
+    return rho_of(s, s->p.solid_wet ? ph + wall_Jphi(s, ph, s->psi[n]) / s->kappa : ph);
+  }
   double ph = s->phi[z * s->nx * s->ny + col];
   double J = m == -1 ? s->Jphi_b[col] : s->Jphi_t[col];
   return rho_of(s, ph + J / s->kappa);
@@ -290,6 +321,10 @@ void orc3_load_fields(orc3_sim* s, const double* phi, const double* psi, const d
   int N = s->N;
   double fe[Q], ge[Q], he[Q];
   for (int n = 0; n < N; ++n) {
+    if (is_solid(s, n)) {
+      for (int i = 0; i < Q; ++i) s->f[(size_t)i * N + n] = s->g[(size_t)i * N + n] = s->h[(size_t)i * N + n] = 0.0;
+      continue;
+    }
     double ux = u ? u[n] : 0.0, uy = u ? u[N + n] : 0.0, uz = u ? u[2 * N + n] : 0.0;
     double ps = s->surf ? psi[n] : 0.0;
     feq_flow(0.0, rho_of(s, phi[n]), ux, uy, uz, fe);
@@ -304,7 +339,8 @@ void orc3_load_fields(orc3_sim* s, const double* phi, const double* psi, const d
   }
   s->have_hist = 0;
   double m = 0.0;
-  for (int n = 0; n < N; ++n) m += hval(s, phi[n]);
+  for (int n = 0; n < N; ++n)
+    if (!is_solid(s, n)) m += hval(s, phi[n]);
   s->m_ref = m;
 }
 
@@ -340,6 +376,7 @@ orc3_sim* orc3_create(const orc3_params* p, char* err, int errlen) {
   s->p = *p;
   s->nx = p->nx; s->ny = p->ny; s->nz = p->nz; s->N = p->nx * p->ny * p->nz;
   s->periodic_z = p->bc_bottom == ORC3_PERIODIC;
+  s->Nf = s->N;
   if (derive(s, err, errlen)) { free(s); return NULL; }
   for (int k = 0; k < Q; ++k)
     for (int i = 0; i < Q; ++i)
@@ -366,6 +403,7 @@ void orc3_destroy(orc3_sim* s) {
                     s->Tpsi, s->rho, s->ux, s->uy, s->uz, s->pr, s->Fx, s->Fy, s->Fz, s->grx, s->gry, s->grz, s->Rphi,
                     s->Rpsi, s->vx, s->vy, s->vz, s->Jphi_b, s->Jpsi_b, s->Jphi_t, s->Jpsi_t};
   for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); ++k) free(ptrs[k]);
+  free(s->solid);
   free(s);
 }
 
@@ -390,7 +428,7 @@ static void macro(orc3_sim* s) {
     for (int i = 0; i < Q; ++i) { a += s->g[(size_t)i * N + n]; b += s->h[(size_t)i * N + n]; }
     s->phi[n] = a;
     s->psi[n] = s->surf ? b : 0.0;
-    s->rho[n] = rho_of(s, a);
+    s->rho[n] = rho_of(s, a);   /* solid nodes: zero populations, never read as fluid */
   }
   /* O2: wall fluxes at the first fluid layer of each wetting wall */
   for (int c = 0; c < cols; ++c) {
@@ -412,12 +450,15 @@ static void macro(orc3_sim* s) {
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         int n = idx(s, x, y, z);
+        if (is_solid(s, n)) { s->mu_phi[n] = s->mu_psi[n] = s->Tphi[n] = s->Tpsi[n] = s->lap0_psi[n] = 0.0; continue; }
         double ph = s->phi[n], ps = s->psi[n], l0p = 0.0, l0s = 0.0;
         for (int i = 1; i < Q; ++i) {
           l0p += 2.0 * WQ[i] / CS2 * (nb_mirror(s, s->phi, x, y, z, i) - ph);
           l0s += 2.0 * WQ[i] / CS2 * (nb_mirror(s, s->psi, x, y, z, i) - ps);
         }
         double tp = wall_T(s, s->Jphi_b, s->Jphi_t, x, y, z), ts = wall_T(s, s->Jpsi_b, s->Jpsi_t, x, y, z);
+        tp += solid_T(s, x, y, z, wall_Jphi(s, ph, ps));
+        if (s->surf) ts += solid_T(s, x, y, z, wall_Jpsi(s, ph, ps));
         s->Tphi[n] = tp;
         s->Tpsi[n] = ts;
         s->lap0_psi[n] = l0s;
@@ -429,6 +470,7 @@ static void macro(orc3_sim* s) {
   /* O4 */
   double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
   for (int n = 0; n < N; ++n) {
+    if (is_solid(s, n)) continue;
     double hp = hprime(s, s->phi[n]);
     S1 += hp * s->mu_phi[n];
     S2 += hp * hp;
@@ -437,13 +479,18 @@ static void macro(orc3_sim* s) {
   }
   s->lambda = S2 > 0.0 ? S1 / S2 : 0.0;
   if (s->p.phi_hold && S2 > 0.0 && s->p.M_phi > 0.0) s->lambda += (s->m_ref - S4) / (s->p.M_phi * S2);
-  s->mubar = S3 / N;
+  s->mubar = S3 / s->Nf;
   /* O5, O6 */
 #pragma omp parallel for if (N >= PAR_MIN_NODES)
   for (int z = 0; z < nz; ++z)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         int n = idx(s, x, y, z);
+        if (is_solid(s, n)) {
+          s->grx[n] = s->gry[n] = s->grz[n] = s->Fx[n] = s->Fy[n] = s->Fz[n] = 0.0;
+          s->ux[n] = s->uy[n] = s->uz[n] = s->pr[n] = 0.0;
+          continue;
+        }
         double gr[3] = {0, 0, 0}, gmp[3] = {0, 0, 0}, gms[3] = {0, 0, 0};
         for (int i = 1; i < Q; ++i) {
           double r = nb_rho(s, x, y, z, i);
@@ -478,6 +525,7 @@ static void step_once(orc3_sim* s) {
   /* O7 */
   double sumR = 0.0, orth = 0.0;
   for (int n = 0; n < N; ++n) {
+    if (is_solid(s, n)) { s->Rphi[n] = s->Rpsi[n] = 0.0; continue; }
     double ph = s->phi[n], ps = s->psi[n], hp = hprime(s, ph);
     s->Rphi[n] = s->p.M_phi * (-4.0 * s->beta * (1.0 - ps) * (ph * ph * ph - ph) - s->W * ps * ph + s->lambda * hp)
                + s->p.M_phi * s->Tphi[n];
@@ -494,6 +542,7 @@ static void step_once(orc3_sim* s) {
   /* O8 */
 #pragma omp parallel for if (N >= PAR_MIN_NODES)
   for (int n = 0; n < N; ++n) {
+    if (is_solid(s, n)) continue;
     double ph = s->phi[n], ps = s->psi[n], rho = s->rho[n], u[3] = {s->ux[n], s->uy[n], s->uz[n]};
     double x[Q], xe[Q], v[Q], out[Q], rates[Q];
     double vv[3] = {u[0], u[1], u[2]};
@@ -554,9 +603,20 @@ static void step_once(orc3_sim* s) {
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         int n = idx(s, x, y, z);
+        if (is_solid(s, n)) {
+          for (int i = 0; i < Q; ++i) s->fn[(size_t)i * N + n] = s->gn[(size_t)i * N + n] = s->hn[(size_t)i * N + n] = 0.0;
+          continue;
+        }
         for (int i = 0; i < Q; ++i) {
           size_t src = (size_t)i * N + n;
           int xx = wrapi(x + CV[i][0], nx), yy = wrapi(y + CV[i][1], ny), zz = z + CV[i][2];
+          if ((s->periodic_z || (zz >= 0 && zz < nz)) && is_solid(s, idx(s, xx, yy, wrapi(zz, nz)))) {
+            /* half-way bounce-back at a solid node (at rest) */
+            s->fn[(size_t)OPP[i] * N + n] = s->f[src];
+            s->gn[(size_t)OPP[i] * N + n] = s->g[src];
+            s->hn[(size_t)OPP[i] * N + n] = s->h[src];
+            continue;
+          }
           if (s->periodic_z || (zz >= 0 && zz < nz)) {
             size_t dst = (size_t)i * N + idx(s, xx, yy, wrapi(zz, nz));
             s->fn[dst] = s->f[src];
@@ -586,6 +646,25 @@ static void step_once(orc3_sim* s) {
   s->step += 1;
 }
 
+int orc3_set_solid(orc3_sim* s, const unsigned char* mask) {
+  int nf = 0;
+  for (int n = 0; n < s->N; ++n) nf += mask[n] ? 0 : 1;
+  if (nf == 0) return -1;
+  if (!s->solid) s->solid = (unsigned char*)calloc((size_t)s->N, 1);
+  for (int n = 0; n < s->N; ++n) s->solid[n] = mask[n] ? 1 : 0;
+  s->Nf = nf;
+  /* rebuild the state from the current fields, fluid nodes only */
+  double* ph = zalloc(s->N);
+  double* ps = zalloc(s->N);
+  macro(s);
+  memcpy(ph, s->phi, (size_t)s->N * sizeof(double));
+  memcpy(ps, s->psi, (size_t)s->N * sizeof(double));
+  orc3_load_fields(s, ph, ps, NULL);
+  free(ph);
+  free(ps);
+  return 0;
+}
+
 void orc3_step(orc3_sim* s, int64_t n) {
   for (int64_t k = 0; k < n; ++k) step_once(s);
 }
@@ -603,6 +682,7 @@ void orc3_invariants(orc3_sim* s, orc3_inv* out) {
   memset(out, 0, sizeof(*out));
   out->step = s->step;
   for (int n = 0; n < s->N; ++n) {
+    if (is_solid(s, n)) continue;
     double ph = s->phi[n], ps = s->psi[n], u2 = s->ux[n] * s->ux[n] + s->uy[n] * s->uy[n] + s->uz[n] * s->uz[n];
     if (!isfinite(ph) || !isfinite(ps) || !isfinite(u2) || !isfinite(s->pr[n])) out->nonfinite++;
     if (s->surf && !(ps > 0.0 && ps < 1.0)) out->psi_out_of_range++;

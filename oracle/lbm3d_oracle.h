@@ -36,6 +36,7 @@ typedef struct {
   int32_t init_kind;
   int32_t adv_raw;               /* 1: advect with u(n); 0: with (u(n) + u(n-1))/2 */
   int32_t phi_hold;              /* 1: lambda also returns sum h_phi to its initial value */
+  int32_t solid_wet;             /* 1: solid nodes (orc3_set_solid) carry the wetting and adsorption BCs */
   double sigma_gl0, eps, M_phi, M_psi, lambda_s, kBT, W, Ex, Pi, psi_b, phi_b;
   double theta0_deg, sigma_sg0, sigma_sl0, beta_sg, beta_sl;
   double rho_l, rho_g, mu_l, mu_g;
@@ -66,6 +67,10 @@ void      orc3_invariants(orc3_sim* s, orc3_inv* out);
 /* Replace phi, psi (and u, may be NULL: three planes ux, uy, uz) by
  * equilibrium populations; the history restarts. */
 void      orc3_load_fields(orc3_sim* s, const double* phi, const double* psi, const double* u);
+/* Mark solid nodes (mask[N], nonzero = solid) and rebuild equilibrium
+ * populations from the current phi, psi at the fluid nodes (history restarts).
+ * Returns -1 if no fluid node is left. */
+int       orc3_set_solid(orc3_sim* s, const unsigned char* mask);
 /* Populations of the current state: 57 planes [f0..f18, g0..g18, h0..h18]. */
 void      orc3_get_populations(const orc3_sim* s, double* out);
 /* The velocity set in the oracle's own order (19 x 3 ints) and weights. */
