@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define LBM3D_ABI_VERSION 1
+#define LBM3D_ABI_VERSION 2
 
 typedef struct lbm3d_handle lbm3d_handle; /* opaque, owned by the library */
 
@@ -55,7 +55,8 @@ typedef struct {
   int32_t init_kind;        /* LBM_INIT_DROP (sphere), _SLAB (|x - x0| < a/2), _BUBBLE */
   int32_t adv_raw;          /* 0: two-step mean advecting velocity; 1: the step's own */
   int32_t phi_hold;         /* 1: lambda also returns sum h_phi to its initial value */
-  int32_t reserved;         /* must be 0 */
+  int32_t solid_wet;        /* 1: solid nodes (lbm3d_set_solid) carry the wetting and adsorption
+                               conditions of theta0, beta_sg, beta_sl; 0: neutral no-flux solids */
   double sigma_gl0, eps, M_phi, M_psi, lambda_s, kBT, W, Ex, Pi, psi_b, phi_b;
   double theta0_deg, sigma_sg0, sigma_sl0, beta_sg, beta_sl;
   double rho_l, rho_g, mu_l, mu_g;
@@ -106,6 +107,17 @@ int lbm3d_fetch_fields(lbm3d_handle* h, uint32_t mask, double* host, size_t n_do
  * u (host: [2 or 5][nz][ny][nx] FP64: phi, psi[, ux, uy, uz]); p = 0, the
  * history restarts and phi_hold's reference becomes this state's sum. */
 int lbm3d_load_fields(lbm3d_handle* h, int32_t with_u, const double* host, size_t n_doubles);
+
+/* Complex walls: mark solid nodes (mask[nz][ny][nx], nonzero = solid; n at
+ * least nx ny nz; caller-owned, read once).  A link from a fluid node into a
+ * solid node is a half-way bounce-back wall for all three lattices; the
+ * stencils see a ghost value there taken at the fluid node itself, link by link
+ * (mirror values for psi and the potentials; with solid_wet, phi + J_phi/kappa
+ * and the wall term (2 w_i / c_s^2) J of eq. "boundary" per link), and sums and
+ * the mean potential run over fluid nodes.  The state is rebuilt as equilibrium
+ * populations of the current phi, psi at the fluid nodes (history restarts,
+ * phi_hold's reference is retaken).  LBM_E_ARG if no fluid node is left. */
+int lbm3d_set_solid(lbm3d_handle* h, const uint8_t* mask, size_t n);
 
 /* Bytes of HBM state one step moves per node by design (all four kernels). */
 int lbm3d_bytes_per_node_step(lbm3d_handle* h, double* bytes);

@@ -18,6 +18,12 @@
 // The rest populations of g and h are stored shifted by the phi, psi of the
 // step that wrote them (read back from the FP64 plane pair that then holds
 // the previous step's values), so FP32 storage rounds only the increments.
+// Complex walls: nodes marked solid (lbm3d_set_solid) hold no fluid; a link
+// from a fluid node x into a solid node is a half-way bounce-back wall for all
+// three lattices, and the stencils see a ghost value there taken at x itself
+// (mirror psi, mu; on wetting solids phi(x) + J_phi(x)/kappa, and the wall term
+// (2 w_i / c_s^2) J(x) per link), the link-wise form of the flat walls' ghost
+// layer.  Sums and the mean potential run over fluid nodes.
 // The MRT transform uses the closed form of the D3Q19 raw-moment basis: the
 // four edge populations of a coordinate plane (a, b) follow from the moments
 // c_a^2 c_b^2, c_a c_b^2, c_a^2 c_b and c_a c_b; the two face populations of
@@ -27,6 +33,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include <hip/hip_runtime.h>
 
@@ -67,6 +74,7 @@ constexpr double kCs2 = 1.0 / 3.0;
 
 struct P3 {
   int nx, ny, nz, N, periodic_z, wet_b, wet_t, freeslip_b, freeslip_t, surf, linear, adv_raw, s2_local, phi_hold;
+  int has_solid, solid_wet, Nf;   // solid mask present; solids carry the wetting BCs; fluid nodes
   double kappa, beta, W, kBT, phib, lambda_s, M0, M_phi, M_psi, eta_phi, eta_psi;
   double rho_l, rho_g, mu_l, mu_g, gx, gy, gz, uw_b, uw_t;
   double sig_cos, dsb, msb;   // sigma cos(theta0), sigma_sg0 beta_sg -/+ sigma_sl0 beta_sl
@@ -91,6 +99,7 @@ struct St3 {
   double* stage;     // FP64 staging [9][N]
   double* inv_out;   // [8]
   P3* dp;            // device copy of the parameters
+  unsigned char* solid;  // [N] 1 = solid node
 };
 
 __device__ __forceinline__ double liquid_frac(const P3& p, double ph) {
@@ -122,14 +131,18 @@ __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >=
 // Neighbour of (x, y, z) along direction i: node index, or -1 / -2 beyond the
 // bottom / top wall; *colnode is the node of the same (x, y) column in the
 // layer of (x, y, z).
-__device__ __forceinline__ int nbr(const P3& p, int x, int y, int z, int i, int* colnode) {
+// -3: the neighbour is a solid node (complex walls).
+__device__ __forceinline__ int nbr(const P3& p, const unsigned char* __restrict__ solid, int x, int y, int z, int i,
+                                   int* colnode) {
   const int xx = wrap(x + cx3(i), p.nx), yy = wrap(y + cy3(i), p.ny);
   int zz = z + cz3(i);
   *colnode = (z * p.ny + yy) * p.nx + xx;
   if (p.periodic_z) zz = wrap(zz, p.nz);
   else if (zz < 0) return -1;
   else if (zz >= p.nz) return -2;
-  return (zz * p.ny + yy) * p.nx + xx;
+  const int m = (zz * p.ny + yy) * p.nx + xx;
+  if (p.has_solid && solid[m]) return -3;
+  return m;
 }
 
 template <class S>
@@ -152,24 +165,34 @@ __device__ double block_sum(double v, double* sh) {
 // mu_psi = kBT ln(psi/(1-psi)) - lambda_s L0 psi - T_psi - beta (1-phi^2)^2 + W phi^2 / 2
 // with L0 the Laplacian with mirror ghosts and T the wall term of each
 // direction pointing into a wetting wall: (2 w_i / c_s^2) J(column).
-__global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const double* __restrict__ pp,
-                                            double* __restrict__ mu, double* __restrict__ part) {
+__global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
+                                            const double* __restrict__ pp, double* __restrict__ mu,
+                                            double* __restrict__ part) {
   const P3& p = *pp_;
   __shared__ double sh[4][kT / 64];
   const int N = p.N;
   double s1 = 0, s2 = 0, s3 = 0, s4 = 0;
   for (int n = blockIdx.x * kT + threadIdx.x; n < N; n += gridDim.x * kT) {
+    if (p.has_solid && solid[n]) {
+      mu[n] = mu[N + n] = 0.0;
+      continue;
+    }
     const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
     const double ph = pp[n], ps = pp[N + n];
     double l0p = 0.0, l0s = 0.0, tp = 0.0, ts = 0.0;
 #pragma unroll
     for (int i = 1; i < Q3; ++i) {
       int cn;
-      const int m = nbr(p, x, y, z, i, &cn);
+      const int m = nbr(p, solid, x, y, z, i, &cn);
       const double wt = 2.0 * w3(i) / kCs2;
       if (m >= 0) {
         l0p += wt * (pp[m] - ph);
         l0s += wt * (pp[N + m] - ps);
+      } else if (m == -3) {   // solid node: link-wise mirror, wall flux of this node
+        if (p.solid_wet) {
+          tp += wt * wall_jphi(p, ph, ps);
+          ts += wt * wall_jpsi(p, ph, ps);
+        }
       } else {
         l0p += wt * (pp[cn] - ph);
         l0s += wt * (pp[N + cn] - ps);
@@ -215,7 +238,7 @@ __global__ __launch_bounds__(kT) void k3_fin(const P3* __restrict__ pp_, const d
   double lam = S2 > 0.0 ? S1 / S2 : 0.0;
   if (p.phi_hold && S2 > 0.0 && p.M_phi > 0.0) lam += (p.m_ref - S4) / (p.M_phi * S2);
   sc->lambda = lam;
-  sc->mubar = S3 / p.N;
+  sc->mubar = S3 / p.Nf;
 }
 
 // ------------------------------------------------------ MRT, closed form
@@ -299,8 +322,8 @@ struct Macro3 {
   double ph, ps, rho, gr[3], F[3], u[3], pr, tphi, tpsi, l0s;
 };
 template <class S>
-__device__ Macro3 macro3(const P3& p, const S* __restrict__ pop, const double* __restrict__ pp,
-                         const double* __restrict__ mu, int n) {
+__device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, const S* __restrict__ pop,
+                         const double* __restrict__ pp, const double* __restrict__ mu, int n) {
   Macro3 M;
   const int N = p.N;
   const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
@@ -311,13 +334,23 @@ __device__ Macro3 macro3(const P3& p, const S* __restrict__ pop, const double* _
 #pragma unroll
   for (int i = 1; i < Q3; ++i) {
     int cn;
-    const int m = nbr(p, x, y, z, i, &cn);
+    const int m = nbr(p, solid, x, y, z, i, &cn);
     double r, mp, ms, pn;
     if (m >= 0) {
       r = rho_of(p, pp[m]);
       mp = mu[m];
       ms = mu[N + m];
       pn = pp[N + m];
+    } else if (m == -3) {   // solid node: ghost values of this node
+      const double jp = p.solid_wet ? wall_jphi(p, M.ph, M.ps) : 0.0;
+      r = rho_of(p, M.ph + jp / p.kappa);
+      mp = mu[n];
+      ms = mu[N + n];
+      pn = M.ps;
+      if (p.solid_wet) {
+        tp += 2.0 * w3(i) / kCs2 * jp;
+        ts += 2.0 * w3(i) / kCs2 * wall_jpsi(p, M.ph, M.ps);
+      }
     } else {
       const bool wet = (m == -1 && p.wet_b) || (m == -2 && p.wet_t);
       const double fph = pp[cn], fps = pp[N + cn];
@@ -367,7 +400,8 @@ __device__ Macro3 macro3(const P3& p, const S* __restrict__ pop, const double* _
 
 // ---------------------------------------------------------------- k3_col
 template <class S>
-__global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const S* __restrict__ pin, S* __restrict__ pout,
+__global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
+                                             const S* __restrict__ pin, S* __restrict__ pout,
                                              const double* __restrict__ pp, const double* __restrict__ pprev,
                                              const double* __restrict__ mu, const double* __restrict__ hin,
                                              double* __restrict__ hout, const Scal3* __restrict__ sc, int have_hist) {
@@ -375,7 +409,8 @@ __global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const S
   const int N = p.N;
   const int n = blockIdx.x * kT + threadIdx.x;
   if (n >= N) return;
-  const Macro3 M = macro3(p, pin, pp, mu, n);
+  if (p.has_solid && solid[n]) return;   // no fluid; its population slots stay zero
+  const Macro3 M = macro3(p, solid, pin, pp, mu, n);
   const double ph = M.ph, ps = M.ps, rho = M.rho;
   const double lam = sc->lambda, mubar = sc->mubar;
   // sources (Sec. 3): R_phi with the multiplier term and the wall flux, R_psi likewise
@@ -434,8 +469,10 @@ __global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const S
     for (int i = 0; i < Q3; ++i) {
       const int zz = z + cz3(i);
       const int xx = wrap(x + cx3(i), p.nx), yy = wrap(y + cy3(i), p.ny);
-      if (p.periodic_z || (zz >= 0 && zz < p.nz)) {
-        const int t = (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx;
+      const int t = (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx;
+      if ((p.periodic_z || (zz >= 0 && zz < p.nz)) && p.has_solid && solid[t]) {
+        pout[(size_t)opp3(i) * N + n] = (S)f[i];   // half-way bounce-back at a solid node at rest
+      } else if (p.periodic_z || (zz >= 0 && zz < p.nz)) {
         pout[(size_t)i * N + t] = (S)f[i];
       } else {
         const bool bot = zz < 0;
@@ -455,7 +492,9 @@ __global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const S
       for (int i = 0; i < Q3; ++i) {   // idle surfactant lattice: keep zeros in the target buffer
         const int zz = z + cz3(i);
         const int xx = wrap(x + cx3(i), p.nx), yy = wrap(y + cy3(i), p.ny);
-        if (p.periodic_z || (zz >= 0 && zz < p.nz)) pout[(size_t)(38 + i) * N + (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx] = (S)0.0;
+        const int t = (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx;
+        const bool inside = p.periodic_z || (zz >= 0 && zz < p.nz);
+        if (inside && !(p.has_solid && solid[t])) pout[(size_t)(38 + i) * N + t] = (S)0.0;
         else pout[(size_t)(38 + opp3(i)) * N + n] = (S)0.0;
       }
       break;
@@ -480,7 +519,9 @@ __global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const S
       if (i == 0) val -= c;
       const int zz = z + cz3(i);
       const int xx = wrap(x + cx3(i), p.nx), yy = wrap(y + cy3(i), p.ny);
-      if (p.periodic_z || (zz >= 0 && zz < p.nz)) pout[(size_t)(base + i) * N + (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx] = (S)val;
+      const int t = (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx;
+      const bool inside = p.periodic_z || (zz >= 0 && zz < p.nz);
+      if (inside && !(p.has_solid && solid[t])) pout[(size_t)(base + i) * N + t] = (S)val;
       else pout[(size_t)(base + opp3(i)) * N + n] = (S)val;
     }
   }
@@ -490,12 +531,14 @@ __global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const S
 // phi, psi of the state just streamed: the moving populations plus the rest
 // population and its shift (phi, psi of the step that wrote it).
 template <class S>
-__global__ __launch_bounds__(kT) void k3_mom(const P3* __restrict__ pp_, const S* __restrict__ pop,
+__global__ __launch_bounds__(kT) void k3_mom(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
+                                             const S* __restrict__ pop,
                                              const double* __restrict__ pold, double* __restrict__ pnew) {
   const P3& p = *pp_;
   const int N = p.N;
   const int n = blockIdx.x * kT + threadIdx.x;
   if (n >= N) return;
+  if (p.has_solid && solid[n]) return;   // stays zero
   double a = 0.0, b = 0.0;
 #pragma unroll
   for (int i = 1; i < Q3; ++i) {
@@ -525,12 +568,19 @@ __global__ __launch_bounds__(kT) void k3_profile(const P3* __restrict__ pp_, dou
 // Equilibrium populations of staged phi, psi (and u) with p = 0; both plane
 // pairs take phi, psi (the rest populations are stored relative to them).
 template <class S>
-__global__ __launch_bounds__(kT) void k3_load(const P3* __restrict__ pp_, const double* __restrict__ stage, int with_u,
-                                              S* __restrict__ pop, double* __restrict__ pa, double* __restrict__ pb) {
+__global__ __launch_bounds__(kT) void k3_load(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
+                                              const double* __restrict__ stage, int with_u, S* __restrict__ pop,
+                                              S* __restrict__ pop2, double* __restrict__ pa, double* __restrict__ pb) {
   const P3& p = *pp_;
   const int N = p.N;
   const int n = blockIdx.x * kT + threadIdx.x;
   if (n >= N) return;
+  if (p.has_solid && solid[n]) {   // no fluid: zero populations in both buffers, zero fields
+#pragma unroll
+    for (int i = 0; i < 57; ++i) pop[(size_t)i * N + n] = pop2[(size_t)i * N + n] = (S)0.0;
+    pa[n] = pb[n] = pa[N + n] = pb[N + n] = 0.0;
+    return;
+  }
   const double ph = stage[n], ps = p.surf ? stage[N + n] : 0.0;
   const double u[3] = {with_u ? stage[2 * (size_t)N + n] : 0.0, with_u ? stage[3 * (size_t)N + n] : 0.0,
                        with_u ? stage[4 * (size_t)N + n] : 0.0};
@@ -552,14 +602,19 @@ __global__ __launch_bounds__(kT) void k3_load(const P3* __restrict__ pp_, const 
 // Fields of the current state into the staging planes:
 // phi, psi, ux, uy, uz, p, rho, mu_phi, mu_psi.
 template <class S>
-__global__ __launch_bounds__(kT) void k3_fields(const P3* __restrict__ pp_, const S* __restrict__ pop,
-                                                const double* __restrict__ pp, const double* __restrict__ mu,
-                                                double* __restrict__ stage) {
+__global__ __launch_bounds__(kT) void k3_fields(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
+                                                const S* __restrict__ pop, const double* __restrict__ pp,
+                                                const double* __restrict__ mu, double* __restrict__ stage) {
   const P3& p = *pp_;
   const int N = p.N;
   const int n = blockIdx.x * kT + threadIdx.x;
   if (n >= N) return;
-  const Macro3 M = macro3(p, pop, pp, mu, n);
+  if (p.has_solid && solid[n]) {   // fields of a solid node: zero
+#pragma unroll
+    for (int k = 0; k < 9; ++k) stage[(size_t)k * N + n] = 0.0;
+    return;
+  }
+  const Macro3 M = macro3(p, solid, pop, pp, mu, n);
   const double v[9] = {M.ph, M.ps, M.u[0], M.u[1], M.u[2], M.pr, M.rho, mu[n], mu[N + n]};
 #pragma unroll
   for (int k = 0; k < 9; ++k) stage[(size_t)k * N + n] = v[k];
@@ -567,14 +622,15 @@ __global__ __launch_bounds__(kT) void k3_fields(const P3* __restrict__ pp_, cons
 
 // Invariant sums from the staged fields: mass_psi, m_phi_h, sum_phi, kinetic,
 // umax (max), nonfinite, psi_out_of_range; per workgroup, then k3_inv_fin.
-__global__ __launch_bounds__(kT) void k3_inv(const P3* __restrict__ pp_, const double* __restrict__ stage,
-                                             double* __restrict__ part) {
+__global__ __launch_bounds__(kT) void k3_inv(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
+                                             const double* __restrict__ stage, double* __restrict__ part) {
   const P3& p = *pp_;
   __shared__ double sh[6][kT / 64];
   __shared__ double smax[kT];
   const int N = p.N;
   double a[6] = {0, 0, 0, 0, 0, 0}, um = 0.0;
   for (int n = blockIdx.x * kT + threadIdx.x; n < N; n += gridDim.x * kT) {
+    if (p.has_solid && solid[n]) continue;
     const double ph = stage[n], ps = stage[N + n], ux = stage[2 * (size_t)N + n], uy = stage[3 * (size_t)N + n],
                  uz = stage[4 * (size_t)N + n], pr = stage[5 * (size_t)N + n], rho = stage[6 * (size_t)N + n];
     const double u2 = ux * ux + uy * uy + uz * uz;
@@ -656,12 +712,14 @@ std::string derive3(const lbm3d_params& q, P3& d) {
   if (q.precision != LBM_FP64 && q.precision != LBM_FP32) return "precision must be LBM_FP64 or LBM_FP32";
   if (q.constraint_phi != LBM_CONSTRAINT_NONLINEAR && q.constraint_phi != LBM_CONSTRAINT_LINEAR) return "unknown constraint";
   if (q.init_kind < LBM_INIT_DROP || q.init_kind > LBM_INIT_BUBBLE) return "unknown init kind";
-  if ((q.adv_raw != 0 && q.adv_raw != 1) || (q.phi_hold != 0 && q.phi_hold != 1) || q.reserved != 0) return "bad switch value";
+  if ((q.adv_raw != 0 && q.adv_raw != 1) || (q.phi_hold != 0 && q.phi_hold != 1) || (q.solid_wet != 0 && q.solid_wet != 1))
+    return "adv_raw, phi_hold and solid_wet must be 0 or 1";
+  if (q.solid_wet && !(q.theta0_deg > 0.0 && q.theta0_deg < 180.0)) return "theta0 must lie in (0,180) on wetting solids";
   if (!(q.sigma_gl0 > 0.0) || !(q.eps > 0.0)) return "sigma_gl0 and eps must be > 0";
   if (!(q.M_phi >= 0.0) || !(q.M_psi >= 0.0)) return "mobilities must be >= 0";
   if (!(q.psi_b >= 0.0 && q.psi_b < 1.0)) return "psi_b must lie in [0,1)";
   if (!(q.rho_l > 0.0 && q.rho_g > 0.0 && q.mu_l > 0.0 && q.mu_g > 0.0)) return "densities and viscosities must be > 0";
-  const bool wet = q.bc_bottom == LBM_BC_WALL_WET || q.bc_top == LBM_BC_WALL_WET;
+  const bool wet = q.bc_bottom == LBM_BC_WALL_WET || q.bc_top == LBM_BC_WALL_WET || q.solid_wet;
   if (wet && !(q.theta0_deg > 0.0 && q.theta0_deg < 180.0)) return "theta0 must lie in (0,180) on a wetting wall";
   const double* rates[3] = {q.s_f, q.s_g, q.s_h};
   for (int l = 0; l < 3; ++l)
@@ -678,6 +736,9 @@ std::string derive3(const lbm3d_params& q, P3& d) {
   d.linear = q.constraint_phi == LBM_CONSTRAINT_LINEAR;
   d.adv_raw = q.adv_raw;
   d.phi_hold = q.phi_hold;
+  d.solid_wet = q.solid_wet;
+  d.has_solid = 0;
+  d.Nf = d.N;
   const double kappa = 0.375 * q.eps * q.sigma_gl0, beta = 0.75 * q.sigma_gl0 / q.eps;
   const double W = q.W > 0.0 ? q.W : 4.0 * beta / (q.Ex > 0.0 ? q.Ex : 0.5);
   const double kBT = q.kBT > 0.0 ? q.kBT : 4.0 * beta * (q.Pi > 0.0 ? q.Pi : 1.35);
@@ -719,7 +780,7 @@ std::string derive3(const lbm3d_params& q, P3& d) {
 }
 
 struct Lay3 {
-  size_t pops, pp, mu, uh, part, sc, stage, inv, dp, total;
+  size_t pops, pp, mu, uh, part, sc, stage, inv, dp, solid, total;
 };
 Lay3 layout3(const lbm3d_params& q) {
   const size_t N = (size_t)q.nx * q.ny * q.nz, sb = q.precision == LBM_FP64 ? 8 : 4;
@@ -735,6 +796,7 @@ Lay3 layout3(const lbm3d_params& q) {
   L.stage = take(9 * N * 8);
   L.inv = take(8 * 8);
   L.dp = take(sizeof(P3));
+  L.solid = take(N);
   L.total = off;
   return L;
 }
@@ -745,12 +807,15 @@ hipError_t step3(lbm3d_handle* h) {
   St3& s = h->s;
   const int c = h->cur;
   const int rb = red_blocks(p.N);
-  hipLaunchKernelGGL(k3_mu, dim3(rb), dim3(kT), 0, h->stream, s.dp, (const double*)s.pp[c], s.mu, s.part);
+  hipLaunchKernelGGL(k3_mu, dim3(rb), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid, (const double*)s.pp[c],
+                     s.mu, s.part);
   hipLaunchKernelGGL(k3_fin, dim3(1), dim3(64), 0, h->stream, s.dp, (const double*)s.part, rb, s.sc);
-  hipLaunchKernelGGL((k3_col<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const S*)s.pops[c], (S*)s.pops[c ^ 1],
+  hipLaunchKernelGGL((k3_col<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
+                     (const S*)s.pops[c], (S*)s.pops[c ^ 1],
                      (const double*)s.pp[c], (const double*)s.pp[c ^ 1], (const double*)s.mu, (const double*)s.uh[c ^ 1],
                      s.uh[c], (const Scal3*)s.sc, h->have_hist);
-  hipLaunchKernelGGL((k3_mom<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const S*)s.pops[c ^ 1],
+  hipLaunchKernelGGL((k3_mom<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
+                     (const S*)s.pops[c ^ 1],
                      (const double*)s.pp[c], s.pp[c ^ 1]);
   return hipGetLastError();
 }
@@ -762,9 +827,11 @@ hipError_t fields3(lbm3d_handle* h) {
   St3& s = h->s;
   const int c = h->cur;
   const int rb = red_blocks(p.N);
-  hipLaunchKernelGGL(k3_mu, dim3(rb), dim3(kT), 0, h->stream, s.dp, (const double*)s.pp[c], s.mu, s.part);
+  hipLaunchKernelGGL(k3_mu, dim3(rb), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid, (const double*)s.pp[c],
+                     s.mu, s.part);
   hipLaunchKernelGGL(k3_fin, dim3(1), dim3(64), 0, h->stream, s.dp, (const double*)s.part, rb, s.sc);
-  hipLaunchKernelGGL((k3_fields<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const S*)s.pops[c],
+  hipLaunchKernelGGL((k3_fields<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
+                     (const S*)s.pops[c],
                      (const double*)s.pp[c], (const double*)s.mu, s.stage);
   return hipGetLastError();
 }
@@ -773,11 +840,11 @@ hipError_t load3(lbm3d_handle* h, int with_u) {
   St3& s = h->s;
   const int c = h->cur;
   if (h->prm.precision == LBM_FP64)
-    hipLaunchKernelGGL((k3_load<double>), dim3(nblk(h->p.N)), dim3(kT), 0, h->stream, s.dp, (const double*)s.stage, with_u,
-                       (double*)s.pops[c], s.pp[c], s.pp[c ^ 1]);
+    hipLaunchKernelGGL((k3_load<double>), dim3(nblk(h->p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
+                       (const double*)s.stage, with_u, (double*)s.pops[c], (double*)s.pops[c ^ 1], s.pp[c], s.pp[c ^ 1]);
   else
-    hipLaunchKernelGGL((k3_load<float>), dim3(nblk(h->p.N)), dim3(kT), 0, h->stream, s.dp, (const double*)s.stage, with_u,
-                       (float*)s.pops[c], s.pp[c], s.pp[c ^ 1]);
+    hipLaunchKernelGGL((k3_load<float>), dim3(nblk(h->p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
+                       (const double*)s.stage, with_u, (float*)s.pops[c], (float*)s.pops[c ^ 1], s.pp[c], s.pp[c ^ 1]);
   return hipGetLastError();
 }
 
@@ -786,7 +853,8 @@ hipError_t load3(lbm3d_handle* h, int with_u) {
 int invariants3(lbm3d_handle* h, double* v7, Scal3* sc) {
   HIP3(h, h->prm.precision == LBM_FP64 ? fields3<double>(h) : fields3<float>(h), "field kernels");
   const int rb = red_blocks(h->p.N);
-  hipLaunchKernelGGL(k3_inv, dim3(rb), dim3(kT), 0, h->stream, h->s.dp, (const double*)h->s.stage, h->s.part);
+  hipLaunchKernelGGL(k3_inv, dim3(rb), dim3(kT), 0, h->stream, h->s.dp, (const unsigned char*)h->s.solid,
+                     (const double*)h->s.stage, h->s.part);
   hipLaunchKernelGGL(k3_inv_fin, dim3(1), dim3(64), 0, h->stream, (const double*)h->s.part, rb, h->s.inv_out);
   HIP3(h, hipGetLastError(), "invariant kernels");
   HIP3(h, hipMemcpyAsync(v7, h->s.inv_out, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy invariants");
@@ -865,7 +933,9 @@ int lbm3d_init(const lbm3d_params* q, void* dev_buf, size_t buf_bytes, void* hip
   h->s.stage = (double*)(b + L.stage);
   h->s.inv_out = (double*)(b + L.inv);
   h->s.dp = (P3*)(b + L.dp);
-  hipError_t e = hipMemcpyAsync(h->s.dp, &h->p, sizeof(P3), hipMemcpyHostToDevice, h->stream);
+  h->s.solid = (unsigned char*)(b + L.solid);
+  hipError_t e = hipMemsetAsync(h->s.solid, 0, N, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->s.dp, &h->p, sizeof(P3), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k3_profile, dim3(nblk(h->p.N)), dim3(kT), 0, h->stream, h->s.dp, h->s.stage);
     e = load3(h, 0);
@@ -937,6 +1007,31 @@ int lbm3d_load_fields(lbm3d_handle* h, int32_t with_u, const double* host, size_
   if (n_doubles < planes * N) return fail3(h, LBM_E_ARG, "host buffer too small");
   HIP3(h, hipMemcpyAsync(h->s.stage, host, planes * N * sizeof(double), hipMemcpyHostToDevice, h->stream), "copy fields");
   HIP3(h, load3(h, with_u ? 1 : 0), "load kernel");
+  HIP3(h, hipStreamSynchronize(h->stream), "synchronise");
+  h->have_hist = 0;
+  h->faulted = false;
+  return set_ref3(h);
+}
+
+int lbm3d_set_solid(lbm3d_handle* h, const uint8_t* mask, size_t n) {
+  if (!h || !mask) return fail3(h, LBM_E_ARG, "null argument");
+  const size_t N = (size_t)h->p.N;
+  if (n < N) return fail3(h, LBM_E_ARG, "mask smaller than nx ny nz");
+  int nf = 0, any = 0;
+  for (size_t k = 0; k < N; ++k) {
+    nf += mask[k] ? 0 : 1;
+    any |= mask[k] ? 1 : 0;
+  }
+  if (nf == 0) return fail3(h, LBM_E_ARG, "no fluid node left");
+  // the current phi, psi (fluid nodes) are rebuilt into equilibrium populations under the new mask
+  HIP3(h, h->prm.precision == LBM_FP64 ? fields3<double>(h) : fields3<float>(h), "field kernels");
+  std::vector<unsigned char> m(N);
+  for (size_t k = 0; k < N; ++k) m[k] = mask[k] ? 1 : 0;
+  HIP3(h, hipMemcpyAsync(h->s.solid, m.data(), N, hipMemcpyHostToDevice, h->stream), "copy mask");
+  h->p.has_solid = any;
+  h->p.Nf = nf;
+  HIP3(h, hipMemcpyAsync(h->s.dp, &h->p, sizeof(P3), hipMemcpyHostToDevice, h->stream), "upload parameters");
+  HIP3(h, load3(h, 0), "load kernel");
   HIP3(h, hipStreamSynchronize(h->stream), "synchronise");
   h->have_hist = 0;
   h->faulted = false;

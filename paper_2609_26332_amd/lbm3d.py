@@ -13,10 +13,11 @@ import torch
 
 from . import lbm as _lbm
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 FIELD_NAMES = ["phi", "psi", "ux", "uy", "uz", "p", "rho", "mu_phi", "mu_psi"]
 EXPORTS = ["lbm3d_required_bytes", "lbm3d_init", "lbm3d_step", "lbm3d_reduce_invariants", "lbm3d_fetch_fields",
-           "lbm3d_load_fields", "lbm3d_bytes_per_node_step", "lbm3d_destroy", "lbm3d_last_error"]
+           "lbm3d_load_fields", "lbm3d_set_solid", "lbm3d_bytes_per_node_step", "lbm3d_destroy",
+           "lbm3d_last_error"]
 
 
 class Params3(ctypes.Structure):
@@ -24,7 +25,7 @@ class Params3(ctypes.Structure):
         ("abi_version", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("bc_bottom", ctypes.c_int32), ("bc_top", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("constraint_phi", ctypes.c_int32), ("init_kind", ctypes.c_int32), ("adv_raw", ctypes.c_int32),
-        ("phi_hold", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("phi_hold", ctypes.c_int32), ("solid_wet", ctypes.c_int32),
         ("sigma_gl0", ctypes.c_double), ("eps", ctypes.c_double), ("M_phi", ctypes.c_double),
         ("M_psi", ctypes.c_double), ("lambda_s", ctypes.c_double), ("kBT", ctypes.c_double), ("W", ctypes.c_double),
         ("Ex", ctypes.c_double), ("Pi", ctypes.c_double), ("psi_b", ctypes.c_double), ("phi_b", ctypes.c_double),
@@ -67,6 +68,7 @@ def lib():
         L.lbm3d_fetch_fields.argtypes = [vp, ctypes.c_uint32, dp, sz]
         L.lbm3d_load_fields.argtypes = [vp, ctypes.c_int32, dp, sz]
         L.lbm3d_bytes_per_node_step.argtypes = [vp, dp]
+        L.lbm3d_set_solid.argtypes = [vp, ctypes.c_char_p, sz]
         L.lbm3d_destroy.argtypes = [vp]
         L.lbm3d_last_error.argtypes = [vp]
         L.lbm3d_last_error.restype = ctypes.c_char_p
@@ -153,6 +155,11 @@ class Sim3:
         arr = np.ascontiguousarray(np.stack([np.asarray(a, dtype=np.float64) for a in planes]))
         _check(lib().lbm3d_load_fields(self._h, 1 if u is not None else 0,
                                        arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), arr.size), self._h)
+
+    def set_solid(self, mask):
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        assert m.shape == (self.nz, self.ny, self.nx)
+        _check(lib().lbm3d_set_solid(self._h, m.tobytes(), m.size), self._h)
 
     def bytes_per_node_step(self) -> float:
         b = ctypes.c_double()

@@ -113,3 +113,51 @@ def test_load_fields_and_errors_3d(lbm3d):
     assert iv["status"] == -5 and iv["nonfinite"] >= 1
     with pytest.raises(Exception):
         g.step(1)
+
+
+def _solid_cases():
+    rng = np.random.default_rng(1)
+    porous = (rng.random((16, 16, 16)) < 0.08).astype(np.uint8)
+    porous[6:11, 6:11, 6:11] = 0
+    nx, nz = 40, 32
+    z, y, x = np.mgrid[0:nz, 0:3, 0:nx].astype(float)
+    disc = ((x - 20.0) ** 2 + (z - 12.0) ** 2 <= 64.0).astype(np.uint8)
+    phi_disc = np.tanh(2.0 * (6.0 - np.sqrt((x - 20.0) ** 2 + (z - 22.0) ** 2)) / 4.0)
+    block = np.zeros((16, 24, 32), np.uint8)
+    block[:4, 8:16, 4:10] = 1
+    return {
+        "porous_adsorbing": (inputs.drop3d(16, 5.0, psi_b=0.02, solid_wet=1, theta0_deg=70.0, beta_sg=0.3,
+                                           beta_sl=0.01, lambda_s=0.0075, M0=0.0), porous, None),
+        "drop_on_disc": (inputs.drop3d(nx, 6.0, psi_b=0.01, ny=3, nz=nz, solid_wet=1, theta0_deg=60.0, beta_sg=0.2,
+                                       beta_sl=0.01, lambda_s=0.0075, M0=0.0), disc, phi_disc),
+        "neutral_block_on_wetting_floor": (inputs.sessile3d(), block, None),
+    }
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("name", ["porous_adsorbing", "drop_on_disc", "neutral_block_on_wetting_floor"])
+def test_parity_3d_solid_walls(lbm3d, name, prec, tol):
+    """Complex walls (lbm3d_set_solid): solid nodes with the link-wise bounce-back
+    and ghost values, wetting and adsorbing or neutral, against the oracle."""
+    cfg, mask, phi0 = _solid_cases()[name]
+    g = lbm3d.Sim3(cfg, prec)
+    o = oracle.Oracle3Sim(cfg)
+    if phi0 is not None:
+        psi0 = np.full_like(phi0, cfg["psi_b"])
+        g.load_fields(phi0, psi0)
+        o.load_fields(phi0, psi0)
+    g.set_solid(mask)
+    o.set_solid(mask)
+    fluid = mask == 0
+    done = 0
+    for c in (1, 10, 100):
+        g.step(c - done)
+        o.step(c - done)
+        done = c
+        gf, of = g.fields(FIELDS3), o.fields(FIELDS3)
+        e = errors({k: v * fluid for k, v in gf.items()}, {k: v * fluid for k, v in of.items()}, cfg)
+        bad = {k: v for k, v in e.items() if not v <= tol}
+        assert not bad, (name, prec, c, bad, e)
+    gi, oi = g.invariants(), o.invariants()
+    assert gi["mass_psi"] == pytest.approx(oi["mass_psi"], rel=tol, abs=1e-14)
+    assert gi["lambda_phi"] == pytest.approx(oi["lambda_phi"], rel=10 * tol, abs=1e-14)
