@@ -68,6 +68,16 @@ int mlp_loss_grad(mlp_handle* h, int32_t member, const float* x_dev, const float
 int mlp_train_step(mlp_handle* h, int32_t member, const float* x_dev, const float* t_dev, const float* m_dev, int32_t n,
                    float lr, float* loss_host);
 
+/* One training step of every member at once, each on its own batch of n
+ * samples (its bootstrap resample): x_dev[members][n][5], t_dev and
+ * m_dev[members][n][2].  Every product and reduction covers all members in one
+ * launch (member = grid z or y); per member the arithmetic is that of
+ * mlp_train_step on its own batch, so the parameters after the step equal, bit
+ * for bit, those of one mlp_train_step per member.  loss_host[members] (each
+ * member's loss before the update) may be NULL: then nothing synchronises. */
+int mlp_train_step_ensemble(mlp_handle* h, const float* x_dev, const float* t_dev, const float* m_dev, int32_t n,
+                            float lr, float* loss_host);
+
 /* Every member on the same n inputs; per sample and output the ensemble mean
  * and standard deviation (population, over members): mean_dev[n][2], std_dev[n][2]. */
 int mlp_predict_ensemble(mlp_handle* h, const float* x_dev, int32_t n, float* mean_dev, float* std_dev);

@@ -2,7 +2,8 @@
 // 5 -> 256 -> 256 -> 256 -> 2, exact GELU, ensemble of members.
 //
 // Every matrix product is one kernel, k_gemm: a 64 x 64 output tile per
-// workgroup of four waves, each wave a 32 x 32 block of 2 x 2 matrix-core
+// workgroup of four waves (grid z: ensemble members, each with its own
+// operand offsets, so the members train or predict in the same launches), each wave a 32 x 32 block of 2 x 2 matrix-core
 // tiles (v_mfma_f32_16x16x32_bf16: bfloat16 operands, FP32 accumulation),
 // operands staged through LDS with zero padding at the edges, strided so the
 // same kernel forms X W, dZ W^T and A^T dZ; epilogues add the bias and apply
@@ -56,6 +57,8 @@ struct Gemm {
   __bf16* Cb;        // bfloat16 copy: GELU(z) (EPI_BIAS_GELU) or the scaled result (EPI_DGELU)
   const float* bias; // [N]
   const float* Zp;   // EPI_DGELU: pre-activation multiplied in through GELU', same layout as C
+  // element offsets between consecutive members (blockIdx.z) of A, B, C / Cb / Zp and bias
+  long long zA, zB, zC, zbias;
 };
 
 constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;   // LDS rows padded to 80 bytes (16-byte aligned fragments)
@@ -65,6 +68,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm(Gemm g) {
   __shared__ __attribute__((aligned(16))) __bf16 Bs[TN][LDK];   // [n][k]: a lane's 8 k values are contiguous
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const long long z = blockIdx.z;
+  const __bf16* __restrict__ gA = g.A + z * g.zA;
+  const __bf16* __restrict__ gB = g.B + z * g.zB;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
   f32x4 acc[2][2];
   for (int i = 0; i < 2; ++i)
@@ -75,8 +81,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(Gemm g) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int k = k0 + kq + j;
-      As[r][kq + j] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : (__bf16)0.0f;
-      Bs[r][kq + j] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : (__bf16)0.0f;
+      As[r][kq + j] = (m < g.M && k < g.K) ? gA[m * g.sam + k * g.sak] : (__bf16)0.0f;
+      Bs[r][kq + j] = (n < g.N && k < g.K) ? gB[k * g.sbk + n * g.sbn] : (__bf16)0.0f;
     }
     __syncthreads();
     // matrix-core fragments: lane l holds row (l mod 16) and k = 8 (l / 16) .. +7
@@ -91,6 +97,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm(Gemm g) {
     __syncthreads();
   }
   // result tile: lane l holds column (l mod 16), rows 4 (l / 16) .. +3
+  float* __restrict__ gC = g.C + z * g.zC;
+  __bf16* __restrict__ gCb = g.Cb ? g.Cb + z * g.zC : nullptr;
+  const float* __restrict__ gbias = g.bias ? g.bias + z * g.zbias : nullptr;
+  const float* __restrict__ gZp = g.Zp ? g.Zp + z * g.zC : nullptr;
 #pragma unroll
   for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
@@ -102,17 +112,17 @@ __global__ __launch_bounds__(kThreads) void k_gemm(Gemm g) {
         const long long at = m * g.scm + n;
         float v = acc[bm][bn][j];
         if (g.epi == EPI_BIAS_GELU) {
-          v += g.bias[n];
-          g.C[at] = v;
-          g.Cb[at] = (__bf16)gelu(v);
+          v += gbias[n];
+          gC[at] = v;
+          gCb[at] = (__bf16)gelu(v);
         } else if (g.epi == EPI_BIAS) {
-          g.C[at] = v + g.bias[n];
+          gC[at] = v + gbias[n];
         } else if (g.epi == EPI_DGELU) {
-          v *= gelu_d(g.Zp[at]);
-          g.C[at] = v;
-          g.Cb[at] = (__bf16)v;
+          v *= gelu_d(gZp[at]);
+          gC[at] = v;
+          gCb[at] = (__bf16)v;
         } else {
-          g.C[at] = v;
+          gC[at] = v;
         }
       }
 }
@@ -134,18 +144,29 @@ __device__ float block_sum(float v) {
   return r;   // valid in thread 0
 }
 
-// 1 / max(sum of the mask, 1), one workgroup
+// 1 / max(sum of the mask, 1), one workgroup per member (blockIdx.x)
 __global__ __launch_bounds__(kThreads) void k_mask_norm(const float* __restrict__ m, int n2, float* __restrict__ inv) {
+  m += (long long)blockIdx.x * n2;
+  inv += blockIdx.x;
   float s = 0.f;
   for (int i = threadIdx.x; i < n2; i += kThreads) s += m[i];
   s = block_sum(s);
   if (threadIdx.x == 0) *inv = 1.0f / fmaxf(s, 1.0f);
 }
 
-// dY = 2 m (y - t) / sum(m) in FP32 and bfloat16; per-workgroup partial sums of m (y - t)^2
+// dY = 2 m (y - t) / sum(m) in FP32 and bfloat16; per-workgroup partial sums
+// of m (y - t)^2 (member blockIdx.y; its arrays n2 apart, its partials kRed apart)
 __global__ __launch_bounds__(kThreads) void k_dy(const float* __restrict__ y, const float* __restrict__ t,
                                                  const float* __restrict__ m, int n2, const float* __restrict__ inv,
                                                  float* __restrict__ dy, __bf16* __restrict__ dyb, float* __restrict__ part) {
+  const long long zo = (long long)blockIdx.y * n2;
+  y += zo;
+  t += zo;
+  m += zo;
+  dy += zo;
+  dyb += zo;
+  inv += blockIdx.y;
+  part += (long long)blockIdx.y * kRed;
   float s = 0.f;
   const float sc = 2.0f * *inv;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < n2; i += gridDim.x * kThreads) {
@@ -161,27 +182,47 @@ __global__ __launch_bounds__(kThreads) void k_dy(const float* __restrict__ y, co
 
 __global__ __launch_bounds__(kThreads) void k_loss_final(const float* __restrict__ part, int nb, const float* __restrict__ inv,
                                                          float* __restrict__ loss) {
+  part += (long long)blockIdx.x * nb;
+  inv += blockIdx.x;
+  loss += blockIdx.x;
   float s = 0.f;
   for (int i = threadIdx.x; i < nb; i += kThreads) s += part[i];
   s = block_sum(s);
   if (threadIdx.x == 0) *loss = s * *inv;
 }
 
-// db[j] = sum over rows of dz[row][j]
+// db[j] = sum over rows of dz[row][j] (member blockIdx.y: dz rows * cols apart, db kParams apart)
 __global__ __launch_bounds__(kThreads) void k_colsum(const float* __restrict__ dz, int rows, int cols, float* __restrict__ db) {
   const int j = blockIdx.x * kThreads + threadIdx.x;
   if (j >= cols) return;
+  dz += (long long)blockIdx.y * rows * cols;
+  db += (long long)blockIdx.y * kParams;
   float s = 0.f;
   for (int i = 0; i < rows; ++i) s += dz[(long long)i * cols + j];
   db[j] = s;
 }
 
-// Adam on the FP32 master parameters, then their bfloat16 copy
+// Bias corrections 1 - beta^t of Adam, per member.
+constexpr int kMaxMembers = 64;
+struct AdamCorr {
+  float c1[kMaxMembers], c2[kMaxMembers];
+};
+
+// Adam on the FP32 master parameters, then their bfloat16 copy (member
+// blockIdx.y: its arrays n apart)
 __global__ __launch_bounds__(kThreads) void k_adam(float* __restrict__ th, float* __restrict__ mo, float* __restrict__ ve,
                                                    const float* __restrict__ g, __bf16* __restrict__ thb, int n, float lr,
-                                                   float c1, float c2) {
+                                                   AdamCorr corr) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
+  const int z = blockIdx.y;
+  const long long zo = (long long)z * n;
+  th += zo;
+  mo += zo;
+  ve += zo;
+  g += zo;
+  thb += zo;
+  const float c1 = corr.c1[z], c2 = corr.c2[z];
   const float gi = g[i];
   const float m = 0.9f * mo[i] + 0.1f * gi;
   const float v = 0.999f * ve[i] + 0.001f * gi * gi;
@@ -226,46 +267,45 @@ struct mlp_handle {
   float *master = nullptr, *mom = nullptr, *vel = nullptr, *grad = nullptr;
   __bf16* wbf = nullptr;
   std::vector<int> adam_t;
-  // activations for max_batch samples
-  __bf16* xb = nullptr;
-  float* Z[3] = {nullptr, nullptr, nullptr};   // pre-activations of the hidden layers
+  // Work arrays, one slot of max_batch samples per member; a call on n
+  // samples packs the members' slots n samples apart.
+  __bf16* xb = nullptr;                        // bfloat16 inputs [members][n][5]
+  float* Z[3] = {nullptr, nullptr, nullptr};   // pre-activations of the hidden layers [members][n][256]
   __bf16* A[3] = {nullptr, nullptr, nullptr};  // their bfloat16 GELU outputs
-  float* y = nullptr;                          // outputs [B][2]
-  float* ys = nullptr;                         // ensemble outputs [members][B][2]
+  float* y = nullptr;                          // outputs [members][n][2]
   float *dy = nullptr, *dzf[2] = {nullptr, nullptr};
   __bf16 *dyb = nullptr, *dzb[2] = {nullptr, nullptr};
-  float *part = nullptr, *inv = nullptr, *loss = nullptr;
+  float *part = nullptr, *inv = nullptr, *loss = nullptr;   // [members][kRed], [members], [members]
   std::string err = "no error";
 };
 
 namespace {
 
 struct MlpLayout {
-  size_t master, mom, vel, grad, wbf, xb, Z, A, y, ys, dy, dyb, dzf, dzb, part, inv, loss, total;
+  size_t master, mom, vel, grad, wbf, xb, Z, A, y, dy, dyb, dzf, dzb, part, inv, loss, total;
 };
 
 MlpLayout mlp_layout(int members, int B) {
   MlpLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += al256(bytes); return o; };
-  const size_t P = (size_t)members * kParams;
+  const size_t P = (size_t)members * kParams, MB = (size_t)members * B;
   L.master = take(P * 4);
   L.mom = take(P * 4);
   L.vel = take(P * 4);
   L.grad = take(P * 4);
   L.wbf = take(P * 2);
-  L.xb = take((size_t)B * kIn * 2);
-  L.Z = take(3 * (size_t)B * kHid * 4);
-  L.A = take(3 * (size_t)B * kHid * 2);
-  L.y = take((size_t)B * kOut * 4);
-  L.ys = take((size_t)members * B * kOut * 4);
-  L.dy = take((size_t)B * kOut * 4);
-  L.dyb = take((size_t)B * kOut * 2);
-  L.dzf = take(2 * (size_t)B * kHid * 4);
-  L.dzb = take(2 * (size_t)B * kHid * 2);
-  L.part = take(kRed * 4);
-  L.inv = take(4);
-  L.loss = take(4);
+  L.xb = take(MB * kIn * 2);
+  L.Z = take(3 * MB * kHid * 4);
+  L.A = take(3 * MB * kHid * 2);
+  L.y = take(MB * kOut * 4);
+  L.dy = take(MB * kOut * 4);
+  L.dyb = take(MB * kOut * 2);
+  L.dzf = take(2 * MB * kHid * 4);
+  L.dzb = take(2 * MB * kHid * 2);
+  L.part = take((size_t)members * kRed * 4);
+  L.inv = take((size_t)members * 4);
+  L.loss = take((size_t)members * 4);
   L.total = off;
   return L;
 }
@@ -281,51 +321,99 @@ int mfail(mlp_handle* h, int code, const std::string& msg) {
     if (e_ != hipSuccess) return mfail(h, -4, std::string(where) + ": " + hipGetErrorString(e_));        \
   } while (0)
 
+// Member offsets of one product (elements): A, B, C (and Cb, Zp), bias.
+struct ZStride {
+  long long A = 0, B = 0, C = 0, bias = 0;
+};
+
 void gemm(hipStream_t st, const __bf16* A, long long sam, long long sak, const __bf16* B, long long sbk, long long sbn,
-          int M, int N, int K, int epi, float* C, long long scm, __bf16* Cb, const float* bias, const float* Zp) {
-  Gemm g{A, sam, sak, B, sbk, sbn, M, N, K, epi, C, scm, Cb, bias, Zp};
-  hipLaunchKernelGGL(k_gemm, dim3((N + TN - 1) / TN, (M + TM - 1) / TM), dim3(kThreads), 0, st, g);
+          int M, int N, int K, int epi, float* C, long long scm, __bf16* Cb, const float* bias, const float* Zp,
+          int count = 1, ZStride zs = ZStride()) {
+  Gemm g{A, sam, sak, B, sbk, sbn, M, N, K, epi, C, scm, Cb, bias, Zp, zs.A, zs.B, zs.C, zs.bias};
+  hipLaunchKernelGGL(k_gemm, dim3((N + TN - 1) / TN, (M + TM - 1) / TM, count), dim3(kThreads), 0, st, g);
 }
 
-// forward of one member on n inputs already in h->xb; outputs to y
-void forward(mlp_handle* h, int member, int n, float* y) {
-  const __bf16* W = h->wbf + (size_t)member * kParams;
-  const float* P = h->master + (size_t)member * kParams;
+// Forward of members k0 .. k0 + count - 1 on n inputs in h->xb (x_stride
+// elements between the members' inputs: 0 when they share one input batch);
+// outputs to y[count][n][2].
+void forward(mlp_handle* h, int k0, int count, int n, long long x_stride, float* y) {
+  const __bf16* W = h->wbf + (size_t)k0 * kParams;
+  const float* P = h->master + (size_t)k0 * kParams;
+  const long long act = (long long)n * kHid;
   const __bf16* a = h->xb;
+  long long az = x_stride;
   int in = kIn;
   for (int l = 0; l < 3; ++l) {
-    gemm(h->stream, a, in, 1, W + w_off(l), kHid, 1, n, kHid, in, EPI_BIAS_GELU, h->Z[l], kHid, h->A[l], P + b_off(l), nullptr);
+    ZStride zs;
+    zs.A = az;
+    zs.B = kParams;
+    zs.C = act;
+    zs.bias = kParams;
+    gemm(h->stream, a, in, 1, W + w_off(l), kHid, 1, n, kHid, in, EPI_BIAS_GELU, h->Z[l], kHid, h->A[l], P + b_off(l),
+         nullptr, count, zs);
     a = h->A[l];
+    az = act;
     in = kHid;
   }
-  gemm(h->stream, a, kHid, 1, W + w_off(3), kOut, 1, n, kOut, kHid, EPI_BIAS, y, kOut, nullptr, P + b_off(3), nullptr);
+  ZStride zs;
+  zs.A = act;
+  zs.B = kParams;
+  zs.C = (long long)n * kOut;
+  zs.bias = kParams;
+  gemm(h->stream, a, kHid, 1, W + w_off(3), kOut, 1, n, kOut, kHid, EPI_BIAS, y, kOut, nullptr, P + b_off(3), nullptr,
+       count, zs);
 }
 
-// loss and gradient of one member (x already in xb); gradient into h->grad[member]
-void backward(mlp_handle* h, int member, const float* t, const float* m, int n) {
-  const __bf16* W = h->wbf + (size_t)member * kParams;
-  float* G = h->grad + (size_t)member * kParams;
-  hipLaunchKernelGGL(k_mask_norm, dim3(1), dim3(kThreads), 0, h->stream, m, n * kOut, h->inv);
-  hipLaunchKernelGGL(k_dy, dim3(kRed), dim3(kThreads), 0, h->stream, h->y, t, m, n * kOut, h->inv, h->dy, h->dyb, h->part);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kThreads), 0, h->stream, h->part, kRed, h->inv, h->loss);
-  // layer 3 (output): dW = A2^T dY, db = sum dY, dZ2 = (dY W3^T) . GELU'(Z2)
+// Loss and gradient of members k0 .. k0 + count - 1 after forward() on their
+// own inputs (h->xb, n apart), targets t and masks m [count][n][2]; gradients
+// into h->grad of those members, losses into h->loss[0 .. count).
+void backward(mlp_handle* h, int k0, int count, const float* t, const float* m, int n) {
+  const __bf16* W = h->wbf + (size_t)k0 * kParams;
+  float* G = h->grad + (size_t)k0 * kParams;
+  const long long act = (long long)n * kHid;
+  hipLaunchKernelGGL(k_mask_norm, dim3(count), dim3(kThreads), 0, h->stream, m, n * kOut, h->inv);
+  hipLaunchKernelGGL(k_dy, dim3(kRed, count), dim3(kThreads), 0, h->stream, h->y, t, m, n * kOut, h->inv, h->dy, h->dyb,
+                     h->part);
+  hipLaunchKernelGGL(k_loss_final, dim3(count), dim3(kThreads), 0, h->stream, h->part, kRed, h->inv, h->loss);
+  // layer l: dW = A_{l-1}^T dZ, db = column sums of dZ, dZ_{l-1} = (dZ W^T) . GELU'(Z_{l-1})
   const float* dzf = h->dy;
   const __bf16* dzb = h->dyb;
   int out = kOut;
   for (int l = 3; l >= 0; --l) {
     const int in = kDims[l];
     const __bf16* ain = l ? h->A[l - 1] : h->xb;
-    gemm(h->stream, ain, 1, in, dzb, out, 1, in, out, n, EPI_STORE, G + w_off(l), out, nullptr, nullptr, nullptr);
-    hipLaunchKernelGGL(k_colsum, dim3(nblk(out)), dim3(kThreads), 0, h->stream, dzf, n, out, G + b_off(l));
+    ZStride zw;
+    zw.A = (long long)n * in;
+    zw.B = (long long)n * out;
+    zw.C = kParams;
+    gemm(h->stream, ain, 1, in, dzb, out, 1, in, out, n, EPI_STORE, G + w_off(l), out, nullptr, nullptr, nullptr, count, zw);
+    hipLaunchKernelGGL(k_colsum, dim3(nblk(out), count), dim3(kThreads), 0, h->stream, dzf, n, out, G + b_off(l));
     if (l > 0) {
       float* nf = h->dzf[l & 1];
       __bf16* nb = h->dzb[l & 1];
-      gemm(h->stream, dzb, out, 1, W + w_off(l), 1, out, n, in, out, EPI_DGELU, nf, in, nb, nullptr, h->Z[l - 1]);
+      ZStride zd;
+      zd.A = (long long)n * out;
+      zd.B = kParams;
+      zd.C = act;
+      gemm(h->stream, dzb, out, 1, W + w_off(l), 1, out, n, in, out, EPI_DGELU, nf, in, nb, nullptr, h->Z[l - 1], count, zd);
       dzf = nf;
       dzb = nb;
       out = in;
     }
   }
+}
+
+// Adam step of members k0 .. k0 + count - 1 (their step counters advance).
+void adam(mlp_handle* h, int k0, int count, float lr) {
+  AdamCorr corr{};
+  for (int k = 0; k < count; ++k) {
+    const int t = ++h->adam_t[k0 + k];
+    corr.c1[k] = 1.0f - std::pow(0.9f, (float)t);
+    corr.c2[k] = 1.0f - std::pow(0.999f, (float)t);
+  }
+  const size_t o = (size_t)k0 * kParams;
+  hipLaunchKernelGGL(k_adam, dim3(nblk(kParams), count), dim3(kThreads), 0, h->stream, h->master + o, h->mom + o,
+                     h->vel + o, (const float*)(h->grad + o), h->wbf + o, kParams, lr, corr);
 }
 
 // ------------------------------------------------------------------------
@@ -414,7 +502,7 @@ int mlp_init(int32_t members, int32_t max_batch, void* dev_buf, size_t buf_bytes
   }
   const MlpLayout L = mlp_layout(members, max_batch);
   char* b = (char*)h->buf;
-  const size_t B = (size_t)max_batch;
+  const size_t MB = (size_t)members * max_batch;
   h->master = (float*)(b + L.master);
   h->mom = (float*)(b + L.mom);
   h->vel = (float*)(b + L.vel);
@@ -422,16 +510,15 @@ int mlp_init(int32_t members, int32_t max_batch, void* dev_buf, size_t buf_bytes
   h->wbf = (__bf16*)(b + L.wbf);
   h->xb = (__bf16*)(b + L.xb);
   for (int l = 0; l < 3; ++l) {
-    h->Z[l] = (float*)(b + L.Z) + l * B * kHid;
-    h->A[l] = (__bf16*)(b + L.A) + l * B * kHid;
+    h->Z[l] = (float*)(b + L.Z) + l * MB * kHid;
+    h->A[l] = (__bf16*)(b + L.A) + l * MB * kHid;
   }
   h->y = (float*)(b + L.y);
-  h->ys = (float*)(b + L.ys);
   h->dy = (float*)(b + L.dy);
   h->dyb = (__bf16*)(b + L.dyb);
   for (int k = 0; k < 2; ++k) {
-    h->dzf[k] = (float*)(b + L.dzf) + k * B * kHid;
-    h->dzb[k] = (__bf16*)(b + L.dzb) + k * B * kHid;
+    h->dzf[k] = (float*)(b + L.dzf) + k * MB * kHid;
+    h->dzb[k] = (__bf16*)(b + L.dzb) + k * MB * kHid;
   }
   h->part = (float*)(b + L.part);
   h->inv = (float*)(b + L.inv);
@@ -476,7 +563,7 @@ int mlp_forward(mlp_handle* h, int32_t member, const float* x_dev, int32_t n, fl
   if (rc) return rc;
   if (!x_dev || !y_dev) return mfail(h, -1, "null argument");
   hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)n * kIn)), dim3(kThreads), 0, h->stream, x_dev, h->xb, n * kIn);
-  forward(h, member, n, y_dev);
+  forward(h, member, 1, n, 0, y_dev);
   MHIP(h, hipGetLastError(), "forward kernels");
   return 0;
 }
@@ -487,8 +574,8 @@ int mlp_loss_grad(mlp_handle* h, int32_t member, const float* x_dev, const float
   if (rc) return rc;
   if (!x_dev || !t_dev || !m_dev) return mfail(h, -1, "null argument");
   hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)n * kIn)), dim3(kThreads), 0, h->stream, x_dev, h->xb, n * kIn);
-  forward(h, member, n, h->y);
-  backward(h, member, t_dev, m_dev, n);
+  forward(h, member, 1, n, 0, h->y);
+  backward(h, member, 1, t_dev, m_dev, n);
   MHIP(h, hipGetLastError(), "training kernels");
   if (loss_host) MHIP(h, hipMemcpyAsync(loss_host, h->loss, 4, hipMemcpyDeviceToHost, h->stream), "copy loss");
   if (grad_host)
@@ -503,16 +590,31 @@ int mlp_train_step(mlp_handle* h, int32_t member, const float* x_dev, const floa
   if (rc) return rc;
   if (!x_dev || !t_dev || !m_dev || !(lr > 0.f)) return mfail(h, -1, "null argument or non-positive rate");
   hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)n * kIn)), dim3(kThreads), 0, h->stream, x_dev, h->xb, n * kIn);
-  forward(h, member, n, h->y);
-  backward(h, member, t_dev, m_dev, n);
-  const int t = ++h->adam_t[member];
-  const float c1 = 1.0f - std::pow(0.9f, (float)t), c2 = 1.0f - std::pow(0.999f, (float)t);
-  const size_t o = (size_t)member * kParams;
-  hipLaunchKernelGGL(k_adam, dim3(nblk(kParams)), dim3(kThreads), 0, h->stream, h->master + o, h->mom + o, h->vel + o,
-                     (const float*)(h->grad + o), h->wbf + o, kParams, lr, c1, c2);
+  forward(h, member, 1, n, 0, h->y);
+  backward(h, member, 1, t_dev, m_dev, n);
+  adam(h, member, 1, lr);
   MHIP(h, hipGetLastError(), "training kernels");
   if (loss_host) {
     MHIP(h, hipMemcpyAsync(loss_host, h->loss, 4, hipMemcpyDeviceToHost, h->stream), "copy loss");
+    MHIP(h, hipStreamSynchronize(h->stream), "synchronise");
+  }
+  return 0;
+}
+
+int mlp_train_step_ensemble(mlp_handle* h, const float* x_dev, const float* t_dev, const float* m_dev, int32_t n, float lr,
+                            float* loss_host) {
+  int rc = check(h, 0, n);
+  if (rc) return rc;
+  if (!x_dev || !t_dev || !m_dev || !(lr > 0.f)) return mfail(h, -1, "null argument or non-positive rate");
+  const int M = h->members;
+  hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)M * n * kIn)), dim3(kThreads), 0, h->stream, x_dev, h->xb,
+                     M * n * kIn);
+  forward(h, 0, M, n, (long long)n * kIn, h->y);
+  backward(h, 0, M, t_dev, m_dev, n);
+  adam(h, 0, M, lr);
+  MHIP(h, hipGetLastError(), "training kernels");
+  if (loss_host) {
+    MHIP(h, hipMemcpyAsync(loss_host, h->loss, 4 * (size_t)M, hipMemcpyDeviceToHost, h->stream), "copy losses");
     MHIP(h, hipStreamSynchronize(h->stream), "synchronise");
   }
   return 0;
@@ -523,8 +625,8 @@ int mlp_predict_ensemble(mlp_handle* h, const float* x_dev, int32_t n, float* me
   if (rc) return rc;
   if (!x_dev || !mean_dev || !std_dev) return mfail(h, -1, "null argument");
   hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)n * kIn)), dim3(kThreads), 0, h->stream, x_dev, h->xb, n * kIn);
-  for (int k = 0; k < h->members; ++k) forward(h, k, n, h->ys + (size_t)k * n * kOut);
-  hipLaunchKernelGGL(k_ens, dim3(nblk((long long)n * kOut)), dim3(kThreads), 0, h->stream, (const float*)h->ys, h->members,
+  forward(h, 0, h->members, n, 0, h->y);
+  hipLaunchKernelGGL(k_ens, dim3(nblk((long long)n * kOut)), dim3(kThreads), 0, h->stream, (const float*)h->y, h->members,
                      n * kOut, mean_dev, std_dev);
   MHIP(h, hipGetLastError(), "ensemble kernels");
   return 0;

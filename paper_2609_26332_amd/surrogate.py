@@ -38,22 +38,23 @@ def lib():
         L.mlp_forward.argtypes = [vp, i32, vp, i32, vp]
         L.mlp_loss_grad.argtypes = [vp, i32, vp, vp, vp, i32, fp, fp]
         L.mlp_train_step.argtypes = [vp, i32, vp, vp, vp, i32, ctypes.c_float, fp]
+        L.mlp_train_step_ensemble.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, fp]
         L.mlp_predict_ensemble.argtypes = [vp, vp, i32, vp, vp]
         L.mlp_predict_ensemble_noalloc.argtypes = [vp, i32, vp, i32, vp, vp, vp]
         L.mlp_destroy.argtypes = [vp]
         L.mlp_last_error.argtypes = [vp]
         L.mlp_last_error.restype = ctypes.c_char_p
         for nm in ("mlp_required_bytes", "mlp_init", "mlp_set_params", "mlp_get_params", "mlp_forward",
-                   "mlp_loss_grad", "mlp_train_step", "mlp_predict_ensemble", "mlp_predict_ensemble_noalloc",
-                   "mlp_destroy"):
+                   "mlp_loss_grad", "mlp_train_step", "mlp_train_step_ensemble", "mlp_predict_ensemble",
+                   "mlp_predict_ensemble_noalloc", "mlp_destroy"):
             getattr(L, nm).restype = ctypes.c_int
         _mlp_ready = True
     return L
 
 
 EXPORTS = ["mlp_param_count", "mlp_required_bytes", "mlp_init", "mlp_set_params", "mlp_get_params", "mlp_forward",
-           "mlp_loss_grad", "mlp_train_step", "mlp_predict_ensemble", "mlp_predict_ensemble_noalloc", "mlp_destroy",
-           "mlp_last_error"]
+           "mlp_loss_grad", "mlp_train_step", "mlp_train_step_ensemble", "mlp_predict_ensemble",
+           "mlp_predict_ensemble_noalloc", "mlp_destroy", "mlp_last_error"]
 
 
 def _check(rc, h=None):
@@ -129,6 +130,15 @@ class Mlp:
                                     ctypes.byref(loss) if want_loss else None), self._h)
         return loss.value if want_loss else None
 
+    def train_step_ensemble(self, x, t, m, lr: float, want_loss: bool = False):
+        """One step of every member, each on its own batch: x [members][n][5],
+        t and m [members][n][2], contiguous FP32 device tensors."""
+        assert x.shape[0] == self.members and x.is_contiguous() and t.is_contiguous() and m.is_contiguous()
+        loss = (ctypes.c_float * self.members)()
+        _check(lib().mlp_train_step_ensemble(self._h, _ptr(x), _ptr(t), _ptr(m), x.shape[1], float(lr),
+                                             loss if want_loss else None), self._h)
+        return list(loss) if want_loss else None
+
     def predict(self, x):
         x = self._dev(x)
         mean = torch.empty((x.shape[0], 2), dtype=torch.float32, device="cuda")
@@ -182,11 +192,16 @@ class Surrogate:
         lo, hi = INPUT_RANGES[:, 0], INPUT_RANGES[:, 1]
         return (2.0 * (X - lo) / (hi - lo) - 1.0).astype(np.float32)
 
-    def fit(self, X, angle, tau, tau_mask, epochs: int = 400, batch: int = 256, lr: float = 1e-3, seed: int = 0,
-            log=None):
+    def fit(self, X, angle, tau, tau_mask, epochs: int = 1000, batch: int = 256, lr: float = 2e-3, seed: int = 0,
+            schedule: str = "cosine", log=None):
         """The angle output learns the standardised shift from the clean angle,
         theta_app - theta0 (a few degrees), rather than theta_app itself.  A case
-        without an angle (NaN: the drop detached) is masked out of that output."""
+        without an angle (NaN: the drop detached) is masked out of that output.
+
+        Each member trains on its own bootstrap resample in its own order; the
+        members step together (one mlp_train_step_ensemble per batch).  The
+        rate follows a cosine decay from lr to zero over the run
+        (schedule="cosine") or stays at lr ("constant")."""
         Xs = self.scale_inputs(X)
         shift = np.asarray(angle, dtype=np.float64) - np.asarray(X, dtype=np.float64)[:, 0]
         has = np.isfinite(shift)
@@ -194,25 +209,30 @@ class Surrogate:
         T = np.stack([np.where(has, (shift - self.angle_mu) / self.angle_sd, 0.0), np.asarray(tau, dtype=np.float64)],
                      1).astype(np.float32)
         Mk = np.stack([has.astype(np.float64), np.asarray(tau_mask, dtype=np.float64)], 1).astype(np.float32)
-        n = len(angle)
-        losses = []
-        for k in range(self.members):
-            rng = np.random.default_rng(seed * 1000 + k)
+        n, M = len(angle), self.members
+        rngs = [np.random.default_rng(seed * 1000 + k) for k in range(M)]
+        boots = [r.integers(0, n, size=n) for r in rngs]   # bootstrap resample per member
+        for k in range(M):
             self.net.set_params(k, glorot_params(seed * 1000 + k + 1, self.net.n_params))
-            boot = rng.integers(0, n, size=n)   # bootstrap resample per member
-            xd, td, md = (torch.as_tensor(a[boot]).cuda() for a in (Xs, T, Mk))
-            nb = max(1, n // batch)
-            for ep in range(epochs):
-                perm = torch.as_tensor(rng.permutation(n)).cuda()
-                for b in range(nb):
-                    idx = perm[b * batch:(b + 1) * batch]
-                    last = ep == epochs - 1 and b == nb - 1
-                    lo = self.net.train_step(k, xd[idx].contiguous(), td[idx].contiguous(), md[idx].contiguous(), lr,
-                                             want_loss=last)
-                    if last:
-                        losses.append(lo)
-            if log:
-                log(f"member {k}: final batch loss {losses[-1]:.4g}")
+        xd, td, md = (torch.as_tensor(np.stack([a[bt] for bt in boots])).cuda() for a in (Xs, T, Mk))
+        rows = torch.arange(M, device="cuda")[:, None]
+        nb = max(1, n // batch)
+        total, it = epochs * nb, 0
+        losses = None
+        for ep in range(epochs):
+            perm = torch.as_tensor(np.stack([r.permutation(n) for r in rngs])).cuda()
+            for b in range(nb):
+                idx = perm[:, b * batch:(b + 1) * batch]
+                last = ep == epochs - 1 and b == nb - 1
+                rate = lr * 0.5 * (1.0 + np.cos(np.pi * it / total)) if schedule == "cosine" else lr
+                out = self.net.train_step_ensemble(xd[rows, idx].contiguous(), td[rows, idx].contiguous(),
+                                                   md[rows, idx].contiguous(), max(rate, 1e-12), want_loss=last)
+                if last:
+                    losses = out
+                it += 1
+        if log:
+            for k, lo in enumerate(losses):
+                log(f"member {k}: final batch loss {lo:.4g}")
         return losses
 
     def predict(self, X):

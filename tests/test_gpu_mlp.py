@@ -88,6 +88,33 @@ def test_training_and_ensemble(sur):
     assert np.allclose(sd.cpu().numpy(), ys.std(0), atol=1e-6)
 
 
+def test_ensemble_step_equals_member_steps(sur):
+    """mlp_train_step_ensemble (every member in the same launches, each on its
+    own batch) leaves every member's parameters and loss equal, bit for bit,
+    to one mlp_train_step per member on that member's batch; three steps, a
+    ragged batch of 77 samples."""
+    import torch
+
+    rng = np.random.default_rng(11)
+    members, n = 3, 77
+    X = rng.uniform(-1, 1, size=(members, n, 5)).astype(np.float32)
+    T = rng.normal(size=(members, n, 2)).astype(np.float32)
+    Mk = (rng.random((members, n, 2)) > 0.3).astype(np.float32)
+    a, b = sur.Mlp(members=members, max_batch=128), sur.Mlp(members=members, max_batch=128)
+    for k in range(members):
+        theta = sur.glorot_params(20 + k, a.n_params)
+        a.set_params(k, theta)
+        b.set_params(k, theta)
+    xd, td, md = (torch.as_tensor(v).cuda() for v in (X, T, Mk))
+    for step in range(3):
+        la = a.train_step_ensemble(xd, td, md, 1e-3 * (step + 1), want_loss=True)
+        lb = [b.train_step(k, xd[k].contiguous(), td[k].contiguous(), md[k].contiguous(), 1e-3 * (step + 1),
+                           want_loss=True) for k in range(members)]
+        assert la == lb, (step, la, lb)
+    for k in range(members):
+        assert np.array_equal(a.get_params(k), b.get_params(k)), k
+
+
 def test_surrogate_gain_over_plain_sweep(sur, tmp_path):
     """What the trained ensemble gains over the plain batched solver on held-out
     cases of the sweep distribution (reduced here: 192 training and 96 held-out
@@ -103,3 +130,30 @@ def test_surrogate_gain_over_plain_sweep(sur, tmp_path):
     assert r["gain"] > 2.0, r
     assert r["within_0p5_deg"] > 0.6, r
     assert r["mean_err_deg"] < 1.0, r
+
+
+def test_calibrated_surrogate_on_committed_sweep(sur):
+    """The calibrated rule on the committed solver runs of the sweep
+    distribution: the ensemble trains on seeds 1000-1014 (7680 cases),
+    calibrates its fallback threshold on seeds 1015-1016 and delivers the 512
+    held-out cases of seed 2000 (the solver runs the declined ones).  At least
+    99% of the delivered angles lie within 0.5 degree of the solver's (the
+    committed labels), and the delivery is at least ten times faster than the
+    plain sweep of the same cases (the time stored with them, measured on this
+    GPU model)."""
+    import os
+
+    from paper_2609_26332_amd import sweep, train_surrogate as ts
+
+    data = os.path.join(os.path.dirname(__file__), "..", "paper_2609_26332_amd", "data")
+    f = lambda k: os.path.join(data, "sweep_seed%d.npz" % k)
+    model, train_s, _, _ = ts.train([f(k) for k in range(1000, 1015)], log=None)
+    cal = ts.calibrate(model, [f(1015), f(1016)], log=None)
+    va, parts = ts.load([f(2000)])
+    cases = sweep.batch_cases(2000, 512)
+    delivered, pred, fb, pred_s, fb_s = ts.deliver(model, cases, cal["threshold_deg"], int(parts[0]["cap"]))
+    acc = ts.accuracy(delivered, pred, fb, va)
+    gain = float(parts[0]["seconds"]) / (pred_s + fb_s)
+    print(dict(calibration=cal, gain=round(gain, 2), train_seconds=round(train_s, 1), **acc))
+    assert acc["within_0p5_deg"] >= 0.99, acc
+    assert gain >= 10.0, (gain, acc)
