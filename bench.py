@@ -144,6 +144,35 @@ def grid_run(cfg, prec, steps, warmup, kernel_steps):
     return out
 
 
+# Algorithmic bytes of a D3Q19 node-step: 57 populations and 5 history planes
+# (phi, psi, u_x, u_y, u_z of the previous step), read and written.
+ALGO_BYTES_3D = {"fp32": 2 * (57 * 4 + 5 * 4), "fp64": 2 * (57 * 8 + 5 * 8)}
+
+
+def grid3d_run(n, prec, steps, warmup):
+    """The 3-D (D3Q19) step on an n^3 periodic drop: whole-step rate (its four
+    kernels) on the algorithmic bytes of a D3Q19 node-step."""
+    from paper_2609_26332_amd import inputs, lbm3d
+
+    sim = lbm3d.Sim3(inputs.drop3d(n, n / 4.0, psi_b=0.01), prec)
+    sim.step(warmup)
+    sync()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sync()
+    wall = time.perf_counter() - t0
+    N = n ** 3
+    ms = wall * 1e3 / steps
+    gbs = ALGO_BYTES_3D[prec] * N / (ms * 1e-3) / 1e9
+    out = {"workload": "periodic drop %d^3, D3Q19, %s storage" % (n, prec.upper()), "mlups": round(N * steps / wall / 1e6, 1),
+           "ms_per_step": round(ms, 5), "bytes_per_node_step": ALGO_BYTES_3D[prec], "achieved": round(gbs, 2),
+           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "design_bytes_per_node_step": sim.bytes_per_node_step(),
+           "what": "whole step (four kernels), wall clock over %d steps" % steps,
+           "nonfinite": sim.invariants(check=False)["nonfinite"]}
+    sim.close()
+    return out
+
+
 def copy_rate(gib: float = 1.0, reps: int = 10) -> float:
     """GB/s of a plain device-to-device copy of `gib` GiB (read + write bytes),
     timed with HIP events on the current stream."""
@@ -183,18 +212,61 @@ def surrogate_rate(n: int = 4096, reps: int = 20) -> dict:
     sync()
     t_pred = (time.perf_counter() - t0) / reps
     b = 256
-    t, m = torch.zeros(b, 2, device="cuda"), torch.ones(b, 2, device="cuda")
-    xb = x[:b].contiguous()
-    net.train_step(0, xb, t, m, 1e-3)
+    t, m = torch.zeros(5, b, 2, device="cuda"), torch.ones(5, b, 2, device="cuda")
+    xb = x[:b].unsqueeze(0).repeat(5, 1, 1).contiguous()
+    net.train_step_ensemble(xb, t, m, 1e-3)
     sync()
     t0 = time.perf_counter()
     for _ in range(reps):
-        net.train_step(0, xb, t, m, 1e-3)
+        net.train_step_ensemble(xb, t, m, 1e-3)
     sync()
     t_train = (time.perf_counter() - t0) / reps
     net.close()
     return {"members": 5, "cases": n, "predict_ms": round(t_pred * 1e3, 4), "predict_cases_per_s": round(n / t_pred, 1),
-            "train_step_ms_batch256": round(t_train * 1e3, 4)}
+            "train_step_ms_batch256_all_members": round(t_train * 1e3, 4)}
+
+
+DATA_DIR = os.path.join(ROOT, "paper_2609_26332_amd", "data")
+TRAIN_SEEDS = list(range(1000, 1015))
+CALIB_SEEDS = [1015, 1016]
+
+
+def sweep_file(seed):
+    return os.path.join(DATA_DIR, "sweep_seed%d.npz" % seed)
+
+
+def surrogate_sweep(cap: int = 50000) -> dict:
+    """The second half of the metric: the 512 held-out cases of the sweep
+    distribution (seed 2000) delivered by the batched solver alone and by the
+    surrogate with its calibrated fallback to the solver, both timed here.
+    The ensemble trains on the committed solver runs of seeds 1000-1014
+    (7680 cases) and calibrates its fallback threshold on seeds 1015-1016;
+    the accuracy of the delivered angles is judged against this run's own
+    plain sweep."""
+    import numpy as np
+    from paper_2609_26332_amd import sweep, train_surrogate as ts
+
+    cases = sweep.batch_cases(SEED, 512)
+    t0 = time.perf_counter()
+    r = sweep.run_sweep(cases, cap=cap)
+    plain_s = time.perf_counter() - t0
+    truth = ts.labels(cases, r, cap)
+    sur, train_s, _, n_train = ts.train([sweep_file(k) for k in TRAIN_SEEDS], log=None)
+    cal = ts.calibrate(sur, [sweep_file(k) for k in CALIB_SEEDS], log=None)
+    delivered, pred, fb, pred_s, fb_s = ts.deliver(sur, cases, cal["threshold_deg"], cap)
+    acc = ts.accuracy(delivered, pred, fb, truth)
+    stored = np.load(sweep_file(SEED))["angle"]
+    both = np.isfinite(stored) & np.isfinite(truth["angle"])
+    n = len(cases)
+    return {"what": "512 held-out sweep cases (seed 2000) to their stop rule: plain batched solver vs surrogate with "
+                    "calibrated fallback to the solver; training and calibration on committed solver runs",
+            "plain_cases_per_s": round(n / plain_s, 3), "plain_seconds": round(plain_s, 2),
+            "cases_per_s": round(n / (pred_s + fb_s), 3), "gain": round(plain_s / (pred_s + fb_s), 2),
+            "predict_seconds": round(pred_s, 4), "fallback_seconds": round(fb_s, 2),
+            "threshold_deg": round(cal["threshold_deg"], 4), "calibration": cal,
+            "train_cases": n_train, "train_seconds": round(train_s, 2), **acc,
+            "plain_angles_vs_committed_max_abs_deg": float(np.abs(stored[both] - truth["angle"][both]).max())
+            if both.any() else None}
 
 
 def cpu_model():
@@ -275,7 +347,7 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=20, help="event-timed steps for the kernel figures")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline batch (profiling aid)")
-    ap.add_argument("--workload", default="all", choices=["all", "batch", "grid4096"],
+    ap.add_argument("--workload", default="all", choices=["all", "batch", "grid4096", "grid3d", "surrogate"],
                     help="profiling aid: one workload only")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16"],
                     help="profiling aid: storage of the single workload run with --workload")
@@ -298,6 +370,13 @@ def main():
         return
     from paper_2609_26332_amd import inputs
 
+    if args.workload == "surrogate":
+        print(json.dumps(surrogate_sweep()), flush=True)
+        return
+    if args.workload == "grid3d":
+        p3 = args.precision if args.precision in ("fp32", "fp64") else "fp32"
+        print(json.dumps(grid3d_run(128, p3, args.steps, args.warmup)), flush=True)
+        return
     if args.workload == "grid4096":
         r = grid_run(inputs.roofline_grid(), args.precision, args.steps, args.warmup, args.kernel_steps)
         print(json.dumps({"workload": "periodic drop 4096x4096 %s" % args.precision, **r}), flush=True)
@@ -347,7 +426,11 @@ def main():
         torch.cuda.empty_cache()
         out["sessile_256x128_fp32"] = grid_run(inputs.sessile_drop(), "fp32", 2000, 100, args.kernel_steps)
         out["stationary_64x64_fp64"] = grid_run(inputs.stationary_drop(), "fp64", 2000, 100, args.kernel_steps)
+        out["grid3d_128"] = {p: grid3d_run(128, p, 40, 5) for p in ("fp32", "fp64")}
+        torch.cuda.empty_cache()
         out["surrogate"] = surrogate_rate()
+        torch.cuda.empty_cache()
+        out["sweep_with_surrogate"] = surrogate_sweep()
     if not args.no_cpu_baseline and args.workload == "all":
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

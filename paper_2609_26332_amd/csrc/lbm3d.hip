@@ -1,18 +1,23 @@
 // lbm3d.hip -- gfx950 kernels and C ABI (include/lbm3d.h) of the D3Q19 step of
 // the conservative Allen-Cahn / Navier-Stokes surfactant model.
 //
-// One step is four launches over the nodes (one thread per node, x fastest,
+// One step is five launches over the nodes (one thread per node, x fastest,
 // so every plane access of a wavefront is 64 consecutive elements):
 //   k3_mu    chemical potentials (eq_muphi, eq_mupsi) from the FP64 phi/psi
 //            planes with the 18-direction isotropic Laplacian, the wall terms
 //            of the first fluid layer, and FP64 per-workgroup multiplier sums
-//   k3_fin   one workgroup: lambda_phi (eq15) and mubar_psi (AC_psi) from the
+//   k3_fin   one wavefront: lambda_phi (eq15) and mubar_psi (AC_psi) from the
 //            sums, in a fixed order
-//   k3_col   gradients of rho and of both potentials, the force (eq_Fs0),
-//            velocity and pressure, the sources with their backward
-//            differences, the three MRT collisions in FP64 and push streaming
-//            into the other population buffer with half-way bounce-back,
-//            moving-wall and free-slip walls
+//   k3_colf  gradients of rho and of both potentials, the force (eq_Fs0),
+//            velocity and pressure, the sources and the advecting velocity
+//            (into the history planes), the flow lattice's MRT collision in
+//            FP64 and push streaming into the other population buffer with
+//            half-way bounce-back, moving-wall and free-slip walls
+//   k3_colgh the phase-field and surfactant lattices: backward differences
+//            from the history planes of this step and the previous one, MRT
+//            collisions in FP64, push streaming
+//            (two kernels rather than one: one kernel holding all three
+//            lattices needs more than 256 registers a lane, one wave per SIMD)
 //   k3_mom   phi, psi of the new state (zeroth moments) into the other FP64
 //            plane pair
 // The rest populations of g and h are stored shifted by the phi, psi of the
@@ -224,17 +229,28 @@ __global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const un
   }
 }
 
-__global__ __launch_bounds__(kT) void k3_fin(const P3* __restrict__ pp_, const double* __restrict__ part, int nb,
+// One wavefront: lane l sums the partials l, l + 64, ... in order, then a
+// fixed shuffle tree combines the lanes (the same order on every call).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;   // valid in lane 0
+}
+
+__global__ __launch_bounds__(64) void k3_fin(const P3* __restrict__ pp_, const double* __restrict__ part, int nb,
                                              Scal3* __restrict__ sc) {
   const P3& p = *pp_;
-  if (threadIdx.x != 0) return;
   double S1 = 0, S2 = 0, S3 = 0, S4 = 0;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = threadIdx.x; b < nb; b += 64) {
     S1 += part[4 * b];
     S2 += part[4 * b + 1];
     S3 += part[4 * b + 2];
     S4 += part[4 * b + 3];
   }
+  S1 = wave_sum(S1);
+  S2 = wave_sum(S2);
+  S3 = wave_sum(S3);
+  S4 = wave_sum(S4);
+  if (threadIdx.x != 0) return;
   double lam = S2 > 0.0 ? S1 / S2 : 0.0;
   if (p.phi_hold && S2 > 0.0 && p.M_phi > 0.0) lam += (p.m_ref - S4) / (p.M_phi * S2);
   sc->lambda = lam;
@@ -242,30 +258,36 @@ __global__ __launch_bounds__(kT) void k3_fin(const P3* __restrict__ pp_, const d
 }
 
 // ------------------------------------------------------ MRT, closed form
-// Raw moments of a population vector, in the order
+// Raw moments in the order
 // 0: 1; 1-3: x y z; 4-9: xx yy zz xy xz yz; 10-15: xxy xxz yyx yyz zzx zzy;
 // 16-18: xxyy xxzz yyzz.
-__device__ __forceinline__ void moments3(const double* f, double* m) {
+// The collision f + M^-1 [-S M (f - feq) + (I - S/2) M v] equals
+// M^-1 [(I - S) M f + S M feq + (I - S/2) M v]: with S diagonal by moment
+// order o, direction i adds to every moment of order o its raw-moment entry
+// times q_o = (1 - s_o) f_i + s_o feq_i + (1 - s_o / 2) v_i.  The post-collision
+// moments accumulate in one array while the populations stream in, and no
+// population array is kept.
+__device__ __forceinline__ void accum3(int i, const double* q, double* m) {
+  const int a = cx3(i), b = cy3(i), c = cz3(i);
+  m[0] += q[0];
+  if (a) m[1] += a * q[1];
+  if (b) m[2] += b * q[1];
+  if (c) m[3] += c * q[1];
+  if (a) m[4] += q[2];
+  if (b) m[5] += q[2];
+  if (c) m[6] += q[2];
+  if (a && b) m[7] += a * b * q[2];
+  if (a && c) m[8] += a * c * q[2];
+  if (b && c) m[9] += b * c * q[2];
+  if (a && b) { m[10] += b * q[3]; m[12] += a * q[3]; m[16] += q[4]; }
+  if (a && c) { m[11] += c * q[3]; m[14] += a * q[3]; m[17] += q[4]; }
+  if (b && c) { m[13] += c * q[3]; m[15] += b * q[3]; m[18] += q[4]; }
+}
+__device__ __forceinline__ void accum3(int i, double f, double feq, double v, const double* rate5, double* m) {
+  double q[5];
 #pragma unroll
-  for (int k = 0; k < Q3; ++k) m[k] = 0.0;
-#pragma unroll
-  for (int i = 0; i < Q3; ++i) {
-    const int a = cx3(i), b = cy3(i), c = cz3(i);
-    const double v = f[i];
-    m[0] += v;
-    if (a) m[1] += a * v;
-    if (b) m[2] += b * v;
-    if (c) m[3] += c * v;
-    if (a) m[4] += v;
-    if (b) m[5] += v;
-    if (c) m[6] += v;
-    if (a && b) m[7] += a * b * v;
-    if (a && c) m[8] += a * c * v;
-    if (b && c) m[9] += b * c * v;
-    if (a && b) { m[10] += b * v; m[12] += a * v; m[16] += v; }
-    if (a && c) { m[11] += c * v; m[14] += a * v; m[17] += v; }
-    if (b && c) { m[13] += c * v; m[15] += b * v; m[18] += v; }
-  }
+  for (int o = 0; o < 5; ++o) q[o] = (1.0 - rate5[o]) * f + rate5[o] * feq + (1.0 - 0.5 * rate5[o]) * v;
+  accum3(i, q, m);
 }
 // Populations from raw moments (the inverse of moments3).
 __device__ __forceinline__ void populations3(const double* m, double* f) {
@@ -292,25 +314,6 @@ __device__ __forceinline__ void populations3(const double* m, double* f) {
   f[6] = 0.5 * (F0z - F1z);
   f[0] = m[0] - (m[4] + m[5] + m[6]) + (m[16] + m[17] + m[18]);
 }
-__device__ __forceinline__ int order3(int k) { return k == 0 ? 0 : (k < 4 ? 1 : (k < 10 ? 2 : (k < 16 ? 3 : 4))); }
-
-// f <- f - M^-1 S M (f - feq) + M^-1 (I - S/2) M v   (the extra w_i term is added by the caller)
-__device__ __forceinline__ void mrt3(double* f, const double* feq, const double* v, const double* rate5) {
-  double d[Q3], md[Q3], mv[Q3];
-#pragma unroll
-  for (int i = 0; i < Q3; ++i) d[i] = f[i] - feq[i];
-  moments3(d, md);
-  moments3(v, mv);
-#pragma unroll
-  for (int k = 0; k < Q3; ++k) {
-    const double s = rate5[order3(k)];
-    md[k] = -s * md[k] + (1.0 - 0.5 * s) * mv[k];
-  }
-  populations3(md, d);
-#pragma unroll
-  for (int i = 0; i < Q3; ++i) f[i] += d[i];
-}
-
 __device__ __forceinline__ double cdot3(int i, double ax, double ay, double az) {
   return cx3(i) * ax + cy3(i) * ay + cz3(i) * az;
 }
@@ -398,13 +401,16 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
   return M;
 }
 
-// ---------------------------------------------------------------- k3_col
+// ---------------------------------------------------------------- k3_colf
+// Macroscopic state, sources and advecting velocity of the step (into the
+// history planes hout), then the flow lattice's collision and streaming.
+// Two waves per SIMD: in FP64 storage a few registers spill (12 bytes a lane),
+// against one wave per SIMD without the bound.
 template <class S>
-__global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
-                                             const S* __restrict__ pin, S* __restrict__ pout,
-                                             const double* __restrict__ pp, const double* __restrict__ pprev,
-                                             const double* __restrict__ mu, const double* __restrict__ hin,
-                                             double* __restrict__ hout, const Scal3* __restrict__ sc, int have_hist) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) void k3_colf(
+    const P3* __restrict__ pp_, const unsigned char* __restrict__ solid, const S* __restrict__ pin, S* __restrict__ pout,
+    const double* __restrict__ pp, const double* __restrict__ mu, const double* __restrict__ hin, double* __restrict__ hout,
+    const Scal3* __restrict__ sc, int have_hist) {
   const P3& p = *pp_;
   const int N = p.N;
   const int n = blockIdx.x * kT + threadIdx.x;
@@ -421,20 +427,10 @@ __global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const u
                                                 - 0.5 * p.W * ph * ph + mubar)
                                    + p.M_psi * M.tpsi
                              : 0.0;
-  // advecting velocity and backward differences (first step: zero)
-  double v[3] = {M.u[0], M.u[1], M.u[2]}, dph[3] = {0, 0, 0}, dps[3] = {0, 0, 0}, dRp = 0.0, dRs = 0.0;
-  if (have_hist) {
-    if (!p.adv_raw)
-      for (int d = 0; d < 3; ++d) v[d] = 0.5 * (M.u[d] + hin[(size_t)d * N + n]);
-    const double php = pprev[n], psp = pprev[N + n];
-    for (int d = 0; d < 3; ++d) {
-      const double vh = hin[(size_t)(3 + d) * N + n];
-      dph[d] = ph * v[d] - php * vh;
-      dps[d] = ps * v[d] - psp * vh;
-    }
-    dRp = Rphi - hin[(size_t)6 * N + n];
-    dRs = Rpsi - hin[(size_t)7 * N + n];
-  }
+  // advecting velocity (the step's own u, or its mean with the previous step's)
+  double v[3] = {M.u[0], M.u[1], M.u[2]};
+  if (have_hist && !p.adv_raw)
+    for (int d = 0; d < 3; ++d) v[d] = 0.5 * (M.u[d] + hin[(size_t)d * N + n]);
   for (int d = 0; d < 3; ++d) {
     hout[(size_t)d * N + n] = M.u[d];
     hout[(size_t)(3 + d) * N + n] = v[d];
@@ -443,8 +439,7 @@ __global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const u
   hout[(size_t)7 * N + n] = Rpsi;
 
   const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
-  double f[Q3], eq[Q3], fv[Q3];
-  // --- flow lattice
+  double m[Q3], f[Q3];
   {
     double rates[5];
     for (int k = 0; k < 5; ++k) rates[k] = p.sf[k];
@@ -455,15 +450,18 @@ __global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const u
     const double uu = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
     const double ugr = M.u[0] * M.gr[0] + M.u[1] * M.gr[1] + M.u[2] * M.gr[2];
 #pragma unroll
+    for (int k = 0; k < Q3; ++k) m[k] = 0.0;
+#pragma unroll
     for (int i = 0; i < Q3; ++i) {
-      f[i] = ld(pin, (size_t)i * N + n);
+      const double fi = ld(pin, (size_t)i * N + n);
       const double cu = cdot3(i, M.u[0], M.u[1], M.u[2]);
       const double su = cu / kCs2 + cu * cu / (2.0 * kCs2 * kCs2) - uu / (2.0 * kCs2);
-      eq[i] = M.pr / kCs2 * (w3(i) - (i == 0 ? 1.0 : 0.0)) + rho * w3(i) * su;
+      const double eq = M.pr / kCs2 * (w3(i) - (i == 0 ? 1.0 : 0.0)) + rho * w3(i) * su;
       const double cg = cdot3(i, M.gr[0], M.gr[1], M.gr[2]), cF = cdot3(i, M.F[0], M.F[1], M.F[2]);
-      fv[i] = w3(i) * (ugr + cF / kCs2 + (cu * cg - kCs2 * ugr) / kCs2);
+      const double fv = w3(i) * (ugr + cF / kCs2 + (cu * cg - kCs2 * ugr) / kCs2);
+      accum3(i, fi, eq, fv, rates, m);
     }
-    mrt3(f, eq, fv, rates);
+    populations3(m, f);
     // push streaming; walls in z
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
@@ -485,6 +483,40 @@ __global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const u
       }
     }
   }
+}
+
+// ---------------------------------------------------------------- k3_colgh
+// Phase-field and surfactant lattices: equilibria with phi v, psi v, forcing
+// with the backward differences of phi v, psi v and of the sources (from the
+// history planes of this step, hcur, and of the previous one, hprev), the
+// rest population stored relative to phi, psi of this step.
+template <class S>
+__global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
+                                               const S* __restrict__ pin, S* __restrict__ pout,
+                                               const double* __restrict__ pp, const double* __restrict__ pprev,
+                                               const double* __restrict__ hcur, const double* __restrict__ hprev,
+                                               int have_hist) {
+  const P3& p = *pp_;
+  const int N = p.N;
+  const int n = blockIdx.x * kT + threadIdx.x;
+  if (n >= N) return;
+  if (p.has_solid && solid[n]) return;
+  const double ph = pp[n], ps = pp[N + n];
+  const double v[3] = {hcur[(size_t)3 * N + n], hcur[(size_t)4 * N + n], hcur[(size_t)5 * N + n]};
+  const double Rphi = hcur[(size_t)6 * N + n], Rpsi = hcur[(size_t)7 * N + n];
+  double dph[3] = {0, 0, 0}, dps[3] = {0, 0, 0}, dRp = 0.0, dRs = 0.0;
+  if (have_hist) {
+    const double php = pprev[n], psp = pprev[N + n];
+    for (int d = 0; d < 3; ++d) {
+      const double vh = hprev[(size_t)(3 + d) * N + n];
+      dph[d] = ph * v[d] - php * vh;
+      dps[d] = ps * v[d] - psp * vh;
+    }
+    dRp = Rphi - hprev[(size_t)6 * N + n];
+    dRs = Rpsi - hprev[(size_t)7 * N + n];
+  }
+  const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
+  double m[Q3], f[Q3];
   // --- phase-field and surfactant lattices (rest population stored relative to phi, psi of this step)
   for (int lat = 1; lat <= 2; ++lat) {
     if (lat == 2 && !p.surf) {
@@ -507,12 +539,15 @@ __global__ __launch_bounds__(kT) void k3_col(const P3* __restrict__ pp_, const u
     const int base = 19 * lat;
     const double cref = lat == 1 ? pprev[n] : pprev[N + n];   // the shift of the stored rest population
 #pragma unroll
+    for (int k = 0; k < Q3; ++k) m[k] = 0.0;
+#pragma unroll
     for (int i = 0; i < Q3; ++i) {
-      f[i] = ld(pin, (size_t)(base + i) * N + n) + (i == 0 ? cref : 0.0);
-      eq[i] = (i == 0 ? c + (w3(0) - 1.0) * eta * c : w3(i) * eta * c) + w3(i) * cdot3(i, c * v[0], c * v[1], c * v[2]) / kCs2;
-      fv[i] = w3(i) * cdot3(i, dj[0], dj[1], dj[2]) / kCs2;
+      const double fi = ld(pin, (size_t)(base + i) * N + n) + (i == 0 ? cref : 0.0);
+      const double eq = (i == 0 ? c + (w3(0) - 1.0) * eta * c : w3(i) * eta * c) + w3(i) * cdot3(i, c * v[0], c * v[1], c * v[2]) / kCs2;
+      const double fv = w3(i) * cdot3(i, dj[0], dj[1], dj[2]) / kCs2;
+      accum3(i, fi, eq, fv, r5, m);
     }
-    mrt3(f, eq, fv, r5);
+    populations3(m, f);
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
       double val = f[i] + w3(i) * extra;
@@ -656,14 +691,16 @@ __global__ __launch_bounds__(kT) void k3_inv(const P3* __restrict__ pp_, const u
     part[8 * blockIdx.x + 6] = smax[0];
   }
 }
-__global__ void k3_inv_fin(const double* __restrict__ part, int nb, double* __restrict__ out) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(64) void k3_inv_fin(const double* __restrict__ part, int nb, double* __restrict__ out) {
   double s[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int b = 0; b < nb; ++b) {
+  for (int b = threadIdx.x; b < nb; b += 64) {
     for (int k = 0; k < 6; ++k) s[k] += part[8 * b + k];
     s[6] = fmax(s[6], part[8 * b + 6]);
   }
-  for (int k = 0; k < 7; ++k) out[k] = s[k];
+  for (int k = 0; k < 6; ++k) s[k] = wave_sum(s[k]);
+  for (int off = 32; off > 0; off >>= 1) s[6] = fmax(s[6], __shfl_down(s[6], off, 64));
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 7; ++k) out[k] = s[k];
 }
 
 int nblk(long long n) { return (int)((n + kT - 1) / kT); }
@@ -810,10 +847,12 @@ hipError_t step3(lbm3d_handle* h) {
   hipLaunchKernelGGL(k3_mu, dim3(rb), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid, (const double*)s.pp[c],
                      s.mu, s.part);
   hipLaunchKernelGGL(k3_fin, dim3(1), dim3(64), 0, h->stream, s.dp, (const double*)s.part, rb, s.sc);
-  hipLaunchKernelGGL((k3_col<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
-                     (const S*)s.pops[c], (S*)s.pops[c ^ 1],
-                     (const double*)s.pp[c], (const double*)s.pp[c ^ 1], (const double*)s.mu, (const double*)s.uh[c ^ 1],
-                     s.uh[c], (const Scal3*)s.sc, h->have_hist);
+  hipLaunchKernelGGL((k3_colf<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
+                     (const S*)s.pops[c], (S*)s.pops[c ^ 1], (const double*)s.pp[c], (const double*)s.mu,
+                     (const double*)s.uh[c ^ 1], s.uh[c], (const Scal3*)s.sc, h->have_hist);
+  hipLaunchKernelGGL((k3_colgh<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
+                     (const S*)s.pops[c], (S*)s.pops[c ^ 1], (const double*)s.pp[c], (const double*)s.pp[c ^ 1],
+                     (const double*)s.uh[c], (const double*)s.uh[c ^ 1], h->have_hist);
   hipLaunchKernelGGL((k3_mom<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
                      (const S*)s.pops[c ^ 1],
                      (const double*)s.pp[c], s.pp[c ^ 1]);
@@ -1041,9 +1080,11 @@ int lbm3d_set_solid(lbm3d_handle* h, const uint8_t* mask, size_t n) {
 int lbm3d_bytes_per_node_step(lbm3d_handle* h, double* bytes) {
   if (!h || !bytes) return fail3(h, LBM_E_ARG, "null argument");
   const double sb = h->prm.precision == LBM_FP64 ? 8.0 : 4.0;
-  // k3_mu: phi/psi read, mu written; k3_col: 57 populations, phi/psi (two steps), mu, 8 history planes read,
-  // 57 populations and 8 history planes written; k3_mom: 38 populations and phi/psi read, phi/psi written
-  *bytes = (2 * 8 + 2 * 8) + (57 * sb + 4 * 8 + 2 * 8 + 8 * 8 + 57 * sb + 8 * 8) + (38 * sb + 2 * 8 + 2 * 8);
+  // k3_mu: phi/psi read, mu written; k3_colf: 19 populations, phi/psi, mu and the previous u read, 19
+  // populations and 8 history planes written; k3_colgh: 38 populations, phi/psi of two steps and 5 history
+  // planes of two steps read, 38 populations written; k3_mom: 38 populations and phi/psi read, phi/psi written
+  *bytes = (2 * 8 + 2 * 8) + (19 * sb + 2 * 8 + 2 * 8 + 3 * 8 + 19 * sb + 8 * 8) +
+           (38 * sb + 4 * 8 + 10 * 8 + 38 * sb) + (38 * sb + 2 * 8 + 2 * 8);
   return LBM_OK;
 }
 
