@@ -150,7 +150,7 @@ ALGO_BYTES_3D = {"fp32": 2 * (57 * 4 + 5 * 4), "fp64": 2 * (57 * 8 + 5 * 8)}
 
 
 def grid3d_run(n, prec, steps, warmup):
-    """The 3-D (D3Q19) step on an n^3 periodic drop: whole-step rate (its four
+    """The 3-D (D3Q19) step on an n^3 periodic drop: whole-step rate (its five
     kernels) on the algorithmic bytes of a D3Q19 node-step."""
     from paper_2609_26332_amd import inputs, lbm3d
 
@@ -167,7 +167,7 @@ def grid3d_run(n, prec, steps, warmup):
     out = {"workload": "periodic drop %d^3, D3Q19, %s storage" % (n, prec.upper()), "mlups": round(N * steps / wall / 1e6, 1),
            "ms_per_step": round(ms, 5), "bytes_per_node_step": ALGO_BYTES_3D[prec], "achieved": round(gbs, 2),
            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "design_bytes_per_node_step": sim.bytes_per_node_step(),
-           "what": "whole step (four kernels), wall clock over %d steps" % steps,
+           "what": "whole step (five kernels), wall clock over %d steps" % steps,
            "nonfinite": sim.invariants(check=False)["nonfinite"]}
     sim.close()
     return out

@@ -104,7 +104,7 @@ def test_fp32_parity(lbm, name):
 FP32_TOL = {"spreading_ratio1000_90": 5e-5, "spreading_ratio1000_60_adsorbing": 5e-5}
 
 
-@pytest.mark.parametrize("rows", [4, 8, 16])
+@pytest.mark.parametrize("rows", [4, 8, 16, 32, 64])
 def test_tile_heights(lbm, rows):
     """Every tile height of the fused step kernel, on a periodic grid and on a
     walled grid whose sizes are not multiples of the tile (ragged tiles in x
