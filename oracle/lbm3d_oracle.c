@@ -51,7 +51,7 @@
 #include <string.h>
 
 #define Q 19
-#define PAR_MIN_NODES 4096   /* node loops on OpenMP threads from this size on (results do not depend on it) */
+#define PAR_MIN_NODES 512   /* node loops on OpenMP threads from this size on (results do not depend on it) */
 
 static int CV[Q][3];
 static double WQ[Q];
@@ -423,6 +423,7 @@ void orc3_get_populations(const orc3_sim* s, double* out) {
 /* O1-O6 at the current state */
 static void macro(orc3_sim* s) {
   int nx = s->nx, ny = s->ny, nz = s->nz, N = s->N, cols = nx * ny;
+#pragma omp parallel for if (N >= PAR_MIN_NODES)
   for (int n = 0; n < N; ++n) {
     double a = 0.0, b = 0.0;
     for (int i = 0; i < Q; ++i) { a += s->g[(size_t)i * N + n]; b += s->h[(size_t)i * N + n]; }
@@ -522,8 +523,8 @@ static void macro(orc3_sim* s) {
 static void step_once(orc3_sim* s) {
   int nx = s->nx, ny = s->ny, nz = s->nz, N = s->N;
   macro(s);
-  /* O7 */
-  double sumR = 0.0, orth = 0.0;
+  /* O7 (the identities' sums afterwards, in node order) */
+#pragma omp parallel for if (N >= PAR_MIN_NODES)
   for (int n = 0; n < N; ++n) {
     if (is_solid(s, n)) { s->Rphi[n] = s->Rpsi[n] = 0.0; continue; }
     double ph = s->phi[n], ps = s->psi[n], hp = hprime(s, ph);
@@ -534,6 +535,11 @@ static void step_once(orc3_sim* s) {
                                              - 0.5 * s->W * ph * ph + s->mubar)
                              + s->p.M_psi * s->Tpsi[n]
                          : 0.0;
+  }
+  double sumR = 0.0, orth = 0.0;
+  for (int n = 0; n < N; ++n) {
+    if (is_solid(s, n)) continue;
+    double hp = hprime(s, s->phi[n]);
     sumR += s->Rpsi[n];
     orth += hp * (s->mu_phi[n] - s->lambda * hp);
   }
@@ -598,7 +604,8 @@ static void step_once(orc3_sim* s) {
       for (int i = 0; i < Q; ++i) s->h[(size_t)i * N + n] = out[i];
     }
   }
-  /* O9: push streaming; walls in z */
+  /* O9: push streaming; walls in z (a permutation of the population slots: layers write disjoint targets) */
+#pragma omp parallel for if (N >= PAR_MIN_NODES)
   for (int z = 0; z < nz; ++z)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {

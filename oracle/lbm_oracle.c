@@ -45,7 +45,7 @@
 /* Node loops run on OpenMP threads only on grids large enough to pay for the
  * fork and join (smaller grids are faster on one thread); results do not
  * depend on it, every threaded loop writes per-node values only. */
-#define ORC_PAR_MIN_NODES 16384
+#define ORC_PAR_MIN_NODES 1024
 static int g_parallel = 1;   /* orc_set_parallel(0): every loop on the calling thread */
 /* D2Q9 velocities c_i, weights w_i, opposite and y-mirrored directions. */
 static const int EX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -453,6 +453,7 @@ void orc_get_populations(const orc_sim* s, double* out) {
 static void macro(orc_sim* s) {
   int nx = s->nx, ny = s->ny, N = s->N;
   /* O1: zeroth moments */
+#pragma omp parallel for if (g_parallel && s->N >= ORC_PAR_MIN_NODES)
   for (int n = 0; n < N; ++n) {
     double a = 0.0, b = 0.0;
     for (int i = 0; i < Q; ++i) { a += s->g[i * N + n]; b += s->h[i * N + n]; }
@@ -551,8 +552,9 @@ static void macro(orc_sim* s) {
 static void step_once(orc_sim* s) {
   int nx = s->nx, ny = s->ny, N = s->N;
   macro(s);
-  /* O7: sources (with the wall-flux terms on wall rows) and the identities */
-  double sumR = 0.0, orth = 0.0;
+  /* O7: sources (with the wall-flux terms on wall rows), then the identities'
+   * sums in node order */
+#pragma omp parallel for if (g_parallel && s->N >= ORC_PAR_MIN_NODES)
   for (int n = 0; n < N; ++n) {
     double ph = s->phi[n], ps = s->psi[n], hp = hprime(s, ph);
     s->Rphi[n] = s->p.M_phi * (-4.0 * s->beta * (1.0 - ps) * (ph * ph * ph - ph) - s->W * ps * ph + s->lambda * hp)
@@ -570,6 +572,10 @@ static void step_once(orc_sim* s) {
       s->Rphi[n] += sp;
       s->Rpsi[n] += ss;
     }
+  }
+  double sumR = 0.0, orth = 0.0;
+  for (int n = 0; n < N; ++n) {
+    double hp = hprime(s, s->phi[n]);
     sumR += s->Rpsi[n];
     orth += hp * (s->mu_phi[n] - s->lambda * hp);
   }
@@ -637,7 +643,8 @@ static void step_once(orc_sim* s) {
       for (int i = 0; i < Q; ++i) s->h[i * N + n] = out[i];
     }
   }
-  /* O9: streaming */
+  /* O9: streaming (a permutation of the population slots: rows write disjoint targets) */
+#pragma omp parallel for if (g_parallel && s->N >= ORC_PAR_MIN_NODES)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       int n = y * nx + x;
