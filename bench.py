@@ -347,7 +347,7 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=20, help="event-timed steps for the kernel figures")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline batch (profiling aid)")
-    ap.add_argument("--workload", default="all", choices=["all", "batch", "grid4096", "grid3d", "surrogate"],
+    ap.add_argument("--workload", default="all", choices=["all", "batch", "grid4096", "grid3d", "surrogate", "mlp"],
                     help="profiling aid: one workload only")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16"],
                     help="profiling aid: storage of the single workload run with --workload")
@@ -372,6 +372,9 @@ def main():
 
     if args.workload == "surrogate":
         print(json.dumps(surrogate_sweep()), flush=True)
+        return
+    if args.workload == "mlp":
+        print(json.dumps(surrogate_rate()), flush=True)
         return
     if args.workload == "grid3d":
         p3 = args.precision if args.precision in ("fp32", "fp64") else "fp32"

@@ -10,12 +10,14 @@
 //            sums, in a fixed order
 //   k3_colf  gradients of rho and of both potentials, the force (eq_Fs0),
 //            velocity and pressure, the sources and the advecting velocity
-//            (into the history planes), the flow lattice's MRT collision in
-//            FP64 and push streaming into the other population buffer with
-//            half-way bounce-back, moving-wall and free-slip walls
+//            (into the history planes), the flow lattice's MRT collision and
+//            push streaming into the other population buffer with half-way
+//            bounce-back, moving-wall and free-slip walls
 //   k3_colgh the phase-field and surfactant lattices: backward differences
 //            from the history planes of this step and the previous one, MRT
-//            collisions in FP64, push streaming
+//            collisions, push streaming
+//   (macroscopic fields, stencils and sources in FP64; the collisions in the
+//   storage type, FP32 or FP64)
 //            (two kernels rather than one: one kernel holding all three
 //            lattices needs more than 256 registers a lane, one wave per SIMD)
 //   k3_mom   phi, psi of the new state (zeroth moments) into the other FP64
@@ -76,6 +78,13 @@ __host__ __device__ constexpr int mirz3(int i) {
   return v[i];
 }
 constexpr double kCs2 = 1.0 / 3.0;
+// The velocity set as device tables, for loops over directions that are not unrolled.
+__constant__ int kC3[Q3][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                               {1, 1, 0},  {-1, 1, 0}, {1, -1, 0}, {-1, -1, 0}, {1, 0, 1},  {-1, 0, 1}, {1, 0, -1},
+                               {-1, 0, -1}, {0, 1, 1}, {0, -1, 1}, {0, 1, -1}, {0, -1, -1}};
+__constant__ double kW3[Q3] = {1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
 struct P3 {
   int nx, ny, nz, N, periodic_z, wet_b, wet_t, freeslip_b, freeslip_t, surf, linear, adv_raw, s2_local, phi_hold;
@@ -149,6 +158,24 @@ __device__ __forceinline__ int nbr(const P3& p, const unsigned char* __restrict_
   if (p.has_solid && solid[m]) return -3;
   return m;
 }
+// The same for a direction given as (cx, cy, cz).
+__device__ __forceinline__ int nbr_c(const P3& p, const unsigned char* __restrict__ solid, int x, int y, int z, int cx,
+                                     int cy, int cz, int* colnode) {
+  const int xx = wrap(x + cx, p.nx), yy = wrap(y + cy, p.ny);
+  int zz = z + cz;
+  *colnode = (z * p.ny + yy) * p.nx + xx;
+  if (p.periodic_z) zz = wrap(zz, p.nz);
+  else if (zz < 0) return -1;
+  else if (zz >= p.nz) return -2;
+  const int m = (zz * p.ny + yy) * p.nx + xx;
+  if (p.has_solid && solid[m]) return -3;
+  return m;
+}
+// Nodes whose 18 neighbours are all fluid nodes inside the box: no solid mask,
+// and not in the first or last layer of a box walled in z.
+__device__ __forceinline__ bool plain_stencil(const P3& p, int z) {
+  return !p.has_solid && (p.periodic_z || (z > 0 && z < p.nz - 1));
+}
 
 template <class S>
 __device__ __forceinline__ double ld(const S* a, size_t k) { return (double)a[k]; }
@@ -185,26 +212,38 @@ __global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const un
     const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
     const double ph = pp[n], ps = pp[N + n];
     double l0p = 0.0, l0s = 0.0, tp = 0.0, ts = 0.0;
+    if (plain_stencil(p, z)) {   // interior: plain stencil, unrolled
 #pragma unroll
-    for (int i = 1; i < Q3; ++i) {
-      int cn;
-      const int m = nbr(p, solid, x, y, z, i, &cn);
-      const double wt = 2.0 * w3(i) / kCs2;
-      if (m >= 0) {
+      for (int i = 1; i < Q3; ++i) {
+        const int m = (wrap(z + cz3(i), p.nz) * p.ny + wrap(y + cy3(i), p.ny)) * p.nx + wrap(x + cx3(i), p.nx);
+        const double wt = 2.0 * w3(i) / kCs2;
         l0p += wt * (pp[m] - ph);
         l0s += wt * (pp[N + m] - ps);
-      } else if (m == -3) {   // solid node: link-wise mirror, wall flux of this node
-        if (p.solid_wet) {
-          tp += wt * wall_jphi(p, ph, ps);
-          ts += wt * wall_jpsi(p, ph, ps);
-        }
-      } else {
-        l0p += wt * (pp[cn] - ph);
-        l0s += wt * (pp[N + cn] - ps);
-        if ((m == -1 && p.wet_b) || (m == -2 && p.wet_t)) {
-          const double fph = pp[cn], fps = pp[N + cn];
-          tp += wt * wall_jphi(p, fph, fps);
-          ts += wt * wall_jpsi(p, fph, fps);
+      }
+    } else {   // next to a wall or a solid node: the general stencil, same order, rolled
+      const double jp_self = p.solid_wet ? wall_jphi(p, ph, ps) : 0.0;
+      const double js_self = p.solid_wet ? wall_jpsi(p, ph, ps) : 0.0;
+#pragma unroll 1
+      for (int i = 1; i < Q3; ++i) {
+        int cn;
+        const int m = nbr_c(p, solid, x, y, z, kC3[i][0], kC3[i][1], kC3[i][2], &cn);
+        const double wt = 2.0 * kW3[i] / kCs2;
+        if (m >= 0) {
+          l0p += wt * (pp[m] - ph);
+          l0s += wt * (pp[N + m] - ps);
+        } else if (m == -3) {   // solid node: link-wise mirror, wall flux of this node
+          if (p.solid_wet) {
+            tp += wt * jp_self;
+            ts += wt * js_self;
+          }
+        } else {
+          l0p += wt * (pp[cn] - ph);
+          l0s += wt * (pp[N + cn] - ps);
+          if ((m == -1 && p.wet_b) || (m == -2 && p.wet_t)) {
+            const double fph = pp[cn], fps = pp[N + cn];
+            tp += wt * wall_jphi(p, fph, fps);
+            ts += wt * wall_jpsi(p, fph, fps);
+          }
         }
       }
     }
@@ -267,7 +306,8 @@ __global__ __launch_bounds__(64) void k3_fin(const P3* __restrict__ pp_, const d
 // times q_o = (1 - s_o) f_i + s_o feq_i + (1 - s_o / 2) v_i.  The post-collision
 // moments accumulate in one array while the populations stream in, and no
 // population array is kept.
-__device__ __forceinline__ void accum3(int i, const double* q, double* m) {
+template <class T>
+__device__ __forceinline__ void accum3(int i, const T* q, T* m) {
   const int a = cx3(i), b = cy3(i), c = cz3(i);
   m[0] += q[0];
   if (a) m[1] += a * q[1];
@@ -283,35 +323,37 @@ __device__ __forceinline__ void accum3(int i, const double* q, double* m) {
   if (a && c) { m[11] += c * q[3]; m[14] += a * q[3]; m[17] += q[4]; }
   if (b && c) { m[13] += c * q[3]; m[15] += b * q[3]; m[18] += q[4]; }
 }
-__device__ __forceinline__ void accum3(int i, double f, double feq, double v, const double* rate5, double* m) {
-  double q[5];
+template <class T>
+__device__ __forceinline__ void accum3(int i, T f, T feq, T v, const T* rate5, T* m) {
+  T q[5];
 #pragma unroll
-  for (int o = 0; o < 5; ++o) q[o] = (1.0 - rate5[o]) * f + rate5[o] * feq + (1.0 - 0.5 * rate5[o]) * v;
+  for (int o = 0; o < 5; ++o) q[o] = (T(1) - rate5[o]) * f + rate5[o] * feq + (T(1) - T(0.5) * rate5[o]) * v;
   accum3(i, q, m);
 }
 // Populations from raw moments (the inverse of moments3).
-__device__ __forceinline__ void populations3(const double* m, double* f) {
+template <class T>
+__device__ __forceinline__ void populations3(const T* m, T* f) {
   // edges of plane (a, b): E0 = m_aabb, Ea = m_abb, Eb = m_aab, Eab = m_ab
-  const double E[3][4] = {{m[16], m[12], m[10], m[7]},    // xy: xxyy, yyx, xxy, xy
+  const T E[3][4] = {{m[16], m[12], m[10], m[7]},    // xy: xxyy, yyx, xxy, xy
                           {m[17], m[14], m[11], m[8]},    // xz: xxzz, zzx, xxz, xz
                           {m[18], m[15], m[13], m[9]}};   // yz: yyzz, zzy, yyz, yz
 #pragma unroll
   for (int pl = 0; pl < 3; ++pl)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double sa = (k & 1) ? -1.0 : 1.0, sb = (k & 2) ? -1.0 : 1.0;
-      f[7 + 4 * pl + k] = 0.25 * (E[pl][0] + sa * E[pl][1] + sb * E[pl][2] + sa * sb * E[pl][3]);
+      const T sa = (k & 1) ? T(-1) : T(1), sb = (k & 2) ? T(-1) : T(1);
+      f[7 + 4 * pl + k] = T(0.25) * (E[pl][0] + sa * E[pl][1] + sb * E[pl][2] + sa * sb * E[pl][3]);
     }
   // faces: F0 = m_aa - (edge sums of the two planes through a), F1 = m_a - (their c_a sums)
-  const double F0x = m[4] - m[16] - m[17], F1x = m[1] - m[12] - m[14];
-  const double F0y = m[5] - m[16] - m[18], F1y = m[2] - m[10] - m[15];
-  const double F0z = m[6] - m[17] - m[18], F1z = m[3] - m[11] - m[13];
-  f[1] = 0.5 * (F0x + F1x);
-  f[2] = 0.5 * (F0x - F1x);
-  f[3] = 0.5 * (F0y + F1y);
-  f[4] = 0.5 * (F0y - F1y);
-  f[5] = 0.5 * (F0z + F1z);
-  f[6] = 0.5 * (F0z - F1z);
+  const T F0x = m[4] - m[16] - m[17], F1x = m[1] - m[12] - m[14];
+  const T F0y = m[5] - m[16] - m[18], F1y = m[2] - m[10] - m[15];
+  const T F0z = m[6] - m[17] - m[18], F1z = m[3] - m[11] - m[13];
+  f[1] = T(0.5) * (F0x + F1x);
+  f[2] = T(0.5) * (F0x - F1x);
+  f[3] = T(0.5) * (F0y + F1y);
+  f[4] = T(0.5) * (F0y - F1y);
+  f[5] = T(0.5) * (F0z + F1z);
+  f[6] = T(0.5) * (F0z - F1z);
   f[0] = m[0] - (m[4] + m[5] + m[6]) + (m[16] + m[17] + m[18]);
 }
 __device__ __forceinline__ double cdot3(int i, double ax, double ay, double az) {
@@ -334,47 +376,69 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
   M.ps = pp[N + n];
   M.rho = rho_of(p, M.ph);
   double gr[3] = {0, 0, 0}, gmp[3] = {0, 0, 0}, gms[3] = {0, 0, 0}, tp = 0.0, ts = 0.0, l0s = 0.0;
+  // Interior nodes take the plain stencil, unrolled; nodes next to a wall or a
+  // solid node take the general one (the same arithmetic per direction, in the
+  // same order), in a loop kept rolled so the kernel's code stays small.
+  if (plain_stencil(p, z)) {
 #pragma unroll
-  for (int i = 1; i < Q3; ++i) {
-    int cn;
-    const int m = nbr(p, solid, x, y, z, i, &cn);
-    double r, mp, ms, pn;
-    if (m >= 0) {
-      r = rho_of(p, pp[m]);
-      mp = mu[m];
-      ms = mu[N + m];
-      pn = pp[N + m];
-    } else if (m == -3) {   // solid node: ghost values of this node
-      const double jp = p.solid_wet ? wall_jphi(p, M.ph, M.ps) : 0.0;
-      r = rho_of(p, M.ph + jp / p.kappa);
-      mp = mu[n];
-      ms = mu[N + n];
-      pn = M.ps;
-      if (p.solid_wet) {
-        tp += 2.0 * w3(i) / kCs2 * jp;
-        ts += 2.0 * w3(i) / kCs2 * wall_jpsi(p, M.ph, M.ps);
-      }
-    } else {
-      const bool wet = (m == -1 && p.wet_b) || (m == -2 && p.wet_t);
-      const double fph = pp[cn], fps = pp[N + cn];
-      const double jp = wet ? wall_jphi(p, fph, fps) : 0.0;
-      r = rho_of(p, fph + jp / p.kappa);
-      mp = mu[cn];
-      ms = mu[N + cn];
-      pn = fps;
-      if (wet) {
-        tp += 2.0 * w3(i) / kCs2 * jp;
-        ts += 2.0 * w3(i) / kCs2 * wall_jpsi(p, fph, fps);
-      }
-    }
-    const double c[3] = {(double)cx3(i), (double)cy3(i), (double)cz3(i)};
+    for (int i = 1; i < Q3; ++i) {
+      const int m = (wrap(z + cz3(i), p.nz) * p.ny + wrap(y + cy3(i), p.ny)) * p.nx + wrap(x + cx3(i), p.nx);
+      const double r = rho_of(p, pp[m]), mp = mu[m], ms = mu[N + m], pn = pp[N + m];
+      const double c[3] = {(double)cx3(i), (double)cy3(i), (double)cz3(i)};
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      gr[d] += w3(i) * c[d] * r / kCs2;
-      gmp[d] += w3(i) * c[d] * mp / kCs2;
-      gms[d] += w3(i) * c[d] * ms / kCs2;
+      for (int d = 0; d < 3; ++d) {
+        gr[d] += w3(i) * c[d] * r / kCs2;
+        gmp[d] += w3(i) * c[d] * mp / kCs2;
+        gms[d] += w3(i) * c[d] * ms / kCs2;
+      }
+      l0s += 2.0 * w3(i) / kCs2 * (pn - M.ps);
     }
-    l0s += 2.0 * w3(i) / kCs2 * (pn - M.ps);
+  } else {
+    // wall fluxes of this node (for links into solid nodes), evaluated once
+    const double jp_self = p.solid_wet ? wall_jphi(p, M.ph, M.ps) : 0.0;
+    const double js_self = p.solid_wet ? wall_jpsi(p, M.ph, M.ps) : 0.0;
+#pragma unroll 1
+    for (int i = 1; i < Q3; ++i) {
+      const int cx = kC3[i][0], cy = kC3[i][1], cz = kC3[i][2];
+      const double wi = kW3[i];
+      int cn;
+      const int m = nbr_c(p, solid, x, y, z, cx, cy, cz, &cn);
+      double r, mp, ms, pn;
+      if (m >= 0) {
+        r = rho_of(p, pp[m]);
+        mp = mu[m];
+        ms = mu[N + m];
+        pn = pp[N + m];
+      } else if (m == -3) {   // solid node: ghost values of this node
+        r = rho_of(p, M.ph + jp_self / p.kappa);
+        mp = mu[n];
+        ms = mu[N + n];
+        pn = M.ps;
+        if (p.solid_wet) {
+          tp += 2.0 * wi / kCs2 * jp_self;
+          ts += 2.0 * wi / kCs2 * js_self;
+        }
+      } else {
+        const bool wet = (m == -1 && p.wet_b) || (m == -2 && p.wet_t);
+        const double fph = pp[cn], fps = pp[N + cn];
+        const double jp = wet ? wall_jphi(p, fph, fps) : 0.0;
+        r = rho_of(p, fph + jp / p.kappa);
+        mp = mu[cn];
+        ms = mu[N + cn];
+        pn = fps;
+        if (wet) {
+          tp += 2.0 * wi / kCs2 * jp;
+          ts += 2.0 * wi / kCs2 * wall_jpsi(p, fph, fps);
+        }
+      }
+      const double c[3] = {(double)cx, (double)cy, (double)cz};
+      for (int d = 0; d < 3; ++d) {
+        gr[d] += wi * c[d] * r / kCs2;
+        gmp[d] += wi * c[d] * mp / kCs2;
+        gms[d] += wi * c[d] * ms / kCs2;
+      }
+      l0s += 2.0 * wi / kCs2 * (pn - M.ps);
+    }
   }
   const double G[3] = {p.gx, p.gy, p.gz};
   double j[3] = {0, 0, 0}, snz = 0.0;
@@ -404,10 +468,12 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
 // ---------------------------------------------------------------- k3_colf
 // Macroscopic state, sources and advecting velocity of the step (into the
 // history planes hout), then the flow lattice's collision and streaming.
-// Two waves per SIMD: in FP64 storage a few registers spill (12 bytes a lane),
-// against one wave per SIMD without the bound.
+// Waves per SIMD the flow kernel is built for: four in FP32 storage (one
+// register spills), two in FP64.
 template <class S>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) void k3_colf(
+constexpr int kColfWaves = sizeof(S) == 8 ? 2 : 4;
+template <class S>
+__global__ __launch_bounds__(kT, kColfWaves<S>) void k3_colf(
     const P3* __restrict__ pp_, const unsigned char* __restrict__ solid, const S* __restrict__ pin, S* __restrict__ pout,
     const double* __restrict__ pp, const double* __restrict__ mu, const double* __restrict__ hin, double* __restrict__ hout,
     const Scal3* __restrict__ sc, int have_hist) {
@@ -439,18 +505,19 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) void k3
   hout[(size_t)7 * N + n] = Rpsi;
 
   const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
-  double m[Q3], f[Q3];
+  using T = S;   // collision arithmetic: the storage type (FP32 or FP64)
+  T m[Q3], f[Q3];
   {
-    double rates[5];
-    for (int k = 0; k < 5; ++k) rates[k] = p.sf[k];
+    T rates[5];
+    for (int k = 0; k < 5; ++k) rates[k] = (T)p.sf[k];
     if (p.s2_local) {
       const double mud = p.mu_g + (p.mu_l - p.mu_g) * liquid_frac(p, ph);
-      rates[2] = 1.0 / (3.0 * mud / rho + 0.5);
+      rates[2] = (T)(1.0 / (3.0 * mud / rho + 0.5));
     }
     const double uu = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
     const double ugr = M.u[0] * M.gr[0] + M.u[1] * M.gr[1] + M.u[2] * M.gr[2];
 #pragma unroll
-    for (int k = 0; k < Q3; ++k) m[k] = 0.0;
+    for (int k = 0; k < Q3; ++k) m[k] = T(0);
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
       const double fi = ld(pin, (size_t)i * N + n);
@@ -459,26 +526,27 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) void k3
       const double eq = M.pr / kCs2 * (w3(i) - (i == 0 ? 1.0 : 0.0)) + rho * w3(i) * su;
       const double cg = cdot3(i, M.gr[0], M.gr[1], M.gr[2]), cF = cdot3(i, M.F[0], M.F[1], M.F[2]);
       const double fv = w3(i) * (ugr + cF / kCs2 + (cu * cg - kCs2 * ugr) / kCs2);
-      accum3(i, fi, eq, fv, rates, m);
+      accum3<T>(i, (T)fi, (T)eq, (T)fv, rates, m);   // pressure-based: f_i are of the order of p w_i / c_s^2
     }
-    populations3(m, f);
+    populations3<T>(m, f);
     // push streaming; walls in z
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
+      const double fo = (double)f[i];
       const int zz = z + cz3(i);
       const int xx = wrap(x + cx3(i), p.nx), yy = wrap(y + cy3(i), p.ny);
       const int t = (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx;
       if ((p.periodic_z || (zz >= 0 && zz < p.nz)) && p.has_solid && solid[t]) {
-        pout[(size_t)opp3(i) * N + n] = (S)f[i];   // half-way bounce-back at a solid node at rest
+        pout[(size_t)opp3(i) * N + n] = (S)fo;   // half-way bounce-back at a solid node at rest
       } else if (p.periodic_z || (zz >= 0 && zz < p.nz)) {
-        pout[(size_t)i * N + t] = (S)f[i];
+        pout[(size_t)i * N + t] = (S)fo;
       } else {
         const bool bot = zz < 0;
         if (bot ? p.freeslip_b : p.freeslip_t) {
-          pout[(size_t)mirz3(i) * N + (z * p.ny + yy) * p.nx + xx] = (S)f[i];
+          pout[(size_t)mirz3(i) * N + (z * p.ny + yy) * p.nx + xx] = (S)fo;
         } else {
           const double uw = bot ? p.uw_b : p.uw_t;
-          pout[(size_t)opp3(i) * N + n] = (S)(f[i] - 2.0 * w3(i) * rho * (cx3(i) * uw) / kCs2);
+          pout[(size_t)opp3(i) * N + n] = (S)(fo - 2.0 * w3(i) * rho * (cx3(i) * uw) / kCs2);
         }
       }
     }
@@ -516,7 +584,8 @@ __global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const
     dRs = Rpsi - hprev[(size_t)7 * N + n];
   }
   const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
-  double m[Q3], f[Q3];
+  using T = S;   // collision arithmetic: the storage type (FP32 or FP64)
+  T m[Q3], f[Q3];
   // --- phase-field and surfactant lattices (rest population stored relative to phi, psi of this step)
   for (int lat = 1; lat <= 2; ++lat) {
     if (lat == 2 && !p.surf) {
@@ -534,24 +603,26 @@ __global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const
     const double c = lat == 1 ? ph : ps;
     const double eta = lat == 1 ? p.eta_phi : p.eta_psi;
     const double* dj = lat == 1 ? dph : dps;
-    const double* r5 = lat == 1 ? p.sg : p.sh;
+    T r5[5];
+    for (int k = 0; k < 5; ++k) r5[k] = (T)(lat == 1 ? p.sg[k] : p.sh[k]);
     const double extra = lat == 1 ? Rphi + 0.5 * dRp : Rpsi + 0.5 * dRs;
     const int base = 19 * lat;
     const double cref = lat == 1 ? pprev[n] : pprev[N + n];   // the shift of the stored rest population
 #pragma unroll
-    for (int k = 0; k < Q3; ++k) m[k] = 0.0;
+    for (int k = 0; k < Q3; ++k) m[k] = T(0);
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
-      const double fi = ld(pin, (size_t)(base + i) * N + n) + (i == 0 ? cref : 0.0);
-      const double eq = (i == 0 ? c + (w3(0) - 1.0) * eta * c : w3(i) * eta * c) + w3(i) * cdot3(i, c * v[0], c * v[1], c * v[2]) / kCs2;
+      // rest population shifted by c (the collision maps g - c e_0 to its image
+      // minus c e_0), so the collision sees increments only
+      const double fi = ld(pin, (size_t)(base + i) * N + n) + (i == 0 ? cref - c : 0.0);
+      const double eq = (i == 0 ? (w3(0) - 1.0) * eta * c : w3(i) * eta * c) + w3(i) * cdot3(i, c * v[0], c * v[1], c * v[2]) / kCs2;
       const double fv = w3(i) * cdot3(i, dj[0], dj[1], dj[2]) / kCs2;
-      accum3(i, fi, eq, fv, r5, m);
+      accum3<T>(i, (T)fi, (T)eq, (T)fv, r5, m);
     }
-    populations3(m, f);
+    populations3<T>(m, f);
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
-      double val = f[i] + w3(i) * extra;
-      if (i == 0) val -= c;
+      const double val = (double)f[i] + w3(i) * extra;   // the rest population stays stored relative to c
       const int zz = z + cz3(i);
       const int xx = wrap(x + cx3(i), p.nx), yy = wrap(y + cy3(i), p.ny);
       const int t = (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx;

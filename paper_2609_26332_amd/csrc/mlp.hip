@@ -191,15 +191,37 @@ __global__ __launch_bounds__(kThreads) void k_loss_final(const float* __restrict
   if (threadIdx.x == 0) *loss = s * *inv;
 }
 
-// db[j] = sum over rows of dz[row][j] (member blockIdx.y: dz rows * cols apart, db kParams apart)
+// db[j] = sum over rows of dz[row][j] (member blockIdx.y: dz rows * cols apart,
+// db kParams apart).  A workgroup takes 64 columns; its four waves sum every
+// fourth row each (eight loads in flight per lane), then wave 0 adds the four
+// partial sums in wave order: the same order on every call.
+constexpr int kColW = 64, kColRowGroups = kThreads / kColW;
 __global__ __launch_bounds__(kThreads) void k_colsum(const float* __restrict__ dz, int rows, int cols, float* __restrict__ db) {
-  const int j = blockIdx.x * kThreads + threadIdx.x;
-  if (j >= cols) return;
+  __shared__ float part[kColRowGroups][kColW];
+  const int tx = threadIdx.x % kColW, ty = threadIdx.x / kColW;
+  const int j = blockIdx.x * kColW + tx;
   dz += (long long)blockIdx.y * rows * cols;
   db += (long long)blockIdx.y * kParams;
   float s = 0.f;
-  for (int i = 0; i < rows; ++i) s += dz[(long long)i * cols + j];
-  db[j] = s;
+  if (j < cols) {
+    int r = ty;
+    for (; r + 7 * kColRowGroups < rows; r += 8 * kColRowGroups) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = dz[(long long)(r + u * kColRowGroups) * cols + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; r < rows; r += kColRowGroups) s += dz[(long long)r * cols + j];
+  }
+  part[ty][tx] = s;
+  __syncthreads();
+  if (ty == 0 && j < cols) {
+    float t = part[0][tx];
+#pragma unroll
+    for (int g = 1; g < kColRowGroups; ++g) t += part[g][tx];
+    db[j] = t;
+  }
 }
 
 // Bias corrections 1 - beta^t of Adam, per member.
@@ -387,7 +409,7 @@ void backward(mlp_handle* h, int k0, int count, const float* t, const float* m, 
     zw.B = (long long)n * out;
     zw.C = kParams;
     gemm(h->stream, ain, 1, in, dzb, out, 1, in, out, n, EPI_STORE, G + w_off(l), out, nullptr, nullptr, nullptr, count, zw);
-    hipLaunchKernelGGL(k_colsum, dim3(nblk(out), count), dim3(kThreads), 0, h->stream, dzf, n, out, G + b_off(l));
+    hipLaunchKernelGGL(k_colsum, dim3((out + kColW - 1) / kColW, count), dim3(kThreads), 0, h->stream, dzf, n, out, G + b_off(l));
     if (l > 0) {
       float* nf = h->dzf[l & 1];
       __bf16* nb = h->dzb[l & 1];

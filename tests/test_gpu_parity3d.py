@@ -1,8 +1,9 @@
 """Parity of the 3-D (D3Q19) HIP path, through the C ABI, with the 3-D FP64
 CPU oracle: every field after 1, 10 and 100 steps within 1e-10 relative in
-FP64 storage and 1e-5 in FP32 storage (velocity normalised by a thousandth
-of the capillary velocity sigma / mu_l or the wall speed, pressure by a
-thousandth of the Laplace pressure 2 sigma / R)."""
+FP64 storage and 1e-5 in FP32 storage (velocity normalised by at least a
+thousandth of the capillary velocity sigma / mu_l or the wall speed, or of a
+case's stated velocity scale; pressure by at least a thousandth of the
+Laplace pressure 2 sigma / R).  FP32 storage also collides in FP32."""
 import numpy as np
 import pytest
 
@@ -26,7 +27,8 @@ def lbm3d():
 
 
 def scales(cfg):
-    u = max(cfg.get("sigma_gl0", 0.01) / cfg.get("mu_l", 0.1), abs(cfg.get("u_wall_top", 0.0)))
+    # u_ref: a case's own velocity scale (test-only key; the library ignores it)
+    u = cfg.get("u_ref", max(cfg.get("sigma_gl0", 0.01) / cfg.get("mu_l", 0.1), abs(cfg.get("u_wall_top", 0.0))))
     R = abs(cfg.get("R0", 8.0)) or 8.0
     return 1e-3 * u, 1e-3 * 2 * cfg.get("sigma_gl0", 0.01) / R
 
@@ -54,8 +56,11 @@ CASES3 = {
                                   init_kind=inputs.INIT_BUBBLE, z0=8.0, bc_bottom=inputs.FREESLIP, bc_top=inputs.WALL_WET),
     "literal_advection": inputs.drop3d(20, 6.0, psi_b=0.01, adv_raw=1),
     "phi_hold_walls": dict(inputs.sessile3d(psi_b=0.0), phi_hold=1),
-    "ratio1000_sessile": inputs.sessile3d(nx=32, ny=24, nz=16, R=8.0, theta0_deg=90.0, psi_b=0.0, eps=6.0,
-                                          rho_l=1000.0, rho_g=1.0, mu_l=100.0, mu_g=1.0, bc_top=inputs.NOSLIP),
+    # at 1000:1 the liquid's capillary velocity (1e-4) is far below the gas's (sigma / mu_g = 0.01), which
+    # sets the scale of the spurious currents where they live: the velocity floor takes the gas's, as in 2-D
+    "ratio1000_sessile": dict(inputs.sessile3d(nx=32, ny=24, nz=16, R=8.0, theta0_deg=90.0, psi_b=0.0, eps=6.0,
+                                               rho_l=1000.0, rho_g=1.0, mu_l=100.0, mu_g=1.0, bc_top=inputs.NOSLIP),
+                              u_ref=0.01),
 }
 
 
