@@ -37,6 +37,10 @@ __host__ __device__ constexpr int w_off(int l) {   // offset of W_l (l = 0..3) i
 }
 __host__ __device__ constexpr int b_off(int l) { return w_off(l) + kDims[l] * kDims[l + 1]; }
 static_assert(w_off(kLayers) == kParams, "layout");
+// Members' parameter vectors inside the library sit kPStride apart (a whole
+// number of 8-element groups, so every member's weight matrices start on a
+// 16-byte boundary for the matrix-core staging loads).
+constexpr int kPStride = (kParams + 7) / 8 * 8;
 
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_d(float z) {
@@ -59,9 +63,56 @@ struct Gemm {
   const float* Zp;   // EPI_DGELU: pre-activation multiplied in through GELU', same layout as C
   // element offsets between consecutive members (blockIdx.z) of A, B, C / Cb / Zp and bias
   long long zA, zB, zC, zbias;
+  // how each operand is staged: STAGE_K (8 consecutive k in one 16-byte load),
+  // STAGE_MN (8 consecutive m or n in one load, scattered into LDS) or
+  // STAGE_ELEM (element by element); chosen on the host from strides and alignment
+  int a_stage, b_stage;
 };
+enum { STAGE_ELEM = 0, STAGE_K = 1, STAGE_MN = 2 };
 
 constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;   // LDS rows padded to 80 bytes (16-byte aligned fragments)
+
+// Stage the 64 x 32 operand tile X(row, k), rows r0 .. r0+63 and k0 .. k0+31,
+// into LDS as T[row][k] (zero beyond the matrix), with X(row, k) =
+// X[row * srow + k * sk].  STAGE_K: thread t loads 8 consecutive k of row
+// t / 4 in one 16-byte load (sk = 1); STAGE_MN: thread t loads 8 consecutive
+// rows at k0 + t / 8 (srow = 1; eight lanes cover 64 rows of one k) and
+// scatters them; both fall back to single elements at the matrix's edges.
+__device__ __forceinline__ void stage_tile(const __bf16* __restrict__ X, long long srow, long long sk, int R, int K,
+                                           int r0, int k0, int mode, __bf16 (*T)[LDK], int t) {
+  if (mode == STAGE_K) {
+    const int r = t >> 2, kq = (t & 3) * 8;
+    const int row = r0 + r, k = k0 + kq;
+    bf16x8 v;
+    if (row < R && k + 7 < K) {
+      v = *(const bf16x8*)(X + row * srow + k);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = (row < R && k + j < K) ? X[row * srow + k + j] : (__bf16)0.0f;
+    }
+    *(bf16x8*)&T[r][kq] = v;
+  } else if (mode == STAGE_MN) {
+    const int kk = t >> 3, rq = (t & 7) * 8;
+    const int k = k0 + kk, row = r0 + rq;
+    bf16x8 v;
+    if (k < K && row + 7 < R) {
+      v = *(const bf16x8*)(X + k * sk + row);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = (k < K && row + j < R) ? X[k * sk + row + j] : (__bf16)0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) T[rq + j][kk] = v[j];
+  } else {
+    const int r = t >> 2, kq = (t & 3) * 8;
+    const int row = r0 + r;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + kq + j;
+      T[r][kq + j] = (row < R && k < K) ? X[row * srow + k * sk] : (__bf16)0.0f;
+    }
+  }
+}
 
 __global__ __launch_bounds__(kThreads) void k_gemm(Gemm g) {
   __shared__ __attribute__((aligned(16))) __bf16 As[TM][LDK];   // [m][k]
@@ -75,15 +126,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm(Gemm g) {
   f32x4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int r = t >> 2, kq = (t & 3) * 8;   // staging: row / column r, k offsets kq .. kq+7
   for (int k0 = 0; k0 < g.K; k0 += TK) {
-    const int m = m0 + r, n = n0 + r;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = k0 + kq + j;
-      As[r][kq + j] = (m < g.M && k < g.K) ? gA[m * g.sam + k * g.sak] : (__bf16)0.0f;
-      Bs[r][kq + j] = (n < g.N && k < g.K) ? gB[k * g.sbk + n * g.sbn] : (__bf16)0.0f;
-    }
+    stage_tile(gA, g.sam, g.sak, g.M, g.K, m0, k0, g.a_stage, As, t);
+    stage_tile(gB, g.sbn, g.sbk, g.N, g.K, n0, k0, g.b_stage, Bs, t);
     __syncthreads();
     // matrix-core fragments: lane l holds row (l mod 16) and k = 8 (l / 16) .. +7
 #pragma unroll
@@ -192,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_loss_final(const float* __restrict
 }
 
 // db[j] = sum over rows of dz[row][j] (member blockIdx.y: dz rows * cols apart,
-// db kParams apart).  A workgroup takes 64 columns; its four waves sum every
+// db kPStride apart).  A workgroup takes 64 columns; its four waves sum every
 // fourth row each (eight loads in flight per lane), then wave 0 adds the four
 // partial sums in wave order: the same order on every call.
 constexpr int kColW = 64, kColRowGroups = kThreads / kColW;
@@ -201,7 +246,7 @@ __global__ __launch_bounds__(kThreads) void k_colsum(const float* __restrict__ d
   const int tx = threadIdx.x % kColW, ty = threadIdx.x / kColW;
   const int j = blockIdx.x * kColW + tx;
   dz += (long long)blockIdx.y * rows * cols;
-  db += (long long)blockIdx.y * kParams;
+  db += (long long)blockIdx.y * kPStride;
   float s = 0.f;
   if (j < cols) {
     int r = ty;
@@ -231,14 +276,14 @@ struct AdamCorr {
 };
 
 // Adam on the FP32 master parameters, then their bfloat16 copy (member
-// blockIdx.y: its arrays n apart)
+// blockIdx.y: its arrays kPStride apart, n of them used)
 __global__ __launch_bounds__(kThreads) void k_adam(float* __restrict__ th, float* __restrict__ mo, float* __restrict__ ve,
                                                    const float* __restrict__ g, __bf16* __restrict__ thb, int n, float lr,
                                                    AdamCorr corr) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
   const int z = blockIdx.y;
-  const long long zo = (long long)z * n;
+  const long long zo = (long long)z * kPStride;
   th += zo;
   mo += zo;
   ve += zo;
@@ -285,7 +330,7 @@ struct mlp_handle {
   bool own_buf = false;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  // per member [members][kParams]
+  // per member [members][kPStride] (the first kParams of each used)
   float *master = nullptr, *mom = nullptr, *vel = nullptr, *grad = nullptr;
   __bf16* wbf = nullptr;
   std::vector<int> adam_t;
@@ -311,7 +356,7 @@ MlpLayout mlp_layout(int members, int B) {
   MlpLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += al256(bytes); return o; };
-  const size_t P = (size_t)members * kParams, MB = (size_t)members * B;
+  const size_t P = (size_t)members * kPStride, MB = (size_t)members * B;
   L.master = take(P * 4);
   L.mom = take(P * 4);
   L.vel = take(P * 4);
@@ -343,6 +388,16 @@ int mfail(mlp_handle* h, int code, const std::string& msg) {
     if (e_ != hipSuccess) return mfail(h, -4, std::string(where) + ": " + hipGetErrorString(e_));        \
   } while (0)
 
+// Staging of an operand X(row, k) = X[row * srow + k * sk] (member offsets
+// zoff): 16-byte loads need a unit stride along k or along the rows, the other
+// stride and the member offset in whole 8-element groups, and an aligned base.
+int stage_mode(const __bf16* X, long long srow, long long sk, long long zoff) {
+  const bool aligned = ((uintptr_t)X % 16) == 0 && zoff % 8 == 0;
+  if (aligned && sk == 1 && srow % 8 == 0) return STAGE_K;
+  if (aligned && srow == 1 && sk % 8 == 0) return STAGE_MN;
+  return STAGE_ELEM;
+}
+
 // Member offsets of one product (elements): A, B, C (and Cb, Zp), bias.
 struct ZStride {
   long long A = 0, B = 0, C = 0, bias = 0;
@@ -351,7 +406,8 @@ struct ZStride {
 void gemm(hipStream_t st, const __bf16* A, long long sam, long long sak, const __bf16* B, long long sbk, long long sbn,
           int M, int N, int K, int epi, float* C, long long scm, __bf16* Cb, const float* bias, const float* Zp,
           int count = 1, ZStride zs = ZStride()) {
-  Gemm g{A, sam, sak, B, sbk, sbn, M, N, K, epi, C, scm, Cb, bias, Zp, zs.A, zs.B, zs.C, zs.bias};
+  Gemm g{A, sam, sak, B, sbk, sbn, M, N, K, epi, C, scm, Cb, bias, Zp, zs.A, zs.B, zs.C, zs.bias,
+         stage_mode(A, sam, sak, zs.A), stage_mode(B, sbn, sbk, zs.B)};
   hipLaunchKernelGGL(k_gemm, dim3((N + TN - 1) / TN, (M + TM - 1) / TM, count), dim3(kThreads), 0, st, g);
 }
 
@@ -359,8 +415,8 @@ void gemm(hipStream_t st, const __bf16* A, long long sam, long long sak, const _
 // elements between the members' inputs: 0 when they share one input batch);
 // outputs to y[count][n][2].
 void forward(mlp_handle* h, int k0, int count, int n, long long x_stride, float* y) {
-  const __bf16* W = h->wbf + (size_t)k0 * kParams;
-  const float* P = h->master + (size_t)k0 * kParams;
+  const __bf16* W = h->wbf + (size_t)k0 * kPStride;
+  const float* P = h->master + (size_t)k0 * kPStride;
   const long long act = (long long)n * kHid;
   const __bf16* a = h->xb;
   long long az = x_stride;
@@ -368,9 +424,9 @@ void forward(mlp_handle* h, int k0, int count, int n, long long x_stride, float*
   for (int l = 0; l < 3; ++l) {
     ZStride zs;
     zs.A = az;
-    zs.B = kParams;
+    zs.B = kPStride;
     zs.C = act;
-    zs.bias = kParams;
+    zs.bias = kPStride;
     gemm(h->stream, a, in, 1, W + w_off(l), kHid, 1, n, kHid, in, EPI_BIAS_GELU, h->Z[l], kHid, h->A[l], P + b_off(l),
          nullptr, count, zs);
     a = h->A[l];
@@ -379,9 +435,9 @@ void forward(mlp_handle* h, int k0, int count, int n, long long x_stride, float*
   }
   ZStride zs;
   zs.A = act;
-  zs.B = kParams;
+  zs.B = kPStride;
   zs.C = (long long)n * kOut;
-  zs.bias = kParams;
+  zs.bias = kPStride;
   gemm(h->stream, a, kHid, 1, W + w_off(3), kOut, 1, n, kOut, kHid, EPI_BIAS, y, kOut, nullptr, P + b_off(3), nullptr,
        count, zs);
 }
@@ -390,8 +446,8 @@ void forward(mlp_handle* h, int k0, int count, int n, long long x_stride, float*
 // own inputs (h->xb, n apart), targets t and masks m [count][n][2]; gradients
 // into h->grad of those members, losses into h->loss[0 .. count).
 void backward(mlp_handle* h, int k0, int count, const float* t, const float* m, int n) {
-  const __bf16* W = h->wbf + (size_t)k0 * kParams;
-  float* G = h->grad + (size_t)k0 * kParams;
+  const __bf16* W = h->wbf + (size_t)k0 * kPStride;
+  float* G = h->grad + (size_t)k0 * kPStride;
   const long long act = (long long)n * kHid;
   hipLaunchKernelGGL(k_mask_norm, dim3(count), dim3(kThreads), 0, h->stream, m, n * kOut, h->inv);
   hipLaunchKernelGGL(k_dy, dim3(kRed, count), dim3(kThreads), 0, h->stream, h->y, t, m, n * kOut, h->inv, h->dy, h->dyb,
@@ -407,7 +463,7 @@ void backward(mlp_handle* h, int k0, int count, const float* t, const float* m, 
     ZStride zw;
     zw.A = (long long)n * in;
     zw.B = (long long)n * out;
-    zw.C = kParams;
+    zw.C = kPStride;
     gemm(h->stream, ain, 1, in, dzb, out, 1, in, out, n, EPI_STORE, G + w_off(l), out, nullptr, nullptr, nullptr, count, zw);
     hipLaunchKernelGGL(k_colsum, dim3((out + kColW - 1) / kColW, count), dim3(kThreads), 0, h->stream, dzf, n, out, G + b_off(l));
     if (l > 0) {
@@ -415,7 +471,7 @@ void backward(mlp_handle* h, int k0, int count, const float* t, const float* m, 
       __bf16* nb = h->dzb[l & 1];
       ZStride zd;
       zd.A = (long long)n * out;
-      zd.B = kParams;
+      zd.B = kPStride;
       zd.C = act;
       gemm(h->stream, dzb, out, 1, W + w_off(l), 1, out, n, in, out, EPI_DGELU, nf, in, nb, nullptr, h->Z[l - 1], count, zd);
       dzf = nf;
@@ -433,7 +489,7 @@ void adam(mlp_handle* h, int k0, int count, float lr) {
     corr.c1[k] = 1.0f - std::pow(0.9f, (float)t);
     corr.c2[k] = 1.0f - std::pow(0.999f, (float)t);
   }
-  const size_t o = (size_t)k0 * kParams;
+  const size_t o = (size_t)k0 * kPStride;
   hipLaunchKernelGGL(k_adam, dim3(nblk(kParams), count), dim3(kThreads), 0, h->stream, h->master + o, h->mom + o,
                      h->vel + o, (const float*)(h->grad + o), h->wbf + o, kParams, lr, corr);
 }
@@ -449,7 +505,7 @@ void adam(mlp_handle* h, int k0, int count, float lr) {
 constexpr int kNoAllocMaxBatch = 1024, kNoAllocMaxMembers = 8, kMaxDevices = 64;
 struct NoAllocLayout {
   static constexpr size_t wbf = 0;
-  static constexpr size_t xb = wbf + ((size_t)kNoAllocMaxMembers * kParams * 2 + 255) / 256 * 256;
+  static constexpr size_t xb = wbf + ((size_t)kNoAllocMaxMembers * kPStride * 2 + 255) / 256 * 256;
   static constexpr size_t Z = xb + ((size_t)kNoAllocMaxBatch * kIn * 2 + 255) / 256 * 256;
   static constexpr size_t A = Z + (size_t)kNoAllocMaxBatch * kHid * 4;
   static constexpr size_t ys = A + 2 * (size_t)kNoAllocMaxBatch * kHid * 2;
@@ -560,7 +616,7 @@ int mlp_set_params(mlp_handle* h, int32_t member, const float* params_host) {
   int rc = check(h, member, 1);
   if (rc) return rc;
   if (!params_host) return mfail(h, -1, "null parameters");
-  const size_t o = (size_t)member * kParams;
+  const size_t o = (size_t)member * kPStride;
   MHIP(h, hipMemcpyAsync(h->master + o, params_host, kParams * 4, hipMemcpyHostToDevice, h->stream), "copy parameters");
   MHIP(h, hipMemsetAsync(h->mom + o, 0, kParams * 4, h->stream), "reset moments");
   MHIP(h, hipMemsetAsync(h->vel + o, 0, kParams * 4, h->stream), "reset moments");
@@ -575,7 +631,7 @@ int mlp_get_params(mlp_handle* h, int32_t member, float* params_host) {
   int rc = check(h, member, 1);
   if (rc) return rc;
   if (!params_host) return mfail(h, -1, "null parameters");
-  MHIP(h, hipMemcpyAsync(params_host, h->master + (size_t)member * kParams, kParams * 4, hipMemcpyDeviceToHost, h->stream), "copy parameters");
+  MHIP(h, hipMemcpyAsync(params_host, h->master + (size_t)member * kPStride, kParams * 4, hipMemcpyDeviceToHost, h->stream), "copy parameters");
   MHIP(h, hipStreamSynchronize(h->stream), "synchronise");
   return 0;
 }
@@ -601,7 +657,7 @@ int mlp_loss_grad(mlp_handle* h, int32_t member, const float* x_dev, const float
   MHIP(h, hipGetLastError(), "training kernels");
   if (loss_host) MHIP(h, hipMemcpyAsync(loss_host, h->loss, 4, hipMemcpyDeviceToHost, h->stream), "copy loss");
   if (grad_host)
-    MHIP(h, hipMemcpyAsync(grad_host, h->grad + (size_t)member * kParams, kParams * 4, hipMemcpyDeviceToHost, h->stream), "copy gradient");
+    MHIP(h, hipMemcpyAsync(grad_host, h->grad + (size_t)member * kPStride, kParams * 4, hipMemcpyDeviceToHost, h->stream), "copy gradient");
   MHIP(h, hipStreamSynchronize(h->stream), "synchronise");
   return 0;
 }
@@ -673,11 +729,12 @@ int mlp_predict_ensemble_noalloc(const float* params_dev, int32_t members, const
   __bf16* A[2] = {(__bf16*)(sp + NoAllocLayout::A), (__bf16*)(sp + NoAllocLayout::A) + (size_t)kNoAllocMaxBatch * kHid};
   float* ys = (float*)(sp + NoAllocLayout::ys);
   // every scratch element read below is written first in the same call
-  hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)members * kParams)), dim3(kThreads), 0, st, params_dev, wbf,
-                     members * kParams);
+  for (int k = 0; k < members; ++k)   // the caller's parameters are kParams apart, the bfloat16 copies kPStride
+    hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(kParams)), dim3(kThreads), 0, st, params_dev + (size_t)k * kParams,
+                       wbf + (size_t)k * kPStride, kParams);
   hipLaunchKernelGGL(k_cast_bf16, dim3(nblk((long long)n * kIn)), dim3(kThreads), 0, st, x_dev, xb, n * kIn);
   for (int k = 0; k < members; ++k) {
-    const __bf16* W = wbf + (size_t)k * kParams;
+    const __bf16* W = wbf + (size_t)k * kPStride;
     const float* P = params_dev + (size_t)k * kParams;
     const __bf16* a = xb;
     int in = kIn;
