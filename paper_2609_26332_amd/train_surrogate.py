@@ -62,7 +62,8 @@ def calibrate(sur, calib_files, tol_deg: float = 0.5, target: float = 0.99, conf
 
     ca, _ = load(calib_files)
     use = ca["status"] != STATUS["fault"]
-    angle, spread, _, _ = sur.predict(ca["X"][use])
+    angle, spread, tau, _ = sur.predict(ca["X"][use])
+    det = ca["tau_mask"][use] > 0
     err = np.abs(angle - ca["angle"][use])
     miss = ~(err <= tol_deg)                       # NaN truth (detached) counts as a miss
     N = int(use.sum())
@@ -76,7 +77,10 @@ def calibrate(sur, calib_files, tol_deg: float = 0.5, target: float = 0.99, conf
     acc = spread <= t
     out = dict(threshold_deg=t, calib_cases=N, target_within=target, confidence=confidence,
                calib_accepted=round(float(acc.mean()), 4), calib_misses=int((miss & acc).sum()),
-               calib_miss_bound=round(float(upper[stop - 1]), 5) if stop > 0 else None)
+               calib_miss_bound=round(float(upper[stop - 1]), 5) if stop > 0 else None,
+               calib_detached=int(det.sum()),
+               calib_detach_tau_mean_abs_err=round(float(np.abs(tau - ca["tau"][use])[det].mean()), 4)
+               if det.any() else None)
     if log:
         log(json.dumps(dict(calibration=out)))
     return out
