@@ -389,6 +389,10 @@ def main():
     rl = kernel_line(hb["kernels"], hb["nodes"], prec, design_bytes(prec))
     rl.update(kernel="k_step_batch", nodes_per_launch=hb["nodes"],
               traffic=measured_traffic("batch_" + prec))
+    from paper_2609_26332_amd import lbm as _lbm
+    hc = _lbm.probe_copy(1.0, 10)
+    rl.update(copy_ceiling_gbs=round(hc["gbs"], 2), frac_of_copy_ceiling=round(rl["achieved"] / hc["gbs"], 4))
+    torch.cuda.empty_cache()
     out = {
         "metric": "MLUPS (3 coupled lattices) + HBM roofline %; batched sweep cases/s at ±0.5°",
         "value": round(hb["mlups"], 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -421,6 +425,11 @@ def main():
         cp = copy_rate()
         g["copy_ceiling"] = {"achieved": round(cp, 2), "unit": "GB/s", "frac_of_peak": round(cp / HBM_PEAK_GBS, 4),
                              "what": "plain 1 GiB device copy (torch copy_), read + write bytes"}
+        hc = lbm.probe_copy(1.0, 10)
+        g["copy_ceiling_hip"] = {"achieved": round(hc["gbs"], 2), "unit": "GB/s", "frac_of_peak": round(hc["gbs"] / HBM_PEAK_GBS, 4),
+                                 "ms_per_copy": round(hc["ms"], 5), "copied": hc["copied"],
+                                 "what": "lbm_probe_copy: 1 GiB streaming copy, 16-byte non-temporal loads and stores, "
+                                         "read + write bytes"}
         g["pattern_ceiling_fp32"] = {"achieved": round(pr["gbs"], 2), "unit": "GB/s",
                                      "frac_of_peak": round(pr["gbs"] / HBM_PEAK_GBS, 4), "ms_per_launch": round(pr["ms"], 5),
                                      "what": "lbm_probe_stream: the FP32 step's design bytes (296 B/node) in its access "

@@ -256,6 +256,15 @@ int lbm_probe_bytes(int32_t nx, int32_t ny, int32_t precision, size_t* bytes);
 int lbm_probe_stream(int32_t nx, int32_t ny, int32_t precision, int32_t reps, void* dev_buf, size_t buf_bytes,
                      void* hip_stream, float* ms_out);
 
+/* The device's streaming-copy ceiling (a measurement aid beside the probe):
+ * copies `bytes` from src to dst (device memory, caller-owned, 16-byte
+ * aligned, bytes a positive multiple of 16, the regions not overlapping) with
+ * 16-byte non-temporal loads and stores, two warm-up copies and `reps` timed
+ * ones (1..10000) on hip_stream (NULL: the null stream); *ms_out is their mean
+ * duration (the rate counts bytes read plus bytes written).  Synchronises the
+ * stream.  Errors go to lbm_last_error(NULL). */
+int lbm_probe_copy(const void* src, void* dst, size_t bytes, int32_t reps, void* hip_stream, float* ms_out);
+
 /* Which kernel this handle's steps launch (the results are the same for
  * each; only the schedule differs), chosen from the number of workgroups
  * against the device's compute units:

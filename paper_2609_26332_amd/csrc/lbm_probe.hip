@@ -9,6 +9,8 @@
 // collision type and two FP64 planes, each read once and written once, with
 // the hints of the row sweep (non-temporal loads of f, plain loads and stores
 // otherwise).  Thread (x, y) owns node (x, y); blocks of 64 x 4 nodes.
+// A plain streaming copy (16-byte non-temporal loads and stores) gives the
+// device's copy ceiling beside it.
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -106,10 +108,59 @@ hipError_t run_probe(int nx, int ny, int precision, int reps, char* buf, hipStre
   return e;
 }
 
+// Plain streaming copy: each thread moves four 16-byte vectors 256 apart
+// (one 16 KiB block per workgroup), non-temporal loads and stores.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n16) {
+  const size_t base = (size_t)blockIdx.x * 1024 + threadIdx.x;
+  u32x4 v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const size_t j = base + (size_t)u * 256;
+    if (j < n16) v[u] = __builtin_nontemporal_load(src + j);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const size_t j = base + (size_t)u * 256;
+    if (j < n16) __builtin_nontemporal_store(v[u], dst + j);
+  }
+}
+
 }  // namespace
 }  // namespace lbm
 
 extern "C" {
+
+int lbm_probe_copy(const void* src, void* dst, size_t bytes, int32_t reps, void* hip_stream, float* ms_out) {
+  if (!src || !dst || !ms_out) return lbm::set_init_error(LBM_E_ARG, "null argument");
+  if ((((uintptr_t)src | (uintptr_t)dst) & 15) != 0 || bytes % 16 != 0 || bytes == 0)
+    return lbm::set_init_error(LBM_E_ARG, "src, dst and bytes must be multiples of 16 (bytes > 0)");
+  if (reps < 1 || reps > 10000) return lbm::set_init_error(LBM_E_ARG, "reps out of range");
+  const size_t n16 = bytes / 16, blocks = (n16 + 1023) / 1024;
+  if (blocks > 0x7fffffffull) return lbm::set_init_error(LBM_E_ARG, "copy too large");
+  hipStream_t st = (hipStream_t)hip_stream;
+  auto launch = [&]() {
+    hipLaunchKernelGGL(lbm::k_copy16, dim3((unsigned)blocks), dim3(256), 0, st, (const lbm::u32x4*)src, (lbm::u32x4*)dst,
+                       n16);
+    return hipGetLastError();
+  };
+  hipError_t e = launch();
+  if (e == hipSuccess) e = launch();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return lbm::set_init_error(LBM_E_DEVICE, std::string("copy kernel: ") + hipGetErrorString(e));
+  *ms_out = t / (float)reps;
+  return LBM_OK;
+}
 
 int lbm_probe_bytes(int32_t nx, int32_t ny, int32_t precision, size_t* bytes) {
   if (!bytes) return lbm::set_init_error(LBM_E_ARG, "null argument");

@@ -34,7 +34,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_UNSUPPORTED", -3: "LBM_E_OOM"
 EXPORTS = ["lbm_required_bytes", "lbm_init", "lbm_step", "lbm_reduce_invariants", "lbm_fetch_fields",
            "lbm_load_fields", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_derived",
            "lbm_fetch_populations", "lbm_destroy", "lbm_last_error", "lbm_timing_begin", "lbm_timing_end",
-           "lbm_bytes_per_node_step", "lbm_probe_bytes", "lbm_probe_stream", "lbm_step_kernel",
+           "lbm_bytes_per_node_step", "lbm_probe_bytes", "lbm_probe_stream", "lbm_probe_copy", "lbm_step_kernel",
            "lbm_batch_required_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_set_active",
            "lbm_batch_reduce_invariants", "lbm_batch_fetch_fields", "lbm_batch_replace_case", "lbm_batch_autotune",
            "lbm_batch_info", "lbm_batch_timing_begin", "lbm_batch_timing_end", "lbm_batch_destroy",
@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_probe_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(sz)]
         L.lbm_probe_stream.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, sz, vp,
                                        ctypes.POINTER(ctypes.c_float)]
+        L.lbm_probe_copy.argtypes = [vp, vp, sz, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_float)]
         L.lbm_step_kernel.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32)]
         L.lbm_last_error.argtypes = [vp]
@@ -308,6 +309,25 @@ def probe_stream(nx: int, ny: int, precision: str = "fp32", reps: int = 20) -> d
                               ctypes.c_void_p(st.cuda_stream), ctypes.byref(ms)))
     per_node = {"fp64": 560.0, "fp32": 296.0, "fp16": 196.0}[precision]
     return dict(ms=ms.value, bytes_per_node=per_node, gbs=per_node * nx * ny / ms.value / 1e6)
+
+
+def probe_copy(gib: float = 1.0, reps: int = 10) -> dict:
+    """The device's streaming-copy ceiling (lbm_probe_copy: 16-byte
+    non-temporal loads and stores) for gib GiB; rate over bytes read plus
+    written."""
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible to torch; the probe has no CPU fallback")
+    n = int(gib * (1 << 30)) // 16 * 16
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    ms = ctypes.c_float()
+    st = torch.cuda.current_stream()
+    _check(lib().lbm_probe_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n, reps,
+                                ctypes.c_void_p(st.cuda_stream), ctypes.byref(ms)))
+    ok = bool(torch.equal(src[:: 1 << 20], dst[:: 1 << 20]))
+    return dict(ms=ms.value, bytes=2 * n, gbs=2 * n / ms.value / 1e6, copied=ok)
 
 
 def _bcheck(rc: int, b=None):
