@@ -299,6 +299,9 @@ int lbm_init(const lbm_params* p, void* dev_buf, size_t buf_bytes, void* hip_str
     const long v = std::strtol(ov, nullptr, 10);
     if (v >= 1 && v <= 65536) h->ds.cus = (int)v;
   }
+  // LBM_STEP_SPLIT_WALLS=0 runs every segment of a walled grid in the walled
+  // form of the sweep (a test aid: the split gives the same results).
+  if (const char* ov = std::getenv("LBM_STEP_SPLIT_WALLS")) h->ds.split_walls = std::strcmp(ov, "0") != 0;
   hipError_t e = hipMemcpyAsync(h->ds.dparams, &h->dp, sizeof(h->dp), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = lbm::launch_init(h->dp, h->ds, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

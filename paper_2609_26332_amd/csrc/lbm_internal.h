@@ -87,6 +87,7 @@ struct DevState {
   int scur;                // scalars[scur] holds the multipliers pending on the stored populations
   int tile_rows;           // rows per workgroup segment of the step kernel (a multiple of 4)
   int cus = 256;           // compute units of the device (the step kernel's variant choice)
+  int split_walls = 1;     // walled sweep: wall-free segments take the periodic form (same results)
   int cur;                 // index of the current population buffer
   int hcur;                // phi/psi and history buffer written by the next step
 };

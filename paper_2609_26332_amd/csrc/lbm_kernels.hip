@@ -482,6 +482,7 @@ struct StepArgs {
   // k_step_finish did not run for step n-1.
   const double* prev_partials;
   int prev_have_hist;
+  int split_walls;          // walled sweep: wall-free segments take the periodic form
 };
 
 // lambda(n) = S1/S2, mubar(n) = S3/N from the per-tile partial sums of
@@ -631,6 +632,32 @@ template <class T> __device__ __forceinline__ T opaque_v(T v) {   // the same fo
 // Schedules of step_body: the sweep, or one tile of four rows in one pass with
 // eight waves (kOneShot8) or four (kOneShot4).
 enum { kSweep = 0, kOneShot8 = 1, kOneShot4 = 2 };
+// LDS of one step workgroup, shared by the walled and the periodic form of a
+// schedule (a kernel that holds both allocates it once).
+template <class S, class C, int SCHED>
+struct StepLds {
+  static constexpr int RP = 16, RM = 8;   // ring rows: h' and (phi, psi); (mu_phi, mu_psi)
+  static constexpr bool H16 = kHalf<S>;
+  // g_1..g_8, h_1..h_8 of a segment row from A to C, in storage form (FP32
+  // and FP16 storage; FP64 would need more LDS than two workgroups per CU
+  // leave, and C gathers them again).  Six slots: the row wave w's A handles
+  // at iteration k (Y0+4k+2+w) takes the slot of the row its C handled at
+  // iteration k-1 (Y0+4k-4+w), which no other wave reads; C reads a row at
+  // least one barrier after A wrote it.
+  static constexpr bool GH = sizeof(S) <= 4;
+  static constexpr int RS = 6;
+  C hp[RP][kStripW + 6];                             // h'(phi(n-1)), columns X0-3 .. X0+62
+  double2 pp[RP][64];                                // (phi, psi)(n), columns X0-2 .. X0+61
+  double2 mu[RM][64];                                // (mu_phi, mu_psi), columns X0-2 .. X0+61 (lanes 1..62 used)
+  float2 ref[H16 ? RP : 1][H16 ? kStripW + 6 : 1];   // FP16 storage: (phi, psi)(n-1) as in hp
+  S gh[GH ? RS : 1][GH ? 16 : 1][64];
+  double2 u[SCHED == kOneShot8 ? 4 : 1][SCHED == kOneShot8 ? 64 : 1];   // velocity of the split collision
+};
+template <class S, class C, int SCHED>
+__device__ __forceinline__ StepLds<S, C, SCHED>& step_lds() {
+  __shared__ StepLds<S, C, SCHED> lds;
+  return lds;
+}
 template <class S, class C, bool WALLS, int SCHED = kSweep>
 __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a, const int tile) {
   // Store hint, as measured on MI355X.  FP32 and FP16 storage store plainly on
@@ -641,21 +668,15 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   // the eight-wave tile of small grids keep the non-temporal hint (FP64 4096^2:
   // 2.35 against 2.45 ms).
   constexpr bool NTS = SCHED == kOneShot8 || sizeof(S) == 8;
-  constexpr int RP = 16, RM = 8;           // ring rows: h' and (phi, psi); (mu_phi, mu_psi)
-  __shared__ C sHp[RP][kStripW + 6];       // h'(phi(n-1)), columns X0-3 .. X0+62
-  __shared__ double2 sPP[RP][64];          // (phi, psi)(n), columns X0-2 .. X0+61
-  __shared__ double2 sMU[RM][64];          // (mu_phi, mu_psi), columns X0-2 .. X0+61 (lanes 1..62 used)
-  constexpr bool H16 = kHalf<S>;
-  __shared__ float2 sRef[H16 ? RP : 1][H16 ? kStripW + 6 : 1];   // FP16 storage: (phi, psi)(n-1) as in sHp
-  // g_1..g_8, h_1..h_8 of a segment row from A to C, in storage form (FP32
-  // and FP16 storage; FP64 would need more LDS than two workgroups per CU
-  // leave, and C gathers them again).  Six slots: the row wave w's A handles
-  // at iteration k (Y0+4k+2+w) takes the slot of the row its C handled at
-  // iteration k-1 (Y0+4k-4+w), which no other wave reads; C reads a row at
-  // least one barrier after A wrote it.
-  constexpr bool GH = sizeof(S) <= 4;
-  constexpr int RS = 6;
-  __shared__ S sGH[GH ? RS : 1][GH ? 16 : 1][64];
+  using L = StepLds<S, C, SCHED>;
+  constexpr int RP = L::RP, RM = L::RM, RS = L::RS;
+  constexpr bool H16 = L::H16, GH = L::GH;
+  L& lds = step_lds<S, C, SCHED>();
+  auto& sHp = lds.hp;
+  auto& sPP = lds.pp;
+  auto& sMU = lds.mu;
+  auto& sRef = lds.ref;
+  auto& sGH = lds.gh;
 
   const int X0 = (tile % a.nstrips) * kStripW, Y0 = (tile / a.nstrips) * a.seg_rows;
   const int Yend = min(Y0 + a.seg_rows, p.ny);
@@ -1021,7 +1042,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   // waves through the heaviest phase.  The velocity goes through LDS across
   // one barrier that every wave of the workgroup reaches once (active or not).
   // The arithmetic is row_C's, term for term.
-  __shared__ double2 sU[SCHED == kOneShot8 ? 4 : 1][SCHED == kOneShot8 ? 64 : 1];
+  auto& sU = lds.u;
   auto gather_Cf = [&](int gy, unsigned x, C* f) {
     const size_t N = opaque((size_t)p.N);
     const unsigned xs = x * sizeof(S), xsm = colm(x) * sizeof(S), xsp = colp(x) * sizeof(S);
@@ -1417,9 +1438,26 @@ template <class S> inline constexpr int kStepMinBlocks = sizeof(S) <= 4 ? 3 : 1;
 // as the batched kernel reads it: scalar loads on demand instead of a kernel
 // argument block held in (spilled) scalar registers, and the same code as the
 // batched step, hence the same results bit for bit.
+// A segment of a walled grid whose rows lie three or more rows inside both
+// walls touches no wall: every row it reads or computes for its collisions
+// (halo rows, stencil and gather sources) is a fluid row, so the periodic form
+// of the sweep computes it exactly as the walled form does, with fewer
+// registers and no wall branches.
+__device__ __forceinline__ bool wall_free_segment(int tile, int nstrips, int seg_rows, int ny) {
+  const int y0 = (tile / nstrips) * seg_rows;
+  return y0 >= 3 && min(y0 + seg_rows, ny) <= ny - 3;
+}
+
 template <class S, class C, bool WALLS, int MINB>
 __global__ __launch_bounds__(kBlock, MINB) void k_step(const DevParams* __restrict__ pp, StepArgs a) {
-  step_body<S, C, WALLS>(*pp, a, xcd_tile(blockIdx.x, gridDim.x));
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  if constexpr (WALLS) {
+    if (a.split_walls && wall_free_segment(t, a.nstrips, a.seg_rows, pp->ny)) {
+      step_body<S, C, false>(*pp, a, t);
+      return;
+    }
+  }
+  step_body<S, C, WALLS>(*pp, a, t);
 }
 
 // Small grids (at most one workgroup of four rows per CU): the one-shot
@@ -1462,7 +1500,15 @@ __global__ __launch_bounds__(kBlock, WALLS ? kStepMinBlocks<S> : 1) void k_step_
   a.ntiles = bc.ntiles;
   a.prev_partials = nullptr;
   a.prev_have_hist = 0;
-  step_body<S, C, WALLS>(bc.p, a, b - bc.tile_begin);
+  a.split_walls = 1;
+  const int t = b - bc.tile_begin;
+  if constexpr (WALLS) {
+    if (wall_free_segment(t, bc.nstrips, bc.seg_rows, bc.p.ny)) {
+      step_body<S, C, false>(bc.p, a, t);
+      return;
+    }
+  }
+  step_body<S, C, WALLS>(bc.p, a, t);
 }
 
 // One workgroup per case: the multipliers of the step just taken, then the
@@ -1799,6 +1845,7 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
   a.ntiles = (int)step_blocks(p.nx, p.ny, s.tile_rows);
   a.prev_partials = (fuse & kFusePrev) ? s.step_partials[s.cur ^ 1] : nullptr;
   a.prev_have_hist = 1;
+  a.split_walls = s.split_walls;
   {
     TimedScope ts(t, LBM_K_STEP, st);
     const DevParams* dp = (const DevParams*)s.dparams;

@@ -316,6 +316,36 @@ def test_every_step_kernel_variant_on_the_sessile_drop(lbm, monkeypatch):
             assert_fields_close(f, of, tol, u_scale(cfg), p_scale(cfg), f"{prec} {kern['kernel']}")
 
 
+def test_wall_free_segments_take_the_periodic_form(lbm, monkeypatch):
+    """On a walled grid the row sweep runs every segment that lies three or
+    more rows inside both walls in the periodic form of the step, which has no
+    wall branches; LBM_STEP_SPLIT_WALLS=0 runs all segments in the walled form.
+    Both give the same fields and multipliers bit for bit, in all three
+    storages, with one and with three workgroups per CU, on a sessile drop and
+    on a sheared drop with adsorbing walls."""
+    cases = [(dict(inputs.sessile_drop(), tile_rows=8), "256"),
+             (dict(inputs.shear_drop(nx=256, ny=128, R=32.0, Ca=0.1, betas=(0.01, 0.9)), tile_rows=16), "256"),
+             (dict(inputs.sessile_drop(nx=192, ny=96, R=30.0), tile_rows=8), "16")]
+    for cfg, cus in cases:
+        for prec in ("fp32", "fp64", "fp16"):
+            out = []
+            for split in ("1", "0"):
+                monkeypatch.setenv("LBM_KERNEL_CUS", cus)
+                monkeypatch.setenv("LBM_STEP_SPLIT_WALLS", split)
+                g = lbm.Sim(cfg, prec)
+                monkeypatch.delenv("LBM_KERNEL_CUS")
+                monkeypatch.delenv("LBM_STEP_SPLIT_WALLS")
+                assert g.step_kernel()["kernel"] in ("k_step", "k_step (three workgroups per CU)"), g.step_kernel()
+                g.step(40)
+                out.append((g.fields(FIELDS), g.invariants()))
+                g.close()
+            (fa, ia), (fb, ib) = out
+            for k in FIELDS:
+                assert np.array_equal(fa[k], fb[k]), (cfg["nx"], prec, k)
+            for k in ("lambda_phi", "mubar_psi", "mass_psi"):
+                assert ia[k] == ib[k], (cfg["nx"], prec, k)
+
+
 def test_deterministic_and_checkpoint_restart(lbm):
     cfg = inputs.sessile_drop(nx=80, ny=40, R=12.0)
     for prec in ("fp64", "fp32", "fp16"):
