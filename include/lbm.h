@@ -324,9 +324,19 @@ int lbm_batch_reduce_invariants(lbm_batch* b, lbm_invariants* out);
 /* lbm_fetch_fields of case index (synchronises). */
 int lbm_batch_fetch_fields(lbm_batch* b, int32_t index, uint32_t mask, double* host, size_t n_doubles);
 
-/* Refill slot index with a new case: same nx, ny, precision and kind of y
- * boundary; initialised as lbm_init does, and made active. */
+/* Refill slot index with a new case of any grid whose state fits the slot
+ * (lbm_required_bytes(p) <= lbm_batch_slot_bytes of the slot), with the
+ * batch's precision and kind of y boundary; initialised as lbm_init does, and
+ * made active.  The other cases keep their state.  A grid of another size
+ * changes the batch's workgroup map, which is rebuilt (and the step graphs
+ * captured again) at the next call that steps or sets activity; results do not
+ * depend on the slot a case runs in.  LBM_E_ARG if the case does not fit or
+ * does not match the batch. */
 int lbm_batch_replace_case(lbm_batch* b, int32_t index, const lbm_params* p);
+
+/* Bytes of device memory slot index holds (set by the case it was created
+ * with): a refill with lbm_batch_replace_case must need no more. */
+int lbm_batch_slot_bytes(lbm_batch* b, int32_t index, size_t* bytes);
 
 /* Autotuner: times trial_steps steps of the batch for each segment height of
  * {4, 8, 16, 32, 64}, keeps the fastest (written to *seg_rows_out) and puts

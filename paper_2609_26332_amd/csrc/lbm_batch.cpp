@@ -20,6 +20,9 @@
 struct lbm_batch {
   std::vector<lbm_handle*> h;
   std::vector<size_t> off;  // byte offset of each case's state in buf
+  std::vector<size_t> slot_bytes;  // bytes of buf each case's slot holds (a refill must fit)
+  std::vector<int> active;         // activity of each slot, as the device table holds it
+  bool table_dirty = false;        // a refill changed the tiling: table and workgroup map are rebuilt before use
   int count = 0;
   int precision = 0;
   bool walls = false;
@@ -59,6 +62,7 @@ int bfail(lbm_batch* b, int code, const std::string& msg) {
   } while (0)
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+void drop_graph(lbm_batch* b);
 
 struct Plan {
   std::vector<size_t> case_bytes, off;
@@ -98,8 +102,11 @@ int plan(const lbm_params* cases, int32_t count, Plan& P, std::string& why) {
   return LBM_OK;
 }
 
-// Device table for the current segment height, positions taken from the handles.
+// Device table for the current segment height, positions taken from the handles
+// (which must be current), activity from b->active.  Graphs captured on an
+// earlier table keep its workgroup count and are dropped.
 int build_table(lbm_batch* b) {
+  drop_graph(b);
   b->hc.assign(b->count, lbm::BatchCase());
   std::vector<int> wg;
   for (int c = 0; c < b->count; ++c) {
@@ -119,7 +126,7 @@ int build_table(lbm_batch* b) {
     e.seg_rows = b->seg_rows;
     e.ntiles = (int)lbm::step_blocks(v.dp->nx, v.dp->ny, b->seg_rows);
     e.tile_begin = (int)wg.size();
-    e.active = 1;
+    e.active = b->active[c];
     e.parity = v.ds->cur;
     e.have_hist = *v.have_hist;
     e.step = *v.step;
@@ -130,6 +137,7 @@ int build_table(lbm_batch* b) {
   BHIP(b, hipMemcpyAsync(b->d_wg, wg.data(), sizeof(int) * wg.size(), hipMemcpyHostToDevice, b->stream), "upload workgroup map");
   BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
   b->device_ahead = false;
+  b->table_dirty = false;
   return LBM_OK;
 }
 
@@ -146,6 +154,14 @@ int sync_handles(lbm_batch* b) {
   }
   b->device_ahead = false;
   return LBM_OK;
+}
+
+// A refill that changed a slot's tiling leaves the table to be rebuilt here,
+// before the next use of the table on the device.
+int ensure_table(lbm_batch* b) {
+  if (!b->table_dirty) return LBM_OK;
+  const int rc = sync_handles(b);
+  return rc ? rc : build_table(b);
 }
 
 // After a host-side change to case c (its handle is current): its table entry again.
@@ -246,6 +262,8 @@ int lbm_batch_init(const lbm_params* cases, int32_t count, int32_t seg_rows, voi
   b->d_cases = (lbm::BatchCase*)(base + P.table);
   b->d_wg = (int*)(base + P.wg);
   b->off = P.off;
+  b->slot_bytes = P.case_bytes;
+  b->active.assign(count, 1);
   b->h.assign(count, nullptr);
   for (int c = 0; c < count; ++c) {
     rc = lbm_init(&cases[c], base + P.off[c], P.case_bytes[c], b->stream, &b->h[c]);
@@ -281,6 +299,8 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
   for (int c = 0; c < b->count; ++c)
     if (*lbm::handle_view(b->h[c]).faulted && b->hc[c].active)
       return bfail(b, LBM_E_STATE, "case " + std::to_string(c) + " holds non-finite or out-of-range values; retire or reload it");
+  const int rt = ensure_table(b);
+  if (rt) return rt;
   int64_t k = 0;
   while (k < n) {
     const bool timing = b->timer.ev && b->timer.used < b->timer.max_steps;
@@ -307,8 +327,9 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
 int lbm_batch_set_active(lbm_batch* b, const int32_t* active) {
   if (!b || !active) return bfail(b, LBM_E_ARG, "null argument");
   int rc = sync_handles(b);
+  if (!rc) rc = ensure_table(b);
   if (rc) return rc;
-  for (int c = 0; c < b->count; ++c) b->hc[c].active = active[c] ? 1 : 0;
+  for (int c = 0; c < b->count; ++c) b->hc[c].active = b->active[c] = active[c] ? 1 : 0;
   BHIP(b, hipMemcpyAsync(b->d_cases, b->hc.data(), sizeof(lbm::BatchCase) * b->count, hipMemcpyHostToDevice, b->stream), "upload batch table");
   BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
   return LBM_OK;
@@ -344,20 +365,36 @@ int lbm_batch_replace_case(lbm_batch* b, int32_t index, const lbm_params* p) {
   int rc = check_index(b, index);
   if (!rc) rc = sync_handles(b);
   if (rc) return rc;
-  lbm::HandleView v = lbm::handle_view(b->h[index]);
-  if (p->nx != v.dp->nx || p->ny != v.dp->ny || p->precision != b->precision || (p->bc_bottom != LBM_BC_PERIODIC) != b->walls)
-    return bfail(b, LBM_E_ARG, "a replacement case needs the grid, precision and y-boundary kind of the slot");
+  if (p->precision != b->precision || (p->bc_bottom != LBM_BC_PERIODIC) != b->walls)
+    return bfail(b, LBM_E_ARG, "a replacement case needs the precision and y-boundary kind of the batch");
   size_t bytes = 0;
   if (lbm_required_bytes(p, &bytes) != LBM_OK) return bfail(b, LBM_E_ARG, lbm_last_error(nullptr));
+  if (bytes > b->slot_bytes[index])
+    return bfail(b, LBM_E_ARG, "the replacement case needs " + std::to_string(bytes) + " bytes; slot " +
+                                   std::to_string(index) + " holds " + std::to_string(b->slot_bytes[index]));
   lbm_handle* nh = nullptr;
-  const size_t slot = (index + 1 < b->count ? b->off[index + 1] : b->off[index] + align256(bytes)) - b->off[index];
-  rc = lbm_init(p, (char*)b->buf + b->off[index], slot, b->stream, &nh);
+  rc = lbm_init(p, (char*)b->buf + b->off[index], b->slot_bytes[index], b->stream, &nh);
   if (rc) return bfail(b, rc, lbm_last_error(nullptr));
+  lbm::HandleView old = lbm::handle_view(b->h[index]);
+  const bool same_tiling = old.dp->nx == p->nx && old.dp->ny == p->ny;
   lbm_destroy(b->h[index]);   // does not own the buffer or the stream
   b->h[index] = nh;
   lbm::handle_view(nh).ds->tile_rows = b->seg_rows;
+  b->active[index] = 1;
   b->hc[index].active = 1;
+  if (!same_tiling || b->table_dirty) {   // another grid: new workgroup map at the next use
+    b->table_dirty = true;
+    return LBM_OK;
+  }
   return push_case(b, index);
+}
+
+int lbm_batch_slot_bytes(lbm_batch* b, int32_t index, size_t* bytes) {
+  if (!b || !bytes) return bfail(b, LBM_E_ARG, "null argument");
+  const int rc = check_index(b, index);
+  if (rc) return rc;
+  *bytes = b->slot_bytes[index];
+  return LBM_OK;
 }
 
 int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, int32_t* seg_rows_out) {

@@ -36,7 +36,7 @@ EXPORTS = ["lbm_required_bytes", "lbm_init", "lbm_step", "lbm_reduce_invariants"
            "lbm_fetch_populations", "lbm_destroy", "lbm_last_error", "lbm_timing_begin", "lbm_timing_end",
            "lbm_bytes_per_node_step", "lbm_probe_bytes", "lbm_probe_stream", "lbm_probe_copy", "lbm_step_kernel",
            "lbm_batch_required_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_set_active",
-           "lbm_batch_reduce_invariants", "lbm_batch_fetch_fields", "lbm_batch_replace_case", "lbm_batch_autotune",
+           "lbm_batch_reduce_invariants", "lbm_batch_fetch_fields", "lbm_batch_replace_case", "lbm_batch_slot_bytes", "lbm_batch_autotune",
            "lbm_batch_info", "lbm_batch_timing_begin", "lbm_batch_timing_end", "lbm_batch_destroy",
            "lbm_batch_last_error"]
 KERNEL_NAMES = ["k_step", "k_step_finish"]
@@ -128,6 +128,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_batch_reduce_invariants.argtypes = [vp, ctypes.POINTER(Invariants)]
         L.lbm_batch_fetch_fields.argtypes = [vp, ctypes.c_int32, ctypes.c_uint32, dp, sz]
         L.lbm_batch_replace_case.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Params)]
+        L.lbm_batch_slot_bytes.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(sz)]
         L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int32, i32p]
         L.lbm_batch_info.argtypes = [vp, i32p, i32p, i32p, i64p]
         L.lbm_batch_timing_begin.argtypes = [vp, ctypes.c_int64]
@@ -401,9 +402,17 @@ class Batch:
         return {nm: out[k * nx * ny:(k + 1) * nx * ny].reshape(ny, nx) for k, nm in enumerate(order)}
 
     def replace_case(self, index: int, cfg: dict):
+        """Refill slot index with a new case of any grid that fits the slot
+        (lbm_batch_replace_case)."""
         p = make_params(cfg, PRECISIONS[self.precision])
         _bcheck(lib().lbm_batch_replace_case(self._b, int(index), ctypes.byref(p)), self._b)
         self.cfgs[index] = dict(cfg)
+
+    def slot_bytes(self, index: int) -> int:
+        """Device bytes slot index holds (lbm_batch_slot_bytes)."""
+        n = ctypes.c_size_t()
+        _bcheck(lib().lbm_batch_slot_bytes(self._b, int(index), ctypes.byref(n)), self._b)
+        return n.value
 
     def autotune(self, trial_steps: int = 20) -> int:
         seg = ctypes.c_int32()

@@ -25,17 +25,18 @@ def lbm():
     return binding
 
 
+def walled_case(nx, ny, R, th, s, psi_b, Ca):
+    cfg = inputs.sessile_drop(nx=nx, ny=ny, R=R, theta0_deg=th, psi_b=psi_b)
+    cfg.update(beta_sg=s, beta_sl=0.01, bc_top=inputs.NOSLIP, u_wall_top=Ca * 0.01 / 0.1)
+    return cfg
+
+
 def sweep_like_cases():
     """Walled cases of uneven sizes and parameters in the spirit of the sweep
     distribution, small enough for quick tests (ragged in x and y)."""
-    out = []
-    for nx, ny, R, th, s, psi_b, Ca in ((64, 32, 10.0, 45.0, 0.1, 0.01, 0.0), (96, 48, 15.0, 120.0, 0.4, 0.03, 0.1),
-                                        (70, 37, 11.0, 90.0, 0.25, 0.02, 0.2), (128, 64, 20.0, 60.0, 0.0, 0.005, 0.05),
-                                        (80, 40, 13.0, 140.0, 0.5, 0.05, 0.15)):
-        cfg = inputs.sessile_drop(nx=nx, ny=ny, R=R, theta0_deg=th, psi_b=psi_b)
-        cfg.update(beta_sg=s, beta_sl=0.01, bc_top=inputs.NOSLIP, u_wall_top=Ca * 0.01 / 0.1)
-        out.append(cfg)
-    return out
+    return [walled_case(*a) for a in ((64, 32, 10.0, 45.0, 0.1, 0.01, 0.0), (96, 48, 15.0, 120.0, 0.4, 0.03, 0.1),
+                                      (70, 37, 11.0, 90.0, 0.25, 0.02, 0.2), (128, 64, 20.0, 60.0, 0.0, 0.005, 0.05),
+                                      (80, 40, 13.0, 140.0, 0.5, 0.05, 0.15))]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64", "fp16"])
@@ -92,6 +93,68 @@ def test_batch_replace_case(lbm):
         assert np.array_equal(fb[nm], fs[nm]), nm
     with pytest.raises(lbm.LbmError):
         b.replace_case(2, dict(new, nx=72))
+
+
+def test_batch_refill_with_other_grids(lbm):
+    """A slot takes a case of another grid that fits it: the workgroup map is
+    rebuilt, the other cases keep their state and go on, and every case
+    matches a single handle bit for bit; a case that needs more bytes than its
+    slot is refused."""
+    cases = sweep_like_cases()
+    b = lbm.Batch(cases, "fp32", seg_rows=8)
+    singles = [lbm.Sim(dict(c, tile_rows=8), "fp32") for c in cases]
+    b.step(20)
+    for s in singles:
+        s.step(20)
+    new3 = walled_case(112, 56, 17.0, 100.0, 0.3, 0.02, 0.1)   # into the 128x64 slot
+    new1 = walled_case(64, 32, 9.0, 70.0, 0.2, 0.01, 0.05)     # into the 96x48 slot
+    assert b.slot_bytes(3) >= lbm.required_bytes(new3, "fp32") and b.slot_bytes(1) >= lbm.required_bytes(new1, "fp32")
+    b.replace_case(3, new3)
+    b.replace_case(1, new1)
+    frozen = b.fields(0, FIELDS)
+    b.set_active([0, 1, 1, 1, 1])   # and case 0 retires meanwhile
+    singles[3] = lbm.Sim(dict(new3, tile_rows=8), "fp32")
+    singles[1] = lbm.Sim(dict(new1, tile_rows=8), "fp32")
+    b.step(37)
+    for k in range(1, 5):
+        singles[k].step(37)
+        fb, fs = b.fields(k, FIELDS), singles[k].fields(FIELDS)
+        for nm in FIELDS:
+            assert np.array_equal(fb[nm], fs[nm]), (k, nm)
+        ib, i1 = b.invariants()[k], singles[k].invariants()
+        assert ib["lambda_phi"] == i1["lambda_phi"] and ib["mass_psi"] == i1["mass_psi"], k
+    f0 = b.fields(0, FIELDS)
+    for nm in FIELDS:
+        assert np.array_equal(f0[nm], frozen[nm]), nm
+    with pytest.raises(lbm.LbmError):
+        b.replace_case(0, cases[3])   # 128x64 into the 64x32 slot
+    # a refill with the slot's own grid keeps the map; stepping on still matches
+    b.replace_case(2, dict(cases[2], theta0_deg=50.0))
+    s2 = lbm.Sim(dict(cases[2], theta0_deg=50.0, tile_rows=8), "fp32")
+    b.step(9)
+    s2.step(9)
+    assert np.array_equal(b.fields(2, ["phi"])["phi"], s2.fields(["phi"])["phi"])
+
+
+def test_sweep_with_refill_equals_one_batch(lbm):
+    """sweep.run_sweep with fewer slots than cases refills each finished slot
+    with the next waiting case (largest first, grids of other sizes): every
+    case's status, stop step and angle equal those of the same cases run in
+    one batch."""
+    from paper_2609_26332_amd import sweep
+
+    cases = [c for c in inputs.sweep_batch(77, 80) if c["nx"] <= 128][:10]
+    assert len(cases) == 10 and len({(c["nx"], c["ny"]) for c in cases}) > 1
+    kw = dict(precision="fp32", seg_rows=8, autotune=False, check_every=250, steady_window=500, steady_tol=0.5,
+              cap=1500)
+    one = sweep.run_sweep(cases, **kw)
+    four = sweep.run_sweep(cases, slots=4, **kw)
+    assert one["refills"] == 0 and four["refills"] == len(cases) - 4 and four["slots"] == 4
+    for k, (a, r) in enumerate(zip(one["results"], four["results"])):
+        assert a["status"] == r["status"] and a["step"] == r["step"], (k, a, r)
+        ta, tr = a.get("theta_app_deg", 0.0), r.get("theta_app_deg", 0.0)
+        assert ta == tr or (np.isnan(ta) and np.isnan(tr)), (k, ta, tr)
+        assert a["mass_psi"] == r["mass_psi"], k
 
 
 def test_batch_fp64_matches_oracle(lbm):
