@@ -235,6 +235,40 @@ def sweep_file(seed):
     return os.path.join(DATA_DIR, "sweep_seed%d.npz" % seed)
 
 
+def stream_sweep(n_cases: int, slots: int, cap: int, seed: int = 3000) -> dict:
+    """A stream of sweep cases longer than the batch: n_cases cases of the
+    sweep distribution through `slots` batch slots, each finished slot
+    refilled with the next waiting case, against the same cases run as
+    consecutive batches of `slots` cases each; 16-row segments in both, so
+    every case's results must agree exactly."""
+    from paper_2609_26332_amd import inputs, sweep
+
+    cases = inputs.sweep_batch(seed, n_cases)
+    kw = dict(precision="fp32", seg_rows=16, autotune=False, cap=cap)
+    print("stream: %d cases through %d slots, cap %d" % (n_cases, slots, cap), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    refill = sweep.run_sweep(cases, slots=slots, **kw)
+    t_refill = time.perf_counter() - t0
+    print("stream: refilled run %.1f s" % t_refill, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    seq = []
+    for i in range(0, n_cases, slots):
+        seq += sweep.run_sweep(cases[i:i + slots], **kw)["results"]
+        print("stream: consecutive batch %d done" % (i // slots), file=sys.stderr, flush=True)
+    t_seq = time.perf_counter() - t0
+    same = all(a["status"] == b["status"] and a["step"] == b["step"] and a["mass_psi"] == b["mass_psi"]
+               for a, b in zip(refill["results"], seq))
+    status = {}
+    for r in refill["results"]:
+        status[r["status"]] = status.get(r["status"], 0) + 1
+    return {"workload": "stream of %d sweep cases (seed %d) through %d slots, stop rule capped at %d steps"
+                        % (n_cases, seed, slots, cap),
+            "refill_seconds": round(t_refill, 2), "refill_cases_per_s": round(n_cases / t_refill, 3),
+            "refills": refill["refills"], "consecutive_batches_seconds": round(t_seq, 2),
+            "consecutive_cases_per_s": round(n_cases / t_seq, 3), "speedup": round(t_seq / t_refill, 3),
+            "identical_results": bool(same), "status": status}
+
+
 def surrogate_sweep(cap: int = 50000) -> dict:
     """The second half of the metric: the 512 held-out cases of the sweep
     distribution (seed 2000) delivered by the batched solver alone and by the
@@ -347,8 +381,12 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=20, help="event-timed steps for the kernel figures")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline batch (profiling aid)")
-    ap.add_argument("--workload", default="all", choices=["all", "batch", "grid4096", "grid3d", "surrogate", "mlp"],
-                    help="profiling aid: one workload only")
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "batch", "grid4096", "grid3d", "surrogate", "mlp", "stream"],
+                    help="profiling aid: one workload only (stream: a case stream longer than the batch, with refill)")
+    ap.add_argument("--stream-cases", type=int, default=1024)
+    ap.add_argument("--stream-slots", type=int, default=512)
+    ap.add_argument("--stream-cap", type=int, default=10000)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16"],
                     help="profiling aid: storage of the single workload run with --workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -375,6 +413,9 @@ def main():
         return
     if args.workload == "mlp":
         print(json.dumps(surrogate_rate()), flush=True)
+        return
+    if args.workload == "stream":
+        print(json.dumps(stream_sweep(args.stream_cases, args.stream_slots, args.stream_cap)), flush=True)
         return
     if args.workload == "grid3d":
         p3 = args.precision if args.precision in ("fp32", "fp64") else "fp32"
