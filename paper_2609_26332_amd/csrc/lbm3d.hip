@@ -85,11 +85,18 @@ __constant__ int kC3[Q3][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {
 __constant__ double kW3[Q3] = {1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
                                1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
                                1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+// w_i / c_s^2, the gradient stencil's coefficients: the same values as the
+// unrolled stencil's w3(i) / kCs2, folded at compile time here and there.
+#define W3CS(i) (w3(i) / kCs2)
+__constant__ double kWC3[Q3] = {W3CS(0),  W3CS(1),  W3CS(2),  W3CS(3),  W3CS(4),  W3CS(5),  W3CS(6),
+                                W3CS(7),  W3CS(8),  W3CS(9),  W3CS(10), W3CS(11), W3CS(12), W3CS(13),
+                                W3CS(14), W3CS(15), W3CS(16), W3CS(17), W3CS(18)};
+#undef W3CS
 
 struct P3 {
   int nx, ny, nz, N, periodic_z, wet_b, wet_t, freeslip_b, freeslip_t, surf, linear, adv_raw, s2_local, phi_hold;
   int has_solid, solid_wet, Nf;   // solid mask present; solids carry the wetting BCs; fluid nodes
-  double kappa, beta, W, kBT, phib, lambda_s, M0, M_phi, M_psi, eta_phi, eta_psi;
+  double kappa, beta, W, kBT, phib, inv_phib, lambda_s, M0, M_phi, M_psi, eta_phi, eta_psi;
   double rho_l, rho_g, mu_l, mu_g, gx, gy, gz, uw_b, uw_t;
   double sig_cos, dsb, msb;   // sigma cos(theta0), sigma_sg0 beta_sg -/+ sigma_sl0 beta_sl
   double sf[5], sg[5], sh[5];
@@ -117,7 +124,7 @@ struct St3 {
 };
 
 __device__ __forceinline__ double liquid_frac(const P3& p, double ph) {
-  const double w = 0.5 * (1.0 + ph / p.phib);
+  const double w = 0.5 * (1.0 + ph * p.inv_phib);
   return w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
 }
 __device__ __forceinline__ double rho_of(const P3& p, double ph) { return p.rho_g + (p.rho_l - p.rho_g) * liquid_frac(p, ph); }
@@ -330,6 +337,109 @@ __device__ __forceinline__ void accum3(int i, T f, T feq, T v, const T* rate5, T
   for (int o = 0; o < 5; ++o) q[o] = (T(1) - rate5[o]) * f + rate5[o] * feq + (T(1) - T(0.5) * rate5[o]) * v;
   accum3(i, q, m);
 }
+// Raw moments of populations as they stream in: direction i adds f to every
+// moment its raw-moment entry selects.
+template <class T>
+__device__ __forceinline__ void raw3(int i, T f, T* m) {
+  const T q[5] = {f, f, f, f, f};
+  accum3(i, q, m);
+}
+// Order of raw moment k (the index of its relaxation rate).
+__host__ __device__ constexpr int order3(int k) { return k == 0 ? 0 : (k < 4 ? 1 : (k < 10 ? 2 : (k < 16 ? 3 : 4))); }
+// Post-collision moments (I - S) m + S meq + (I - S/2) mv, S diagonal by order.
+template <class T>
+__device__ __forceinline__ void relax3(const T* rate5, const T* mf, const double* meq, const double* mv, T* m) {
+#pragma unroll
+  for (int k = 0; k < Q3; ++k) {
+    const T s = rate5[order3(k)];
+    m[k] = (T(1) - s) * mf[k] + s * (T)meq[k] + (T(1) - T(0.5) * s) * (T)mv[k];
+  }
+}
+// Raw moments of D3Q19's weights times the velocity monomials that the
+// equilibria below need: sum w = 1, sum w c_a^2 = c_s^2 = 1/3, sum w c_a^2 c_b^2
+// = c_s^4 = 1/9 (a != b), sum w c_a^4 = 1/3, sum w c_a^4 c_b^2 = 1/9, and no
+// velocity has three nonzero components; odd monomials sum to zero.  From
+// these, the moments of the flow equilibrium (Sec. 3, pressure based: p/c_s^2
+// (w_i - delta_i0) + rho w_i s_i(u)) and of its forcing vector
+// w_i [u.grad rho + c_i.F/c_s^2 + ((c_i.u)(c_i.grad rho) - c_s^2 u.grad rho)/c_s^2]
+// follow in closed form: no per-direction equilibrium is formed.
+__device__ __forceinline__ void flow_moments3(double pr, double rho, const double* u, const double* G, const double* F,
+                                              double* meq, double* mv) {
+  const double ux = u[0], uy = u[1], uz = u[2];
+  const double xx = ux * ux, yy = uy * uy, zz = uz * uz;
+  meq[0] = 0.0;
+  meq[1] = rho * ux;
+  meq[2] = rho * uy;
+  meq[3] = rho * uz;
+  meq[4] = pr + rho * xx;
+  meq[5] = pr + rho * yy;
+  meq[6] = pr + rho * zz;
+  meq[7] = rho * ux * uy;
+  meq[8] = rho * ux * uz;
+  meq[9] = rho * uy * uz;
+  meq[10] = rho * uy / 3.0;   // xxy
+  meq[11] = rho * uz / 3.0;   // xxz
+  meq[12] = rho * ux / 3.0;   // yyx
+  meq[13] = rho * uz / 3.0;   // yyz
+  meq[14] = rho * ux / 3.0;   // zzx
+  meq[15] = rho * uy / 3.0;   // zzy
+  meq[16] = pr / 3.0 + rho * ((xx + yy) / 3.0 - zz / 6.0);
+  meq[17] = pr / 3.0 + rho * ((xx + zz) / 3.0 - yy / 6.0);
+  meq[18] = pr / 3.0 + rho * ((yy + zz) / 3.0 - xx / 6.0);
+  const double gx = ux * G[0], gy = uy * G[1], gz = uz * G[2];
+  mv[0] = gx + gy + gz;
+  mv[1] = F[0];
+  mv[2] = F[1];
+  mv[3] = F[2];
+  mv[4] = gx + (gy + gz) / 3.0;
+  mv[5] = gy + (gx + gz) / 3.0;
+  mv[6] = gz + (gx + gy) / 3.0;
+  mv[7] = (ux * G[1] + uy * G[0]) / 3.0;
+  mv[8] = (ux * G[2] + uz * G[0]) / 3.0;
+  mv[9] = (uy * G[2] + uz * G[1]) / 3.0;
+  mv[10] = F[1] / 3.0;
+  mv[11] = F[2] / 3.0;
+  mv[12] = F[0] / 3.0;
+  mv[13] = F[2] / 3.0;
+  mv[14] = F[0] / 3.0;
+  mv[15] = F[1] / 3.0;
+  mv[16] = (gx + gy) / 3.0;
+  mv[17] = (gx + gz) / 3.0;
+  mv[18] = (gy + gz) / 3.0;
+}
+// The same for a phase-field or surfactant lattice (Sec. 3): equilibrium
+// (i = 0: (w_0 - 1) eta c, the rest population taken relative to c; else
+// w_i eta c) + w_i c_i.(c v)/c_s^2, forcing w_i c_i.d/c_s^2 with d the backward
+// difference of c v.
+__device__ __forceinline__ void scalar_moments3(double c, double eta, const double* v, const double* d, double* meq,
+                                                double* mv) {
+  const double e = eta * c, jx = c * v[0], jy = c * v[1], jz = c * v[2];
+  meq[0] = 0.0;
+  meq[1] = jx;
+  meq[2] = jy;
+  meq[3] = jz;
+  meq[4] = meq[5] = meq[6] = e / 3.0;
+  meq[7] = meq[8] = meq[9] = 0.0;
+  meq[10] = jy / 3.0;
+  meq[11] = jz / 3.0;
+  meq[12] = jx / 3.0;
+  meq[13] = jz / 3.0;
+  meq[14] = jx / 3.0;
+  meq[15] = jy / 3.0;
+  meq[16] = meq[17] = meq[18] = e / 9.0;
+  mv[0] = 0.0;
+  mv[1] = d[0];
+  mv[2] = d[1];
+  mv[3] = d[2];
+  mv[4] = mv[5] = mv[6] = mv[7] = mv[8] = mv[9] = 0.0;
+  mv[10] = d[1] / 3.0;
+  mv[11] = d[2] / 3.0;
+  mv[12] = d[0] / 3.0;
+  mv[13] = d[2] / 3.0;
+  mv[14] = d[0] / 3.0;
+  mv[15] = d[1] / 3.0;
+  mv[16] = mv[17] = mv[18] = 0.0;
+}
 // Populations from raw moments (the inverse of moments3).
 template <class T>
 __device__ __forceinline__ void populations3(const T* m, T* f) {
@@ -384,12 +494,14 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
     for (int i = 1; i < Q3; ++i) {
       const int m = (wrap(z + cz3(i), p.nz) * p.ny + wrap(y + cy3(i), p.ny)) * p.nx + wrap(x + cx3(i), p.nx);
       const double r = rho_of(p, pp[m]), mp = mu[m], ms = mu[N + m], pn = pp[N + m];
-      const double c[3] = {(double)cx3(i), (double)cy3(i), (double)cz3(i)};
+      const int c[3] = {cx3(i), cy3(i), cz3(i)};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        gr[d] += w3(i) * c[d] * r / kCs2;
-        gmp[d] += w3(i) * c[d] * mp / kCs2;
-        gms[d] += w3(i) * c[d] * ms / kCs2;
+        if (c[d] == 0) continue;   // adds zero in the general form
+        const double wc = c[d] * (w3(i) / kCs2);
+        gr[d] += wc * r;
+        gmp[d] += wc * mp;
+        gms[d] += wc * ms;
       }
       l0s += 2.0 * w3(i) / kCs2 * (pn - M.ps);
     }
@@ -431,16 +543,17 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
           ts += 2.0 * wi / kCs2 * wall_jpsi(p, fph, fps);
         }
       }
-      const double c[3] = {(double)cx, (double)cy, (double)cz};
+      const int c[3] = {cx, cy, cz};
       for (int d = 0; d < 3; ++d) {
-        gr[d] += wi * c[d] * r / kCs2;
-        gmp[d] += wi * c[d] * mp / kCs2;
-        gms[d] += wi * c[d] * ms / kCs2;
+        const double wc = c[d] * kWC3[i];
+        gr[d] += wc * r;
+        gmp[d] += wc * mp;
+        gms[d] += wc * ms;
       }
       l0s += 2.0 * wi / kCs2 * (pn - M.ps);
     }
   }
-  const double G[3] = {p.gx, p.gy, p.gz};
+  const double G[3] = {p.gx, p.gy, p.gz}, inv_rho = 1.0 / M.rho;
   double j[3] = {0, 0, 0}, snz = 0.0;
 #pragma unroll
   for (int i = 0; i < Q3; ++i) {
@@ -454,7 +567,7 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
   for (int d = 0; d < 3; ++d) {
     M.gr[d] = gr[d];
     M.F[d] = -M.ph * gmp[d] - M.ps * gms[d] + M.rho * G[d];
-    M.u[d] = (j[d] + 0.5 * M.F[d]) / M.rho;
+    M.u[d] = (j[d] + 0.5 * M.F[d]) * inv_rho;
   }
   const double ugr = M.u[0] * gr[0] + M.u[1] * gr[1] + M.u[2] * gr[2];
   const double uu = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
@@ -514,20 +627,14 @@ __global__ __launch_bounds__(kT, kColfWaves<S>) void k3_colf(
       const double mud = p.mu_g + (p.mu_l - p.mu_g) * liquid_frac(p, ph);
       rates[2] = (T)(1.0 / (3.0 * mud / rho + 0.5));
     }
-    const double uu = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
-    const double ugr = M.u[0] * M.gr[0] + M.u[1] * M.gr[1] + M.u[2] * M.gr[2];
+    T mf[Q3];
 #pragma unroll
-    for (int k = 0; k < Q3; ++k) m[k] = T(0);
+    for (int k = 0; k < Q3; ++k) mf[k] = T(0);
 #pragma unroll
-    for (int i = 0; i < Q3; ++i) {
-      const double fi = ld(pin, (size_t)i * N + n);
-      const double cu = cdot3(i, M.u[0], M.u[1], M.u[2]);
-      const double su = cu / kCs2 + cu * cu / (2.0 * kCs2 * kCs2) - uu / (2.0 * kCs2);
-      const double eq = M.pr / kCs2 * (w3(i) - (i == 0 ? 1.0 : 0.0)) + rho * w3(i) * su;
-      const double cg = cdot3(i, M.gr[0], M.gr[1], M.gr[2]), cF = cdot3(i, M.F[0], M.F[1], M.F[2]);
-      const double fv = w3(i) * (ugr + cF / kCs2 + (cu * cg - kCs2 * ugr) / kCs2);
-      accum3<T>(i, (T)fi, (T)eq, (T)fv, rates, m);   // pressure-based: f_i are of the order of p w_i / c_s^2
-    }
+    for (int i = 0; i < Q3; ++i) raw3<T>(i, (T)ld(pin, (size_t)i * N + n), mf);   // pressure-based: of the order of p w_i / c_s^2
+    double meq[Q3], mv[Q3];
+    flow_moments3(M.pr, rho, M.u, M.gr, M.F, meq, mv);
+    relax3<T>(rates, mf, meq, mv, m);
     populations3<T>(m, f);
     // push streaming; walls in z
 #pragma unroll
@@ -608,17 +715,19 @@ __global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const
     const double extra = lat == 1 ? Rphi + 0.5 * dRp : Rpsi + 0.5 * dRs;
     const int base = 19 * lat;
     const double cref = lat == 1 ? pprev[n] : pprev[N + n];   // the shift of the stored rest population
+    T mf[Q3];
 #pragma unroll
-    for (int k = 0; k < Q3; ++k) m[k] = T(0);
+    for (int k = 0; k < Q3; ++k) mf[k] = T(0);
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
       // rest population shifted by c (the collision maps g - c e_0 to its image
       // minus c e_0), so the collision sees increments only
       const double fi = ld(pin, (size_t)(base + i) * N + n) + (i == 0 ? cref - c : 0.0);
-      const double eq = (i == 0 ? (w3(0) - 1.0) * eta * c : w3(i) * eta * c) + w3(i) * cdot3(i, c * v[0], c * v[1], c * v[2]) / kCs2;
-      const double fv = w3(i) * cdot3(i, dj[0], dj[1], dj[2]) / kCs2;
-      accum3<T>(i, (T)fi, (T)eq, (T)fv, r5, m);
+      raw3<T>(i, (T)fi, mf);
     }
+    double meq[Q3], mv[Q3];
+    scalar_moments3(c, eta, v, dj, meq, mv);
+    relax3<T>(r5, mf, meq, mv, m);
     populations3<T>(m, f);
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
@@ -869,7 +978,7 @@ std::string derive3(const lbm3d_params& q, P3& d) {
   const double M0 = q.M0 >= 0.0 ? q.M0 : (lambda_s > 0.0 ? 0.0 : q.M_phi * kappa);
   auto rate = [](double v) { return v > 0.0 ? v : 1.0; };
   const double s1g = rate(q.s_g[1]), s1h = rate(q.s_h[1]);
-  d.kappa = kappa; d.beta = beta; d.W = W; d.kBT = kBT; d.phib = phib;
+  d.kappa = kappa; d.beta = beta; d.W = W; d.kBT = kBT; d.phib = phib; d.inv_phib = 1.0 / phib;
   d.lambda_s = lambda_s; d.M0 = M0; d.M_phi = q.M_phi; d.M_psi = q.M_psi;
   d.eta_phi = q.eta_phi > 0.0 ? q.eta_phi : q.M_phi * kappa / ((1.0 / s1g - 0.5) * kCs2);
   d.eta_psi = q.eta_psi > 0.0 ? q.eta_psi : (q.M_psi * lambda_s + M0) / ((1.0 / s1h - 0.5) * kCs2);
