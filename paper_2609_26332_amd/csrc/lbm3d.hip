@@ -114,7 +114,7 @@ struct St3 {
   void* pops[2];     // 57 planes each (f 0..18, g 19..37, h 38..56), storage type
   double* pp[2];     // phi, psi planes of a state (pp[cur]: current, pp[cur ^ 1]: previous)
   double* mu;        // mu_phi, mu_psi planes
-  double* uh[2];     // history: ux, uy, uz, vx, vy, vz, R_phi, R_psi of a step
+  void* uh[2];       // history: ux, uy, uz, vx, vy, vz, R_phi, R_psi of a step, in the storage type
   double* part;      // [kRedB][4] multiplier sums or [kRedB][8] invariant sums
   Scal3* sc;         // multipliers of the current step
   double* stage;     // FP64 staging [9][N]
@@ -581,14 +581,15 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
 // ---------------------------------------------------------------- k3_colf
 // Macroscopic state, sources and advecting velocity of the step (into the
 // history planes hout), then the flow lattice's collision and streaming.
-// Waves per SIMD the flow kernel is built for: four in FP32 storage (one
-// register spills), two in FP64.
+// Launch bound of the flow kernel: four waves per SIMD in FP32 storage, two in
+// FP64; both compile without spills to at most 128 registers, so both run at
+// four.
 template <class S>
 constexpr int kColfWaves = sizeof(S) == 8 ? 2 : 4;
 template <class S>
 __global__ __launch_bounds__(kT, kColfWaves<S>) void k3_colf(
     const P3* __restrict__ pp_, const unsigned char* __restrict__ solid, const S* __restrict__ pin, S* __restrict__ pout,
-    const double* __restrict__ pp, const double* __restrict__ mu, const double* __restrict__ hin, double* __restrict__ hout,
+    const double* __restrict__ pp, const double* __restrict__ mu, const S* __restrict__ hin, S* __restrict__ hout,
     const Scal3* __restrict__ sc, int have_hist) {
   const P3& p = *pp_;
   const int N = p.N;
@@ -609,13 +610,13 @@ __global__ __launch_bounds__(kT, kColfWaves<S>) void k3_colf(
   // advecting velocity (the step's own u, or its mean with the previous step's)
   double v[3] = {M.u[0], M.u[1], M.u[2]};
   if (have_hist && !p.adv_raw)
-    for (int d = 0; d < 3; ++d) v[d] = 0.5 * (M.u[d] + hin[(size_t)d * N + n]);
+    for (int d = 0; d < 3; ++d) v[d] = 0.5 * (M.u[d] + (double)hin[(size_t)d * N + n]);
   for (int d = 0; d < 3; ++d) {
-    hout[(size_t)d * N + n] = M.u[d];
-    hout[(size_t)(3 + d) * N + n] = v[d];
+    hout[(size_t)d * N + n] = (S)M.u[d];
+    hout[(size_t)(3 + d) * N + n] = (S)v[d];
   }
-  hout[(size_t)6 * N + n] = Rphi;
-  hout[(size_t)7 * N + n] = Rpsi;
+  hout[(size_t)6 * N + n] = (S)Rphi;
+  hout[(size_t)7 * N + n] = (S)Rpsi;
 
   const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
   using T = S;   // collision arithmetic: the storage type (FP32 or FP64)
@@ -669,7 +670,7 @@ template <class S>
 __global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
                                                const S* __restrict__ pin, S* __restrict__ pout,
                                                const double* __restrict__ pp, const double* __restrict__ pprev,
-                                               const double* __restrict__ hcur, const double* __restrict__ hprev,
+                                               const S* __restrict__ hcur, const S* __restrict__ hprev,
                                                int have_hist) {
   const P3& p = *pp_;
   const int N = p.N;
@@ -677,18 +678,18 @@ __global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const
   if (n >= N) return;
   if (p.has_solid && solid[n]) return;
   const double ph = pp[n], ps = pp[N + n];
-  const double v[3] = {hcur[(size_t)3 * N + n], hcur[(size_t)4 * N + n], hcur[(size_t)5 * N + n]};
-  const double Rphi = hcur[(size_t)6 * N + n], Rpsi = hcur[(size_t)7 * N + n];
+  const double v[3] = {(double)hcur[(size_t)3 * N + n], (double)hcur[(size_t)4 * N + n], (double)hcur[(size_t)5 * N + n]};
+  const double Rphi = (double)hcur[(size_t)6 * N + n], Rpsi = (double)hcur[(size_t)7 * N + n];
   double dph[3] = {0, 0, 0}, dps[3] = {0, 0, 0}, dRp = 0.0, dRs = 0.0;
   if (have_hist) {
     const double php = pprev[n], psp = pprev[N + n];
     for (int d = 0; d < 3; ++d) {
-      const double vh = hprev[(size_t)(3 + d) * N + n];
+      const double vh = (double)hprev[(size_t)(3 + d) * N + n];
       dph[d] = ph * v[d] - php * vh;
       dps[d] = ps * v[d] - psp * vh;
     }
-    dRp = Rphi - hprev[(size_t)6 * N + n];
-    dRs = Rpsi - hprev[(size_t)7 * N + n];
+    dRp = Rphi - (double)hprev[(size_t)6 * N + n];
+    dRs = Rpsi - (double)hprev[(size_t)7 * N + n];
   }
   const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
   using T = S;   // collision arithmetic: the storage type (FP32 or FP64)
@@ -1007,7 +1008,7 @@ Lay3 layout3(const lbm3d_params& q) {
   L.pops = take(2 * 57 * N * sb);
   L.pp = take(2 * 2 * N * 8);
   L.mu = take(2 * N * 8);
-  L.uh = take(2 * 8 * N * 8);
+  L.uh = take(2 * 8 * N * sb);
   L.part = take((size_t)kRedB * 8 * 8);
   L.sc = take(sizeof(Scal3));
   L.stage = take(9 * N * 8);
@@ -1029,10 +1030,10 @@ hipError_t step3(lbm3d_handle* h) {
   hipLaunchKernelGGL(k3_fin, dim3(1), dim3(64), 0, h->stream, s.dp, (const double*)s.part, rb, s.sc);
   hipLaunchKernelGGL((k3_colf<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
                      (const S*)s.pops[c], (S*)s.pops[c ^ 1], (const double*)s.pp[c], (const double*)s.mu,
-                     (const double*)s.uh[c ^ 1], s.uh[c], (const Scal3*)s.sc, h->have_hist);
+                     (const S*)s.uh[c ^ 1], (S*)s.uh[c], (const Scal3*)s.sc, h->have_hist);
   hipLaunchKernelGGL((k3_colgh<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
                      (const S*)s.pops[c], (S*)s.pops[c ^ 1], (const double*)s.pp[c], (const double*)s.pp[c ^ 1],
-                     (const double*)s.uh[c], (const double*)s.uh[c ^ 1], h->have_hist);
+                     (const S*)s.uh[c], (const S*)s.uh[c ^ 1], h->have_hist);
   hipLaunchKernelGGL((k3_mom<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
                      (const S*)s.pops[c ^ 1],
                      (const double*)s.pp[c], s.pp[c ^ 1]);
@@ -1145,8 +1146,8 @@ int lbm3d_init(const lbm3d_params* q, void* dev_buf, size_t buf_bytes, void* hip
   h->s.pp[0] = (double*)(b + L.pp);
   h->s.pp[1] = h->s.pp[0] + 2 * N;
   h->s.mu = (double*)(b + L.mu);
-  h->s.uh[0] = (double*)(b + L.uh);
-  h->s.uh[1] = h->s.uh[0] + 8 * N;
+  h->s.uh[0] = b + L.uh;
+  h->s.uh[1] = b + L.uh + 8 * N * sb;
   h->s.part = (double*)(b + L.part);
   h->s.sc = (Scal3*)(b + L.sc);
   h->s.stage = (double*)(b + L.stage);
@@ -1263,8 +1264,8 @@ int lbm3d_bytes_per_node_step(lbm3d_handle* h, double* bytes) {
   // k3_mu: phi/psi read, mu written; k3_colf: 19 populations, phi/psi, mu and the previous u read, 19
   // populations and 8 history planes written; k3_colgh: 38 populations, phi/psi of two steps and 5 history
   // planes of two steps read, 38 populations written; k3_mom: 38 populations and phi/psi read, phi/psi written
-  *bytes = (2 * 8 + 2 * 8) + (19 * sb + 2 * 8 + 2 * 8 + 3 * 8 + 19 * sb + 8 * 8) +
-           (38 * sb + 4 * 8 + 10 * 8 + 38 * sb) + (38 * sb + 2 * 8 + 2 * 8);
+  *bytes = (2 * 8 + 2 * 8) + (19 * sb + 2 * 8 + 2 * 8 + 3 * sb + 19 * sb + 8 * sb) +
+           (38 * sb + 4 * 8 + 10 * sb + 38 * sb) + (38 * sb + 2 * 8 + 2 * 8);
   return LBM_OK;
 }
 
