@@ -129,12 +129,12 @@ __device__ __forceinline__ double liquid_frac(const P3& p, double ph) {
 }
 __device__ __forceinline__ double rho_of(const P3& p, double ph) { return p.rho_g + (p.rho_l - p.rho_g) * liquid_frac(p, ph); }
 __device__ __forceinline__ double gsw(const P3& p, double ph) {
-  const double b = p.phib;
-  return 0.75 * ph / b - 0.25 * ph * ph * ph / (b * b * b);
+  const double r = ph * p.inv_phib;
+  return 0.75 * r - 0.25 * r * r * r;
 }
 __device__ __forceinline__ double gsw_d(const P3& p, double ph) {
-  const double r = ph / p.phib;
-  return 0.75 / p.phib * (1.0 - r * r);
+  const double r = ph * p.inv_phib;
+  return 0.75 * p.inv_phib * (1.0 - r * r);
 }
 __device__ __forceinline__ double hprime(const P3& p, double ph) { return p.linear ? 1.0 : gsw_d(p, ph); }
 __device__ __forceinline__ double hval(const P3& p, double ph) { return p.linear ? ph : 0.5 + gsw(p, ph); }
@@ -1035,8 +1035,7 @@ hipError_t step3(lbm3d_handle* h) {
                      (const S*)s.pops[c], (S*)s.pops[c ^ 1], (const double*)s.pp[c], (const double*)s.pp[c ^ 1],
                      (const S*)s.uh[c], (const S*)s.uh[c ^ 1], h->have_hist);
   hipLaunchKernelGGL((k3_mom<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
-                     (const S*)s.pops[c ^ 1],
-                     (const double*)s.pp[c], s.pp[c ^ 1]);
+                     (const S*)s.pops[c ^ 1], (const double*)s.pp[c], s.pp[c ^ 1]);
   return hipGetLastError();
 }
 
