@@ -149,6 +149,29 @@ __device__ __forceinline__ double wall_jpsi(const P3& p, double ph, double ps) {
 
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
+// Node index offsets of the layers, rows and columns one step away from (x, y,
+// z) along each axis (index 0: -1, 1: 0, 2: +1), periodic wraps included (in z
+// as well: where z has walls the caller decides first whether a neighbour
+// lies beyond one).  The neighbour along direction i is at3(o, i).
+struct Off3 {
+  int x[3], y[3], z[3];
+};
+__device__ __forceinline__ Off3 offsets3(const P3& p, int x, int y, int z) {
+  const int nxy = p.nx * p.ny;
+  Off3 o;
+  o.x[0] = x == 0 ? p.nx - 1 : x - 1;
+  o.x[1] = x;
+  o.x[2] = x + 1 == p.nx ? 0 : x + 1;
+  o.y[0] = (y == 0 ? p.ny - 1 : y - 1) * p.nx;
+  o.y[1] = y * p.nx;
+  o.y[2] = (y + 1 == p.ny ? 0 : y + 1) * p.nx;
+  o.z[0] = (z == 0 ? p.nz - 1 : z - 1) * nxy;
+  o.z[1] = z * nxy;
+  o.z[2] = (z + 1 == p.nz ? 0 : z + 1) * nxy;
+  return o;
+}
+__device__ __forceinline__ int at3(const Off3& o, int i) { return o.z[cz3(i) + 1] + o.y[cy3(i) + 1] + o.x[cx3(i) + 1]; }
+
 // Neighbour of (x, y, z) along direction i: node index, or -1 / -2 beyond the
 // bottom / top wall; *colnode is the node of the same (x, y) column in the
 // layer of (x, y, z).
@@ -184,8 +207,15 @@ __device__ __forceinline__ bool plain_stencil(const P3& p, int z) {
   return !p.has_solid && (p.periodic_z || (z > 0 && z < p.nz - 1));
 }
 
-template <class S>
-__device__ __forceinline__ double ld(const S* a, size_t k) { return (double)a[k]; }
+
+// Element k of plane pl of an array of planes of N values, addressed as a
+// wave-uniform plane base plus a 32-bit per-lane byte offset (the node count
+// stays below 2^29, so the offset of an FP64 value fits): the base stays in
+// scalar registers and no 64-bit address is formed per lane.
+template <class T>
+__device__ __forceinline__ T& el(T* a, int pl, int N, int k) {
+  return *(T*)((char*)(a + (size_t)pl * N) + (unsigned)k * (unsigned)sizeof(T));
+}
 
 // Deterministic FP64 block sum of kT threads (valid in thread 0).
 __device__ double block_sum(double v, double* sh) {
@@ -213,19 +243,20 @@ __global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const un
   double s1 = 0, s2 = 0, s3 = 0, s4 = 0;
   for (int n = blockIdx.x * kT + threadIdx.x; n < N; n += gridDim.x * kT) {
     if (p.has_solid && solid[n]) {
-      mu[n] = mu[N + n] = 0.0;
+      el(mu, 0, N, n) = el(mu, 1, N, n) = 0.0;
       continue;
     }
     const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
-    const double ph = pp[n], ps = pp[N + n];
+    const double ph = el(pp, 0, N, n), ps = el(pp, 1, N, n);
     double l0p = 0.0, l0s = 0.0, tp = 0.0, ts = 0.0;
     if (plain_stencil(p, z)) {   // interior: plain stencil, unrolled
+      const Off3 o = offsets3(p, x, y, z);
 #pragma unroll
       for (int i = 1; i < Q3; ++i) {
-        const int m = (wrap(z + cz3(i), p.nz) * p.ny + wrap(y + cy3(i), p.ny)) * p.nx + wrap(x + cx3(i), p.nx);
+        const int m = at3(o, i);
         const double wt = 2.0 * w3(i) / kCs2;
-        l0p += wt * (pp[m] - ph);
-        l0s += wt * (pp[N + m] - ps);
+        l0p += wt * (el(pp, 0, N, m) - ph);
+        l0s += wt * (el(pp, 1, N, m) - ps);
       }
     } else {   // next to a wall or a solid node: the general stencil, same order, rolled
       const double jp_self = p.solid_wet ? wall_jphi(p, ph, ps) : 0.0;
@@ -236,18 +267,18 @@ __global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const un
         const int m = nbr_c(p, solid, x, y, z, kC3[i][0], kC3[i][1], kC3[i][2], &cn);
         const double wt = 2.0 * kW3[i] / kCs2;
         if (m >= 0) {
-          l0p += wt * (pp[m] - ph);
-          l0s += wt * (pp[N + m] - ps);
+          l0p += wt * (el(pp, 0, N, m) - ph);
+          l0s += wt * (el(pp, 1, N, m) - ps);
         } else if (m == -3) {   // solid node: link-wise mirror, wall flux of this node
           if (p.solid_wet) {
             tp += wt * jp_self;
             ts += wt * js_self;
           }
         } else {
-          l0p += wt * (pp[cn] - ph);
-          l0s += wt * (pp[N + cn] - ps);
+          l0p += wt * (el(pp, 0, N, cn) - ph);
+          l0s += wt * (el(pp, 1, N, cn) - ps);
           if ((m == -1 && p.wet_b) || (m == -2 && p.wet_t)) {
-            const double fph = pp[cn], fps = pp[N + cn];
+            const double fph = el(pp, 0, N, cn), fps = el(pp, 1, N, cn);
             tp += wt * wall_jphi(p, fph, fps);
             ts += wt * wall_jpsi(p, fph, fps);
           }
@@ -258,8 +289,8 @@ __global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const un
     const double mpsi = p.surf ? p.kBT * log(ps / (1.0 - ps)) - p.lambda_s * l0s - ts
                                      - p.beta * (1.0 - ph * ph) * (1.0 - ph * ph) + 0.5 * p.W * ph * ph
                                : 0.0;
-    mu[n] = mphi;
-    mu[N + n] = mpsi;
+    el(mu, 0, N, n) = mphi;
+    el(mu, 1, N, n) = mpsi;
     const double hp = hprime(p, ph);
     s1 += hp * mphi;
     s2 += hp * hp;
@@ -482,18 +513,19 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
   Macro3 M;
   const int N = p.N;
   const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
-  M.ph = pp[n];
-  M.ps = pp[N + n];
+  M.ph = el(pp, 0, N, n);
+  M.ps = el(pp, 1, N, n);
   M.rho = rho_of(p, M.ph);
   double gr[3] = {0, 0, 0}, gmp[3] = {0, 0, 0}, gms[3] = {0, 0, 0}, tp = 0.0, ts = 0.0, l0s = 0.0;
   // Interior nodes take the plain stencil, unrolled; nodes next to a wall or a
   // solid node take the general one (the same arithmetic per direction, in the
   // same order), in a loop kept rolled so the kernel's code stays small.
   if (plain_stencil(p, z)) {
+    const Off3 o = offsets3(p, x, y, z);
 #pragma unroll
     for (int i = 1; i < Q3; ++i) {
-      const int m = (wrap(z + cz3(i), p.nz) * p.ny + wrap(y + cy3(i), p.ny)) * p.nx + wrap(x + cx3(i), p.nx);
-      const double r = rho_of(p, pp[m]), mp = mu[m], ms = mu[N + m], pn = pp[N + m];
+      const int m = at3(o, i);
+      const double r = rho_of(p, el(pp, 0, N, m)), mp = el(mu, 0, N, m), ms = el(mu, 1, N, m), pn = el(pp, 1, N, m);
       const int c[3] = {cx3(i), cy3(i), cz3(i)};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -517,14 +549,14 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
       const int m = nbr_c(p, solid, x, y, z, cx, cy, cz, &cn);
       double r, mp, ms, pn;
       if (m >= 0) {
-        r = rho_of(p, pp[m]);
-        mp = mu[m];
-        ms = mu[N + m];
-        pn = pp[N + m];
+        r = rho_of(p, el(pp, 0, N, m));
+        mp = el(mu, 0, N, m);
+        ms = el(mu, 1, N, m);
+        pn = el(pp, 1, N, m);
       } else if (m == -3) {   // solid node: ghost values of this node
         r = rho_of(p, M.ph + jp_self / p.kappa);
-        mp = mu[n];
-        ms = mu[N + n];
+        mp = el(mu, 0, N, n);
+        ms = el(mu, 1, N, n);
         pn = M.ps;
         if (p.solid_wet) {
           tp += 2.0 * wi / kCs2 * jp_self;
@@ -532,11 +564,11 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
         }
       } else {
         const bool wet = (m == -1 && p.wet_b) || (m == -2 && p.wet_t);
-        const double fph = pp[cn], fps = pp[N + cn];
+        const double fph = el(pp, 0, N, cn), fps = el(pp, 1, N, cn);
         const double jp = wet ? wall_jphi(p, fph, fps) : 0.0;
         r = rho_of(p, fph + jp / p.kappa);
-        mp = mu[cn];
-        ms = mu[N + cn];
+        mp = el(mu, 0, N, cn);
+        ms = el(mu, 1, N, cn);
         pn = fps;
         if (wet) {
           tp += 2.0 * wi / kCs2 * jp;
@@ -557,7 +589,7 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
   double j[3] = {0, 0, 0}, snz = 0.0;
 #pragma unroll
   for (int i = 0; i < Q3; ++i) {
-    const double fi = ld(pop, (size_t)i * N + n);
+    const double fi = (double)el(pop, i, N, n);
     j[0] += cx3(i) * fi;
     j[1] += cy3(i) * fi;
     j[2] += cz3(i) * fi;
@@ -610,13 +642,13 @@ __global__ __launch_bounds__(kT, kColfWaves<S>) void k3_colf(
   // advecting velocity (the step's own u, or its mean with the previous step's)
   double v[3] = {M.u[0], M.u[1], M.u[2]};
   if (have_hist && !p.adv_raw)
-    for (int d = 0; d < 3; ++d) v[d] = 0.5 * (M.u[d] + (double)hin[(size_t)d * N + n]);
+    for (int d = 0; d < 3; ++d) v[d] = 0.5 * (M.u[d] + (double)el(hin, d, N, n));
   for (int d = 0; d < 3; ++d) {
-    hout[(size_t)d * N + n] = (S)M.u[d];
-    hout[(size_t)(3 + d) * N + n] = (S)v[d];
+    el(hout, d, N, n) = (S)M.u[d];
+    el(hout, (3 + d), N, n) = (S)v[d];
   }
-  hout[(size_t)6 * N + n] = (S)Rphi;
-  hout[(size_t)7 * N + n] = (S)Rpsi;
+  el(hout, 6, N, n) = (S)Rphi;
+  el(hout, 7, N, n) = (S)Rpsi;
 
   const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
   using T = S;   // collision arithmetic: the storage type (FP32 or FP64)
@@ -632,29 +664,34 @@ __global__ __launch_bounds__(kT, kColfWaves<S>) void k3_colf(
 #pragma unroll
     for (int k = 0; k < Q3; ++k) mf[k] = T(0);
 #pragma unroll
-    for (int i = 0; i < Q3; ++i) raw3<T>(i, (T)ld(pin, (size_t)i * N + n), mf);   // pressure-based: of the order of p w_i / c_s^2
+    for (int i = 0; i < Q3; ++i) raw3<T>(i, (T)el(pin, i, N, n), mf);   // pressure-based: of the order of p w_i / c_s^2
     double meq[Q3], mv[Q3];
     flow_moments3(M.pr, rho, M.u, M.gr, M.F, meq, mv);
     relax3<T>(rates, mf, meq, mv, m);
     populations3<T>(m, f);
     // push streaming; walls in z
+    const Off3 o = offsets3(p, x, y, z);
+    if (!p.has_solid && (p.periodic_z || (z > 0 && z < p.nz - 1))) {   // every target is a fluid node
+#pragma unroll
+      for (int i = 0; i < Q3; ++i) el(pout, i, N, at3(o, i)) = f[i];
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
       const double fo = (double)f[i];
       const int zz = z + cz3(i);
-      const int xx = wrap(x + cx3(i), p.nx), yy = wrap(y + cy3(i), p.ny);
-      const int t = (wrap(zz, p.nz) * p.ny + yy) * p.nx + xx;
+      const int t = at3(o, i);
       if ((p.periodic_z || (zz >= 0 && zz < p.nz)) && p.has_solid && solid[t]) {
-        pout[(size_t)opp3(i) * N + n] = (S)fo;   // half-way bounce-back at a solid node at rest
+        el(pout, opp3(i), N, n) = (S)fo;   // half-way bounce-back at a solid node at rest
       } else if (p.periodic_z || (zz >= 0 && zz < p.nz)) {
-        pout[(size_t)i * N + t] = (S)fo;
+        el(pout, i, N, t) = (S)fo;
       } else {
         const bool bot = zz < 0;
         if (bot ? p.freeslip_b : p.freeslip_t) {
-          pout[(size_t)mirz3(i) * N + (z * p.ny + yy) * p.nx + xx] = (S)fo;
+          el(pout, mirz3(i), N, o.z[1] + o.y[cy3(i) + 1] + o.x[cx3(i) + 1]) = (S)fo;
         } else {
           const double uw = bot ? p.uw_b : p.uw_t;
-          pout[(size_t)opp3(i) * N + n] = (S)(fo - 2.0 * w3(i) * rho * (cx3(i) * uw) / kCs2);
+          el(pout, opp3(i), N, n) = (S)(fo - (2.0 * w3(i) / kCs2) * rho * (cx3(i) * uw));
         }
       }
     }
@@ -723,7 +760,7 @@ __global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const
     for (int i = 0; i < Q3; ++i) {
       // rest population shifted by c (the collision maps g - c e_0 to its image
       // minus c e_0), so the collision sees increments only
-      const double fi = ld(pin, (size_t)(base + i) * N + n) + (i == 0 ? cref - c : 0.0);
+      const double fi = (double)pin[(size_t)(base + i) * N + n] + (i == 0 ? cref - c : 0.0);
       raw3<T>(i, (T)fi, mf);
     }
     double meq[Q3], mv[Q3];
@@ -758,11 +795,11 @@ __global__ __launch_bounds__(kT) void k3_mom(const P3* __restrict__ pp_, const u
   double a = 0.0, b = 0.0;
 #pragma unroll
   for (int i = 1; i < Q3; ++i) {
-    a += ld(pop, (size_t)(19 + i) * N + n);
-    b += ld(pop, (size_t)(38 + i) * N + n);
+    a += (double)el(pop, (19 + i), N, n);
+    b += (double)el(pop, (38 + i), N, n);
   }
-  pnew[n] = pold[n] + ld(pop, (size_t)19 * N + n) + a;
-  pnew[N + n] = p.surf ? pold[N + n] + ld(pop, (size_t)38 * N + n) + b : 0.0;
+  el(pnew, 0, N, n) = el(pold, 0, N, n) + (double)el(pop, 19, N, n) + a;
+  el(pnew, 1, N, n) = p.surf ? el(pold, 1, N, n) + (double)el(pop, 38, N, n) + b : 0.0;
 }
 
 // ------------------------------------------------------- initial state, load
@@ -831,7 +868,7 @@ __global__ __launch_bounds__(kT) void k3_fields(const P3* __restrict__ pp_, cons
     return;
   }
   const Macro3 M = macro3(p, solid, pop, pp, mu, n);
-  const double v[9] = {M.ph, M.ps, M.u[0], M.u[1], M.u[2], M.pr, M.rho, mu[n], mu[N + n]};
+  const double v[9] = {M.ph, M.ps, M.u[0], M.u[1], M.u[2], M.pr, M.rho, el(mu, 0, N, n), el(mu, 1, N, n)};
 #pragma unroll
   for (int k = 0; k < 9; ++k) stage[(size_t)k * N + n] = v[k];
 }
@@ -923,7 +960,7 @@ int fail3(lbm3d_handle* h, int code, const std::string& msg) {
 std::string derive3(const lbm3d_params& q, P3& d) {
   if (q.abi_version != LBM3D_ABI_VERSION) return "abi_version mismatch";
   if (q.nx < 3 || q.ny < 3 || q.nz < 3) return "nx, ny and nz must be >= 3";
-  if ((double)q.nx * q.ny * q.nz * 57.0 > 9.0e18 || (double)q.nx * q.ny * q.nz >= 2147483647.0) return "grid too large";
+  if ((double)q.nx * q.ny * q.nz * 57.0 > 9.0e18 || (double)q.nx * q.ny * q.nz >= 536870912.0) return "grid too large (at most 2^29 nodes)";
   auto bc_ok = [](int b) { return b >= LBM_BC_PERIODIC && b <= LBM_BC_FREESLIP; };
   if (!bc_ok(q.bc_bottom) || !bc_ok(q.bc_top)) return "unknown boundary kind";
   if ((q.bc_bottom == LBM_BC_PERIODIC) != (q.bc_top == LBM_BC_PERIODIC)) return "periodic z needs both walls periodic";
