@@ -83,13 +83,15 @@ int lbm3d_required_bytes(const lbm3d_params* p, size_t* bytes);
  * the initial fields (the tanh profile of Sec. 2.2 around a sphere, a slab or
  * a spherical bubble; u = 0, p = 0; equilibrium populations).  dev_buf: NULL
  * or caller-owned device memory of lbm3d_required_bytes, 256-byte aligned
- * (never freed here); hip_stream: NULL for a library stream. */
+ * (never freed here); hip_stream: NULL for a library stream.  LBM_E_ARG for
+ * invalid parameters and for grids of 2^29 nodes or more. */
 int lbm3d_init(const lbm3d_params* p, void* dev_buf, size_t buf_bytes, void* hip_stream, lbm3d_handle** out);
 
-/* Enqueue n >= 0 time steps of Sec. 3 (four kernels each: chemical potentials
+/* Enqueue n >= 0 time steps of Sec. 3 (five kernels each: chemical potentials
  * with the multiplier sums; the multipliers; force, velocity, pressure,
- * sources, the three MRT collisions and push streaming with the walls; the
- * zeroth moments of the new state).  Asynchronous. */
+ * sources, the flow lattice's MRT collision and push streaming with the walls;
+ * the phase-field and surfactant collisions and streaming; the zeroth moments
+ * of the new state).  Asynchronous. */
 int lbm3d_step(lbm3d_handle* h, int64_t n);
 
 /* Conserved sums (sum psi of AC_psi, sum h_phi of eq15, sum phi), kinetic
