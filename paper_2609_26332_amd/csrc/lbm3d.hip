@@ -217,6 +217,14 @@ __device__ __forceinline__ T& el(T* a, int pl, int N, int k) {
   return *(T*)((char*)(a + (size_t)pl * N) + (unsigned)k * (unsigned)sizeof(T));
 }
 
+// (phi, psi) or (mu_phi, mu_psi) of node k: each pair of fields is stored
+// interleaved, so a node's pair is one 16-byte access (a wave-uniform base
+// plus a 32-bit per-lane offset, as el).
+__device__ __forceinline__ double2& pr(double2* a, int k) { return *(double2*)((char*)a + (unsigned)k * 16u); }
+__device__ __forceinline__ const double2& pr(const double2* a, int k) {
+  return *(const double2*)((const char*)a + (unsigned)k * 16u);
+}
+
 // Deterministic FP64 block sum of kT threads (valid in thread 0).
 __device__ double block_sum(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -235,7 +243,7 @@ __device__ double block_sum(double v, double* sh) {
 // with L0 the Laplacian with mirror ghosts and T the wall term of each
 // direction pointing into a wetting wall: (2 w_i / c_s^2) J(column).
 __global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
-                                            const double* __restrict__ pp, double* __restrict__ mu,
+                                            const double2* __restrict__ pp, double2* __restrict__ mu,
                                             double* __restrict__ part) {
   const P3& p = *pp_;
   __shared__ double sh[4][kT / 64];
@@ -243,11 +251,11 @@ __global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const un
   double s1 = 0, s2 = 0, s3 = 0, s4 = 0;
   for (int n = blockIdx.x * kT + threadIdx.x; n < N; n += gridDim.x * kT) {
     if (p.has_solid && solid[n]) {
-      el(mu, 0, N, n) = el(mu, 1, N, n) = 0.0;
+      pr(mu, n) = make_double2(0.0, 0.0);
       continue;
     }
     const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
-    const double ph = el(pp, 0, N, n), ps = el(pp, 1, N, n);
+    const double ph = pr(pp, n).x, ps = pr(pp, n).y;
     double l0p = 0.0, l0s = 0.0, tp = 0.0, ts = 0.0;
     if (plain_stencil(p, z)) {   // interior: plain stencil, unrolled
       const Off3 o = offsets3(p, x, y, z);
@@ -255,8 +263,8 @@ __global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const un
       for (int i = 1; i < Q3; ++i) {
         const int m = at3(o, i);
         const double wt = 2.0 * w3(i) / kCs2;
-        l0p += wt * (el(pp, 0, N, m) - ph);
-        l0s += wt * (el(pp, 1, N, m) - ps);
+        l0p += wt * (pr(pp, m).x - ph);
+        l0s += wt * (pr(pp, m).y - ps);
       }
     } else {   // next to a wall or a solid node: the general stencil, same order, rolled
       const double jp_self = p.solid_wet ? wall_jphi(p, ph, ps) : 0.0;
@@ -267,18 +275,18 @@ __global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const un
         const int m = nbr_c(p, solid, x, y, z, kC3[i][0], kC3[i][1], kC3[i][2], &cn);
         const double wt = 2.0 * kW3[i] / kCs2;
         if (m >= 0) {
-          l0p += wt * (el(pp, 0, N, m) - ph);
-          l0s += wt * (el(pp, 1, N, m) - ps);
+          l0p += wt * (pr(pp, m).x - ph);
+          l0s += wt * (pr(pp, m).y - ps);
         } else if (m == -3) {   // solid node: link-wise mirror, wall flux of this node
           if (p.solid_wet) {
             tp += wt * jp_self;
             ts += wt * js_self;
           }
         } else {
-          l0p += wt * (el(pp, 0, N, cn) - ph);
-          l0s += wt * (el(pp, 1, N, cn) - ps);
+          l0p += wt * (pr(pp, cn).x - ph);
+          l0s += wt * (pr(pp, cn).y - ps);
           if ((m == -1 && p.wet_b) || (m == -2 && p.wet_t)) {
-            const double fph = el(pp, 0, N, cn), fps = el(pp, 1, N, cn);
+            const double fph = pr(pp, cn).x, fps = pr(pp, cn).y;
             tp += wt * wall_jphi(p, fph, fps);
             ts += wt * wall_jpsi(p, fph, fps);
           }
@@ -289,8 +297,7 @@ __global__ __launch_bounds__(kT) void k3_mu(const P3* __restrict__ pp_, const un
     const double mpsi = p.surf ? p.kBT * log(ps / (1.0 - ps)) - p.lambda_s * l0s - ts
                                      - p.beta * (1.0 - ph * ph) * (1.0 - ph * ph) + 0.5 * p.W * ph * ph
                                : 0.0;
-    el(mu, 0, N, n) = mphi;
-    el(mu, 1, N, n) = mpsi;
+    pr(mu, n) = make_double2(mphi, mpsi);
     const double hp = hprime(p, ph);
     s1 += hp * mphi;
     s2 += hp * hp;
@@ -509,12 +516,12 @@ struct Macro3 {
 };
 template <class S>
 __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, const S* __restrict__ pop,
-                         const double* __restrict__ pp, const double* __restrict__ mu, int n) {
+                         const double2* __restrict__ pp, const double2* __restrict__ mu, int n) {
   Macro3 M;
   const int N = p.N;
   const int x = n % p.nx, y = (n / p.nx) % p.ny, z = n / (p.nx * p.ny);
-  M.ph = el(pp, 0, N, n);
-  M.ps = el(pp, 1, N, n);
+  M.ph = pr(pp, n).x;
+  M.ps = pr(pp, n).y;
   M.rho = rho_of(p, M.ph);
   double gr[3] = {0, 0, 0}, gmp[3] = {0, 0, 0}, gms[3] = {0, 0, 0}, tp = 0.0, ts = 0.0, l0s = 0.0;
   // Interior nodes take the plain stencil, unrolled; nodes next to a wall or a
@@ -525,7 +532,7 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
 #pragma unroll
     for (int i = 1; i < Q3; ++i) {
       const int m = at3(o, i);
-      const double r = rho_of(p, el(pp, 0, N, m)), mp = el(mu, 0, N, m), ms = el(mu, 1, N, m), pn = el(pp, 1, N, m);
+      const double r = rho_of(p, pr(pp, m).x), mp = pr(mu, m).x, ms = pr(mu, m).y, pn = pr(pp, m).y;
       const int c[3] = {cx3(i), cy3(i), cz3(i)};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -549,14 +556,14 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
       const int m = nbr_c(p, solid, x, y, z, cx, cy, cz, &cn);
       double r, mp, ms, pn;
       if (m >= 0) {
-        r = rho_of(p, el(pp, 0, N, m));
-        mp = el(mu, 0, N, m);
-        ms = el(mu, 1, N, m);
-        pn = el(pp, 1, N, m);
+        r = rho_of(p, pr(pp, m).x);
+        mp = pr(mu, m).x;
+        ms = pr(mu, m).y;
+        pn = pr(pp, m).y;
       } else if (m == -3) {   // solid node: ghost values of this node
         r = rho_of(p, M.ph + jp_self / p.kappa);
-        mp = el(mu, 0, N, n);
-        ms = el(mu, 1, N, n);
+        mp = pr(mu, n).x;
+        ms = pr(mu, n).y;
         pn = M.ps;
         if (p.solid_wet) {
           tp += 2.0 * wi / kCs2 * jp_self;
@@ -564,11 +571,11 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
         }
       } else {
         const bool wet = (m == -1 && p.wet_b) || (m == -2 && p.wet_t);
-        const double fph = el(pp, 0, N, cn), fps = el(pp, 1, N, cn);
+        const double fph = pr(pp, cn).x, fps = pr(pp, cn).y;
         const double jp = wet ? wall_jphi(p, fph, fps) : 0.0;
         r = rho_of(p, fph + jp / p.kappa);
-        mp = el(mu, 0, N, cn);
-        ms = el(mu, 1, N, cn);
+        mp = pr(mu, cn).x;
+        ms = pr(mu, cn).y;
         pn = fps;
         if (wet) {
           tp += 2.0 * wi / kCs2 * jp;
@@ -621,7 +628,7 @@ constexpr int kColfWaves = sizeof(S) == 8 ? 2 : 4;
 template <class S>
 __global__ __launch_bounds__(kT, kColfWaves<S>) void k3_colf(
     const P3* __restrict__ pp_, const unsigned char* __restrict__ solid, const S* __restrict__ pin, S* __restrict__ pout,
-    const double* __restrict__ pp, const double* __restrict__ mu, const S* __restrict__ hin, S* __restrict__ hout,
+    const double2* __restrict__ pp, const double2* __restrict__ mu, const S* __restrict__ hin, S* __restrict__ hout,
     const Scal3* __restrict__ sc, int have_hist) {
   const P3& p = *pp_;
   const int N = p.N;
@@ -706,7 +713,7 @@ __global__ __launch_bounds__(kT, kColfWaves<S>) void k3_colf(
 template <class S>
 __global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
                                                const S* __restrict__ pin, S* __restrict__ pout,
-                                               const double* __restrict__ pp, const double* __restrict__ pprev,
+                                               const double2* __restrict__ pp, const double2* __restrict__ pprev,
                                                const S* __restrict__ hcur, const S* __restrict__ hprev,
                                                int have_hist) {
   const P3& p = *pp_;
@@ -714,12 +721,14 @@ __global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const
   const int n = blockIdx.x * kT + threadIdx.x;
   if (n >= N) return;
   if (p.has_solid && solid[n]) return;
-  const double ph = pp[n], ps = pp[N + n];
+  const double2 c2 = pr(pp, n);
+  const double ph = c2.x, ps = c2.y;
   const double v[3] = {(double)hcur[(size_t)3 * N + n], (double)hcur[(size_t)4 * N + n], (double)hcur[(size_t)5 * N + n]};
   const double Rphi = (double)hcur[(size_t)6 * N + n], Rpsi = (double)hcur[(size_t)7 * N + n];
   double dph[3] = {0, 0, 0}, dps[3] = {0, 0, 0}, dRp = 0.0, dRs = 0.0;
   if (have_hist) {
-    const double php = pprev[n], psp = pprev[N + n];
+    const double2 q2 = pr(pprev, n);
+    const double php = q2.x, psp = q2.y;
     for (int d = 0; d < 3; ++d) {
       const double vh = (double)hprev[(size_t)(3 + d) * N + n];
       dph[d] = ph * v[d] - php * vh;
@@ -752,7 +761,7 @@ __global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const
     for (int k = 0; k < 5; ++k) r5[k] = (T)(lat == 1 ? p.sg[k] : p.sh[k]);
     const double extra = lat == 1 ? Rphi + 0.5 * dRp : Rpsi + 0.5 * dRs;
     const int base = 19 * lat;
-    const double cref = lat == 1 ? pprev[n] : pprev[N + n];   // the shift of the stored rest population
+    const double cref = lat == 1 ? pr(pprev, n).x : pr(pprev, n).y;   // the shift of the stored rest population
     T mf[Q3];
 #pragma unroll
     for (int k = 0; k < Q3; ++k) mf[k] = T(0);
@@ -786,7 +795,7 @@ __global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const
 template <class S>
 __global__ __launch_bounds__(kT) void k3_mom(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
                                              const S* __restrict__ pop,
-                                             const double* __restrict__ pold, double* __restrict__ pnew) {
+                                             const double2* __restrict__ pold, double2* __restrict__ pnew) {
   const P3& p = *pp_;
   const int N = p.N;
   const int n = blockIdx.x * kT + threadIdx.x;
@@ -798,8 +807,8 @@ __global__ __launch_bounds__(kT) void k3_mom(const P3* __restrict__ pp_, const u
     a += (double)el(pop, (19 + i), N, n);
     b += (double)el(pop, (38 + i), N, n);
   }
-  el(pnew, 0, N, n) = el(pold, 0, N, n) + (double)el(pop, 19, N, n) + a;
-  el(pnew, 1, N, n) = p.surf ? el(pold, 1, N, n) + (double)el(pop, 38, N, n) + b : 0.0;
+  const double2 o = pr(pold, n);
+  pr(pnew, n) = make_double2(o.x + (double)el(pop, 19, N, n) + a, p.surf ? o.y + (double)el(pop, 38, N, n) + b : 0.0);
 }
 
 // ------------------------------------------------------- initial state, load
@@ -823,7 +832,7 @@ __global__ __launch_bounds__(kT) void k3_profile(const P3* __restrict__ pp_, dou
 template <class S>
 __global__ __launch_bounds__(kT) void k3_load(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
                                               const double* __restrict__ stage, int with_u, S* __restrict__ pop,
-                                              S* __restrict__ pop2, double* __restrict__ pa, double* __restrict__ pb) {
+                                              S* __restrict__ pop2, double2* __restrict__ pa, double2* __restrict__ pb) {
   const P3& p = *pp_;
   const int N = p.N;
   const int n = blockIdx.x * kT + threadIdx.x;
@@ -831,7 +840,7 @@ __global__ __launch_bounds__(kT) void k3_load(const P3* __restrict__ pp_, const 
   if (p.has_solid && solid[n]) {   // no fluid: zero populations in both buffers, zero fields
 #pragma unroll
     for (int i = 0; i < 57; ++i) pop[(size_t)i * N + n] = pop2[(size_t)i * N + n] = (S)0.0;
-    pa[n] = pb[n] = pa[N + n] = pb[N + n] = 0.0;
+    pr(pa, n) = pr(pb, n) = make_double2(0.0, 0.0);
     return;
   }
   const double ph = stage[n], ps = p.surf ? stage[N + n] : 0.0;
@@ -848,16 +857,15 @@ __global__ __launch_bounds__(kT) void k3_load(const P3* __restrict__ pp_, const 
     pop[(size_t)(19 + i) * N + n] = (S)(i == 0 ? ge - ph : ge);
     pop[(size_t)(38 + i) * N + n] = (S)(p.surf ? (i == 0 ? he - ps : he) : 0.0);
   }
-  pa[n] = pb[n] = ph;
-  pa[N + n] = pb[N + n] = ps;
+  pr(pa, n) = pr(pb, n) = make_double2(ph, ps);
 }
 
 // Fields of the current state into the staging planes:
 // phi, psi, ux, uy, uz, p, rho, mu_phi, mu_psi.
 template <class S>
 __global__ __launch_bounds__(kT) void k3_fields(const P3* __restrict__ pp_, const unsigned char* __restrict__ solid,
-                                                const S* __restrict__ pop, const double* __restrict__ pp,
-                                                const double* __restrict__ mu, double* __restrict__ stage) {
+                                                const S* __restrict__ pop, const double2* __restrict__ pp,
+                                                const double2* __restrict__ mu, double* __restrict__ stage) {
   const P3& p = *pp_;
   const int N = p.N;
   const int n = blockIdx.x * kT + threadIdx.x;
@@ -868,7 +876,7 @@ __global__ __launch_bounds__(kT) void k3_fields(const P3* __restrict__ pp_, cons
     return;
   }
   const Macro3 M = macro3(p, solid, pop, pp, mu, n);
-  const double v[9] = {M.ph, M.ps, M.u[0], M.u[1], M.u[2], M.pr, M.rho, el(mu, 0, N, n), el(mu, 1, N, n)};
+  const double v[9] = {M.ph, M.ps, M.u[0], M.u[1], M.u[2], M.pr, M.rho, pr(mu, n).x, pr(mu, n).y};
 #pragma unroll
   for (int k = 0; k < 9; ++k) stage[(size_t)k * N + n] = v[k];
 }
@@ -1062,17 +1070,17 @@ hipError_t step3(lbm3d_handle* h) {
   St3& s = h->s;
   const int c = h->cur;
   const int rb = red_blocks(p.N);
-  hipLaunchKernelGGL(k3_mu, dim3(rb), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid, (const double*)s.pp[c],
-                     s.mu, s.part);
+  hipLaunchKernelGGL(k3_mu, dim3(rb), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid, (const double2*)s.pp[c],
+                     (double2*)s.mu, s.part);
   hipLaunchKernelGGL(k3_fin, dim3(1), dim3(64), 0, h->stream, s.dp, (const double*)s.part, rb, s.sc);
   hipLaunchKernelGGL((k3_colf<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
-                     (const S*)s.pops[c], (S*)s.pops[c ^ 1], (const double*)s.pp[c], (const double*)s.mu,
+                     (const S*)s.pops[c], (S*)s.pops[c ^ 1], (const double2*)s.pp[c], (const double2*)s.mu,
                      (const S*)s.uh[c ^ 1], (S*)s.uh[c], (const Scal3*)s.sc, h->have_hist);
   hipLaunchKernelGGL((k3_colgh<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
-                     (const S*)s.pops[c], (S*)s.pops[c ^ 1], (const double*)s.pp[c], (const double*)s.pp[c ^ 1],
+                     (const S*)s.pops[c], (S*)s.pops[c ^ 1], (const double2*)s.pp[c], (const double2*)s.pp[c ^ 1],
                      (const S*)s.uh[c], (const S*)s.uh[c ^ 1], h->have_hist);
   hipLaunchKernelGGL((k3_mom<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
-                     (const S*)s.pops[c ^ 1], (const double*)s.pp[c], s.pp[c ^ 1]);
+                     (const S*)s.pops[c ^ 1], (const double2*)s.pp[c], (double2*)s.pp[c ^ 1]);
   return hipGetLastError();
 }
 
@@ -1083,12 +1091,12 @@ hipError_t fields3(lbm3d_handle* h) {
   St3& s = h->s;
   const int c = h->cur;
   const int rb = red_blocks(p.N);
-  hipLaunchKernelGGL(k3_mu, dim3(rb), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid, (const double*)s.pp[c],
-                     s.mu, s.part);
+  hipLaunchKernelGGL(k3_mu, dim3(rb), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid, (const double2*)s.pp[c],
+                     (double2*)s.mu, s.part);
   hipLaunchKernelGGL(k3_fin, dim3(1), dim3(64), 0, h->stream, s.dp, (const double*)s.part, rb, s.sc);
   hipLaunchKernelGGL((k3_fields<S>), dim3(nblk(p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
                      (const S*)s.pops[c],
-                     (const double*)s.pp[c], (const double*)s.mu, s.stage);
+                     (const double2*)s.pp[c], (const double2*)s.mu, s.stage);
   return hipGetLastError();
 }
 
@@ -1097,10 +1105,10 @@ hipError_t load3(lbm3d_handle* h, int with_u) {
   const int c = h->cur;
   if (h->prm.precision == LBM_FP64)
     hipLaunchKernelGGL((k3_load<double>), dim3(nblk(h->p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
-                       (const double*)s.stage, with_u, (double*)s.pops[c], (double*)s.pops[c ^ 1], s.pp[c], s.pp[c ^ 1]);
+                       (const double*)s.stage, with_u, (double*)s.pops[c], (double*)s.pops[c ^ 1], (double2*)s.pp[c], (double2*)s.pp[c ^ 1]);
   else
     hipLaunchKernelGGL((k3_load<float>), dim3(nblk(h->p.N)), dim3(kT), 0, h->stream, s.dp, (const unsigned char*)s.solid,
-                       (const double*)s.stage, with_u, (float*)s.pops[c], (float*)s.pops[c ^ 1], s.pp[c], s.pp[c ^ 1]);
+                       (const double*)s.stage, with_u, (float*)s.pops[c], (float*)s.pops[c ^ 1], (double2*)s.pp[c], (double2*)s.pp[c ^ 1]);
   return hipGetLastError();
 }
 
