@@ -385,8 +385,8 @@ __device__ __forceinline__ void raw3(int i, T f, T* m) {
 // Order of raw moment k (the index of its relaxation rate).
 __host__ __device__ constexpr int order3(int k) { return k == 0 ? 0 : (k < 4 ? 1 : (k < 10 ? 2 : (k < 16 ? 3 : 4))); }
 // Post-collision moments (I - S) m + S meq + (I - S/2) mv, S diagonal by order.
-template <class T>
-__device__ __forceinline__ void relax3(const T* rate5, const T* mf, const double* meq, const double* mv, T* m) {
+template <class T, class E>
+__device__ __forceinline__ void relax3(const T* rate5, const T* mf, const E* meq, const E* mv, T* m) {
 #pragma unroll
   for (int k = 0; k < Q3; ++k) {
     const T s = rate5[order3(k)];
@@ -401,11 +401,13 @@ __device__ __forceinline__ void relax3(const T* rate5, const T* mf, const double
 // (w_i - delta_i0) + rho w_i s_i(u)) and of its forcing vector
 // w_i [u.grad rho + c_i.F/c_s^2 + ((c_i.u)(c_i.grad rho) - c_s^2 u.grad rho)/c_s^2]
 // follow in closed form: no per-direction equilibrium is formed.
-__device__ __forceinline__ void flow_moments3(double pr, double rho, const double* u, const double* G, const double* F,
-                                              double* meq, double* mv) {
-  const double ux = u[0], uy = u[1], uz = u[2];
-  const double xx = ux * ux, yy = uy * uy, zz = uz * uz;
-  meq[0] = 0.0;
+template <class T>
+__device__ __forceinline__ void flow_moments3(double pr_, double rho_, const double* u, const double* G_, const double* F_,
+                                              T* meq, T* mv) {
+  const T pr = (T)pr_, rho = (T)rho_, ux = (T)u[0], uy = (T)u[1], uz = (T)u[2];
+  const T G[3] = {(T)G_[0], (T)G_[1], (T)G_[2]}, F[3] = {(T)F_[0], (T)F_[1], (T)F_[2]};
+  const T xx = ux * ux, yy = uy * uy, zz = uz * uz;
+  meq[0] = T(0);
   meq[1] = rho * ux;
   meq[2] = rho * uy;
   meq[3] = rho * uz;
@@ -415,68 +417,71 @@ __device__ __forceinline__ void flow_moments3(double pr, double rho, const doubl
   meq[7] = rho * ux * uy;
   meq[8] = rho * ux * uz;
   meq[9] = rho * uy * uz;
-  meq[10] = rho * uy / 3.0;   // xxy
-  meq[11] = rho * uz / 3.0;   // xxz
-  meq[12] = rho * ux / 3.0;   // yyx
-  meq[13] = rho * uz / 3.0;   // yyz
-  meq[14] = rho * ux / 3.0;   // zzx
-  meq[15] = rho * uy / 3.0;   // zzy
-  meq[16] = pr / 3.0 + rho * ((xx + yy) / 3.0 - zz / 6.0);
-  meq[17] = pr / 3.0 + rho * ((xx + zz) / 3.0 - yy / 6.0);
-  meq[18] = pr / 3.0 + rho * ((yy + zz) / 3.0 - xx / 6.0);
-  const double gx = ux * G[0], gy = uy * G[1], gz = uz * G[2];
+  const T third = T(1) / T(3), sixth = T(1) / T(6);
+  meq[10] = rho * uy * third;   // xxy
+  meq[11] = rho * uz * third;   // xxz
+  meq[12] = rho * ux * third;   // yyx
+  meq[13] = rho * uz * third;   // yyz
+  meq[14] = rho * ux * third;   // zzx
+  meq[15] = rho * uy * third;   // zzy
+  meq[16] = pr * third + rho * ((xx + yy) * third - zz * sixth);
+  meq[17] = pr * third + rho * ((xx + zz) * third - yy * sixth);
+  meq[18] = pr * third + rho * ((yy + zz) * third - xx * sixth);
+  const T gx = ux * G[0], gy = uy * G[1], gz = uz * G[2];
   mv[0] = gx + gy + gz;
   mv[1] = F[0];
   mv[2] = F[1];
   mv[3] = F[2];
-  mv[4] = gx + (gy + gz) / 3.0;
-  mv[5] = gy + (gx + gz) / 3.0;
-  mv[6] = gz + (gx + gy) / 3.0;
-  mv[7] = (ux * G[1] + uy * G[0]) / 3.0;
-  mv[8] = (ux * G[2] + uz * G[0]) / 3.0;
-  mv[9] = (uy * G[2] + uz * G[1]) / 3.0;
-  mv[10] = F[1] / 3.0;
-  mv[11] = F[2] / 3.0;
-  mv[12] = F[0] / 3.0;
-  mv[13] = F[2] / 3.0;
-  mv[14] = F[0] / 3.0;
-  mv[15] = F[1] / 3.0;
-  mv[16] = (gx + gy) / 3.0;
-  mv[17] = (gx + gz) / 3.0;
-  mv[18] = (gy + gz) / 3.0;
+  mv[4] = gx + (gy + gz) * third;
+  mv[5] = gy + (gx + gz) * third;
+  mv[6] = gz + (gx + gy) * third;
+  mv[7] = (ux * G[1] + uy * G[0]) * third;
+  mv[8] = (ux * G[2] + uz * G[0]) * third;
+  mv[9] = (uy * G[2] + uz * G[1]) * third;
+  mv[10] = F[1] * third;
+  mv[11] = F[2] * third;
+  mv[12] = F[0] * third;
+  mv[13] = F[2] * third;
+  mv[14] = F[0] * third;
+  mv[15] = F[1] * third;
+  mv[16] = (gx + gy) * third;
+  mv[17] = (gx + gz) * third;
+  mv[18] = (gy + gz) * third;
 }
 // The same for a phase-field or surfactant lattice (Sec. 3): equilibrium
 // (i = 0: (w_0 - 1) eta c, the rest population taken relative to c; else
 // w_i eta c) + w_i c_i.(c v)/c_s^2, forcing w_i c_i.d/c_s^2 with d the backward
 // difference of c v.
-__device__ __forceinline__ void scalar_moments3(double c, double eta, const double* v, const double* d, double* meq,
-                                                double* mv) {
-  const double e = eta * c, jx = c * v[0], jy = c * v[1], jz = c * v[2];
-  meq[0] = 0.0;
+template <class T>
+__device__ __forceinline__ void scalar_moments3(double c_, double eta, const double* v, const double* d_, T* meq, T* mv) {
+  const T c = (T)c_, e = (T)(eta * c_), jx = c * (T)v[0], jy = c * (T)v[1], jz = c * (T)v[2];
+  const T d[3] = {(T)d_[0], (T)d_[1], (T)d_[2]};
+  const T third = T(1) / T(3), ninth = T(1) / T(9);
+  meq[0] = T(0);
   meq[1] = jx;
   meq[2] = jy;
   meq[3] = jz;
-  meq[4] = meq[5] = meq[6] = e / 3.0;
-  meq[7] = meq[8] = meq[9] = 0.0;
-  meq[10] = jy / 3.0;
-  meq[11] = jz / 3.0;
-  meq[12] = jx / 3.0;
-  meq[13] = jz / 3.0;
-  meq[14] = jx / 3.0;
-  meq[15] = jy / 3.0;
-  meq[16] = meq[17] = meq[18] = e / 9.0;
-  mv[0] = 0.0;
+  meq[4] = meq[5] = meq[6] = e * third;
+  meq[7] = meq[8] = meq[9] = T(0);
+  meq[10] = jy * third;
+  meq[11] = jz * third;
+  meq[12] = jx * third;
+  meq[13] = jz * third;
+  meq[14] = jx * third;
+  meq[15] = jy * third;
+  meq[16] = meq[17] = meq[18] = e * ninth;
+  mv[0] = T(0);
   mv[1] = d[0];
   mv[2] = d[1];
   mv[3] = d[2];
-  mv[4] = mv[5] = mv[6] = mv[7] = mv[8] = mv[9] = 0.0;
-  mv[10] = d[1] / 3.0;
-  mv[11] = d[2] / 3.0;
-  mv[12] = d[0] / 3.0;
-  mv[13] = d[2] / 3.0;
-  mv[14] = d[0] / 3.0;
-  mv[15] = d[1] / 3.0;
-  mv[16] = mv[17] = mv[18] = 0.0;
+  mv[4] = mv[5] = mv[6] = mv[7] = mv[8] = mv[9] = T(0);
+  mv[10] = d[1] * third;
+  mv[11] = d[2] * third;
+  mv[12] = d[0] * third;
+  mv[13] = d[2] * third;
+  mv[14] = d[0] * third;
+  mv[15] = d[1] * third;
+  mv[16] = mv[17] = mv[18] = T(0);
 }
 // Populations from raw moments (the inverse of moments3).
 template <class T>
@@ -610,7 +615,7 @@ __device__ Macro3 macro3(const P3& p, const unsigned char* __restrict__ solid, c
   }
   const double ugr = M.u[0] * gr[0] + M.u[1] * gr[1] + M.u[2] * gr[2];
   const double uu = M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2];
-  M.pr = kCs2 / (1.0 - w3(0)) * (snz + 0.5 * ugr - M.rho * w3(0) * uu / (2.0 * kCs2));
+  M.pr = kCs2 / (1.0 - w3(0)) * (snz + 0.5 * ugr - M.rho * w3(0) * uu * 1.5);   // 1 / (2 c_s^2) = 3/2
   M.tphi = tp;
   M.tpsi = ts;
   M.l0s = l0s;
@@ -641,11 +646,12 @@ __global__ __launch_bounds__(kT, kColfWaves<S>) void k3_colf(
   // sources (Sec. 3): R_phi with the multiplier term and the wall flux, R_psi likewise
   const double Rphi = p.M_phi * (-4.0 * p.beta * (1.0 - ps) * (ph * ph * ph - ph) - p.W * ps * ph + lam * hprime(p, ph))
                     + p.M_phi * M.tphi;
-  const double Rpsi = p.surf ? -p.M0 * M.l0s
-                                   + p.M_psi * (-p.kBT * log(ps / (1.0 - ps)) + p.beta * (1.0 - ph * ph) * (1.0 - ph * ph)
-                                                - 0.5 * p.W * ph * ph + mubar)
-                                   + p.M_psi * M.tpsi
-                             : 0.0;
+  // The bulk part -kBT ln(psi/(1-psi)) + beta (1-phi^2)^2 - W phi^2 / 2 of
+  // R_psi is -(mu_psi + lambda_s L0 psi + T_psi), from mu_psi as k3_mu formed it
+  // (the same L0 psi and wall term, summed in the same order): no second
+  // logarithm per node.
+  const double bulk = -(pr(mu, n).y + p.lambda_s * M.l0s + M.tpsi);
+  const double Rpsi = p.surf ? -p.M0 * M.l0s + p.M_psi * (bulk + mubar) + p.M_psi * M.tpsi : 0.0;
   // advecting velocity (the step's own u, or its mean with the previous step's)
   double v[3] = {M.u[0], M.u[1], M.u[2]};
   if (have_hist && !p.adv_raw)
@@ -672,9 +678,9 @@ __global__ __launch_bounds__(kT, kColfWaves<S>) void k3_colf(
     for (int k = 0; k < Q3; ++k) mf[k] = T(0);
 #pragma unroll
     for (int i = 0; i < Q3; ++i) raw3<T>(i, (T)el(pin, i, N, n), mf);   // pressure-based: of the order of p w_i / c_s^2
-    double meq[Q3], mv[Q3];
-    flow_moments3(M.pr, rho, M.u, M.gr, M.F, meq, mv);
-    relax3<T>(rates, mf, meq, mv, m);
+    T meq[Q3], mv[Q3];
+    flow_moments3<T>(M.pr, rho, M.u, M.gr, M.F, meq, mv);
+    relax3(rates, mf, meq, mv, m);
     populations3<T>(m, f);
     // push streaming; walls in z
     const Off3 o = offsets3(p, x, y, z);
@@ -772,9 +778,9 @@ __global__ __launch_bounds__(kT) void k3_colgh(const P3* __restrict__ pp_, const
       const double fi = (double)pin[(size_t)(base + i) * N + n] + (i == 0 ? cref - c : 0.0);
       raw3<T>(i, (T)fi, mf);
     }
-    double meq[Q3], mv[Q3];
-    scalar_moments3(c, eta, v, dj, meq, mv);
-    relax3<T>(r5, mf, meq, mv, m);
+    T meq[Q3], mv[Q3];
+    scalar_moments3<T>(c, eta, v, dj, meq, mv);
+    relax3(r5, mf, meq, mv, m);
     populations3<T>(m, f);
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
