@@ -66,6 +66,12 @@ def test_3d_parameter_validation_without_a_device(lbm):
     assert b"nz" in L.lbm3d_last_error(None)
     bad = lbm3d.make_params(inputs.drop3d(16, 5.0), lbm.FP16_SHIFTED)
     assert L.lbm3d_required_bytes(ctypes.byref(bad), ctypes.byref(n)) == -1
+    # the kernels address a node's values with 32-bit byte offsets: 2^29 nodes or more are refused
+    big = lbm3d.make_params(dict(inputs.drop3d(16, 5.0), nx=1024, ny=1024, nz=512), lbm.FP32)
+    assert L.lbm3d_required_bytes(ctypes.byref(big), ctypes.byref(n)) == -1
+    assert b"2^29" in L.lbm3d_last_error(None)
+    ok = lbm3d.make_params(dict(inputs.drop3d(16, 5.0), nx=1024, ny=1024, nz=511), lbm.FP32)
+    assert L.lbm3d_required_bytes(ctypes.byref(ok), ctypes.byref(n)) == 0
 
 
 def test_param_struct_layout_matches_header(lbm):
