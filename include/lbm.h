@@ -331,7 +331,8 @@ int lbm_batch_fetch_fields(lbm_batch* b, int32_t index, uint32_t mask, double* h
  * changes the batch's workgroup map, which is rebuilt (and the step graphs
  * captured again) at the next call that steps or sets activity; results do not
  * depend on the slot a case runs in.  LBM_E_ARG if the case does not fit or
- * does not match the batch. */
+ * does not match the batch (the slot keeps its case); if initialising the new
+ * case fails on the device the slot is retired and the error returned. */
 int lbm_batch_replace_case(lbm_batch* b, int32_t index, const lbm_params* p);
 
 /* Bytes of device memory slot index holds (set by the case it was created

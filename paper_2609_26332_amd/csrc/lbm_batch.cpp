@@ -374,7 +374,13 @@ int lbm_batch_replace_case(lbm_batch* b, int32_t index, const lbm_params* p) {
                                    std::to_string(index) + " holds " + std::to_string(b->slot_bytes[index]));
   lbm_handle* nh = nullptr;
   rc = lbm_init(p, (char*)b->buf + b->off[index], b->slot_bytes[index], b->stream, &nh);
-  if (rc) return bfail(b, rc, lbm_last_error(nullptr));
+  if (rc) {   // the slot's memory may be partly overwritten: retire the slot
+    const std::string msg = lbm_last_error(nullptr);
+    b->active[index] = 0;
+    b->hc[index].active = 0;
+    if (!b->table_dirty) (void)push_case(b, index);
+    return bfail(b, rc, msg);
+  }
   lbm::HandleView old = lbm::handle_view(b->h[index]);
   const bool same_tiling = old.dp->nx == p->nx && old.dp->ny == p->ny;
   lbm_destroy(b->h[index]);   // does not own the buffer or the stream
