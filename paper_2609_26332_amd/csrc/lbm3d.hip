@@ -3,8 +3,8 @@
 //
 // One step is five launches over the nodes (one thread per node, x fastest,
 // so every plane access of a wavefront is 64 consecutive elements):
-//   k3_mu    chemical potentials (eq_muphi, eq_mupsi) from the FP64 phi/psi
-//            planes with the 18-direction isotropic Laplacian, the wall terms
+//   k3_mu    chemical potentials (eq_muphi, eq_mupsi) from the FP64 (phi, psi)
+//            pairs with the 18-direction isotropic Laplacian, the wall terms
 //            of the first fluid layer, and FP64 per-workgroup multiplier sums
 //   k3_fin   one wavefront: lambda_phi (eq15) and mubar_psi (AC_psi) from the
 //            sums, in a fixed order
@@ -21,9 +21,11 @@
 //            (two kernels rather than one: one kernel holding all three
 //            lattices needs more than 256 registers a lane, one wave per SIMD)
 //   k3_mom   phi, psi of the new state (zeroth moments) into the other FP64
-//            plane pair
+//            pair array
+// (phi, psi) and (mu_phi, mu_psi) are stored interleaved, one 16-byte pair a
+// node, so a stencil reads a neighbour's pair with one load.
 // The rest populations of g and h are stored shifted by the phi, psi of the
-// step that wrote them (read back from the FP64 plane pair that then holds
+// step that wrote them (read back from the FP64 pair array that then holds
 // the previous step's values), so FP32 storage rounds only the increments.
 // Complex walls: nodes marked solid (lbm3d_set_solid) hold no fluid; a link
 // from a fluid node x into a solid node is a half-way bounce-back wall for all
@@ -112,8 +114,8 @@ struct Scal3 {
 // Device state of one handle.
 struct St3 {
   void* pops[2];     // 57 planes each (f 0..18, g 19..37, h 38..56), storage type
-  double* pp[2];     // phi, psi planes of a state (pp[cur]: current, pp[cur ^ 1]: previous)
-  double* mu;        // mu_phi, mu_psi planes
+  double* pp[2];     // (phi, psi) pairs of a state, interleaved (pp[cur]: current, pp[cur ^ 1]: previous)
+  double* mu;        // (mu_phi, mu_psi) pairs, interleaved
   void* uh[2];       // history: ux, uy, uz, vx, vy, vz, R_phi, R_psi of a step, in the storage type
   double* part;      // [kRedB][4] multiplier sums or [kRedB][8] invariant sums
   Scal3* sc;         // multipliers of the current step
@@ -514,7 +516,7 @@ __device__ __forceinline__ double cdot3(int i, double ax, double ay, double az) 
 }
 
 // Macroscopic state at a node (phi, psi, rho, grad rho, F, u, p, the wall
-// terms and the zero-flux Laplacian of psi), from the FP64 planes and the f
+// terms and the zero-flux Laplacian of psi), from the FP64 pairs and the f
 // populations of the current state.
 struct Macro3 {
   double ph, ps, rho, gr[3], F[3], u[3], pr, tphi, tpsi, l0s;
