@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 3
+#define LBM_ABI_VERSION 4
 
 typedef struct lbm_handle lbm_handle; /* opaque, owned by the library */
 
@@ -115,6 +115,13 @@ typedef struct {
   double M0;                /* < 0 derive: 0 if lambda_s > 0, else M_phi kappa */
   double s_f[5], s_g[5], s_h[5]; /* MRT rates by moment order 0..4 (<= 0: 1); s_f[2] <= 0: local 1/(3 mu/rho + 1/2) */
   double x0, y0, R0, a, b;  /* initial geometry */
+  double mms_dx;            /* 0 (default): off.  > 0: the accuracy test of Sec. 4.1 on the unit square
+                               with grid spacing mms_dx (nx mms_dx = ny mms_dx = 1, periodic, FP64
+                               storage, linear constraint, surfactant on): the step prescribes the
+                               velocity (0.05, -0.03) (lattice units: times dt/dx, dt = dx^2/0.15) and
+                               p = 0, and adds dt times the test's manufactured sources S_phi, S_psi
+                               at time t = n dt of step n to R_phi and R_psi; steps run eagerly (the
+                               step index is a launch argument), without captured graphs */
 } lbm_params;
 
 typedef struct {

@@ -93,8 +93,25 @@ std::string derive(const lbm_params& p, lbm::DevParams& d, double* derived) {
     for (int k = 0; k < 5; ++k)
       if (!(rates[l][k] < 2.0) || std::isnan(rates[l][k])) return "relaxation rates must lie in (0,2)";
 
+  if (!(p.mms_dx >= 0.0)) return "mms_dx must be >= 0";
+  if (p.mms_dx > 0.0) {
+    if (p.bc_bottom != LBM_BC_PERIODIC) return "the accuracy test needs periodic boundaries";
+    if (std::fabs(p.nx * p.mms_dx - 1.0) > 1e-9 || std::fabs(p.ny * p.mms_dx - 1.0) > 1e-9)
+      return "the accuracy test runs on the unit square: nx mms_dx = ny mms_dx = 1";
+    if (p.precision != LBM_FP64) return "the accuracy test runs in FP64 storage";
+    if (p.constraint_phi != LBM_CONSTRAINT_LINEAR) return "the accuracy test uses the linear constraint";
+    if (!(p.psi_b > 0.0)) return "the accuracy test needs the surfactant (psi_b > 0)";
+  }
+
   std::memset(&d, 0, sizeof(d));
   d.nx = p.nx; d.ny = p.ny; d.N = p.nx * p.ny;
+  if (p.mms_dx > 0.0) {
+    d.mms = 1;
+    d.mms_dx = p.mms_dx;
+    d.mms_dt = p.mms_dx * p.mms_dx / 0.15;
+    d.mms_ux = 0.05 * d.mms_dt / p.mms_dx;
+    d.mms_uy = -0.03 * d.mms_dt / p.mms_dx;
+  }
   d.periodic_y = p.bc_bottom == LBM_BC_PERIODIC;
   d.bc_bottom = p.bc_bottom; d.bc_top = p.bc_top;
   d.wet_bottom = wet_b; d.wet_top = wet_t;
@@ -357,7 +374,7 @@ int lbm_step(lbm_handle* h, int64_t n) {
     const bool timing = h->timer.ev && h->timer.used < h->timer.max_steps;
     int kind = kGraphKinds - 1;
     while (kind >= 0 && n - k < (int64_t(2) << kind)) --kind;
-    if (!timing && kind >= 0 && h->have_hist && h->ds.cur == h->ds.hcur && h->ds.cur == h->ds.scur &&
+    if (!timing && !h->dp.mms && kind >= 0 && h->have_hist && h->ds.cur == h->ds.hcur && h->ds.cur == h->ds.scur &&
         (!h->graph[kind] || h->ds.cur == h->graph_parity[kind])) {
       if (!h->graph[kind]) {
         const int rc = capture_graph(h, kind);
@@ -368,7 +385,7 @@ int lbm_step(lbm_handle* h, int64_t n) {
       k += int64_t(2) << kind;
       continue;
     }
-    HIP_OR_FAIL(h, lbm::launch_step(h->dp, h->ds, h->have_hist, h->stream, &h->timer), "step kernels");
+    HIP_OR_FAIL(h, lbm::launch_step(h->dp, h->ds, h->have_hist, h->stream, &h->timer, 0, h->step), "step kernels");
     h->have_hist = 1;
     h->step += 1;
     k += 1;

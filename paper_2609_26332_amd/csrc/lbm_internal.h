@@ -47,6 +47,10 @@ struct DevParams {
   int phi_hold;
   double m_ref;
   int init_kind;
+  // Accuracy test of Sec. 4.1 (mms != 0): grid spacing and time step of the
+  // unit square, the prescribed velocity in lattice units.
+  int mms;
+  double mms_dx, mms_dt, mms_ux, mms_uy;
 };
 
 // FP64 multiplier state kept on the device.  The fused step leaves the
@@ -143,8 +147,9 @@ struct StepTimer {
 // steps with a history and at most kFuseTiles workgroups.
 enum { kFusePrev = 1, kFuseNext = 2 };
 constexpr int kFuseTiles = 1024;
+// step: index of the step being taken (the accuracy test's source time).
 hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t stream, StepTimer* timer = nullptr,
-                       int fuse = 0);
+                       int fuse = 0, int64_t step = 0);
 hipError_t launch_step_batch(int precision, bool walls, const BatchCase* d_cases, const int* d_wg_case, int nwg, int count,
                              hipStream_t stream, StepTimer* timer = nullptr);
 hipError_t launch_macro(const DevParams& p, DevState& s, hipStream_t stream);  // phi/psi, mu, multipliers of the current state

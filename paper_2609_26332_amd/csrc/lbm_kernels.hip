@@ -632,6 +632,31 @@ template <class T> __device__ __forceinline__ T opaque_v(T v) {   // the same fo
 // Schedules of step_body: the sweep, or one tile of four rows in one pass with
 // eight waves (kOneShot8) or four (kOneShot4).
 enum { kSweep = 0, kOneShot8 = 1, kOneShot4 = 2 };
+// Manufactured source of the accuracy test (Sec. 4.1) at node (x, y) of step
+// n, in lattice units (dt times the physical source): the exact fields
+// phi^e = e^-t sin(2 pi (x - 0.05 t)) cos(2 pi (y + 0.03 t)) / 2 and psi^e =
+// 1/2 + e^-2t cos(2 pi (x - 0.05 t)) sin(2 pi (y + 0.03 t)) / 20 solve the
+// phi and psi equations with the prescribed velocity when S_phi = -phi^e +
+// M (mu_phi^e - 0) and S_psi = -2 (psi^e - 1/2) + M (mu_psi^e - mubar_psi^e),
+// mu^e the chemical potentials (eq_muphi, eq_mupsi; the Laplacian of phi^e
+// is -8 pi^2 phi^e, lambda_s = 0) and mubar_psi^e = -beta (1 - a^2/2 + 9 a^4
+// / 64) + W a^2 / 8, a = e^-t / 2, their stated means.  The lattice mobility
+// is M dt, so dt S = -dt phi^e + M_lattice mu^e; kappa in physical units is
+// the lattice kappa times dx^2.
+__device__ __forceinline__ void manufactured_source(const DevParams& p, unsigned x, int y, int n, double& sphi,
+                                                    double& spsi) {
+  const double dx = p.mms_dx, dt = p.mms_dt, t = (double)n * dt, tp = 2.0 * 3.14159265358979323846;
+  const double X = tp * ((double)x * dx - 0.05 * t), Y = tp * ((double)y * dx + 0.03 * t);
+  const double a = 0.5 * exp(-t);
+  const double ph = a * sin(X) * cos(Y), ps = 0.5 + 0.05 * exp(-2.0 * t) * cos(X) * sin(Y);
+  const double kap = p.kappa * dx * dx;
+  const double mu_phi = 4.0 * p.beta * (1.0 - ps) * (ph * ph * ph - ph) + kap * tp * tp * 2.0 * ph + p.W * ps * ph;
+  const double mu_psi = p.kBT * log(ps / (1.0 - ps)) - p.beta * (1.0 - ph * ph) * (1.0 - ph * ph) + 0.5 * p.W * ph * ph;
+  const double a2 = a * a, mubar = -p.beta * (1.0 - 0.5 * a2 + 9.0 * a2 * a2 / 64.0) + p.W * a2 / 8.0;
+  sphi = -dt * ph + p.M_phi * mu_phi;
+  spsi = -dt * 2.0 * (ps - 0.5) + p.M_psi * (mu_psi - mubar);
+}
+
 // LDS of one step workgroup, shared by the walled and the periodic form of a
 // schedule (a kernel that holds both allocates it once).
 template <class S, class C, int SCHED>
@@ -658,8 +683,8 @@ __device__ __forceinline__ StepLds<S, C, SCHED>& step_lds() {
   __shared__ StepLds<S, C, SCHED> lds;
   return lds;
 }
-template <class S, class C, bool WALLS, int SCHED = kSweep>
-__device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a, const int tile) {
+template <class S, class C, bool WALLS, int SCHED = kSweep, bool MMS = false>
+__device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a, const int tile, const int mms_step = 0) {
   // Store hint, as measured on MI355X.  FP32 and FP16 storage store plainly on
   // the row sweep and the four-wave tile: the lines of neighbouring strips
   // combine in the L2 before they are written back (at 4096^2 WRITE_SIZE falls
@@ -940,17 +965,28 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     const double grx = gfx, gry = gfy;
     const double rho = rho_of(p, ph);
     const double Fx = -ph * gpx - ps * gsx + rho * p.gx, Fy = -ph * gpy - ps * gsy + rho * p.gy;
-    const double ux = ((double)(f[1] - f[3] + f[5] - f[6] - f[7] + f[8]) + 0.5 * Fx) / rho;
-    const double uy = ((double)(f[2] - f[4] + f[5] + f[6] - f[7] - f[8]) + 0.5 * Fy) / rho;
+    double ux = ((double)(f[1] - f[3] + f[5] - f[6] - f[7] + f[8]) + 0.5 * Fx) / rho;
+    double uy = ((double)(f[2] - f[4] + f[5] + f[6] - f[7] - f[8]) + 0.5 * Fy) / rho;
     const double snz = (double)(f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]);
-    const double pr = 0.6 * (snz + 0.5 * (ux * grx + uy * gry) - rho * (2.0 / 3.0) * (ux * ux + uy * uy));
+    double pr = 0.6 * (snz + 0.5 * (ux * grx + uy * gry) - rho * (2.0 / 3.0) * (ux * ux + uy * uy));
+    if constexpr (MMS) {   // the accuracy test prescribes u and p
+      ux = p.mms_ux;
+      uy = p.mms_uy;
+      pr = 0.0;
+    }
 
     // Sources without this step's multiplier terms (those are deferred).  With
     // the chemical potentials of phase B: R_phi = -M_phi (mu_phi + kappa L0(phi))
     // and R_psi = -M_psi mu_psi - (M0 + M_psi lambda_s) L0(psi), identical to the
     // bulk terms plus the wall terms of eq_muphi / eq_mupsi.
-    const double Rp0 = -p.M_phi * (mc.x + p.kappa * l0p);
-    const double Rs0 = p.surf ? -p.M_psi * mc.y - (p.M0 + p.M_psi * p.lambda_s) * l0s : 0.0;
+    double Rp0 = -p.M_phi * (mc.x + p.kappa * l0p);
+    double Rs0 = p.surf ? -p.M_psi * mc.y - (p.M0 + p.M_psi * p.lambda_s) * l0s : 0.0;
+    if constexpr (MMS) {
+      double sp, ss;
+      manufactured_source(p, x, gy, mms_step, sp, ss);
+      Rp0 += sp;
+      Rs0 += ss;
+    }
     // the psi source the collision carries includes M_psi mu_ref (the rest of the multiplier term is pending)
     const double Rs0c = p.surf ? Rs0 + p.M_psi * p.mu_ref : 0.0;
     double vx = ux, vy = uy, dpx = 0, dpy = 0, dsx = 0, dsy = 0, Rtp = Rp0, Rts = Rs0c;
@@ -1460,6 +1496,12 @@ __global__ __launch_bounds__(kBlock, MINB) void k_step(const DevParams* __restri
   step_body<S, C, WALLS>(*pp, a, t);
 }
 
+// The accuracy test of Sec. 4.1 (periodic grid, FP64): the row sweep with the
+// prescribed velocity and the manufactured sources of step `step`.
+__global__ __launch_bounds__(kBlock) void k_step_mms(const DevParams* __restrict__ pp, StepArgs a, int step) {
+  step_body<double, double, false, kSweep, true>(*pp, a, xcd_tile(blockIdx.x, gridDim.x), step);
+}
+
 // Small grids (at most one workgroup of four rows per CU): the one-shot
 // schedule of a tile with eight waves.
 template <class S, class C, bool WALLS>
@@ -1828,7 +1870,8 @@ hipError_t macro_impl(const DevParams& p, DevState& s, hipStream_t st) {
 }
 
 template <class S, class C>
-void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* t, int fuse) {
+void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* t, int fuse,
+                 long long step) {
   StepArgs a;
   a.Pin = s.pops[s.cur];
   a.Pout = s.pops[s.cur ^ 1];
@@ -1849,6 +1892,12 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
   {
     TimedScope ts(t, LBM_K_STEP, st);
     const DevParams* dp = (const DevParams*)s.dparams;
+    if constexpr (std::is_same<S, double>::value) {
+      if (p.mms) {   // the accuracy test: periodic, FP64, the row sweep with its sources
+        hipLaunchKernelGGL(k_step_mms, dim3(a.ntiles), dim3(kBlock), 0, st, dp, a, (int)step);
+        goto finish;
+      }
+    }
     // the choice depends on the number of workgroups against the device's CUs
     // (256 on an MI355X); every variant gives the same results
     switch (step_variant(p, s)) {
@@ -1868,6 +1917,7 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
         else hipLaunchKernelGGL((k_step<S, C, true, 1>), dim3(a.ntiles), dim3(kBlock), 0, st, dp, a);
     }
   }
+finish:
   if (!(fuse & kFuseNext)) {
     TimedScope ts(t, LBM_K_FINISH, st);
     hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(kBlock), 0, st, (const DevParams*)s.dparams, (const double*)a.partials,
@@ -1876,9 +1926,10 @@ void launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st,
 }
 
 template <class S, class C>
-hipError_t step_impl(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer, int fuse) {
+hipError_t step_impl(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer, int fuse,
+                     long long step) {
   StepTimer* t = (timer && timer->ev && timer->used < timer->max_steps) ? timer : nullptr;
-  launch_step<S, C>(p, s, have_hist, st, t, fuse);
+  launch_step<S, C>(p, s, have_hist, st, t, fuse, step);
   if (t) t->used += 1;
   s.cur ^= 1;
   s.hcur ^= 1;
@@ -1934,6 +1985,7 @@ size_t step_blocks(int nx, int ny, int seg_rows) {
   return (size_t)((nx + kStripW - 1) / kStripW) * (size_t)((ny + seg_rows - 1) / seg_rows);
 }
 int step_variant(const DevParams& p, const DevState& s) {
+  if (p.mms) return kVarSweep;   // the accuracy test runs the row sweep
   const size_t ntiles = step_blocks(p.nx, p.ny, s.tile_rows);
   const size_t cus = (size_t)s.cus;
   const size_t packed = s.precision == LBM_FP64 ? (size_t)kStepMinBlocks<double> : (size_t)kStepMinBlocks<float>;
@@ -1997,10 +2049,11 @@ hipError_t launch_step_batch(int precision, bool walls, const BatchCase* d_cases
                (batch_step_impl<float, float>(walls, d_cases, d_wg_case, nwg, count, st, timer)),
                (batch_step_impl<_Float16, float>(walls, d_cases, d_wg_case, nwg, count, st, timer)));
 }
-hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer, int fuse) {
-  LBM_DISPATCH(s.precision, (step_impl<double, double>(p, s, have_hist, st, timer, fuse)),
-               (step_impl<float, float>(p, s, have_hist, st, timer, fuse)),
-               (step_impl<_Float16, float>(p, s, have_hist, st, timer, fuse)));
+hipError_t launch_step(const DevParams& p, DevState& s, int have_hist, hipStream_t st, StepTimer* timer, int fuse,
+                       int64_t step) {
+  LBM_DISPATCH(s.precision, (step_impl<double, double>(p, s, have_hist, st, timer, fuse, step)),
+               (step_impl<float, float>(p, s, have_hist, st, timer, fuse, step)),
+               (step_impl<_Float16, float>(p, s, have_hist, st, timer, fuse, step)));
 }
 hipError_t launch_macro(const DevParams& p, DevState& s, hipStream_t st) {
   LBM_DISPATCH(s.precision, (macro_impl<double, double>(p, s, st)), (macro_impl<float, float>(p, s, st)),

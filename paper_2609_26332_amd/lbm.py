@@ -18,7 +18,7 @@ import torch  # noqa: F401  -- loads torch's HIP runtime first so one runtime se
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 PERIODIC, WALL_WET, NOSLIP, FREESLIP = 0, 1, 2, 3
 FP64, FP32, FP16_SHIFTED = 0, 1, 2
 NONLINEAR, LINEAR = 0, 1
@@ -68,7 +68,7 @@ class Params(ctypes.Structure):
         ("eta_phi", ctypes.c_double), ("eta_psi", ctypes.c_double), ("M0", ctypes.c_double),
         ("s_f", ctypes.c_double * 5), ("s_g", ctypes.c_double * 5), ("s_h", ctypes.c_double * 5),
         ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("R0", ctypes.c_double),
-        ("a", ctypes.c_double), ("b", ctypes.c_double),
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("mms_dx", ctypes.c_double),
     ]
 
 
