@@ -85,6 +85,7 @@ int plan(const lbm_params* cases, int32_t count, Plan& P, std::string& why) {
       return LBM_E_ARG;
     }
     if (cases[c].precision != cases[0].precision) { why = "all cases of a batch share one storage precision"; return LBM_E_ARG; }
+    if (cases[c].mms_dx > 0.0) { why = "the accuracy test (mms_dx) runs on single handles, not in a batch"; return LBM_E_ARG; }
     if ((cases[c].bc_bottom != LBM_BC_PERIODIC) != walls0) { why = "all cases of a batch are walled in y, or all periodic"; return LBM_E_ARG; }
     P.case_bytes[c] = align256(bytes);
     wg += lbm::step_blocks(cases[c].nx, cases[c].ny, 4);

@@ -144,3 +144,13 @@ def test_batch_validation(lbm):
     assert L.lbm_required_bytes(ctypes.byref(arr[0]), ctypes.byref(single)) == 0
     assert n.value > single.value
     assert L.lbm_batch_required_bytes(arr, 0, ctypes.byref(n)) == -1
+    # the accuracy test of Sec. 4.1 runs on single handles only, and only as specified
+    mms = inputs.manufactured(32)
+    arr = (lbm.Params * 2)(lbm.make_params(mms, lbm.FP64), lbm.make_params(mms, lbm.FP64))
+    assert L.lbm_batch_required_bytes(arr, 2, ctypes.byref(n)) == -1
+    assert b"accuracy test" in L.lbm_batch_last_error(None)
+    assert L.lbm_required_bytes(ctypes.byref(arr[0]), ctypes.byref(single)) == 0
+    for bad in (lbm.make_params(mms, lbm.FP32), lbm.make_params(dict(mms, nx=33), lbm.FP64),
+                lbm.make_params(dict(mms, constraint_phi=inputs.NONLINEAR), lbm.FP64)):
+        assert L.lbm_required_bytes(ctypes.byref(bad), ctypes.byref(single)) == -1
+        assert b"accuracy test" in L.lbm_last_error(None)
