@@ -430,6 +430,9 @@ def main():
     rl = kernel_line(hb["kernels"], hb["nodes"], prec, design_bytes(prec))
     rl.update(kernel="k_step_batch", nodes_per_launch=hb["nodes"],
               traffic=measured_traffic("batch_" + prec))
+    if rl["traffic"] is not None:
+        rl["traffic_source"] = ("rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel source, scaled by a 1 GiB copy's "
+                                "readings (profiles/k_step_traffic.md); not counted in this run")
     from paper_2609_26332_amd import lbm as _lbm
     hc = _lbm.probe_copy(1.0, 10)
     rl.update(copy_ceiling_gbs=round(hc["gbs"], 2), frac_of_copy_ceiling=round(rl["achieved"] / hc["gbs"], 4))
@@ -460,6 +463,7 @@ def main():
         g = {}
         for p in ("fp32", "fp64", "fp16"):
             g[p] = grid_run(big, p, 100, 10, args.kernel_steps)
+            g[p]["traffic"] = measured_traffic("grid_" + p)
             torch.cuda.empty_cache()
         from paper_2609_26332_amd import lbm
         pr = lbm.probe_stream(big["nx"], big["ny"], "fp32", reps=20)
