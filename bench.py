@@ -93,6 +93,7 @@ def batch_run(prec, steps, warmup, kernel_steps, count=512):
     cases = sweep.batch_cases(SEED, count)
     b = lbm.Batch(cases, prec)
     seg = b.autotune(trial_steps=10)
+    tune = b.autotune_report()
     info = b.info()
     b.step(warmup)
     sync()
@@ -111,7 +112,9 @@ def batch_run(prec, steps, warmup, kernel_steps, count=512):
            "nodes": nodes, "cases": count, "seg_rows": seg, "workgroups": info["workgroups"],
            "wall_s": wall, "mlups": nodes * steps / wall / 1e6, "ms_per_step": wall * 1e3 / steps,
            "case_steps_per_s": count * steps / wall, "nonfinite_cases": int(sum(1 for v in inv if v["nonfinite"])),
-           "kernels": kt}
+           "kernels": kt,
+           "autotune": [dict(seg_rows=r["seg_rows"], trial_ms=round(r["ms"], 3), max_rel_dev=float("%.3g" % r["max_rel_dev"]),
+                             passed=r["passed"]) for r in tune]}
     b.close()
     return out
 
@@ -448,6 +451,9 @@ def main():
         "lattice_mlups": round(3 * hb["mlups"], 2),
         "case_steps_per_s": round(hb["case_steps_per_s"], 1),
         "roofline": rl,
+        "autotune": {"what": "segment heights tried on the batch, 10 timed steps each from the initial state; a "
+                             "candidate counts only if its sums agree with the first's (relative 1e-6 in FP32)",
+                     "candidates": hb["autotune"]},
     }
     if hb["nonfinite_cases"]:
         out["warning"] = "%d cases with non-finite fields after the timed run" % hb["nonfinite_cases"]

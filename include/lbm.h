@@ -346,10 +346,24 @@ int lbm_batch_replace_case(lbm_batch* b, int32_t index, const lbm_params* p);
  * with): a refill with lbm_batch_replace_case must need no more. */
 int lbm_batch_slot_bytes(lbm_batch* b, int32_t index, size_t* bytes);
 
-/* Autotuner: times trial_steps steps of the batch for each segment height of
- * {4, 8, 16, 32, 64}, keeps the fastest (written to *seg_rows_out) and puts
- * every case back to its initial state.  Only before the first step. */
+/* Autotuner: for each segment height of {4, 8, 16, 32, 64} steps the batch
+ * 1 + trial_steps times from its initial state, timing the last trial_steps,
+ * and checks the result: every active case's sum psi, sum phi, sum h_phi and
+ * lambda_phi must lie within a relative 1e-10 (FP64 storage), 1e-6 (FP32) or
+ * 1e-4 (FP16) of the first candidate's, with no non-finite field (the
+ * candidates change only how the FP64 multiplier sums are grouped).  Keeps the
+ * fastest candidate that passes (written to *seg_rows_out) and puts every case
+ * back to its initial state.  Only before the first step.  LBM_E_NONFINITE if
+ * no candidate passes (the batch keeps its previous height). */
 int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, int32_t* seg_rows_out);
+
+/* The last autotune's candidates, in the order tried: segment height, time of
+ * the trial steps (ms), largest relative deviation of the checked sums from
+ * the first candidate's (0 for the first), and 1 when the candidate passed the
+ * check.  Caller-owned arrays of max_rows entries; *rows receives the number of
+ * candidates (0 before any autotune).  LBM_E_ARG when max_rows is smaller. */
+int lbm_batch_autotune_report(lbm_batch* b, int32_t max_rows, int32_t* seg_rows, double* ms, double* max_rel_dev,
+                              int32_t* passed, int32_t* rows);
 
 /* Cases, segment height, workgroups of one step launch and total nodes. */
 int lbm_batch_info(lbm_batch* b, int32_t* count, int32_t* seg_rows, int32_t* workgroups, int64_t* nodes);

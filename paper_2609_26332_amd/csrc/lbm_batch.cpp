@@ -10,6 +10,7 @@
 // count and activity live in the table on the device, so runs of steps replay
 // from one captured HIP graph whatever the cases' states, and cases retire
 // (activity 0) without rebuilding anything.
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -39,6 +40,11 @@ struct lbm_batch {
   hipGraphExec_t graph[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // 2^k steps
   int64_t step = 0;
   lbm::StepTimer timer;
+  // the last autotune: per candidate segment height, time of its trial steps,
+  // largest relative deviation of its checked sums from the first candidate's,
+  // and whether it passed that check
+  struct TuneRow { int seg; double ms; double dev; int ok; };
+  std::vector<TuneRow> tune;
   std::string err = "no error";
 };
 
@@ -404,17 +410,32 @@ int lbm_batch_slot_bytes(lbm_batch* b, int32_t index, size_t* bytes) {
   return LBM_OK;
 }
 
+// Relative tolerance of the autotuner's check: candidates differ only in how
+// the FP64 multiplier sums are grouped (their last bits), which the storage
+// rounding then carries into the fields.
+static double tune_tol(int precision) {
+  return precision == LBM_FP64 ? 1e-10 : (precision == LBM_FP32 ? 1e-6 : 1e-4);
+}
+
 int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, int32_t* seg_rows_out) {
   if (!b || !seg_rows_out) return bfail(b, LBM_E_ARG, "null argument");
   if (trial_steps < 2 || trial_steps > 10000) return bfail(b, LBM_E_ARG, "trial_steps must lie in [2, 10000]");
   if (b->step != 0) return bfail(b, LBM_E_STATE, "autotune before the first step of a batch");
+  int rc = ensure_table(b);
+  if (rc) return rc;
   const int cand[] = {4, 8, 16, 32, 64};
   double best = 1e300;
   int best_seg = b->seg_rows;
+  // Every candidate steps the batch from its initial state; the conserved sums
+  // and the multiplier of each active case after the trial are compared with
+  // the first candidate's, and a candidate that departs is not chosen.
+  std::vector<lbm_invariants> ref(b->count), cur(b->count);
+  b->tune.clear();
+  const double tol = tune_tol(b->precision);
   for (int seg : cand) {
     b->seg_rows = seg;
     drop_graph(b);
-    int rc = build_table(b);
+    rc = build_table(b);
     if (rc) return rc;
     BHIP(b, lbm::launch_step_batch(b->precision, b->walls, b->d_cases, b->d_wg, b->nwg, b->count, b->stream, nullptr), "warm-up step");
     hipEvent_t e0, e1;
@@ -430,17 +451,58 @@ int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, int32_t* seg_rows_out)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
-    if (ms < best) { best = ms; best_seg = seg; }
+    b->device_ahead = true;
+    rc = sync_handles(b);
+    if (rc) return rc;
+    std::vector<lbm_invariants>& out = b->tune.empty() ? ref : cur;
+    double dev = 0.0;
+    int ok = 1;
+    for (int c = 0; c < b->count; ++c) {
+      if (!b->active[c]) continue;
+      const int r = lbm_reduce_invariants(b->h[c], &out[c]);   // a non-finite or out-of-range field fails the candidate
+      if (r != LBM_OK && r != LBM_E_NONFINITE && r != LBM_E_RANGE) return bfail(b, r, lbm_last_error(b->h[c]));
+      if (r != LBM_OK || out[c].nonfinite) ok = 0;
+      if (&out == &cur) {
+        const double a[4] = {ref[c].mass_psi, ref[c].sum_phi, ref[c].m_phi_h, ref[c].lambda_phi};
+        const double q[4] = {cur[c].mass_psi, cur[c].sum_phi, cur[c].m_phi_h, cur[c].lambda_phi};
+        for (int k = 0; k < 4; ++k) {
+          const double d = std::fabs(q[k] - a[k]) / std::fmax(std::fabs(a[k]), 1e-300);
+          dev = std::isnan(d) ? 1e300 : std::fmax(dev, d);
+        }
+      }
+    }
+    if (dev > tol) ok = 0;
+    b->tune.push_back({seg, (double)ms, dev, ok});
+    if (ok && ms < best) { best = ms; best_seg = seg; }
     for (int c = 0; c < b->count; ++c) {  // back to the initial state
       rc = lbm::handle_reinit(b->h[c]);
       if (rc) return bfail(b, rc, lbm_last_error(b->h[c]));
     }
   }
+  if (best == 1e300) return bfail(b, LBM_E_NONFINITE, "autotune: every candidate's trial left a non-finite field");
   b->seg_rows = best_seg;
   drop_graph(b);
-  const int rc = build_table(b);
+  rc = build_table(b);
   if (rc) return rc;
   *seg_rows_out = best_seg;
+  return LBM_OK;
+}
+
+int lbm_batch_autotune_report(lbm_batch* b, int32_t max_rows, int32_t* seg_rows, double* ms, double* max_rel_dev,
+                              int32_t* passed, int32_t* rows) {
+  if (!b || !rows || (max_rows > 0 && (!seg_rows || !ms || !max_rel_dev || !passed)))
+    return bfail(b, LBM_E_ARG, "null argument");
+  if (max_rows < (int32_t)b->tune.size()) {
+    *rows = (int32_t)b->tune.size();
+    return bfail(b, LBM_E_ARG, "max_rows is smaller than the number of candidates");
+  }
+  for (size_t k = 0; k < b->tune.size(); ++k) {
+    seg_rows[k] = b->tune[k].seg;
+    ms[k] = b->tune[k].ms;
+    max_rel_dev[k] = b->tune[k].dev;
+    passed[k] = b->tune[k].ok;
+  }
+  *rows = (int32_t)b->tune.size();
   return LBM_OK;
 }
 

@@ -37,6 +37,7 @@ EXPORTS = ["lbm_required_bytes", "lbm_init", "lbm_step", "lbm_reduce_invariants"
            "lbm_bytes_per_node_step", "lbm_probe_bytes", "lbm_probe_stream", "lbm_probe_copy", "lbm_step_kernel",
            "lbm_batch_required_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_set_active",
            "lbm_batch_reduce_invariants", "lbm_batch_fetch_fields", "lbm_batch_replace_case", "lbm_batch_slot_bytes", "lbm_batch_autotune",
+           "lbm_batch_autotune_report",
            "lbm_batch_info", "lbm_batch_timing_begin", "lbm_batch_timing_end", "lbm_batch_destroy",
            "lbm_batch_last_error"]
 KERNEL_NAMES = ["k_step", "k_step_finish"]
@@ -130,6 +131,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_batch_replace_case.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Params)]
         L.lbm_batch_slot_bytes.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(sz)]
         L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int32, i32p]
+        L.lbm_batch_autotune_report.argtypes = [vp, ctypes.c_int32, i32p, dp, dp, i32p, i32p]
         L.lbm_batch_info.argtypes = [vp, i32p, i32p, i32p, i64p]
         L.lbm_batch_timing_begin.argtypes = [vp, ctypes.c_int64]
         L.lbm_batch_timing_end.argtypes = [vp, dp, i64p]
@@ -418,6 +420,15 @@ class Batch:
         seg = ctypes.c_int32()
         _bcheck(lib().lbm_batch_autotune(self._b, int(trial_steps), ctypes.byref(seg)), self._b)
         return seg.value
+
+    def autotune_report(self) -> list:
+        """The last autotune's candidates (lbm_batch_autotune_report): dicts of
+        seg_rows, ms, max_rel_dev and passed, in the order tried."""
+        m = 8
+        seg, ok, rows = (ctypes.c_int32 * m)(), (ctypes.c_int32 * m)(), ctypes.c_int32()
+        ms, dev = (ctypes.c_double * m)(), (ctypes.c_double * m)()
+        _bcheck(lib().lbm_batch_autotune_report(self._b, m, seg, ms, dev, ok, ctypes.byref(rows)), self._b)
+        return [dict(seg_rows=seg[k], ms=ms[k], max_rel_dev=dev[k], passed=bool(ok[k])) for k in range(rows.value)]
 
     def info(self) -> dict:
         c, s, w, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()

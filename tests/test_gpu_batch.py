@@ -175,6 +175,11 @@ def test_batch_autotune_restores_initial_state(lbm):
     seg = b.autotune(trial_steps=4)
     assert seg in (4, 8, 16, 32, 64)
     assert b.info()["seg_rows"] == seg
+    rep = b.autotune_report()
+    assert [r["seg_rows"] for r in rep] == [4, 8, 16, 32, 64]
+    assert rep[0]["max_rel_dev"] == 0.0
+    assert all(r["passed"] and r["max_rel_dev"] <= 1e-6 for r in rep), rep
+    assert seg == min(rep, key=lambda r: r["ms"])["seg_rows"]
     for k in range(len(cases)):
         f = b.fields(k, ["phi", "psi"])
         assert np.array_equal(f["phi"], f0[k]["phi"]) and np.array_equal(f["psi"], f0[k]["psi"]), k
@@ -182,6 +187,29 @@ def test_batch_autotune_restores_initial_state(lbm):
     s = lbm.Sim(dict(cases[3], tile_rows=seg), "fp32")
     s.step(5)
     assert np.array_equal(b.fields(3, ["phi"])["phi"], s.fields(["phi"])["phi"])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp16", 1e-4)])
+def test_batch_autotune_checks_every_candidate(lbm, prec, tol):
+    """Every segment height the autotuner tries steps the batch from the same
+    initial state; its checked sums agree with the first candidate's within the
+    storage's bound, and the batch then matches single handles."""
+    cases = sweep_like_cases()
+    b = lbm.Batch(cases, prec, seg_rows=4)
+    seg = b.autotune(trial_steps=6)
+    rep = b.autotune_report()
+    assert len(rep) == 5 and all(r["passed"] and r["max_rel_dev"] <= tol for r in rep), rep
+    b.step(6)
+    s = lbm.Sim(dict(cases[1], tile_rows=seg), prec)
+    s.step(6)
+    fb, fs = b.fields(1, ["phi", "psi"]), s.fields(["phi", "psi"])
+    for k in ("phi", "psi"):   # FP64: the single handle's tile kernel may contract multiply-adds differently
+        if prec == "fp64":
+            assert np.abs(fb[k] - fs[k]).max() < 1e-13, k
+        else:
+            assert np.array_equal(fb[k], fs[k]), k
+    s.close()
+    b.close()
 
 
 def test_batch_no_read_of_unwritten_state(lbm):
@@ -214,6 +242,7 @@ def test_full_sweep_batch_in_bench_configuration(lbm):
     cases = sweep.batch_cases(2000, 512)
     b = lbm.Batch(cases, "fp32")
     b.autotune(trial_steps=4)
+    assert all(r["passed"] for r in b.autotune_report()), b.autotune_report()
     m0 = [v["mass_psi"] for v in b.invariants(check=False)]
     b.step(100)
     inv = b.invariants(check=False)
