@@ -661,21 +661,25 @@ __device__ __forceinline__ void manufactured_source(const DevParams& p, unsigned
 // schedule (a kernel that holds both allocates it once).
 template <class S, class C, int SCHED>
 struct StepLds {
-  static constexpr int RP = 16, RM = 8;   // ring rows: h' and (phi, psi); (mu_phi, mu_psi)
+  static constexpr int RP = 16, RM = 8;   // ring rows: h'; (mu_phi, mu_psi)
+  // ring rows of (phi, psi): A writes at most 10 rows ahead of the oldest row C
+  // still reads.  FP64 storage takes 12 slots (row gy in slot gy mod 12), so
+  // that the g, h ring below fits two workgroups per CU; FP32 and FP16 keep 16
+  // (a mask instead of a remainder: measured 0.5-0.8% faster)
+  static constexpr int RPP = sizeof(S) == 8 ? 12 : 16;
   static constexpr bool H16 = kHalf<S>;
-  // g_1..g_8, h_1..h_8 of a segment row from A to C, in storage form (FP32
-  // and FP16 storage; FP64 would need more LDS than two workgroups per CU
-  // leave, and C gathers them again).  Six slots: the row wave w's A handles
+  // g_1..g_8, h_1..h_8 of a segment row from A to C, in storage form (FP64
+  // storage: 48 KB, with the 12-slot (phi, psi) ring two workgroups per CU
+  // still fit; C then gathers only f).  Six slots: the row wave w's A handles
   // at iteration k (Y0+4k+2+w) takes the slot of the row its C handled at
   // iteration k-1 (Y0+4k-4+w), which no other wave reads; C reads a row at
   // least one barrier after A wrote it.
-  static constexpr bool GH = sizeof(S) <= 4;
   static constexpr int RS = 6;
   C hp[RP][kStripW + 6];                             // h'(phi(n-1)), columns X0-3 .. X0+62
-  double2 pp[RP][64];                                // (phi, psi)(n), columns X0-2 .. X0+61
+  double2 pp[RPP][64];                               // (phi, psi)(n), columns X0-2 .. X0+61
   double2 mu[RM][64];                                // (mu_phi, mu_psi), columns X0-2 .. X0+61 (lanes 1..62 used)
   float2 ref[H16 ? RP : 1][H16 ? kStripW + 6 : 1];   // FP16 storage: (phi, psi)(n-1) as in hp
-  S gh[GH ? RS : 1][GH ? 16 : 1][64];
+  S gh[RS][16][64];
   double2 u[SCHED == kOneShot8 ? 4 : 1][SCHED == kOneShot8 ? 64 : 1];   // velocity of the split collision
 };
 template <class S, class C, int SCHED>
@@ -694,8 +698,12 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   // 2.35 against 2.45 ms).
   constexpr bool NTS = SCHED == kOneShot8 || sizeof(S) == 8;
   using L = StepLds<S, C, SCHED>;
-  constexpr int RP = L::RP, RM = L::RM, RS = L::RS;
-  constexpr bool H16 = L::H16, GH = L::GH;
+  constexpr int RP = L::RP, RM = L::RM, RS = L::RS, RPP = L::RPP;
+  auto pslot = [](int gy) {   // gy may lie below 0 (halo rows)
+    if constexpr ((RPP & (RPP - 1)) == 0) return gy & (RPP - 1);
+    else return ((gy % RPP) + RPP) % RPP;
+  };
+  constexpr bool H16 = L::H16;
   L& lds = step_lds<S, C, SCHED>();
   auto& sHp = lds.hp;
   auto& sPP = lds.pp;
@@ -786,7 +794,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   };
   auto row_A = [&](int gy, int ln, unsigned x, const C* tg, const C* th, const double* r0) {
     const int y = wave_uniform(row_of(gy)), yc = centre(gy);
-    const bool keep = GH && gy >= Y0 && gy < Yend;   // a row C collides
+    const bool keep = gy >= Y0 && gy < Yend;   // a row C collides
     const int ks = gh_slot(gy);
     const unsigned xd = x * sizeof(double);
     C sg = C(0), sh = C(0), corr = C(0);
@@ -821,7 +829,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       }
       ps = r0[1] + (double)sh + mub1_;
     }
-    sPP[gy & (RP - 1)][ln] = make_double2(ph, ps);
+    sPP[pslot(gy)][ln] = make_double2(ph, ps);
     if (is_interior(ln) && gy >= Y0 && gy < Yend) {
       store_hint<NTS>(byte_at(a.out + row, xd), ph);
       store_hint<NTS>(byte_at(a.out + N + row, xd), ps);
@@ -833,7 +841,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   auto row_B = [&](int gy, int ln) {
     const int y = wave_uniform(row_of(gy)), yc = centre(gy);
     const int l = min(max(ln, 1), 62);   // lanes 0 and 63 have no neighbour column: computed, unused
-    const double2 c = sPP[yc & (RP - 1)][l];
+    const double2 c = sPP[pslot(yc)][l];
     const double ph = c.x, ps = c.y;
     // Next to a wetting wall the wall values J of this row's columns l - 1,
     // l, l + 1 enter: each lane evaluates them at its own column, the
@@ -842,7 +850,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     const bool wet = wside != 0 && wet_side(p, wside);
     double jp = 0.0, js = 0.0;
     if (wet) {
-      const double2 o = sPP[yc & (RP - 1)][ln];
+      const double2 o = sPP[pslot(yc)][ln];
       jp = Jphi(p, o.x, o.y);
       if (p.surf) js = Jpsi(p, o.x, o.y);
     }
@@ -850,7 +858,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const double w2 = 6.0 * WQ<double>(i);
-      const double2 nb = sPP[(yc + CY(i)) & (RP - 1)][l + CX(i)];
+      const double2 nb = sPP[pslot((yc + CY(i)))][l + CX(i)];
       L.l0p += w2 * (nb.x - ph);
       L.l0s += w2 * (nb.y - ps);
       if (wet && CY(i) == wside) {   // the fluid node next to the ghost: column x + c_x of this row
@@ -872,19 +880,13 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   // ---- C: collide row gy (a fluid row of the segment)
   const C* __restrict__ hin = (const C*)a.hin;
   C* __restrict__ hout = (C*)a.hout;
-  // the gathers of a collision row (f; g and h unless they come from A
-  // through LDS), issued an iteration phase ahead of their use
-  auto gather_C = [&](int gy, unsigned x, C* f, C* g, C* h) {
+  // the gathers of a collision row (f only: g and h come from A through LDS),
+  // issued an iteration phase ahead of their use
+  auto gather_C = [&](int gy, unsigned x, C* f) {
     const size_t N = opaque((size_t)p.N);
     const unsigned xs = x * sizeof(S), xsm = colm(x) * sizeof(S), xsp = colp(x) * sizeof(S);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      f[i] = pull_row<S, C, WALLS, 0>(p, Pin, N, i, gy, xsm, xs, xsp);
-      if constexpr (!GH) {
-        g[i] = i ? pull_row<S, C, WALLS, 1>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
-        h[i] = (i && p.surf) ? pull_row<S, C, WALLS, 2>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
-      }
-    }
+    for (int i = 0; i < 9; ++i) f[i] = pull_row<S, C, WALLS, 0>(p, Pin, N, i, gy, xsm, xs, xsp);
   };
   auto row_C = [&](int gy, int ln, unsigned x, C* f, C* g, C* h) {
     const size_t row = (size_t)gy * p.nx;
@@ -903,12 +905,12 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       rg[k] = opaque(p.sg[k]);
       rh[k] = opaque(p.sh[k]);
     }
-    const double2 c = sPP[gy & (RP - 1)][lc];
+    const double2 c = sPP[pslot(gy)][lc];
     const double ph = c.x, ps = c.y;
     const double2 mc = sMU[gy & (RM - 1)][lc];
     const double ph0 = *byte_at(ref + row, xd);   // phi(n-1)
 
-    if constexpr (GH) {
+    {   // g_i, h_i (i >= 1) as A gathered them
       g[0] = h[0] = C(0);
       const int ks = gh_slot(gy);
 #pragma unroll
@@ -943,14 +945,14 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     const bool wet = wside != 0 && wet_side(p, wside);
     double jg = 0.0;
     if (wet) {
-      const double2 o = sPP[(gy + wside) & (RP - 1)][ln];
+      const double2 o = sPP[pslot((gy + wside))][ln];
       jg = Jphi(p, o.x, o.y);
     }
     double gfx = 0, gfy = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0, l0p = 0, l0s = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const double w3 = 3.0 * WQ<double>(i), w2 = 2.0 * w3;
-      const double2 nb = sPP[(gy + CY(i)) & (RP - 1)][lc + CX(i)];
+      const double2 nb = sPP[pslot((gy + CY(i)))][lc + CX(i)];
       double q = nb.x;
       if (wet && CY(i) == wside) q += __shfl(jg, lc + CX(i)) / p.kappa;
       l0p += w2 * (nb.x - ph);
@@ -1085,18 +1087,10 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = pull_row<S, C, WALLS, 0>(p, Pin, N, i, gy, xsm, xs, xsp);
   };
-  // g, h of a collision row (FP64 storage: FP32 and FP16 keep A's in LDS) and
-  // the history the row reads: phi, psi(n-1); u, v and the stored R of step n-1
-  auto gather_Cgh = [&](int gy, unsigned x, C* g, C* h, double* hv) {
+  // the history a collision row reads (its g, h come from A through LDS):
+  // phi, psi(n-1); u, v and the stored R of step n-1
+  auto gather_Cgh = [&](int gy, unsigned x, double* hv) {
     const size_t N = opaque((size_t)p.N);
-    const unsigned xs = x * sizeof(S), xsm = colm(x) * sizeof(S), xsp = colp(x) * sizeof(S);
-    if constexpr (!GH) {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        g[i] = i ? pull_row<S, C, WALLS, 1>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
-        h[i] = (i && p.surf) ? pull_row<S, C, WALLS, 2>(p, Pin, N, i, gy, xsm, xs, xsp) : C(0);
-      }
-    }
     const size_t row = (size_t)gy * p.nx;
     const unsigned xd = x * sizeof(double), xc = x * sizeof(C);
     hv[0] = *byte_at(ref + row, xd);
@@ -1119,7 +1113,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     const size_t N = opaque((size_t)p.N);
     double ph = 0.0, rho = 1.0, ux = 0.0, uy = 0.0, pr = 0.0, Fx = 0.0, Fy = 0.0, grx = 0.0, gry = 0.0;
     if (active) {
-      const double2 c = sPP[gy & (RP - 1)][lc];
+      const double2 c = sPP[pslot(gy)][lc];
       ph = c.x;
       const double ps = c.y;
       if constexpr (H16) {
@@ -1130,14 +1124,14 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       const bool wet = wside != 0 && wet_side(p, wside);
       double jg = 0.0;
       if (wet) {
-        const double2 o = sPP[(gy + wside) & (RP - 1)][ln];
+        const double2 o = sPP[pslot((gy + wside))][ln];
         jg = Jphi(p, o.x, o.y);
       }
       double gfx = 0, gfy = 0, gpx = 0, gpy = 0, gsx = 0, gsy = 0;
 #pragma unroll
       for (int i = 1; i < 9; ++i) {
         const double w3 = 3.0 * WQ<double>(i);
-        const double2 nb = sPP[(gy + CY(i)) & (RP - 1)][lc + CX(i)];
+        const double2 nb = sPP[pslot((gy + CY(i)))][lc + CX(i)];
         double q = nb.x;
         if (wet && CY(i) == wside) q += __shfl(jg, lc + CX(i)) / p.kappa;
         const double rq = rho_of(p, q);   // as in row_C
@@ -1202,12 +1196,12 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     double uxh = 0.0, uyh = 0.0, vxh = 0.0, vyh = 0.0, ps0 = 0.0;
     if (active) {
       const double lam1 = opaque_v(lam1_), mub1 = opaque_v(mub1_);
-      const double2 c = sPP[gy & (RP - 1)][lc];
+      const double2 c = sPP[pslot(gy)][lc];
       ph = c.x;
       ps = c.y;
       const double2 mc = sMU[gy & (RM - 1)][lc];
       ph0 = hv[0];
-      if constexpr (GH) {
+      {   // g_i, h_i (i >= 1) as A gathered them
         g[0] = h[0] = C(0);
         const int ks = gh_slot(gy);
 #pragma unroll
@@ -1233,7 +1227,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
 #pragma unroll
       for (int i = 1; i < 9; ++i) {
         const double w3 = 3.0 * WQ<double>(i), w2 = 2.0 * w3;
-        const double2 nb = sPP[(gy + CY(i)) & (RP - 1)][lc + CX(i)];
+        const double2 nb = sPP[pslot((gy + CY(i)))][lc + CX(i)];
         l0p += w2 * (nb.x - ph);
         l0s += w2 * (nb.y - ps);
       }
@@ -1318,7 +1312,6 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     // before the first wait.  The phases are those of the sweep on the same
     // rows, and the tile's sums are added in the order of the sweep's waves
     // (rows Y0+1, Y0+2, Y0+3, Y0), so the results equal the sweep's bit for bit.
-    constexpr bool preA = GH;
     C f[9], g[9], h[9], tg[9], th[9];
     double r0[2], v0[4], v1[4], hv[8];
     const int rc = Y0 + (wave & 3);   // the collision row of this wave's half of C
@@ -1326,16 +1319,15 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     pend_load();   // first: the multipliers are reduced while the gathers are in flight
     gather_H(Y0 - 3 + wave, lane, xcol, v0);
     if (wave < 2) gather_H(Y0 + 5 + wave, lane, xcol, v1);
-    if (preA) gather_A(Y0 - 2 + wave, xcol, tg, th, r0);
+    gather_A(Y0 - 2 + wave, xcol, tg, th, r0);
     if (collide) {
       if (fwave) gather_Cf(rc, xcol, f);
-      else gather_Cgh(rc, xcol, g, h, hv);
+      else gather_Cgh(rc, xcol, hv);
     }
     pend_set();
     row_H(Y0 - 3 + wave, lane, v0);
     if (wave < 2) row_H(Y0 + 5 + wave, lane, v1);
     __syncthreads();
-    if (!preA) gather_A(Y0 - 2 + wave, xcol, tg, th, r0);
     row_A(Y0 - 2 + wave, lane, xcol, tg, th, r0);
     __syncthreads();
     if (wave < 6) row_B(Y0 - 1 + wave, lane);
@@ -1370,7 +1362,6 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     // and Y0+1+w; the collision of row Y0+w), in the same order, but with all
     // loads issued before the first wait and no pipelining across rows: the
     // same results bit for bit, three dependent phases less.
-    constexpr bool preA = GH;
     C f[9], g[9], h[9], tg0[9], th0[9], tg1[9], th1[9];
     double r00[2], r01[2], v0[4], v1[4], v2[4];
     const int rc = Y0 + wave;
@@ -1379,19 +1370,15 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     gather_H(Y0 - 3 + wave, lane, xcol, v0);
     gather_H(Y0 + 1 + wave, lane, xcol, v1);
     if (wave < 2) gather_H(Y0 + 5 + wave, lane, xcol, v2);
-    if (preA) {
-      gather_A(Y0 - 2 + wave, xcol, tg0, th0, r00);
-      gather_A(Y0 + 2 + wave, xcol, tg1, th1, r01);
-    }
-    if (collide) gather_C(rc, xcol, f, g, h);
+    gather_A(Y0 - 2 + wave, xcol, tg0, th0, r00);
+    gather_A(Y0 + 2 + wave, xcol, tg1, th1, r01);
+    if (collide) gather_C(rc, xcol, f);
     pend_set();
     row_H(Y0 - 3 + wave, lane, v0);
     row_H(Y0 + 1 + wave, lane, v1);
     if (wave < 2) row_H(Y0 + 5 + wave, lane, v2);
     __syncthreads();
-    if (!preA) gather_A(Y0 - 2 + wave, xcol, tg0, th0, r00);
     row_A(Y0 - 2 + wave, lane, xcol, tg0, th0, r00);
-    if (!preA) gather_A(Y0 + 2 + wave, xcol, tg1, th1, r01);
     row_A(Y0 + 2 + wave, lane, xcol, tg1, th1, r01);
     __syncthreads();
     if (wave >= 2) row_B(Y0 - 3 + wave, lane);
@@ -1433,16 +1420,12 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     // All loads of the iteration are issued here, in the order of their use
     // (their counter drains in order): A's and H's gathers, then C's, which
     // stay in flight during A, H, B and the barriers.  H may follow A: A reads
-    // h' of rows up to ra + 1, written by earlier iterations.  FP64 (whose C
-    // also gathers g and h) gathers A's populations in A itself, to stay at
-    // two waves per SIMD.
-    constexpr bool preA = GH;
+    // h' of rows up to ra + 1, written by earlier iterations.
     C f[9], g[9], h[9], tg[9], th[9];
     double r0[2], v[4];
-    if (preA) gather_A(ra, x, tg, th, r0);
+    gather_A(ra, x, tg, th, r0);
     if (k >= 0) gather_H(rh, ln, x, v);
-    if (collide) gather_C(rc, x, f, g, h);
-    if (!preA) gather_A(ra, x, tg, th, r0);
+    if (collide) gather_C(rc, x, f);
     row_A(ra, ln, x, tg, th, r0);
     if (k >= 0) row_H(rh, ln, v);
     __syncthreads();
