@@ -1410,6 +1410,13 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     row_H(Y0 - 3 + j, lane, v);
   }
   __syncthreads();
+  // FP64 storage runs at two waves per SIMD with registers to spare: its A
+  // gathers are issued one iteration ahead, behind that iteration's H and C
+  // gathers, so that they land while B and C run.
+  constexpr bool PREA = sizeof(S) == 8 && !MMS;
+  C tgn[PREA ? 9 : 1], thn[PREA ? 9 : 1];
+  double r0n[PREA ? 2 : 1];
+  if constexpr (PREA) gather_A(Y0 - 4 + 2 + wave, xcol, tgn, thn, r0n);
 #pragma unroll 1
   for (int k = -1; 4 * k < Yend - Y0; ++k) {
     const int ln = opaque_v(lane);
@@ -1423,9 +1430,22 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     // h' of rows up to ra + 1, written by earlier iterations.
     C f[9], g[9], h[9], tg[9], th[9];
     double r0[2], v[4];
-    gather_A(ra, x, tg, th, r0);
+    if constexpr (PREA) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        tg[i] = tgn[i];
+        th[i] = thn[i];
+      }
+      r0[0] = r0n[0];
+      r0[1] = r0n[1];
+    } else {
+      gather_A(ra, x, tg, th, r0);
+    }
     if (k >= 0) gather_H(rh, ln, x, v);
     if (collide) gather_C(rc, x, f);
+    if constexpr (PREA) {
+      if (4 * (k + 1) < Yend - Y0) gather_A(ra + 4, x, tgn, thn, r0n);
+    }
     row_A(ra, ln, x, tg, th, r0);
     if (k >= 0) row_H(rh, ln, v);
     __syncthreads();
