@@ -154,3 +154,8 @@ def test_batch_validation(lbm):
                 lbm.make_params(dict(mms, constraint_phi=inputs.NONLINEAR), lbm.FP64)):
         assert L.lbm_required_bytes(ctypes.byref(bad), ctypes.byref(single)) == -1
         assert b"accuracy test" in L.lbm_last_error(None)
+    # the autotuner and its report refuse missing arguments before touching a device
+    i32 = ctypes.c_int32()
+    assert L.lbm_batch_autotune(None, 4, ctypes.byref(i32)) == -1
+    assert L.lbm_batch_autotune_report(None, 0, None, None, None, None, ctypes.byref(i32)) == -1
+    assert b"null" in L.lbm_batch_last_error(None)
