@@ -658,15 +658,24 @@ __device__ __forceinline__ void manufactured_source(const DevParams& p, unsigned
 }
 
 // LDS of one step workgroup, shared by the walled and the periodic form of a
-// schedule (a kernel that holds both allocates it once).
-template <class S, class C, int SCHED>
+// schedule (a kernel that holds both allocates it once; WK: a kernel with the
+// walled form).
+template <class S, class C, int SCHED, bool WK>
 struct StepLds {
-  static constexpr int RP = 16, RM = 8;   // ring rows: h'; (mu_phi, mu_psi)
-  // ring rows of (phi, psi): A writes at most 10 rows ahead of the oldest row C
-  // still reads.  FP64 storage takes 12 slots (row gy in slot gy mod 12), so
-  // that the g, h ring below fits two workgroups per CU; FP32 and FP16 keep 16
-  // (a mask instead of a remainder: measured 0.5-0.8% faster)
-  static constexpr int RPP = sizeof(S) == 8 ? 12 : 16;
+  // The walled form of the row sweep in FP32 and FP16 storage keeps each
+  // thread's three FP64 sums (h' mu_phi, h'^2, mu_psi) here instead of in
+  // registers: held in registers they are spilled to scratch there, and every
+  // reload waits for all the row's gathers in flight.  The wall-free form keeps
+  // them in registers; both add the same terms in the same order.
+  static constexpr bool LSUM = sizeof(S) <= 4 && SCHED == kSweep && WK;
+  // Ring rows: h' 16 (H writes at most 15 rows ahead of the oldest row C
+  // reads); (phi, psi) 16, or 12 where LDS is short (FP64 storage, and the
+  // sums above): A writes at most 10 rows ahead of the oldest row C reads;
+  // (mu_phi, mu_psi) 8, or 6 beside the sums: B writes rows up to 4 ahead of
+  // the oldest row C reads, after the barrier that ends C's reads of the rows
+  // it replaces.  Row gy lives in slot gy mod rows (a mask for 16 and 8: the
+  // remainder costs the periodic 4096^2 FP32 step 0.5%).
+  static constexpr int RP = 16, RPP = (sizeof(S) == 8 || LSUM) ? 12 : 16, RM = LSUM ? 6 : 8;
   static constexpr bool H16 = kHalf<S>;
   // g_1..g_8, h_1..h_8 of a segment row from A to C, in storage form (FP64
   // storage: 48 KB, with the 12-slot (phi, psi) ring two workgroups per CU
@@ -681,13 +690,14 @@ struct StepLds {
   float2 ref[H16 ? RP : 1][H16 ? kStripW + 6 : 1];   // FP16 storage: (phi, psi)(n-1) as in hp
   S gh[RS][16][64];
   double2 u[SCHED == kOneShot8 ? 4 : 1][SCHED == kOneShot8 ? 64 : 1];   // velocity of the split collision
+  double sacc[LSUM ? 3 : 1][LSUM ? kBlock : 1];
 };
-template <class S, class C, int SCHED>
-__device__ __forceinline__ StepLds<S, C, SCHED>& step_lds() {
-  __shared__ StepLds<S, C, SCHED> lds;
+template <class S, class C, int SCHED, bool WK>
+__device__ __forceinline__ StepLds<S, C, SCHED, WK>& step_lds() {
+  __shared__ StepLds<S, C, SCHED, WK> lds;
   return lds;
 }
-template <class S, class C, bool WALLS, int SCHED = kSweep, bool MMS = false>
+template <class S, class C, bool WALLS, int SCHED = kSweep, bool MMS = false, bool WK = WALLS>
 __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a, const int tile, const int mms_step = 0) {
   // Store hint, as measured on MI355X.  FP32 and FP16 storage store plainly on
   // the row sweep and the four-wave tile: the lines of neighbouring strips
@@ -697,14 +707,20 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   // the eight-wave tile of small grids keep the non-temporal hint (FP64 4096^2:
   // 2.35 against 2.45 ms).
   constexpr bool NTS = SCHED == kOneShot8 || sizeof(S) == 8;
-  using L = StepLds<S, C, SCHED>;
+  using L = StepLds<S, C, SCHED, WK>;
   constexpr int RP = L::RP, RM = L::RM, RS = L::RS, RPP = L::RPP;
-  auto pslot = [](int gy) {   // gy may lie below 0 (halo rows)
+  constexpr bool LS = L::LSUM && WALLS;
+  // ring slots of a (wave-uniform) row index, which may lie below 0 (halo rows)
+  auto pslot = [](int gy) {
     if constexpr ((RPP & (RPP - 1)) == 0) return gy & (RPP - 1);
-    else return ((gy % RPP) + RPP) % RPP;
+    else return wave_uniform(((gy % RPP) + RPP) % RPP);
+  };
+  auto mslot = [](int gy) {
+    if constexpr ((RM & (RM - 1)) == 0) return gy & (RM - 1);
+    else return wave_uniform(((gy % RM) + RM) % RM);
   };
   constexpr bool H16 = L::H16;
-  L& lds = step_lds<S, C, SCHED>();
+  L& lds = step_lds<S, C, SCHED, WK>();
   auto& sHp = lds.hp;
   auto& sPP = lds.pp;
   auto& sMU = lds.mu;
@@ -867,12 +883,19 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       }
     }
     const double mp = mu_phi_of(p, ph, ps, L), ms = mu_psi_of(p, ph, ps, L);
-    sMU[gy & (RM - 1)][ln] = make_double2(mp, ms);
+    sMU[mslot(gy)][ln] = make_double2(mp, ms);
     if (is_interior(ln) && gy >= Y0 && gy < Yend) {
       const double hp = hprime(p, ph);
-      s1 += hp * mp;
-      s2 += hp * hp;
-      s3 += ms;
+      if constexpr (LS) {
+        double* q = &lds.sacc[0][threadIdx.x];
+        q[0] = fma(hp, mp, q[0]);
+        q[kBlock] = fma(hp, hp, q[kBlock]);
+        q[2 * kBlock] += ms;
+      } else {
+        s1 = fma(hp, mp, s1);
+        s2 = fma(hp, hp, s2);
+        s3 += ms;
+      }
       if (p.phi_hold) s4 += hval(p, ph);   // S4 serves the hold only
     }
   };
@@ -907,7 +930,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     }
     const double2 c = sPP[pslot(gy)][lc];
     const double ph = c.x, ps = c.y;
-    const double2 mc = sMU[gy & (RM - 1)][lc];
+    const double2 mc = sMU[mslot(gy)][lc];
     const double ph0 = *byte_at(ref + row, xd);   // phi(n-1)
 
     {   // g_i, h_i (i >= 1) as A gathered them
@@ -960,7 +983,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       const double rq = rho_of(p, q);   // grad rho from the neighbours' densities (ghost phi at a wall)
       if (CX(i)) gfx += (CX(i) * w3) * rq;
       if (CY(i)) gfy += (CY(i) * w3) * rq;
-      const double2 mn = sMU[(gy + CY(i)) & (RM - 1)][lc + CX(i)];
+      const double2 mn = sMU[mslot(gy + CY(i))][lc + CX(i)];
       if (CX(i)) { gpx += (CX(i) * w3) * mn.x; gsx += (CX(i) * w3) * mn.y; }
       if (CY(i)) { gpy += (CY(i) * w3) * mn.x; gsy += (CY(i) * w3) * mn.y; }
     }
@@ -1137,7 +1160,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
         const double rq = rho_of(p, q);   // as in row_C
         if (CX(i)) gfx += (CX(i) * w3) * rq;
         if (CY(i)) gfy += (CY(i) * w3) * rq;
-        const double2 mn = sMU[(gy + CY(i)) & (RM - 1)][lc + CX(i)];
+        const double2 mn = sMU[mslot(gy + CY(i))][lc + CX(i)];
         if (CX(i)) { gpx += (CX(i) * w3) * mn.x; gsx += (CX(i) * w3) * mn.y; }
         if (CY(i)) { gpy += (CY(i) * w3) * mn.x; gsy += (CY(i) * w3) * mn.y; }
       }
@@ -1199,7 +1222,7 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
       const double2 c = sPP[pslot(gy)][lc];
       ph = c.x;
       ps = c.y;
-      const double2 mc = sMU[gy & (RM - 1)][lc];
+      const double2 mc = sMU[mslot(gy)][lc];
       ph0 = hv[0];
       {   // g_i, h_i (i >= 1) as A gathered them
         g[0] = h[0] = C(0);
@@ -1399,6 +1422,10 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
   }
 
   set_pend();
+  if constexpr (LS) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) lds.sacc[c][threadIdx.x] = 0.0;   // each thread's own slots
+  }
   // ---- the sweep.  Iteration k collides rows Y0+4k .. Y0+4k+3 (k = -1 only
   // fills the rings).  Ring lifetimes: H writes rows <= 15 ahead of the oldest
   // h' row C still reads; A writes <= 10 rows ahead of the oldest (phi, psi)
@@ -1453,6 +1480,11 @@ __device__ __forceinline__ void step_body(const DevParams& p, const StepArgs& a,
     __syncthreads();
     if (collide) row_C(rc, ln, x, f, g, h);
   }
+  if constexpr (LS) {
+    s1 = lds.sacc[0][threadIdx.x];
+    s2 = lds.sacc[1][threadIdx.x];
+    s3 = lds.sacc[2][threadIdx.x];
+  }
   s1 = block_reduce(s1, false);
   s2 = block_reduce(s2, false);
   s3 = block_reduce(s3, false);
@@ -1492,7 +1524,7 @@ __global__ __launch_bounds__(kBlock, MINB) void k_step(const DevParams* __restri
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   if constexpr (WALLS) {
     if (a.split_walls && wall_free_segment(t, a.nstrips, a.seg_rows, pp->ny)) {
-      step_body<S, C, false>(*pp, a, t);
+      step_body<S, C, false, kSweep, false, true>(*pp, a, t);
       return;
     }
   }
@@ -1549,7 +1581,7 @@ __global__ __launch_bounds__(kBlock, WALLS ? kStepMinBlocks<S> : 1) void k_step_
   const int t = b - bc.tile_begin;
   if constexpr (WALLS) {
     if (wall_free_segment(t, bc.nstrips, bc.seg_rows, bc.p.ny)) {
-      step_body<S, C, false>(bc.p, a, t);
+      step_body<S, C, false, kSweep, false, true>(bc.p, a, t);
       return;
     }
   }
